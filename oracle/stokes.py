@@ -1,0 +1,231 @@
+"""Generalized Stokes saddle-point system, its direct / MINRES solution, the true
+residual and the adjoint gradient (TEST INFRASTRUCTURE ONLY).
+
+The paper's discrete problem (Sec. 2.2, Eq. "Saddle_point_A_BT_B"):
+
+    A U - B^T P = F,   B U = 0,      A = (1/dt) M_V + mu E_V.
+
+Readings used here (listed with the others in the design notes):
+
+* viscous block: mu L_V, the vector Laplacian (the paper's A~_{lambda,3} =
+  dt^-1 M_V + mu L_V of Sec. 3.2); alpha = 1/dt.
+* Dirichlet data on the whole boundary (Sec. 3.1, V = H^1_0): the velocity
+  is eliminated on boundary nodes with nodal values G and lifted,
+      F~ = (M_V f)_I - A_{I,Gamma} G,    g = -B_Gamma G,
+  where f is the forcing given at every P2 node (F = M_V f, exact).
+* g is made compatible by removing its l2 mean (1^T g = 0 is required since
+  B_I^T 1 = 0); the pressure is returned with zero integral (1^T M_Q P = 0).
+* augmented Lagrangian (Sec. 2.3, Eq. "def_of_Alambda"): A_gamma = A +
+  gamma mu B^T M_Q^{-1} B with right-hand side F~ + gamma mu B^T M_Q^{-1} g.
+  Because B U = g at the solution, the solution does not depend on gamma, so
+  the oracle solves the gamma = 0 system; ``apply_coupled`` still applies
+  the gamma operator for residual checks.
+* "relative residual": the unpreconditioned l2 residual of the plain (gamma
+  = 0) coupled FP64 system, ||b - K x|| / ||b|| with b = (F~, g).
+"""
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .fem import assemble
+
+
+class StokesSystem:
+    """Assembled and boundary-reduced generalized Stokes system on a mesh.
+
+    Unknown layout: U is (d, n_I) (component-major over interior P2 nodes in
+    increasing node id), P is (n_p1,)."""
+
+    def __init__(self, mesh, mu, alpha, gamma=0.0, mats=None):
+        self.mesh = mesh
+        self.mu, self.alpha, self.gamma = float(mu), float(alpha), float(gamma)
+        self.mats = assemble(mesh) if mats is None else mats
+        m = self.mats
+        self.d = mesh.dim
+        self.I = mesh.interior_nodes
+        self.nI = self.I.size
+        self.np1 = mesh.n_p1
+        self.As_full = (self.alpha * m.Ms + self.mu * m.Ls).tocsr()
+        self.A_II = self.As_full[self.I][:, self.I].tocsr()
+        self.A_Iall = self.As_full[self.I].tocsr()
+        self.B_I = [b[:, self.I].tocsr() for b in m.B]
+        self.mQ = m.MQ @ np.ones(self.np1)   # M_Q 1 (pressure integral weights)
+        self._MQ_lu = None
+
+    # ------------------------------------------------------------- helpers
+    def MQ_solve(self, r):
+        if self._MQ_lu is None:
+            self._MQ_lu = spla.splu(self.mats.MQ.tocsc())
+        return self._MQ_lu.solve(r)
+
+    def lift(self, ubc):
+        """Nodal lifting G: ubc on boundary nodes, zero inside. (d, n_p2)."""
+        G = np.zeros((self.d, self.mesh.n_p2))
+        if ubc is not None:
+            bnd = self.mesh.p2_boundary
+            G[:, bnd] = np.asarray(ubc, dtype=np.float64).reshape(self.d, -1)[:, bnd]
+        return G
+
+    def rhs(self, f, ubc=None, gamma_rhs=False):
+        """(F~, g) of the reduced system; f, ubc are (d, n_p2) nodal arrays.
+
+        gamma_rhs=True adds the augmented-Lagrangian term gamma mu B^T M_Q^{-1} g."""
+        f = np.asarray(f, dtype=np.float64).reshape(self.d, -1)
+        G = self.lift(ubc)
+        F = np.empty((self.d, self.nI))
+        for c in range(self.d):
+            F[c] = (self.mats.Ms @ f[c])[self.I] - self.A_Iall @ G[c]
+        g = np.zeros(self.np1)
+        for c in range(self.d):
+            g -= self.mats.B[c] @ G[c]
+        g -= g.mean()
+        if gamma_rhs and self.gamma != 0.0:
+            w = self.MQ_solve(g)
+            for c in range(self.d):
+                F[c] += self.gamma * self.mu * (self.B_I[c].T @ w)
+        return F, g
+
+    def apply_coupled(self, U, P, gamma=None):
+        """K_gamma (U, P) = (A_gamma U - B^T P, B U) for U (d, n_I), P (n_p1,)."""
+        gamma = self.gamma if gamma is None else gamma
+        U = np.asarray(U).reshape(self.d, self.nI)
+        BU = sum(self.B_I[c] @ U[c] for c in range(self.d))
+        RU = np.empty_like(U)
+        w = self.MQ_solve(BU) if gamma != 0.0 else None
+        for c in range(self.d):
+            RU[c] = self.A_II @ U[c] - self.B_I[c].T @ P
+            if w is not None:
+                RU[c] += gamma * self.mu * (self.B_I[c].T @ w)
+        return RU, BU
+
+    def residual(self, U, P, F, g):
+        """True relative residual ||b - K x||_2 / ||b||_2 of the plain system."""
+        RU, RP = self.apply_coupled(U, P, gamma=0.0)
+        num = np.sqrt(np.sum((F - RU) ** 2) + np.sum((g - RP) ** 2))
+        den = np.sqrt(np.sum(F ** 2) + np.sum(g ** 2))
+        return num / den if den > 0 else num
+
+    def normalize_pressure(self, P):
+        """Shift P so that int p_h = 1^T M_Q P = 0."""
+        return P - (self.mQ @ P) / self.mQ.sum()
+
+    def full_velocity(self, U, ubc=None):
+        """Scatter interior U (d, n_I) and the boundary data to all P2 nodes."""
+        u = self.lift(ubc)
+        u[:, self.I] = U
+        return u
+
+    # ------------------------------------------------------------- operators
+    def coupled_matrix(self, bordered=True):
+        """Sparse K = [[I_d (x) A_II, -B_I^T], [B_I, 0]], optionally bordered with
+        the zero-mean constraint [0, m^T] / column [0; m] (m = M_Q 1)."""
+        d = self.d
+        Ablk = sp.block_diag([self.A_II] * d, format="csr")
+        BT = sp.vstack([b.T for b in self.B_I], format="csr")
+        Bm = sp.hstack(self.B_I, format="csr")
+        if not bordered:
+            return sp.bmat([[Ablk, -BT], [Bm, None]], format="csc")
+        mcol = sp.csr_matrix(self.mQ[:, None])
+        return sp.bmat([[Ablk, -BT, None], [Bm, None, mcol], [None, mcol.T, None]],
+                       format="csc")
+
+    # ------------------------------------------------------------- solvers
+    def solve_direct(self, F, g):
+        """Sparse LU of the bordered system (small meshes)."""
+        K = self.coupled_matrix(bordered=True)
+        b = np.concatenate([F.ravel(), g, [0.0]])
+        x = spla.spsolve(K, b)
+        U = x[: self.d * self.nI].reshape(self.d, self.nI)
+        P = self.normalize_pressure(x[self.d * self.nI: self.d * self.nI + self.np1])
+        return U, P
+
+    def solve_dense_lstsq(self, F, g):
+        """Minimum-norm least-squares solution of the singular unbordered system
+        (tiny meshes only) -- an independent route to the same (U, P)."""
+        K = self.coupled_matrix(bordered=False).toarray()
+        b = np.concatenate([F.ravel(), g])
+        x = np.linalg.lstsq(K, b, rcond=None)[0]
+        U = x[: self.d * self.nI].reshape(self.d, self.nI)
+        P = self.normalize_pressure(x[self.d * self.nI:])
+        return U, P
+
+    def solve_minres(self, F, g, rtol=1e-13, maxiter=5000, inner_rtol=1e-14, callback=None):
+        """Preconditioned MINRES on the symmetric form [[A, B^T], [B, 0]] (U, -P).
+
+        Block-diagonal SPD preconditioner: per-component CG on A_II (Jacobi,
+        tight tolerance) and mu M_Q^{-1} + alpha (M_Q + L_Q)^{-1} on the
+        pressure, both by CG.  Only the iteration count depends on it."""
+        d, nI, np1 = self.d, self.nI, self.np1
+        Ablk = sp.block_diag([self.A_II] * d, format="csr")
+        Bm = sp.hstack(self.B_I, format="csr")
+        Ksym = sp.bmat([[Ablk, Bm.T], [Bm, None]], format="csr")
+        Dinv_A = 1.0 / self.A_II.diagonal()
+        MQ, XQ = self.mats.MQ, (self.mats.MQ + self.mats.LQ).tocsr()
+        Dinv_MQ, Dinv_XQ = 1.0 / MQ.diagonal(), 1.0 / XQ.diagonal()
+
+        def cg(A, b, dinv):
+            x, _ = spla.cg(A, b, rtol=inner_rtol, atol=0.0, maxiter=10000,
+                           M=spla.LinearOperator(A.shape, lambda v: dinv * v))
+            return x
+
+        def prec(v):
+            out = np.empty_like(v)
+            for c in range(d):
+                out[c * nI:(c + 1) * nI] = cg(self.A_II, v[c * nI:(c + 1) * nI], Dinv_A)
+            vp = v[d * nI:]
+            out[d * nI:] = self.mu * cg(MQ, vp, Dinv_MQ) + self.alpha * cg(XQ, vp, Dinv_XQ)
+            return out
+
+        n = d * nI + np1
+        b = np.concatenate([F.ravel(), g])
+        x, info = spla.minres(Ksym, b, M=spla.LinearOperator((n, n), prec), rtol=rtol,
+                              maxiter=maxiter, callback=callback)
+        U = x[: d * nI].reshape(d, nI)
+        P = self.normalize_pressure(-x[d * nI:])
+        return U, P, info
+
+    def solve(self, F, g, method="auto", **kw):
+        if method == "auto":
+            method = "direct" if self.d * self.nI + self.np1 <= 150_000 else "minres"
+        if method == "direct":
+            return self.solve_direct(F, g)
+        if method == "lstsq":
+            return self.solve_dense_lstsq(F, g)
+        U, P, _ = self.solve_minres(F, g, **kw)
+        return U, P
+
+    # ------------------------------------------------------------- adjoint
+    def adjoint_gradient(self, u_full, dJdu_full, dJdp=None, method="auto", **kw):
+        """Gradient of a loss J(u, p) w.r.t. the nodal forcing f and mu.
+
+        The transposed system K^T (lam_u, lam_p) = (dJ/dU_I, Pi^T dJ/dP), with
+        K^T = [[A, B^T], [-B, 0]], becomes the forward system after the
+        substitution q = -lam_p:  A lam_u - B^T q = j_u,  B lam_u = -j_p.
+        Then dJ/df_c = M_s[:, I] lam_u,c (all P2 nodes) and
+        dJ/dmu = -sum_c lam_u,c . (L_s[I, :] u_c).  Pi is the zero-mean
+        normalisation of the pressure output."""
+        d = self.d
+        ju = np.asarray(dJdu_full).reshape(d, -1)[:, self.I]
+        jp = np.zeros(self.np1) if dJdp is None else np.asarray(dJdp, dtype=np.float64)
+        # Pi = I - 1 m^T / (1^T m); its transpose applied to jp:
+        jp = jp - self.mQ * jp.sum() / self.mQ.sum()
+        lam_u, q = self.solve(ju, -jp, method=method, **kw)
+        lam_p = -q
+        dJdf = np.zeros((d, self.mesh.n_p2))
+        Ls_I = self.mats.Ls[self.I]
+        dJdmu = 0.0
+        u_full = np.asarray(u_full).reshape(d, -1)
+        for c in range(d):
+            ext = np.zeros(self.mesh.n_p2)
+            ext[self.I] = lam_u[c]
+            dJdf[c] = self.mats.Ms @ ext
+            dJdmu -= lam_u[c] @ (Ls_I @ u_full[c])
+        return dJdf, dJdmu, lam_u, lam_p
+
+
+def quadratic_loss(sysm, u_full, u_target_full):
+    """J = 1/2 (u - u*)^T M_V (u - u*) over all P2 nodes, and dJ/du."""
+    diff = np.asarray(u_full).reshape(sysm.d, -1) - np.asarray(u_target_full).reshape(sysm.d, -1)
+    Md = np.stack([sysm.mats.Ms @ diff[c] for c in range(sysm.d)])
+    return 0.5 * float(np.sum(diff * Md)), Md
