@@ -1,0 +1,232 @@
+/*
+ * stokes.h -- C ABI of the MI355X (gfx950) generalized Stokes solver.
+ *
+ * Problem (Creff & Guermond, arXiv 2407.01783, Sec. 2.2, the saddle-point
+ * system A U - B^T P = F, B U = 0, with A = (1/dt) M_V + mu (viscous term)):
+ * on the unit square (dim 2) or unit cube (dim 3) split into n^dim cells, each
+ * cut into dim! Kuhn simplices, with Taylor-Hood P2 velocity / P1 pressure,
+ * find (u, p) with
+ *
+ *     (alpha M_V + mu L_V + gamma mu B^T M_Q^{-1} B) U - B^T P = F~,   B U = g,
+ *
+ * alpha = 1/dt, L_V the vector Laplacian (the paper's A~_{lambda,3} block of
+ * Sec. 3.2), gamma the augmented-Lagrangian weight (Sec. 2.3, Eq.
+ * "def_of_Alambda", written lambda there), Dirichlet velocity on the whole
+ * boundary (Sec. 3.1), F~ = (M_V f)_I - A_{I,Gamma} G the lifted load of a
+ * nodal forcing f, g = -B_Gamma G made mean-free, and the pressure returned
+ * with zero integral.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All solver arrays are DEVICE pointers to float64, owned by the caller; the
+ *   library reads and writes them on the context's HIP stream and never keeps
+ *   them past the call.  Host pointers are marked _host.
+ * - Velocity-shaped arrays (f, ubc, u, x0_u, lam_u, dJdu, dJdf) are laid out
+ *   [nrhs][dim][n_p2]: component-major over ALL P2 nodes in the natural
+ *   numbering (P2 node (I,J[,K]) of the refined (2n+1)^dim grid has id
+ *   I + (2n+1) J [+ (2n+1)^2 K]).  Pressure-shaped arrays (p, x0_p, lam_p,
+ *   dJdp) are [nrhs][n_p1] over the vertices (i,j[,k]), id i + (n+1) j [+ ...].
+ * - Return value: STOKES_OK (0), STOKES_NOT_CONVERGED (1, outputs hold the
+ *   best iterate), or a negative error code; stokes_last_error() then gives a
+ *   message (thread-local).  Arguments are validated before any HIP call.
+ *   After an error the output arrays are unspecified.
+ * - One context per host thread at a time; calls on one context serialise on
+ *   its stream.
+ */
+#ifndef STOKES_H
+#define STOKES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stokes_ctx stokes_ctx; /* opaque; owned by the library */
+typedef int32_t stokes_status;
+
+enum {
+  STOKES_OK = 0,
+  STOKES_NOT_CONVERGED = 1,
+  STOKES_ERR_ARG = -1,
+  STOKES_ERR_ALLOC = -2,
+  STOKES_ERR_HIP = -3,
+  STOKES_ERR_NONFINITE = -4,
+  STOKES_ERR_BREAKDOWN = -5,
+  STOKES_ERR_STATE = -6,
+  STOKES_ERR_UNSUPPORTED = -7
+};
+
+/* stokes_solve_opts.precision */
+enum { STOKES_FP64 = 0, STOKES_MIXED = 1 };
+/* stokes_solve_opts.inner_mode: inner solves to a tolerance ("th" in the
+ * paper, Sec. 3.3) or a fixed polynomial ("2Vc" counterpart). */
+enum { STOKES_INNER_TOL = 0, STOKES_INNER_FIXED = 1 };
+/* stokes_solve_opts.schur_pc: the Cahouet-Chabard family of Sec. 4.1,
+ * alpha X^{-1} + mu (1 + gamma) M_Q^{-1} with X = L_Q (C^Delta),
+ * B Lambda_V^{-1} B^T (C^Lambda) or B M_V^{-1} B^T (C). */
+enum { STOKES_CC_LAPLACE = 0, STOKES_CC_LUMPED = 1, STOKES_CC_MASS = 2 };
+/* stokes_solve_opts.coupled_pc: block preconditioners of Sec. 2.4:
+ * FULL = the three-factor inexact factorisation (Eq.
+ * "inexact_factorization_of_Alambda", two A~^{-1} per step), LOWER = the
+ * "incomplete Full" of Sec. 6.2 (left factor dropped), UPPER = block upper
+ * triangular [[A~, -B^T], [0, S~]]. */
+enum { STOKES_PC_FULL = 0, STOKES_PC_UPPER = 1, STOKES_PC_LOWER = 2 };
+
+typedef struct {
+  int32_t dim;        /* 2 or 3 */
+  int32_t n;          /* cells per side, >= 1 (>= 2 for a unique pressure) */
+  uint64_t mesh_seed; /* seed of the interior-vertex jitter */
+  double jitter;      /* jitter amplitude as a fraction of h, in [0, 0.2] */
+  double mu;          /* viscosity, > 0 */
+  double alpha;       /* 1/dt, > 0 */
+  double gamma;       /* augmented-Lagrangian weight, >= 0 */
+  int32_t flags;      /* reserved, must be 0 */
+} stokes_problem;
+
+typedef struct {
+  int32_t precision;      /* STOKES_FP64 or STOKES_MIXED (FP32 inner solves) */
+  double rtol;            /* target true relative residual of the coupled FP64
+                             system ||b - K x||_2 / ||b||_2 (per right-hand side) */
+  int32_t max_outer;      /* cap on outer Krylov iterations, summed over sweeps */
+  int32_t restart;        /* FGMRES restart length m (1..64) */
+  int32_t max_inner;      /* cap on each inner CG */
+  int32_t inner_mode;     /* STOKES_INNER_TOL or STOKES_INNER_FIXED */
+  int32_t cheb_degree;    /* Chebyshev-Jacobi degree of the velocity block (1..16) */
+  double inner_rtol_u;    /* relative tolerance of inner velocity CG */
+  double inner_rtol_p;    /* relative tolerance of inner pressure CG */
+  int32_t schur_pc;       /* STOKES_CC_* */
+  int32_t coupled_pc;     /* STOKES_PC_* */
+  int32_t max_refine;     /* cap on iterative-refinement sweeps */
+  int32_t profile;        /* 1: time the dominant SpMV with HIP events */
+  int32_t reserved[4];    /* must be 0 */
+} stokes_solve_opts;
+
+typedef struct {
+  int32_t converged;      /* 1 if every right-hand side met rtol */
+  int32_t outer_iters;    /* outer Krylov iterations (all sweeps) */
+  int32_t inner_iters_u;  /* inner velocity CG iterations (all solves) */
+  int32_t inner_iters_p;  /* inner pressure CG iterations */
+  int32_t refinements;    /* sweeps of the refinement loop */
+  int32_t spmv_launches;  /* launches of the timed SpMV (profile = 1) */
+  double rel_res;         /* max over right-hand sides of the final true residual */
+  double seconds_total;   /* wall time of the call */
+  double spmv_seconds;    /* summed duration of the timed SpMV launches */
+  double spmv_bytes;      /* algorithmic bytes of one timed SpMV launch */
+} stokes_solve_info;
+
+/* Fill *opts with defaults: FP64, rtol 1e-8, FGMRES(30), Chebyshev degree 4,
+ * inner tolerances 1e-6 / 1e-4, C^Lambda, FULL, 8 refinement sweeps. */
+void stokes_default_opts(stokes_solve_opts* opts);
+
+/* Sizes of the problem without building anything (host only, no GPU):
+ * sizes[0..9] = n_p2, n_p1, n_free_nodes, nnz(A_II), nnz(B_I one plane),
+ * nnz(M_Q), n_elem, dim, nnz(full P2 scalar pattern), nnz(B full one plane). */
+stokes_status stokes_problem_sizes(const stokes_problem* prob, int64_t sizes[10]);
+
+/* Host-only mesh construction (no GPU): vertex coordinates [n_p1][dim],
+ * simplex vertex ids [n_elem][dim+1], P2 node coordinates [n_p2][dim], and the
+ * P2 node ids of every simplex [n_elem][n_loc] (local order: vertices, then
+ * edges (0,1),(0,2),(0,3),(1,2),(1,3),(2,3) / (0,1),(0,2),(1,2)).  Any pointer
+ * may be NULL to skip that output. */
+stokes_status stokes_build_mesh_host(const stokes_problem* prob, double* vcoords_host,
+                                     int32_t* elems_host, double* p2coords_host,
+                                     int32_t* p2_host);
+
+/* Host-only sparsity pattern (no GPU), CSR with sorted columns.
+ * which: 0 = P2 x P2 over all nodes, 1 = interior P2 x interior P2 (natural
+ * ids of interior nodes renumbered 0.. in increasing order), 2 = P1 x all P2
+ * (B), 3 = P1 x interior P2 (B_I), 4 = P1 x P1.  Call with rowptr_host and
+ * cols_host NULL to get *nrows / *nnz, then again with arrays of that size. */
+stokes_status stokes_host_pattern(const stokes_problem* prob, int32_t which, int64_t* nrows,
+                                  int64_t* nnz, int32_t* rowptr_host, int32_t* cols_host);
+
+/* Build the mesh, assemble every operator on the GPU (Sec. 2.2, 3.2, 4.1:
+ * M_V, L_V, B, M_Q, L_Q, Lambda_V), estimate the Chebyshev bounds and return a
+ * context bound to hip_stream (NULL = default stream) and the current device. */
+stokes_status stokes_assemble(const stokes_problem* prob, void* hip_stream, stokes_ctx** out);
+
+/* Method 1 (Sec. 2.3): flexible CG on the pressure Schur complement
+ * S = B A^{-1} B^T preconditioned by the Cahouet-Chabard operator
+ * (Sec. 4.1), inside an FP64 iterative-refinement loop on the coupled
+ * residual.  f: nodal forcing; ubc: Dirichlet data (boundary entries read;
+ * NULL = 0); x0_u, x0_p: initial guess (NULL = 0); u, p: outputs (boundary
+ * entries of u equal ubc; p has zero integral).  info may be NULL. */
+stokes_status stokes_solve_schur(stokes_ctx* ctx, int32_t nrhs, const double* f,
+                                 const double* ubc, const double* x0_u, const double* x0_p,
+                                 double* u, double* p, const stokes_solve_opts* opts,
+                                 stokes_solve_info* info);
+
+/* Method 2 (Sec. 2.4): right-preconditioned flexible GMRES(m) on the coupled
+ * matrix [[A_gamma, -B^T], [B, 0]] with a block preconditioner
+ * (opts->coupled_pc), restarts checked against the true FP64 residual.
+ * Same arguments as stokes_solve_schur. */
+stokes_status stokes_solve_coupled(stokes_ctx* ctx, int32_t nrhs, const double* f,
+                                   const double* ubc, const double* x0_u, const double* x0_p,
+                                   double* u, double* p, const stokes_solve_opts* opts,
+                                   stokes_solve_info* info);
+
+/* Adjoint of the solve: given the forward velocity u ([nrhs][dim][n_p2]) and
+ * the loss gradients dJdu ([nrhs][dim][n_p2], boundary entries ignored) and
+ * dJdp ([nrhs][n_p1], NULL = 0), solve the transposed coupled system
+ * [[A, B^T], [-B, 0]] (lam_u, lam_p) = (dJ/dU_I, dJ/dP) and return
+ * lam_u ([nrhs][dim][n_p2], zero on the boundary), lam_p ([nrhs][n_p1]),
+ * dJdf = M_V[I,:]^T lam_u ([nrhs][dim][n_p2]) and
+ * dJdmu[r] = -lam_u^T L_V[I,:] u ([nrhs], device).  Uses the coupled solver
+ * with opts (solved as the forward system after lam_p -> -lam_p). */
+stokes_status stokes_solve_adjoint(stokes_ctx* ctx, int32_t nrhs, const double* u,
+                                   const double* dJdu, const double* dJdp, double* lam_u,
+                                   double* lam_p, double* dJdf, double* dJdmu,
+                                   const stokes_solve_opts* opts, stokes_solve_info* info);
+
+/* Apply one assembled operator in FP64 (precision 0) or FP32 (1) to device
+ * arrays in the caller layout.  op: 0 = y = A_gamma=0 x on interior nodes
+ * (x, y velocity-shaped, boundary entries of x ignored, of y set to 0);
+ * 1 = y = B x (x velocity-shaped, y pressure-shaped); 2 = y = B^T x (x
+ * pressure, y velocity, boundary 0); 3 = M_Q x; 4 = L_Q x; 5 = the coupled
+ * operator: (y_u, y_p) = (A u - B^T p, B u) with x = (x_u, x_p) packed as
+ * [nrhs][dim][n_p2] followed by [nrhs][n_p1]. */
+stokes_status stokes_apply(stokes_ctx* ctx, int32_t op, int32_t precision, int32_t nrhs,
+                           const double* x, double* y);
+
+/* True relative residual ||b - K x|| / ||b|| of the plain coupled system for
+ * the given forcing, boundary data and solution (all device, caller layout);
+ * rel_res_host[nrhs] receives one value per right-hand side. */
+stokes_status stokes_residual(stokes_ctx* ctx, int32_t nrhs, const double* f, const double* ubc,
+                              const double* u, const double* p, double* rel_res_host);
+
+/* sizes[0..9] as in stokes_problem_sizes, for an assembled context. */
+stokes_status stokes_query(const stokes_ctx* ctx, int64_t sizes[10]);
+
+/* Change mu and re-form A = alpha M + mu L on the device. */
+stokes_status stokes_set_mu(stokes_ctx* ctx, double mu);
+
+/* Rebind the context to another HIP stream of the same device. */
+stokes_status stokes_set_stream(stokes_ctx* ctx, void* hip_stream);
+
+/* Copy the P2 node coordinates [n_p2][dim] and simplex P2 ids
+ * [n_elem][n_loc] to host arrays (either may be NULL). */
+stokes_status stokes_export_mesh(const stokes_ctx* ctx, double* p2coords_host, int32_t* p2_host);
+
+/* Copy an assembled FP64 matrix to host CSR arrays in the natural numbering
+ * of stokes_host_pattern.  which: 0 = M_s (all P2), 1 = L_s (all P2),
+ * 2..4 = B plane x, y, z (P1 x all P2), 5 = M_Q, 6 = L_Q, 7 = A_II (interior,
+ * pattern 1), 8 = Lambda_V (diagonal: rowptr/cols ignored, vals [n_p2]). */
+stokes_status stokes_export_csr(const stokes_ctx* ctx, int32_t which, int32_t* rowptr_host,
+                                int32_t* cols_host, double* vals_host);
+
+/* Chebyshev interval estimates [lo, hi] of the Jacobi-scaled operators:
+ * bounds_host[0..7] = A_II, M_V, M_Q, M_Q + L_Q. */
+stokes_status stokes_bounds(const stokes_ctx* ctx, double bounds_host[8]);
+
+/* Free the context and every device buffer it owns.  NULL is a no-op. */
+void stokes_destroy(stokes_ctx* ctx);
+
+/* Message of the last error on this thread ("" if none). */
+const char* stokes_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STOKES_H */

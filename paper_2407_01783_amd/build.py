@@ -1,0 +1,74 @@
+"""Build libstokes.so (HIP for gfx950) in the package directory.
+
+The host mesh code is compiled by g++ without floating-point contraction so
+the jittered coordinates are reproducible bit for bit; the HIP sources are
+compiled by hipcc for gfx950 with packed-FP32 instructions disabled.
+"""
+
+import os
+import shutil
+import subprocess
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libstokes.so")
+ARCH = os.environ.get("STOKES_OFFLOAD_ARCH", "gfx950")
+
+HIP_SOURCES = ["assemble.hip", "ops.hip", "solver.hip", "abi.hip"]
+HOST_SOURCES = ["mesh_host.cpp"]
+
+HIPCC_FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-munsafe-fp-atomics", "-Wno-unused-result",
+]
+
+
+def _run(cmd):
+    t = time.time()
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(" ".join(cmd) + "\n" + r.stdout + r.stderr)
+        raise RuntimeError(f"build step failed: {os.path.basename(cmd[-1])}")
+    return time.time() - t
+
+
+def build(verbose=True, jobs=None):
+    """Compile every source and link libstokes.so; returns the library path."""
+    os.makedirs(BUILD, exist_ok=True)
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    objs, cmds = [], []
+    for src in HOST_SOURCES:
+        obj = os.path.join(BUILD, src + ".o")
+        cmds.append(["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-pthread",
+                     "-c", "-o", obj, os.path.join(CSRC, src)])
+        objs.append(obj)
+    for src in HIP_SOURCES:
+        obj = os.path.join(BUILD, src + ".o")
+        cmds.append([hipcc] + HIPCC_FLAGS + ["-c", "-o", obj, os.path.join(CSRC, src)])
+        objs.append(obj)
+    procs = []
+    for cmd in cmds:  # compile in parallel
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+    failed = []
+    for cmd, p in procs:
+        out, err = p.communicate()
+        if p.returncode != 0:
+            failed.append((cmd, out + err))
+    if failed:
+        for cmd, msg in failed:
+            sys.stderr.write(" ".join(cmd) + "\n" + msg[-20000:] + "\n")
+        raise RuntimeError("compilation failed")
+    tmp = LIB + ".tmp"
+    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-pthread"])
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB}")
+    return LIB
+
+
+if __name__ == "__main__":
+    build()

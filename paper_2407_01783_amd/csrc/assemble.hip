@@ -1,0 +1,786 @@
+// GPU finite-element assembly of the Taylor-Hood P2/P1 operators (paper Sec.
+// 2.2: M_V, B, M_Q; Sec. 3.2: the vector Laplacian L_V; Sec. 4.1: L_Q and the
+// lumped Lambda_V), and the build of the sliced-ELL operators used inside the
+// Krylov iterations.
+//
+// Element integrals use reference tables computed once on the host with the
+// Grundmann-Moller degree-5 rule on the simplex (Grundmann & Moller, SIAM J.
+// Numer. Anal. 15, 1978), which is exact for the degree-4 integrands here.
+// Geometry enters through |K| and J^{-1} (x = x_0 + J xi):
+//     M_ij  = |K| Mref_ij
+//     L_ij  = |K| sum_pq (J^{-1} J^{-T})_pq Sref_ipjq
+//     B^c_ki = |K| sum_p (J^{-1})_pc Wref_kip
+// Assembly is deterministic and atomic-free: one thread owns each matrix row,
+// walks the simplices incident to its node in a fixed order and adds each
+// element row into its sorted CSR slots.
+#include <algorithm>
+#include <cmath>
+#include <functional>
+#include <numeric>
+
+#include "common.h"
+#include "kernels.h"
+#include "ops.h"
+
+namespace stokes {
+
+namespace {
+
+// reference tables, [2] = 2D, [3] = 3D (index by dim)
+__constant__ double c_Mref3[100], c_Sref3[900], c_Wref3[120], c_M1ref3[16], c_abs3[10];
+__constant__ double c_Mref2[36], c_Sref2[144], c_Wref2[36], c_M1ref2[9], c_abs2[6];
+
+struct RefTables {
+  std::vector<double> M, S, W, M1, absphi;
+  double mass_lo = 0, mass_hi = 0, p1_lo = 0, p1_hi = 0;
+};
+
+// Grundmann-Moller rule of degree 2s+1 on the d-simplex (volume 1/d!), points in
+// barycentric coordinates.
+void gm_rule(int d, int s, std::vector<std::vector<double>>& pts, std::vector<double>& wts) {
+  const int deg = 2 * s + 1;
+  auto fact = [](int k) {
+    double f = 1;
+    for (int i = 2; i <= k; ++i) f *= i;
+    return f;
+  };
+  for (int i = 0; i <= s; ++i) {
+    const double w = ((i % 2) ? -1.0 : 1.0) * std::pow(2.0, -2 * s) * std::pow(double(deg + d - 2 * i), deg) /
+                     (fact(i) * fact(deg + d - i));
+    const int tot = s - i;
+    std::vector<int> beta(d + 1, 0);
+    // enumerate compositions of tot into d+1 parts
+    std::function<void(int, int)> rec = [&](int pos, int left) {
+      if (pos == d) {
+        beta[d] = left;
+        std::vector<double> lam(d + 1);
+        for (int j = 0; j <= d; ++j) lam[j] = (2.0 * beta[j] + 1.0) / double(deg + d - 2 * i);
+        pts.push_back(lam);
+        wts.push_back(w);
+        return;
+      }
+      for (int b = 0; b <= left; ++b) {
+        beta[pos] = b;
+        rec(pos + 1, left - b);
+      }
+    };
+    rec(0, tot);
+  }
+}
+
+// Symmetric Jacobi eigenvalue sweep (small dense matrices, host).
+void sym_eig_extremes(std::vector<double> A, int n, double& lo, double& hi) {
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += A[p * n + q] * A[p * n + q];
+    if (off < 1e-30) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double th = 0.5 * (A[q * n + q] - A[p * n + p]) / apq;
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - s * akq;
+          A[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - s * aqk;
+          A[q * n + k] = s * apk + c * aqk;
+        }
+      }
+  }
+  lo = hi = A[0];
+  for (int i = 1; i < n; ++i) {
+    lo = std::min(lo, A[i * n + i]);
+    hi = std::max(hi, A[i * n + i]);
+  }
+}
+
+RefTables make_tables(int d) {
+  RefTables t;
+  const int nv = d + 1, nl = d == 3 ? 10 : 6;
+  std::vector<std::pair<int, int>> edges;
+  for (int a = 0; a < nv; ++a)
+    for (int b = a + 1; b < nv; ++b) edges.emplace_back(a, b);
+  std::vector<std::vector<double>> pts;
+  std::vector<double> wts;
+  gm_rule(d, 2, pts, wts);
+  double volref = 1.0;
+  for (int i = 2; i <= d; ++i) volref /= i;
+  // d lambda_a / d xi_p, with lambda_0 = 1 - sum xi, lambda_a = xi_{a-1}
+  auto dlam = [&](int a, int p) { return a == 0 ? -1.0 : (a - 1 == p ? 1.0 : 0.0); };
+  t.M.assign(nl * nl, 0);
+  t.S.assign(nl * d * nl * d, 0);
+  t.W.assign(nv * nl * d, 0);
+  t.M1.assign(nv * nv, 0);
+  for (size_t q = 0; q < pts.size(); ++q) {
+    const auto& L = pts[q];
+    const double w = wts[q] / volref;
+    std::vector<double> phi(nl), g(nl * d);
+    for (int a = 0; a < nv; ++a) {
+      phi[a] = L[a] * (2.0 * L[a] - 1.0);
+      for (int p = 0; p < d; ++p) g[a * d + p] = (4.0 * L[a] - 1.0) * dlam(a, p);
+    }
+    for (size_t k = 0; k < edges.size(); ++k) {
+      const int a = edges[k].first, b = edges[k].second;
+      phi[nv + k] = 4.0 * L[a] * L[b];
+      for (int p = 0; p < d; ++p) g[(nv + k) * d + p] = 4.0 * (dlam(a, p) * L[b] + L[a] * dlam(b, p));
+    }
+    for (int i = 0; i < nl; ++i)
+      for (int j = 0; j < nl; ++j) {
+        t.M[i * nl + j] += w * phi[i] * phi[j];
+        for (int p = 0; p < d; ++p)
+          for (int r = 0; r < d; ++r) t.S[((i * d + p) * nl + j) * d + r] += w * g[i * d + p] * g[j * d + r];
+      }
+    for (int k = 0; k < nv; ++k)
+      for (int i = 0; i < nl; ++i)
+        for (int p = 0; p < d; ++p) t.W[(k * nl + i) * d + p] += w * L[k] * g[i * d + p];
+    for (int a = 0; a < nv; ++a)
+      for (int b = 0; b < nv; ++b) t.M1[a * nv + b] += w * L[a] * L[b];
+  }
+  // int |phi| / |K|: the vertex function lambda(2 lambda - 1) changes sign at
+  // lambda = 1/2; integrating against the density d (1 - t)^(d-1) of one
+  // barycentric coordinate on each side gives 3/32 (3D) and 1/8 (2D).  Edge
+  // functions are non-negative, so their value is int phi = 1/5 (3D), 1/3 (2D).
+  t.absphi.assign(nl, 0);
+  for (int i = 0; i < nl; ++i) t.absphi[i] = i < nv ? (d == 3 ? 3.0 / 32.0 : 1.0 / 8.0) : (d == 3 ? 0.2 : 1.0 / 3.0);
+  // Element bounds of the Jacobi-scaled mass matrices (shape independent on
+  // affine simplices): eigenvalues of D^{-1/2} Mref D^{-1/2}.
+  auto scaled = [](const std::vector<double>& A, int n) {
+    std::vector<double> B(A);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) B[i * n + j] = A[i * n + j] / std::sqrt(A[i * n + i] * A[j * n + j]);
+    return B;
+  };
+  sym_eig_extremes(scaled(t.M, nl), nl, t.mass_lo, t.mass_hi);
+  sym_eig_extremes(scaled(t.M1, nv), nv, t.p1_lo, t.p1_hi);
+  return t;
+}
+
+RefTables g_tab2, g_tab3;
+
+void upload_tables() {
+  static bool done = false;
+  if (done) return;
+  g_tab2 = make_tables(2);
+  g_tab3 = make_tables(3);
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_Mref3), g_tab3.M.data(), 100 * sizeof(double)));
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_Sref3), g_tab3.S.data(), 900 * sizeof(double)));
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_Wref3), g_tab3.W.data(), 120 * sizeof(double)));
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_M1ref3), g_tab3.M1.data(), 16 * sizeof(double)));
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_abs3), g_tab3.absphi.data(), 10 * sizeof(double)));
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_Mref2), g_tab2.M.data(), 36 * sizeof(double)));
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_Sref2), g_tab2.S.data(), 144 * sizeof(double)));
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_Wref2), g_tab2.W.data(), 36 * sizeof(double)));
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_M1ref2), g_tab2.M1.data(), 9 * sizeof(double)));
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_abs2), g_tab2.absphi.data(), 6 * sizeof(double)));
+  done = true;
+}
+
+template <int D>
+struct Tab {
+  static constexpr int NL = D == 3 ? 10 : 6;
+  static constexpr int NV = D + 1;
+  __device__ static double M(int i, int j) { return D == 3 ? c_Mref3[i * NL + j] : c_Mref2[i * NL + j]; }
+  __device__ static double S(int i, int p, int j, int r) {
+    const int k = ((i * D + p) * NL + j) * D + r;
+    return D == 3 ? c_Sref3[k] : c_Sref2[k];
+  }
+  __device__ static double W(int k, int i, int p) {
+    const int o = (k * NL + i) * D + p;
+    return D == 3 ? c_Wref3[o] : c_Wref2[o];
+  }
+  __device__ static double M1(int a, int b) { return D == 3 ? c_M1ref3[a * NV + b] : c_M1ref2[a * NV + b]; }
+  __device__ static double absphi(int i) { return D == 3 ? c_abs3[i] : c_abs2[i]; }
+};
+
+// |K| and J^{-1} (stored [p][c]) of every simplex
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_geom(int64_t n_e, const double* __restrict__ vc,
+                                                 const int32_t* __restrict__ el, double* __restrict__ vol,
+                                                 double* __restrict__ jinv) {
+  GRID_STRIDE_ROWS(e, n_e) {
+    double X[D + 1][D];
+    for (int a = 0; a <= D; ++a)
+      for (int c = 0; c < D; ++c) X[a][c] = vc[(int64_t)el[e * (D + 1) + a] * D + c];
+    double J[D][D];  // J[c][p] = X[p+1][c] - X[0][c]
+    for (int c = 0; c < D; ++c)
+      for (int p = 0; p < D; ++p) J[c][p] = X[p + 1][c] - X[0][c];
+    double det, inv[D][D];
+    if (D == 2) {
+      det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      inv[0][0] = J[1][1] / det;
+      inv[0][1] = -J[0][1] / det;
+      inv[1][0] = -J[1][0] / det;
+      inv[1][1] = J[0][0] / det;
+    } else {
+      const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+      const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+      const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+      det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+      // inverse = adj(J) / det, adj = cofactor^T
+      inv[0][0] = c00 / det;
+      inv[1][0] = c01 / det;
+      inv[2][0] = c02 / det;
+      inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+      inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+      inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+      inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+      inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+      inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    }
+    vol[e] = fabs(det) / (D == 3 ? 6.0 : 2.0);
+    for (int p = 0; p < D; ++p)
+      for (int c = 0; c < D; ++c) jinv[e * D * D + p * D + c] = inv[p][c];
+  }
+}
+
+__device__ __forceinline__ int64_t find_slot(const int32_t* __restrict__ cols, int64_t lo, int64_t hi, int32_t c) {
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (cols[mid] < c) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// rows of M_s and L_s over all P2 nodes
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_gather_p2(int64_t n_p2, const int64_t* __restrict__ iptr,
+                                                      const int32_t* __restrict__ ilist,
+                                                      const int32_t* __restrict__ p2, const double* __restrict__ vol,
+                                                      const double* __restrict__ jinv, const int32_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ cols, double* __restrict__ Mo,
+                                                      double* __restrict__ Lo) {
+  using Tb = Tab<D>;
+  GRID_STRIDE_ROWS(v, n_p2) {
+    const int64_t lo = rp[v], hi = rp[v + 1];
+    for (int64_t k = iptr[v]; k < iptr[v + 1]; ++k) {
+      const int64_t e = ilist[k] >> 4;
+      const int i = ilist[k] & 15;
+      const double V = vol[e];
+      double K[D][D];
+      for (int p = 0; p < D; ++p)
+        for (int r = 0; r < D; ++r) {
+          double s = 0;
+          for (int c = 0; c < D; ++c) s += jinv[e * D * D + p * D + c] * jinv[e * D * D + r * D + c];
+          K[p][r] = s;
+        }
+      for (int j = 0; j < Tb::NL; ++j) {
+        double l = 0;
+        for (int p = 0; p < D; ++p)
+          for (int r = 0; r < D; ++r) l += K[p][r] * Tb::S(i, p, j, r);
+        const int64_t slot = find_slot(cols, lo, hi, p2[e * Tb::NL + j]);
+        Mo[slot] += V * Tb::M(i, j);
+        Lo[slot] += V * l;
+      }
+    }
+  }
+}
+
+// rows of B (one per P1 vertex, D planes) over all P2 columns
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_gather_b(int64_t n_p1, const int64_t* __restrict__ iptr,
+                                                     const int32_t* __restrict__ ilist,
+                                                     const int32_t* __restrict__ p2, const double* __restrict__ vol,
+                                                     const double* __restrict__ jinv, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ cols, double* __restrict__ Bo) {
+  using Tb = Tab<D>;
+  GRID_STRIDE_ROWS(v, n_p1) {
+    const int64_t lo = rp[v], hi = rp[v + 1];
+    for (int64_t k = iptr[v]; k < iptr[v + 1]; ++k) {
+      const int64_t e = ilist[k] >> 4;
+      const int a = ilist[k] & 15;
+      const double V = vol[e];
+      for (int j = 0; j < Tb::NL; ++j) {
+        const int64_t slot = find_slot(cols, lo, hi, p2[e * Tb::NL + j]);
+        for (int c = 0; c < D; ++c) {
+          double s = 0;
+          for (int p = 0; p < D; ++p) s += jinv[e * D * D + p * D + c] * Tb::W(a, j, p);
+          Bo[slot * D + c] += V * s;
+        }
+      }
+    }
+  }
+}
+
+// rows of M_Q and L_Q
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_gather_q(int64_t n_p1, const int64_t* __restrict__ iptr,
+                                                     const int32_t* __restrict__ ilist,
+                                                     const int32_t* __restrict__ el, const double* __restrict__ vol,
+                                                     const double* __restrict__ jinv, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ cols, double* __restrict__ MQ,
+                                                     double* __restrict__ LQ) {
+  using Tb = Tab<D>;
+  GRID_STRIDE_ROWS(v, n_p1) {
+    const int64_t lo = rp[v], hi = rp[v + 1];
+    for (int64_t k = iptr[v]; k < iptr[v + 1]; ++k) {
+      const int64_t e = ilist[k] >> 4;
+      const int a = ilist[k] & 15;
+      const double V = vol[e];
+      double ga[D];
+      for (int c = 0; c < D; ++c) {  // physical gradient of lambda_a
+        double s = 0;
+        for (int p = 0; p < D; ++p) s += jinv[e * D * D + p * D + c] * (a == 0 ? -1.0 : (a - 1 == p ? 1.0 : 0.0));
+        ga[c] = s;
+      }
+      for (int b = 0; b <= D; ++b) {
+        double l = 0;
+        for (int c = 0; c < D; ++c) {
+          double s = 0;
+          for (int p = 0; p < D; ++p) s += jinv[e * D * D + p * D + c] * (b == 0 ? -1.0 : (b - 1 == p ? 1.0 : 0.0));
+          l += ga[c] * s;
+        }
+        const int64_t slot = find_slot(cols, lo, hi, el[e * (D + 1) + b]);
+        MQ[slot] += V * Tb::M1(a, b);
+        LQ[slot] += V * l;
+      }
+    }
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_gather_lam(int64_t n_p2, const int64_t* __restrict__ iptr,
+                                                       const int32_t* __restrict__ ilist,
+                                                       const double* __restrict__ vol, double* __restrict__ lam) {
+  GRID_STRIDE_ROWS(v, n_p2) {
+    double s = 0;
+    for (int64_t k = iptr[v]; k < iptr[v + 1]; ++k) s += vol[ilist[k] >> 4] * Tab<D>::absphi(ilist[k] & 15);
+    lam[v] = s;
+  }
+}
+
+// out[k*planes + c] = a * v1[src*planes + c] + b * v2[...]   (0 on padding)
+__global__ __launch_bounds__(kBlock) void k_fill(int64_t n, const int32_t* __restrict__ src, int planes, double a,
+                                                 const double* __restrict__ v1, double b, const double* __restrict__ v2,
+                                                 double* __restrict__ out) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = src[k];
+    for (int c = 0; c < planes; ++c) {
+      double o = 0;
+      if (s >= 0) {
+        o = a * v1[s * planes + c];
+        if (v2) o += b * v2[s * planes + c];
+      }
+      out[k * planes + c] = o;
+    }
+  }
+}
+
+// inverse diagonal of a scalar SELL matrix (diagonal entry has column == row)
+__global__ __launch_bounds__(kBlock) void k_dinv(int64_t nrows, const int64_t* __restrict__ sp,
+                                                 const int32_t* __restrict__ cols, const double* __restrict__ vals,
+                                                 double* __restrict__ out) {
+  GRID_STRIDE_ROWS(row, nrows) {
+    const int64_t s = row >> 6;
+    double dv = 0;
+    for (int64_t k = sp[s] + (row & 63); k < sp[s + 1]; k += 64)
+      if (cols[k] == row) dv = vals[k];
+    out[row] = dv != 0 ? 1.0 / dv : 0.0;
+  }
+}
+
+// row abs-sum times inverse diagonal (Gershgorin bound of D^{-1} S)
+__global__ __launch_bounds__(kBlock) void k_gersh(int64_t nrows, const int64_t* __restrict__ sp,
+                                                  const int32_t* __restrict__ vals_cols_dummy,
+                                                  const double* __restrict__ vals, const double* __restrict__ dinv,
+                                                  double* __restrict__ out) {
+  GRID_STRIDE_ROWS(row, nrows) {
+    const int64_t s = row >> 6;
+    double a = 0;
+    for (int64_t k = sp[s] + (row & 63); k < sp[s + 1]; k += 64) a += fabs(vals[k]);
+    out[row] = a * fabs(dinv[row]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_lam_int(int64_t n_int, const int32_t* __restrict__ int2nat,
+                                                    const double* __restrict__ lam, double* __restrict__ out) {
+  GRID_STRIDE_ROWS(k, n_int) out[k] = 1.0 / lam[int2nat[k]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_rowsum_csr(int64_t nrows, const int32_t* __restrict__ rp,
+                                                       const double* __restrict__ v, double* __restrict__ out) {
+  GRID_STRIDE_ROWS(row, nrows) {
+    double s = 0;
+    for (int64_t k = rp[row]; k < rp[row + 1]; ++k) s += v[k];
+    out[row] = s;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mul(int64_t n, const double* __restrict__ a, const double* __restrict__ x,
+                                                double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a[i] * x[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_sqrt(int64_t n, const double* __restrict__ a, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = sqrt(a[i]);
+}
+
+// ------------------------------------------------------------ SELL build
+
+// rows_in_order[r] = source row of output row r; entries kept where
+// col_map[col] >= 0; entry_map (optional) renames source entries.
+void build_sell(const HostCsr& in, const std::vector<int32_t>& rows_in_order, const std::vector<int32_t>& col_map,
+                const std::vector<int64_t>* entry_map, int planes, Sell& out) {
+  const int64_t nrows = static_cast<int64_t>(rows_in_order.size());
+  const int64_t nsl = (nrows + 63) / 64;
+  std::vector<int64_t> sp(nsl + 1, 0);
+  std::vector<int32_t> len(nrows, 0);
+  int64_t nnz = 0;
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t s = rows_in_order[r];
+    int32_t c = 0;
+    for (int64_t k = in.rowptr[s]; k < in.rowptr[s + 1]; ++k)
+      if (col_map[in.cols[k]] >= 0) ++c;
+    len[r] = c;
+    nnz += c;
+  }
+  for (int64_t s = 0; s < nsl; ++s) {
+    int32_t w = 0;
+    for (int64_t r = s * 64; r < std::min(nrows, (s + 1) * 64); ++r) w = std::max(w, len[r]);
+    sp[s + 1] = sp[s] + 64 * int64_t(w);
+  }
+  const int64_t npad = sp[nsl];
+  if (npad >= (int64_t(1) << 31)) throw Error(STOKES_ERR_UNSUPPORTED, "sparse operator exceeds 2^31 entries");
+  std::vector<int32_t> cols(npad, 0), src(npad, -1);
+  std::vector<std::pair<int32_t, int64_t>> buf;
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t s = rows_in_order[r];
+    buf.clear();
+    for (int64_t k = in.rowptr[s]; k < in.rowptr[s + 1]; ++k) {
+      const int32_t c = col_map[in.cols[k]];
+      if (c >= 0) buf.emplace_back(c, entry_map ? (*entry_map)[k] : k);
+    }
+    std::sort(buf.begin(), buf.end());
+    const int64_t base = sp[r / 64] + (r % 64);
+    for (size_t j = 0; j < buf.size(); ++j) {
+      cols[base + 64 * j] = buf[j].first;
+      src[base + 64 * j] = static_cast<int32_t>(buf[j].second);
+    }
+    // padding points at the row itself when square, else column 0
+  }
+  out.nrows = nrows;
+  out.nslices = nsl;
+  out.nnz = nnz;
+  out.nnz_pad = npad;
+  out.planes = planes;
+  upload(out.slice_ptr, sp);
+  upload(out.cols, cols);
+  upload(out.src, src);
+}
+
+template <class K, class... A>
+void launch(stokes_ctx* c, int64_t n, K kern, A... args) {
+  const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 65535));
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, args...);
+  HIP_CHECK(hipGetLastError());
+}
+
+// Tridiagonal Lanczos extreme eigenvalues by Sturm bisection.
+void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b, double& lo, double& hi) {
+  const int k = static_cast<int>(a.size());
+  double gl = 1e300, gh = -1e300;
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0) + (i + 1 < k ? std::fabs(b[i]) : 0);
+    gl = std::min(gl, a[i] - r);
+    gh = std::max(gh, a[i] + r);
+  }
+  auto count_below = [&](double x) {  // number of eigenvalues < x
+    int cnt = 0;
+    double q = a[0] - x;
+    if (q < 0) ++cnt;
+    for (int i = 1; i < k; ++i) {
+      if (q == 0) q = 1e-300;
+      q = a[i] - x - b[i - 1] * b[i - 1] / q;
+      if (q < 0) ++cnt;
+    }
+    return cnt;
+  };
+  double l = gl, h = gh;
+  for (int it = 0; it < 200; ++it) {  // largest: count_below(x) == k - 1 boundary
+    const double m = 0.5 * (l + h);
+    if (count_below(m) >= k) h = m;
+    else l = m;
+  }
+  hi = h;
+  l = gl;
+  h = gh;
+  for (int it = 0; it < 200; ++it) {  // smallest
+    const double m = 0.5 * (l + h);
+    if (count_below(m) >= 1) h = m;
+    else l = m;
+  }
+  lo = l;
+}
+
+}  // namespace
+
+// Lanczos on D^{-1/2} S D^{-1/2} (FP64, scalar SELL); returns Ritz extremes.
+void lanczos_bounds(stokes_ctx* c, const Sell& S, const double* vals, const double* dinv, int steps, double& rlo,
+                    double& rhi, double& gersh) {
+  const int64_t n = S.nrows;
+  double* sq = static_cast<double*>(c->workspace("lz_sq", n * sizeof(double)));
+  double* v0 = static_cast<double*>(c->workspace("lz_v0", n * sizeof(double)));
+  double* v1 = static_cast<double*>(c->workspace("lz_v1", n * sizeof(double)));
+  double* t = static_cast<double*>(c->workspace("lz_t", n * sizeof(double)));
+  double* w = static_cast<double*>(c->workspace("lz_w", n * sizeof(double)));
+  launch(c, n, k_sqrt, n, dinv, sq);
+  // Gershgorin bound of D^{-1} S
+  launch(c, n, k_gersh, n, S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, dinv, t);
+  {
+    std::vector<double> h(n);
+    HIP_CHECK(hipMemcpyAsync(h.data(), t, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    gersh = *std::max_element(h.begin(), h.end());
+  }
+  // deterministic start vector: smooth-plus-oscillating pattern
+  {
+    std::vector<double> h(n);
+    for (int64_t i = 0; i < n; ++i) h[i] = 1.0 + 0.5 * std::sin(0.7 * double(i)) + 0.25 * std::cos(1.3 * double(i));
+    double nn = 0;
+    for (double x : h) nn += x * x;
+    for (double& x : h) x /= std::sqrt(nn);
+    HIP_CHECK(hipMemcpyAsync(v1, h.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_CHECK(hipMemsetAsync(v0, 0, n * sizeof(double), c->stream));
+  }
+  std::vector<double> al, be;
+  double beta_prev = 0;
+  for (int j = 0; j < steps; ++j) {
+    // w = sq .* S (sq .* v1)
+    launch(c, n, k_mul, n, sq, v1, t);
+    ops::spmv<double>(c, S, vals, 1, t, w, 1.0, nullptr, 0.0);
+    launch(c, n, k_mul, n, sq, w, w);
+    const double a = ops::dot_host<double>(c, n, 1, v1, w)[0];
+    // w = w - a v1 - beta_prev v0
+    launch(c, n, k_axpby<double>, n, -a, (const double*)v1, 1.0, w);
+    if (j > 0) launch(c, n, k_axpby<double>, n, -beta_prev, (const double*)v0, 1.0, w);
+    const double bn = std::sqrt(ops::dot_host<double>(c, n, 1, w, w)[0]);
+    al.push_back(a);
+    if (j + 1 == steps || bn < 1e-14 * std::fabs(a)) break;
+    be.push_back(bn);
+    std::swap(v0, v1);
+    launch(c, n, k_axpby<double>, n, 1.0 / bn, (const double*)w, 0.0, v1);
+    beta_prev = bn;
+  }
+  be.resize(al.size() > 0 ? al.size() - 1 : 0);
+  tridiag_extremes(al, be, rlo, rhi);
+}
+
+void assemble_ctx(stokes_ctx* c) {
+  upload_tables();
+  const HostMesh& m = c->mesh;
+  const int D = m.dim;
+  const int nv = D + 1;
+
+  // ---- host patterns
+  HostCsr P2full, Bfull, P1;
+  element_pattern(m.p2, m.nloc, m.n_p2, m.p2, m.nloc, m.n_p2, m.n_e, P2full);
+  element_pattern(m.elems, nv, m.n_p1, m.p2, m.nloc, m.n_p2, m.n_e, Bfull);
+  element_pattern(m.elems, nv, m.n_p1, m.elems, nv, m.n_p1, m.n_e, P1);
+  if (P2full.rowptr.back() >= (int64_t(1) << 31) || Bfull.rowptr.back() * D >= (int64_t(1) << 31))
+    throw Error(STOKES_ERR_UNSUPPORTED, "mesh too large for 32-bit sparse indices");
+
+  // internal numbering: interior nodes by decreasing interior row length
+  std::vector<int32_t> interior;
+  std::vector<int32_t> ilen(m.n_p2, 0);
+  for (int64_t v = 0; v < m.n_p2; ++v) {
+    if (m.p2_bnd[v]) continue;
+    interior.push_back(static_cast<int32_t>(v));
+    int32_t cnt = 0;
+    for (int64_t k = P2full.rowptr[v]; k < P2full.rowptr[v + 1]; ++k)
+      if (!m.p2_bnd[P2full.cols[k]]) ++cnt;
+    ilen[v] = cnt;
+  }
+  std::stable_sort(interior.begin(), interior.end(), [&](int32_t a, int32_t b) { return ilen[a] > ilen[b]; });
+  c->n_int = static_cast<int64_t>(interior.size());
+  c->h_int2nat = interior;
+  c->h_nat2int.assign(m.n_p2, -1);
+  for (int64_t k = 0; k < c->n_int; ++k) c->h_nat2int[interior[k]] = static_cast<int32_t>(k);
+  upload(c->int2nat, c->h_int2nat);
+  upload(c->nat2int, c->h_nat2int);
+
+  // ---- upload mesh + incidences, geometry
+  DevBuf d_vc, d_el, d_p2, d_vol, d_jinv, d_i2p, d_i2l, d_i1p, d_i1l;
+  upload(d_vc, m.vcoords);
+  upload(d_el, m.elems);
+  upload(d_p2, m.p2);
+  d_vol.alloc(m.n_e * sizeof(double));
+  d_jinv.alloc(m.n_e * D * D * sizeof(double));
+  if (D == 3) launch(c, m.n_e, k_geom<3>, m.n_e, d_vc.as<double>(), d_el.as<int32_t>(), d_vol.as<double>(), d_jinv.as<double>());
+  else launch(c, m.n_e, k_geom<2>, m.n_e, d_vc.as<double>(), d_el.as<int32_t>(), d_vol.as<double>(), d_jinv.as<double>());
+  {
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> lst;
+    incidence(m.p2, m.nloc, m.n_e, m.n_p2, ptr, lst);
+    upload(d_i2p, ptr);
+    upload(d_i2l, lst);
+    incidence(m.elems, nv, m.n_e, m.n_p1, ptr, lst);
+    upload(d_i1p, ptr);
+    upload(d_i1l, lst);
+  }
+  auto up_csr = [&](const HostCsr& h, DevCsr& dcsr) {
+    std::vector<int32_t> rp(h.rowptr.begin(), h.rowptr.end());
+    dcsr.nrows = h.nrows;
+    dcsr.nnz = h.rowptr.back();
+    upload(dcsr.rowptr, rp);
+    upload(dcsr.cols, h.cols);
+  };
+  up_csr(P2full, c->p2full);
+  up_csr(Bfull, c->bfull);
+  up_csr(P1, c->p1);
+
+  // ---- element gathers (FP64, full numbering)
+  const int64_t nnz2 = c->p2full.nnz, nnzb = c->bfull.nnz, nnz1 = c->p1.nnz;
+  c->M_full.alloc(nnz2 * sizeof(double));
+  c->L_full.alloc(nnz2 * sizeof(double));
+  c->B_full.alloc(nnzb * D * sizeof(double));
+  c->MQ_csr.alloc(nnz1 * sizeof(double));
+  c->LQ_csr.alloc(nnz1 * sizeof(double));
+  c->lam_full.alloc(m.n_p2 * sizeof(double));
+  HIP_CHECK(hipMemsetAsync(c->M_full.p, 0, nnz2 * sizeof(double), c->stream));
+  HIP_CHECK(hipMemsetAsync(c->L_full.p, 0, nnz2 * sizeof(double), c->stream));
+  HIP_CHECK(hipMemsetAsync(c->B_full.p, 0, nnzb * D * sizeof(double), c->stream));
+  HIP_CHECK(hipMemsetAsync(c->MQ_csr.p, 0, nnz1 * sizeof(double), c->stream));
+  HIP_CHECK(hipMemsetAsync(c->LQ_csr.p, 0, nnz1 * sizeof(double), c->stream));
+  if (D == 3) {
+    launch(c, m.n_p2, k_gather_p2<3>, m.n_p2, d_i2p.as<int64_t>(), d_i2l.as<int32_t>(), d_p2.as<int32_t>(),
+           d_vol.as<double>(), d_jinv.as<double>(), c->p2full.rowptr.as<int32_t>(), c->p2full.cols.as<int32_t>(),
+           c->M_full.as<double>(), c->L_full.as<double>());
+    launch(c, m.n_p1, k_gather_b<3>, m.n_p1, d_i1p.as<int64_t>(), d_i1l.as<int32_t>(), d_p2.as<int32_t>(),
+           d_vol.as<double>(), d_jinv.as<double>(), c->bfull.rowptr.as<int32_t>(), c->bfull.cols.as<int32_t>(),
+           c->B_full.as<double>());
+    launch(c, m.n_p1, k_gather_q<3>, m.n_p1, d_i1p.as<int64_t>(), d_i1l.as<int32_t>(), d_el.as<int32_t>(),
+           d_vol.as<double>(), d_jinv.as<double>(), c->p1.rowptr.as<int32_t>(), c->p1.cols.as<int32_t>(),
+           c->MQ_csr.as<double>(), c->LQ_csr.as<double>());
+    launch(c, m.n_p2, k_gather_lam<3>, m.n_p2, d_i2p.as<int64_t>(), d_i2l.as<int32_t>(), d_vol.as<double>(),
+           c->lam_full.as<double>());
+  } else {
+    launch(c, m.n_p2, k_gather_p2<2>, m.n_p2, d_i2p.as<int64_t>(), d_i2l.as<int32_t>(), d_p2.as<int32_t>(),
+           d_vol.as<double>(), d_jinv.as<double>(), c->p2full.rowptr.as<int32_t>(), c->p2full.cols.as<int32_t>(),
+           c->M_full.as<double>(), c->L_full.as<double>());
+    launch(c, m.n_p1, k_gather_b<2>, m.n_p1, d_i1p.as<int64_t>(), d_i1l.as<int32_t>(), d_p2.as<int32_t>(),
+           d_vol.as<double>(), d_jinv.as<double>(), c->bfull.rowptr.as<int32_t>(), c->bfull.cols.as<int32_t>(),
+           c->B_full.as<double>());
+    launch(c, m.n_p1, k_gather_q<2>, m.n_p1, d_i1p.as<int64_t>(), d_i1l.as<int32_t>(), d_el.as<int32_t>(),
+           d_vol.as<double>(), d_jinv.as<double>(), c->p1.rowptr.as<int32_t>(), c->p1.cols.as<int32_t>(),
+           c->MQ_csr.as<double>(), c->LQ_csr.as<double>());
+    launch(c, m.n_p2, k_gather_lam<2>, m.n_p2, d_i2p.as<int64_t>(), d_i2l.as<int32_t>(), d_vol.as<double>(),
+           c->lam_full.as<double>());
+  }
+
+  // ---- SELL operators
+  std::vector<int32_t> p1_rows(m.n_p1), p1_ident(m.n_p1);
+  std::iota(p1_rows.begin(), p1_rows.end(), 0);
+  std::iota(p1_ident.begin(), p1_ident.end(), 0);
+  build_sell(P2full, c->h_int2nat, c->h_nat2int, nullptr, 1, c->sA);
+  build_sell(Bfull, p1_rows, c->h_nat2int, nullptr, D, c->sB);
+  {
+    HostCsr BT;
+    std::vector<int64_t> tsrc;
+    transpose_pattern(Bfull, BT, tsrc);
+    build_sell(BT, c->h_int2nat, p1_ident, &tsrc, D, c->sBt);
+  }
+  build_sell(P1, p1_rows, p1_ident, nullptr, 1, c->sQ);
+
+  auto fill = [&](const Sell& S, DevBuf& out, double a, const DevBuf& v1, double b, const DevBuf* v2) {
+    out.alloc(S.nnz_pad * S.planes * sizeof(double));
+    launch(c, S.nnz_pad, k_fill, S.nnz_pad, S.src.as<int32_t>(), S.planes, a, v1.as<double>(), b,
+           v2 ? v2->as<double>() : nullptr, out.as<double>());
+  };
+  const double alpha = c->prob.alpha, mu = c->prob.mu;
+  fill(c->sA, c->A64, alpha, c->M_full, mu, &c->L_full);
+  fill(c->sA, c->MV64, 1.0, c->M_full, 0.0, nullptr);
+  fill(c->sB, c->B64, 1.0, c->B_full, 0.0, nullptr);
+  fill(c->sBt, c->Bt64, 1.0, c->B_full, 0.0, nullptr);
+  fill(c->sQ, c->MQ64, 1.0, c->MQ_csr, 0.0, nullptr);
+  fill(c->sQ, c->LQ64, 1.0, c->LQ_csr, 0.0, nullptr);
+  fill(c->sQ, c->XQ64, 1.0, c->MQ_csr, 1.0, &c->LQ_csr);
+
+  auto dinv = [&](const Sell& S, const DevBuf& v, DevBuf& out) {
+    out.alloc(S.nrows * sizeof(double));
+    launch(c, S.nrows, k_dinv, S.nrows, S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), v.as<double>(),
+           out.as<double>());
+  };
+  dinv(c->sA, c->A64, c->dA64);
+  dinv(c->sA, c->MV64, c->dMV64);
+  dinv(c->sQ, c->MQ64, c->dMQ64);
+  dinv(c->sQ, c->XQ64, c->dXQ64);
+  dinv(c->sQ, c->LQ64, c->dLQ64);
+  c->lamInv64.alloc(c->n_int * sizeof(double));
+  launch(c, c->n_int, k_lam_int, c->n_int, c->int2nat.as<int32_t>(), c->lam_full.as<double>(), c->lamInv64.as<double>());
+  c->mQ.alloc(m.n_p1 * sizeof(double));
+  launch(c, m.n_p1, k_rowsum_csr, m.n_p1, c->p1.rowptr.as<int32_t>(), c->MQ_csr.as<double>(), c->mQ.as<double>());
+  {
+    std::vector<double> h(m.n_p1);
+    HIP_CHECK(hipMemcpyAsync(h.data(), c->mQ.p, m.n_p1 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    c->mQ_sum = 0;
+    for (double x : h) c->mQ_sum += x;
+  }
+
+  // FP32 copies
+  auto to32 = [&](const DevBuf& src, DevBuf& dst, int64_t n) {
+    dst.alloc(n * sizeof(float));
+    launch(c, n, k_cast<double, float>, n, src.as<double>(), dst.as<float>());
+  };
+  to32(c->A64, c->A32, c->sA.nnz_pad);
+  to32(c->MV64, c->MV32, c->sA.nnz_pad);
+  to32(c->B64, c->B32, c->sB.nnz_pad * D);
+  to32(c->Bt64, c->Bt32, c->sBt.nnz_pad * D);
+  to32(c->MQ64, c->MQ32, c->sQ.nnz_pad);
+  to32(c->LQ64, c->LQ32, c->sQ.nnz_pad);
+  to32(c->XQ64, c->XQ32, c->sQ.nnz_pad);
+  to32(c->dA64, c->dA32, c->n_int);
+  to32(c->dMV64, c->dMV32, c->n_int);
+  to32(c->dMQ64, c->dMQ32, m.n_p1);
+  to32(c->dXQ64, c->dXQ32, m.n_p1);
+  to32(c->dLQ64, c->dLQ32, m.n_p1);
+  to32(c->lamInv64, c->lamInv32, c->n_int);
+
+  // ---- Chebyshev intervals
+  const RefTables& tb = D == 3 ? g_tab3 : g_tab2;
+  c->bMV = {tb.mass_lo, tb.mass_hi};
+  c->bMQ = {tb.p1_lo, tb.p1_hi};
+  estimate_bounds(c);
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+}
+
+void estimate_bounds(stokes_ctx* c) {
+  const int steps = 40;
+  double lo, hi, g;
+  lanczos_bounds(c, c->sA, c->A64.as<double>(), c->dA64.as<double>(), steps, lo, hi, g);
+  c->bA.hi = std::min(g, 1.05 * hi);
+  c->bA.lo = std::max(0.9 * lo, c->bA.hi / 1000.0);
+  lanczos_bounds(c, c->sQ, c->XQ64.as<double>(), c->dXQ64.as<double>(), steps, lo, hi, g);
+  c->bXQ.hi = std::min(g, 1.05 * hi);
+  c->bXQ.lo = std::max(0.9 * lo, c->bXQ.hi / 1000.0);
+  lanczos_bounds(c, c->sQ, c->LQ64.as<double>(), c->dLQ64.as<double>(), steps, lo, hi, g);
+  c->bLQ.hi = std::min(g, 1.05 * hi);
+  c->bLQ.lo = c->bLQ.hi / 100.0;  // L_Q is singular: the constant mode is projected out
+}
+
+// Re-form A = alpha M + mu L (SELL values and FP32 copy, diagonal, bounds).
+void reform_A(stokes_ctx* c) {
+  const int64_t n = c->sA.nnz_pad;
+  launch(c, n, k_fill, n, c->sA.src.as<int32_t>(), 1, c->prob.alpha, c->M_full.as<double>(), c->prob.mu,
+         c->L_full.as<double>(), c->A64.as<double>());
+  launch(c, n, k_cast<double, float>, n, c->A64.as<double>(), c->A32.as<float>());
+  launch(c, c->sA.nrows, k_dinv, c->sA.nrows, c->sA.slice_ptr.as<int64_t>(), c->sA.cols.as<int32_t>(),
+         c->A64.as<double>(), c->dA64.as<double>());
+  launch(c, c->n_int, k_cast<double, float>, c->n_int, c->dA64.as<double>(), c->dA32.as<float>());
+  double lo, hi, g;
+  lanczos_bounds(c, c->sA, c->A64.as<double>(), c->dA64.as<double>(), 40, lo, hi, g);
+  c->bA.hi = std::min(g, 1.05 * hi);
+  c->bA.lo = std::max(0.9 * lo, c->bA.hi / 1000.0);
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+}
+
+}  // namespace stokes

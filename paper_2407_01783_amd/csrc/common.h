@@ -1,0 +1,158 @@
+// Internal declarations shared by the HIP translation units of libstokes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/stokes.h"
+#include "mesh_host.h"
+
+namespace stokes {
+
+// ------------------------------------------------------------------ errors
+struct Error : std::runtime_error {
+  stokes_status code;
+  Error(stokes_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIP_CHECK(expr)                                                                        \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      throw ::stokes::Error(STOKES_ERR_HIP, std::string(#expr " failed: ") + hipGetErrorString(e_) + \
+                                                " (" __FILE__ ":" + std::to_string(__LINE__) + ")"); \
+  } while (0)
+
+void set_last_error(const std::string& msg);
+
+// --------------------------------------------------------- device buffers
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release();
+  void alloc(size_t b);          // exact size, contents undefined
+  void ensure(size_t b);         // grow-only
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+template <class T>
+void upload(DevBuf& b, const std::vector<T>& v) {
+  b.alloc(std::max<size_t>(1, v.size()) * sizeof(T));
+  if (!v.empty()) HIP_CHECK(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// Sliced ELL with slice height 64 (one wavefront), one thread per row.
+// Entry j of row r (slice s = r / 64, lane l = r % 64) sits at
+// slice_ptr[s] + 64 j + l; padding entries have column 0 and value 0.
+struct Sell {
+  int64_t nrows = 0, nslices = 0, nnz = 0, nnz_pad = 0;
+  int planes = 1;       // values per entry (B and B^T carry dim planes)
+  DevBuf slice_ptr;     // int64 [nslices + 1]
+  DevBuf cols;          // int32 [nnz_pad]
+  DevBuf src;           // int32 [nnz_pad] source entry in the assembled CSR (-1 = pad)
+};
+
+struct DevCsr {
+  int64_t nrows = 0, nnz = 0;
+  DevBuf rowptr;  // int32 [nrows + 1]
+  DevBuf cols;    // int32 [nnz]
+};
+
+// Chebyshev interval of a Jacobi-scaled SPD operator.
+struct Bounds {
+  double lo = 0, hi = 0;
+};
+
+// Reduction scratch for one-pass grid reductions (per context / stream).
+struct RedScratch {
+  DevBuf partials;  // double [max_blocks * max_slots]
+  DevBuf ticket;    // unsigned
+  DevBuf result;    // double [max_slots], last reduction result
+};
+
+constexpr int kMaxSys = 24;   // systems per batched solve (dim * rhs)
+constexpr int kMaxBlocks = 2048;
+constexpr int kBlock = 256;
+
+// Per-solver device scalars (one set per Krylov instance).
+struct Scalars {
+  double rho[kMaxSys], rho_old[kMaxSys], alpha[kMaxSys], beta[kMaxSys];
+  double sigma[kMaxSys], rr[kMaxSys], bb[kMaxSys], tol2[kMaxSys];
+  int active[kMaxSys];
+  int breakdown;
+};
+
+}  // namespace stokes
+
+struct stokes_ctx {
+  stokes_problem prob{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int dim = 0, nloc = 0;
+  int64_t n_p1 = 0, n_p2 = 0, n_e = 0, n_int = 0;
+
+  stokes::HostMesh mesh;  // kept for export
+
+  // full-numbering CSR matrices (assembly products)
+  stokes::DevCsr p2full, bfull, p1;
+  stokes::DevBuf M_full, L_full;  // double [nnz p2full]
+  stokes::DevBuf B_full;          // double [nnz bfull][dim]
+  stokes::DevBuf MQ_csr, LQ_csr;  // double [nnz p1]
+  stokes::DevBuf lam_full;        // double [n_p2]  Lambda_V
+
+  // internal numbering: interior P2 nodes sorted by row length of A_II
+  stokes::DevBuf int2nat;  // int32 [n_int]
+  stokes::DevBuf nat2int;  // int32 [n_p2], -1 on the boundary
+  std::vector<int32_t> h_int2nat, h_nat2int;
+
+  // SELL operators used inside the iterations
+  stokes::Sell sA;   // interior x interior (velocity), scalar values
+  stokes::Sell sB;   // P1 x interior, dim planes
+  stokes::Sell sBt;  // interior x P1, dim planes
+  stokes::Sell sQ;   // P1 x P1, scalar values
+  stokes::DevBuf A64, A32, MV64, MV32;       // values of A_II and M_II (SELL)
+  stokes::DevBuf B64, B32, Bt64, Bt32;       // [nnz_pad][dim]
+  stokes::DevBuf MQ64, MQ32, LQ64, LQ32, XQ64, XQ32;  // XQ = M_Q + L_Q
+  stokes::DevBuf dA64, dA32, dMV64, dMV32;   // inverse diagonals (interior)
+  stokes::DevBuf dMQ64, dMQ32, dXQ64, dXQ32, dLQ64, dLQ32;
+  stokes::DevBuf lamInv64, lamInv32;         // 1 / Lambda_V on interior nodes
+  stokes::DevBuf mQ;                         // M_Q 1 (double, n_p1)
+  double mQ_sum = 0;
+
+  stokes::Bounds bA, bMV, bMQ, bXQ, bLQ;
+
+  stokes::RedScratch red;
+  stokes::DevBuf scal;  // Scalars pool
+  int scal_count = 0;
+  std::map<std::string, stokes::DevBuf> ws;  // named workspaces (grow-only)
+
+  stokes::DevBuf ones64, ones32;  // n_p1 * 8 ones (pressure sums)
+
+  // timing of the dominant SpMV (opts.profile): event pairs, read at the end
+  int prof_on = 0, prof_idx = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+  double prof_bytes = 0;
+
+  // pinned host mirror of the solver scalars
+  stokes::Scalars* h_scal = nullptr;
+
+  std::map<std::string, std::pair<void*, size_t>> ws_host;  // pinned host buffers
+
+  void* workspace(const std::string& name, size_t bytes) {
+    auto& b = ws[name];
+    b.ensure(bytes);
+    return b.p;
+  }
+  void* workspace_host(const std::string& name, size_t bytes);
+  ~stokes_ctx();
+};

@@ -1,0 +1,813 @@
+// Device kernels of the solver: sliced-ELL SpMV/SpMM with fused Krylov
+// epilogues, B / B^T, one-pass deterministic grid reductions, vector updates
+// and layout conversions.  Everything here is memory-bandwidth bound; no MFMA.
+//
+// Vector layouts (internal):
+//   velocity  T[n_int][nrb][dim]   (W = dim * nrb values per interior node)
+//   pressure  T[n_p1][nrb]
+// Reductions produce one partial per "slot" w < W (the value index inside a
+// row); systems are groups of cps consecutive slots (cps = 1 for one CG per
+// component and right-hand side, cps = dim for a joint vector CG).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace stokes {
+
+// ------------------------------------------------------------ reductions
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// Reduce v[0..NS) over the block; thread s < NS receives the block total of
+// slot s in the return array `out` (shared).  Fixed order => deterministic.
+template <int NS>
+__device__ __forceinline__ void block_sum(double (&v)[NS], double* out_shared) {
+  __shared__ double sh[kBlock / 64][NS];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const double t = wave_sum(v[s]);
+    if (lane == 0) sh[wid][s] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < NS) {
+    double a = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) a += sh[w][threadIdx.x];
+    out_shared[threadIdx.x] = a;
+  }
+  __syncthreads();
+}
+
+// One-pass grid reduction: every block stores its NS partials, the last block
+// to arrive (atomic ticket) sums them in block order and calls fin(tot) with
+// the totals in shared memory; then the ticket is reset.  Returns true in the
+// last block.
+template <int NS, class Fin>
+__device__ __forceinline__ void grid_reduce(double (&v)[NS], double* partials, unsigned* ticket,
+                                            Fin fin) {
+  __shared__ double tot[NS];
+  __shared__ int last;
+  block_sum<NS>(v, tot);
+  if (threadIdx.x < NS) partials[(size_t)blockIdx.x * NS + threadIdx.x] = tot[threadIdx.x];
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(ticket, 1u) == gridDim.x - 1) ? 1 : 0;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double a[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) a[s] = 0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) a[s] += partials[(size_t)b * NS + s];
+  }
+  block_sum<NS>(a, tot);
+  fin(tot);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicExch(ticket, 0u);
+}
+
+// --------------------------------------------------------- SELL row sums
+
+template <typename T, int W>
+__device__ __forceinline__ void sell_row(const int64_t* __restrict__ sp, const int32_t* __restrict__ cols,
+                                         const T* __restrict__ vals, const T* __restrict__ x, int64_t row,
+                                         T (&acc)[W]) {
+  const int64_t s = row >> 6;
+  const int64_t end = sp[s + 1];
+  for (int64_t k = sp[s] + (row & 63); k < end; k += 64) {
+    const int32_t c = __builtin_nontemporal_load(cols + k);
+    const T v = __builtin_nontemporal_load(vals + k);
+    const T* xp = x + (int64_t)c * W;
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = fma(v, xp[w], acc[w]);
+  }
+}
+
+// B rows (pressure vertex): acc[r] = sum_j sum_c B^c_j u[col_j][r][c]
+template <typename T, int D, int NRB>
+__device__ __forceinline__ void sell_row_B(const int64_t* __restrict__ sp, const int32_t* __restrict__ cols,
+                                           const T* __restrict__ vals, const T* __restrict__ u, int64_t row,
+                                           T (&acc)[NRB]) {
+  const int64_t s = row >> 6;
+  const int64_t end = sp[s + 1];
+  for (int64_t k = sp[s] + (row & 63); k < end; k += 64) {
+    const int32_t c = __builtin_nontemporal_load(cols + k);
+    T b[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) b[d] = __builtin_nontemporal_load(vals + k * D + d);
+    const T* up = u + (int64_t)c * (D * NRB);
+#pragma unroll
+    for (int r = 0; r < NRB; ++r)
+#pragma unroll
+      for (int d = 0; d < D; ++d) acc[r] = fma(b[d], up[r * D + d], acc[r]);
+  }
+}
+
+// B^T rows (interior velocity node): acc[r][c] = sum_j B^c_j p[col_j][r]
+template <typename T, int D, int NRB>
+__device__ __forceinline__ void sell_row_Bt(const int64_t* __restrict__ sp, const int32_t* __restrict__ cols,
+                                            const T* __restrict__ vals, const T* __restrict__ p, int64_t row,
+                                            T (&acc)[D * NRB]) {
+  const int64_t s = row >> 6;
+  const int64_t end = sp[s + 1];
+  for (int64_t k = sp[s] + (row & 63); k < end; k += 64) {
+    const int32_t c = __builtin_nontemporal_load(cols + k);
+    T b[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) b[d] = __builtin_nontemporal_load(vals + k * D + d);
+    const T* pp = p + (int64_t)c * NRB;
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) {
+      const T pv = pp[r];
+#pragma unroll
+      for (int d = 0; d < D; ++d) acc[r * D + d] = fma(b[d], pv, acc[r * D + d]);
+    }
+  }
+}
+
+#define GRID_STRIDE_ROWS(row, nrows)                                                      \
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < (nrows);      \
+       row += (int64_t)gridDim.x * blockDim.x)
+
+// ----------------------------------------------------------- SpMV kernels
+
+// y = a * (S x) + b * yin   (yin may alias y; ignored when b == 0)
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, const int64_t* __restrict__ sp,
+                                                 const int32_t* __restrict__ cols, const T* __restrict__ vals,
+                                                 const T* __restrict__ x, T* y, T a, const T* yin, T b) {
+  GRID_STRIDE_ROWS(row, nrows) {
+    T acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = 0;
+    sell_row<T, W>(sp, cols, vals, x, row, acc);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      T o = a * acc[w];
+      if (b != T(0)) o = fma(b, yin[row * W + w], o);
+      y[row * W + w] = o;
+    }
+  }
+}
+
+// CG direction step with the product folded in:
+//   q = S z (+ extra) + beta q,  p = z + beta p,  sigma = p . q  -> alpha
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t nrows, const int64_t* __restrict__ sp,
+                                                    const int32_t* __restrict__ cols,
+                                                    const T* __restrict__ vals, const T* __restrict__ z,
+                                                    const T* __restrict__ extra, T* __restrict__ q,
+                                                    T* __restrict__ p, Scalars* sc, int cps, int nsys,
+                                                    double* partials, unsigned* ticket) {
+  T beta[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) beta[w] = (T)sc->beta[w / cps];
+  double part[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) part[w] = 0;
+  GRID_STRIDE_ROWS(row, nrows) {
+    T acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = 0;
+    if (sp) sell_row<T, W>(sp, cols, vals, z, row, acc);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const int64_t i = row * W + w;
+      T a = acc[w];
+      if (extra) a += extra[i];
+      const T qn = fma(beta[w], q[i], a);
+      const T pn = fma(beta[w], p[i], z[i]);
+      q[i] = qn;
+      p[i] = pn;
+      part[w] += (double)pn * (double)qn;
+    }
+  }
+  grid_reduce<W>(part, partials, ticket, [&](double* tot) {
+    const int s = threadIdx.x;
+    if (s < nsys) {
+      double sig = 0;
+      for (int w = s * cps; w < (s + 1) * cps; ++w) sig += tot[w];
+      sc->sigma[s] = sig;
+      double al = 0;
+      if (sc->active[s]) {
+        if (sig > 0) al = sc->rho[s] / sig;
+        else sc->breakdown = 1;
+      }
+      sc->alpha[s] = al;
+    }
+  });
+}
+
+// PREC: 0 = Chebyshev prologue (d0 = dinv r / theta, z = d0), 1 = Jacobi
+// (z = dinv r, rho = r . z).  Always: x += alpha p, r -= alpha q, rr = r . r.
+template <typename T, int W, int PREC>
+__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t nrows, T* __restrict__ x, T* __restrict__ r,
+                                                      const T* __restrict__ p, const T* __restrict__ q,
+                                                      const T* __restrict__ dinv, T theta_inv, T* __restrict__ d0,
+                                                      T* __restrict__ z, Scalars* sc, int cps, int nsys,
+                                                      double* partials, unsigned* ticket) {
+  constexpr int NS = PREC == 1 ? 2 * W : W;
+  T alpha[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) alpha[w] = (T)sc->alpha[w / cps];
+  double part[NS];
+#pragma unroll
+  for (int w = 0; w < NS; ++w) part[w] = 0;
+  GRID_STRIDE_ROWS(row, nrows) {
+    const T di = dinv[row];  // one inverse diagonal per node, shared by its W values
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const int64_t i = row * W + w;
+      x[i] = fma(alpha[w], p[i], x[i]);
+      const T rn = fma(-alpha[w], q[i], r[i]);
+      r[i] = rn;
+      part[w] += (double)rn * (double)rn;
+      if (PREC == 0) {
+        const T dd = rn * di * theta_inv;
+        d0[i] = dd;
+        z[i] = dd;
+      } else {
+        const T zz = rn * di;
+        z[i] = zz;
+        part[W + w] += (double)rn * (double)zz;
+      }
+    }
+  }
+  grid_reduce<NS>(part, partials, ticket, [&](double* tot) {
+    const int s = threadIdx.x;
+    if (s < nsys) {
+      double rr = 0;
+      for (int w = s * cps; w < (s + 1) * cps; ++w) rr += tot[w];
+      sc->rr[s] = rr;
+      if (sc->active[s] && !(rr > sc->tol2[s])) sc->active[s] = 0;
+      if (PREC == 1) {
+        double rho = 0;
+        for (int w = s * cps; w < (s + 1) * cps; ++w) rho += tot[W + w];
+        sc->beta[s] = (sc->active[s] && sc->rho[s] != 0) ? rho / sc->rho[s] : 0.0;
+        if (sc->active[s] && !(rho > 0)) sc->breakdown = 1;
+        sc->rho[s] = rho;
+      }
+    }
+  });
+}
+
+// Chebyshev prologue on its own: d0 = dinv r / theta, z = d0 (optionally with
+// the Jacobi dot rho = r . z when the polynomial has degree 1).
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_cheb_init(int64_t nrows, const T* __restrict__ r,
+                                                      const T* __restrict__ dinv, T theta_inv, T* __restrict__ d0,
+                                                      T* __restrict__ z) {
+  GRID_STRIDE_ROWS(row, nrows) {
+    const T di = dinv[row] * theta_inv;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const T dd = r[row * W + w] * di;
+      d0[row * W + w] = dd;
+      z[row * W + w] = dd;
+    }
+  }
+}
+
+// One Chebyshev step (Saad, Iterative Methods, Alg. 12.1, three-term form):
+//   res = res_in - S d ;  dn = c1 d + c2 dinv res ;  z += dn
+// DOT: also rho = rvec . z -> beta (CG preconditioner use), first => beta = 0.
+template <typename T, int W, int DOT>
+__global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, const int64_t* __restrict__ sp,
+                                                      const int32_t* __restrict__ cols,
+                                                      const T* __restrict__ vals, const T* __restrict__ d,
+                                                      T* __restrict__ dn, const T* res_in, T* res_out,
+                                                      T* __restrict__ z, const T* __restrict__ dinv, T c1, T c2,
+                                                      const T* __restrict__ rvec, Scalars* sc, int cps, int nsys,
+                                                      int first, double* partials, unsigned* ticket) {
+  double part[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) part[w] = 0;
+  GRID_STRIDE_ROWS(row, nrows) {
+    T acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = 0;
+    sell_row<T, W>(sp, cols, vals, d, row, acc);
+    const T di = c2 * dinv[row];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const int64_t i = row * W + w;
+      const T rs = res_in[i] - acc[w];
+      res_out[i] = rs;
+      const T dnew = fma(c1, d[i], di * rs);
+      dn[i] = dnew;
+      const T zn = z[i] + dnew;
+      z[i] = zn;
+      if (DOT) part[w] += (double)rvec[i] * (double)zn;
+    }
+  }
+  if (DOT) {
+    grid_reduce<W>(part, partials, ticket, [&](double* tot) {
+      const int s = threadIdx.x;
+      if (s < nsys) {
+        double rho = 0;
+        for (int w = s * cps; w < (s + 1) * cps; ++w) rho += tot[w];
+        if (first) {
+          sc->beta[s] = 0.0;
+        } else {
+          sc->beta[s] = (sc->active[s] && sc->rho[s] != 0) ? rho / sc->rho[s] : 0.0;
+        }
+        if (sc->active[s] && !(rho > 0)) sc->breakdown = 1;
+        sc->rho[s] = rho;
+      }
+    });
+  }
+}
+
+// ------------------------------------------------------------- B and B^T
+
+// p = a * (B u) + b * pin
+template <typename T, int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_B(int64_t nrows, const int64_t* __restrict__ sp,
+                                              const int32_t* __restrict__ cols, const T* __restrict__ vals,
+                                              const T* __restrict__ u, T* pout, T a, const T* pin, T b) {
+  GRID_STRIDE_ROWS(row, nrows) {
+    T acc[NRB];
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) acc[r] = 0;
+    sell_row_B<T, D, NRB>(sp, cols, vals, u, row, acc);
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) {
+      T o = a * acc[r];
+      if (b != T(0)) o = fma(b, pin[row * NRB + r], o);
+      pout[row * NRB + r] = o;
+    }
+  }
+}
+
+// u = a * scale .* (B^T p) + b * uin     (scale per node, may be null)
+template <typename T, int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_Bt(int64_t nrows, const int64_t* __restrict__ sp,
+                                               const int32_t* __restrict__ cols, const T* __restrict__ vals,
+                                               const T* __restrict__ p, const T* __restrict__ scale, T* uout,
+                                               T a, const T* uin, T b) {
+  constexpr int W = D * NRB;
+  GRID_STRIDE_ROWS(row, nrows) {
+    T acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = 0;
+    sell_row_Bt<T, D, NRB>(sp, cols, vals, p, row, acc);
+    const T sc = scale ? a * scale[row] : a;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      T o = sc * acc[w];
+      if (b != T(0)) o = fma(b, uin[row * W + w], o);
+      uout[row * W + w] = o;
+    }
+  }
+}
+
+// Momentum rows of the coupled operator:
+//   y = sgn * (A u - B^T p) + yin   (sgn = -1 with yin = F gives the residual)
+template <typename T, int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_momentum(int64_t nrows, const int64_t* __restrict__ spA,
+                                                     const int32_t* __restrict__ colsA, const T* __restrict__ A,
+                                                     const int64_t* __restrict__ spT,
+                                                     const int32_t* __restrict__ colsT, const T* __restrict__ Bt,
+                                                     const T* __restrict__ u, const T* __restrict__ p,
+                                                     const T* __restrict__ extra, T* y, T sgn, const T* yin) {
+  constexpr int W = D * NRB;
+  GRID_STRIDE_ROWS(row, nrows) {
+    T acc[W], bt[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = bt[w] = 0;
+    sell_row<T, W>(spA, colsA, A, u, row, acc);
+    sell_row_Bt<T, D, NRB>(spT, colsT, Bt, p, row, bt);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      T o = acc[w] - bt[w];
+      if (extra) o += extra[row * W + w];
+      o = sgn * o;
+      if (yin) o += yin[row * W + w];
+      y[row * W + w] = o;
+    }
+  }
+}
+
+// ------------------------------------------------------------ vector ops
+
+// y = a x + b y
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_axpby(int64_t n, T a, const T* __restrict__ x, T b, T* y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (b == T(0)) ? a * x[i] : fma(a, x[i], b * y[i]);
+}
+
+// y[i] = x[i] + s[slot] * v[i]  with per-system coefficients from device memory
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_axpy_sys(int64_t n, int W, int cps, const double* coef,
+                                                     double scale, const T* __restrict__ v, T* y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int w = (int)(i % W);
+    y[i] = fma((T)(scale * coef[w / cps]), v[i], y[i]);
+  }
+}
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kBlock) void k_cast(int64_t n, const Tin* __restrict__ x, Tout* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (Tout)x[i];
+}
+
+// out[w] = sum_rows x[row][w] * y[row][w]  (y null => x[row][w]^2); weight per
+// row optional.  Result written to res[0..W) by the last block.
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_dot(int64_t nrows, const T* __restrict__ x, const T* __restrict__ y,
+                                                const double* __restrict__ rw, double* res, double* partials,
+                                                unsigned* ticket) {
+  double part[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) part[w] = 0;
+  GRID_STRIDE_ROWS(row, nrows) {
+    const double wt = rw ? rw[row] : 1.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const double a = x[row * W + w];
+      const double b = y ? (double)y[row * W + w] : a;
+      part[w] += wt * a * b;
+    }
+  }
+  grid_reduce<W>(part, partials, ticket, [&](double* tot) {
+    if (threadIdx.x < W) res[threadIdx.x] = tot[threadIdx.x];
+  });
+}
+
+// x[row][r] -= shift[r]   (pressure mean removal; shift from device)
+template <typename T, int NRB>
+__global__ __launch_bounds__(kBlock) void k_shift(int64_t nrows, T* x, const double* __restrict__ sum,
+                                                  double scale) {
+  GRID_STRIDE_ROWS(row, nrows) {
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) x[row * NRB + r] -= (T)(sum[r] * scale);
+  }
+}
+
+// ------------------------------------------------------- layout transfers
+
+// caller [nrb][D][n_p2] (double) -> internal [n_int][nrb][D] (T), interior only
+template <typename T, int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_vel_in(int64_t n_int, int64_t n_p2, const int32_t* __restrict__ int2nat,
+                                                   const double* __restrict__ src, T* __restrict__ dst) {
+  GRID_STRIDE_ROWS(row, n_int) {
+    const int64_t nat = int2nat[row];
+#pragma unroll
+    for (int r = 0; r < NRB; ++r)
+#pragma unroll
+      for (int d = 0; d < D; ++d) dst[(row * NRB + r) * D + d] = (T)src[((int64_t)r * D + d) * n_p2 + nat];
+  }
+}
+
+// internal -> caller (interior nodes); boundary nodes: ubc (or 0 if null) when
+// bnd_fill != 0, untouched otherwise
+template <typename T, int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_vel_out(int64_t n_p2, const int32_t* __restrict__ nat2int,
+                                                    const T* __restrict__ src, const double* __restrict__ ubc,
+                                                    double* __restrict__ dst, int bnd_fill) {
+  GRID_STRIDE_ROWS(nat, n_p2) {
+    const int64_t k = nat2int[nat];
+#pragma unroll
+    for (int r = 0; r < NRB; ++r)
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int64_t o = ((int64_t)r * D + d) * n_p2 + nat;
+        if (k >= 0) dst[o] = (double)src[(k * NRB + r) * D + d];
+        else if (bnd_fill) dst[o] = ubc ? ubc[o] : 0.0;
+      }
+  }
+}
+
+// caller [nrb][n_p1] <-> internal [n_p1][nrb]
+template <typename T, int NRB>
+__global__ __launch_bounds__(kBlock) void k_p_in(int64_t n_p1, const double* __restrict__ src, T* __restrict__ dst) {
+  GRID_STRIDE_ROWS(row, n_p1) {
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) dst[row * NRB + r] = (T)src[(int64_t)r * n_p1 + row];
+  }
+}
+template <typename T, int NRB>
+__global__ __launch_bounds__(kBlock) void k_p_out(int64_t n_p1, const T* __restrict__ src, double* __restrict__ dst) {
+  GRID_STRIDE_ROWS(row, n_p1) {
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) dst[(int64_t)r * n_p1 + row] = (double)src[row * NRB + r];
+  }
+}
+
+// ------------------------------------------------- right-hand side (FP64)
+
+// F~ on interior rows: F~ = (M f)_I - ((alpha M + mu L) G)_I, G = ubc on the
+// boundary columns; CSR over all P2 nodes, output internal layout.
+template <int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_rhs_u(int64_t n_int, int64_t n_p2, const int32_t* __restrict__ int2nat,
+                                                  const int32_t* __restrict__ nat2int,
+                                                  const int32_t* __restrict__ rp, const int32_t* __restrict__ cols,
+                                                  const double* __restrict__ M, const double* __restrict__ L,
+                                                  double alpha, double mu, const double* __restrict__ f,
+                                                  const double* __restrict__ ubc, double* __restrict__ F) {
+  constexpr int W = D * NRB;
+  GRID_STRIDE_ROWS(row, n_int) {
+    const int64_t nat = int2nat[row];
+    double acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = 0;
+    for (int64_t k = rp[nat]; k < rp[nat + 1]; ++k) {
+      const int64_t c = cols[k];
+      const double m = M[k];
+      const bool bnd = nat2int[c] < 0;
+      const double a = alpha * m + mu * L[k];
+#pragma unroll
+      for (int r = 0; r < NRB; ++r)
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const int64_t o = ((int64_t)r * D + d) * n_p2 + c;
+          double v = f ? m * f[o] : 0.0;
+          if (bnd && ubc) v -= a * ubc[o];
+          acc[r * D + d] += v;
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) F[row * W + w] = acc[w];
+  }
+}
+
+// g = -B_Gamma G over the P1 rows (CSR over all P2 columns, D planes)
+template <int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_rhs_p(int64_t n_p1, int64_t n_p2, const int32_t* __restrict__ nat2int,
+                                                  const int32_t* __restrict__ rp, const int32_t* __restrict__ cols,
+                                                  const double* __restrict__ Bv, const double* __restrict__ ubc,
+                                                  double* __restrict__ g) {
+  GRID_STRIDE_ROWS(row, n_p1) {
+    double acc[NRB];
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) acc[r] = 0;
+    if (ubc) {
+      for (int64_t k = rp[row]; k < rp[row + 1]; ++k) {
+        const int64_t c = cols[k];
+        if (nat2int[c] >= 0) continue;
+#pragma unroll
+        for (int r = 0; r < NRB; ++r)
+#pragma unroll
+          for (int d = 0; d < D; ++d) acc[r] -= Bv[k * D + d] * ubc[((int64_t)r * D + d) * n_p2 + c];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) g[row * NRB + r] = acc[r];
+  }
+}
+
+// Gradient pieces of the adjoint (FP64, CSR over all P2 nodes):
+// dJdf[r][d][nat] = sum_k M[k] lam[int(col_k)]   (zero outside the interior)
+template <int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_adj_dJdf(int64_t n_p2, const int32_t* __restrict__ nat2int,
+                                                     const int32_t* __restrict__ rp, const int32_t* __restrict__ cols,
+                                                     const double* __restrict__ M, const double* __restrict__ lam,
+                                                     double* __restrict__ out) {
+  constexpr int W = D * NRB;
+  GRID_STRIDE_ROWS(nat, n_p2) {
+    double acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = 0;
+    for (int64_t k = rp[nat]; k < rp[nat + 1]; ++k) {
+      const int64_t c = nat2int[cols[k]];
+      if (c < 0) continue;
+      const double m = M[k];
+#pragma unroll
+      for (int w = 0; w < W; ++w) acc[w] += m * lam[c * W + w];
+    }
+#pragma unroll
+    for (int r = 0; r < NRB; ++r)
+#pragma unroll
+      for (int d = 0; d < D; ++d) out[((int64_t)r * D + d) * n_p2 + nat] = acc[r * D + d];
+  }
+}
+
+// dJdmu[r] = -sum_{interior rows} lam[row][r][:] . (L u_full)[row][r][:]
+template <int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_adj_dJdmu(int64_t n_int, int64_t n_p2, const int32_t* __restrict__ int2nat,
+                                                      const int32_t* __restrict__ rp, const int32_t* __restrict__ cols,
+                                                      const double* __restrict__ L, const double* __restrict__ u,
+                                                      const double* __restrict__ lam, double* res,
+                                                      double* partials, unsigned* ticket) {
+  constexpr int W = D * NRB;
+  double part[NRB];
+#pragma unroll
+  for (int r = 0; r < NRB; ++r) part[r] = 0;
+  GRID_STRIDE_ROWS(row, n_int) {
+    const int64_t nat = int2nat[row];
+    double acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = 0;
+    for (int64_t k = rp[nat]; k < rp[nat + 1]; ++k) {
+      const int64_t c = cols[k];
+      const double l = L[k];
+#pragma unroll
+      for (int r = 0; r < NRB; ++r)
+#pragma unroll
+        for (int d = 0; d < D; ++d) acc[r * D + d] += l * u[((int64_t)r * D + d) * n_p2 + c];
+    }
+#pragma unroll
+    for (int r = 0; r < NRB; ++r)
+#pragma unroll
+      for (int d = 0; d < D; ++d) part[r] -= lam[row * W + r * D + d] * acc[r * D + d];
+  }
+  grid_reduce<NRB>(part, partials, ticket, [&](double* tot) {
+    if (threadIdx.x < NRB) res[threadIdx.x] = tot[threadIdx.x];
+  });
+}
+
+}  // namespace stokes
+
+namespace stokes {
+
+// ------------------------------------------- coupled-vector (FGMRES) kernels
+// A coupled vector is the velocity part [n_int][NRB][D] followed by the
+// pressure part [n_p1][NRB]; right-hand side r owns slots r*D..r*D+D-1 of a
+// velocity row and slot r of a pressure row.
+
+struct Coef8 {
+  double v[8];
+};
+
+// partial dots h[i][r] = V_i . w over blockIdx.y = i; block partials to part
+template <typename TV, int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_mdot(int64_t n_int, int64_t n_p1, const TV* __restrict__ V, int64_t ldv,
+                                                 const double* __restrict__ w, double* __restrict__ part) {
+  constexpr int W = D * NRB;
+  const TV* v = V + (int64_t)blockIdx.y * ldv;
+  const int64_t nv = n_int * W;
+  double acc[NRB];
+#pragma unroll
+  for (int r = 0; r < NRB; ++r) acc[r] = 0;
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n_int + n_p1;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    if (row < n_int) {
+#pragma unroll
+      for (int r = 0; r < NRB; ++r)
+#pragma unroll
+        for (int d = 0; d < D; ++d) acc[r] += (double)v[row * W + r * D + d] * w[row * W + r * D + d];
+    } else {
+      const int64_t pr = row - n_int;
+#pragma unroll
+      for (int r = 0; r < NRB; ++r) acc[r] += (double)v[nv + pr * NRB + r] * w[nv + pr * NRB + r];
+    }
+  }
+  __shared__ double tot[NRB];
+  block_sum<NRB>(acc, tot);
+  if (threadIdx.x < NRB) part[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * NRB + threadIdx.x] = tot[threadIdx.x];
+}
+
+// h[i][r] = sum over blocks of part (one block per i, fixed order)
+template <int NRB>
+__global__ __launch_bounds__(kBlock) void k_mdot_fin(int nblk, const double* __restrict__ part, double* __restrict__ h) {
+  double acc[NRB];
+#pragma unroll
+  for (int r = 0; r < NRB; ++r) acc[r] = 0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) acc[r] += part[((int64_t)blockIdx.x * nblk + b) * NRB + r];
+  __shared__ double tot[NRB];
+  block_sum<NRB>(acc, tot);
+  if (threadIdx.x < NRB) h[blockIdx.x * NRB + threadIdx.x] = tot[threadIdx.x];
+}
+
+// w += sgn * sum_{i<nb} h[i][r] V_i ; NORM: res[r] = ||w_r||^2 after the update
+template <typename TV, int D, int NRB, int NORM>
+__global__ __launch_bounds__(kBlock) void k_mupdate(int64_t n_int, int64_t n_p1, const TV* __restrict__ V,
+                                                    int64_t ldv, int nb, const double* __restrict__ h, double sgn,
+                                                    double* __restrict__ w, double* res, double* partials,
+                                                    unsigned* ticket) {
+  constexpr int W = D * NRB;
+  __shared__ double hs[64 * NRB];
+  for (int i = threadIdx.x; i < nb * NRB; i += blockDim.x) hs[i] = sgn * h[i];
+  __syncthreads();
+  const int64_t nv = n_int * W;
+  double part[NRB];
+#pragma unroll
+  for (int r = 0; r < NRB; ++r) part[r] = 0;
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n_int + n_p1;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    if (row < n_int) {
+      double a[W];
+#pragma unroll
+      for (int k = 0; k < W; ++k) a[k] = w[row * W + k];
+      for (int i = 0; i < nb; ++i) {
+        const TV* v = V + (int64_t)i * ldv + row * W;
+#pragma unroll
+        for (int r = 0; r < NRB; ++r)
+#pragma unroll
+          for (int d = 0; d < D; ++d) a[r * D + d] += hs[i * NRB + r] * (double)v[r * D + d];
+      }
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        w[row * W + k] = a[k];
+        if (NORM) part[k / D] += a[k] * a[k];
+      }
+    } else {
+      const int64_t pr = row - n_int;
+      double a[NRB];
+#pragma unroll
+      for (int r = 0; r < NRB; ++r) a[r] = w[nv + pr * NRB + r];
+      for (int i = 0; i < nb; ++i) {
+        const TV* v = V + (int64_t)i * ldv + nv + pr * NRB;
+#pragma unroll
+        for (int r = 0; r < NRB; ++r) a[r] += hs[i * NRB + r] * (double)v[r];
+      }
+#pragma unroll
+      for (int r = 0; r < NRB; ++r) {
+        w[nv + pr * NRB + r] = a[r];
+        if (NORM) part[r] += a[r] * a[r];
+      }
+    }
+  }
+  if (NORM) {
+    grid_reduce<NRB>(part, partials, ticket, [&](double* tot) {
+      if (threadIdx.x < NRB) res[threadIdx.x] = tot[threadIdx.x];
+    });
+  }
+}
+
+// v = s[r] * w  (coupled vectors, per right-hand-side scale)
+template <int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_scale_coupled(int64_t n_int, int64_t n_p1, Coef8 s,
+                                                          const double* __restrict__ w, double* __restrict__ v) {
+  constexpr int W = D * NRB;
+  const int64_t nv = n_int * W;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv + n_p1 * NRB;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int r = i < nv ? (int)((i % W) / D) : (int)((i - nv) % NRB);
+    v[i] = s.v[r] * w[i];
+  }
+}
+
+// y = a[r] x + b[r] y over rows of WROW values, r = slot / CPS
+template <typename TX, typename TY, int WROW, int CPS>
+__global__ __launch_bounds__(kBlock) void k_axpy_rhs(int64_t nrows, Coef8 a, Coef8 b, const TX* __restrict__ x,
+                                                     TY* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nrows * WROW;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(i % WROW) / CPS;
+    y[i] = (TY)(a.v[r] * (double)x[i] + b.v[r] * (double)y[i]);
+  }
+}
+
+// ------------------------------------------------------ scalar bookkeeping
+
+// Start of a CG: bb from slot sums, tolerances, flags.
+static __global__ void k_scal_init(Scalars* sc, const double* __restrict__ slots, int cps, int nsys, double rtol2) {
+  const int s = threadIdx.x;
+  if (s < kMaxSys) {
+    double bb = 0;
+    if (s < nsys)
+      for (int w = s * cps; w < (s + 1) * cps; ++w) bb += slots[w];
+    sc->bb[s] = bb;
+    sc->tol2[s] = rtol2 * bb;
+    sc->rr[s] = bb;
+    sc->active[s] = (s < nsys && bb > 0) ? 1 : 0;
+    sc->rho[s] = sc->rho_old[s] = sc->alpha[s] = sc->beta[s] = sc->sigma[s] = 0;
+  }
+  if (s == 0) sc->breakdown = 0;
+}
+
+// rho from slot sums; beta = rho / rho_prev (0 on the first step)
+static __global__ void k_scal_rho(Scalars* sc, const double* __restrict__ slots, int cps, int nsys, int first) {
+  const int s = threadIdx.x;
+  if (s < nsys) {
+    double rho = 0;
+    for (int w = s * cps; w < (s + 1) * cps; ++w) rho += slots[w];
+    sc->beta[s] = (!first && sc->active[s] && sc->rho[s] != 0) ? rho / sc->rho[s] : 0.0;
+    if (sc->active[s] && !(rho > 0)) sc->breakdown = 1;
+    sc->rho[s] = rho;
+  }
+}
+
+// g = -(g - m sum_r / (1^T m)): the transpose of the zero-integral
+// normalisation applied to a pressure loss gradient, negated for the forward form
+template <int NRB>
+__global__ __launch_bounds__(kBlock) void k_adj_jp(int64_t n_p1, const double* __restrict__ m,
+                                                   const double* __restrict__ sum, double inv_msum,
+                                                   double* __restrict__ g) {
+  GRID_STRIDE_ROWS(row, n_p1) {
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) g[row * NRB + r] = -(g[row * NRB + r] - m[row] * sum[r] * inv_msum);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_set(int64_t n, T v, T* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+
+}  // namespace stokes

@@ -1,0 +1,268 @@
+// Host-side Kuhn mesh, numbering and sparsity patterns (see mesh_host.h).
+#include "mesh_host.h"
+
+#include <algorithm>
+#include <thread>
+
+namespace stokes {
+
+int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+namespace {
+
+uint64_t splitmix_finalise(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// U in [0, 1): top 53 bits of the finalised counter state.
+double unit_draw(uint64_t seed, uint64_t counter) {
+  const uint64_t state = seed + (counter + 1ULL) * 0x9E3779B97F4A7C15ULL;
+  return static_cast<double>(splitmix_finalise(state) >> 11) * 0x1.0p-53;
+}
+
+template <class F>
+void parallel_for(int64_t n, F&& body) {
+  unsigned nt = std::thread::hardware_concurrency();
+  if (nt == 0) nt = 1;
+  if (nt > 16) nt = 16;
+  if (n < 4096) nt = 1;
+  if (nt == 1) {
+    body(int64_t(0), n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t chunk = (n + nt - 1) / nt;
+  for (unsigned t = 0; t < nt; ++t) {
+    const int64_t b = t * chunk, e = std::min<int64_t>(n, b + chunk);
+    if (b >= e) break;
+    th.emplace_back([&body, b, e] { body(b, e); });
+  }
+  for (auto& x : th) x.join();
+}
+
+}  // namespace
+
+bool build_mesh(int dim, int n, uint64_t seed, double jitter, HostMesh& m) {
+  m.dim = dim;
+  m.n = n;
+  m.nloc = dim == 3 ? 10 : 6;
+  const int nv = dim + 1;
+  const int64_t n1 = n + 1, n2 = 2 * int64_t(n) + 1;
+  m.n_p1 = ipow(n1, dim);
+  m.n_p2 = ipow(n2, dim);
+  const int64_t ncell = ipow(n, dim);
+  const int nperm = dim == 3 ? 6 : 2;
+  m.n_e = ncell * nperm;
+  if (m.n_p2 >= (int64_t(1) << 31) || m.n_e >= (int64_t(1) << 27)) return false;
+
+  // vertex coordinates: x fastest, interior vertices jittered
+  m.vcoords.assign(m.n_p1 * dim, 0.0);
+  const double inv_n_div = static_cast<double>(n);
+  for (int64_t g = 0; g < m.n_p1; ++g) {
+    int64_t rem = g;
+    int idx[3] = {0, 0, 0};
+    bool interior = true;
+    for (int c = 0; c < dim; ++c) {
+      idx[c] = static_cast<int>(rem % n1);
+      rem /= n1;
+      if (idx[c] == 0 || idx[c] == n) interior = false;
+    }
+    for (int c = 0; c < dim; ++c) {
+      double x = static_cast<double>(idx[c]);
+      if (interior) {
+        const double u = unit_draw(seed, static_cast<uint64_t>(dim) * g + c);
+        const double two_u = 2.0 * u;
+        const double centred = two_u - 1.0;
+        const double delta = centred * jitter;
+        x = x + delta;
+      }
+      m.vcoords[g * dim + c] = x / inv_n_div;
+    }
+  }
+
+  // simplices (cell-major, x fastest, then permutations in lexicographic order)
+  static const int perm3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  static const int perm2[2][2] = {{0, 1}, {1, 0}};
+  static const int edges3[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+  static const int edges2[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+  m.elems.assign(m.n_e * nv, 0);
+  m.p2.assign(m.n_e * m.nloc, 0);
+  int64_t e = 0;
+  for (int64_t cell = 0; cell < ncell; ++cell) {
+    int64_t rem = cell;
+    int cg[3] = {0, 0, 0};
+    for (int c = 0; c < dim; ++c) {
+      cg[c] = static_cast<int>(rem % n);
+      rem /= n;
+    }
+    for (int q = 0; q < nperm; ++q, ++e) {
+      int pos[4][3];
+      for (int c = 0; c < 3; ++c) pos[0][c] = cg[c];
+      for (int s = 0; s < dim; ++s) {
+        for (int c = 0; c < 3; ++c) pos[s + 1][c] = pos[s][c];
+        const int ax = dim == 3 ? perm3[q][s] : perm2[q][s];
+        pos[s + 1][ax] += 1;
+      }
+      for (int a = 0; a < nv; ++a) {
+        int64_t id = 0, st = 1;
+        for (int c = 0; c < dim; ++c, st *= n1) id += pos[a][c] * st;
+        m.elems[e * nv + a] = static_cast<int32_t>(id);
+        int64_t id2 = 0, st2 = 1;
+        for (int c = 0; c < dim; ++c, st2 *= n2) id2 += 2 * pos[a][c] * st2;
+        m.p2[e * m.nloc + a] = static_cast<int32_t>(id2);
+      }
+      const int ned = dim == 3 ? 6 : 3;
+      for (int k = 0; k < ned; ++k) {
+        const int a = dim == 3 ? edges3[k][0] : edges2[k][0];
+        const int b = dim == 3 ? edges3[k][1] : edges2[k][1];
+        int64_t id2 = 0, st2 = 1;
+        for (int c = 0; c < dim; ++c, st2 *= n2) id2 += (pos[a][c] + pos[b][c]) * st2;
+        m.p2[e * m.nloc + nv + k] = static_cast<int32_t>(id2);
+      }
+    }
+  }
+
+  // P2 coordinates: vertices copy, edge nodes (x_a + x_b) * 0.5
+  m.p2coords.assign(m.n_p2 * dim, 0.0);
+  for (int64_t el = 0; el < m.n_e; ++el) {
+    const int32_t* ev = &m.elems[el * nv];
+    const int32_t* ep = &m.p2[el * m.nloc];
+    for (int a = 0; a < nv; ++a)
+      for (int c = 0; c < dim; ++c) m.p2coords[int64_t(ep[a]) * dim + c] = m.vcoords[int64_t(ev[a]) * dim + c];
+    const int ned = dim == 3 ? 6 : 3;
+    for (int k = 0; k < ned; ++k) {
+      const int a = dim == 3 ? edges3[k][0] : edges2[k][0];
+      const int b = dim == 3 ? edges3[k][1] : edges2[k][1];
+      for (int c = 0; c < dim; ++c) {
+        const double s = m.vcoords[int64_t(ev[a]) * dim + c] + m.vcoords[int64_t(ev[b]) * dim + c];
+        m.p2coords[int64_t(ep[nv + k]) * dim + c] = s * 0.5;
+      }
+    }
+  }
+
+  m.p2_bnd.assign(m.n_p2, 0);
+  for (int64_t id = 0; id < m.n_p2; ++id) {
+    int64_t rem = id;
+    for (int c = 0; c < dim; ++c) {
+      const int64_t I = rem % n2;
+      rem /= n2;
+      if (I == 0 || I == n2 - 1) m.p2_bnd[id] = 1;
+    }
+  }
+  return true;
+}
+
+void incidence(const std::vector<int32_t>& nodes, int nl, int64_t n_e, int64_t n_nodes,
+               std::vector<int64_t>& ptr, std::vector<int32_t>& list) {
+  ptr.assign(n_nodes + 1, 0);
+  for (int64_t e = 0; e < n_e; ++e)
+    for (int a = 0; a < nl; ++a) ptr[nodes[e * nl + a] + 1]++;
+  for (int64_t i = 0; i < n_nodes; ++i) ptr[i + 1] += ptr[i];
+  list.assign(ptr[n_nodes], 0);
+  std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+  for (int64_t e = 0; e < n_e; ++e)
+    for (int a = 0; a < nl; ++a) list[fill[nodes[e * nl + a]]++] = static_cast<int32_t>((e << 4) | a);
+}
+
+void element_pattern(const std::vector<int32_t>& row_nodes, int nr, int64_t nrows,
+                     const std::vector<int32_t>& col_nodes, int nc, int64_t ncols, int64_t n_e,
+                     HostCsr& out) {
+  std::vector<int64_t> iptr;
+  std::vector<int32_t> ilist;
+  incidence(row_nodes, nr, n_e, nrows, iptr, ilist);
+  out.nrows = nrows;
+  out.ncols = ncols;
+  out.rowptr.assign(nrows + 1, 0);
+  auto gather = [&](int64_t r, std::vector<int32_t>& buf) {
+    buf.clear();
+    for (int64_t k = iptr[r]; k < iptr[r + 1]; ++k) {
+      const int64_t e = ilist[k] >> 4;
+      for (int b = 0; b < nc; ++b) buf.push_back(col_nodes[e * nc + b]);
+    }
+    std::sort(buf.begin(), buf.end());
+    buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+  };
+  parallel_for(nrows, [&](int64_t b, int64_t e) {
+    std::vector<int32_t> buf;
+    for (int64_t r = b; r < e; ++r) {
+      gather(r, buf);
+      out.rowptr[r + 1] = static_cast<int64_t>(buf.size());
+    }
+  });
+  for (int64_t r = 0; r < nrows; ++r) out.rowptr[r + 1] += out.rowptr[r];
+  out.cols.assign(out.rowptr[nrows], 0);
+  parallel_for(nrows, [&](int64_t b, int64_t e) {
+    std::vector<int32_t> buf;
+    for (int64_t r = b; r < e; ++r) {
+      gather(r, buf);
+      std::copy(buf.begin(), buf.end(), out.cols.begin() + out.rowptr[r]);
+    }
+  });
+}
+
+void restrict_pattern(const HostCsr& in, const std::vector<int32_t>& row_map, int64_t nrows_out,
+                      const std::vector<int32_t>& col_map, int64_t ncols_out, HostCsr& out,
+                      std::vector<int64_t>* src) {
+  out.nrows = nrows_out;
+  out.ncols = ncols_out;
+  out.rowptr.assign(nrows_out + 1, 0);
+  std::vector<int64_t> inrow(nrows_out, -1);
+  for (int64_t r = 0; r < in.nrows; ++r)
+    if (row_map[r] >= 0) inrow[row_map[r]] = r;
+  parallel_for(nrows_out, [&](int64_t b, int64_t e) {
+    for (int64_t ro = b; ro < e; ++ro) {
+      const int64_t r = inrow[ro];
+      int64_t cnt = 0;
+      for (int64_t k = in.rowptr[r]; k < in.rowptr[r + 1]; ++k)
+        if (col_map[in.cols[k]] >= 0) ++cnt;
+      out.rowptr[ro + 1] = cnt;
+    }
+  });
+  for (int64_t r = 0; r < nrows_out; ++r) out.rowptr[r + 1] += out.rowptr[r];
+  out.cols.assign(out.rowptr[nrows_out], 0);
+  if (src) src->assign(out.rowptr[nrows_out], 0);
+  parallel_for(nrows_out, [&](int64_t b, int64_t e) {
+    std::vector<std::pair<int32_t, int64_t>> buf;
+    for (int64_t ro = b; ro < e; ++ro) {
+      const int64_t r = inrow[ro];
+      buf.clear();
+      for (int64_t k = in.rowptr[r]; k < in.rowptr[r + 1]; ++k) {
+        const int32_t c = col_map[in.cols[k]];
+        if (c >= 0) buf.emplace_back(c, k);
+      }
+      std::sort(buf.begin(), buf.end());
+      int64_t o = out.rowptr[ro];
+      for (auto& pr : buf) {
+        out.cols[o] = pr.first;
+        if (src) (*src)[o] = pr.second;
+        ++o;
+      }
+    }
+  });
+}
+
+void transpose_pattern(const HostCsr& in, HostCsr& out, std::vector<int64_t>& src) {
+  out.nrows = in.ncols;
+  out.ncols = in.nrows;
+  out.rowptr.assign(out.nrows + 1, 0);
+  for (int64_t k = 0; k < in.rowptr[in.nrows]; ++k) out.rowptr[in.cols[k] + 1]++;
+  for (int64_t r = 0; r < out.nrows; ++r) out.rowptr[r + 1] += out.rowptr[r];
+  out.cols.assign(out.rowptr[out.nrows], 0);
+  src.assign(out.rowptr[out.nrows], 0);
+  std::vector<int64_t> fill(out.rowptr.begin(), out.rowptr.end() - 1);
+  // rows of `in` visited in increasing order, so each transposed row is sorted
+  for (int64_t r = 0; r < in.nrows; ++r)
+    for (int64_t k = in.rowptr[r]; k < in.rowptr[r + 1]; ++k) {
+      const int64_t o = fill[in.cols[k]]++;
+      out.cols[o] = static_cast<int32_t>(r);
+      src[o] = k;
+    }
+}
+
+}  // namespace stokes

@@ -1,0 +1,89 @@
+// Host-side launchers of the device kernels (dispatch over value type, the
+// number of values per row W and (dim, right-hand sides per batch)).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace stokes {
+
+void assemble_ctx(stokes_ctx* c);
+void estimate_bounds(stokes_ctx* c);
+void reform_A(stokes_ctx* c);
+void lanczos_bounds(stokes_ctx* c, const Sell& S, const double* vals, const double* dinv, int steps, double& rlo,
+                    double& rhi, double& gersh);
+
+namespace ops {
+
+int grid_for(int64_t rows);
+bool prof_begin(stokes_ctx* c, const Sell* S, const void* vals, const void* avals);
+void prof_end(stokes_ctx* c, double bytes);
+void check_launch();
+
+template <class T> const T* pick(const DevBuf& b64, const DevBuf& b32);
+
+// y = a * (S x) + b * yin, S scalar SELL shared by W values per row
+template <class T>
+void spmv(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* x, T* y, T a, const T* yin, T b);
+// p = a * B u + b * pin
+template <class T>
+void Bmul(stokes_ctx* c, int nrb, const T* u, T* p, T a, const T* pin, T b);
+// u = a * scale .* (B^T p) + b * uin
+template <class T>
+void Btmul(stokes_ctx* c, int nrb, const T* p, const T* scale, T* u, T a, const T* uin, T b);
+// y = sgn (A u - B^T p + extra) + yin
+template <class T>
+void momentum(stokes_ctx* c, int nrb, const T* u, const T* p, const T* extra, T* y, T sgn, const T* yin);
+
+// slot sums of x .* y (y null => x .* x), rw optional row weights
+template <class T>
+void dot_dev(stokes_ctx* c, int64_t nrows, int W, const T* x, const T* y, const double* rw, double* res);
+template <class T>
+std::vector<double> dot_host(stokes_ctx* c, int64_t nrows, int W, const T* x, const T* y, const double* rw = nullptr);
+
+// x[row][r] -= mean over rows (l2 mean per right-hand side)
+template <class T>
+void remove_mean(stokes_ctx* c, int nrb, T* x);
+// x[row][r] -= (m . x_r) / (m . 1) with m = M_Q 1 (zero pressure integral)
+template <class T>
+void normalize_pressure(stokes_ctx* c, int nrb, T* x);
+
+template <class Tin, class Tout>
+void cast(stokes_ctx* c, int64_t n, const Tin* x, Tout* y);
+template <class T>
+void axpby(stokes_ctx* c, int64_t n, T a, const T* x, T b, T* y);
+template <class T>
+void axpy_sys(stokes_ctx* c, int64_t n, int W, int cps, const double* coef, double scale, const T* v, T* y);
+
+// CG / Chebyshev building blocks (see kernels.h)
+template <class T>
+void cg_spmv(stokes_ctx* c, int64_t nrows, const Sell* S, const T* vals, int W, const T* z, const T* extra, T* q,
+             T* p, Scalars* sc, int cps, int nsys);
+template <class T>
+void cg_update(stokes_ctx* c, int64_t nrows, int W, int prec, T* x, T* r, const T* p, const T* q, const T* dinv,
+               T theta_inv, T* d0, T* z, Scalars* sc, int cps, int nsys);
+template <class T>
+void cheb_init(stokes_ctx* c, int64_t nrows, int W, const T* r, const T* dinv, T theta_inv, T* d0, T* z);
+template <class T>
+void cheb_step(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* d, T* dn, const T* res_in, T* res_out,
+               T* z, const T* dinv, T c1, T c2, const T* rvec, Scalars* sc, int cps, int nsys, int first);
+
+// layout transfers
+template <class T>
+void vel_in(stokes_ctx* c, int nrb, const double* src, T* dst);
+template <class T>
+void vel_out(stokes_ctx* c, int nrb, const T* src, const double* ubc, double* dst, int bnd_fill);
+template <class T>
+void p_in(stokes_ctx* c, int nrb, const double* src, T* dst);
+template <class T>
+void p_out(stokes_ctx* c, int nrb, const T* src, double* dst);
+
+// FP64 right-hand side and adjoint gradient pieces
+void rhs(stokes_ctx* c, int nrb, const double* f, const double* ubc, double* F, double* g);
+void adj_jp(stokes_ctx* c, int nrb, double* g);
+void adj_dJdf(stokes_ctx* c, int nrb, const double* lam, double* out);
+void adj_dJdmu(stokes_ctx* c, int nrb, const double* u_full, const double* lam, double* res_dev);
+
+}  // namespace ops
+}  // namespace stokes

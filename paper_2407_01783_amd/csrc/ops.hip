@@ -1,0 +1,382 @@
+// Launchers for the kernels in kernels.h.
+#include <type_traits>
+
+#include "kernels.h"
+#include "ops.h"
+
+namespace stokes {
+namespace ops {
+
+int grid_for(int64_t rows) {
+  const int64_t nb = (rows + kBlock - 1) / kBlock;
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nb, kMaxBlocks)));
+}
+
+void check_launch() { HIP_CHECK(hipGetLastError()); }
+
+template <>
+const double* pick<double>(const DevBuf& b64, const DevBuf&) {
+  return b64.as<double>();
+}
+template <>
+const float* pick<float>(const DevBuf&, const DevBuf& b32) {
+  return b32.as<float>();
+}
+
+// Timing of the dominant kernel (the velocity-block SpMV) with HIP events on
+// the context stream; events are read back at the end of the solve.
+bool prof_begin(stokes_ctx* c, const Sell* S, const void* vals, const void* avals) {
+  if (!c->prof_on || S != &c->sA || vals != avals) return false;
+  if (c->prof_idx >= static_cast<int>(c->prof_ev.size())) return false;
+  HIP_CHECK(hipEventRecord(c->prof_ev[c->prof_idx].first, c->stream));
+  return true;
+}
+
+void prof_end(stokes_ctx* c, double bytes) {
+  HIP_CHECK(hipEventRecord(c->prof_ev[c->prof_idx].second, c->stream));
+  c->prof_idx++;
+  c->prof_bytes = bytes;
+}
+
+namespace {
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// W in {1,2,3,4,6,8,12,16,24}
+template <class F>
+void dispatch_w(int W, F&& f) {
+  switch (W) {
+    case 1: f(IC<1>{}); break;
+    case 2: f(IC<2>{}); break;
+    case 3: f(IC<3>{}); break;
+    case 4: f(IC<4>{}); break;
+    case 6: f(IC<6>{}); break;
+    case 8: f(IC<8>{}); break;
+    case 12: f(IC<12>{}); break;
+    case 16: f(IC<16>{}); break;
+    case 24: f(IC<24>{}); break;
+    default: throw Error(STOKES_ERR_UNSUPPORTED, "unsupported vector width " + std::to_string(W));
+  }
+}
+
+// dim in {2,3}, nrb in {1,2,4,8}
+template <class F>
+void dispatch_dn(int D, int NRB, F&& f) {
+  auto inner = [&](auto Dc) {
+    switch (NRB) {
+      case 1: f(Dc, IC<1>{}); break;
+      case 2: f(Dc, IC<2>{}); break;
+      case 4: f(Dc, IC<4>{}); break;
+      case 8: f(Dc, IC<8>{}); break;
+      default: throw Error(STOKES_ERR_UNSUPPORTED, "unsupported batch " + std::to_string(NRB));
+    }
+  };
+  if (D == 3) inner(IC<3>{});
+  else if (D == 2) inner(IC<2>{});
+  else throw Error(STOKES_ERR_UNSUPPORTED, "dim");
+}
+
+inline double* partials(stokes_ctx* c) { return c->red.partials.as<double>(); }
+inline unsigned* ticket(stokes_ctx* c) { return c->red.ticket.as<unsigned>(); }
+
+template <class T> const DevBuf& bvals(stokes_ctx* c);
+template <> const DevBuf& bvals<double>(stokes_ctx* c) { return c->B64; }
+template <> const DevBuf& bvals<float>(stokes_ctx* c) { return c->B32; }
+template <class T> const DevBuf& btvals(stokes_ctx* c);
+template <> const DevBuf& btvals<double>(stokes_ctx* c) { return c->Bt64; }
+template <> const DevBuf& btvals<float>(stokes_ctx* c) { return c->Bt32; }
+template <class T> const DevBuf& avals(stokes_ctx* c);
+template <> const DevBuf& avals<double>(stokes_ctx* c) { return c->A64; }
+template <> const DevBuf& avals<float>(stokes_ctx* c) { return c->A32; }
+
+}  // namespace
+
+template <class T>
+void spmv(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* x, T* y, T a, const T* yin, T b) {
+  dispatch_w(W, [&](auto Wc) {
+    constexpr int WW = decltype(Wc)::value;
+    hipLaunchKernelGGL((k_spmv<T, WW>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
+                       S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, x, y, a, yin, b);
+  });
+  check_launch();
+}
+
+template <class T>
+void Bmul(stokes_ctx* c, int nrb, const T* u, T* p, T a, const T* pin, T b) {
+  const Sell& S = c->sB;
+  dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
+    constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
+    hipLaunchKernelGGL((k_B<T, D, N>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
+                       S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), bvals<T>(c).template as<T>(), u, p, a, pin, b);
+  });
+  check_launch();
+}
+
+template <class T>
+void Btmul(stokes_ctx* c, int nrb, const T* p, const T* scale, T* u, T a, const T* uin, T b) {
+  const Sell& S = c->sBt;
+  dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
+    constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
+    hipLaunchKernelGGL((k_Bt<T, D, N>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
+                       S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), btvals<T>(c).template as<T>(), p, scale, u, a,
+                       uin, b);
+  });
+  check_launch();
+}
+
+template <class T>
+void momentum(stokes_ctx* c, int nrb, const T* u, const T* p, const T* extra, T* y, T sgn, const T* yin) {
+  dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
+    constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
+    hipLaunchKernelGGL((k_momentum<T, D, N>), dim3(grid_for(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int,
+                       c->sA.slice_ptr.as<int64_t>(), c->sA.cols.as<int32_t>(), avals<T>(c).template as<T>(),
+                       c->sBt.slice_ptr.as<int64_t>(), c->sBt.cols.as<int32_t>(), btvals<T>(c).template as<T>(), u, p,
+                       extra, y, sgn, yin);
+  });
+  check_launch();
+}
+
+template <class T>
+void dot_dev(stokes_ctx* c, int64_t nrows, int W, const T* x, const T* y, const double* rw, double* res) {
+  dispatch_w(W, [&](auto Wc) {
+    constexpr int WW = decltype(Wc)::value;
+    hipLaunchKernelGGL((k_dot<T, WW>), dim3(grid_for(nrows)), dim3(kBlock), 0, c->stream, nrows, x, y, rw, res,
+                       partials(c), ticket(c));
+  });
+  check_launch();
+}
+
+template <class T>
+std::vector<double> dot_host(stokes_ctx* c, int64_t nrows, int W, const T* x, const T* y, const double* rw) {
+  double* res = c->red.result.as<double>();
+  dot_dev<T>(c, nrows, W, x, y, rw, res);
+  std::vector<double> h(W);
+  HIP_CHECK(hipMemcpyAsync(h.data(), res, W * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+  return h;
+}
+
+template <class T>
+void remove_mean(stokes_ctx* c, int nrb, T* x) {
+  double* res = c->red.result.as<double>() + kMaxSys;
+  const T* ones = std::is_same<T, double>::value ? (const T*)c->ones64.p : (const T*)c->ones32.p;
+  dispatch_w(nrb, [&](auto Nc) {
+    constexpr int N = decltype(Nc)::value;
+    hipLaunchKernelGGL((k_dot<T, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1,
+                       (const T*)x, ones, (const double*)nullptr, res, partials(c), ticket(c));
+    check_launch();
+    hipLaunchKernelGGL((k_shift<T, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1, x,
+                       (const double*)res, 1.0 / double(c->n_p1));
+  });
+  check_launch();
+}
+
+template <class T>
+void normalize_pressure(stokes_ctx* c, int nrb, T* x) {
+  double* res = c->red.result.as<double>() + kMaxSys;
+  const T* ones = std::is_same<T, double>::value ? (const T*)c->ones64.p : (const T*)c->ones32.p;
+  dispatch_w(nrb, [&](auto Nc) {
+    constexpr int N = decltype(Nc)::value;
+    hipLaunchKernelGGL((k_dot<T, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1,
+                       (const T*)x, ones, (const double*)c->mQ.as<double>(), res, partials(c), ticket(c));
+    check_launch();
+    hipLaunchKernelGGL((k_shift<T, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1, x,
+                       (const double*)res, 1.0 / c->mQ_sum);
+  });
+  check_launch();
+}
+
+template <class Tin, class Tout>
+void cast(stokes_ctx* c, int64_t n, const Tin* x, Tout* y) {
+  hipLaunchKernelGGL((k_cast<Tin, Tout>), dim3(grid_for(n)), dim3(kBlock), 0, c->stream, n, x, y);
+  check_launch();
+}
+
+template <class T>
+void axpby(stokes_ctx* c, int64_t n, T a, const T* x, T b, T* y) {
+  hipLaunchKernelGGL((k_axpby<T>), dim3(grid_for(n)), dim3(kBlock), 0, c->stream, n, a, x, b, y);
+  check_launch();
+}
+
+template <class T>
+void axpy_sys(stokes_ctx* c, int64_t n, int W, int cps, const double* coef, double scale, const T* v, T* y) {
+  hipLaunchKernelGGL((k_axpy_sys<T>), dim3(grid_for(n)), dim3(kBlock), 0, c->stream, n, W, cps, coef, scale, v, y);
+  check_launch();
+}
+
+template <class T>
+void cg_spmv(stokes_ctx* c, int64_t nrows, const Sell* S, const T* vals, int W, const T* z, const T* extra, T* q,
+             T* p, Scalars* sc, int cps, int nsys) {
+  const bool timed = prof_begin(c, S, (const void*)vals, (const void*)avals<T>(c).template as<T>());
+  dispatch_w(W, [&](auto Wc) {
+    constexpr int WW = decltype(Wc)::value;
+    hipLaunchKernelGGL((k_cg_spmv<T, WW>), dim3(grid_for(nrows)), dim3(kBlock), 0, c->stream, nrows,
+                       S ? S->slice_ptr.as<int64_t>() : nullptr, S ? S->cols.as<int32_t>() : nullptr, vals, z, extra,
+                       q, p, sc, cps, nsys, partials(c), ticket(c));
+  });
+  check_launch();
+  if (timed) prof_end(c, double(S->nnz) * (sizeof(T) + 4.0) + double(nrows) * W * sizeof(T) * (extra ? 6.0 : 5.0));
+}
+
+template <class T>
+void cg_update(stokes_ctx* c, int64_t nrows, int W, int prec, T* x, T* r, const T* p, const T* q, const T* dinv,
+               T theta_inv, T* d0, T* z, Scalars* sc, int cps, int nsys) {
+  dispatch_w(W, [&](auto Wc) {
+    constexpr int WW = decltype(Wc)::value;
+    if (prec == 0)
+      hipLaunchKernelGGL((k_cg_update<T, WW, 0>), dim3(grid_for(nrows)), dim3(kBlock), 0, c->stream, nrows, x, r, p,
+                         q, dinv, theta_inv, d0, z, sc, cps, nsys, partials(c), ticket(c));
+    else
+      hipLaunchKernelGGL((k_cg_update<T, WW, 1>), dim3(grid_for(nrows)), dim3(kBlock), 0, c->stream, nrows, x, r, p,
+                         q, dinv, theta_inv, d0, z, sc, cps, nsys, partials(c), ticket(c));
+  });
+  check_launch();
+}
+
+template <class T>
+void cheb_init(stokes_ctx* c, int64_t nrows, int W, const T* r, const T* dinv, T theta_inv, T* d0, T* z) {
+  dispatch_w(W, [&](auto Wc) {
+    constexpr int WW = decltype(Wc)::value;
+    hipLaunchKernelGGL((k_cheb_init<T, WW>), dim3(grid_for(nrows)), dim3(kBlock), 0, c->stream, nrows, r, dinv,
+                       theta_inv, d0, z);
+  });
+  check_launch();
+}
+
+template <class T>
+void cheb_step(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* d, T* dn, const T* res_in, T* res_out,
+               T* z, const T* dinv, T c1, T c2, const T* rvec, Scalars* sc, int cps, int nsys, int first) {
+  const bool timed = prof_begin(c, &S, (const void*)vals, (const void*)avals<T>(c).template as<T>());
+  dispatch_w(W, [&](auto Wc) {
+    constexpr int WW = decltype(Wc)::value;
+    if (rvec)
+      hipLaunchKernelGGL((k_cheb_step<T, WW, 1>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
+                         S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, d, dn, res_in, res_out, z, dinv, c1,
+                         c2, rvec, sc, cps, nsys, first, partials(c), ticket(c));
+    else
+      hipLaunchKernelGGL((k_cheb_step<T, WW, 0>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
+                         S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, d, dn, res_in, res_out, z, dinv, c1,
+                         c2, rvec, sc, cps, nsys, first, partials(c), ticket(c));
+  });
+  check_launch();
+  // algorithmic bytes: values + column indices once; d gathered once; res_in,
+  // z, dinv (and rvec) read; res_out, dn, z written
+  if (timed)
+    prof_end(c, double(S.nnz) * (sizeof(T) + 4.0) + double(S.nrows) * sizeof(T) * (W * (rvec ? 7.0 : 6.0) + 1.0));
+}
+
+template <class T>
+void vel_in(stokes_ctx* c, int nrb, const double* src, T* dst) {
+  dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
+    constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
+    hipLaunchKernelGGL((k_vel_in<T, D, N>), dim3(grid_for(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int, c->n_p2,
+                       c->int2nat.as<int32_t>(), src, dst);
+  });
+  check_launch();
+}
+
+template <class T>
+void vel_out(stokes_ctx* c, int nrb, const T* src, const double* ubc, double* dst, int bnd_fill) {
+  dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
+    constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
+    hipLaunchKernelGGL((k_vel_out<T, D, N>), dim3(grid_for(c->n_p2)), dim3(kBlock), 0, c->stream, c->n_p2,
+                       c->nat2int.as<int32_t>(), src, ubc, dst, bnd_fill);
+  });
+  check_launch();
+}
+
+template <class T>
+void p_in(stokes_ctx* c, int nrb, const double* src, T* dst) {
+  dispatch_w(nrb, [&](auto Nc) {
+    constexpr int N = decltype(Nc)::value;
+    hipLaunchKernelGGL((k_p_in<T, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1, src, dst);
+  });
+  check_launch();
+}
+
+template <class T>
+void p_out(stokes_ctx* c, int nrb, const T* src, double* dst) {
+  dispatch_w(nrb, [&](auto Nc) {
+    constexpr int N = decltype(Nc)::value;
+    hipLaunchKernelGGL((k_p_out<T, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1, src, dst);
+  });
+  check_launch();
+}
+
+void rhs(stokes_ctx* c, int nrb, const double* f, const double* ubc, double* F, double* g) {
+  dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
+    constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
+    hipLaunchKernelGGL((k_rhs_u<D, N>), dim3(grid_for(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int, c->n_p2,
+                       c->int2nat.as<int32_t>(), c->nat2int.as<int32_t>(), c->p2full.rowptr.as<int32_t>(),
+                       c->p2full.cols.as<int32_t>(), c->M_full.as<double>(), c->L_full.as<double>(), c->prob.alpha,
+                       c->prob.mu, f, ubc, F);
+    check_launch();
+    hipLaunchKernelGGL((k_rhs_p<D, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1, c->n_p2,
+                       c->nat2int.as<int32_t>(), c->bfull.rowptr.as<int32_t>(), c->bfull.cols.as<int32_t>(),
+                       c->B_full.as<double>(), ubc, g);
+  });
+  check_launch();
+}
+
+void adj_jp(stokes_ctx* c, int nrb, double* g) {
+  double* sum = c->red.result.as<double>() + 3 * kMaxSys;
+  dot_dev<double>(c, c->n_p1, nrb, g, c->ones64.as<double>(), nullptr, sum);
+  dispatch_w(nrb, [&](auto Nc) {
+    constexpr int N = decltype(Nc)::value;
+    hipLaunchKernelGGL((k_adj_jp<N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1,
+                       c->mQ.as<double>(), (const double*)sum, 1.0 / c->mQ_sum, g);
+  });
+  check_launch();
+}
+
+void adj_dJdf(stokes_ctx* c, int nrb, const double* lam, double* out) {
+  dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
+    constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
+    hipLaunchKernelGGL((k_adj_dJdf<D, N>), dim3(grid_for(c->n_p2)), dim3(kBlock), 0, c->stream, c->n_p2,
+                       c->nat2int.as<int32_t>(), c->p2full.rowptr.as<int32_t>(), c->p2full.cols.as<int32_t>(),
+                       c->M_full.as<double>(), lam, out);
+  });
+  check_launch();
+}
+
+void adj_dJdmu(stokes_ctx* c, int nrb, const double* u_full, const double* lam, double* res_dev) {
+  dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
+    constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
+    hipLaunchKernelGGL((k_adj_dJdmu<D, N>), dim3(grid_for(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int, c->n_p2,
+                       c->int2nat.as<int32_t>(), c->p2full.rowptr.as<int32_t>(), c->p2full.cols.as<int32_t>(),
+                       c->L_full.as<double>(), u_full, lam, res_dev, partials(c), ticket(c));
+  });
+  check_launch();
+}
+
+#define INST(T)                                                                                                      \
+  template void spmv<T>(stokes_ctx*, const Sell&, const T*, int, const T*, T*, T, const T*, T);                     \
+  template void Bmul<T>(stokes_ctx*, int, const T*, T*, T, const T*, T);                                            \
+  template void Btmul<T>(stokes_ctx*, int, const T*, const T*, T*, T, const T*, T);                                 \
+  template void momentum<T>(stokes_ctx*, int, const T*, const T*, const T*, T*, T, const T*);                       \
+  template void dot_dev<T>(stokes_ctx*, int64_t, int, const T*, const T*, const double*, double*);                  \
+  template std::vector<double> dot_host<T>(stokes_ctx*, int64_t, int, const T*, const T*, const double*);           \
+  template void remove_mean<T>(stokes_ctx*, int, T*);                                                               \
+  template void normalize_pressure<T>(stokes_ctx*, int, T*);                                                        \
+  template void axpby<T>(stokes_ctx*, int64_t, T, const T*, T, T*);                                                 \
+  template void axpy_sys<T>(stokes_ctx*, int64_t, int, int, const double*, double, const T*, T*);                   \
+  template void cg_spmv<T>(stokes_ctx*, int64_t, const Sell*, const T*, int, const T*, const T*, T*, T*, Scalars*, int, \
+                           int);                                                                                 \
+  template void cg_update<T>(stokes_ctx*, int64_t, int, int, T*, T*, const T*, const T*, const T*, T, T*, T*,       \
+                             Scalars*, int, int);                                                                    \
+  template void cheb_init<T>(stokes_ctx*, int64_t, int, const T*, const T*, T, T*, T*);                             \
+  template void cheb_step<T>(stokes_ctx*, const Sell&, const T*, int, const T*, T*, const T*, T*, T*, const T*, T,  \
+                             T, const T*, Scalars*, int, int, int);                                                  \
+  template void vel_in<T>(stokes_ctx*, int, const double*, T*);                                                     \
+  template void vel_out<T>(stokes_ctx*, int, const T*, const double*, double*, int);                                \
+  template void p_in<T>(stokes_ctx*, int, const double*, T*);                                                       \
+  template void p_out<T>(stokes_ctx*, int, const T*, double*);
+
+INST(double)
+INST(float)
+template void cast<double, float>(stokes_ctx*, int64_t, const double*, float*);
+template void cast<float, double>(stokes_ctx*, int64_t, const float*, double*);
+
+}  // namespace ops
+}  // namespace stokes

@@ -1,0 +1,22 @@
+// Solver entry points used by the C ABI layer.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace stokes {
+
+struct SolveStats {
+  int inner_u = 0, inner_p = 0, outer = 0, sweeps = 0;
+  double seconds_orth = 0;
+  std::vector<double> rel_res;  // per right-hand side, final true residual
+};
+
+// Solve K x = b with b = (F, g) in the internal FP64 layout, x = (xu, xp) as
+// initial guess and result.  method 0 = coupled FGMRES, 1 = Schur FCG.
+// Returns STOKES_OK or STOKES_NOT_CONVERGED.
+int solve_internal(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, const double* F, const double* g,
+                   double* xu, double* xp, SolveStats& st);
+
+}  // namespace stokes

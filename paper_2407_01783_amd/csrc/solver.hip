@@ -1,0 +1,682 @@
+// Krylov solvers of the generalized Stokes system.
+//
+//   * inner velocity solve A~^{-1}: PCG (one system per component and
+//     right-hand side; one joint system per right-hand side when the
+//     augmented-Lagrangian term couples the components) preconditioned by a
+//     Chebyshev-Jacobi polynomial of A = alpha M + mu L (the paper's
+//     A~_{lambda,3}, Sec. 3.2), or the polynomial alone (fixed mode);
+//   * Cahouet-Chabard preconditioner of the Schur complement (Sec. 4.1):
+//     C = alpha X^{-1} + mu (1 + gamma) M_Q^{-1}, X in {L_Q, B Lambda^{-1} B^T,
+//     B M^{-1} B^T}, X^{-1} by PCG preconditioned with Chebyshev-Jacobi on
+//     eps M_Q + L_Q (eps = 1, Sec. 4.2);
+//   * Method 1 (Sec. 2.3): flexible CG on S = B A^{-1} B^T;
+//   * Method 2 (Sec. 2.4): right-preconditioned flexible GMRES(m) on the
+//     coupled matrix with the block preconditioners of Sec. 2.4 / 6.2,
+//     classical Gram-Schmidt with re-orthogonalisation (CGS2);
+//   * an FP64 refinement loop around either: true residual of the coupled
+//     system, correction solve (inner precision FP32 in mixed mode), update.
+//
+// All vectors are in the internal layout (see kernels.h); scalars of the
+// inner CG live on the device, outer Krylov scalars on the host.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <type_traits>
+
+#include "kernels.h"
+#include "ops.h"
+#include "solver.h"
+
+namespace stokes {
+
+namespace {
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+template <class F>
+void dispatch_dn(int D, int NRB, F&& f) {
+  auto inner = [&](auto Dc) {
+    switch (NRB) {
+      case 1: f(Dc, IC<1>{}); break;
+      case 2: f(Dc, IC<2>{}); break;
+      case 4: f(Dc, IC<4>{}); break;
+      case 8: f(Dc, IC<8>{}); break;
+      default: throw Error(STOKES_ERR_UNSUPPORTED, "batch");
+    }
+  };
+  if (D == 3) inner(IC<3>{});
+  else inner(IC<2>{});
+}
+
+struct ChebCoef {
+  double theta_inv = 1;
+  std::vector<double> c1, c2;  // steps 1..k-1
+};
+
+// Coefficients of the Chebyshev iteration on [lo, hi] (Saad, Iterative
+// Methods for Sparse Linear Systems, Alg. 12.1).
+ChebCoef cheb_coef(const Bounds& b, int degree) {
+  ChebCoef k;
+  const double theta = 0.5 * (b.hi + b.lo), delta = 0.5 * (b.hi - b.lo);
+  k.theta_inv = 1.0 / theta;
+  if (degree <= 1) return k;
+  const double sigma1 = theta / delta;
+  double rho = 1.0 / sigma1;
+  for (int j = 1; j < degree; ++j) {
+    const double rn = 1.0 / (2.0 * sigma1 - rho);
+    k.c1.push_back(rn * rho);
+    k.c2.push_back(2.0 * rn / delta);
+    rho = rn;
+  }
+  return k;
+}
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// ======================================================================
+template <class T>
+class Engine {
+ public:
+  Engine(stokes_ctx* c, const stokes_solve_opts& o, int nrb, SolveStats& st)
+      : c_(c), o_(o), nrb_(nrb), D_(c->dim), W_(c->dim * nrb), st_(st) {
+    gamma_ = c->prob.gamma;
+    mu_ = c->prob.mu;
+    alpha_ = c->prob.alpha;
+    const bool f32 = std::is_same<T, float>::value;
+    al_deg_ = f32 ? 18 : 26;  // M_Q^{-1} inside A_gamma: 2 * 0.382^k below 1e-7 / 1e-11
+    cc_mq_deg_ = 6;           // mu M_Q^{-1} term of the Cahouet-Chabard operator
+    mv_deg_ = 8;              // M_V^{-1} inside B M^{-1} B^T
+  }
+
+  // ------------------------------------------------------------ buffers
+  T* buf(const std::string& name, int64_t n) {
+    return static_cast<T*>(c_->workspace(name + (std::is_same<T, float>::value ? "_f" : "_d"), n * sizeof(T)));
+  }
+  int64_t nu() const { return c_->n_int * W_; }
+  int64_t np() const { return c_->n_p1 * nrb_; }
+
+  const T* A() const { return ops::pick<T>(c_->A64, c_->A32); }
+  const T* dA() const { return ops::pick<T>(c_->dA64, c_->dA32); }
+  Scalars* scal(int i) { return c_->scal.as<Scalars>() + i; }
+
+  // ------------------------------------------------------- Chebyshev
+  // z = p_k(D^{-1} S) D^{-1} r  (k = degree), buffers tagged by `tag`
+  void cheb_apply(const std::string& tag, const Sell& S, const T* vals, const T* dinv, const Bounds& b, int degree,
+                  int W, const T* r, T* z) {
+    const int64_t n = S.nrows * W;
+    const ChebCoef k = cheb_coef(b, degree);
+    T* d0 = buf(tag + "_d0", n);
+    T* d1 = buf(tag + "_d1", n);
+    T* res = buf(tag + "_res", n);
+    ops::cheb_init<T>(c_, S.nrows, W, r, dinv, (T)k.theta_inv, d0, z);
+    for (int j = 1; j < degree; ++j) {
+      ops::cheb_step<T>(c_, S, vals, W, d0, d1, j == 1 ? r : res, res, z, dinv, (T)k.c1[j - 1], (T)k.c2[j - 1],
+                        nullptr, nullptr, 1, 0, 0);
+      std::swap(d0, d1);
+    }
+  }
+
+  // ------------------------------------------------------------ PCG
+  struct Op {
+    const Sell* S = nullptr;  // fused scalar SELL operator, or
+    std::function<void(const T*, T*)> apply;  // composite t = X z
+    std::function<void(const T*, T*)> extra;  // added term (augmented Lagrangian)
+  };
+  struct Prec {
+    const Sell* S;
+    const T* vals;
+    const T* dinv;
+    Bounds b;
+    int degree;
+  };
+
+  // Solve op x = b per system to ||r|| <= rtol ||b||; returns iterations.
+  int pcg(const std::string& tag, const Op& op, const T* opvals, const Prec& pc, int64_t nrows, int W, int cps,
+          const T* b, T* x, double rtol, int maxit, int sc_index) {
+    const int64_t n = nrows * W;
+    const int nsys = W / cps;
+    Scalars* sc = scal(sc_index);
+    T* r = buf(tag + "_r", n);
+    T* z = buf(tag + "_z", n);
+    T* p = buf(tag + "_p", n);
+    T* q = buf(tag + "_q", n);
+    T* d0 = buf(tag + "_d0", n);
+    T* d1 = buf(tag + "_d1", n);
+    T* res = buf(tag + "_res", n);
+    T* t = (op.apply || op.extra) ? buf(tag + "_t", n) : nullptr;
+    HIP_CHECK(hipMemsetAsync(x, 0, n * sizeof(T), c_->stream));
+    HIP_CHECK(hipMemsetAsync(p, 0, n * sizeof(T), c_->stream));
+    HIP_CHECK(hipMemsetAsync(q, 0, n * sizeof(T), c_->stream));
+    HIP_CHECK(hipMemcpyAsync(r, b, n * sizeof(T), hipMemcpyDeviceToDevice, c_->stream));
+    double* slots = c_->red.result.as<double>() + 2 * kMaxSys;
+    ops::dot_dev<T>(c_, nrows, W, b, nullptr, nullptr, slots);
+    hipLaunchKernelGGL(k_scal_init, dim3(1), dim3(64), 0, c_->stream, sc, (const double*)slots, cps, nsys,
+                       rtol * rtol);
+    ops::check_launch();
+    const ChebCoef k = cheb_coef(pc.b, pc.degree);
+    const T thinv = pc.degree > 1 ? (T)k.theta_inv : (T)1;
+    // z = M^{-1} r with rho = r . z
+    auto precond = [&](bool first) {
+      if (pc.degree <= 1) {
+        ops::cheb_init<T>(c_, nrows, W, r, pc.dinv, thinv, d0, z);
+        ops::dot_dev<T>(c_, nrows, W, r, z, nullptr, slots);
+        hipLaunchKernelGGL(k_scal_rho, dim3(1), dim3(64), 0, c_->stream, sc, (const double*)slots, cps, nsys,
+                           first ? 1 : 0);
+        ops::check_launch();
+        return;
+      }
+      if (first) ops::cheb_init<T>(c_, nrows, W, r, pc.dinv, thinv, d0, z);
+      T* da = d0;
+      T* db = d1;
+      for (int j = 1; j < pc.degree; ++j) {
+        const bool last = j == pc.degree - 1;
+        ops::cheb_step<T>(c_, *pc.S, pc.vals, W, da, db, j == 1 ? r : res, res, z, pc.dinv, (T)k.c1[j - 1],
+                          (T)k.c2[j - 1], last ? r : nullptr, sc, cps, nsys, first ? 1 : 0);
+        std::swap(da, db);
+      }
+    };
+    precond(true);
+    int it = 0;
+    for (;;) {
+      sync_scalars(sc_index);
+      const Scalars& h = *c_->h_scal;
+      if (h.breakdown) throw Error(STOKES_ERR_BREAKDOWN, "inner CG breakdown (non-positive curvature)");
+      bool any = false;
+      for (int s = 0; s < nsys; ++s) any = any || h.active[s];
+      if (!any || it >= maxit) break;
+      ++it;
+      if (op.apply) {
+        op.apply(z, t);
+        ops::cg_spmv<T>(c_, nrows, nullptr, nullptr, W, z, t, q, p, sc, cps, nsys);
+      } else {
+        if (op.extra) op.extra(z, t);
+        ops::cg_spmv<T>(c_, nrows, op.S, opvals, W, z, op.extra ? t : nullptr, q, p, sc, cps, nsys);
+      }
+      if (pc.degree <= 1) {
+        ops::cg_update<T>(c_, nrows, W, 1, x, r, p, q, pc.dinv, (T)1, d0, z, sc, cps, nsys);
+      } else {
+        ops::cg_update<T>(c_, nrows, W, 0, x, r, p, q, pc.dinv, thinv, d0, z, sc, cps, nsys);
+        precond(false);
+      }
+    }
+    return it;
+  }
+
+  void sync_scalars(int i) {
+    HIP_CHECK(hipMemcpyAsync(c_->h_scal, scal(i), sizeof(Scalars), hipMemcpyDeviceToHost, c_->stream));
+    HIP_CHECK(hipStreamSynchronize(c_->stream));
+  }
+
+  // ------------------------------------------------- operator pieces
+  // t = gamma mu B^T M_Q^{-1} B z   (augmented-Lagrangian term, Eq. "def_of_Alambda")
+  void al_term(const T* z, T* t) {
+    T* bp = buf("al_bz", np());
+    T* y = buf("al_y", np());
+    ops::Bmul<T>(c_, nrb_, z, bp, (T)1, nullptr, (T)0);
+    cheb_apply("alq", c_->sQ, ops::pick<T>(c_->MQ64, c_->MQ32), ops::pick<T>(c_->dMQ64, c_->dMQ32), c_->bMQ, al_deg_,
+               nrb_, bp, y);
+    ops::Btmul<T>(c_, nrb_, y, nullptr, t, (T)(gamma_ * mu_), nullptr, (T)0);
+  }
+
+  // x = A~^{-1} b (velocity block)
+  void vel_solve(const T* b, T* x) {
+    const Prec pc{&c_->sA, A(), dA(), c_->bA, std::max(1, o_.cheb_degree)};
+    if (o_.inner_mode == STOKES_INNER_FIXED) {
+      cheb_apply("vfx", c_->sA, A(), dA(), c_->bA, std::max(1, o_.cheb_degree), W_, b, x);
+      return;
+    }
+    Op op;
+    op.S = &c_->sA;
+    int cps = 1;
+    if (gamma_ > 0) {
+      op.extra = [this](const T* z, T* t) { al_term(z, t); };
+      cps = D_;
+    }
+    st_.inner_u += pcg("vcg", op, A(), pc, c_->n_int, W_, cps, b, x, o_.inner_rtol_u, o_.max_inner, 0);
+  }
+
+  // t = X z for the Cahouet-Chabard family
+  void x_apply(const T* z, T* t) {
+    if (o_.schur_pc == STOKES_CC_LUMPED) {
+      T* tu = buf("x_tu", nu());
+      ops::Btmul<T>(c_, nrb_, z, ops::pick<T>(c_->lamInv64, c_->lamInv32), tu, (T)1, nullptr, (T)0);
+      ops::Bmul<T>(c_, nrb_, tu, t, (T)1, nullptr, (T)0);
+    } else if (o_.schur_pc == STOKES_CC_MASS) {
+      T* tu = buf("x_tu", nu());
+      T* yu = buf("x_yu", nu());
+      ops::Btmul<T>(c_, nrb_, z, nullptr, tu, (T)1, nullptr, (T)0);
+      cheb_apply("mvc", c_->sA, ops::pick<T>(c_->MV64, c_->MV32), ops::pick<T>(c_->dMV64, c_->dMV32), c_->bMV,
+                 mv_deg_, W_, tu, yu);
+      ops::Bmul<T>(c_, nrb_, yu, t, (T)1, nullptr, (T)0);
+    } else {
+      ops::spmv<T>(c_, c_->sQ, ops::pick<T>(c_->LQ64, c_->LQ32), nrb_, z, t, (T)1, nullptr, (T)0);
+    }
+  }
+
+  // x = X^{-1} b on the mean-free pressures
+  void x_solve(const T* b, T* x) {
+    const Prec pc{&c_->sQ, ops::pick<T>(c_->XQ64, c_->XQ32), ops::pick<T>(c_->dXQ64, c_->dXQ32), c_->bXQ,
+                  std::max(1, o_.cheb_degree)};
+    if (o_.inner_mode == STOKES_INNER_FIXED) {
+      cheb_apply("xfx", *pc.S, pc.vals, pc.dinv, pc.b, pc.degree, nrb_, b, x);
+      return;
+    }
+    Op op;
+    const T* opvals = nullptr;
+    if (o_.schur_pc == STOKES_CC_LAPLACE) {
+      op.S = &c_->sQ;
+      opvals = ops::pick<T>(c_->LQ64, c_->LQ32);
+    } else {
+      op.apply = [this](const T* z, T* t) { x_apply(z, t); };
+    }
+    st_.inner_p += pcg("pcg", op, opvals, pc, c_->n_p1, nrb_, 1, b, x, o_.inner_rtol_p, o_.max_inner, 1);
+  }
+
+  // z = C r = alpha X^{-1} r + mu (1 + gamma) M_Q^{-1} r, mean removed
+  void cc_apply(const T* r, T* z) {
+    T* y = buf("cc_y", np());
+    x_solve(r, z);
+    cheb_apply("ccq", c_->sQ, ops::pick<T>(c_->MQ64, c_->MQ32), ops::pick<T>(c_->dMQ64, c_->dMQ32), c_->bMQ,
+               cc_mq_deg_, nrb_, r, y);
+    ops::axpby<T>(c_, np(), (T)(mu_ * (1.0 + gamma_)), y, (T)alpha_, z);
+    ops::remove_mean<T>(c_, nrb_, z);
+  }
+
+  // z = P^{-1} v, block preconditioners of the coupled matrix (Sec. 2.4)
+  void block_prec(const T* vu, const T* vp, T* zu, T* zp) {
+    T* tp = buf("bp_tp", np());
+    T* tu = buf("bp_tu", nu());
+    T* yu = buf("bp_yu", nu());
+    if (o_.coupled_pc == STOKES_PC_UPPER) {
+      cc_apply(vp, zp);
+      ops::Btmul<T>(c_, nrb_, zp, nullptr, tu, (T)1, vu, (T)1);  // tu = v_u + B^T z_p
+      vel_solve(tu, zu);
+      return;
+    }
+    vel_solve(vu, zu);                                            // y_u = A~^{-1} v_u
+    ops::Bmul<T>(c_, nrb_, zu, tp, (T)-1, vp, (T)1);             // t_p = v_p - B y_u
+    cc_apply(tp, zp);                                             // z_p = S~^{-1} t_p
+    if (o_.coupled_pc == STOKES_PC_LOWER) return;
+    ops::Btmul<T>(c_, nrb_, zp, nullptr, tu, (T)1, nullptr, (T)0);  // B^T z_p
+    vel_solve(tu, yu);                                               // A~^{-1} B^T z_p
+    ops::axpby<T>(c_, nu(), (T)1, yu, (T)1, zu);                      // z_u = y_u + ...
+  }
+
+  // ------------------------------------------------------- helpers
+  template <class TX, class TY>
+  void axpy_rhs(int64_t nrows, bool vel, const double* a, const double* b, const TX* x, TY* y) {
+    Coef8 ca{}, cb{};
+    for (int r = 0; r < 8; ++r) {
+      ca.v[r] = r < nrb_ ? a[r] : 0;
+      cb.v[r] = r < nrb_ ? b[r] : 0;
+    }
+    dispatch_dn(D_, nrb_, [&](auto Dc, auto Nc) {
+      constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
+      if (vel)
+        hipLaunchKernelGGL((k_axpy_rhs<TX, TY, D * N, D>), dim3(ops::grid_for(nrows)), dim3(kBlock), 0, c_->stream,
+                           nrows, ca, cb, x, y);
+      else
+        hipLaunchKernelGGL((k_axpy_rhs<TX, TY, N, 1>), dim3(ops::grid_for(nrows)), dim3(kBlock), 0, c_->stream,
+                           nrows, ca, cb, x, y);
+    });
+    ops::check_launch();
+  }
+
+  // per right-hand-side dots over (velocity, pressure) FP64 pieces
+  std::vector<double> dots(const double* xu, const double* yu, const double* xp, const double* yp) {
+    std::vector<double> out(nrb_, 0.0);
+    if (xu) {
+      auto s = ops::dot_host<double>(c_, c_->n_int, W_, xu, yu);
+      for (int w = 0; w < W_; ++w) out[w / D_] += s[w];
+    }
+    if (xp) {
+      auto s = ops::dot_host<double>(c_, c_->n_p1, nrb_, xp, yp);
+      for (int r = 0; r < nrb_; ++r) out[r] += s[r];
+    }
+    return out;
+  }
+
+  // y = (A u - B^T p [+ AL]) , w_p = B u  in FP64 (coupled operator)
+  void coupled_apply64(const double* u, const double* p, double* yu, double* yp, bool al) {
+    ops::Bmul<double>(c_, nrb_, u, yp, 1.0, nullptr, 0.0);
+    double* ex = nullptr;
+    if (al && gamma_ > 0) {
+      double* y = static_cast<double*>(c_->workspace("al64_y", np() * sizeof(double)));
+      ex = static_cast<double*>(c_->workspace("al64_t", nu() * sizeof(double)));
+      Engine<double> e64(c_, o_, nrb_, st_);
+      e64.cheb_apply("al64q", c_->sQ, c_->MQ64.as<double>(), c_->dMQ64.as<double>(), c_->bMQ, 26, nrb_, yp, y);
+      ops::Btmul<double>(c_, nrb_, y, nullptr, ex, gamma_ * mu_, nullptr, 0.0);
+    }
+    ops::momentum<double>(c_, nrb_, u, p, ex, yu, 1.0, nullptr);
+  }
+
+  // ------------------------------------------------------ FGMRES cycle
+  // One restart cycle on K_gamma delta = r (FP64 Arnoldi, preconditioner in T);
+  // x += delta.  target[r]: absolute residual goal per right-hand side.
+  int fgmres_cycle(const double* ru, const double* rp, double* xu, double* xp, const std::vector<double>& target,
+                   int max_steps) {
+    const int m = std::max(1, std::min({o_.restart, 63, max_steps}));
+    const int64_t nc = nu() + np();
+    double* V = static_cast<double*>(c_->workspace("gm_V", (m + 1) * nc * sizeof(double)));
+    T* Z = buf("gm_Z", m * nc);
+    double* w = static_cast<double*>(c_->workspace("gm_w", nc * sizeof(double)));
+    double* zd = static_cast<double*>(c_->workspace("gm_zd", nc * sizeof(double)));
+    T* vin = buf("gm_vin", nc);
+    const int nbx = ops::grid_for(c_->n_int + c_->n_p1);
+    double* part = static_cast<double*>(c_->workspace("gm_part", (int64_t)(m + 1) * nbx * 8 * sizeof(double)));
+    double* hdev = static_cast<double*>(c_->workspace("gm_h", 3 * 64 * 8 * sizeof(double)));
+    double* h1 = hdev;
+    double* h2 = hdev + 64 * 8;
+    double* nrm = hdev + 2 * 64 * 8;
+    double* hhost = static_cast<double*>(c_->workspace_host("gm_hh", 3 * 64 * 8 * sizeof(double)));
+    double* yhost = static_cast<double*>(c_->workspace_host("gm_yh", 64 * 8 * sizeof(double)));
+    double* ydev = static_cast<double*>(c_->workspace("gm_y", 64 * 8 * sizeof(double)));
+
+    auto mdot = [&](const double* Vb, int nb, const double* x, double* hout) {
+      dispatch_dn(D_, nrb_, [&](auto Dc, auto Nc) {
+        constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
+        hipLaunchKernelGGL((k_mdot<double, D, N>), dim3(nbx, nb), dim3(kBlock), 0, c_->stream, c_->n_int, c_->n_p1,
+                           Vb, nc, x, part);
+        ops::check_launch();
+        hipLaunchKernelGGL((k_mdot_fin<N>), dim3(nb), dim3(kBlock), 0, c_->stream, nbx, (const double*)part, hout);
+      });
+      ops::check_launch();
+    };
+    auto mupdate = [&](auto* Vb, int nb, const double* h, double sgn, double* x, double* res) {
+      using TV = std::remove_const_t<std::remove_pointer_t<decltype(Vb)>>;
+      dispatch_dn(D_, nrb_, [&](auto Dc, auto Nc) {
+        constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
+        if (res)
+          hipLaunchKernelGGL((k_mupdate<TV, D, N, 1>), dim3(nbx), dim3(kBlock), 0, c_->stream, c_->n_int, c_->n_p1,
+                             (const TV*)Vb, nc, nb, h, sgn, x, res, c_->red.partials.as<double>(),
+                             c_->red.ticket.as<unsigned>());
+        else
+          hipLaunchKernelGGL((k_mupdate<TV, D, N, 0>), dim3(nbx), dim3(kBlock), 0, c_->stream, c_->n_int, c_->n_p1,
+                             (const TV*)Vb, nc, nb, h, sgn, x, res, c_->red.partials.as<double>(),
+                             c_->red.ticket.as<unsigned>());
+      });
+      ops::check_launch();
+    };
+    auto scale_into = [&](const std::vector<double>& s, const double* src, double* dst) {
+      Coef8 cs{};
+      for (int r = 0; r < 8; ++r) cs.v[r] = r < nrb_ ? s[r] : 0;
+      dispatch_dn(D_, nrb_, [&](auto Dc, auto Nc) {
+        constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
+        hipLaunchKernelGGL((k_scale_coupled<D, N>), dim3(ops::grid_for(nc)), dim3(kBlock), 0, c_->stream, c_->n_int,
+                           c_->n_p1, cs, src, dst);
+      });
+      ops::check_launch();
+    };
+
+    // V_0 = r / ||r||
+    HIP_CHECK(hipMemcpyAsync(w, ru, nu() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+    HIP_CHECK(hipMemcpyAsync(w + nu(), rp, np() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+    mdot(w, 1, w, h1);
+    HIP_CHECK(hipMemcpyAsync(hhost, h1, nrb_ * sizeof(double), hipMemcpyDeviceToHost, c_->stream));
+    HIP_CHECK(hipStreamSynchronize(c_->stream));
+    const int R = nrb_;
+    std::vector<double> beta(R), g((m + 1) * R, 0.0), H((m + 1) * m * R, 0.0), cs(m * R), sn(m * R);
+    std::vector<int> active(R), kdone(R, 0);
+    std::vector<double> s(R);
+    for (int r = 0; r < R; ++r) {
+      beta[r] = std::sqrt(std::max(0.0, hhost[r]));
+      active[r] = beta[r] > target[r];
+      s[r] = active[r] ? 1.0 / beta[r] : 0.0;
+      g[0 * R + r] = beta[r];
+    }
+    scale_into(s, w, V);
+    auto Hat = [&](int i, int j, int r) -> double& { return H[((size_t)i * m + j) * R + r]; };
+    int j = 0;
+    for (; j < m; ++j) {
+      bool any = false;
+      for (int r = 0; r < R; ++r) any = any || active[r];
+      if (!any) break;
+      double* Vj = V + (int64_t)j * nc;
+      T* Zj = Z + (int64_t)j * nc;
+      // z_j = P^{-1} v_j in the inner precision
+      const T* vsrc;
+      if (std::is_same<T, double>::value) {
+        vsrc = reinterpret_cast<const T*>(Vj);
+      } else {
+        ops::cast<double, float>(c_, nc, Vj, reinterpret_cast<float*>(vin));
+        vsrc = vin;
+      }
+      block_prec(vsrc, vsrc + nu(), Zj, Zj + nu());
+      const double* zsrc;
+      if (std::is_same<T, double>::value) {
+        zsrc = reinterpret_cast<const double*>(Zj);
+      } else {
+        ops::cast<float, double>(c_, nc, reinterpret_cast<const float*>(Zj), zd);
+        zsrc = zd;
+      }
+      // w = K_gamma z_j (FP64)
+      coupled_apply64(zsrc, zsrc + nu(), w, w + nu(), true);
+      // CGS2
+      const double t0 = now();
+      mdot(V, j + 1, w, h1);
+      mupdate(V, j + 1, h1, -1.0, w, nullptr);
+      mdot(V, j + 1, w, h2);
+      mupdate(V, j + 1, h2, -1.0, w, nrm);
+      HIP_CHECK(hipMemcpyAsync(hhost, hdev, 3 * 64 * 8 * sizeof(double), hipMemcpyDeviceToHost, c_->stream));
+      HIP_CHECK(hipStreamSynchronize(c_->stream));
+      st_.seconds_orth += now() - t0;
+      for (int r = 0; r < R; ++r) {
+        if (!active[r]) {
+          s[r] = 0;
+          continue;
+        }
+        for (int i = 0; i <= j; ++i) Hat(i, j, r) = hhost[i * R + r] + hhost[64 * 8 + i * R + r];
+        const double hn = std::sqrt(std::max(0.0, hhost[2 * 64 * 8 + r]));
+        // apply previous rotations, then a new one
+        for (int i = 0; i < j; ++i) {
+          const double a = Hat(i, j, r), b = Hat(i + 1, j, r);
+          Hat(i, j, r) = cs[i * R + r] * a + sn[i * R + r] * b;
+          Hat(i + 1, j, r) = -sn[i * R + r] * a + cs[i * R + r] * b;
+        }
+        const double a = Hat(j, j, r);
+        const double den = std::hypot(a, hn);
+        const double cc = den > 0 ? a / den : 1.0, ss = den > 0 ? hn / den : 0.0;
+        cs[j * R + r] = cc;
+        sn[j * R + r] = ss;
+        Hat(j, j, r) = den;
+        g[(j + 1) * R + r] = -ss * g[j * R + r];
+        g[j * R + r] = cc * g[j * R + r];
+        kdone[r] = j + 1;
+        const double est = std::fabs(g[(j + 1) * R + r]);
+        if (est <= target[r] || hn <= 1e-300) active[r] = 0;
+        s[r] = (active[r] && hn > 0) ? 1.0 / hn : 0.0;
+      }
+      st_.outer += 1;
+      if (j + 1 < m) scale_into(s, w, V + (int64_t)(j + 1) * nc);
+    }
+    // y = H^{-1} g per right-hand side; x += Z y
+    const int steps = j;
+    std::fill(yhost, yhost + 64 * 8, 0.0);
+    for (int r = 0; r < R; ++r) {
+      const int k = kdone[r];
+      for (int i = k - 1; i >= 0; --i) {
+        double acc = g[i * R + r];
+        for (int l = i + 1; l < k; ++l) acc -= Hat(i, l, r) * yhost[l * R + r];
+        yhost[i * R + r] = Hat(i, i, r) != 0 ? acc / Hat(i, i, r) : 0.0;
+      }
+    }
+    if (steps > 0) {
+      HIP_CHECK(hipMemcpyAsync(ydev, yhost, steps * R * sizeof(double), hipMemcpyHostToDevice, c_->stream));
+      // x is the concatenation (xu, xp) only when contiguous; update both parts
+      double* xc = static_cast<double*>(c_->workspace("gm_x", nc * sizeof(double)));
+      HIP_CHECK(hipMemcpyAsync(xc, xu, nu() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+      HIP_CHECK(hipMemcpyAsync(xc + nu(), xp, np() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+      mupdate((const T*)Z, steps, ydev, 1.0, xc, nullptr);
+      HIP_CHECK(hipMemcpyAsync(xu, xc, nu() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+      HIP_CHECK(hipMemcpyAsync(xp, xc + nu(), np() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+      HIP_CHECK(hipStreamSynchronize(c_->stream));
+    }
+    return steps;
+  }
+
+  // ---------------------------------------------------- Schur FCG sweep
+  // Correction (du, dp) of K_gamma (du, dp) = (ru, rp) by flexible CG on the
+  // Schur complement; x += correction.  target: absolute continuity goal.
+  int schur_sweep(const double* ru, const double* rp, double* xu, double* xp, const std::vector<double>& target,
+                  int max_steps) {
+    const int R = nrb_;
+    T* tu = buf("sc_tu", nu());
+    T* vu = buf("sc_vu", nu());
+    T* tp = buf("sc_tp", np());
+    T* zp = buf("sc_zp", np());
+    double* s = static_cast<double*>(c_->workspace("sc_s", np() * sizeof(double)));
+    double* z = static_cast<double*>(c_->workspace("sc_z", np() * sizeof(double)));
+    double* zo = static_cast<double*>(c_->workspace("sc_zo", np() * sizeof(double)));
+    double* pp = static_cast<double*>(c_->workspace("sc_p", np() * sizeof(double)));
+    double* q = static_cast<double*>(c_->workspace("sc_q", np() * sizeof(double)));
+    auto to_T = [&](const double* x, T* y, int64_t n) {
+      if (std::is_same<T, double>::value) HIP_CHECK(hipMemcpyAsync(y, x, n * sizeof(T), hipMemcpyDeviceToDevice, c_->stream));
+      else ops::cast<double, float>(c_, n, x, reinterpret_cast<float*>(y));
+    };
+    auto to_64 = [&](const T* x, double* y, int64_t n) {
+      if (std::is_same<T, double>::value) HIP_CHECK(hipMemcpyAsync(y, x, n * sizeof(T), hipMemcpyDeviceToDevice, c_->stream));
+      else ops::cast<float, double>(c_, n, reinterpret_cast<const float*>(x), y);
+    };
+    std::vector<double> one(R, 1.0), zero(R, 0.0), mone(R, -1.0);
+    // w_u = A~^{-1} r_u ; x_u += w_u ; s = r_p - B w_u
+    to_T(ru, tu, nu());
+    vel_solve(tu, vu);
+    axpy_rhs<T, double>(c_->n_int, true, one.data(), one.data(), vu, xu);
+    ops::Bmul<T>(c_, nrb_, vu, tp, (T)1, nullptr, (T)0);
+    to_64(tp, q, np());
+    HIP_CHECK(hipMemcpyAsync(s, rp, np() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+    ops::axpby<double>(c_, np(), -1.0, q, 1.0, s);
+    ops::remove_mean<double>(c_, nrb_, s);
+    auto cc64 = [&](const double* in, double* out) {
+      to_T(in, tp, np());
+      cc_apply(tp, zp);
+      to_64(zp, out, np());
+    };
+    std::vector<double> ss = dots(nullptr, nullptr, s, s);
+    std::vector<int> active(R);
+    bool any = false;
+    for (int r = 0; r < R; ++r) {
+      active[r] = std::sqrt(ss[r]) > target[r];
+      any = any || active[r];
+    }
+    if (!any) return 0;
+    cc64(s, z);
+    std::vector<double> rho = dots(nullptr, nullptr, s, z);
+    HIP_CHECK(hipMemcpyAsync(pp, z, np() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+    int it = 0;
+    while (it < max_steps) {
+      ++it;
+      st_.outer += 1;
+      // q = S p = B A~^{-1} B^T p
+      to_T(pp, tp, np());
+      ops::Btmul<T>(c_, nrb_, tp, nullptr, tu, (T)1, nullptr, (T)0);
+      vel_solve(tu, vu);
+      ops::Bmul<T>(c_, nrb_, vu, tp, (T)1, nullptr, (T)0);
+      to_64(tp, q, np());
+      std::vector<double> sig = dots(nullptr, nullptr, pp, q);
+      std::vector<double> al(R, 0.0), mal(R, 0.0);
+      for (int r = 0; r < R; ++r) {
+        if (!active[r]) continue;
+        if (!(sig[r] > 0)) throw Error(STOKES_ERR_BREAKDOWN, "Schur CG breakdown (non-positive curvature)");
+        al[r] = rho[r] / sig[r];
+        mal[r] = -al[r];
+      }
+      axpy_rhs<double, double>(c_->n_p1, false, al.data(), one.data(), pp, xp);
+      axpy_rhs<T, double>(c_->n_int, true, al.data(), one.data(), vu, xu);
+      axpy_rhs<double, double>(c_->n_p1, false, mal.data(), one.data(), q, s);
+      ss = dots(nullptr, nullptr, s, s);
+      any = false;
+      for (int r = 0; r < R; ++r) {
+        if (active[r] && !(std::sqrt(ss[r]) > target[r])) active[r] = 0;
+        any = any || active[r];
+      }
+      if (!any) break;
+      std::swap(z, zo);
+      cc64(s, z);
+      std::vector<double> rz = dots(nullptr, nullptr, s, z);
+      std::vector<double> rzo = dots(nullptr, nullptr, s, zo);
+      std::vector<double> be(R, 0.0);
+      for (int r = 0; r < R; ++r) {
+        if (active[r] && rho[r] != 0) be[r] = (rz[r] - rzo[r]) / rho[r];  // Polak-Ribiere (flexible)
+        rho[r] = rz[r];
+      }
+      axpy_rhs<double, double>(c_->n_p1, false, one.data(), be.data(), z, pp);
+    }
+    return it;
+  }
+
+ private:
+  stokes_ctx* c_;
+  stokes_solve_opts o_;
+  int nrb_, D_, W_;
+  SolveStats& st_;
+  double gamma_, mu_, alpha_;
+  int al_deg_, cc_mq_deg_, mv_deg_;
+};
+
+// ======================================================================
+// Refinement loop: x (internal FP64) solves K x = b, b = (F, g).
+template <class T>
+int refine_loop(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, const double* F, const double* g,
+                double* xu, double* xp, SolveStats& st) {
+  Engine<T> e(c, o, nrb, st);
+  Engine<double> e64(c, o, nrb, st);
+  const int64_t nu = c->n_int * c->dim * nrb, np = c->n_p1 * nrb;
+  double* ru = static_cast<double*>(c->workspace("rf_ru", nu * sizeof(double)));
+  double* rp = static_cast<double*>(c->workspace("rf_rp", np * sizeof(double)));
+  std::vector<double> bn = e64.dots(F, F, g, g);
+  for (double& x : bn) x = std::sqrt(x);
+  st.rel_res.assign(nrb, 0.0);
+  int status = STOKES_NOT_CONVERGED;
+  for (int sweep = 0;; ++sweep) {
+    // r = b - K x (plain system, FP64)
+    ops::momentum<double>(c, nrb, xu, xp, nullptr, ru, -1.0, F);
+    ops::Bmul<double>(c, nrb, xu, rp, -1.0, g, 1.0);
+    std::vector<double> rn = e64.dots(ru, ru, rp, rp);
+    std::vector<double> target(nrb);
+    bool done = true;
+    for (int r = 0; r < nrb; ++r) {
+      rn[r] = std::sqrt(rn[r]);
+      st.rel_res[r] = bn[r] > 0 ? rn[r] / bn[r] : 0.0;
+      if (bn[r] > 0 && st.rel_res[r] > o.rtol) done = false;
+      // goal of this sweep: the final tolerance, or the reduction the inner
+      // precision can deliver
+      const double floor_rel = method == 0 ? (std::is_same<T, float>::value ? 1e-5 : 0.0)
+                                           : (std::is_same<T, float>::value ? std::max(10 * o.inner_rtol_u, 1e-5)
+                                                                            : 10 * o.inner_rtol_u);
+      target[r] = std::max(0.5 * o.rtol * bn[r], floor_rel * rn[r]);
+    }
+    if (done) {
+      status = STOKES_OK;
+      break;
+    }
+    if (sweep >= o.max_refine || st.outer >= o.max_outer) break;
+    st.sweeps += 1;
+    ops::remove_mean<double>(c, nrb, rp);
+    if (c->prob.gamma > 0) {  // right-hand side of the augmented system
+      double* y = static_cast<double*>(c->workspace("rf_y", np * sizeof(double)));
+      e64.cheb_apply("rfq", c->sQ, c->MQ64.as<double>(), c->dMQ64.as<double>(), c->bMQ, 26, nrb, rp, y);
+      ops::Btmul<double>(c, nrb, y, nullptr, ru, c->prob.gamma * c->prob.mu, ru, 1.0);
+    }
+    const int budget = o.max_outer - st.outer;
+    if (method == 0) e.fgmres_cycle(ru, rp, xu, xp, target, budget);
+    else e.schur_sweep(ru, rp, xu, xp, target, budget);
+  }
+  ops::normalize_pressure<double>(c, nrb, xp);
+  return status;
+}
+
+int solve_internal(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, const double* F, const double* g,
+                   double* xu, double* xp, SolveStats& st) {
+  if (o.precision == STOKES_MIXED) return refine_loop<float>(c, o, method, nrb, F, g, xu, xp, st);
+  return refine_loop<double>(c, o, method, nrb, F, g, xu, xp, st);
+}
+
+}  // namespace stokes
