@@ -46,7 +46,12 @@ class StokesSystem:
         self.I = mesh.interior_nodes
         self.nI = self.I.size
         self.np1 = mesh.n_p1
-        self.As_full = (self.alpha * m.Ms + self.mu * m.Ls).tocsr()
+        # A_s = alpha M_s + mu L_s on the shared structural pattern (a sparse sum
+        # would drop entries that cancel exactly, e.g. on right triangles)
+        if not (np.array_equal(m.Ms.indptr, m.Ls.indptr) and np.array_equal(m.Ms.indices, m.Ls.indices)):
+            raise AssertionError("M_s and L_s must share one pattern")
+        self.As_full = m.Ms.copy()
+        self.As_full.data = self.alpha * m.Ms.data + self.mu * m.Ls.data
         self.A_II = self.As_full[self.I][:, self.I].tocsr()
         self.A_Iall = self.As_full[self.I].tocsr()
         self.B_I = [b[:, self.I].tocsr() for b in m.B]
