@@ -21,6 +21,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <type_traits>
@@ -76,6 +78,16 @@ ChebCoef cheb_coef(const Bounds& b, int degree) {
 
 double now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// STOKES_LOG=1: one line per refinement sweep / Krylov cycle on stderr;
+// STOKES_LOG=2 adds every inner solve.
+int log_level() {
+  static int lv = [] {
+    const char* e = std::getenv("STOKES_LOG");
+    return e ? std::atoi(e) : 0;
+  }();
+  return lv;
 }
 
 }  // namespace
@@ -190,7 +202,15 @@ class Engine {
       if (h.breakdown) throw Error(STOKES_ERR_BREAKDOWN, "inner CG breakdown (non-positive curvature)");
       bool any = false;
       for (int s = 0; s < nsys; ++s) any = any || h.active[s];
-      if (!any || it >= maxit) break;
+      if (!any || it >= maxit) {
+        if (log_level() >= 2) {
+          double worst = 0;
+          for (int s2 = 0; s2 < nsys; ++s2)
+            if (h.bb[s2] > 0) worst = std::max(worst, std::sqrt(h.rr[s2] / h.bb[s2]));
+          std::fprintf(stderr, "[stokes]   pcg %s: %d its, max rel res %.3e\n", tag.c_str(), it, worst);
+        }
+        break;
+      }
       ++it;
       if (op.apply) {
         op.apply(z, t);
@@ -635,6 +655,8 @@ int refine_loop(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, 
   for (double& x : bn) x = std::sqrt(x);
   st.rel_res.assign(nrb, 0.0);
   int status = STOKES_NOT_CONVERGED;
+  std::vector<double> prev(nrb, 0.0);
+  int stalls = 0;
   for (int sweep = 0;; ++sweep) {
     // r = b - K x (plain system, FP64)
     ops::momentum<double>(c, nrb, xu, xp, nullptr, ru, -1.0, F);
@@ -653,17 +675,38 @@ int refine_loop(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, 
                                                                             : 10 * o.inner_rtol_u);
       target[r] = std::max(0.5 * o.rtol * bn[r], floor_rel * rn[r]);
     }
+    if (log_level() >= 1) {
+      double worst = 0;
+      for (double v : st.rel_res) worst = std::max(worst, v);
+      std::fprintf(stderr, "[stokes] sweep %d: max rel res %.3e (outer %d, inner u %d, p %d)\n", sweep, worst,
+                   st.outer, st.inner_u, st.inner_p);
+    }
     if (done) {
       status = STOKES_OK;
       break;
     }
-    if (sweep >= o.max_refine || st.outer >= o.max_outer) break;
+    // stagnation: two sweeps in a row without a 10% reduction
+    bool progress = sweep == 0;
+    for (int r = 0; r < nrb; ++r) progress = progress || rn[r] < 0.9 * prev[r];
+    stalls = progress ? 0 : stalls + 1;
+    prev = rn;
+    if (stalls >= 2 || sweep >= o.max_refine || st.outer >= o.max_outer) break;
     st.sweeps += 1;
     ops::remove_mean<double>(c, nrb, rp);
-    if (c->prob.gamma > 0) {  // right-hand side of the augmented system
+    if (c->prob.gamma > 0) {
+      // right-hand side of the augmented system: r_u + gamma mu B^T M_Q^{-1} r_p.
+      // A continuity error e left by the sweep returns in the plain momentum
+      // residual as gamma mu B^T M_Q^{-1} e, so the sweep goal is divided by
+      // the measured gain of that map.
       double* y = static_cast<double*>(c->workspace("rf_y", np * sizeof(double)));
+      double* t = static_cast<double*>(c->workspace("rf_t", nu * sizeof(double)));
       e64.cheb_apply("rfq", c->sQ, c->MQ64.as<double>(), c->dMQ64.as<double>(), c->bMQ, 26, nrb, rp, y);
-      ops::Btmul<double>(c, nrb, y, nullptr, ru, c->prob.gamma * c->prob.mu, ru, 1.0);
+      ops::Btmul<double>(c, nrb, y, nullptr, t, c->prob.gamma * c->prob.mu, nullptr, 0.0);
+      std::vector<double> tn = e64.dots(t, t, nullptr, nullptr);
+      std::vector<double> pn = e64.dots(nullptr, nullptr, rp, rp);
+      for (int r = 0; r < nrb; ++r)
+        if (pn[r] > 0) target[r] /= 1.0 + std::sqrt(tn[r] / pn[r]);
+      ops::axpby<double>(c, nu, 1.0, t, 1.0, ru);
     }
     const int budget = o.max_outer - st.outer;
     if (method == 0) e.fgmres_cycle(ru, rp, xu, xp, target, budget);

@@ -138,7 +138,10 @@ def _solve_and_compare(P, S, f, ubc, method, tol_err, **opts):
 
 
 @pytest.mark.parametrize("method", ["schur", "coupled"])
-@pytest.mark.parametrize("precision,rtol,tol", [(0, 1e-12, 1e-10), (1, 1e-10, 1e-8)])
+# The pressure is weakly determined by an l2 residual dominated by the momentum
+# rows (its error runs ~1e4 x the relative residual here), so the solves are
+# driven to rel-res 1e-14 (FP64) / 1e-12 (mixed) to meet the error bars.
+@pytest.mark.parametrize("precision,rtol,tol", [(0, 1e-14, 1e-10), (1, 1e-12, 1e-8)])
 def test_manufactured_2d_solve(gpu_lib, method, precision, rtol, tol):
     S, f, u, kw = _c1_case()
     P = _problem(**kw)
@@ -172,7 +175,7 @@ def test_augmented_lagrangian_same_solution(gpu_lib, gamma, method):
     f = inputs.fourier_forcing(S.mesh.p2coords, 1004)
     x = S.mesh.p2coords
     ubc = np.stack([np.sin(2 * x[:, 1]), np.cos(x[:, 0]), x[:, 0] * x[:, 1]])
-    _solve_and_compare(P, S, f, ubc, method, 1e-10, rtol=1e-12, max_outer=2000, max_refine=20)
+    _solve_and_compare(P, S, f, ubc, method, 1e-10, rtol=1e-14, max_outer=2000, max_refine=30)
 
 
 def test_batched_matches_single_and_mixed(gpu_lib):
@@ -230,7 +233,11 @@ def test_degenerate_single_interior_node(gpu_lib):
                          method="coupled", rtol=1e-12)
     assert info["status"] == 0
     assert _rel(u.cpu().numpy()[0], S.full_velocity(U, ubc)) <= 1e-10
-    assert _rel(p.cpu().numpy()[0], Pp) <= 1e-9
+    # B_I has rank 3 < n_p1 - 1 here: the pressure is unique only up to the
+    # kernel of B_I^T, so compare B_I^T p (fixed by the momentum equation)
+    pg = p.cpu().numpy()[0]
+    for c in range(3):
+        assert _rel(S.B_I[c].T @ pg, S.B_I[c].T @ Pp) <= 1e-9
 
 
 # ------------------------------------------------------------------- adjoint
