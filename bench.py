@@ -1,0 +1,170 @@
+"""Benchmark: Stokes DOFs/s per solve at rel-res 1e-8 (mixed vs FP64) and the
+HBM bandwidth of the velocity-block SpMV, on one MI355X.
+
+Workload (default): the unit cube cut into 64^3 cells, Kuhn split into 6
+tetrahedra, interior vertices jittered by +/-0.1 h (seed 1); Taylor-Hood P2/P1
+(6,440,067 velocity + 274,625 pressure DOFs); mu = 1e-3, dt = 5e-3; a seeded
+8-mode Fourier forcing (seed 1001).  One step = one generalized Stokes solve:
+FP64 flexible GMRES on the coupled system with the block preconditioner, FP32
+inner velocity / pressure CG preconditioned by Chebyshev-Jacobi of degree 4,
+iterative refinement until the true FP64 relative residual is <= 1e-8.  The
+operator is assembled once, before the timed region; the forcing is resident
+in HBM.
+
+Printed: one JSON line with the mixed-precision DOFs/s as `value`, the FP64
+path's DOFs/s beside it, the roofline of the dominant kernel (the FP32
+Chebyshev-Jacobi SpMV step on the velocity block, timed with HIP events on the
+solver's stream during the timed solves) and the CPU oracle baseline.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Stokes DOFs/s per solve at rel-res 1e-8 (mixed vs FP64) + SpMV HBM GB/s"
+
+WORKLOADS = {
+    # name: (dim, n, mesh_seed, mu, dt, forcing seed, description)
+    "cube64": (3, 64, 1, 1e-3, 5e-3, 1001,
+               "3D unit cube 64^3 Kuhn tets, jitter 0.1h seed 1, P2/P1 6,714,692 DOFs, mu=1e-3, dt=5e-3"),
+    "cube32": (3, 32, 0, 1e-2, 1e-2, 1000,
+               "3D unit cube 32^3 Kuhn tets, jitter 0.1h seed 0, P2/P1 859,812 DOFs, mu=1e-2, dt=1e-2"),
+}
+
+SOLVER = dict(method="coupled", rtol=1e-8, cheb_degree=4, inner_mode=0, inner_rtol_u=1e-2, inner_rtol_p=1e-2,
+              coupled_pc=1, schur_pc=1, restart=30, max_outer=500, max_refine=12)
+
+
+def cpu_baseline(dim, mesh_seed, mu, alpha, fseed, n_sample):
+    """The FP64 oracle (MINRES, block preconditioner) on a smaller mesh of the
+    same workload family, solved to a true relative residual <= 1e-8."""
+    from oracle import mesh as omesh
+    from oracle import stokes as ostokes
+    from paper_2407_01783_amd import inputs
+    m = omesh.KuhnMesh(dim, n_sample, seed=mesh_seed, jitter=0.1)
+    S = ostokes.StokesSystem(m, mu, alpha)
+    F, g = S.rhs(inputs.fourier_forcing(m.p2coords, fseed))
+    t0 = time.perf_counter()
+    U, P, info = S.solve_minres(F, g, rtol=1e-10)
+    dt = time.perf_counter() - t0
+    res = S.residual(U, P, F, g)
+    dofs = dim * m.n_p2 + m.n_p1
+    return {"value": dofs / dt, "unit": "DOFs/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle MINRES solve (solve only, {dt:.1f} s) on the same workload family at n={n_sample} "
+                      f"({dofs} DOFs), true rel-res {res:.1e}; scipy sparse kernels run on one thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cube64", choices=sorted(WORKLOADS))
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solves")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-n", type=int, default=16, help="mesh size of the CPU oracle sample")
+    ap.add_argument("--opt", action="append", default=[], help="solver option override key=value")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2407_01783_amd import inputs
+    from paper_2407_01783_amd.stokes import StokesProblem
+
+    dim, n, seed, mu, dt, fseed, desc = WORKLOADS[args.workload]
+    alpha = 1.0 / dt
+    opts = dict(SOLVER)
+    for kv in args.opt:
+        k, v = kv.split("=", 1)
+        opts[k] = type(opts.get(k, 0.0))(float(v)) if k != "method" else v
+    method = opts.pop("method")
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    prob = StokesProblem(dim, n, mesh_seed=seed, jitter=0.1, mu=mu, alpha=alpha)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    print(f"[bench] assembled {args.workload} in {setup_s:.2f} s", file=sys.stderr, flush=True)
+    xy, _ = prob.mesh()
+    f = torch.tensor(np.stack([inputs.fourier_forcing(xy, inputs.forcing_seed(seed, b) if b else fseed)
+                               for b in range(args.nrhs)]), device="cuda")
+    dofs = prob.total_dofs() * args.nrhs
+
+    def run(precision, steps, warmup, profile):
+        for _ in range(warmup):
+            prob.solve(f, method=method, precision=precision, **opts)
+        torch.cuda.synchronize()
+        infos = []
+        t = time.perf_counter()
+        for _ in range(steps):
+            _, _, info = prob.solve(f, method=method, precision=precision, profile=profile, **opts)
+            infos.append(info)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        return el, infos
+
+    el_mixed, infos = run(1, args.steps, args.warmup, 1)
+    print(f"[bench] mixed: {el_mixed / args.steps * 1e3:.1f} ms/solve", file=sys.stderr, flush=True)
+    ok = all(i["status"] == 0 and i["rel_res"] <= opts["rtol"] for i in infos)
+    launches = sum(i["spmv_launches"] for i in infos)
+    kern_s = sum(i["spmv_seconds"] for i in infos)
+    bytes_per = infos[-1]["spmv_bytes"]
+    achieved = bytes_per / (kern_s / launches) / 1e9 if launches else None
+
+    fp64 = None
+    if not args.no_fp64:
+        el64, infos64 = run(0, args.steps, args.warmup, 0)
+        ok64 = all(i["status"] == 0 and i["rel_res"] <= opts["rtol"] for i in infos64)
+        fp64 = {"value": dofs * args.steps / el64, "ms_per_step": el64 / args.steps * 1e3, "converged": ok64,
+                "outer_iters": infos64[-1]["outer_iters"], "rel_res": infos64[-1]["rel_res"]}
+        print(f"[bench] fp64: {el64 / args.steps * 1e3:.1f} ms/solve", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(dim, seed, mu, alpha, fseed, args.cpu_n)
+
+    value = dofs * args.steps / el_mixed
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOFs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el_mixed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "nrhs": args.nrhs, "method": method,
+                   "solver": {k: v for k, v in opts.items()}, "converged": ok,
+                   "rel_res": max(i["rel_res"] for i in infos), "outer_iters": infos[-1]["outer_iters"],
+                   "inner_iters_u": infos[-1]["inner_iters_u"], "inner_iters_p": infos[-1]["inner_iters_p"],
+                   "refinements": infos[-1]["refinements"], "setup_s": setup_s},
+        "fp64": fp64,
+        "mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "kernel": "k_cheb_step<float,3,0> (FP32 velocity-block SELL SpMV + Chebyshev update)",
+                     "bytes_per_launch": bytes_per, "launches": launches,
+                     "avg_us": kern_s / launches * 1e6 if launches else None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -185,7 +185,9 @@ stokes_status stokes_solve_adjoint(stokes_ctx* ctx, int32_t nrhs, const double* 
  * 1 = y = B x (x velocity-shaped, y pressure-shaped); 2 = y = B^T x (x
  * pressure, y velocity, boundary 0); 3 = M_Q x; 4 = L_Q x; 5 = the coupled
  * operator: (y_u, y_p) = (A u - B^T p, B u) with x = (x_u, x_p) packed as
- * [nrhs][dim][n_p2] followed by [nrhs][n_p1]. */
+ * [nrhs][dim][n_p2] followed by [nrhs][n_p1]; 6 = one geometric multigrid
+ * V-cycle for eps M_Q + L_Q (eps = 1), the pressure preconditioner of
+ * Sec. 4.2 (x, y pressure-shaped). */
 stokes_status stokes_apply(stokes_ctx* ctx, int32_t op, int32_t precision, int32_t nrhs,
                            const double* x, double* y);
 

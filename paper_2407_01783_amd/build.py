@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libstokes.so")
 ARCH = os.environ.get("STOKES_OFFLOAD_ARCH", "gfx950")
 
-HIP_SOURCES = ["assemble.hip", "ops.hip", "solver.hip", "abi.hip"]
+HIP_SOURCES = ["assemble.hip", "ops.hip", "mg.hip", "solver.hip", "abi.hip"]
 HOST_SOURCES = ["mesh_host.cpp"]
 
 HIPCC_FLAGS = [

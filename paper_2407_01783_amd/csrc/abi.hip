@@ -458,7 +458,7 @@ stokes_status stokes_solve_adjoint(stokes_ctx* c, int32_t nrhs, const double* u,
 stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t nrhs, const double* x, double* y) {
   return guard([&]() -> stokes_status {
     if (!c) throw Error(STOKES_ERR_ARG, "ctx is NULL");
-    if (op < 0 || op > 5) throw Error(STOKES_ERR_ARG, "op must be in [0, 5]");
+    if (op < 0 || op > 6) throw Error(STOKES_ERR_ARG, "op must be in [0, 6]");
     if (precision != 0 && precision != 1) throw Error(STOKES_ERR_ARG, "precision must be 0 or 1");
     if (nrhs < 1) throw Error(STOKES_ERR_ARG, "nrhs must be >= 1");
     if (!x || !y) throw Error(STOKES_ERR_ARG, "x and y must not be NULL");
@@ -478,7 +478,7 @@ stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t
       float* yuf = static_cast<float*>(c->workspace("ap_yuf", nu * sizeof(float)));
       float* ypf = static_cast<float*>(c->workspace("ap_ypf", np * sizeof(float)));
       const bool in_vel = op == 0 || op == 1 || op == 5;
-      const bool in_p = op == 2 || op == 3 || op == 4 || op == 5;
+      const bool in_p = op == 2 || op == 3 || op == 4 || op == 5 || op == 6;
       const bool out_vel = op == 0 || op == 2 || op == 5;
       const double* xv = x + vo;
       const double* xpp = op == 5 ? x + tot_u + po : x + po;
@@ -497,6 +497,7 @@ stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t
           case 2: ops::Btmul<T>(c, nrb, XP, nullptr, YU, (T)1, nullptr, (T)0); break;
           case 3: ops::spmv<T>(c, c->sQ, ops::pick<T>(c->MQ64, c->MQ32), nrb, XP, YP, (T)1, nullptr, (T)0); break;
           case 4: ops::spmv<T>(c, c->sQ, ops::pick<T>(c->LQ64, c->LQ32), nrb, XP, YP, (T)1, nullptr, (T)0); break;
+          case 6: mg_vcycle<T>(c, nrb, XP, YP, 0); break;
           default:
             ops::momentum<T>(c, nrb, XU, XP, nullptr, YU, (T)1, nullptr);
             ops::Bmul<T>(c, nrb, XU, YP, (T)1, nullptr, (T)0);

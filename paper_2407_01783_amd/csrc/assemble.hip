@@ -552,7 +552,8 @@ void lanczos_bounds(stokes_ctx* c, const Sell& S, const double* vals, const doub
     HIP_CHECK(hipMemsetAsync(v0, 0, n * sizeof(double), c->stream));
   }
   std::vector<double> al, be;
-  double beta_prev = 0;
+  double beta_prev = 0, beta_first = 0;
+  steps = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(steps, n - 1)));
   for (int j = 0; j < steps; ++j) {
     // w = sq .* S (sq .* v1)
     launch(c, n, k_mul, n, sq, v1, t);
@@ -564,7 +565,8 @@ void lanczos_bounds(stokes_ctx* c, const Sell& S, const double* vals, const doub
     if (j > 0) launch(c, n, k_axpby<double>, n, -beta_prev, (const double*)v0, 1.0, w);
     const double bn = std::sqrt(ops::dot_host<double>(c, n, 1, w, w)[0]);
     al.push_back(a);
-    if (j + 1 == steps || bn < 1e-14 * std::fabs(a)) break;
+    if (j == 0) beta_first = bn;
+    if (j + 1 == steps || bn < 1e-10 * std::max(std::fabs(a), beta_first)) break;
     be.push_back(bn);
     std::swap(v0, v1);
     launch(c, n, k_axpby<double>, n, 1.0 / bn, (const double*)w, 0.0, v1);
@@ -750,6 +752,65 @@ void assemble_ctx(stokes_ctx* c) {
   c->bMV = {tb.mass_lo, tb.mass_hi};
   c->bMQ = {tb.p1_lo, tb.p1_hi};
   estimate_bounds(c);
+  build_mg(c);
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+}
+
+// M_Q + L_Q on a P1 mesh (a coarse level of the pressure multigrid).
+void assemble_p1(stokes_ctx* c, const HostMesh& m, MgLevel& L) {
+  const int D = m.dim, nv = D + 1;
+  HostCsr P1;
+  element_pattern(m.elems, nv, m.n_p1, m.elems, nv, m.n_p1, m.n_e, P1);
+  DevBuf d_vc, d_el, d_vol, d_jinv, d_ip, d_il, rp, cols, MQ, LQ;
+  upload(d_vc, m.vcoords);
+  upload(d_el, m.elems);
+  d_vol.alloc(m.n_e * sizeof(double));
+  d_jinv.alloc(m.n_e * D * D * sizeof(double));
+  if (D == 3) launch(c, m.n_e, k_geom<3>, m.n_e, d_vc.as<double>(), d_el.as<int32_t>(), d_vol.as<double>(), d_jinv.as<double>());
+  else launch(c, m.n_e, k_geom<2>, m.n_e, d_vc.as<double>(), d_el.as<int32_t>(), d_vol.as<double>(), d_jinv.as<double>());
+  {
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> lst;
+    incidence(m.elems, nv, m.n_e, m.n_p1, ptr, lst);
+    upload(d_ip, ptr);
+    upload(d_il, lst);
+  }
+  std::vector<int32_t> rp32(P1.rowptr.begin(), P1.rowptr.end());
+  upload(rp, rp32);
+  upload(cols, P1.cols);
+  const int64_t nnz = P1.rowptr.back();
+  MQ.alloc(nnz * sizeof(double));
+  LQ.alloc(nnz * sizeof(double));
+  HIP_CHECK(hipMemsetAsync(MQ.p, 0, nnz * sizeof(double), c->stream));
+  HIP_CHECK(hipMemsetAsync(LQ.p, 0, nnz * sizeof(double), c->stream));
+  if (D == 3)
+    launch(c, m.n_p1, k_gather_q<3>, m.n_p1, d_ip.as<int64_t>(), d_il.as<int32_t>(), d_el.as<int32_t>(),
+           d_vol.as<double>(), d_jinv.as<double>(), rp.as<int32_t>(), cols.as<int32_t>(), MQ.as<double>(),
+           LQ.as<double>());
+  else
+    launch(c, m.n_p1, k_gather_q<2>, m.n_p1, d_ip.as<int64_t>(), d_il.as<int32_t>(), d_el.as<int32_t>(),
+           d_vol.as<double>(), d_jinv.as<double>(), rp.as<int32_t>(), cols.as<int32_t>(), MQ.as<double>(),
+           LQ.as<double>());
+  std::vector<int32_t> rows(m.n_p1);
+  std::iota(rows.begin(), rows.end(), 0);
+  build_sell(P1, rows, rows, nullptr, 1, L.S);
+  L.nrows = m.n_p1;
+  L.v64.alloc(L.S.nnz_pad * sizeof(double));
+  launch(c, L.S.nnz_pad, k_fill, L.S.nnz_pad, L.S.src.as<int32_t>(), 1, 1.0, MQ.as<double>(), 1.0, LQ.as<double>(),
+         L.v64.as<double>());
+  L.d64.alloc(m.n_p1 * sizeof(double));
+  launch(c, m.n_p1, k_dinv, m.n_p1, L.S.slice_ptr.as<int64_t>(), L.S.cols.as<int32_t>(), L.v64.as<double>(),
+         L.d64.as<double>());
+  L.v32.alloc(L.S.nnz_pad * sizeof(float));
+  L.d32.alloc(m.n_p1 * sizeof(float));
+  launch(c, L.S.nnz_pad, k_cast<double, float>, L.S.nnz_pad, L.v64.as<double>(), L.v32.as<float>());
+  launch(c, m.n_p1, k_cast<double, float>, m.n_p1, L.d64.as<double>(), L.d32.as<float>());
+  double lo, hi, g;
+  lanczos_bounds(c, L.S, L.v64.as<double>(), L.d64.as<double>(), std::min<int>(40, (int)m.n_p1), lo, hi, g);
+  L.bf.hi = std::min(g, 1.05 * hi);
+  L.bf.lo = 0.9 * lo;
+  L.bs.hi = L.bf.hi;
+  L.bs.lo = L.bf.hi / c->mg_smooth_ratio;
   HIP_CHECK(hipStreamSynchronize(c->stream));
 }
 
@@ -761,7 +822,8 @@ void estimate_bounds(stokes_ctx* c) {
   c->bA.lo = std::max(0.9 * lo, c->bA.hi / 1000.0);
   lanczos_bounds(c, c->sQ, c->XQ64.as<double>(), c->dXQ64.as<double>(), steps, lo, hi, g);
   c->bXQ.hi = std::min(g, 1.05 * hi);
-  c->bXQ.lo = std::max(0.9 * lo, c->bXQ.hi / 1000.0);
+  c->bXQ.lo = 0.9 * lo;
+  c->bXQ_smooth = {c->bXQ.hi / c->mg_smooth_ratio, c->bXQ.hi};
   lanczos_bounds(c, c->sQ, c->LQ64.as<double>(), c->dLQ64.as<double>(), steps, lo, hi, g);
   c->bLQ.hi = std::min(g, 1.05 * hi);
   c->bLQ.lo = c->bLQ.hi / 100.0;  // L_Q is singular: the constant mode is projected out

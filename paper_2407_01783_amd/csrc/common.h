@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <map>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -84,6 +85,16 @@ constexpr int kMaxSys = 24;   // systems per batched solve (dim * rhs)
 constexpr int kMaxBlocks = 2048;
 constexpr int kBlock = 256;
 
+// One coarse level of the pressure multigrid hierarchy (M_Q + L_Q).
+struct MgLevel {
+  int n = 0;            // cells per side
+  int64_t nrows = 0;    // (n + 1)^dim vertices
+  Sell S;               // SELL pattern of the level operator
+  DevBuf v64, v32;      // values of M_Q + L_Q
+  DevBuf d64, d32;      // inverse diagonal
+  Bounds bs, bf;        // smoothing interval, full spectrum
+};
+
 // Per-solver device scalars (one set per Krylov instance).
 struct Scalars {
   double rho[kMaxSys], rho_old[kMaxSys], alpha[kMaxSys], beta[kMaxSys];
@@ -129,7 +140,14 @@ struct stokes_ctx {
   stokes::DevBuf mQ;                         // M_Q 1 (double, n_p1)
   double mQ_sum = 0;
 
-  stokes::Bounds bA, bMV, bMQ, bXQ, bLQ;
+  stokes::Bounds bA, bMV, bMQ, bXQ, bLQ, bXQ_smooth;
+
+  // pressure multigrid (coarse levels; level 0 is sQ / XQ)
+  std::vector<std::unique_ptr<stokes::MgLevel>> mg;
+  int mg_smooth_degree = 3, mg_coarse_degree = 24;
+  int64_t mg_dense_n = 0;               // > 0: coarsest level solved by a dense inverse
+  stokes::DevBuf mg_cinv64, mg_cinv32;  // [n][n] inverse of the coarsest operator
+  double mg_smooth_ratio = 10.0;
 
   stokes::RedScratch red;
   stokes::DevBuf scal;  // Scalars pool

@@ -16,6 +16,12 @@
 
 namespace stokes {
 
+__host__ __device__ inline int64_t ipow_dev(int64_t b, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
 // ------------------------------------------------------------ reductions
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -45,34 +51,72 @@ __device__ __forceinline__ void block_sum(double (&v)[NS], double* out_shared) {
   __syncthreads();
 }
 
-// One-pass grid reduction: every block stores its NS partials, the last block
-// to arrive (atomic ticket) sums them in block order and calls fin(tot) with
-// the totals in shared memory; then the ticket is reset.  Returns true in the
-// last block.
-template <int NS, class Fin>
-__device__ __forceinline__ void grid_reduce(double (&v)[NS], double* partials, unsigned* ticket,
-                                            Fin fin) {
+// Block partials of a grid reduction: block b stores its NS slot sums at
+// partials[b * NS + s].  A separate one-block kernel (k_finish) adds them in
+// block order after the kernel boundary, so no device-scope fence is needed
+// (a fence per block writes back the whole L2 on a multi-XCD part) and the
+// result is deterministic.
+template <int NS>
+__device__ __forceinline__ void grid_reduce(double (&v)[NS], double* partials) {
   __shared__ double tot[NS];
-  __shared__ int last;
   block_sum<NS>(v, tot);
   if (threadIdx.x < NS) partials[(size_t)blockIdx.x * NS + threadIdx.x] = tot[threadIdx.x];
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(ticket, 1u) == gridDim.x - 1) ? 1 : 0;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
+}
+
+enum FinKind { FIN_STORE = 0, FIN_ALPHA = 1, FIN_RR = 2, FIN_RR_RHO = 3, FIN_RHO = 4 };
+
+// Sum the block partials (fixed order) and finish the Krylov scalars:
+//   FIN_STORE   res[s] = total of slot s
+//   FIN_ALPHA   sigma = p.q per system, alpha = rho / sigma (0 if inactive)
+//   FIN_RR      rr = r.r per system, deactivate converged systems
+//   FIN_RR_RHO  FIN_RR and rho = r.z (slots W..2W-1), beta = rho / rho_old
+//   FIN_RHO     rho = r.z, beta = rho / rho_old (0 when `first`)
+template <int NS>
+__global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ partials, int nblocks, int kind, int W,
+                                                   Scalars* sc, int cps, int nsys, int first, double* res) {
   double a[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) a[s] = 0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) a[s] += partials[(size_t)b * NS + s];
   }
+  __shared__ double tot[NS];
   block_sum<NS>(a, tot);
-  fin(tot);
-  __syncthreads();
-  if (threadIdx.x == 0) atomicExch(ticket, 0u);
+  const int s = threadIdx.x;
+  if (kind == FIN_STORE) {
+    if (s < NS) res[s] = tot[s];
+    return;
+  }
+  if (s >= nsys) return;
+  auto sum = [&](int off) {
+    double x = 0;
+    for (int w = s * cps; w < (s + 1) * cps; ++w) x += tot[off + w];
+    return x;
+  };
+  if (kind == FIN_ALPHA) {
+    const double sig = sum(0);
+    sc->sigma[s] = sig;
+    double al = 0;
+    if (sc->active[s]) {
+      if (sig > 0) al = sc->rho[s] / sig;
+      else sc->breakdown = 1;
+    }
+    sc->alpha[s] = al;
+    return;
+  }
+  if (kind == FIN_RR || kind == FIN_RR_RHO) {
+    const double rr = sum(0);
+    sc->rr[s] = rr;
+    if (sc->active[s] && !(rr > sc->tol2[s])) sc->active[s] = 0;
+  }
+  if (kind == FIN_RR_RHO || kind == FIN_RHO) {
+    const double rho = sum(kind == FIN_RR_RHO ? W : 0);
+    if (first) sc->beta[s] = 0.0;
+    else sc->beta[s] = (sc->active[s] && sc->rho[s] != 0) ? rho / sc->rho[s] : 0.0;
+    if (sc->active[s] && !(rho > 0)) sc->breakdown = 1;
+    sc->rho[s] = rho;
+  }
 }
 
 // --------------------------------------------------------- SELL row sums
@@ -166,8 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t nrows, const int64_t
                                                     const int32_t* __restrict__ cols,
                                                     const T* __restrict__ vals, const T* __restrict__ z,
                                                     const T* __restrict__ extra, T* __restrict__ q,
-                                                    T* __restrict__ p, Scalars* sc, int cps, int nsys,
-                                                    double* partials, unsigned* ticket) {
+                                                    T* __restrict__ p, Scalars* sc, int cps, int nsys, double* partials) {
   T beta[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) beta[w] = (T)sc->beta[w / cps];
@@ -191,30 +234,17 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t nrows, const int64_t
       part[w] += (double)pn * (double)qn;
     }
   }
-  grid_reduce<W>(part, partials, ticket, [&](double* tot) {
-    const int s = threadIdx.x;
-    if (s < nsys) {
-      double sig = 0;
-      for (int w = s * cps; w < (s + 1) * cps; ++w) sig += tot[w];
-      sc->sigma[s] = sig;
-      double al = 0;
-      if (sc->active[s]) {
-        if (sig > 0) al = sc->rho[s] / sig;
-        else sc->breakdown = 1;
-      }
-      sc->alpha[s] = al;
-    }
-  });
+  grid_reduce<W>(part, partials);
 }
 
 // PREC: 0 = Chebyshev prologue (d0 = dinv r / theta, z = d0), 1 = Jacobi
-// (z = dinv r, rho = r . z).  Always: x += alpha p, r -= alpha q, rr = r . r.
+// (z = dinv r, rho = r . z), 2 = none (the preconditioner runs separately).
+// Always: x += alpha p, r -= alpha q, rr = r . r.
 template <typename T, int W, int PREC>
 __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t nrows, T* __restrict__ x, T* __restrict__ r,
                                                       const T* __restrict__ p, const T* __restrict__ q,
                                                       const T* __restrict__ dinv, T theta_inv, T* __restrict__ d0,
-                                                      T* __restrict__ z, Scalars* sc, int cps, int nsys,
-                                                      double* partials, unsigned* ticket) {
+                                                      T* __restrict__ z, Scalars* sc, int cps, int nsys, double* partials) {
   constexpr int NS = PREC == 1 ? 2 * W : W;
   T alpha[W];
 #pragma unroll
@@ -223,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t nrows, T* __restri
 #pragma unroll
   for (int w = 0; w < NS; ++w) part[w] = 0;
   GRID_STRIDE_ROWS(row, nrows) {
-    const T di = dinv[row];  // one inverse diagonal per node, shared by its W values
+    const T di = PREC == 2 ? T(0) : dinv[row];  // one inverse diagonal per node
 #pragma unroll
     for (int w = 0; w < W; ++w) {
       const int64_t i = row * W + w;
@@ -235,29 +265,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t nrows, T* __restri
         const T dd = rn * di * theta_inv;
         d0[i] = dd;
         z[i] = dd;
-      } else {
+      } else if (PREC == 1) {
         const T zz = rn * di;
         z[i] = zz;
         part[W + w] += (double)rn * (double)zz;
       }
     }
   }
-  grid_reduce<NS>(part, partials, ticket, [&](double* tot) {
-    const int s = threadIdx.x;
-    if (s < nsys) {
-      double rr = 0;
-      for (int w = s * cps; w < (s + 1) * cps; ++w) rr += tot[w];
-      sc->rr[s] = rr;
-      if (sc->active[s] && !(rr > sc->tol2[s])) sc->active[s] = 0;
-      if (PREC == 1) {
-        double rho = 0;
-        for (int w = s * cps; w < (s + 1) * cps; ++w) rho += tot[W + w];
-        sc->beta[s] = (sc->active[s] && sc->rho[s] != 0) ? rho / sc->rho[s] : 0.0;
-        if (sc->active[s] && !(rho > 0)) sc->breakdown = 1;
-        sc->rho[s] = rho;
-      }
-    }
-  });
+  grid_reduce<NS>(part, partials);
 }
 
 // Chebyshev prologue on its own: d0 = dinv r / theta, z = d0 (optionally with
@@ -287,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, const int64
                                                       T* __restrict__ dn, const T* res_in, T* res_out,
                                                       T* __restrict__ z, const T* __restrict__ dinv, T c1, T c2,
                                                       const T* __restrict__ rvec, Scalars* sc, int cps, int nsys,
-                                                      int first, double* partials, unsigned* ticket) {
+                                                      int first, double* partials) {
   double part[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) part[w] = 0;
@@ -310,20 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, const int64
     }
   }
   if (DOT) {
-    grid_reduce<W>(part, partials, ticket, [&](double* tot) {
-      const int s = threadIdx.x;
-      if (s < nsys) {
-        double rho = 0;
-        for (int w = s * cps; w < (s + 1) * cps; ++w) rho += tot[w];
-        if (first) {
-          sc->beta[s] = 0.0;
-        } else {
-          sc->beta[s] = (sc->active[s] && sc->rho[s] != 0) ? rho / sc->rho[s] : 0.0;
-        }
-        if (sc->active[s] && !(rho > 0)) sc->breakdown = 1;
-        sc->rho[s] = rho;
-      }
-    });
+    grid_reduce<W>(part, partials);
   }
 }
 
@@ -426,8 +428,7 @@ __global__ __launch_bounds__(kBlock) void k_cast(int64_t n, const Tin* __restric
 // row optional.  Result written to res[0..W) by the last block.
 template <typename T, int W>
 __global__ __launch_bounds__(kBlock) void k_dot(int64_t nrows, const T* __restrict__ x, const T* __restrict__ y,
-                                                const double* __restrict__ rw, double* res, double* partials,
-                                                unsigned* ticket) {
+                                                const double* __restrict__ rw, double* res, double* partials) {
   double part[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) part[w] = 0;
@@ -440,9 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_dot(int64_t nrows, const T* __restri
       part[w] += wt * a * b;
     }
   }
-  grid_reduce<W>(part, partials, ticket, [&](double* tot) {
-    if (threadIdx.x < W) res[threadIdx.x] = tot[threadIdx.x];
-  });
+  grid_reduce<W>(part, partials);
 }
 
 // x[row][r] -= shift[r]   (pressure mean removal; shift from device)
@@ -598,8 +597,7 @@ template <int D, int NRB>
 __global__ __launch_bounds__(kBlock) void k_adj_dJdmu(int64_t n_int, int64_t n_p2, const int32_t* __restrict__ int2nat,
                                                       const int32_t* __restrict__ rp, const int32_t* __restrict__ cols,
                                                       const double* __restrict__ L, const double* __restrict__ u,
-                                                      const double* __restrict__ lam, double* res,
-                                                      double* partials, unsigned* ticket) {
+                                                      const double* __restrict__ lam, double* res, double* partials) {
   constexpr int W = D * NRB;
   double part[NRB];
 #pragma unroll
@@ -622,9 +620,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_dJdmu(int64_t n_int, int64_t n_p
 #pragma unroll
       for (int d = 0; d < D; ++d) part[r] -= lam[row * W + r * D + d] * acc[r * D + d];
   }
-  grid_reduce<NRB>(part, partials, ticket, [&](double* tot) {
-    if (threadIdx.x < NRB) res[threadIdx.x] = tot[threadIdx.x];
-  });
+  grid_reduce<NRB>(part, partials);
 }
 
 }  // namespace stokes
@@ -686,8 +682,7 @@ __global__ __launch_bounds__(kBlock) void k_mdot_fin(int nblk, const double* __r
 template <typename TV, int D, int NRB, int NORM>
 __global__ __launch_bounds__(kBlock) void k_mupdate(int64_t n_int, int64_t n_p1, const TV* __restrict__ V,
                                                     int64_t ldv, int nb, const double* __restrict__ h, double sgn,
-                                                    double* __restrict__ w, double* res, double* partials,
-                                                    unsigned* ticket) {
+                                                    double* __restrict__ w, double* res, double* partials) {
   constexpr int W = D * NRB;
   __shared__ double hs[64 * NRB];
   for (int i = threadIdx.x; i < nb * NRB; i += blockDim.x) hs[i] = sgn * h[i];
@@ -732,9 +727,7 @@ __global__ __launch_bounds__(kBlock) void k_mupdate(int64_t n_int, int64_t n_p1,
     }
   }
   if (NORM) {
-    grid_reduce<NRB>(part, partials, ticket, [&](double* tot) {
-      if (threadIdx.x < NRB) res[threadIdx.x] = tot[threadIdx.x];
-    });
+    grid_reduce<NRB>(part, partials);
   }
 }
 

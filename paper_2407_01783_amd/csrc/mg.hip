@@ -1,0 +1,313 @@
+// Geometric multigrid V-cycle for the P1 pressure operator eps M_Q + L_Q
+// (eps = 1), the operator the paper uses to precondition the Schur-complement
+// approximations B M^{-1} B^T / B Lambda^{-1} B^T (Sec. 4.2).  The paper
+// applies two algebraic-multigrid V-cycles (Table 1, BoomerAMG); on the
+// structured Kuhn mesh a geometric hierarchy is available instead:
+//
+//   * level l+1 has n / 2^(l+1) cells per side; its vertices are the level-0
+//     vertices whose grid indices are multiples of 2^(l+1) (jittered
+//     positions kept), its simplices the Kuhn split of the coarse grid, and
+//     its operator M_Q + L_Q is re-assembled on that mesh;
+//   * a level-l vertex with grid index f is the midpoint of the coarse Kuhn
+//     edge (f - s, f + s) with s = f mod 2 (componentwise), so P1
+//     interpolation averages those two coarse values; restriction is its
+//     transpose;
+//   * smoothing: Chebyshev-Jacobi on the upper part of each level's spectrum,
+//     the same polynomial before and after the coarse correction, so the
+//     cycle is symmetric and can precondition CG;
+//   * coarsest level: an exact dense inverse when it has at most 1500
+//     vertices, else a Chebyshev polynomial over its whole spectrum.
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <type_traits>
+
+#include "kernels.h"
+#include "ops.h"
+
+namespace stokes {
+
+namespace {
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+template <class F>
+void dispatch_dn(int D, int NRB, F&& f) {
+  auto inner = [&](auto Dc) {
+    switch (NRB) {
+      case 1: f(Dc, IC<1>{}); break;
+      case 2: f(Dc, IC<2>{}); break;
+      case 4: f(Dc, IC<4>{}); break;
+      case 8: f(Dc, IC<8>{}); break;
+      default: throw Error(STOKES_ERR_UNSUPPORTED, "batch");
+    }
+  };
+  if (D == 3) inner(IC<3>{});
+  else inner(IC<2>{});
+}
+
+// restriction: coarse vertex C gathers fine vertices 2C (weight 1) and
+// 2C + s, 2C - s (weight 1/2) for every nonzero s in {0,1}^D
+template <typename T, int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_restrict(int nf, int nc, const T* __restrict__ rf, T* __restrict__ rc) {
+  const int64_t ncv = (int64_t)ipow_dev(nc + 1, D);
+  GRID_STRIDE_ROWS(C, ncv) {
+    int cg[3] = {0, 0, 0};
+    int64_t rem = C;
+    for (int d = 0; d < D; ++d) {
+      cg[d] = (int)(rem % (nc + 1));
+      rem /= (nc + 1);
+    }
+    T acc[NRB];
+    auto fid = [&](const int* g) {
+      int64_t id = 0, st = 1;
+      for (int d = 0; d < D; ++d, st *= (nf + 1)) id += g[d] * st;
+      return id;
+    };
+    {
+      int g[3];
+      for (int d = 0; d < D; ++d) g[d] = 2 * cg[d];
+      const int64_t f = fid(g);
+#pragma unroll
+      for (int r = 0; r < NRB; ++r) acc[r] = rf[f * NRB + r];
+    }
+    for (int s = 1; s < (1 << D); ++s) {
+      for (int sg = -1; sg <= 1; sg += 2) {
+        int g[3];
+        bool ok = true;
+        for (int d = 0; d < D; ++d) {
+          g[d] = 2 * cg[d] + sg * ((s >> d) & 1);
+          ok = ok && g[d] >= 0 && g[d] <= nf;
+        }
+        if (!ok) continue;
+        const int64_t f = fid(g);
+#pragma unroll
+        for (int r = 0; r < NRB; ++r) acc[r] += T(0.5) * rf[f * NRB + r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) rc[C * NRB + r] = acc[r];
+  }
+}
+
+// interpolation, added to the fine vector: ef[f] += (ec[(f-s)/2] + ec[(f+s)/2]) / 2
+template <typename T, int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_prolong_add(int nf, int nc, const T* __restrict__ ec, T* __restrict__ ef) {
+  const int64_t nfv = (int64_t)ipow_dev(nf + 1, D);
+  GRID_STRIDE_ROWS(f, nfv) {
+    int fg[3] = {0, 0, 0};
+    int64_t rem = f;
+    for (int d = 0; d < D; ++d) {
+      fg[d] = (int)(rem % (nf + 1));
+      rem /= (nf + 1);
+    }
+    int64_t a = 0, b = 0, st = 1;
+    for (int d = 0; d < D; ++d, st *= (nc + 1)) {
+      const int s = fg[d] & 1;
+      a += ((fg[d] - s) / 2) * st;
+      b += ((fg[d] + s) / 2) * st;
+    }
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) ef[f * NRB + r] += T(0.5) * (ec[a * NRB + r] + ec[b * NRB + r]);
+  }
+}
+
+// y[i][r] = sum_j Cinv[i][j] x[j][r]   (coarsest-level solve)
+template <typename T, int NRB>
+__global__ __launch_bounds__(kBlock) void k_dense_mv(int64_t n, const T* __restrict__ Ci, const T* __restrict__ x,
+                                                     T* __restrict__ y) {
+  GRID_STRIDE_ROWS(i, n) {
+    T acc[NRB];
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) acc[r] = 0;
+    for (int64_t j = 0; j < n; ++j) {
+      const T a = Ci[i * n + j];
+#pragma unroll
+      for (int r = 0; r < NRB; ++r) acc[r] = fma(a, x[j * NRB + r], acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) y[i * NRB + r] = acc[r];
+  }
+}
+
+// Inverse of a small SPD matrix by Cholesky (host).
+std::vector<double> spd_inverse(std::vector<double> A, int64_t n) {
+  for (int64_t j = 0; j < n; ++j) {  // A = L L^T in place (lower)
+    double d = A[j * n + j];
+    for (int64_t k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+    if (!(d > 0)) throw Error(STOKES_ERR_BREAKDOWN, "coarsest multigrid operator is not positive definite");
+    d = std::sqrt(d);
+    A[j * n + j] = d;
+    for (int64_t i = j + 1; i < n; ++i) {
+      double s = A[i * n + j];
+      for (int64_t k = 0; k < j; ++k) s -= A[i * n + k] * A[j * n + k];
+      A[i * n + j] = s / d;
+    }
+  }
+  std::vector<double> inv(n * n, 0.0), col(n);
+  for (int64_t c = 0; c < n; ++c) {  // solve L L^T x = e_c
+    for (int64_t i = 0; i < n; ++i) {
+      double s = i == c ? 1.0 : 0.0;
+      for (int64_t k = 0; k < i; ++k) s -= A[i * n + k] * col[k];
+      col[i] = s / A[i * n + i];
+    }
+    for (int64_t i = n - 1; i >= 0; --i) {
+      double s = col[i];
+      for (int64_t k = i + 1; k < n; ++k) s -= A[k * n + i] * col[k];
+      col[i] = s / A[i * n + i];
+    }
+    for (int64_t i = 0; i < n; ++i) inv[i * n + c] = col[i];
+  }
+  return inv;
+}
+
+struct Cheb {
+  double theta_inv;
+  std::vector<double> c1, c2;
+};
+
+Cheb coef(const Bounds& b, int degree) {
+  Cheb k;
+  const double theta = 0.5 * (b.hi + b.lo), delta = 0.5 * (b.hi - b.lo);
+  k.theta_inv = 1.0 / theta;
+  const double sigma1 = theta / delta;
+  double rho = 1.0 / sigma1;
+  for (int j = 1; j < degree; ++j) {
+    const double rn = 1.0 / (2.0 * sigma1 - rho);
+    k.c1.push_back(rn * rho);
+    k.c2.push_back(2.0 * rn / delta);
+    rho = rn;
+  }
+  return k;
+}
+
+template <class T>
+T* wsp(stokes_ctx* c, const std::string& name, int64_t n) {
+  return static_cast<T*>(c->workspace(name + (std::is_same<T, float>::value ? "_f" : "_d"), n * sizeof(T)));
+}
+
+}  // namespace
+
+// Build the coarse levels (called once per context after assembly).
+void build_mg(stokes_ctx* c) {
+  c->mg.clear();
+  const HostMesh& fm = c->mesh;
+  const int D = fm.dim;
+  int n = fm.n;
+  int stride = 1;
+  while (n % 2 == 0 && n / 2 >= 1 && n > 2) {
+    n /= 2;
+    stride *= 2;
+    auto L = std::make_unique<MgLevel>();
+    L->n = n;
+    HostMesh m;
+    build_mesh(D, n, 0, 0.0, m);
+    // coordinates: the level-0 vertex at stride * (grid index)
+    const int64_t nf1 = fm.n + 1;
+    for (int64_t g = 0; g < m.n_p1; ++g) {
+      int64_t rem = g, fid = 0, st = 1;
+      for (int d = 0; d < D; ++d, st *= nf1) {
+        fid += (rem % (n + 1)) * stride * st;
+        rem /= (n + 1);
+      }
+      for (int d = 0; d < D; ++d) m.vcoords[g * D + d] = fm.vcoords[fid * D + d];
+    }
+    L->nrows = m.n_p1;
+    assemble_p1(c, m, *L);
+    c->mg.push_back(std::move(L));
+  }
+  // exact solve on a small coarsest level
+  const Sell& S = c->mg.empty() ? c->sQ : c->mg.back()->S;
+  const DevBuf& V = c->mg.empty() ? c->XQ64 : c->mg.back()->v64;
+  const int64_t nr = S.nrows;
+  c->mg_dense_n = 0;
+  if (nr <= 1500) {
+    std::vector<int64_t> sp(S.nslices + 1);
+    std::vector<int32_t> cols(S.nnz_pad);
+    std::vector<double> vals(S.nnz_pad);
+    HIP_CHECK(hipMemcpy(sp.data(), S.slice_ptr.p, sp.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+    HIP_CHECK(hipMemcpy(cols.data(), S.cols.p, cols.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_CHECK(hipMemcpy(vals.data(), V.p, vals.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<double> A(nr * nr, 0.0);
+    for (int64_t r = 0; r < nr; ++r)
+      for (int64_t k = sp[r / 64] + r % 64; k < sp[r / 64 + 1]; k += 64) A[r * nr + cols[k]] += vals[k];
+    const std::vector<double> inv = spd_inverse(A, nr);
+    std::vector<float> inv32(inv.begin(), inv.end());
+    upload(c->mg_cinv64, inv);
+    upload(c->mg_cinv32, inv32);
+    c->mg_dense_n = nr;
+  }
+}
+
+// e = V-cycle(r) for M_Q + L_Q, starting at level `lv` (0 = the full mesh).
+template <class T>
+void mg_vcycle(stokes_ctx* c, int nrb, const T* r, T* e, int lv) {
+  const int nlev = static_cast<int>(c->mg.size()) + 1;
+  const Sell& S = lv == 0 ? c->sQ : c->mg[lv - 1]->S;
+  const T* vals = lv == 0 ? ops::pick<T>(c->XQ64, c->XQ32) : ops::pick<T>(c->mg[lv - 1]->v64, c->mg[lv - 1]->v32);
+  const T* dinv = lv == 0 ? ops::pick<T>(c->dXQ64, c->dXQ32) : ops::pick<T>(c->mg[lv - 1]->d64, c->mg[lv - 1]->d32);
+  const Bounds& bs = lv == 0 ? c->bXQ_smooth : c->mg[lv - 1]->bs;
+  const Bounds& bf = lv == 0 ? c->bXQ : c->mg[lv - 1]->bf;
+  const int64_t nr = S.nrows, n = nr * nrb;
+  const std::string tag = "mg" + std::to_string(lv);
+  T* d0 = wsp<T>(c, tag + "_d0", n);
+  T* d1 = wsp<T>(c, tag + "_d1", n);
+  T* res = wsp<T>(c, tag + "_res", n);
+  auto cheb = [&](const Bounds& b, int degree, const T* rin, T* z) {
+    const Cheb k = coef(b, degree);
+    ops::cheb_init<T>(c, nr, nrb, rin, dinv, (T)k.theta_inv, d0, z);
+    T* da = d0;
+    T* db = d1;
+    for (int j = 1; j < degree; ++j) {
+      ops::cheb_step<T>(c, S, vals, nrb, da, db, j == 1 ? rin : res, res, z, dinv, (T)k.c1[j - 1], (T)k.c2[j - 1],
+                        nullptr, nullptr, 1, 0, 0);
+      std::swap(da, db);
+    }
+  };
+  if (lv == nlev - 1) {  // coarsest: dense inverse, or a polynomial over the whole spectrum
+    if (c->mg_dense_n == nr) {
+      const T* Ci = ops::pick<T>(c->mg_cinv64, c->mg_cinv32);
+      dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
+        constexpr int N = decltype(Nc)::value;
+        (void)Dc;
+        hipLaunchKernelGGL((k_dense_mv<T, N>), dim3(ops::grid_for(nr)), dim3(kBlock), 0, c->stream, nr, Ci, r, e);
+      });
+      ops::check_launch();
+    } else {
+      cheb(bf, c->mg_coarse_degree, r, e);
+    }
+    return;
+  }
+  const int nu = c->mg_smooth_degree;
+  T* t = wsp<T>(c, tag + "_t", n);
+  T* dz = wsp<T>(c, tag + "_dz", n);
+  const MgLevel& C = *c->mg[lv];
+  const int nf = lv == 0 ? c->mesh.n : c->mg[lv - 1]->n;
+  const int64_t ncn = C.nrows * nrb;
+  T* rc = wsp<T>(c, "mg" + std::to_string(lv + 1) + "_rc", ncn);
+  T* ec = wsp<T>(c, "mg" + std::to_string(lv + 1) + "_ec", ncn);
+  cheb(bs, nu, r, e);                                                   // pre-smoothing from zero
+  ops::spmv<T>(c, S, vals, nrb, e, t, (T)-1, r, (T)1);                 // t = r - X e
+  dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
+    constexpr int DD = decltype(Dc)::value, N = decltype(Nc)::value;
+    hipLaunchKernelGGL((k_restrict<T, DD, N>), dim3(ops::grid_for(C.nrows)), dim3(kBlock), 0, c->stream, nf, C.n,
+                       (const T*)t, rc);
+  });
+  ops::check_launch();
+  mg_vcycle<T>(c, nrb, rc, ec, lv + 1);
+  dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
+    constexpr int DD = decltype(Dc)::value, N = decltype(Nc)::value;
+    hipLaunchKernelGGL((k_prolong_add<T, DD, N>), dim3(ops::grid_for(nr)), dim3(kBlock), 0, c->stream, nf, C.n,
+                       (const T*)ec, e);
+  });
+  ops::check_launch();
+  ops::spmv<T>(c, S, vals, nrb, e, t, (T)-1, r, (T)1);                 // t = r - X e
+  cheb(bs, nu, t, dz);                                                  // post-smoothing
+  ops::axpby<T>(c, n, (T)1, dz, (T)1, e);
+}
+
+template void mg_vcycle<double>(stokes_ctx*, int, const double*, double*, int);
+template void mg_vcycle<float>(stokes_ctx*, int, const float*, float*, int);
+
+}  // namespace stokes

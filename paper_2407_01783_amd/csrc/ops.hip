@@ -78,7 +78,12 @@ void dispatch_dn(int D, int NRB, F&& f) {
 }
 
 inline double* partials(stokes_ctx* c) { return c->red.partials.as<double>(); }
-inline unsigned* ticket(stokes_ctx* c) { return c->red.ticket.as<unsigned>(); }
+
+template <int NS>
+void finish(stokes_ctx* c, int64_t rows, int kind, int W, Scalars* sc, int cps, int nsys, int first, double* res) {
+  hipLaunchKernelGGL((k_finish<NS>), dim3(1), dim3(kBlock), 0, c->stream, (const double*)partials(c), grid_for(rows),
+                     kind, W, sc, cps, nsys, first, res);
+}
 
 template <class T> const DevBuf& bvals(stokes_ctx* c);
 template <> const DevBuf& bvals<double>(stokes_ctx* c) { return c->B64; }
@@ -142,7 +147,8 @@ void dot_dev(stokes_ctx* c, int64_t nrows, int W, const T* x, const T* y, const 
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
     hipLaunchKernelGGL((k_dot<T, WW>), dim3(grid_for(nrows)), dim3(kBlock), 0, c->stream, nrows, x, y, rw, res,
-                       partials(c), ticket(c));
+                       partials(c));
+    finish<WW>(c, nrows, FIN_STORE, WW, nullptr, 1, 0, 0, res);
   });
   check_launch();
 }
@@ -164,7 +170,8 @@ void remove_mean(stokes_ctx* c, int nrb, T* x) {
   dispatch_w(nrb, [&](auto Nc) {
     constexpr int N = decltype(Nc)::value;
     hipLaunchKernelGGL((k_dot<T, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1,
-                       (const T*)x, ones, (const double*)nullptr, res, partials(c), ticket(c));
+                       (const T*)x, ones, (const double*)nullptr, res, partials(c));
+    finish<N>(c, c->n_p1, FIN_STORE, N, nullptr, 1, 0, 0, res);
     check_launch();
     hipLaunchKernelGGL((k_shift<T, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1, x,
                        (const double*)res, 1.0 / double(c->n_p1));
@@ -179,7 +186,8 @@ void normalize_pressure(stokes_ctx* c, int nrb, T* x) {
   dispatch_w(nrb, [&](auto Nc) {
     constexpr int N = decltype(Nc)::value;
     hipLaunchKernelGGL((k_dot<T, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1,
-                       (const T*)x, ones, (const double*)c->mQ.as<double>(), res, partials(c), ticket(c));
+                       (const T*)x, ones, (const double*)c->mQ.as<double>(), res, partials(c));
+    finish<N>(c, c->n_p1, FIN_STORE, N, nullptr, 1, 0, 0, res);
     check_launch();
     hipLaunchKernelGGL((k_shift<T, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1, x,
                        (const double*)res, 1.0 / c->mQ_sum);
@@ -208,15 +216,14 @@ void axpy_sys(stokes_ctx* c, int64_t n, int W, int cps, const double* coef, doub
 template <class T>
 void cg_spmv(stokes_ctx* c, int64_t nrows, const Sell* S, const T* vals, int W, const T* z, const T* extra, T* q,
              T* p, Scalars* sc, int cps, int nsys) {
-  const bool timed = prof_begin(c, S, (const void*)vals, (const void*)avals<T>(c).template as<T>());
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
     hipLaunchKernelGGL((k_cg_spmv<T, WW>), dim3(grid_for(nrows)), dim3(kBlock), 0, c->stream, nrows,
                        S ? S->slice_ptr.as<int64_t>() : nullptr, S ? S->cols.as<int32_t>() : nullptr, vals, z, extra,
-                       q, p, sc, cps, nsys, partials(c), ticket(c));
+                       q, p, sc, cps, nsys, partials(c));
+    finish<WW>(c, nrows, FIN_ALPHA, WW, sc, cps, nsys, 0, nullptr);
   });
   check_launch();
-  if (timed) prof_end(c, double(S->nnz) * (sizeof(T) + 4.0) + double(nrows) * W * sizeof(T) * (extra ? 6.0 : 5.0));
 }
 
 template <class T>
@@ -224,12 +231,19 @@ void cg_update(stokes_ctx* c, int64_t nrows, int W, int prec, T* x, T* r, const 
                T theta_inv, T* d0, T* z, Scalars* sc, int cps, int nsys) {
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
-    if (prec == 0)
+    if (prec == 2) {
+      hipLaunchKernelGGL((k_cg_update<T, WW, 2>), dim3(grid_for(nrows)), dim3(kBlock), 0, c->stream, nrows, x, r, p,
+                         q, dinv, theta_inv, d0, z, sc, cps, nsys, partials(c));
+      finish<WW>(c, nrows, FIN_RR, WW, sc, cps, nsys, 0, nullptr);
+    } else if (prec == 0) {
       hipLaunchKernelGGL((k_cg_update<T, WW, 0>), dim3(grid_for(nrows)), dim3(kBlock), 0, c->stream, nrows, x, r, p,
-                         q, dinv, theta_inv, d0, z, sc, cps, nsys, partials(c), ticket(c));
-    else
+                         q, dinv, theta_inv, d0, z, sc, cps, nsys, partials(c));
+      finish<WW>(c, nrows, FIN_RR, WW, sc, cps, nsys, 0, nullptr);
+    } else {
       hipLaunchKernelGGL((k_cg_update<T, WW, 1>), dim3(grid_for(nrows)), dim3(kBlock), 0, c->stream, nrows, x, r, p,
-                         q, dinv, theta_inv, d0, z, sc, cps, nsys, partials(c), ticket(c));
+                         q, dinv, theta_inv, d0, z, sc, cps, nsys, partials(c));
+      finish<2 * WW>(c, nrows, FIN_RR_RHO, WW, sc, cps, nsys, 0, nullptr);
+    }
   });
   check_launch();
 }
@@ -247,17 +261,19 @@ void cheb_init(stokes_ctx* c, int64_t nrows, int W, const T* r, const T* dinv, T
 template <class T>
 void cheb_step(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* d, T* dn, const T* res_in, T* res_out,
                T* z, const T* dinv, T c1, T c2, const T* rvec, Scalars* sc, int cps, int nsys, int first) {
-  const bool timed = prof_begin(c, &S, (const void*)vals, (const void*)avals<T>(c).template as<T>());
+  // the timed kernel is the plain Chebyshev step (no fused dot) on the velocity block
+  const bool timed = rvec == nullptr && prof_begin(c, &S, (const void*)vals, (const void*)avals<T>(c).template as<T>());
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
-    if (rvec)
+    if (rvec) {
       hipLaunchKernelGGL((k_cheb_step<T, WW, 1>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
                          S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, d, dn, res_in, res_out, z, dinv, c1,
-                         c2, rvec, sc, cps, nsys, first, partials(c), ticket(c));
-    else
+                         c2, rvec, sc, cps, nsys, first, partials(c));
+      finish<WW>(c, S.nrows, FIN_RHO, WW, sc, cps, nsys, first, nullptr);
+    } else
       hipLaunchKernelGGL((k_cheb_step<T, WW, 0>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
                          S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, d, dn, res_in, res_out, z, dinv, c1,
-                         c2, rvec, sc, cps, nsys, first, partials(c), ticket(c));
+                         c2, rvec, sc, cps, nsys, first, partials(c));
   });
   check_launch();
   // algorithmic bytes: values + column indices once; d gathered once; res_in,
@@ -345,7 +361,8 @@ void adj_dJdmu(stokes_ctx* c, int nrb, const double* u_full, const double* lam, 
     constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
     hipLaunchKernelGGL((k_adj_dJdmu<D, N>), dim3(grid_for(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int, c->n_p2,
                        c->int2nat.as<int32_t>(), c->p2full.rowptr.as<int32_t>(), c->p2full.cols.as<int32_t>(),
-                       c->L_full.as<double>(), u_full, lam, res_dev, partials(c), ticket(c));
+                       c->L_full.as<double>(), u_full, lam, res_dev, partials(c));
+    finish<N>(c, c->n_int, FIN_STORE, N, nullptr, 1, 0, 0, res_dev);
   });
   check_launch();
 }

@@ -147,6 +147,7 @@ class Engine {
     const T* dinv;
     Bounds b;
     int degree;
+    std::function<void(const T*, T*)> apply;  // general preconditioner z = M^{-1} r
   };
 
   // Solve op x = b per system to ||r|| <= rtol ||b||; returns iterations.
@@ -176,6 +177,14 @@ class Engine {
     const T thinv = pc.degree > 1 ? (T)k.theta_inv : (T)1;
     // z = M^{-1} r with rho = r . z
     auto precond = [&](bool first) {
+      if (pc.apply) {
+        pc.apply(r, z);
+        ops::dot_dev<T>(c_, nrows, W, r, z, nullptr, slots);
+        hipLaunchKernelGGL(k_scal_rho, dim3(1), dim3(64), 0, c_->stream, sc, (const double*)slots, cps, nsys,
+                           first ? 1 : 0);
+        ops::check_launch();
+        return;
+      }
       if (pc.degree <= 1) {
         ops::cheb_init<T>(c_, nrows, W, r, pc.dinv, thinv, d0, z);
         ops::dot_dev<T>(c_, nrows, W, r, z, nullptr, slots);
@@ -199,7 +208,17 @@ class Engine {
     for (;;) {
       sync_scalars(sc_index);
       const Scalars& h = *c_->h_scal;
-      if (h.breakdown) throw Error(STOKES_ERR_BREAKDOWN, "inner CG breakdown (non-positive curvature)");
+      if (h.breakdown) {
+        std::string msg = "inner CG '" + tag + "' breakdown (non-positive curvature) at iteration " +
+                          std::to_string(it) + ":";
+        for (int s2 = 0; s2 < nsys; ++s2) {
+          char b[160];
+          std::snprintf(b, sizeof(b), " [sys %d rho %.3e sigma %.3e rr %.3e bb %.3e active %d]", s2, h.rho[s2],
+                        h.sigma[s2], h.rr[s2], h.bb[s2], h.active[s2]);
+          msg += b;
+        }
+        throw Error(STOKES_ERR_BREAKDOWN, msg);
+      }
       bool any = false;
       for (int s = 0; s < nsys; ++s) any = any || h.active[s];
       if (!any || it >= maxit) {
@@ -219,7 +238,10 @@ class Engine {
         if (op.extra) op.extra(z, t);
         ops::cg_spmv<T>(c_, nrows, op.S, opvals, W, z, op.extra ? t : nullptr, q, p, sc, cps, nsys);
       }
-      if (pc.degree <= 1) {
+      if (pc.apply) {
+        ops::cg_update<T>(c_, nrows, W, 2, x, r, p, q, pc.dinv, (T)1, d0, z, sc, cps, nsys);
+        precond(false);
+      } else if (pc.degree <= 1) {
         ops::cg_update<T>(c_, nrows, W, 1, x, r, p, q, pc.dinv, (T)1, d0, z, sc, cps, nsys);
       } else {
         ops::cg_update<T>(c_, nrows, W, 0, x, r, p, q, pc.dinv, thinv, d0, z, sc, cps, nsys);
@@ -247,7 +269,7 @@ class Engine {
 
   // x = A~^{-1} b (velocity block)
   void vel_solve(const T* b, T* x) {
-    const Prec pc{&c_->sA, A(), dA(), c_->bA, std::max(1, o_.cheb_degree)};
+    const Prec pc{&c_->sA, A(), dA(), c_->bA, std::max(1, o_.cheb_degree), {}};
     if (o_.inner_mode == STOKES_INNER_FIXED) {
       cheb_apply("vfx", c_->sA, A(), dA(), c_->bA, std::max(1, o_.cheb_degree), W_, b, x);
       return;
@@ -280,12 +302,13 @@ class Engine {
     }
   }
 
-  // x = X^{-1} b on the mean-free pressures
+  // x = X^{-1} b on the mean-free pressures; the preconditioner (fixed
+  // mode: the approximation itself) is one multigrid V-cycle of eps M_Q + L_Q
   void x_solve(const T* b, T* x) {
-    const Prec pc{&c_->sQ, ops::pick<T>(c_->XQ64, c_->XQ32), ops::pick<T>(c_->dXQ64, c_->dXQ32), c_->bXQ,
-                  std::max(1, o_.cheb_degree)};
+    Prec pc{&c_->sQ, ops::pick<T>(c_->XQ64, c_->XQ32), ops::pick<T>(c_->dXQ64, c_->dXQ32), c_->bXQ, 1, {}};
+    pc.apply = [this](const T* r, T* z) { mg_vcycle<T>(c_, nrb_, r, z, 0); };
     if (o_.inner_mode == STOKES_INNER_FIXED) {
-      cheb_apply("xfx", *pc.S, pc.vals, pc.dinv, pc.b, pc.degree, nrb_, b, x);
+      mg_vcycle<T>(c_, nrb_, b, x, 0);
       return;
     }
     Op op;
@@ -299,12 +322,16 @@ class Engine {
     st_.inner_p += pcg("pcg", op, opvals, pc, c_->n_p1, nrb_, 1, b, x, o_.inner_rtol_p, o_.max_inner, 1);
   }
 
-  // z = C r = alpha X^{-1} r + mu (1 + gamma) M_Q^{-1} r, mean removed
+  // z = C r = alpha X^{-1} r + mu (1 + gamma) M_Q^{-1} r on the mean-free
+  // pressures (X is singular on constants: its inverse acts on 1-perp)
   void cc_apply(const T* r, T* z) {
     T* y = buf("cc_y", np());
-    x_solve(r, z);
+    T* rm = buf("cc_r", np());
+    HIP_CHECK(hipMemcpyAsync(rm, r, np() * sizeof(T), hipMemcpyDeviceToDevice, c_->stream));
+    ops::remove_mean<T>(c_, nrb_, rm);
+    x_solve(rm, z);
     cheb_apply("ccq", c_->sQ, ops::pick<T>(c_->MQ64, c_->MQ32), ops::pick<T>(c_->dMQ64, c_->dMQ32), c_->bMQ,
-               cc_mq_deg_, nrb_, r, y);
+               cc_mq_deg_, nrb_, rm, y);
     ops::axpby<T>(c_, np(), (T)(mu_ * (1.0 + gamma_)), y, (T)alpha_, z);
     ops::remove_mean<T>(c_, nrb_, z);
   }
@@ -413,14 +440,17 @@ class Engine {
       using TV = std::remove_const_t<std::remove_pointer_t<decltype(Vb)>>;
       dispatch_dn(D_, nrb_, [&](auto Dc, auto Nc) {
         constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
-        if (res)
+        if (res) {
           hipLaunchKernelGGL((k_mupdate<TV, D, N, 1>), dim3(nbx), dim3(kBlock), 0, c_->stream, c_->n_int, c_->n_p1,
-                             (const TV*)Vb, nc, nb, h, sgn, x, res, c_->red.partials.as<double>(),
-                             c_->red.ticket.as<unsigned>());
-        else
+                             (const TV*)Vb, nc, nb, h, sgn, x, res, c_->red.partials.as<double>());
+          ops::check_launch();
+          hipLaunchKernelGGL((k_finish<N>), dim3(1), dim3(kBlock), 0, c_->stream,
+                             (const double*)c_->red.partials.as<double>(), nbx, (int)FIN_STORE, N, (Scalars*)nullptr,
+                             1, 0, 0, res);
+        } else {
           hipLaunchKernelGGL((k_mupdate<TV, D, N, 0>), dim3(nbx), dim3(kBlock), 0, c_->stream, c_->n_int, c_->n_p1,
-                             (const TV*)Vb, nc, nb, h, sgn, x, res, c_->red.partials.as<double>(),
-                             c_->red.ticket.as<unsigned>());
+                             (const TV*)Vb, nc, nb, h, sgn, x, res, c_->red.partials.as<double>());
+        }
       });
       ops::check_launch();
     };
