@@ -38,7 +38,7 @@ WORKLOADS = {
                "3D unit cube 32^3 Kuhn tets, jitter 0.1h seed 0, P2/P1 859,812 DOFs, mu=1e-2, dt=1e-2"),
 }
 
-SOLVER = dict(method="coupled", rtol=1e-8, cheb_degree=4, inner_mode=0, inner_rtol_u=1e-2, inner_rtol_p=1e-2,
+SOLVER = dict(method="coupled", rtol=1e-8, cheb_degree=4, inner_mode=0, inner_rtol_u=1e-2, inner_rtol_p=1e-1,
               coupled_pc=1, schur_pc=1, restart=30, max_outer=500, max_refine=12)
 
 

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 
@@ -116,6 +117,19 @@ int chunk_size(int remaining) {
   return 1;
 }
 
+// Order library work after the caller's stream, and the caller's stream
+// after the library work.
+struct StreamScope {
+  stokes_ctx* c;
+  explicit StreamScope(stokes_ctx* cc) : c(cc) {
+    HIP_CHECK(hipEventRecord(c->ev_in, c->user_stream));
+    HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_in, 0));
+  }
+  ~StreamScope() {
+    if (hipEventRecord(c->ev_out, c->stream) == hipSuccess) (void)hipStreamWaitEvent(c->user_stream, c->ev_out, 0);
+  }
+};
+
 void info_reset(stokes_solve_info* info) {
   if (info) std::memset(info, 0, sizeof(*info));
 }
@@ -165,6 +179,7 @@ stokes_status solve_forward(stokes_ctx* c, int method, int32_t nrhs, const doubl
   info_reset(info);
   const double t0 = wall();
   HIP_CHECK(hipSetDevice(c->device));
+  StreamScope scope(c);
   prof_start(c, o);
   const int D = c->dim;
   stokes_status status = STOKES_OK;
@@ -215,7 +230,58 @@ stokes_status solve_forward(stokes_ctx* c, int method, int32_t nrhs, const doubl
 
 using namespace stokes;
 
+void stokes_ctx::clear_graphs() {
+  for (auto& kv : graphs)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  graphs.clear();
+}
+
+void stokes_ctx::run_graph(const std::string& key, const std::function<void()>& enqueue) {
+  if (!use_graphs) {
+    enqueue();
+    return;
+  }
+  Graph& g = graphs[key];
+  if (g.exec && g.gen == ws_gen) {
+    HIP_CHECK(hipGraphLaunch(g.exec, stream));
+    return;
+  }
+  if (g.exec) {
+    (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+  }
+  if (g.eager_runs == 0 || g.gen != ws_gen) {
+    // first use (or moved buffers): run eagerly so every workspace exists
+    g.gen = ws_gen;
+    enqueue();
+    g.eager_runs = 1;
+    g.gen = ws_gen;
+    return;
+  }
+  const uint64_t gen0 = ws_gen;
+  hipGraph_t graph = nullptr;
+  HIP_CHECK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  try {
+    enqueue();
+  } catch (...) {
+    (void)hipStreamEndCapture(stream, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  HIP_CHECK(hipStreamEndCapture(stream, &graph));
+  if (ws_gen != gen0) throw Error(STOKES_ERR_STATE, "workspace reallocated during graph capture");
+  hipGraphExec_t exec = nullptr;
+  HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  (void)hipGraphDestroy(graph);
+  g.exec = exec;
+  g.gen = ws_gen;
+  HIP_CHECK(hipGraphLaunch(g.exec, stream));
+}
+
 stokes_ctx::~stokes_ctx() {
+  clear_graphs();
+  if (ev_in) (void)hipEventDestroy(ev_in);
+  if (ev_out) (void)hipEventDestroy(ev_out);
   for (auto& pr : prof_ev) {
     (void)hipEventDestroy(pr.first);
     (void)hipEventDestroy(pr.second);
@@ -223,6 +289,8 @@ stokes_ctx::~stokes_ctx() {
   for (auto& kv : ws_host)
     if (kv.second.first) (void)hipHostFree(kv.second.first);
   if (h_scal) (void)hipHostFree(h_scal);
+  ws.clear();
+  if (stream) (void)hipStreamDestroy(stream);
 }
 
 void* stokes_ctx::workspace_host(const std::string& name, size_t bytes) {
@@ -348,7 +416,13 @@ stokes_status stokes_assemble(const stokes_problem* prob, void* hip_stream, stok
     auto c = std::make_unique<stokes_ctx>();
     c->prob = *prob;
     HIP_CHECK(hipGetDevice(&c->device));
-    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->user_stream = static_cast<hipStream_t>(hip_stream);
+    if (const char* e = std::getenv("STOKES_GRAPHS")) c->use_graphs = std::atoi(e) != 0;
+    if (const char* e = std::getenv("STOKES_CG_CHECK")) c->cg_check_every = std::max(1, std::atoi(e));
+    HIP_CHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    HIP_CHECK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    HIP_CHECK(hipStreamSynchronize(c->user_stream));
     if (!build_mesh(prob->dim, prob->n, prob->mesh_seed, prob->jitter, c->mesh))
       throw Error(STOKES_ERR_UNSUPPORTED, "mesh too large");
     c->dim = prob->dim;
@@ -400,6 +474,7 @@ stokes_status stokes_solve_adjoint(stokes_ctx* c, int32_t nrhs, const double* u,
     info_reset(info);
     const double t0 = wall();
     HIP_CHECK(hipSetDevice(c->device));
+    StreamScope scope(c);
     prof_start(c, o);
     const int D = c->dim;
     stokes_status status = STOKES_OK;
@@ -463,6 +538,7 @@ stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t
     if (nrhs < 1) throw Error(STOKES_ERR_ARG, "nrhs must be >= 1");
     if (!x || !y) throw Error(STOKES_ERR_ARG, "x and y must not be NULL");
     HIP_CHECK(hipSetDevice(c->device));
+    StreamScope scope(c);
     const int D = c->dim;
     for (int r0 = 0; r0 < nrhs;) {
       const int nrb = chunk_size(nrhs - r0);
@@ -525,6 +601,7 @@ stokes_status stokes_residual(stokes_ctx* c, int32_t nrhs, const double* f, cons
     if (nrhs < 1) throw Error(STOKES_ERR_ARG, "nrhs must be >= 1");
     if (!f || !u || !p || !rel) throw Error(STOKES_ERR_ARG, "NULL array argument");
     HIP_CHECK(hipSetDevice(c->device));
+    StreamScope scope(c);
     const int D = c->dim;
     for (int r0 = 0; r0 < nrhs;) {
       const int nrb = chunk_size(nrhs - r0);
@@ -592,7 +669,7 @@ stokes_status stokes_set_stream(stokes_ctx* c, void* stream) {
   return guard([&]() -> stokes_status {
     if (!c) throw Error(STOKES_ERR_ARG, "ctx is NULL");
     HIP_CHECK(hipStreamSynchronize(c->stream));
-    c->stream = static_cast<hipStream_t>(stream);
+    c->user_stream = static_cast<hipStream_t>(stream);
     return STOKES_OK;
   });
 }

@@ -831,6 +831,7 @@ void estimate_bounds(stokes_ctx* c) {
 
 // Re-form A = alpha M + mu L (SELL values and FP32 copy, diagonal, bounds).
 void reform_A(stokes_ctx* c) {
+  c->clear_graphs();  // captured Chebyshev coefficients depend on the bounds
   const int64_t n = c->sA.nnz_pad;
   launch(c, n, k_fill, n, c->sA.src.as<int32_t>(), 1, c->prob.alpha, c->M_full.as<double>(), c->prob.mu,
          c->L_full.as<double>(), c->A64.as<double>());

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -107,7 +108,9 @@ struct Scalars {
 
 struct stokes_ctx {
   stokes_problem prob{};
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;       // library-owned stream (all work; capturable)
+  hipStream_t user_stream = nullptr;  // caller's stream, ordered with `stream` by events
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   int device = 0;
   int dim = 0, nloc = 0;
   int64_t n_p1 = 0, n_p2 = 0, n_e = 0, n_int = 0;
@@ -146,6 +149,7 @@ struct stokes_ctx {
   std::vector<std::unique_ptr<stokes::MgLevel>> mg;
   int mg_smooth_degree = 3, mg_coarse_degree = 24;
   int64_t mg_dense_n = 0;               // > 0: coarsest level solved by a dense inverse
+  int64_t mg_dense_max = 1500;          // largest level solved densely
   stokes::DevBuf mg_cinv64, mg_cinv32;  // [n][n] inverse of the coarsest operator
   double mg_smooth_ratio = 10.0;
 
@@ -165,12 +169,28 @@ struct stokes_ctx {
   stokes::Scalars* h_scal = nullptr;
 
   std::map<std::string, std::pair<void*, size_t>> ws_host;  // pinned host buffers
+  uint64_t ws_gen = 1;  // bumped whenever a workspace moves (captured graphs go stale)
+
+  // captured kernel sequences replayed with hipGraphLaunch
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    uint64_t gen = 0;
+    int eager_runs = 0;
+  };
+  std::map<std::string, Graph> graphs;
+  int use_graphs = 1;
+  int cg_check_every = 2;  // inner CG: iterations between host convergence checks
 
   void* workspace(const std::string& name, size_t bytes) {
     auto& b = ws[name];
+    void* old = b.p;
     b.ensure(bytes);
+    if (b.p != old) ++ws_gen;
     return b.p;
   }
+  // Run `enqueue` (a fixed kernel sequence on `stream`) through a cached graph.
+  void run_graph(const std::string& key, const std::function<void()>& enqueue);
+  void clear_graphs();
   void* workspace_host(const std::string& name, size_t bytes);
   ~stokes_ctx();
 };

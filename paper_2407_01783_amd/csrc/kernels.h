@@ -121,15 +121,39 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ pa
 
 // --------------------------------------------------------- SELL row sums
 
+// Row sum of a scalar SELL matrix applied to W values per column.  The
+// entries of a row are walked four at a time so that eight matrix loads and
+// 4W gathers are in flight per thread (one-at-a-time loops leave HBM
+// under-subscribed).
 template <typename T, int W>
 __device__ __forceinline__ void sell_row(const int64_t* __restrict__ sp, const int32_t* __restrict__ cols,
                                          const T* __restrict__ vals, const T* __restrict__ x, int64_t row,
                                          T (&acc)[W]) {
   const int64_t s = row >> 6;
-  const int64_t end = sp[s + 1];
-  for (int64_t k = sp[s] + (row & 63); k < end; k += 64) {
-    const int32_t c = __builtin_nontemporal_load(cols + k);
-    const T v = __builtin_nontemporal_load(vals + k);
+  const int64_t beg = sp[s] + (row & 63);
+  const int width = (int)((sp[s + 1] - sp[s]) >> 6);
+  int j = 0;
+  for (; j + 4 <= width; j += 4) {
+    int32_t c[4];
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      c[u] = __builtin_nontemporal_load(cols + beg + 64 * (j + u));
+      v[u] = __builtin_nontemporal_load(vals + beg + 64 * (j + u));
+    }
+    T xv[4][W];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int w = 0; w < W; ++w) xv[u][w] = x[(int64_t)c[u] * W + w];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int w = 0; w < W; ++w) acc[w] = fma(v[u], xv[u][w], acc[w]);
+  }
+  for (; j < width; ++j) {
+    const int32_t c = __builtin_nontemporal_load(cols + beg + 64 * j);
+    const T v = __builtin_nontemporal_load(vals + beg + 64 * j);
     const T* xp = x + (int64_t)c * W;
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = fma(v, xp[w], acc[w]);
@@ -137,13 +161,39 @@ __device__ __forceinline__ void sell_row(const int64_t* __restrict__ sp, const i
 }
 
 // B rows (pressure vertex): acc[r] = sum_j sum_c B^c_j u[col_j][r][c]
+// (entries walked two at a time to keep more loads in flight)
 template <typename T, int D, int NRB>
 __device__ __forceinline__ void sell_row_B(const int64_t* __restrict__ sp, const int32_t* __restrict__ cols,
                                            const T* __restrict__ vals, const T* __restrict__ u, int64_t row,
                                            T (&acc)[NRB]) {
   const int64_t s = row >> 6;
-  const int64_t end = sp[s + 1];
-  for (int64_t k = sp[s] + (row & 63); k < end; k += 64) {
+  const int64_t beg = sp[s] + (row & 63);
+  const int width = (int)((sp[s + 1] - sp[s]) >> 6);
+  constexpr int U = 2;
+  int j = 0;
+  for (; j + U <= width; j += U) {
+    int32_t c[U];
+    T b[U][D], x[U][D * NRB];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int64_t k = beg + 64 * (j + q);
+      c[q] = __builtin_nontemporal_load(cols + k);
+#pragma unroll
+      for (int d = 0; d < D; ++d) b[q][d] = __builtin_nontemporal_load(vals + k * D + d);
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+      for (int w = 0; w < D * NRB; ++w) x[q][w] = u[(int64_t)c[q] * (D * NRB) + w];
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+      for (int r = 0; r < NRB; ++r)
+#pragma unroll
+        for (int d = 0; d < D; ++d) acc[r] = fma(b[q][d], x[q][r * D + d], acc[r]);
+  }
+  for (; j < width; ++j) {
+    const int64_t k = beg + 64 * j;
     const int32_t c = __builtin_nontemporal_load(cols + k);
     T b[D];
 #pragma unroll
@@ -162,8 +212,33 @@ __device__ __forceinline__ void sell_row_Bt(const int64_t* __restrict__ sp, cons
                                             const T* __restrict__ vals, const T* __restrict__ p, int64_t row,
                                             T (&acc)[D * NRB]) {
   const int64_t s = row >> 6;
-  const int64_t end = sp[s + 1];
-  for (int64_t k = sp[s] + (row & 63); k < end; k += 64) {
+  const int64_t beg = sp[s] + (row & 63);
+  const int width = (int)((sp[s + 1] - sp[s]) >> 6);
+  constexpr int U = 4;
+  int j = 0;
+  for (; j + U <= width; j += U) {
+    int32_t c[U];
+    T b[U][D], pv[U][NRB];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int64_t k = beg + 64 * (j + q);
+      c[q] = __builtin_nontemporal_load(cols + k);
+#pragma unroll
+      for (int d = 0; d < D; ++d) b[q][d] = __builtin_nontemporal_load(vals + k * D + d);
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+      for (int r = 0; r < NRB; ++r) pv[q][r] = p[(int64_t)c[q] * NRB + r];
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+      for (int r = 0; r < NRB; ++r)
+#pragma unroll
+        for (int d = 0; d < D; ++d) acc[r * D + d] = fma(b[q][d], pv[q][r], acc[r * D + d]);
+  }
+  for (; j < width; ++j) {
+    const int64_t k = beg + 64 * j;
     const int32_t c = __builtin_nontemporal_load(cols + k);
     T b[D];
 #pragma unroll
@@ -326,6 +401,43 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, const int64
   }
   if (DOT) {
     grid_reduce<W>(part, partials);
+  }
+}
+
+// First Chebyshev step with the prologue folded in: d0 = theta_inv dinv r is
+// formed on the fly at every gathered column, so no separate pass is needed:
+//   res = r - S d0 ;  d1 = c1 d0 + c2 dinv res ;  z = d0 + d1
+// ACC: z += d0 + d1 (z holds a previous approximation) instead of z = d0 + d1
+template <typename T, int W, int ACC>
+__global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, const int64_t* __restrict__ sp,
+                                                       const int32_t* __restrict__ cols, const T* __restrict__ vals,
+                                                       const T* __restrict__ r, const T* __restrict__ dinv, T theta_inv,
+                                                       T* __restrict__ d1, T* __restrict__ res, T* __restrict__ z,
+                                                       T c1, T c2) {
+  GRID_STRIDE_ROWS(row, nrows) {
+    T acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = 0;
+    const int64_t s = row >> 6;
+    const int64_t end = sp[s + 1];
+    for (int64_t k = sp[s] + (row & 63); k < end; k += 64) {
+      const int32_t c = __builtin_nontemporal_load(cols + k);
+      const T v = __builtin_nontemporal_load(vals + k) * dinv[c];
+      const T* xp = r + (int64_t)c * W;
+#pragma unroll
+      for (int w = 0; w < W; ++w) acc[w] = fma(v, xp[w], acc[w]);
+    }
+    const T di = dinv[row];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const int64_t i = row * W + w;
+      const T d0 = theta_inv * di * r[i];
+      const T rs = r[i] - theta_inv * acc[w];
+      res[i] = rs;
+      const T dn = fma(c1, d0, c2 * di * rs);
+      d1[i] = dn;
+      z[i] = ACC ? z[i] + (d0 + dn) : d0 + dn;
+    }
   }
 }
 

@@ -113,22 +113,27 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(int nf, int nc, const T*
   }
 }
 
-// y[i][r] = sum_j Cinv[i][j] x[j][r]   (coarsest-level solve)
+// y[i][r] = sum_j Cinv[i][j] x[j][r]   (coarsest-level solve): one wavefront
+// per row, coalesced over j, wavefront-shuffle reduction
 template <typename T, int NRB>
 __global__ __launch_bounds__(kBlock) void k_dense_mv(int64_t n, const T* __restrict__ Ci, const T* __restrict__ x,
                                                      T* __restrict__ y) {
-  GRID_STRIDE_ROWS(i, n) {
-    T acc[NRB];
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (row >= n) return;  // whole wavefronts exit together
+  double acc[NRB];
 #pragma unroll
-    for (int r = 0; r < NRB; ++r) acc[r] = 0;
-    for (int64_t j = 0; j < n; ++j) {
-      const T a = Ci[i * n + j];
+  for (int r = 0; r < NRB; ++r) acc[r] = 0;
+  for (int64_t j = lane; j < n; j += 64) {
+    const double a = Ci[row * n + j];
 #pragma unroll
-      for (int r = 0; r < NRB; ++r) acc[r] = fma(a, x[j * NRB + r], acc[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < NRB; ++r) y[i * NRB + r] = acc[r];
+    for (int r = 0; r < NRB; ++r) acc[r] += a * (double)x[j * NRB + r];
   }
+#pragma unroll
+  for (int r = 0; r < NRB; ++r) acc[r] = wave_sum(acc[r]);
+  if (lane == 0)
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) y[row * NRB + r] = (T)acc[r];
 }
 
 // Inverse of a small SPD matrix by Cholesky (host).
@@ -196,7 +201,8 @@ void build_mg(stokes_ctx* c) {
   const int D = fm.dim;
   int n = fm.n;
   int stride = 1;
-  while (n % 2 == 0 && n / 2 >= 1 && n > 2) {
+  // coarsen while the current level is too large for the dense coarse solve
+  while (n % 2 == 0 && n > 2 && ipow(n + 1, D) > c->mg_dense_max) {
     n /= 2;
     stride *= 2;
     auto L = std::make_unique<MgLevel>();
@@ -222,7 +228,7 @@ void build_mg(stokes_ctx* c) {
   const DevBuf& V = c->mg.empty() ? c->XQ64 : c->mg.back()->v64;
   const int64_t nr = S.nrows;
   c->mg_dense_n = 0;
-  if (nr <= 1500) {
+  if (nr <= c->mg_dense_max) {
     std::vector<int64_t> sp(S.nslices + 1);
     std::vector<int32_t> cols(S.nnz_pad);
     std::vector<double> vals(S.nnz_pad);
@@ -254,14 +260,19 @@ void mg_vcycle(stokes_ctx* c, int nrb, const T* r, T* e, int lv) {
   T* d0 = wsp<T>(c, tag + "_d0", n);
   T* d1 = wsp<T>(c, tag + "_d1", n);
   T* res = wsp<T>(c, tag + "_res", n);
-  auto cheb = [&](const Bounds& b, int degree, const T* rin, T* z) {
+  // z (+)= p(D^{-1} X) D^{-1} rin ; accumulate into z when acc != 0 (degree >= 2)
+  auto cheb = [&](const Bounds& b, int degree, const T* rin, T* z, int acc) {
     const Cheb k = coef(b, degree);
-    ops::cheb_init<T>(c, nr, nrb, rin, dinv, (T)k.theta_inv, d0, z);
+    if (degree == 1) {
+      ops::cheb_init<T>(c, nr, nrb, rin, dinv, (T)k.theta_inv, d0, z);
+      return;
+    }
+    ops::cheb_first<T>(c, S, vals, nrb, rin, dinv, (T)k.theta_inv, d0, res, z, (T)k.c1[0], (T)k.c2[0], acc);
     T* da = d0;
     T* db = d1;
-    for (int j = 1; j < degree; ++j) {
-      ops::cheb_step<T>(c, S, vals, nrb, da, db, j == 1 ? rin : res, res, z, dinv, (T)k.c1[j - 1], (T)k.c2[j - 1],
-                        nullptr, nullptr, 1, 0, 0);
+    for (int j = 2; j < degree; ++j) {
+      ops::cheb_step<T>(c, S, vals, nrb, da, db, res, res, z, dinv, (T)k.c1[j - 1], (T)k.c2[j - 1], nullptr, nullptr,
+                        1, 0, 0);
       std::swap(da, db);
     }
   };
@@ -271,23 +282,23 @@ void mg_vcycle(stokes_ctx* c, int nrb, const T* r, T* e, int lv) {
       dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
         constexpr int N = decltype(Nc)::value;
         (void)Dc;
-        hipLaunchKernelGGL((k_dense_mv<T, N>), dim3(ops::grid_for(nr)), dim3(kBlock), 0, c->stream, nr, Ci, r, e);
+        hipLaunchKernelGGL((k_dense_mv<T, N>), dim3((nr + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0,
+                           c->stream, nr, Ci, r, e);
       });
       ops::check_launch();
     } else {
-      cheb(bf, c->mg_coarse_degree, r, e);
+      cheb(bf, c->mg_coarse_degree, r, e, 0);
     }
     return;
   }
   const int nu = c->mg_smooth_degree;
   T* t = wsp<T>(c, tag + "_t", n);
-  T* dz = wsp<T>(c, tag + "_dz", n);
   const MgLevel& C = *c->mg[lv];
   const int nf = lv == 0 ? c->mesh.n : c->mg[lv - 1]->n;
   const int64_t ncn = C.nrows * nrb;
   T* rc = wsp<T>(c, "mg" + std::to_string(lv + 1) + "_rc", ncn);
   T* ec = wsp<T>(c, "mg" + std::to_string(lv + 1) + "_ec", ncn);
-  cheb(bs, nu, r, e);                                                   // pre-smoothing from zero
+  cheb(bs, nu, r, e, 0);                                                // pre-smoothing from zero
   ops::spmv<T>(c, S, vals, nrb, e, t, (T)-1, r, (T)1);                 // t = r - X e
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
     constexpr int DD = decltype(Dc)::value, N = decltype(Nc)::value;
@@ -303,8 +314,13 @@ void mg_vcycle(stokes_ctx* c, int nrb, const T* r, T* e, int lv) {
   });
   ops::check_launch();
   ops::spmv<T>(c, S, vals, nrb, e, t, (T)-1, r, (T)1);                 // t = r - X e
-  cheb(bs, nu, t, dz);                                                  // post-smoothing
-  ops::axpby<T>(c, n, (T)1, dz, (T)1, e);
+  if (nu >= 2) {
+    cheb(bs, nu, t, e, 1);                                              // post-smoothing, e += p(.) t
+  } else {
+    T* dz = wsp<T>(c, tag + "_dz", n);
+    cheb(bs, nu, t, dz, 0);
+    ops::axpby<T>(c, n, (T)1, dz, (T)1, e);
+  }
 }
 
 template void mg_vcycle<double>(stokes_ctx*, int, const double*, double*, int);

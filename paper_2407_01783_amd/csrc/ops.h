@@ -70,6 +70,10 @@ void cg_update(stokes_ctx* c, int64_t nrows, int W, int prec, T* x, T* r, const 
                T theta_inv, T* d0, T* z, Scalars* sc, int cps, int nsys);
 template <class T>
 void cheb_init(stokes_ctx* c, int64_t nrows, int W, const T* r, const T* dinv, T theta_inv, T* d0, T* z);
+// first Chebyshev step from x0 = 0 with the prologue fused (writes d1, res, z)
+template <class T>
+void cheb_first(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* r, const T* dinv, T theta_inv, T* d1,
+                T* res, T* z, T c1, T c2, int accumulate = 0);
 template <class T>
 void cheb_step(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* d, T* dn, const T* res_in, T* res_out,
                T* z, const T* dinv, T c1, T c2, const T* rvec, Scalars* sc, int cps, int nsys, int first);

@@ -28,6 +28,9 @@ const float* pick<float>(const DevBuf&, const DevBuf& b32) {
 bool prof_begin(stokes_ctx* c, const Sell* S, const void* vals, const void* avals) {
   if (!c->prof_on || S != &c->sA || vals != avals) return false;
   if (c->prof_idx >= static_cast<int>(c->prof_ev.size())) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_CHECK(hipStreamIsCapturing(c->stream, &cs));
+  if (cs != hipStreamCaptureStatusNone) return false;  // launches inside a graph are not timed
   HIP_CHECK(hipEventRecord(c->prof_ev[c->prof_idx].first, c->stream));
   return true;
 }
@@ -259,6 +262,23 @@ void cheb_init(stokes_ctx* c, int64_t nrows, int W, const T* r, const T* dinv, T
 }
 
 template <class T>
+void cheb_first(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* r, const T* dinv, T theta_inv, T* d1,
+                T* res, T* z, T c1, T c2, int accumulate) {
+  dispatch_w(W, [&](auto Wc) {
+    constexpr int WW = decltype(Wc)::value;
+    if (accumulate)
+      hipLaunchKernelGGL((k_cheb_first<T, WW, 1>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
+                         S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, r, dinv, theta_inv, d1, res, z, c1,
+                         c2);
+    else
+      hipLaunchKernelGGL((k_cheb_first<T, WW, 0>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
+                         S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, r, dinv, theta_inv, d1, res, z, c1,
+                         c2);
+  });
+  check_launch();
+}
+
+template <class T>
 void cheb_step(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* d, T* dn, const T* res_in, T* res_out,
                T* z, const T* dinv, T c1, T c2, const T* rvec, Scalars* sc, int cps, int nsys, int first) {
   // the timed kernel is the plain Chebyshev step (no fused dot) on the velocity block
@@ -383,6 +403,7 @@ void adj_dJdmu(stokes_ctx* c, int nrb, const double* u_full, const double* lam, 
   template void cg_update<T>(stokes_ctx*, int64_t, int, int, T*, T*, const T*, const T*, const T*, T, T*, T*,       \
                              Scalars*, int, int);                                                                    \
   template void cheb_init<T>(stokes_ctx*, int64_t, int, const T*, const T*, T, T*, T*);                             \
+  template void cheb_first<T>(stokes_ctx*, const Sell&, const T*, int, const T*, const T*, T, T*, T*, T*, T, T, int); \
   template void cheb_step<T>(stokes_ctx*, const Sell&, const T*, int, const T*, T*, const T*, T*, T*, const T*, T,  \
                              T, const T*, Scalars*, int, int, int);                                                  \
   template void vel_in<T>(stokes_ctx*, int, const double*, T*);                                                     \

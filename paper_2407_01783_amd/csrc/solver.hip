@@ -127,10 +127,14 @@ class Engine {
     T* d0 = buf(tag + "_d0", n);
     T* d1 = buf(tag + "_d1", n);
     T* res = buf(tag + "_res", n);
-    ops::cheb_init<T>(c_, S.nrows, W, r, dinv, (T)k.theta_inv, d0, z);
-    for (int j = 1; j < degree; ++j) {
-      ops::cheb_step<T>(c_, S, vals, W, d0, d1, j == 1 ? r : res, res, z, dinv, (T)k.c1[j - 1], (T)k.c2[j - 1],
-                        nullptr, nullptr, 1, 0, 0);
+    if (degree <= 1) {
+      ops::cheb_init<T>(c_, S.nrows, W, r, dinv, (T)k.theta_inv, d0, z);
+      return;
+    }
+    ops::cheb_first<T>(c_, S, vals, W, r, dinv, (T)k.theta_inv, d0, res, z, (T)k.c1[0], (T)k.c2[0]);
+    for (int j = 2; j < degree; ++j) {
+      ops::cheb_step<T>(c_, S, vals, W, d0, d1, res, res, z, dinv, (T)k.c1[j - 1], (T)k.c2[j - 1], nullptr, nullptr,
+                        1, 0, 0);
       std::swap(d0, d1);
     }
   }
@@ -151,8 +155,10 @@ class Engine {
   };
 
   // Solve op x = b per system to ||r|| <= rtol ||b||; returns iterations.
+  // graph = true replays the iteration body as a captured graph (worth it for
+  // the many short kernels of the pressure solve).
   int pcg(const std::string& tag, const Op& op, const T* opvals, const Prec& pc, int64_t nrows, int W, int cps,
-          const T* b, T* x, double rtol, int maxit, int sc_index) {
+          const T* b, T* x, double rtol, int maxit, int sc_index, bool graph) {
     const int64_t n = nrows * W;
     const int nsys = W / cps;
     Scalars* sc = scal(sc_index);
@@ -204,6 +210,31 @@ class Engine {
       }
     };
     precond(true);
+    // one CG iteration; converged systems are frozen on the device (alpha =
+    // beta = 0), so several iterations can run between host checks, and the
+    // fixed kernel sequence is replayed as a captured graph
+    auto body = [&]() {
+      if (op.apply) {
+        op.apply(z, t);
+        ops::cg_spmv<T>(c_, nrows, nullptr, nullptr, W, z, t, q, p, sc, cps, nsys);
+      } else {
+        if (op.extra) op.extra(z, t);
+        ops::cg_spmv<T>(c_, nrows, op.S, opvals, W, z, op.extra ? t : nullptr, q, p, sc, cps, nsys);
+      }
+      if (pc.apply) {
+        ops::cg_update<T>(c_, nrows, W, 2, x, r, p, q, pc.dinv, (T)1, d0, z, sc, cps, nsys);
+        precond(false);
+      } else if (pc.degree <= 1) {
+        ops::cg_update<T>(c_, nrows, W, 1, x, r, p, q, pc.dinv, (T)1, d0, z, sc, cps, nsys);
+      } else {
+        ops::cg_update<T>(c_, nrows, W, 0, x, r, p, q, pc.dinv, thinv, d0, z, sc, cps, nsys);
+        precond(false);
+      }
+    };
+    char key[256];
+    std::snprintf(key, sizeof(key), "pcg:%s:%d:%d:%p:%d:%d:%d", tag.c_str(), W, (int)sizeof(T), (void*)x, o_.schur_pc,
+                  pc.degree, pc.apply ? 1 : 0);
+    const int every = std::max(1, c_->cg_check_every);
     int it = 0;
     for (;;) {
       sync_scalars(sc_index);
@@ -230,23 +261,12 @@ class Engine {
         }
         break;
       }
-      ++it;
-      if (op.apply) {
-        op.apply(z, t);
-        ops::cg_spmv<T>(c_, nrows, nullptr, nullptr, W, z, t, q, p, sc, cps, nsys);
-      } else {
-        if (op.extra) op.extra(z, t);
-        ops::cg_spmv<T>(c_, nrows, op.S, opvals, W, z, op.extra ? t : nullptr, q, p, sc, cps, nsys);
+      const int k = std::min(every, maxit - it);
+      for (int i = 0; i < k; ++i) {
+        if (graph) c_->run_graph(key, body);
+        else body();
       }
-      if (pc.apply) {
-        ops::cg_update<T>(c_, nrows, W, 2, x, r, p, q, pc.dinv, (T)1, d0, z, sc, cps, nsys);
-        precond(false);
-      } else if (pc.degree <= 1) {
-        ops::cg_update<T>(c_, nrows, W, 1, x, r, p, q, pc.dinv, (T)1, d0, z, sc, cps, nsys);
-      } else {
-        ops::cg_update<T>(c_, nrows, W, 0, x, r, p, q, pc.dinv, thinv, d0, z, sc, cps, nsys);
-        precond(false);
-      }
+      it += k;
     }
     return it;
   }
@@ -281,7 +301,7 @@ class Engine {
       op.extra = [this](const T* z, T* t) { al_term(z, t); };
       cps = D_;
     }
-    st_.inner_u += pcg("vcg", op, A(), pc, c_->n_int, W_, cps, b, x, o_.inner_rtol_u, o_.max_inner, 0);
+    st_.inner_u += pcg("vcg", op, A(), pc, c_->n_int, W_, cps, b, x, o_.inner_rtol_u, o_.max_inner, 0, false);
   }
 
   // t = X z for the Cahouet-Chabard family
@@ -319,7 +339,7 @@ class Engine {
     } else {
       op.apply = [this](const T* z, T* t) { x_apply(z, t); };
     }
-    st_.inner_p += pcg("pcg", op, opvals, pc, c_->n_p1, nrb_, 1, b, x, o_.inner_rtol_p, o_.max_inner, 1);
+    st_.inner_p += pcg("pcg", op, opvals, pc, c_->n_p1, nrb_, 1, b, x, o_.inner_rtol_p, o_.max_inner, 1, true);
   }
 
   // z = C r = alpha X^{-1} r + mu (1 + gamma) M_Q^{-1} r on the mean-free

@@ -220,6 +220,25 @@ def test_deterministic_bitwise(gpu_lib):
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
 
 
+def test_graph_replay_matches_eager_bitwise(gpu_lib, monkeypatch):
+    # captured-graph replays of the inner CG bodies give the same bits as the
+    # eager kernel sequence (fixed-order reductions, same kernels); repeated
+    # solves replay the graphs several times with host work in between
+    kw = dict(dim=3, n=4, seed=9, mu=0.02, alpha=100.0)
+    S = _oracle(**kw)
+    fb = torch.tensor(inputs.fourier_forcing(S.mesh.p2coords, 1009)[None], device="cuda")
+    monkeypatch.setenv("STOKES_GRAPHS", "0")
+    Pe = _problem(**kw)
+    monkeypatch.setenv("STOKES_GRAPHS", "1")
+    Pg = _problem(**kw)
+    for method in ("coupled", "schur"):
+        ref = Pe.solve(fb, method=method, precision=1)
+        for _ in range(3):
+            got = Pg.solve(fb, method=method, precision=1)
+            assert torch.equal(ref[0], got[0]) and torch.equal(ref[1], got[1]), method
+            assert got[2]["status"] == 0
+
+
 def test_degenerate_single_interior_node(gpu_lib):
     # n = 1 in 3D: one interior P2 node (the body-diagonal midpoint)
     kw = dict(dim=3, n=1, seed=0, jitter=0.0, mu=1.0, alpha=10.0)
