@@ -72,6 +72,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=16, help="mesh size of the CPU oracle sample")
     ap.add_argument("--opt", action="append", default=[], help="solver option override key=value")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed solves, copy 1 GiB device-to-device 3 times (a kernel of known size "
+                         "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver has no multi-GPU path",
@@ -130,6 +133,14 @@ def main():
         fp64 = {"value": dofs * args.steps / el64, "ms_per_step": el64 / args.steps * 1e3, "converged": ok64,
                 "outer_iters": infos64[-1]["outer_iters"], "rel_res": infos64[-1]["rel_res"]}
         print(f"[bench] fp64: {el64 / args.steps * 1e3:.1f} ms/solve", file=sys.stderr, flush=True)
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu:

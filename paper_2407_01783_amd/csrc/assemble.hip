@@ -380,8 +380,10 @@ __global__ __launch_bounds__(kBlock) void k_dinv(int64_t nrows, const int64_t* _
   GRID_STRIDE_ROWS(row, nrows) {
     const int64_t s = row >> 6;
     double dv = 0;
+    // padding entries carry column 0 and value 0: skip them (row 0 would
+    // otherwise pick up a zero "diagonal")
     for (int64_t k = sp[s] + (row & 63); k < sp[s + 1]; k += 64)
-      if (cols[k] == row) dv = vals[k];
+      if (cols[k] == row && vals[k] != 0.0) dv = vals[k];
     out[row] = dv != 0 ? 1.0 / dv : 0.0;
   }
 }
@@ -541,15 +543,24 @@ void lanczos_bounds(stokes_ctx* c, const Sell& S, const double* vals, const doub
     HIP_CHECK(hipStreamSynchronize(c->stream));
     gersh = *std::max_element(h.begin(), h.end());
   }
-  // deterministic start vector: smooth-plus-oscillating pattern
+  // deterministic pseudo-random start vector (SplitMix64 finaliser of the row
+  // index): it has components along every eigenvector with overwhelming
+  // probability, independent of how the rows are ordered
   {
     std::vector<double> h(n);
-    for (int64_t i = 0; i < n; ++i) h[i] = 1.0 + 0.5 * std::sin(0.7 * double(i)) + 0.25 * std::cos(1.3 * double(i));
     double nn = 0;
-    for (double x : h) nn += x * x;
+    for (int64_t i = 0; i < n; ++i) {
+      uint64_t z = 0x9E3779B97F4A7C15ULL * uint64_t(i + 1);
+      z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+      z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+      z ^= z >> 31;
+      h[i] = double(z >> 11) * 0x1.0p-53 - 0.5;
+      nn += h[i] * h[i];
+    }
     for (double& x : h) x /= std::sqrt(nn);
     HIP_CHECK(hipMemcpyAsync(v1, h.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIP_CHECK(hipMemsetAsync(v0, 0, n * sizeof(double), c->stream));
+    HIP_CHECK(hipStreamSynchronize(c->stream));
   }
   std::vector<double> al, be;
   double beta_prev = 0, beta_first = 0;
@@ -601,7 +612,20 @@ void assemble_ctx(stokes_ctx* c) {
       if (!m.p2_bnd[P2full.cols[k]]) ++cnt;
     ilen[v] = cnt;
   }
-  std::stable_sort(interior.begin(), interior.end(), [&](int32_t a, int32_t b) { return ilen[a] > ilen[b]; });
+  // internal order: 8 slabs along the slowest axis (one per XCD, see the
+  // XCD-aware row partition of the gathering kernels), rows sorted by
+  // decreasing length inside each slab (the sliced-ELL padding then stays near
+  // zero), natural order among equal lengths
+  const int64_t n2 = 2 * int64_t(m.n) + 1, plane = D == 3 ? n2 * n2 : n2;
+  auto slab = [&](int32_t v) {
+    const int64_t K = v / plane;  // 1 .. 2n-1 on interior nodes
+    return std::min<int64_t>(7, (K - 1) * 8 / (n2 - 2));
+  };
+  std::stable_sort(interior.begin(), interior.end(), [&](int32_t a, int32_t b) {
+    const int64_t sa = slab(a), sb = slab(b);
+    if (sa != sb) return sa < sb;
+    return ilen[a] > ilen[b];
+  });
   c->n_int = static_cast<int64_t>(interior.size());
   c->h_int2nat = interior;
   c->h_nat2int.assign(m.n_p2, -1);
@@ -807,7 +831,7 @@ void assemble_p1(stokes_ctx* c, const HostMesh& m, MgLevel& L) {
   launch(c, m.n_p1, k_cast<double, float>, m.n_p1, L.d64.as<double>(), L.d32.as<float>());
   double lo, hi, g;
   lanczos_bounds(c, L.S, L.v64.as<double>(), L.d64.as<double>(), std::min<int>(40, (int)m.n_p1), lo, hi, g);
-  L.bf.hi = std::min(g, 1.05 * hi);
+  L.bf.hi = std::min(g, 1.1 * hi);
   L.bf.lo = 0.9 * lo;
   L.bs.hi = L.bf.hi;
   L.bs.lo = L.bf.hi / c->mg_smooth_ratio;
@@ -818,14 +842,14 @@ void estimate_bounds(stokes_ctx* c) {
   const int steps = 40;
   double lo, hi, g;
   lanczos_bounds(c, c->sA, c->A64.as<double>(), c->dA64.as<double>(), steps, lo, hi, g);
-  c->bA.hi = std::min(g, 1.05 * hi);
+  c->bA.hi = std::min(g, 1.1 * hi);
   c->bA.lo = std::max(0.9 * lo, c->bA.hi / 1000.0);
   lanczos_bounds(c, c->sQ, c->XQ64.as<double>(), c->dXQ64.as<double>(), steps, lo, hi, g);
-  c->bXQ.hi = std::min(g, 1.05 * hi);
+  c->bXQ.hi = std::min(g, 1.1 * hi);
   c->bXQ.lo = 0.9 * lo;
   c->bXQ_smooth = {c->bXQ.hi / c->mg_smooth_ratio, c->bXQ.hi};
   lanczos_bounds(c, c->sQ, c->LQ64.as<double>(), c->dLQ64.as<double>(), steps, lo, hi, g);
-  c->bLQ.hi = std::min(g, 1.05 * hi);
+  c->bLQ.hi = std::min(g, 1.1 * hi);
   c->bLQ.lo = c->bLQ.hi / 100.0;  // L_Q is singular: the constant mode is projected out
 }
 
@@ -841,7 +865,7 @@ void reform_A(stokes_ctx* c) {
   launch(c, c->n_int, k_cast<double, float>, c->n_int, c->dA64.as<double>(), c->dA32.as<float>());
   double lo, hi, g;
   lanczos_bounds(c, c->sA, c->A64.as<double>(), c->dA64.as<double>(), 40, lo, hi, g);
-  c->bA.hi = std::min(g, 1.05 * hi);
+  c->bA.hi = std::min(g, 1.1 * hi);
   c->bA.lo = std::max(0.9 * lo, c->bA.hi / 1000.0);
   HIP_CHECK(hipStreamSynchronize(c->stream));
 }

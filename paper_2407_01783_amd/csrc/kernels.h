@@ -257,6 +257,21 @@ __device__ __forceinline__ void sell_row_Bt(const int64_t* __restrict__ sp, cons
   for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < (nrows);      \
        row += (int64_t)gridDim.x * blockDim.x)
 
+// XCD-aware row partition for kernels that gather: workgroups are dealt
+// round-robin over the 8 XCDs (each with its own L2), so workgroup b works on
+// eighth (b % 8) of the rows -- one z-slab of the internal ordering, whose
+// gathered columns then stay in that XCD's L2 -- and the workgroups of one XCD
+// stride through their eighth, so each sees the same mix of long and short
+// rows.
+#define XCD_ROWS(row, nrows)                                                               \
+  const int64_t xg_ = (gridDim.x % 8 == 0) ? gridDim.x / 8 : gridDim.x;                   \
+  const int64_t xx_ = (gridDim.x % 8 == 0) ? blockIdx.x % 8 : 0;                          \
+  const int64_t xi_ = (gridDim.x % 8 == 0) ? blockIdx.x / 8 : blockIdx.x;                 \
+  const int64_t xn_ = (gridDim.x % 8 == 0) ? ((((nrows) + 7) / 8 + 63) / 64) * 64 : (nrows); \
+  const int64_t xb_ = xx_ * xn_;                                                          \
+  const int64_t xe_ = xb_ + xn_ < (nrows) ? xb_ + xn_ : (nrows);                          \
+  for (int64_t row = xb_ + xi_ * blockDim.x + threadIdx.x; row < xe_; row += xg_ * blockDim.x)
+
 // ----------------------------------------------------------- SpMV kernels
 
 // y = a * (S x) + b * yin   (yin may alias y; ignored when b == 0)
@@ -264,7 +279,7 @@ template <typename T, int W>
 __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, const int64_t* __restrict__ sp,
                                                  const int32_t* __restrict__ cols, const T* __restrict__ vals,
                                                  const T* __restrict__ x, T* y, T a, const T* yin, T b) {
-  GRID_STRIDE_ROWS(row, nrows) {
+  XCD_ROWS(row, nrows) {
     T acc[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = 0;
@@ -292,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t nrows, const int64_t
   double part[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) part[w] = 0;
-  GRID_STRIDE_ROWS(row, nrows) {
+  XCD_ROWS(row, nrows) {
     T acc[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = 0;
@@ -381,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, const int64
   double part[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) part[w] = 0;
-  GRID_STRIDE_ROWS(row, nrows) {
+  XCD_ROWS(row, nrows) {
     T acc[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = 0;
@@ -414,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, const int6
                                                        const T* __restrict__ r, const T* __restrict__ dinv, T theta_inv,
                                                        T* __restrict__ d1, T* __restrict__ res, T* __restrict__ z,
                                                        T c1, T c2) {
-  GRID_STRIDE_ROWS(row, nrows) {
+  XCD_ROWS(row, nrows) {
     T acc[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = 0;
@@ -448,7 +463,7 @@ template <typename T, int D, int NRB>
 __global__ __launch_bounds__(kBlock) void k_B(int64_t nrows, const int64_t* __restrict__ sp,
                                               const int32_t* __restrict__ cols, const T* __restrict__ vals,
                                               const T* __restrict__ u, T* pout, T a, const T* pin, T b) {
-  GRID_STRIDE_ROWS(row, nrows) {
+  XCD_ROWS(row, nrows) {
     T acc[NRB];
 #pragma unroll
     for (int r = 0; r < NRB; ++r) acc[r] = 0;
@@ -469,7 +484,7 @@ __global__ __launch_bounds__(kBlock) void k_Bt(int64_t nrows, const int64_t* __r
                                                const T* __restrict__ p, const T* __restrict__ scale, T* uout,
                                                T a, const T* uin, T b) {
   constexpr int W = D * NRB;
-  GRID_STRIDE_ROWS(row, nrows) {
+  XCD_ROWS(row, nrows) {
     T acc[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = 0;
@@ -494,7 +509,7 @@ __global__ __launch_bounds__(kBlock) void k_momentum(int64_t nrows, const int64_
                                                      const T* __restrict__ u, const T* __restrict__ p,
                                                      const T* __restrict__ extra, T* y, T sgn, const T* yin) {
   constexpr int W = D * NRB;
-  GRID_STRIDE_ROWS(row, nrows) {
+  XCD_ROWS(row, nrows) {
     T acc[W], bt[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = bt[w] = 0;

@@ -65,6 +65,28 @@ def test_mass_bounds_are_element_constants(gpu_lib):
     assert 0 < b[0] < b[1]
 
 
+@pytest.mark.parametrize("dim,n,mu", [(3, 4, 0.1), (3, 5, 1.0), (2, 8, 0.01)])
+def test_chebyshev_intervals_bracket_spectrum(gpu_lib, dim, n, mu):
+    # the velocity interval must contain the spectrum of D^-1 A (an upper
+    # bound below lambda_max makes the polynomial preconditioner indefinite);
+    # its lower end sits at or below lambda_min.  Regression: padding entries
+    # (column 0, value 0) once replaced row 0's diagonal.
+    P = _problem(dim, n, seed=3, mu=mu, alpha=100.0)
+    S = _oracle(dim, n, seed=3, mu=mu, alpha=100.0)
+    b = P.bounds()
+
+    def spec(A):
+        A = A.toarray()
+        d = np.sqrt(np.diag(A))
+        return np.linalg.eigvalsh(A / np.outer(d, d))
+
+    ev = spec(S.A_II)
+    assert b[1] >= ev[-1] and b[1] <= 1.2 * ev[-1], (b[:2], ev[[0, -1]])
+    assert 0.5 * ev[0] <= b[0] <= ev[0], (b[:2], ev[[0, -1]])
+    evq = spec(S.mats.MQ + S.mats.LQ)
+    assert b[7] >= evq[-1] and 0 < b[6] <= evq[0], (b[6:], evq[[0, -1]])
+
+
 # ----------------------------------------------------------------- operators
 
 def _ops_reference(S, x_u, x_p):
