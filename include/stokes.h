@@ -99,7 +99,10 @@ typedef struct {
   int32_t coupled_pc;     /* STOKES_PC_* */
   int32_t max_refine;     /* cap on iterative-refinement sweeps */
   int32_t profile;        /* 1: time the dominant SpMV with HIP events */
-  int32_t reserved[4];    /* must be 0 */
+  int32_t inner_its_u;    /* > 0: every inner velocity CG runs exactly this many
+                             iterations (no convergence checks); 0: use inner_rtol_u */
+  int32_t inner_its_p;    /* the same for the inner pressure CG (0: inner_rtol_p) */
+  int32_t reserved[2];    /* must be 0 */
 } stokes_solve_opts;
 
 typedef struct {

@@ -40,7 +40,8 @@ class SolveOpts(ctypes.Structure):
                 ("restart", ctypes.c_int32), ("max_inner", ctypes.c_int32), ("inner_mode", ctypes.c_int32),
                 ("cheb_degree", ctypes.c_int32), ("inner_rtol_u", ctypes.c_double),
                 ("inner_rtol_p", ctypes.c_double), ("schur_pc", ctypes.c_int32), ("coupled_pc", ctypes.c_int32),
-                ("max_refine", ctypes.c_int32), ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("max_refine", ctypes.c_int32), ("profile", ctypes.c_int32), ("inner_its_u", ctypes.c_int32),
+                ("inner_its_p", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -73,7 +73,9 @@ void check_opts(const stokes_solve_opts* o) {
     throw Error(STOKES_ERR_ARG, "inner tolerances must be in (0, 1)");
   if (o->schur_pc < 0 || o->schur_pc > 2) throw Error(STOKES_ERR_ARG, "schur_pc");
   if (o->coupled_pc < 0 || o->coupled_pc > 2) throw Error(STOKES_ERR_ARG, "coupled_pc");
-  for (int i = 0; i < 4; ++i)
+  if (o->inner_its_u < 0 || o->inner_its_u > 1000 || o->inner_its_p < 0 || o->inner_its_p > 1000)
+    throw Error(STOKES_ERR_ARG, "inner_its_u / inner_its_p must be in [0, 1000]");
+  for (int i = 0; i < 2; ++i)
     if (o->reserved[i] != 0) throw Error(STOKES_ERR_ARG, "reserved fields must be 0");
 }
 

@@ -634,7 +634,9 @@ __global__ __launch_bounds__(kBlock) void k_p_out(int64_t n_p1, const T* __restr
 // ------------------------------------------------- right-hand side (FP64)
 
 // F~ on interior rows: F~ = (M f)_I - ((alpha M + mu L) G)_I, G = ubc on the
-// boundary columns; CSR over all P2 nodes, output internal layout.
+// boundary columns; CSR over all P2 nodes, output internal layout.  One
+// wavefront per row: the lanes read the row's entries contiguously and the
+// partial sums are combined with wavefront shuffles.
 template <int D, int NRB>
 __global__ __launch_bounds__(kBlock) void k_rhs_u(int64_t n_int, int64_t n_p2, const int32_t* __restrict__ int2nat,
                                                   const int32_t* __restrict__ nat2int,
@@ -643,12 +645,14 @@ __global__ __launch_bounds__(kBlock) void k_rhs_u(int64_t n_int, int64_t n_p2, c
                                                   double alpha, double mu, const double* __restrict__ f,
                                                   const double* __restrict__ ubc, double* __restrict__ F) {
   constexpr int W = D * NRB;
-  GRID_STRIDE_ROWS(row, n_int) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+  for (int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); row < n_int; row += waves) {
     const int64_t nat = int2nat[row];
     double acc[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = 0;
-    for (int64_t k = rp[nat]; k < rp[nat + 1]; ++k) {
+    for (int64_t k = rp[nat] + lane; k < rp[nat + 1]; k += 64) {
       const int64_t c = cols[k];
       const double m = M[k];
       const bool bnd = nat2int[c] < 0;
@@ -664,7 +668,10 @@ __global__ __launch_bounds__(kBlock) void k_rhs_u(int64_t n_int, int64_t n_p2, c
         }
     }
 #pragma unroll
-    for (int w = 0; w < W; ++w) F[row * W + w] = acc[w];
+    for (int w = 0; w < W; ++w) acc[w] = wave_sum(acc[w]);
+    if (lane == 0)
+#pragma unroll
+      for (int w = 0; w < W; ++w) F[row * W + w] = acc[w];
   }
 }
 

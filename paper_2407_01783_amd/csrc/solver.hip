@@ -157,8 +157,9 @@ class Engine {
   // Solve op x = b per system to ||r|| <= rtol ||b||; returns iterations.
   // graph = true replays the iteration body as a captured graph (worth it for
   // the many short kernels of the pressure solve).
+  // fixed > 0 runs exactly that many iterations without convergence checks.
   int pcg(const std::string& tag, const Op& op, const T* opvals, const Prec& pc, int64_t nrows, int W, int cps,
-          const T* b, T* x, double rtol, int maxit, int sc_index, bool graph) {
+          const T* b, T* x, double rtol, int maxit, int sc_index, bool graph, int fixed = 0) {
     const int64_t n = nrows * W;
     const int nsys = W / cps;
     Scalars* sc = scal(sc_index);
@@ -236,6 +237,14 @@ class Engine {
                   pc.degree, pc.apply ? 1 : 0);
     const int every = std::max(1, c_->cg_check_every);
     int it = 0;
+    if (fixed > 0) {
+      for (int i = 0; i < fixed; ++i) {
+        if (graph) c_->run_graph(key, body);
+        else body();
+      }
+      it = fixed;
+      maxit = fixed;  // the check below only looks for breakdown
+    }
     for (;;) {
       sync_scalars(sc_index);
       const Scalars& h = *c_->h_scal;
@@ -301,7 +310,8 @@ class Engine {
       op.extra = [this](const T* z, T* t) { al_term(z, t); };
       cps = D_;
     }
-    st_.inner_u += pcg("vcg", op, A(), pc, c_->n_int, W_, cps, b, x, o_.inner_rtol_u, o_.max_inner, 0, false);
+    st_.inner_u += pcg("vcg", op, A(), pc, c_->n_int, W_, cps, b, x, o_.inner_rtol_u, o_.max_inner, 0, false,
+                       o_.inner_its_u);
   }
 
   // t = X z for the Cahouet-Chabard family
@@ -339,7 +349,8 @@ class Engine {
     } else {
       op.apply = [this](const T* z, T* t) { x_apply(z, t); };
     }
-    st_.inner_p += pcg("pcg", op, opvals, pc, c_->n_p1, nrb_, 1, b, x, o_.inner_rtol_p, o_.max_inner, 1, true);
+    st_.inner_p += pcg("pcg", op, opvals, pc, c_->n_p1, nrb_, 1, b, x, o_.inner_rtol_p, o_.max_inner, 1, true,
+                       o_.inner_its_p);
   }
 
   // z = C r = alpha X^{-1} r + mu (1 + gamma) M_Q^{-1} r on the mean-free
