@@ -42,6 +42,41 @@ SOLVER = dict(method="coupled", rtol=1e-8, cheb_degree=4, inner_mode=0, inner_rt
               coupled_pc=1, schur_pc=1, restart=30, max_outer=500, max_refine=12)
 
 
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILE_DIR, "k_cheb_step_f32_cube64_hbm_traffic.txt")
+
+
+def kernel_source_digest():
+    """sha256 over the HIP/C++ sources of the library (file names + contents)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2407_01783_amd", "csrc")
+    for path in sorted(glob.glob(os.path.join(src, "*.h")) + glob.glob(os.path.join(src, "*.hip")) +
+                       glob.glob(os.path.join(src, "*.cpp"))):
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, nrhs):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when that summary was taken on
+    other sources (any kernel changed since), another workload, or is absent."""
+    if workload != "cube64" or nrhs != 1 or not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and line.split(":", 1)[0].strip() in ("source_sha256", "hbm_bytes_per_launch"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("source_sha256") != kernel_source_digest() or "hbm_bytes_per_launch" not in fields:
+        return None
+    return float(fields["hbm_bytes_per_launch"])
+
+
 def cpu_baseline(dim, mesh_seed, mu, alpha, fseed, n_sample):
     """The FP64 oracle (MINRES, block preconditioner) on a smaller mesh of the
     same workload family, solved to a true relative residual <= 1e-8."""
@@ -168,7 +203,8 @@ def main():
         "fp64": fp64,
         "mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": measured_traffic(args.workload, args.nrhs),
                      "kernel": "k_cheb_step<float,3,0> (FP32 velocity-block SELL SpMV + Chebyshev update)",
                      "bytes_per_launch": bytes_per, "launches": launches,
                      "avg_us": kern_s / launches * 1e6 if launches else None},
