@@ -287,3 +287,47 @@ def assemble_rows(mesh, rows):
         cols = np.array(sorted(acc[r]))
         out[r] = (cols, np.array([acc[r][c][0] for c in cols]), np.array([acc[r][c][1] for c in cols]))
     return out
+
+
+def residual_rows(mesh, mu, alpha, f, u_full, p, vel_rows, p_rows):
+    """Rows of the coupled residual computed one by one from incident elements.
+
+    Discrete problem of Sec. 2.2 with the velocity block alpha M_V + mu L_V
+    (the A~_{lambda,3} form of Sec. 3.2) and F = M_V f:
+      momentum row (node i, component c):
+          (M f_c)_i - ((alpha M + mu L) u_c)_i + sum_k B_c[k, i] p_k
+      continuity row k:   - sum_c (B_c u_c)_k
+    where u_full holds every P2 node (boundary values included), so the
+    Dirichlet lifting is implicit.  f, u_full: (d, n_p2); p: (n_p1,).
+    vel_rows: iterable of (c, node); p_rows: iterable of P1 vertex ids.
+    Returns (momentum residuals, continuity residuals, momentum right-hand
+    sides (M f_c)_i) as arrays in the order given."""
+    d = mesh.dim
+    vel_rows = [(int(c), int(i)) for c, i in vel_rows]
+    p_rows = [int(k) for k in p_rows]
+    nodes = {i for _, i in vel_rows}
+    verts = set(p_rows)
+    rm = {r: 0.0 for r in vel_rows}
+    rf = {r: 0.0 for r in vel_rows}
+    rp = {k: 0.0 for k in p_rows}
+    hit = np.isin(mesh.p2, list(nodes)).any(axis=1) if nodes else np.zeros(mesh.n_e, bool)
+    if verts:
+        hit |= np.isin(mesh.elems, list(verts)).any(axis=1)
+    for e in np.nonzero(hit)[0]:
+        em = element_matrices(mesh, e)
+        loc = mesh.p2[e]
+        vs = mesh.elems[e]
+        A = alpha * em["M"] + mu * em["L"]
+        for a, i in enumerate(loc):
+            for c in range(d):
+                key = (c, int(i))
+                if key not in rm:
+                    continue
+                mf = em["M"][a] @ f[c, loc]
+                rf[key] += mf
+                rm[key] += mf - A[a] @ u_full[c, loc] + em["B"][c, :, a] @ p[vs]
+        for kk, k in enumerate(vs):
+            if int(k) in rp:
+                rp[int(k)] -= sum(em["B"][c, kk, :] @ u_full[c, loc] for c in range(d))
+    return (np.array([rm[r] for r in vel_rows]), np.array([rp[k] for k in p_rows]),
+            np.array([rf[r] for r in vel_rows]))

@@ -194,6 +194,7 @@ class StokesSolve(torch.autograd.Function):
             raise _lib.StokesError(info["status"], "forward solve did not converge")
         ctx.problem, ctx.opts = problem, opts
         ctx.shape = f.shape
+        ctx.mu_like = mu if torch.is_tensor(mu) else None
         ctx.save_for_backward(u)
         return u.view(f.shape), p.view(f.shape[:-2] + (problem.n_p1,)) if f.dim() == 3 else p.view(problem.n_p1)
 
@@ -207,4 +208,7 @@ class StokesSolve(torch.autograd.Function):
         _, _, dJdf, dJdmu, info = prob.adjoint(u, gu, gp, **ctx.opts)
         if info["status"] != 0:
             raise _lib.StokesError(info["status"], "adjoint solve did not converge")
-        return dJdf.view(ctx.shape), dJdmu.sum(), None, None
+        gmu = None
+        if ctx.mu_like is not None:
+            gmu = dJdmu.sum().to(device=ctx.mu_like.device, dtype=ctx.mu_like.dtype).reshape(ctx.mu_like.shape)
+        return dJdf.view(ctx.shape), gmu, None, None

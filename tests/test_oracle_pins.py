@@ -237,6 +237,41 @@ def test_assembly_rows_match_element_sums():
         assert np.allclose(Lr.data, lv, rtol=1e-13, atol=1e-14)
 
 
+def test_residual_rows_match_assembled_system():
+    """Row-by-row residuals (used at full size) == the assembled operators;
+    and they vanish on a direct solution with Dirichlet data."""
+    for dim, n in ((2, 4), (3, 3)):
+        m = mesh.KuhnMesh(dim, n, seed=2, jitter=0.1)
+        mats = fem.assemble(m)
+        rng = np.random.default_rng(dim)
+        mu, alpha = 0.3, 7.0
+        f = rng.standard_normal((dim, m.n_p2))
+        u = rng.standard_normal((dim, m.n_p2))
+        p = rng.standard_normal(m.n_p1)
+        A = alpha * mats.Ms + mu * mats.Ls
+        mom = np.stack([mats.Ms @ f[c] - A @ u[c] + mats.B[c].T @ p for c in range(dim)])
+        con = -sum(mats.B[c] @ u[c] for c in range(dim))
+        vrows = [(c, i) for c in range(dim) for i in (0, 5, m.n_p2 // 2, m.n_p2 - 2)]
+        prow = [0, 3, m.n_p1 - 1]
+        rm, rp, rf = fem.residual_rows(m, mu, alpha, f, u, p, vrows, prow)
+        assert np.allclose(rm, [mom[c, i] for c, i in vrows], rtol=1e-12, atol=1e-12)
+        assert np.allclose(rp, con[prow], rtol=1e-12, atol=1e-13)
+        assert np.allclose(rf, [(mats.Ms @ f[c])[i] for c, i in vrows], rtol=1e-13, atol=1e-14)
+        # at a solution with nonzero Dirichlet data every interior row vanishes
+        s = stokes.StokesSystem(m, mu, alpha, mats=mats)
+        ubc = rng.standard_normal((dim, m.n_p2))
+        ubc[:, m.interior_nodes] = 0
+        F, g = s.rhs(f, ubc)
+        U, P = s.solve_direct(F, g)
+        uf = s.full_velocity(U, ubc)
+        inner = [(c, int(i)) for c in range(dim) for i in m.interior_nodes[[0, -1]]]
+        rm, rp, _ = fem.residual_rows(m, mu, alpha, f, uf, P, inner, range(m.n_p1))
+        scale = np.abs(F).max()
+        assert np.abs(rm).max() <= 1e-10 * scale
+        # continuity holds up to the l2-mean removed from g (compatibility)
+        assert np.abs(rp - rp.mean()).max() <= 1e-10 * scale
+
+
 # ------------------------------------------------------------------- solves
 
 
