@@ -190,7 +190,9 @@ stokes_status stokes_solve_adjoint(stokes_ctx* ctx, int32_t nrhs, const double* 
  * operator: (y_u, y_p) = (A u - B^T p, B u) with x = (x_u, x_p) packed as
  * [nrhs][dim][n_p2] followed by [nrhs][n_p1]; 6 = one geometric multigrid
  * V-cycle for eps M_Q + L_Q (eps = 1), the pressure preconditioner of
- * Sec. 4.2 (x, y pressure-shaped). */
+ * Sec. 4.2 (x, y pressure-shaped); 7 = y = B_I Lambda_V^-1 B_I^T x, the
+ * lumped-mass pressure operator of Sec. 4.3, assembled explicitly (x, y
+ * pressure-shaped). */
 stokes_status stokes_apply(stokes_ctx* ctx, int32_t op, int32_t precision, int32_t nrhs,
                            const double* x, double* y);
 
@@ -200,8 +202,10 @@ stokes_status stokes_apply(stokes_ctx* ctx, int32_t op, int32_t precision, int32
 stokes_status stokes_residual(stokes_ctx* ctx, int32_t nrhs, const double* f, const double* ubc,
                               const double* u, const double* p, double* rel_res_host);
 
-/* sizes[0..9] as in stokes_problem_sizes, for an assembled context. */
-stokes_status stokes_query(const stokes_ctx* ctx, int64_t sizes[10]);
+/* sizes[0..9] as in stokes_problem_sizes, for an assembled context;
+ * sizes[10] = entries of B_I Lambda_V^-1 B_I^T (export_csr which 9),
+ * sizes[11] = 0 (reserved). */
+stokes_status stokes_query(const stokes_ctx* ctx, int64_t sizes[12]);
 
 /* Change mu and re-form A = alpha M + mu L on the device. */
 stokes_status stokes_set_mu(stokes_ctx* ctx, double mu);
@@ -216,7 +220,8 @@ stokes_status stokes_export_mesh(const stokes_ctx* ctx, double* p2coords_host, i
 /* Copy an assembled FP64 matrix to host CSR arrays in the natural numbering
  * of stokes_host_pattern.  which: 0 = M_s (all P2), 1 = L_s (all P2),
  * 2..4 = B plane x, y, z (P1 x all P2), 5 = M_Q, 6 = L_Q, 7 = A_II (interior,
- * pattern 1), 8 = Lambda_V (diagonal: rowptr/cols ignored, vals [n_p2]). */
+ * pattern 1), 8 = Lambda_V (diagonal: rowptr/cols ignored, vals [n_p2]),
+ * 9 = B_I Lambda_V^-1 B_I^T (P1 x P1, stokes_query sizes[10] entries). */
 stokes_status stokes_export_csr(const stokes_ctx* ctx, int32_t which, int32_t* rowptr_host,
                                 int32_t* cols_host, double* vals_host);
 

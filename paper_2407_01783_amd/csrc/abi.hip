@@ -535,7 +535,7 @@ stokes_status stokes_solve_adjoint(stokes_ctx* c, int32_t nrhs, const double* u,
 stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t nrhs, const double* x, double* y) {
   return guard([&]() -> stokes_status {
     if (!c) throw Error(STOKES_ERR_ARG, "ctx is NULL");
-    if (op < 0 || op > 6) throw Error(STOKES_ERR_ARG, "op must be in [0, 6]");
+    if (op < 0 || op > 7) throw Error(STOKES_ERR_ARG, "op must be in [0, 7]");
     if (precision != 0 && precision != 1) throw Error(STOKES_ERR_ARG, "precision must be 0 or 1");
     if (nrhs < 1) throw Error(STOKES_ERR_ARG, "nrhs must be >= 1");
     if (!x || !y) throw Error(STOKES_ERR_ARG, "x and y must not be NULL");
@@ -556,7 +556,7 @@ stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t
       float* yuf = static_cast<float*>(c->workspace("ap_yuf", nu * sizeof(float)));
       float* ypf = static_cast<float*>(c->workspace("ap_ypf", np * sizeof(float)));
       const bool in_vel = op == 0 || op == 1 || op == 5;
-      const bool in_p = op == 2 || op == 3 || op == 4 || op == 5 || op == 6;
+      const bool in_p = op == 2 || op == 3 || op == 4 || op == 5 || op == 6 || op == 7;
       const bool out_vel = op == 0 || op == 2 || op == 5;
       const double* xv = x + vo;
       const double* xpp = op == 5 ? x + tot_u + po : x + po;
@@ -576,6 +576,7 @@ stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t
           case 3: ops::spmv<T>(c, c->sQ, ops::pick<T>(c->MQ64, c->MQ32), nrb, XP, YP, (T)1, nullptr, (T)0); break;
           case 4: ops::spmv<T>(c, c->sQ, ops::pick<T>(c->LQ64, c->LQ32), nrb, XP, YP, (T)1, nullptr, (T)0); break;
           case 6: mg_vcycle<T>(c, nrb, XP, YP, 0); break;
+          case 7: ops::spmv<T>(c, c->sX, ops::pick<T>(c->XL64, c->XL32), nrb, XP, YP, (T)1, nullptr, (T)0); break;
           default:
             ops::momentum<T>(c, nrb, XU, XP, nullptr, YU, (T)1, nullptr);
             ops::Bmul<T>(c, nrb, XU, YP, (T)1, nullptr, (T)0);
@@ -639,7 +640,7 @@ stokes_status stokes_residual(stokes_ctx* c, int32_t nrhs, const double* f, cons
   });
 }
 
-stokes_status stokes_query(const stokes_ctx* c, int64_t sizes[10]) {
+stokes_status stokes_query(const stokes_ctx* c, int64_t sizes[12]) {
   return guard([&]() -> stokes_status {
     if (!c || !sizes) throw Error(STOKES_ERR_ARG, "NULL argument");
     sizes[0] = c->n_p2;
@@ -652,6 +653,8 @@ stokes_status stokes_query(const stokes_ctx* c, int64_t sizes[10]) {
     sizes[7] = c->dim;
     sizes[8] = c->p2full.nnz;
     sizes[9] = c->bfull.nnz;
+    sizes[10] = c->xl.nnz;
+    sizes[11] = 0;
     return STOKES_OK;
   });
 }
@@ -689,7 +692,7 @@ stokes_status stokes_export_csr(const stokes_ctx* cc, int32_t which, int32_t* ro
   stokes_ctx* c = const_cast<stokes_ctx*>(cc);
   return guard([&]() -> stokes_status {
     if (!c) throw Error(STOKES_ERR_ARG, "ctx is NULL");
-    if (which < 0 || which > 8) throw Error(STOKES_ERR_ARG, "which must be in [0, 8]");
+    if (which < 0 || which > 9) throw Error(STOKES_ERR_ARG, "which must be in [0, 9]");
     if (!vals) throw Error(STOKES_ERR_ARG, "vals is NULL");
     HIP_CHECK(hipSetDevice(c->device));
     HIP_CHECK(hipStreamSynchronize(c->stream));
@@ -711,6 +714,7 @@ stokes_status stokes_export_csr(const stokes_ctx* cc, int32_t which, int32_t* ro
         break;
       case 5: copy_csr(c->p1, c->MQ_csr, 1, 0); break;
       case 6: copy_csr(c->p1, c->LQ_csr, 1, 0); break;
+      case 9: copy_csr(c->xl, c->XL_csr, 1, 0); break;
       case 7: {
         // A_II in the natural interior numbering (pattern 1 of stokes_host_pattern)
         const Sell& S = c->sA;
@@ -747,8 +751,11 @@ stokes_status stokes_export_csr(const stokes_ctx* cc, int32_t which, int32_t* ro
         }
         break;
       }
-      default:
+      case 8:
         HIP_CHECK(hipMemcpy(vals, c->lam_full.p, c->n_p2 * sizeof(double), hipMemcpyDeviceToHost));
+        break;
+      default:
+        break;
     }
     return STOKES_OK;
   });

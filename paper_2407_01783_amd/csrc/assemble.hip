@@ -309,6 +309,47 @@ __global__ __launch_bounds__(kBlock) void k_gather_b(int64_t n_p1, const int64_t
   }
 }
 
+// rows of X = B_I Lambda_V^-1 B_I^T (lumped-mass pressure operator of Sec. 4.3),
+// one wavefront per P1 row k: each lane owns output entries (k, l) and merges
+// the sorted B rows k and l, summing over the shared interior P2 columns j
+//   X_kl = sum_j sum_c B_c[k, j] B_c[l, j] / Lambda_j
+// in increasing j, so the result does not depend on the launch shape.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_gather_xl(int64_t n_p1, const int32_t* __restrict__ brp,
+                                                      const int32_t* __restrict__ bcols,
+                                                      const double* __restrict__ Bv, const double* __restrict__ lam,
+                                                      const int32_t* __restrict__ nat2int,
+                                                      const int32_t* __restrict__ xrp,
+                                                      const int32_t* __restrict__ xcols, double* __restrict__ X) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+  for (int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); k < n_p1; k += waves) {
+    for (int64_t q = xrp[k] + lane; q < xrp[k + 1]; q += 64) {
+      const int64_t l = xcols[q];
+      int64_t ia = brp[k], ib = brp[l];
+      const int64_t ea = brp[k + 1], eb = brp[l + 1];
+      double s = 0;
+      while (ia < ea && ib < eb) {
+        const int32_t ja = bcols[ia], jb = bcols[ib];
+        if (ja < jb) {
+          ++ia;
+        } else if (jb < ja) {
+          ++ib;
+        } else {
+          if (nat2int[ja] >= 0) {
+            double t = 0;
+            for (int c = 0; c < D; ++c) t += Bv[ia * D + c] * Bv[ib * D + c];
+            s += t / lam[ja];
+          }
+          ++ia;
+          ++ib;
+        }
+      }
+      X[q] = s;
+    }
+  }
+}
+
 // rows of M_Q and L_Q
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_gather_q(int64_t n_p1, const int64_t* __restrict__ iptr,
@@ -709,10 +750,27 @@ void assemble_ctx(stokes_ctx* c) {
   build_sell(P2full, c->h_int2nat, c->h_nat2int, nullptr, 1, c->sA);
   build_sell(Bfull, p1_rows, c->h_nat2int, nullptr, D, c->sB);
   {
-    HostCsr BT;
+    HostCsr BT, XLpat;
     std::vector<int64_t> tsrc;
     transpose_pattern(Bfull, BT, tsrc);
     build_sell(BT, c->h_int2nat, p1_ident, &tsrc, D, c->sBt);
+    // B_I Lambda_V^-1 B_I^T: shared interior P2 columns only
+    product_pattern(Bfull, BT, c->h_nat2int, XLpat);
+    up_csr(XLpat, c->xl);
+    c->XL_csr.alloc(c->xl.nnz * sizeof(double));
+    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((m.n_p1 + 3) / 4, 65535));
+    if (D == 3)
+      hipLaunchKernelGGL(k_gather_xl<3>, dim3(nb), dim3(kBlock), 0, c->stream, m.n_p1, c->bfull.rowptr.as<int32_t>(),
+                         c->bfull.cols.as<int32_t>(), c->B_full.as<double>(), c->lam_full.as<double>(),
+                         c->nat2int.as<int32_t>(), c->xl.rowptr.as<int32_t>(), c->xl.cols.as<int32_t>(),
+                         c->XL_csr.as<double>());
+    else
+      hipLaunchKernelGGL(k_gather_xl<2>, dim3(nb), dim3(kBlock), 0, c->stream, m.n_p1, c->bfull.rowptr.as<int32_t>(),
+                         c->bfull.cols.as<int32_t>(), c->B_full.as<double>(), c->lam_full.as<double>(),
+                         c->nat2int.as<int32_t>(), c->xl.rowptr.as<int32_t>(), c->xl.cols.as<int32_t>(),
+                         c->XL_csr.as<double>());
+    HIP_CHECK(hipGetLastError());
+    build_sell(XLpat, p1_rows, p1_ident, nullptr, 1, c->sX);
   }
   build_sell(P1, p1_rows, p1_ident, nullptr, 1, c->sQ);
 
@@ -729,6 +787,7 @@ void assemble_ctx(stokes_ctx* c) {
   fill(c->sQ, c->MQ64, 1.0, c->MQ_csr, 0.0, nullptr);
   fill(c->sQ, c->LQ64, 1.0, c->LQ_csr, 0.0, nullptr);
   fill(c->sQ, c->XQ64, 1.0, c->MQ_csr, 1.0, &c->LQ_csr);
+  fill(c->sX, c->XL64, 1.0, c->XL_csr, 0.0, nullptr);
 
   auto dinv = [&](const Sell& S, const DevBuf& v, DevBuf& out) {
     out.alloc(S.nrows * sizeof(double));
@@ -764,6 +823,7 @@ void assemble_ctx(stokes_ctx* c) {
   to32(c->MQ64, c->MQ32, c->sQ.nnz_pad);
   to32(c->LQ64, c->LQ32, c->sQ.nnz_pad);
   to32(c->XQ64, c->XQ32, c->sQ.nnz_pad);
+  to32(c->XL64, c->XL32, c->sX.nnz_pad);
   to32(c->dA64, c->dA32, c->n_int);
   to32(c->dMV64, c->dMV32, c->n_int);
   to32(c->dMQ64, c->dMQ32, m.n_p1);

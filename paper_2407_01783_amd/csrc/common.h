@@ -119,6 +119,8 @@ struct stokes_ctx {
 
   // full-numbering CSR matrices (assembly products)
   stokes::DevCsr p2full, bfull, p1;
+  stokes::DevCsr xl;              // P1 x P1 pattern of B_I Lambda_V^-1 B_I^T
+  stokes::DevBuf XL_csr;          // double [nnz xl]
   stokes::DevBuf M_full, L_full;  // double [nnz p2full]
   stokes::DevBuf B_full;          // double [nnz bfull][dim]
   stokes::DevBuf MQ_csr, LQ_csr;  // double [nnz p1]
@@ -134,12 +136,14 @@ struct stokes_ctx {
   stokes::Sell sB;   // P1 x interior, dim planes
   stokes::Sell sBt;  // interior x P1, dim planes
   stokes::Sell sQ;   // P1 x P1, scalar values
+  stokes::Sell sX;   // P1 x P1, B_I Lambda_V^-1 B_I^T (two-ring stencil)
   stokes::DevBuf A64, A32, MV64, MV32;       // values of A_II and M_II (SELL)
   stokes::DevBuf B64, B32, Bt64, Bt32;       // [nnz_pad][dim]
   stokes::DevBuf MQ64, MQ32, LQ64, LQ32, XQ64, XQ32;  // XQ = M_Q + L_Q
   stokes::DevBuf dA64, dA32, dMV64, dMV32;   // inverse diagonals (interior)
   stokes::DevBuf dMQ64, dMQ32, dXQ64, dXQ32, dLQ64, dLQ32;
   stokes::DevBuf lamInv64, lamInv32;         // 1 / Lambda_V on interior nodes
+  stokes::DevBuf XL64, XL32;                 // values of B_I Lambda_V^-1 B_I^T (SELL sX)
   stokes::DevBuf mQ;                         // M_Q 1 (double, n_p1)
   double mQ_sum = 0;
 

@@ -265,4 +265,36 @@ void transpose_pattern(const HostCsr& in, HostCsr& out, std::vector<int64_t>& sr
     }
 }
 
+void product_pattern(const HostCsr& A, const HostCsr& At, const std::vector<int32_t>& mid_keep, HostCsr& out) {
+  out.nrows = A.nrows;
+  out.ncols = A.nrows;
+  out.rowptr.assign(A.nrows + 1, 0);
+  auto gather = [&](int64_t r, std::vector<int32_t>& buf) {
+    buf.clear();
+    for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) {
+      const int32_t j = A.cols[k];
+      if (mid_keep[j] < 0) continue;
+      for (int64_t t = At.rowptr[j]; t < At.rowptr[j + 1]; ++t) buf.push_back(At.cols[t]);
+    }
+    std::sort(buf.begin(), buf.end());
+    buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+  };
+  parallel_for(A.nrows, [&](int64_t b, int64_t e) {
+    std::vector<int32_t> buf;
+    for (int64_t r = b; r < e; ++r) {
+      gather(r, buf);
+      out.rowptr[r + 1] = static_cast<int64_t>(buf.size());
+    }
+  });
+  for (int64_t r = 0; r < A.nrows; ++r) out.rowptr[r + 1] += out.rowptr[r];
+  out.cols.assign(out.rowptr[A.nrows], 0);
+  parallel_for(A.nrows, [&](int64_t b, int64_t e) {
+    std::vector<int32_t> buf;
+    for (int64_t r = b; r < e; ++r) {
+      gather(r, buf);
+      std::copy(buf.begin(), buf.end(), out.cols.begin() + out.rowptr[r]);
+    }
+  });
+}
+
 }  // namespace stokes

@@ -53,6 +53,11 @@ void restrict_pattern(const HostCsr& in, const std::vector<int32_t>& row_map, in
 // Transpose of a pattern; src[k] = index of the transposed entry in `in`.
 void transpose_pattern(const HostCsr& in, HostCsr& out, std::vector<int64_t>& src);
 
+// Pattern of A A^T through the middle index: row r of the output holds every
+// row s of A that shares a kept column j (mid_keep[j] >= 0) with row r.
+// At is the transpose pattern of A.  Rows come out sorted.
+void product_pattern(const HostCsr& A, const HostCsr& At, const std::vector<int32_t>& mid_keep, HostCsr& out);
+
 // Incidence node -> (simplex << 4 | local index) for the node table
 // nodes[e][0..nl), as CSR over n_nodes.
 void incidence(const std::vector<int32_t>& nodes, int nl, int64_t n_e, int64_t n_nodes,

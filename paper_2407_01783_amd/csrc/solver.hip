@@ -317,9 +317,7 @@ class Engine {
   // t = X z for the Cahouet-Chabard family
   void x_apply(const T* z, T* t) {
     if (o_.schur_pc == STOKES_CC_LUMPED) {
-      T* tu = buf("x_tu", nu());
-      ops::Btmul<T>(c_, nrb_, z, ops::pick<T>(c_->lamInv64, c_->lamInv32), tu, (T)1, nullptr, (T)0);
-      ops::Bmul<T>(c_, nrb_, tu, t, (T)1, nullptr, (T)0);
+      ops::spmv<T>(c_, c_->sX, ops::pick<T>(c_->XL64, c_->XL32), nrb_, z, t, (T)1, nullptr, (T)0);
     } else if (o_.schur_pc == STOKES_CC_MASS) {
       T* tu = buf("x_tu", nu());
       T* yu = buf("x_yu", nu());
@@ -346,6 +344,9 @@ class Engine {
     if (o_.schur_pc == STOKES_CC_LAPLACE) {
       op.S = &c_->sQ;
       opvals = ops::pick<T>(c_->LQ64, c_->LQ32);
+    } else if (o_.schur_pc == STOKES_CC_LUMPED) {
+      op.S = &c_->sX;  // B_I Lambda_V^-1 B_I^T assembled at setup
+      opvals = ops::pick<T>(c_->XL64, c_->XL32);
     } else {
       op.apply = [this](const T* z, T* t) { x_apply(z, t); };
     }

@@ -32,10 +32,10 @@ class StokesProblem:
         check(self.lib.stokes_assemble(ctypes.byref(self.prob), _stream_handle(), ctypes.byref(h)),
               "stokes_assemble")
         self.ctx = h
-        s = (ctypes.c_int64 * 10)()
+        s = (ctypes.c_int64 * 12)()
         check(self.lib.stokes_query(self.ctx, s), "stokes_query")
         (self.n_p2, self.n_p1, self.n_free_nodes, self.nnz_A, self.nnz_B, self.nnz_Q, self.n_elem, self.dim,
-         self.nnz_full, self.nnz_Bfull) = [int(v) for v in s]
+         self.nnz_full, self.nnz_Bfull, self.nnz_X, _) = [int(v) for v in s]
         self.n_loc = 10 if self.dim == 3 else 6
 
     def __del__(self):
@@ -79,6 +79,8 @@ class StokesProblem:
             nrows, nnz = self.n_p1, self.nnz_Bfull
         elif which in (5, 6):
             nrows, nnz = self.n_p1, self.nnz_Q
+        elif which == 9:
+            nrows, nnz = self.n_p1, self.nnz_X
         else:
             nrows, nnz = self.n_free_nodes, self.nnz_A
         rp = np.empty(nrows + 1, dtype=np.int32)
@@ -158,7 +160,7 @@ class StokesProblem:
         """One assembled operator (see stokes_apply) on caller-layout tensors."""
         x = torch.as_tensor(x, dtype=torch.float64, device=self.device).contiguous()
         nu, npr = nrhs * self.dim * self.n_p2, nrhs * self.n_p1
-        out_len = {0: nu, 1: npr, 2: nu, 3: npr, 4: npr, 5: nu + npr, 6: npr}[op]
+        out_len = {0: nu, 1: npr, 2: nu, 3: npr, 4: npr, 5: nu + npr, 6: npr, 7: npr}[op]
         y = torch.empty(out_len, dtype=torch.float64, device=self.device)
         check(self.lib.stokes_set_stream(self.ctx, _stream_handle()))
         check(self.lib.stokes_apply(self.ctx, int(op), int(precision), int(nrhs), ptr(x), ptr(y)), "stokes_apply")

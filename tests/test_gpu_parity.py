@@ -57,6 +57,19 @@ def test_assembled_matrices_match_oracle(gpu_lib, dim, n, jit):
     assert np.abs(lam - S.mats.Lam).max() <= 1e-14 * np.abs(S.mats.Lam).max()
 
 
+@pytest.mark.parametrize("dim,n", [(2, 5), (3, 3), (3, 4)])
+def test_lumped_pressure_operator_matches_oracle(gpu_lib, dim, n):
+    """B_I Lambda_V^-1 B_I^T assembled on the device == the oracle's product."""
+    P, S = _problem(dim, n, seed=2), _oracle(dim, n, seed=2)
+    rp, cols, vals = P.export_csr(9)
+    X = sp.csr_matrix((vals, cols, rp), shape=(S.np1, S.np1)).toarray()
+    lam_inv = sp.diags(1.0 / S.mats.Lam[S.I])
+    ref = sum(S.B_I[c] @ lam_inv @ S.B_I[c].T for c in range(dim)).toarray()
+    assert np.abs(X - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.all(np.diff(rp) > 0) and np.all(np.abs(ref)[X == 0] <= 1e-13 * np.abs(ref).max())
+    assert np.array_equal(X, X.T)
+
+
 def test_mass_bounds_are_element_constants(gpu_lib):
     P = _problem(3, 3)
     b = P.bounds()
@@ -104,6 +117,9 @@ def _ops_reference(S, x_u, x_p):
             out[2][r, c, I] = S.B_I[c].T @ x_p[r]
     out[3] = np.stack([S.mats.MQ @ x_p[r] for r in range(x_p.shape[0])])
     out[4] = np.stack([S.mats.LQ @ x_p[r] for r in range(x_p.shape[0])])
+    lam_inv = 1.0 / S.mats.Lam[I]
+    out[7] = np.stack([sum(S.B_I[c] @ (lam_inv * (S.B_I[c].T @ x_p[r])) for c in range(d))
+                       for r in range(x_p.shape[0])])
     return out
 
 
@@ -115,8 +131,8 @@ def test_operator_actions_match_oracle(gpu_lib, dim, n, nrhs):
     x_u = rng.standard_normal((nrhs, dim, P.n_p2))
     x_p = rng.standard_normal((nrhs, P.n_p1))
     ref = _ops_reference(S, x_u, x_p)
-    for op in range(5):
-        x = x_p if op in (2, 3, 4) else x_u
+    for op in (0, 1, 2, 3, 4, 7):
+        x = x_p if op in (2, 3, 4, 7) else x_u
         for prec, tol in ((0, 1e-13), (1, 2e-6)):
             y = P.apply(op, torch.tensor(x.ravel(), device="cuda"), precision=prec, nrhs=nrhs).cpu().numpy()
             assert _rel(y, ref[op]) <= tol, (op, prec, _rel(y, ref[op]))
