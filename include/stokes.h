@@ -192,6 +192,8 @@ stokes_status stokes_solve_adjoint(stokes_ctx* ctx, int32_t nrhs, const double* 
  * V-cycle for eps M_Q + L_Q (eps = 1), the pressure preconditioner of
  * Sec. 4.2 (x, y pressure-shaped); 7 = y = B_I Lambda_V^-1 B_I^T x, the
  * lumped-mass pressure operator of Sec. 4.3, assembled explicitly (x, y
+ * pressure-shaped); 8 = one V-cycle of the Galerkin multigrid hierarchy of
+ * B_I Lambda_V^-1 B_I^T + M_Q, the preconditioner of that operator (x, y
  * pressure-shaped). */
 stokes_status stokes_apply(stokes_ctx* ctx, int32_t op, int32_t precision, int32_t nrhs,
                            const double* x, double* y);

@@ -421,6 +421,9 @@ stokes_status stokes_assemble(const stokes_problem* prob, void* hip_stream, stok
     c->user_stream = static_cast<hipStream_t>(hip_stream);
     if (const char* e = std::getenv("STOKES_GRAPHS")) c->use_graphs = std::atoi(e) != 0;
     if (const char* e = std::getenv("STOKES_CG_CHECK")) c->cg_check_every = std::max(1, std::atoi(e));
+    if (const char* e = std::getenv("STOKES_MGX")) c->use_mgx = std::atoi(e) != 0;
+    if (const char* e = std::getenv("STOKES_MG_DEGREE")) c->mg_smooth_degree = std::max(1, std::atoi(e));
+    if (const char* e = std::getenv("STOKES_MG_RATIO")) c->mg_smooth_ratio = std::max(1.5, std::atof(e));
     HIP_CHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     HIP_CHECK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
     HIP_CHECK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
@@ -535,7 +538,7 @@ stokes_status stokes_solve_adjoint(stokes_ctx* c, int32_t nrhs, const double* u,
 stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t nrhs, const double* x, double* y) {
   return guard([&]() -> stokes_status {
     if (!c) throw Error(STOKES_ERR_ARG, "ctx is NULL");
-    if (op < 0 || op > 7) throw Error(STOKES_ERR_ARG, "op must be in [0, 7]");
+    if (op < 0 || op > 8) throw Error(STOKES_ERR_ARG, "op must be in [0, 8]");
     if (precision != 0 && precision != 1) throw Error(STOKES_ERR_ARG, "precision must be 0 or 1");
     if (nrhs < 1) throw Error(STOKES_ERR_ARG, "nrhs must be >= 1");
     if (!x || !y) throw Error(STOKES_ERR_ARG, "x and y must not be NULL");
@@ -556,7 +559,7 @@ stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t
       float* yuf = static_cast<float*>(c->workspace("ap_yuf", nu * sizeof(float)));
       float* ypf = static_cast<float*>(c->workspace("ap_ypf", np * sizeof(float)));
       const bool in_vel = op == 0 || op == 1 || op == 5;
-      const bool in_p = op == 2 || op == 3 || op == 4 || op == 5 || op == 6 || op == 7;
+      const bool in_p = op == 2 || op == 3 || op == 4 || op == 5 || op == 6 || op == 7 || op == 8;
       const bool out_vel = op == 0 || op == 2 || op == 5;
       const double* xv = x + vo;
       const double* xpp = op == 5 ? x + tot_u + po : x + po;
@@ -575,7 +578,8 @@ stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t
           case 2: ops::Btmul<T>(c, nrb, XP, nullptr, YU, (T)1, nullptr, (T)0); break;
           case 3: ops::spmv<T>(c, c->sQ, ops::pick<T>(c->MQ64, c->MQ32), nrb, XP, YP, (T)1, nullptr, (T)0); break;
           case 4: ops::spmv<T>(c, c->sQ, ops::pick<T>(c->LQ64, c->LQ32), nrb, XP, YP, (T)1, nullptr, (T)0); break;
-          case 6: mg_vcycle<T>(c, nrb, XP, YP, 0); break;
+          case 6: mg_vcycle<T>(c, c->mgq, nrb, XP, YP, 0); break;
+          case 8: mg_vcycle<T>(c, c->mgx, nrb, XP, YP, 0); break;
           case 7: ops::spmv<T>(c, c->sX, ops::pick<T>(c->XL64, c->XL32), nrb, XP, YP, (T)1, nullptr, (T)0); break;
           default:
             ops::momentum<T>(c, nrb, XU, XP, nullptr, YU, (T)1, nullptr);

@@ -898,6 +898,96 @@ void assemble_p1(stokes_ctx* c, const HostMesh& m, MgLevel& L) {
   HIP_CHECK(hipStreamSynchronize(c->stream));
 }
 
+namespace {
+
+// Device copy of one hierarchy level from a host CSR operator.
+void upload_level(stokes_ctx* c, const HostCsr& A, const std::vector<double>& av, MgLevel& L) {
+  const int64_t nr = A.nrows;
+  std::vector<int32_t> rows(nr);
+  std::iota(rows.begin(), rows.end(), 0);
+  build_sell(A, rows, rows, nullptr, 1, L.S);
+  L.nrows = nr;
+  DevBuf dv;
+  upload(dv, av);
+  L.v64.alloc(L.S.nnz_pad * sizeof(double));
+  launch(c, L.S.nnz_pad, k_fill, L.S.nnz_pad, L.S.src.as<int32_t>(), 1, 1.0, dv.as<double>(), 0.0, nullptr,
+         L.v64.as<double>());
+  L.d64.alloc(nr * sizeof(double));
+  launch(c, nr, k_dinv, nr, L.S.slice_ptr.as<int64_t>(), L.S.cols.as<int32_t>(), L.v64.as<double>(),
+         L.d64.as<double>());
+  L.v32.alloc(L.S.nnz_pad * sizeof(float));
+  L.d32.alloc(nr * sizeof(float));
+  launch(c, L.S.nnz_pad, k_cast<double, float>, L.S.nnz_pad, L.v64.as<double>(), L.v32.as<float>());
+  launch(c, nr, k_cast<double, float>, nr, L.d64.as<double>(), L.d32.as<float>());
+  double lo, hi, g;
+  lanczos_bounds(c, L.S, L.v64.as<double>(), L.d64.as<double>(), std::min<int>(40, (int)nr), lo, hi, g);
+  L.bf.hi = std::min(g, 1.1 * hi);
+  L.bf.lo = 0.9 * lo;
+  L.bs.hi = L.bf.hi;
+  L.bs.lo = L.bf.hi / c->mg_smooth_ratio;
+  HIP_CHECK(hipStreamSynchronize(c->stream));  // dv is freed on return
+}
+
+void download_csr(stokes_ctx* c, const DevCsr& P, const DevBuf& v, HostCsr& h, std::vector<double>& hv) {
+  std::vector<int32_t> rp(P.nrows + 1);
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+  HIP_CHECK(hipMemcpy(rp.data(), P.rowptr.p, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  h.nrows = h.ncols = P.nrows;
+  h.rowptr.assign(rp.begin(), rp.end());
+  h.cols.resize(P.nnz);
+  hv.resize(P.nnz);
+  HIP_CHECK(hipMemcpy(h.cols.data(), P.cols.p, P.nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIP_CHECK(hipMemcpy(hv.data(), v.p, P.nnz * sizeof(double), hipMemcpyDeviceToHost));
+}
+
+}  // namespace
+
+void assemble_galerkin(stokes_ctx* c, MgHier& H) {
+  H.lv.clear();
+  H.own.clear();
+  H.dense_n = 0;
+  const int D = c->dim;
+  // level 0: B_I Lambda_V^-1 B_I^T + M_Q on the union of the two patterns
+  HostCsr X, Q, A;
+  std::vector<double> xv, qv, av;
+  download_csr(c, c->xl, c->XL_csr, X, xv);
+  download_csr(c, c->p1, c->MQ_csr, Q, qv);
+  A.nrows = A.ncols = X.nrows;
+  A.rowptr.assign(X.nrows + 1, 0);
+  for (int64_t r = 0; r < X.nrows; ++r) {
+    int64_t i = X.rowptr[r], j = Q.rowptr[r];
+    const int64_t ie = X.rowptr[r + 1], je = Q.rowptr[r + 1];
+    while (i < ie || j < je) {
+      if (j >= je || (i < ie && X.cols[i] < Q.cols[j])) {
+        A.cols.push_back(X.cols[i]);
+        av.push_back(xv[i++]);
+      } else if (i >= ie || Q.cols[j] < X.cols[i]) {
+        A.cols.push_back(Q.cols[j]);
+        av.push_back(qv[j++]);
+      } else {
+        A.cols.push_back(X.cols[i]);
+        av.push_back(xv[i++] + qv[j++]);
+      }
+    }
+    A.rowptr[r + 1] = static_cast<int64_t>(A.cols.size());
+  }
+  int n = c->mesh.n;
+  for (;;) {
+    auto L = std::make_unique<MgLevel>();
+    L->n = n;
+    upload_level(c, A, av, *L);
+    H.lv.push_back({&L->S, &L->v64, &L->v32, &L->d64, &L->d32, &L->bs, &L->bf, n});
+    H.own.push_back(std::move(L));
+    if (!(n % 2 == 0 && n > 2 && ipow(n + 1, D) > c->mg_dense_max)) break;
+    HostCsr Ac;
+    std::vector<double> acv;
+    galerkin_p1(D, n, n / 2, A, av, Ac, acv);
+    A = std::move(Ac);
+    av = std::move(acv);
+    n /= 2;
+  }
+}
+
 void estimate_bounds(stokes_ctx* c) {
   const int steps = 40;
   double lo, hi, g;

@@ -86,14 +86,29 @@ constexpr int kMaxSys = 24;   // systems per batched solve (dim * rhs)
 constexpr int kMaxBlocks = 2048;
 constexpr int kBlock = 256;
 
-// One coarse level of the pressure multigrid hierarchy (M_Q + L_Q).
+// One level of a pressure multigrid hierarchy, owned by the hierarchy.
 struct MgLevel {
   int n = 0;            // cells per side
   int64_t nrows = 0;    // (n + 1)^dim vertices
   Sell S;               // SELL pattern of the level operator
-  DevBuf v64, v32;      // values of M_Q + L_Q
+  DevBuf v64, v32;      // operator values
   DevBuf d64, d32;      // inverse diagonal
   Bounds bs, bf;        // smoothing interval, full spectrum
+};
+
+// A multigrid hierarchy on the nested Kuhn meshes n, n/2, ...  Level views
+// point either at context-owned operators or at levels in `own`.
+struct MgHier {
+  struct View {
+    const Sell* S;
+    const DevBuf *v64, *v32, *d64, *d32;
+    const Bounds *bs, *bf;
+    int n;
+  };
+  std::vector<View> lv;
+  std::vector<std::unique_ptr<MgLevel>> own;
+  int64_t dense_n = 0;        // > 0: the coarsest level is solved by a dense inverse
+  DevBuf cinv64, cinv32;      // [n][n] inverse of the coarsest operator
 };
 
 // Per-solver device scalars (one set per Krylov instance).
@@ -149,13 +164,14 @@ struct stokes_ctx {
 
   stokes::Bounds bA, bMV, bMQ, bXQ, bLQ, bXQ_smooth;
 
-  // pressure multigrid (coarse levels; level 0 is sQ / XQ)
-  std::vector<std::unique_ptr<stokes::MgLevel>> mg;
+  // pressure multigrid: mgq on eps M_Q + L_Q (rediscretised coarse levels,
+  // level 0 is sQ / XQ); mgx on B_I Lambda_V^-1 B_I^T + M_Q with Galerkin
+  // coarse levels P^T A P
+  stokes::MgHier mgq, mgx;
   int mg_smooth_degree = 3, mg_coarse_degree = 24;
-  int64_t mg_dense_n = 0;               // > 0: coarsest level solved by a dense inverse
   int64_t mg_dense_max = 1500;          // largest level solved densely
-  stokes::DevBuf mg_cinv64, mg_cinv32;  // [n][n] inverse of the coarsest operator
   double mg_smooth_ratio = 10.0;
+  int use_mgx = 1;                      // lumped CC: precondition with mgx (0: mgq)
 
   stokes::RedScratch red;
   stokes::DevBuf scal;  // Scalars pool

@@ -297,4 +297,74 @@ void product_pattern(const HostCsr& A, const HostCsr& At, const std::vector<int3
   });
 }
 
+void galerkin_p1(int dim, int nf, int nc, const HostCsr& A, const std::vector<double>& av, HostCsr& out,
+                 std::vector<double>& ov) {
+  const int64_t ncv = ipow(nc + 1, dim), nfv1 = nf + 1, ncv1 = nc + 1;
+  std::vector<std::vector<std::pair<int32_t, double>>> rows(ncv);
+  parallel_for(ncv, [&](int64_t b, int64_t e) {
+    std::vector<std::pair<int32_t, double>> acc;
+    for (int64_t I = b; I < e; ++I) {
+      acc.clear();
+      int G[3] = {0, 0, 0};
+      int64_t rem = I;
+      for (int d = 0; d < dim; ++d) {
+        G[d] = static_cast<int>(rem % ncv1);
+        rem /= ncv1;
+      }
+      // fine rows f with P[f, I] != 0: f = 2G (weight 1) and 2G +- s (weight 1/2)
+      for (int s = 0; s < (1 << dim); ++s) {
+        for (int sg = 1; sg >= -1; sg -= 2) {
+          if (s == 0 && sg < 0) continue;
+          int64_t f = 0, st = 1;
+          bool ok = true;
+          for (int d = 0; d < dim; ++d, st *= nfv1) {
+            const int g = 2 * G[d] + sg * ((s >> d) & 1);
+            ok = ok && g >= 0 && g <= nf;
+            f += int64_t(g) * st;
+          }
+          if (!ok) continue;
+          const double w = s == 0 ? 1.0 : 0.5;
+          for (int64_t k = A.rowptr[f]; k < A.rowptr[f + 1]; ++k) {
+            // column g of the fine level interpolates coarse vertices a and b
+            int64_t rg = A.cols[k], a = 0, bb = 0, sc = 1;
+            for (int d = 0; d < dim; ++d, sc *= ncv1) {
+              const int64_t fg = rg % nfv1;
+              rg /= nfv1;
+              const int64_t par = fg & 1;
+              a += ((fg - par) / 2) * sc;
+              bb += ((fg + par) / 2) * sc;
+            }
+            const double v = 0.5 * w * av[k];
+            acc.emplace_back(static_cast<int32_t>(a), v);
+            acc.emplace_back(static_cast<int32_t>(bb), v);
+          }
+        }
+      }
+      std::stable_sort(acc.begin(), acc.end(),
+                       [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
+                         return x.first < y.first;
+                       });
+      auto& row = rows[I];
+      row.clear();
+      for (const auto& pr : acc) {
+        if (!row.empty() && row.back().first == pr.first) row.back().second += pr.second;
+        else row.push_back(pr);
+      }
+    }
+  });
+  out.nrows = out.ncols = ncv;
+  out.rowptr.assign(ncv + 1, 0);
+  for (int64_t I = 0; I < ncv; ++I) out.rowptr[I + 1] = out.rowptr[I] + static_cast<int64_t>(rows[I].size());
+  out.cols.resize(out.rowptr[ncv]);
+  ov.resize(out.rowptr[ncv]);
+  for (int64_t I = 0; I < ncv; ++I) {
+    int64_t o = out.rowptr[I];
+    for (const auto& pr : rows[I]) {
+      out.cols[o] = pr.first;
+      ov[o] = pr.second;
+      ++o;
+    }
+  }
+}
+
 }  // namespace stokes

@@ -58,6 +58,14 @@ void transpose_pattern(const HostCsr& in, HostCsr& out, std::vector<int64_t>& sr
 // At is the transpose pattern of A.  Rows come out sorted.
 void product_pattern(const HostCsr& A, const HostCsr& At, const std::vector<int32_t>& mid_keep, HostCsr& out);
 
+// Galerkin coarse operator P^T A P on the Kuhn hierarchy nf -> nc = nf / 2
+// for the P1 interpolation that puts fine vertex f at the midpoint of the
+// coarse edge (f - s, f + s) / 2, s = f mod 2 componentwise.  A is a P1 x P1
+// operator on the (nf+1)^dim fine vertices; each output entry is summed in a
+// fixed order.
+void galerkin_p1(int dim, int nf, int nc, const HostCsr& A, const std::vector<double>& av, HostCsr& out,
+                 std::vector<double>& ov);
+
 // Incidence node -> (simplex << 4 | local index) for the node table
 // nodes[e][0..nl), as CSR over n_nodes.
 void incidence(const std::vector<int32_t>& nodes, int nl, int64_t n_e, int64_t n_nodes,

@@ -194,13 +194,40 @@ T* wsp(stokes_ctx* c, const std::string& name, int64_t n) {
 
 }  // namespace
 
-// Build the coarse levels (called once per context after assembly).
+// Dense inverse of the coarsest level when it is small enough.
+static void dense_coarsest(stokes_ctx* c, MgHier& H) {
+  const MgHier::View& V = H.lv.back();
+  const Sell& S = *V.S;
+  const int64_t nr = S.nrows;
+  H.dense_n = 0;
+  if (nr > c->mg_dense_max) return;
+  std::vector<int64_t> sp(S.nslices + 1);
+  std::vector<int32_t> cols(S.nnz_pad);
+  std::vector<double> vals(S.nnz_pad);
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+  HIP_CHECK(hipMemcpy(sp.data(), S.slice_ptr.p, sp.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  HIP_CHECK(hipMemcpy(cols.data(), S.cols.p, cols.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIP_CHECK(hipMemcpy(vals.data(), V.v64->p, vals.size() * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<double> A(nr * nr, 0.0);
+  for (int64_t r = 0; r < nr; ++r)
+    for (int64_t k = sp[r / 64] + r % 64; k < sp[r / 64 + 1]; k += 64) A[r * nr + cols[k]] += vals[k];
+  const std::vector<double> inv = spd_inverse(A, nr);
+  std::vector<float> inv32(inv.begin(), inv.end());
+  upload(H.cinv64, inv);
+  upload(H.cinv32, inv32);
+  H.dense_n = nr;
+}
+
+// Build both hierarchies (called once per context after assembly).
 void build_mg(stokes_ctx* c) {
-  c->mg.clear();
+  MgHier& H = c->mgq;
+  H.lv.clear();
+  H.own.clear();
   const HostMesh& fm = c->mesh;
   const int D = fm.dim;
   int n = fm.n;
   int stride = 1;
+  H.lv.push_back({&c->sQ, &c->XQ64, &c->XQ32, &c->dXQ64, &c->dXQ32, &c->bXQ_smooth, &c->bXQ, n});
   // coarsen while the current level is too large for the dense coarse solve
   while (n % 2 == 0 && n > 2 && ipow(n + 1, D) > c->mg_dense_max) {
     n /= 2;
@@ -221,40 +248,23 @@ void build_mg(stokes_ctx* c) {
     }
     L->nrows = m.n_p1;
     assemble_p1(c, m, *L);
-    c->mg.push_back(std::move(L));
+    H.lv.push_back({&L->S, &L->v64, &L->v32, &L->d64, &L->d32, &L->bs, &L->bf, n});
+    H.own.push_back(std::move(L));
   }
-  // exact solve on a small coarsest level
-  const Sell& S = c->mg.empty() ? c->sQ : c->mg.back()->S;
-  const DevBuf& V = c->mg.empty() ? c->XQ64 : c->mg.back()->v64;
-  const int64_t nr = S.nrows;
-  c->mg_dense_n = 0;
-  if (nr <= c->mg_dense_max) {
-    std::vector<int64_t> sp(S.nslices + 1);
-    std::vector<int32_t> cols(S.nnz_pad);
-    std::vector<double> vals(S.nnz_pad);
-    HIP_CHECK(hipMemcpy(sp.data(), S.slice_ptr.p, sp.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
-    HIP_CHECK(hipMemcpy(cols.data(), S.cols.p, cols.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-    HIP_CHECK(hipMemcpy(vals.data(), V.p, vals.size() * sizeof(double), hipMemcpyDeviceToHost));
-    std::vector<double> A(nr * nr, 0.0);
-    for (int64_t r = 0; r < nr; ++r)
-      for (int64_t k = sp[r / 64] + r % 64; k < sp[r / 64 + 1]; k += 64) A[r * nr + cols[k]] += vals[k];
-    const std::vector<double> inv = spd_inverse(A, nr);
-    std::vector<float> inv32(inv.begin(), inv.end());
-    upload(c->mg_cinv64, inv);
-    upload(c->mg_cinv32, inv32);
-    c->mg_dense_n = nr;
-  }
+  dense_coarsest(c, H);
+  assemble_galerkin(c, c->mgx);
+  dense_coarsest(c, c->mgx);
 }
 
-// e = V-cycle(r) for M_Q + L_Q, starting at level `lv` (0 = the full mesh).
 template <class T>
-void mg_vcycle(stokes_ctx* c, int nrb, const T* r, T* e, int lv) {
-  const int nlev = static_cast<int>(c->mg.size()) + 1;
-  const Sell& S = lv == 0 ? c->sQ : c->mg[lv - 1]->S;
-  const T* vals = lv == 0 ? ops::pick<T>(c->XQ64, c->XQ32) : ops::pick<T>(c->mg[lv - 1]->v64, c->mg[lv - 1]->v32);
-  const T* dinv = lv == 0 ? ops::pick<T>(c->dXQ64, c->dXQ32) : ops::pick<T>(c->mg[lv - 1]->d64, c->mg[lv - 1]->d32);
-  const Bounds& bs = lv == 0 ? c->bXQ_smooth : c->mg[lv - 1]->bs;
-  const Bounds& bf = lv == 0 ? c->bXQ : c->mg[lv - 1]->bf;
+void mg_vcycle(stokes_ctx* c, const MgHier& H, int nrb, const T* r, T* e, int lv) {
+  const int nlev = static_cast<int>(H.lv.size());
+  const MgHier::View& V = H.lv[lv];
+  const Sell& S = *V.S;
+  const T* vals = ops::pick<T>(*V.v64, *V.v32);
+  const T* dinv = ops::pick<T>(*V.d64, *V.d32);
+  const Bounds& bs = *V.bs;
+  const Bounds& bf = *V.bf;
   const int64_t nr = S.nrows, n = nr * nrb;
   const std::string tag = "mg" + std::to_string(lv);
   T* d0 = wsp<T>(c, tag + "_d0", n);
@@ -277,8 +287,8 @@ void mg_vcycle(stokes_ctx* c, int nrb, const T* r, T* e, int lv) {
     }
   };
   if (lv == nlev - 1) {  // coarsest: dense inverse, or a polynomial over the whole spectrum
-    if (c->mg_dense_n == nr) {
-      const T* Ci = ops::pick<T>(c->mg_cinv64, c->mg_cinv32);
+    if (H.dense_n == nr) {
+      const T* Ci = ops::pick<T>(H.cinv64, H.cinv32);
       dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
         constexpr int N = decltype(Nc)::value;
         (void)Dc;
@@ -293,20 +303,20 @@ void mg_vcycle(stokes_ctx* c, int nrb, const T* r, T* e, int lv) {
   }
   const int nu = c->mg_smooth_degree;
   T* t = wsp<T>(c, tag + "_t", n);
-  const MgLevel& C = *c->mg[lv];
-  const int nf = lv == 0 ? c->mesh.n : c->mg[lv - 1]->n;
-  const int64_t ncn = C.nrows * nrb;
+  const MgHier::View& C = H.lv[lv + 1];
+  const int nf = V.n;
+  const int64_t ncn = C.S->nrows * nrb;
   T* rc = wsp<T>(c, "mg" + std::to_string(lv + 1) + "_rc", ncn);
   T* ec = wsp<T>(c, "mg" + std::to_string(lv + 1) + "_ec", ncn);
   cheb(bs, nu, r, e, 0);                                                // pre-smoothing from zero
   ops::spmv<T>(c, S, vals, nrb, e, t, (T)-1, r, (T)1);                 // t = r - X e
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
     constexpr int DD = decltype(Dc)::value, N = decltype(Nc)::value;
-    hipLaunchKernelGGL((k_restrict<T, DD, N>), dim3(ops::grid_for(C.nrows)), dim3(kBlock), 0, c->stream, nf, C.n,
+    hipLaunchKernelGGL((k_restrict<T, DD, N>), dim3(ops::grid_for(C.S->nrows)), dim3(kBlock), 0, c->stream, nf, C.n,
                        (const T*)t, rc);
   });
   ops::check_launch();
-  mg_vcycle<T>(c, nrb, rc, ec, lv + 1);
+  mg_vcycle<T>(c, H, nrb, rc, ec, lv + 1);
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
     constexpr int DD = decltype(Dc)::value, N = decltype(Nc)::value;
     hipLaunchKernelGGL((k_prolong_add<T, DD, N>), dim3(ops::grid_for(nr)), dim3(kBlock), 0, c->stream, nf, C.n,
@@ -323,7 +333,7 @@ void mg_vcycle(stokes_ctx* c, int nrb, const T* r, T* e, int lv) {
   }
 }
 
-template void mg_vcycle<double>(stokes_ctx*, int, const double*, double*, int);
-template void mg_vcycle<float>(stokes_ctx*, int, const float*, float*, int);
+template void mg_vcycle<double>(stokes_ctx*, const MgHier&, int, const double*, double*, int);
+template void mg_vcycle<float>(stokes_ctx*, const MgHier&, int, const float*, float*, int);
 
 }  // namespace stokes

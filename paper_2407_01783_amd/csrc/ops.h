@@ -11,9 +11,12 @@ namespace stokes {
 void assemble_ctx(stokes_ctx* c);
 void assemble_p1(stokes_ctx* c, const HostMesh& m, MgLevel& L);
 void build_mg(stokes_ctx* c);
-// e = multigrid V-cycle for M_Q + L_Q applied to r (pressure layout)
+// Galerkin hierarchy on B_I Lambda_V^-1 B_I^T + M_Q (levels only; the dense
+// coarsest inverse is added by build_mg)
+void assemble_galerkin(stokes_ctx* c, MgHier& H);
+// e = one multigrid V-cycle of hierarchy H applied to r (pressure layout)
 template <class T>
-void mg_vcycle(stokes_ctx* c, int nrb, const T* r, T* e, int level = 0);
+void mg_vcycle(stokes_ctx* c, const MgHier& H, int nrb, const T* r, T* e, int level = 0);
 void estimate_bounds(stokes_ctx* c);
 void reform_A(stokes_ctx* c);
 void lanczos_bounds(stokes_ctx* c, const Sell& S, const double* vals, const double* dinv, int steps, double& rlo,

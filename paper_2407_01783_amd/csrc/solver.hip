@@ -334,9 +334,10 @@ class Engine {
   // mode: the approximation itself) is one multigrid V-cycle of eps M_Q + L_Q
   void x_solve(const T* b, T* x) {
     Prec pc{&c_->sQ, ops::pick<T>(c_->XQ64, c_->XQ32), ops::pick<T>(c_->dXQ64, c_->dXQ32), c_->bXQ, 1, {}};
-    pc.apply = [this](const T* r, T* z) { mg_vcycle<T>(c_, nrb_, r, z, 0); };
+    const MgHier& H = (o_.schur_pc == STOKES_CC_LUMPED && c_->use_mgx) ? c_->mgx : c_->mgq;
+    pc.apply = [this, &H](const T* r, T* z) { mg_vcycle<T>(c_, H, nrb_, r, z, 0); };
     if (o_.inner_mode == STOKES_INNER_FIXED) {
-      mg_vcycle<T>(c_, nrb_, b, x, 0);
+      mg_vcycle<T>(c_, H, nrb_, b, x, 0);
       return;
     }
     Op op;

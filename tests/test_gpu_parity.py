@@ -70,6 +70,46 @@ def test_lumped_pressure_operator_matches_oracle(gpu_lib, dim, n):
     assert np.array_equal(X, X.T)
 
 
+def _pressure_mg_operators(S):
+    lam_inv = sp.diags(1.0 / S.mats.Lam[S.I])
+    XL = sum(S.B_I[c] @ lam_inv @ S.B_I[c].T for c in range(S.d))
+    return {6: (S.mats.MQ + S.mats.LQ).tocsr(), 8: (XL + S.mats.MQ).tocsr()}
+
+
+def test_multigrid_single_level_is_exact_inverse(gpu_lib):
+    """With (n+1)^3 <= 1500 vertices the hierarchy is one dense level: the
+    V-cycle is the exact inverse of eps M_Q + L_Q (op 6) and of
+    B_I Lambda_V^-1 B_I^T + M_Q (op 8)."""
+    P, S = _problem(3, 8, seed=4), _oracle(3, 8, seed=4)
+    rng = np.random.default_rng(3)
+    r = rng.standard_normal(S.np1)
+    for op, A in _pressure_mg_operators(S).items():
+        y = P.apply(op, torch.tensor(r, device="cuda"), precision=0).cpu().numpy()
+        assert _rel(y, np.linalg.solve(A.toarray(), r)) <= 1e-10, op
+
+
+@pytest.mark.parametrize("n", [16, 24])
+def test_multigrid_vcycle_symmetric_and_contracting(gpu_lib, n):
+    """Several levels: the V-cycle is symmetric positive definite (it
+    preconditions CG) and, used as a stationary iteration on the oracle's
+    operator, reduces the residual by at least 2x per cycle."""
+    P, S = _problem(3, n, seed=4), _oracle(3, n, seed=4)
+    rng = np.random.default_rng(5)
+    u, v, b = rng.standard_normal((3, S.np1))
+    for op, A in _pressure_mg_operators(S).items():
+        V = lambda x: P.apply(op, torch.tensor(x, device="cuda"), precision=0).cpu().numpy()  # noqa: E731
+        Vu, Vv = V(u), V(v)
+        assert abs(u @ Vv - v @ Vu) <= 1e-12 * abs(u @ Vv), op
+        assert u @ Vu > 0 and v @ Vv > 0
+        x = np.zeros_like(b)
+        res = [np.linalg.norm(b)]
+        for _ in range(4):
+            x = x + V(b - A @ x)
+            res.append(np.linalg.norm(b - A @ x))
+        rates = np.array(res[1:]) / np.array(res[:-1])
+        assert rates.max() <= 0.5, (op, rates)
+
+
 def test_mass_bounds_are_element_constants(gpu_lib):
     P = _problem(3, 3)
     b = P.bounds()
