@@ -168,7 +168,7 @@ struct stokes_ctx {
   // level 0 is sQ / XQ); mgx on B_I Lambda_V^-1 B_I^T + M_Q with Galerkin
   // coarse levels P^T A P
   stokes::MgHier mgq, mgx;
-  int mg_smooth_degree = 3, mg_coarse_degree = 24;
+  int mg_smooth_degree = 2, mg_coarse_degree = 24;
   int64_t mg_dense_max = 1500;          // largest level solved densely
   double mg_smooth_ratio = 10.0;
   int use_mgx = 1;                      // lumped CC: precondition with mgx (0: mgq)
