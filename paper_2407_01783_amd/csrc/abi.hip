@@ -422,6 +422,7 @@ stokes_status stokes_assemble(const stokes_problem* prob, void* hip_stream, stok
     if (const char* e = std::getenv("STOKES_GRAPHS")) c->use_graphs = std::atoi(e) != 0;
     if (const char* e = std::getenv("STOKES_CG_CHECK")) c->cg_check_every = std::max(1, std::atoi(e));
     if (const char* e = std::getenv("STOKES_MGX")) c->use_mgx = std::atoi(e) != 0;
+    if (const char* e = std::getenv("STOKES_LANES")) c->force_lanes = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("STOKES_MG_DEGREE")) c->mg_smooth_degree = std::max(1, std::atoi(e));
     if (const char* e = std::getenv("STOKES_MG_RATIO")) c->mg_smooth_ratio = std::max(1.5, std::atof(e));
     HIP_CHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
@@ -586,6 +587,7 @@ stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t
             ops::Bmul<T>(c, nrb, XU, YP, (T)1, nullptr, (T)0);
         }
       };
+      ops::ensure_lanes(c, D * nrb, precision == 1);
       if (precision == 1) run(0, xuf, xpf, yuf, ypf);
       else run(0, xu, xp, yu, yp);
       if (precision == 1) {

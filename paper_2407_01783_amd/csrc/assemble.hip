@@ -14,6 +14,9 @@
 // walks the simplices incident to its node in a fixed order and adds each
 // element row into its sorted CSR slots.
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <functional>
 #include <numeric>
@@ -629,6 +632,17 @@ void lanczos_bounds(stokes_ctx* c, const Sell& S, const double* vals, const doub
 }
 
 void assemble_ctx(stokes_ctx* c) {
+  // STOKES_LOG >= 1: one stderr line per set-up phase with the elapsed time
+  const char* log_env = std::getenv("STOKES_LOG");
+  const bool log = log_env && std::atoi(log_env) >= 1;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto phase = [&](const char* what) {
+    if (!log) return;
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    std::fprintf(stderr, "[stokes] assemble %-28s %8.2f s\n", what, s);
+    std::fflush(stderr);
+  };
   upload_tables();
   const HostMesh& m = c->mesh;
   const int D = m.dim;
@@ -641,6 +655,7 @@ void assemble_ctx(stokes_ctx* c) {
   element_pattern(m.elems, nv, m.n_p1, m.elems, nv, m.n_p1, m.n_e, P1);
   if (P2full.rowptr.back() >= (int64_t(1) << 31) || Bfull.rowptr.back() * D >= (int64_t(1) << 31))
     throw Error(STOKES_ERR_UNSUPPORTED, "mesh too large for 32-bit sparse indices");
+  phase("host patterns");
 
   // internal numbering: interior nodes by decreasing interior row length
   std::vector<int32_t> interior;
@@ -743,6 +758,7 @@ void assemble_ctx(stokes_ctx* c) {
            c->lam_full.as<double>());
   }
 
+  phase("element gathers");
   // ---- SELL operators
   std::vector<int32_t> p1_rows(m.n_p1), p1_ident(m.n_p1);
   std::iota(p1_rows.begin(), p1_rows.end(), 0);
@@ -773,6 +789,7 @@ void assemble_ctx(stokes_ctx* c) {
     build_sell(XLpat, p1_rows, p1_ident, nullptr, 1, c->sX);
   }
   build_sell(P1, p1_rows, p1_ident, nullptr, 1, c->sQ);
+  phase("sliced-ELL layouts");
 
   auto fill = [&](const Sell& S, DevBuf& out, double a, const DevBuf& v1, double b, const DevBuf* v2) {
     out.alloc(S.nnz_pad * S.planes * sizeof(double));
@@ -835,8 +852,11 @@ void assemble_ctx(stokes_ctx* c) {
   const RefTables& tb = D == 3 ? g_tab3 : g_tab2;
   c->bMV = {tb.mass_lo, tb.mass_hi};
   c->bMQ = {tb.p1_lo, tb.p1_hi};
+  phase("values and FP32 copies");
   estimate_bounds(c);
+  phase("Chebyshev intervals");
   build_mg(c);
+  phase("multigrid hierarchies");
   HIP_CHECK(hipStreamSynchronize(c->stream));
 }
 

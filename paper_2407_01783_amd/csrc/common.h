@@ -173,6 +173,10 @@ struct stokes_ctx {
   double mg_smooth_ratio = 10.0;
   int use_mgx = 1;                      // lumped CC: precondition with mgx (0: mgq)
 
+  // lanes per row of the velocity-row kernels, key W * 2 + (FP32 ? 1 : 0)
+  std::map<int, int> lanes;
+  int force_lanes = 0;                  // > 0: use this G everywhere (tuning, tests)
+
   stokes::RedScratch red;
   stokes::DevBuf scal;  // Scalars pool
   int scal_count = 0;

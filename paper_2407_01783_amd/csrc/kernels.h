@@ -120,18 +120,30 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ pa
 }
 
 // --------------------------------------------------------- SELL row sums
-
-// Row sum of a scalar SELL matrix applied to W values per column.  The
-// entries of a row are walked four at a time so that eight matrix loads and
-// 4W gathers are in flight per thread (one-at-a-time loops leave HBM
-// under-subscribed).
-template <typename T, int W>
+//
+// Sliced ELL with slice height 64 (one wavefront): entry j of row r sits at
+// sp[r / 64] + 64 j + (r mod 64), so the lanes of a wavefront read
+// consecutive column indices and values.  Right-hand sides are interleaved:
+// a velocity-shaped vector holds W = dim x nrhs values per row.
+//
+// G lanes per row (G in {1, 2, 4, 8}, dividing W): the lanes of a group walk
+// the same row -- they load the same index and value, which the memory
+// pipeline merges -- and each gathers and accumulates its own W / G
+// consecutive components.  With large W this turns one wavefront-wide gather
+// of 64 scattered W-vectors into a few contiguous segments per column; the
+// summation order of every component is the same for every G.
+//
+// Entries of a row are walked four at a time so that eight matrix loads and
+// 4 W/G gathers are in flight per lane.
+template <typename T, int W, int G = 1>
 __device__ __forceinline__ void sell_row(const int64_t* __restrict__ sp, const int32_t* __restrict__ cols,
-                                         const T* __restrict__ vals, const T* __restrict__ x, int64_t row,
-                                         T (&acc)[W]) {
+                                         const T* __restrict__ vals, const T* __restrict__ x, int64_t row, int sub,
+                                         T (&acc)[W / G]) {
+  constexpr int WG = W / G;
   const int64_t s = row >> 6;
   const int64_t beg = sp[s] + (row & 63);
   const int width = (int)((sp[s + 1] - sp[s]) >> 6);
+  const T* __restrict__ xs = x + sub * WG;
   int j = 0;
   for (; j + 4 <= width; j += 4) {
     int32_t c[4];
@@ -141,22 +153,22 @@ __device__ __forceinline__ void sell_row(const int64_t* __restrict__ sp, const i
       c[u] = __builtin_nontemporal_load(cols + beg + 64 * (j + u));
       v[u] = __builtin_nontemporal_load(vals + beg + 64 * (j + u));
     }
-    T xv[4][W];
+    T xv[4][WG];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int w = 0; w < W; ++w) xv[u][w] = x[(int64_t)c[u] * W + w];
+      for (int w = 0; w < WG; ++w) xv[u][w] = xs[(int64_t)c[u] * W + w];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int w = 0; w < W; ++w) acc[w] = fma(v[u], xv[u][w], acc[w]);
+      for (int w = 0; w < WG; ++w) acc[w] = fma(v[u], xv[u][w], acc[w]);
   }
   for (; j < width; ++j) {
     const int32_t c = __builtin_nontemporal_load(cols + beg + 64 * j);
     const T v = __builtin_nontemporal_load(vals + beg + 64 * j);
-    const T* xp = x + (int64_t)c * W;
+    const T* xp = xs + (int64_t)c * W;
 #pragma unroll
-    for (int w = 0; w < W; ++w) acc[w] = fma(v, xp[w], acc[w]);
+    for (int w = 0; w < WG; ++w) acc[w] = fma(v, xp[w], acc[w]);
   }
 }
 
@@ -206,19 +218,37 @@ __device__ __forceinline__ void sell_row_B(const int64_t* __restrict__ sp, const
   }
 }
 
-// B^T rows (interior velocity node): acc[r][c] = sum_j B^c_j p[col_j][r]
-template <typename T, int D, int NRB>
+// value plane d (runtime, d < D) of a small register array
+template <typename T, int D>
+__device__ __forceinline__ T plane(const T (&b)[D], int d) {
+  T o = b[0];
+#pragma unroll
+  for (int e = 1; e < D; ++e) o = d == e ? b[e] : o;
+  return o;
+}
+
+// B^T rows (interior velocity node): acc[r][c] = sum_j B^c_j p[col_j][r];
+// with G lanes per row, lane `sub` owns components sub W/G .. (sub+1) W/G - 1
+// of the W = D NRB outputs (component w is rhs w / D, plane w mod D).
+template <typename T, int D, int NRB, int G = 1>
 __device__ __forceinline__ void sell_row_Bt(const int64_t* __restrict__ sp, const int32_t* __restrict__ cols,
                                             const T* __restrict__ vals, const T* __restrict__ p, int64_t row,
-                                            T (&acc)[D * NRB]) {
+                                            int sub, T (&acc)[D * NRB / G]) {
+  constexpr int WG = D * NRB / G;
   const int64_t s = row >> 6;
   const int64_t beg = sp[s] + (row & 63);
   const int width = (int)((sp[s + 1] - sp[s]) >> 6);
+  int rr[WG], dd[WG];
+#pragma unroll
+  for (int w = 0; w < WG; ++w) {
+    rr[w] = (sub * WG + w) / D;
+    dd[w] = (sub * WG + w) - rr[w] * D;
+  }
   constexpr int U = 4;
   int j = 0;
   for (; j + U <= width; j += U) {
     int32_t c[U];
-    T b[U][D], pv[U][NRB];
+    T b[U][D], pv[U][WG];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int64_t k = beg + 64 * (j + q);
@@ -229,13 +259,11 @@ __device__ __forceinline__ void sell_row_Bt(const int64_t* __restrict__ sp, cons
 #pragma unroll
     for (int q = 0; q < U; ++q)
 #pragma unroll
-      for (int r = 0; r < NRB; ++r) pv[q][r] = p[(int64_t)c[q] * NRB + r];
+      for (int w = 0; w < WG; ++w) pv[q][w] = p[(int64_t)c[q] * NRB + rr[w]];
 #pragma unroll
     for (int q = 0; q < U; ++q)
 #pragma unroll
-      for (int r = 0; r < NRB; ++r)
-#pragma unroll
-        for (int d = 0; d < D; ++d) acc[r * D + d] = fma(b[q][d], pv[q][r], acc[r * D + d]);
+      for (int w = 0; w < WG; ++w) acc[w] = fma(G == 1 ? b[q][w % D] : plane<T, D>(b[q], dd[w]), pv[q][w], acc[w]);
   }
   for (; j < width; ++j) {
     const int64_t k = beg + 64 * j;
@@ -245,11 +273,7 @@ __device__ __forceinline__ void sell_row_Bt(const int64_t* __restrict__ sp, cons
     for (int d = 0; d < D; ++d) b[d] = __builtin_nontemporal_load(vals + k * D + d);
     const T* pp = p + (int64_t)c * NRB;
 #pragma unroll
-    for (int r = 0; r < NRB; ++r) {
-      const T pv = pp[r];
-#pragma unroll
-      for (int d = 0; d < D; ++d) acc[r * D + d] = fma(b[d], pv, acc[r * D + d]);
-    }
+    for (int w = 0; w < WG; ++w) acc[w] = fma(G == 1 ? b[w % D] : plane<T, D>(b, dd[w]), pp[rr[w]], acc[w]);
   }
 }
 
@@ -260,61 +284,83 @@ __device__ __forceinline__ void sell_row_Bt(const int64_t* __restrict__ sp, cons
 // XCD-aware row partition for kernels that gather: workgroups are dealt
 // round-robin over the 8 XCDs (each with its own L2), so workgroup b works on
 // eighth (b % 8) of the rows -- one z-slab of the internal ordering, whose
-// gathered columns then stay in that XCD's L2 -- and the workgroups of one XCD
-// stride through their eighth, so each sees the same mix of long and short
-// rows.
-#define XCD_ROWS(row, nrows)                                                               \
+// x-gathers then stay in one L2.  Rows of an eighth are strided over its
+// workgroups.  G lanes per row: thread t of the eighth serves row t / G as
+// lane `sub` = t mod G of its group (G divides the block size).
+#define XCD_ROWS_G(row, sub, nrows, G)                                                     \
   const int64_t xg_ = (gridDim.x % 8 == 0) ? gridDim.x / 8 : gridDim.x;                   \
   const int64_t xx_ = (gridDim.x % 8 == 0) ? blockIdx.x % 8 : 0;                          \
   const int64_t xi_ = (gridDim.x % 8 == 0) ? blockIdx.x / 8 : blockIdx.x;                 \
   const int64_t xn_ = (gridDim.x % 8 == 0) ? ((((nrows) + 7) / 8 + 63) / 64) * 64 : (nrows); \
   const int64_t xb_ = xx_ * xn_;                                                          \
   const int64_t xe_ = xb_ + xn_ < (nrows) ? xb_ + xn_ : (nrows);                          \
-  for (int64_t row = xb_ + xi_ * blockDim.x + threadIdx.x; row < xe_; row += xg_ * blockDim.x)
+  const int sub = (int)(threadIdx.x % (G));                                               \
+  for (int64_t row = xb_ + (xi_ * blockDim.x + threadIdx.x) / (G); row < xe_; row += xg_ * blockDim.x / (G))
+
+#define XCD_ROWS(row, nrows) XCD_ROWS_G(row, sub_unused_ [[maybe_unused]], nrows, 1)
+
+// Row-group mapping without the XCD partition (streaming kernels).
+#define GRID_STRIDE_ROWS_G(row, sub, nrows, G)                                             \
+  const int sub = (int)(threadIdx.x % (G));                                               \
+  for (int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / (G); row < (nrows); \
+       row += (int64_t)gridDim.x * blockDim.x / (G))
+
+// Per-lane partial sums of components sub W/G .. into a full W-slot array
+// (the other slots 0), for the block reduction.
+template <int W, int G>
+__device__ __forceinline__ void expand_parts(const double (&pg)[W / G], int sub, double (&pf)[W]) {
+  constexpr int WG = W / G;
+#pragma unroll
+  for (int w = 0; w < W; ++w) pf[w] = (w / WG == sub) ? pg[w % WG] : 0.0;
+}
 
 // ----------------------------------------------------------- SpMV kernels
 
 // y = a * (S x) + b * yin   (yin may alias y; ignored when b == 0)
-template <typename T, int W>
+template <typename T, int W, int G>
 __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, const int64_t* __restrict__ sp,
                                                  const int32_t* __restrict__ cols, const T* __restrict__ vals,
                                                  const T* __restrict__ x, T* y, T a, const T* yin, T b) {
-  XCD_ROWS(row, nrows) {
-    T acc[W];
+  constexpr int WG = W / G;
+  XCD_ROWS_G(row, sub, nrows, G) {
+    T acc[WG];
 #pragma unroll
-    for (int w = 0; w < W; ++w) acc[w] = 0;
-    sell_row<T, W>(sp, cols, vals, x, row, acc);
+    for (int w = 0; w < WG; ++w) acc[w] = 0;
+    sell_row<T, W, G>(sp, cols, vals, x, row, sub, acc);
+    const int64_t o = row * W + sub * WG;
+    // yin may alias y: every load of the row is issued before its stores
+    T yi[WG];
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      T o = a * acc[w];
-      if (b != T(0)) o = fma(b, yin[row * W + w], o);
-      y[row * W + w] = o;
-    }
+    for (int w = 0; w < WG; ++w) yi[w] = b != T(0) ? yin[o + w] : T(0);
+#pragma unroll
+    for (int w = 0; w < WG; ++w) y[o + w] = fma(b, yi[w], a * acc[w]);
   }
 }
 
 // CG direction step with the product folded in:
 //   q = S z (+ extra) + beta q,  p = z + beta p,  sigma = p . q  -> alpha
-template <typename T, int W>
+template <typename T, int W, int G>
 __global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t nrows, const int64_t* __restrict__ sp,
                                                     const int32_t* __restrict__ cols,
                                                     const T* __restrict__ vals, const T* __restrict__ z,
                                                     const T* __restrict__ extra, T* __restrict__ q,
                                                     T* __restrict__ p, Scalars* sc, int cps, int nsys, double* partials) {
-  T beta[W];
+  constexpr int WG = W / G;
+  const int sub0 = (int)(threadIdx.x % G);
+  T beta[WG];
 #pragma unroll
-  for (int w = 0; w < W; ++w) beta[w] = (T)sc->beta[w / cps];
-  double part[W];
+  for (int w = 0; w < WG; ++w) beta[w] = (T)sc->beta[(sub0 * WG + w) / cps];
+  double part[WG];
 #pragma unroll
-  for (int w = 0; w < W; ++w) part[w] = 0;
-  XCD_ROWS(row, nrows) {
-    T acc[W];
+  for (int w = 0; w < WG; ++w) part[w] = 0;
+  XCD_ROWS_G(row, sub, nrows, G) {
+    T acc[WG];
 #pragma unroll
-    for (int w = 0; w < W; ++w) acc[w] = 0;
-    if (sp) sell_row<T, W>(sp, cols, vals, z, row, acc);
+    for (int w = 0; w < WG; ++w) acc[w] = 0;
+    if (sp) sell_row<T, W, G>(sp, cols, vals, z, row, sub, acc);
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const int64_t i = row * W + w;
+    for (int w = 0; w < WG; ++w) {
+      const int64_t i = row * W + sub * WG + w;
       T a = acc[w];
       if (extra) a += extra[i];
       const T qn = fma(beta[w], q[i], a);
@@ -324,33 +370,36 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t nrows, const int64_t
       part[w] += (double)pn * (double)qn;
     }
   }
-  grid_reduce<W>(part, partials);
+  double pf[W];
+  expand_parts<W, G>(part, sub0, pf);
+  grid_reduce<W>(pf, partials);
 }
 
 // PREC: 0 = Chebyshev prologue (d0 = dinv r / theta, z = d0), 1 = Jacobi
 // (z = dinv r, rho = r . z), 2 = none (the preconditioner runs separately).
 // Always: x += alpha p, r -= alpha q, rr = r . r.
-template <typename T, int W, int PREC>
+template <typename T, int W, int PREC, int G>
 __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t nrows, T* __restrict__ x, T* __restrict__ r,
                                                       const T* __restrict__ p, const T* __restrict__ q,
                                                       const T* __restrict__ dinv, T theta_inv, T* __restrict__ d0,
                                                       T* __restrict__ z, Scalars* sc, int cps, int nsys, double* partials) {
-  constexpr int NS = PREC == 1 ? 2 * W : W;
-  T alpha[W];
+  constexpr int WG = W / G;
+  const int sub0 = (int)(threadIdx.x % G);
+  T alpha[WG];
 #pragma unroll
-  for (int w = 0; w < W; ++w) alpha[w] = (T)sc->alpha[w / cps];
-  double part[NS];
+  for (int w = 0; w < WG; ++w) alpha[w] = (T)sc->alpha[(sub0 * WG + w) / cps];
+  double prr[WG], prz[WG];
 #pragma unroll
-  for (int w = 0; w < NS; ++w) part[w] = 0;
-  GRID_STRIDE_ROWS(row, nrows) {
+  for (int w = 0; w < WG; ++w) prr[w] = prz[w] = 0;
+  GRID_STRIDE_ROWS_G(row, sub, nrows, G) {
     const T di = PREC == 2 ? T(0) : dinv[row];  // one inverse diagonal per node
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const int64_t i = row * W + w;
+    for (int w = 0; w < WG; ++w) {
+      const int64_t i = row * W + sub * WG + w;
       x[i] = fma(alpha[w], p[i], x[i]);
       const T rn = fma(-alpha[w], q[i], r[i]);
       r[i] = rn;
-      part[w] += (double)rn * (double)rn;
+      prr[w] += (double)rn * (double)rn;
       if (PREC == 0) {
         const T dd = rn * di * theta_inv;
         d0[i] = dd;
@@ -358,26 +407,37 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t nrows, T* __restri
       } else if (PREC == 1) {
         const T zz = rn * di;
         z[i] = zz;
-        part[W + w] += (double)rn * (double)zz;
+        prz[w] += (double)rn * (double)zz;
       }
     }
   }
-  grid_reduce<NS>(part, partials);
+  constexpr int NS = PREC == 1 ? 2 * W : W;
+  double pf[NS], t[W];
+  expand_parts<W, G>(prr, sub0, t);
+#pragma unroll
+  for (int w = 0; w < W; ++w) pf[w] = t[w];
+  if constexpr (PREC == 1) {
+    expand_parts<W, G>(prz, sub0, t);
+#pragma unroll
+    for (int w = 0; w < W; ++w) pf[W + w] = t[w];
+  }
+  grid_reduce<NS>(pf, partials);
 }
 
-// Chebyshev prologue on its own: d0 = dinv r / theta, z = d0 (optionally with
-// the Jacobi dot rho = r . z when the polynomial has degree 1).
-template <typename T, int W>
+// Chebyshev prologue on its own: d0 = dinv r / theta, z = d0.
+template <typename T, int W, int G>
 __global__ __launch_bounds__(kBlock) void k_cheb_init(int64_t nrows, const T* __restrict__ r,
                                                       const T* __restrict__ dinv, T theta_inv, T* __restrict__ d0,
                                                       T* __restrict__ z) {
-  GRID_STRIDE_ROWS(row, nrows) {
+  constexpr int WG = W / G;
+  GRID_STRIDE_ROWS_G(row, sub, nrows, G) {
     const T di = dinv[row] * theta_inv;
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const T dd = r[row * W + w] * di;
-      d0[row * W + w] = dd;
-      z[row * W + w] = dd;
+    for (int w = 0; w < WG; ++w) {
+      const int64_t i = row * W + sub * WG + w;
+      const T dd = r[i] * di;
+      d0[i] = dd;
+      z[i] = dd;
     }
   }
 }
@@ -385,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_init(int64_t nrows, const T* __
 // One Chebyshev step (Saad, Iterative Methods, Alg. 12.1, three-term form):
 //   res = res_in - S d ;  dn = c1 d + c2 dinv res ;  z += dn
 // DOT: also rho = rvec . z -> beta (CG preconditioner use), first => beta = 0.
-template <typename T, int W, int DOT>
+template <typename T, int W, int DOT, int G>
 __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, const int64_t* __restrict__ sp,
                                                       const int32_t* __restrict__ cols,
                                                       const T* __restrict__ vals, const T* __restrict__ d,
@@ -393,29 +453,40 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, const int64
                                                       T* __restrict__ z, const T* __restrict__ dinv, T c1, T c2,
                                                       const T* __restrict__ rvec, Scalars* sc, int cps, int nsys,
                                                       int first, double* partials) {
-  double part[W];
+  constexpr int WG = W / G;
+  double part[WG];
 #pragma unroll
-  for (int w = 0; w < W; ++w) part[w] = 0;
-  XCD_ROWS(row, nrows) {
-    T acc[W];
+  for (int w = 0; w < WG; ++w) part[w] = 0;
+  XCD_ROWS_G(row, sub, nrows, G) {
+    T acc[WG];
 #pragma unroll
-    for (int w = 0; w < W; ++w) acc[w] = 0;
-    sell_row<T, W>(sp, cols, vals, d, row, acc);
+    for (int w = 0; w < WG; ++w) acc[w] = 0;
+    sell_row<T, W, G>(sp, cols, vals, d, row, sub, acc);
     const T di = c2 * dinv[row];
+    const int64_t o = row * W + sub * WG;
+    // res_in may alias res_out: load the whole row before any store
+    T ri[WG], dd[WG], zz[WG];
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const int64_t i = row * W + w;
-      const T rs = res_in[i] - acc[w];
-      res_out[i] = rs;
-      const T dnew = fma(c1, d[i], di * rs);
-      dn[i] = dnew;
-      const T zn = z[i] + dnew;
-      z[i] = zn;
-      if (DOT) part[w] += (double)rvec[i] * (double)zn;
+    for (int w = 0; w < WG; ++w) {
+      ri[w] = res_in[o + w];
+      dd[w] = d[o + w];
+      zz[w] = z[o + w];
+    }
+#pragma unroll
+    for (int w = 0; w < WG; ++w) {
+      const T rs = ri[w] - acc[w];
+      res_out[o + w] = rs;
+      const T dnew = fma(c1, dd[w], di * rs);
+      dn[o + w] = dnew;
+      const T zn = zz[w] + dnew;
+      z[o + w] = zn;
+      if (DOT) part[w] += (double)rvec[o + w] * (double)zn;
     }
   }
   if (DOT) {
-    grid_reduce<W>(part, partials);
+    double pf[W];
+    expand_parts<W, G>(part, (int)(threadIdx.x % G), pf);
+    grid_reduce<W>(pf, partials);
   }
 }
 
@@ -423,35 +494,38 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, const int64
 // formed on the fly at every gathered column, so no separate pass is needed:
 //   res = r - S d0 ;  d1 = c1 d0 + c2 dinv res ;  z = d0 + d1
 // ACC: z += d0 + d1 (z holds a previous approximation) instead of z = d0 + d1
-template <typename T, int W, int ACC>
+template <typename T, int W, int ACC, int G>
 __global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, const int64_t* __restrict__ sp,
                                                        const int32_t* __restrict__ cols, const T* __restrict__ vals,
                                                        const T* __restrict__ r, const T* __restrict__ dinv, T theta_inv,
                                                        T* __restrict__ d1, T* __restrict__ res, T* __restrict__ z,
                                                        T c1, T c2) {
-  XCD_ROWS(row, nrows) {
-    T acc[W];
+  constexpr int WG = W / G;
+  XCD_ROWS_G(row, sub, nrows, G) {
+    T acc[WG];
 #pragma unroll
-    for (int w = 0; w < W; ++w) acc[w] = 0;
+    for (int w = 0; w < WG; ++w) acc[w] = 0;
     const int64_t s = row >> 6;
     const int64_t end = sp[s + 1];
+    const T* rs_ = r + sub * WG;
     for (int64_t k = sp[s] + (row & 63); k < end; k += 64) {
       const int32_t c = __builtin_nontemporal_load(cols + k);
       const T v = __builtin_nontemporal_load(vals + k) * dinv[c];
-      const T* xp = r + (int64_t)c * W;
+      const T* xp = rs_ + (int64_t)c * W;
 #pragma unroll
-      for (int w = 0; w < W; ++w) acc[w] = fma(v, xp[w], acc[w]);
+      for (int w = 0; w < WG; ++w) acc[w] = fma(v, xp[w], acc[w]);
     }
     const T di = dinv[row];
+    const int64_t o = row * W + sub * WG;
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const int64_t i = row * W + w;
+    for (int w = 0; w < WG; ++w) {
+      const int64_t i = o + w;
       const T d0 = theta_inv * di * r[i];
       const T rs = r[i] - theta_inv * acc[w];
       res[i] = rs;
-      const T dn = fma(c1, d0, c2 * di * rs);
-      d1[i] = dn;
-      z[i] = ACC ? z[i] + (d0 + dn) : d0 + dn;
+      const T dnv = fma(c1, d0, c2 * di * rs);
+      d1[i] = dnv;
+      z[i] = ACC ? z[i] + (d0 + dnv) : d0 + dnv;
     }
   }
 }
@@ -468,61 +542,61 @@ __global__ __launch_bounds__(kBlock) void k_B(int64_t nrows, const int64_t* __re
 #pragma unroll
     for (int r = 0; r < NRB; ++r) acc[r] = 0;
     sell_row_B<T, D, NRB>(sp, cols, vals, u, row, acc);
+    T pi[NRB];  // pin may alias pout
 #pragma unroll
-    for (int r = 0; r < NRB; ++r) {
-      T o = a * acc[r];
-      if (b != T(0)) o = fma(b, pin[row * NRB + r], o);
-      pout[row * NRB + r] = o;
-    }
+    for (int r = 0; r < NRB; ++r) pi[r] = b != T(0) ? pin[row * NRB + r] : T(0);
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) pout[row * NRB + r] = fma(b, pi[r], a * acc[r]);
   }
 }
 
 // u = a * scale .* (B^T p) + b * uin     (scale per node, may be null)
-template <typename T, int D, int NRB>
+template <typename T, int D, int NRB, int G>
 __global__ __launch_bounds__(kBlock) void k_Bt(int64_t nrows, const int64_t* __restrict__ sp,
                                                const int32_t* __restrict__ cols, const T* __restrict__ vals,
                                                const T* __restrict__ p, const T* __restrict__ scale, T* uout,
                                                T a, const T* uin, T b) {
-  constexpr int W = D * NRB;
-  XCD_ROWS(row, nrows) {
-    T acc[W];
+  constexpr int W = D * NRB, WG = W / G;
+  XCD_ROWS_G(row, sub, nrows, G) {
+    T acc[WG];
 #pragma unroll
-    for (int w = 0; w < W; ++w) acc[w] = 0;
-    sell_row_Bt<T, D, NRB>(sp, cols, vals, p, row, acc);
+    for (int w = 0; w < WG; ++w) acc[w] = 0;
+    sell_row_Bt<T, D, NRB, G>(sp, cols, vals, p, row, sub, acc);
     const T sc = scale ? a * scale[row] : a;
+    const int64_t o = row * W + sub * WG;
+    T ui[WG];  // uin may alias uout
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      T o = sc * acc[w];
-      if (b != T(0)) o = fma(b, uin[row * W + w], o);
-      uout[row * W + w] = o;
-    }
+    for (int w = 0; w < WG; ++w) ui[w] = b != T(0) ? uin[o + w] : T(0);
+#pragma unroll
+    for (int w = 0; w < WG; ++w) uout[o + w] = fma(b, ui[w], sc * acc[w]);
   }
 }
 
 // Momentum rows of the coupled operator:
-//   y = sgn * (A u - B^T p) + yin   (sgn = -1 with yin = F gives the residual)
-template <typename T, int D, int NRB>
+//   y = sgn * (A u - B^T p + extra) + yin   (sgn = -1 with yin = F gives the residual)
+template <typename T, int D, int NRB, int G>
 __global__ __launch_bounds__(kBlock) void k_momentum(int64_t nrows, const int64_t* __restrict__ spA,
                                                      const int32_t* __restrict__ colsA, const T* __restrict__ A,
                                                      const int64_t* __restrict__ spT,
                                                      const int32_t* __restrict__ colsT, const T* __restrict__ Bt,
                                                      const T* __restrict__ u, const T* __restrict__ p,
                                                      const T* __restrict__ extra, T* y, T sgn, const T* yin) {
-  constexpr int W = D * NRB;
-  XCD_ROWS(row, nrows) {
-    T acc[W], bt[W];
+  constexpr int W = D * NRB, WG = W / G;
+  XCD_ROWS_G(row, sub, nrows, G) {
+    T acc[WG], bt[WG];
 #pragma unroll
-    for (int w = 0; w < W; ++w) acc[w] = bt[w] = 0;
-    sell_row<T, W>(spA, colsA, A, u, row, acc);
-    sell_row_Bt<T, D, NRB>(spT, colsT, Bt, p, row, bt);
+    for (int w = 0; w < WG; ++w) acc[w] = bt[w] = 0;
+    sell_row<T, W, G>(spA, colsA, A, u, row, sub, acc);
+    sell_row_Bt<T, D, NRB, G>(spT, colsT, Bt, p, row, sub, bt);
+    const int64_t o = row * W + sub * WG;
+    T ex[WG], yi[WG];  // yin may alias y
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      T o = acc[w] - bt[w];
-      if (extra) o += extra[row * W + w];
-      o = sgn * o;
-      if (yin) o += yin[row * W + w];
-      y[row * W + w] = o;
+    for (int w = 0; w < WG; ++w) {
+      ex[w] = extra ? extra[o + w] : T(0);
+      yi[w] = yin ? yin[o + w] : T(0);
     }
+#pragma unroll
+    for (int w = 0; w < WG; ++w) y[o + w] = fma(sgn, acc[w] - bt[w] + ex[w], yi[w]);
   }
 }
 

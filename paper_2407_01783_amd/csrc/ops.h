@@ -25,6 +25,8 @@ void lanczos_bounds(stokes_ctx* c, const Sell& S, const double* vals, const doub
 namespace ops {
 
 int grid_for(int64_t rows);
+// lanes per row of the velocity-row kernels, autotuned once per (W, precision)
+void ensure_lanes(stokes_ctx* c, int W, bool f32);
 bool prof_begin(stokes_ctx* c, const Sell* S, const void* vals, const void* avals);
 void prof_end(stokes_ctx* c, double bytes);
 void check_launch();

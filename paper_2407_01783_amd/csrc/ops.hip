@@ -1,4 +1,6 @@
 // Launchers for the kernels in kernels.h.
+#include <cstdio>
+#include <cstdlib>
 #include <type_traits>
 
 #include "kernels.h"
@@ -82,6 +84,44 @@ void dispatch_dn(int D, int NRB, F&& f) {
 
 inline double* partials(stokes_ctx* c) { return c->red.partials.as<double>(); }
 
+// Lanes per row G of the velocity-row kernels: the largest of 8, 4, 2 not
+// above the request that divides W (the compiled variants).
+template <int WW, class F>
+void with_g(int G, F&& f) {
+  if constexpr (WW % 8 == 0) {
+    if (G >= 8) return f(IC<8>{});
+  }
+  if constexpr (WW % 4 == 0) {
+    if (G >= 4) return f(IC<4>{});
+  }
+  if constexpr (WW % 2 == 0) {
+    if (G >= 2) return f(IC<2>{});
+  }
+  f(IC<1>{});
+}
+
+// Before tuning: the largest G leaving each lane at least 3 components.
+int heuristic_lanes(int W) {
+  for (int g : {8, 4, 2})
+    if (W % g == 0 && W / g >= 3) return g;
+  return 1;
+}
+
+int lanes_w(stokes_ctx* c, int W, bool f32) {
+  if (c->force_lanes > 0) return c->force_lanes;
+  const auto it = c->lanes.find(W * 2 + (f32 ? 1 : 0));
+  return it != c->lanes.end() ? it->second : heuristic_lanes(W);
+}
+
+// velocity-row operators use the tuned G; the pressure operators one lane per row
+int lanes_op(stokes_ctx* c, const Sell* S, int W, bool f32) {
+  return (S == &c->sA || S == &c->sBt) ? lanes_w(c, W, f32) : 1;
+}
+
+int lanes_rows(stokes_ctx* c, int64_t nrows, int W, bool f32) {
+  return nrows == c->n_int ? lanes_w(c, W, f32) : 1;
+}
+
 template <int NS>
 void finish(stokes_ctx* c, int64_t rows, int kind, int W, Scalars* sc, int cps, int nsys, int first, double* res) {
   hipLaunchKernelGGL((k_finish<NS>), dim3(1), dim3(kBlock), 0, c->stream, (const double*)partials(c), grid_for(rows),
@@ -102,10 +142,14 @@ template <> const DevBuf& avals<float>(stokes_ctx* c) { return c->A32; }
 
 template <class T>
 void spmv(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* x, T* y, T a, const T* yin, T b) {
+  const int G = lanes_op(c, &S, W, std::is_same<T, float>::value);
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
-    hipLaunchKernelGGL((k_spmv<T, WW>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
-                       S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, x, y, a, yin, b);
+    with_g<WW>(G, [&](auto Gc) {
+      constexpr int GG = decltype(Gc)::value;
+      hipLaunchKernelGGL((k_spmv<T, WW, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows,
+                         S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, x, y, a, yin, b);
+    });
   });
   check_launch();
 }
@@ -124,23 +168,31 @@ void Bmul(stokes_ctx* c, int nrb, const T* u, T* p, T a, const T* pin, T b) {
 template <class T>
 void Btmul(stokes_ctx* c, int nrb, const T* p, const T* scale, T* u, T a, const T* uin, T b) {
   const Sell& S = c->sBt;
+  const int G = lanes_op(c, &S, c->dim * nrb, std::is_same<T, float>::value);
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
     constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
-    hipLaunchKernelGGL((k_Bt<T, D, N>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
-                       S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), btvals<T>(c).template as<T>(), p, scale, u, a,
-                       uin, b);
+    with_g<D * N>(G, [&](auto Gc) {
+      constexpr int GG = decltype(Gc)::value;
+      hipLaunchKernelGGL((k_Bt<T, D, N, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows,
+                         S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), btvals<T>(c).template as<T>(), p, scale, u,
+                         a, uin, b);
+    });
   });
   check_launch();
 }
 
 template <class T>
 void momentum(stokes_ctx* c, int nrb, const T* u, const T* p, const T* extra, T* y, T sgn, const T* yin) {
+  const int G = lanes_w(c, c->dim * nrb, std::is_same<T, float>::value);
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
     constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
-    hipLaunchKernelGGL((k_momentum<T, D, N>), dim3(grid_for(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int,
-                       c->sA.slice_ptr.as<int64_t>(), c->sA.cols.as<int32_t>(), avals<T>(c).template as<T>(),
-                       c->sBt.slice_ptr.as<int64_t>(), c->sBt.cols.as<int32_t>(), btvals<T>(c).template as<T>(), u, p,
-                       extra, y, sgn, yin);
+    with_g<D * N>(G, [&](auto Gc) {
+      constexpr int GG = decltype(Gc)::value;
+      hipLaunchKernelGGL((k_momentum<T, D, N, GG>), dim3(grid_for(c->n_int * GG)), dim3(kBlock), 0, c->stream,
+                         c->n_int, c->sA.slice_ptr.as<int64_t>(), c->sA.cols.as<int32_t>(),
+                         avals<T>(c).template as<T>(), c->sBt.slice_ptr.as<int64_t>(), c->sBt.cols.as<int32_t>(),
+                         btvals<T>(c).template as<T>(), u, p, extra, y, sgn, yin);
+    });
   });
   check_launch();
 }
@@ -219,12 +271,16 @@ void axpy_sys(stokes_ctx* c, int64_t n, int W, int cps, const double* coef, doub
 template <class T>
 void cg_spmv(stokes_ctx* c, int64_t nrows, const Sell* S, const T* vals, int W, const T* z, const T* extra, T* q,
              T* p, Scalars* sc, int cps, int nsys) {
+  const int G = S ? lanes_op(c, S, W, std::is_same<T, float>::value) : 1;
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
-    hipLaunchKernelGGL((k_cg_spmv<T, WW>), dim3(grid_for(nrows)), dim3(kBlock), 0, c->stream, nrows,
-                       S ? S->slice_ptr.as<int64_t>() : nullptr, S ? S->cols.as<int32_t>() : nullptr, vals, z, extra,
-                       q, p, sc, cps, nsys, partials(c));
-    finish<WW>(c, nrows, FIN_ALPHA, WW, sc, cps, nsys, 0, nullptr);
+    with_g<WW>(G, [&](auto Gc) {
+      constexpr int GG = decltype(Gc)::value;
+      hipLaunchKernelGGL((k_cg_spmv<T, WW, GG>), dim3(grid_for(nrows * GG)), dim3(kBlock), 0, c->stream, nrows,
+                         S ? S->slice_ptr.as<int64_t>() : nullptr, S ? S->cols.as<int32_t>() : nullptr, vals, z,
+                         extra, q, p, sc, cps, nsys, partials(c));
+      finish<WW>(c, nrows * GG, FIN_ALPHA, WW, sc, cps, nsys, 0, nullptr);
+    });
   });
   check_launch();
 }
@@ -232,31 +288,40 @@ void cg_spmv(stokes_ctx* c, int64_t nrows, const Sell* S, const T* vals, int W, 
 template <class T>
 void cg_update(stokes_ctx* c, int64_t nrows, int W, int prec, T* x, T* r, const T* p, const T* q, const T* dinv,
                T theta_inv, T* d0, T* z, Scalars* sc, int cps, int nsys) {
+  const int G = lanes_rows(c, nrows, W, std::is_same<T, float>::value);
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
-    if (prec == 2) {
-      hipLaunchKernelGGL((k_cg_update<T, WW, 2>), dim3(grid_for(nrows)), dim3(kBlock), 0, c->stream, nrows, x, r, p,
-                         q, dinv, theta_inv, d0, z, sc, cps, nsys, partials(c));
-      finish<WW>(c, nrows, FIN_RR, WW, sc, cps, nsys, 0, nullptr);
-    } else if (prec == 0) {
-      hipLaunchKernelGGL((k_cg_update<T, WW, 0>), dim3(grid_for(nrows)), dim3(kBlock), 0, c->stream, nrows, x, r, p,
-                         q, dinv, theta_inv, d0, z, sc, cps, nsys, partials(c));
-      finish<WW>(c, nrows, FIN_RR, WW, sc, cps, nsys, 0, nullptr);
-    } else {
-      hipLaunchKernelGGL((k_cg_update<T, WW, 1>), dim3(grid_for(nrows)), dim3(kBlock), 0, c->stream, nrows, x, r, p,
-                         q, dinv, theta_inv, d0, z, sc, cps, nsys, partials(c));
-      finish<2 * WW>(c, nrows, FIN_RR_RHO, WW, sc, cps, nsys, 0, nullptr);
-    }
+    with_g<WW>(G, [&](auto Gc) {
+      constexpr int GG = decltype(Gc)::value;
+      const int nb = grid_for(nrows * GG);
+      if (prec == 2) {
+        hipLaunchKernelGGL((k_cg_update<T, WW, 2, GG>), dim3(nb), dim3(kBlock), 0, c->stream, nrows, x, r, p, q, dinv,
+                           theta_inv, d0, z, sc, cps, nsys, partials(c));
+        finish<WW>(c, nrows * GG, FIN_RR, WW, sc, cps, nsys, 0, nullptr);
+      } else if (prec == 0) {
+        hipLaunchKernelGGL((k_cg_update<T, WW, 0, GG>), dim3(nb), dim3(kBlock), 0, c->stream, nrows, x, r, p, q, dinv,
+                           theta_inv, d0, z, sc, cps, nsys, partials(c));
+        finish<WW>(c, nrows * GG, FIN_RR, WW, sc, cps, nsys, 0, nullptr);
+      } else {
+        hipLaunchKernelGGL((k_cg_update<T, WW, 1, GG>), dim3(nb), dim3(kBlock), 0, c->stream, nrows, x, r, p, q, dinv,
+                           theta_inv, d0, z, sc, cps, nsys, partials(c));
+        finish<2 * WW>(c, nrows * GG, FIN_RR_RHO, WW, sc, cps, nsys, 0, nullptr);
+      }
+    });
   });
   check_launch();
 }
 
 template <class T>
 void cheb_init(stokes_ctx* c, int64_t nrows, int W, const T* r, const T* dinv, T theta_inv, T* d0, T* z) {
+  const int G = lanes_rows(c, nrows, W, std::is_same<T, float>::value);
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
-    hipLaunchKernelGGL((k_cheb_init<T, WW>), dim3(grid_for(nrows)), dim3(kBlock), 0, c->stream, nrows, r, dinv,
-                       theta_inv, d0, z);
+    with_g<WW>(G, [&](auto Gc) {
+      constexpr int GG = decltype(Gc)::value;
+      hipLaunchKernelGGL((k_cheb_init<T, WW, GG>), dim3(grid_for(nrows * GG)), dim3(kBlock), 0, c->stream, nrows, r,
+                         dinv, theta_inv, d0, z);
+    });
   });
   check_launch();
 }
@@ -264,16 +329,21 @@ void cheb_init(stokes_ctx* c, int64_t nrows, int W, const T* r, const T* dinv, T
 template <class T>
 void cheb_first(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* r, const T* dinv, T theta_inv, T* d1,
                 T* res, T* z, T c1, T c2, int accumulate) {
+  const int G = lanes_op(c, &S, W, std::is_same<T, float>::value);
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
-    if (accumulate)
-      hipLaunchKernelGGL((k_cheb_first<T, WW, 1>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
-                         S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, r, dinv, theta_inv, d1, res, z, c1,
-                         c2);
-    else
-      hipLaunchKernelGGL((k_cheb_first<T, WW, 0>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
-                         S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, r, dinv, theta_inv, d1, res, z, c1,
-                         c2);
+    with_g<WW>(G, [&](auto Gc) {
+      constexpr int GG = decltype(Gc)::value;
+      const int nb = grid_for(S.nrows * GG);
+      if (accumulate)
+        hipLaunchKernelGGL((k_cheb_first<T, WW, 1, GG>), dim3(nb), dim3(kBlock), 0, c->stream, S.nrows,
+                           S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, r, dinv, theta_inv, d1, res, z, c1,
+                           c2);
+      else
+        hipLaunchKernelGGL((k_cheb_first<T, WW, 0, GG>), dim3(nb), dim3(kBlock), 0, c->stream, S.nrows,
+                           S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, r, dinv, theta_inv, d1, res, z, c1,
+                           c2);
+    });
   });
   check_launch();
 }
@@ -283,23 +353,86 @@ void cheb_step(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* d, T
                T* z, const T* dinv, T c1, T c2, const T* rvec, Scalars* sc, int cps, int nsys, int first) {
   // the timed kernel is the plain Chebyshev step (no fused dot) on the velocity block
   const bool timed = rvec == nullptr && prof_begin(c, &S, (const void*)vals, (const void*)avals<T>(c).template as<T>());
+  const int G = lanes_op(c, &S, W, std::is_same<T, float>::value);
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
-    if (rvec) {
-      hipLaunchKernelGGL((k_cheb_step<T, WW, 1>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
-                         S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, d, dn, res_in, res_out, z, dinv, c1,
-                         c2, rvec, sc, cps, nsys, first, partials(c));
-      finish<WW>(c, S.nrows, FIN_RHO, WW, sc, cps, nsys, first, nullptr);
-    } else
-      hipLaunchKernelGGL((k_cheb_step<T, WW, 0>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
-                         S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, d, dn, res_in, res_out, z, dinv, c1,
-                         c2, rvec, sc, cps, nsys, first, partials(c));
+    with_g<WW>(G, [&](auto Gc) {
+      constexpr int GG = decltype(Gc)::value;
+      const int nb = grid_for(S.nrows * GG);
+      if (rvec) {
+        hipLaunchKernelGGL((k_cheb_step<T, WW, 1, GG>), dim3(nb), dim3(kBlock), 0, c->stream, S.nrows,
+                           S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, d, dn, res_in, res_out, z, dinv, c1,
+                           c2, rvec, sc, cps, nsys, first, partials(c));
+        finish<WW>(c, S.nrows * GG, FIN_RHO, WW, sc, cps, nsys, first, nullptr);
+      } else
+        hipLaunchKernelGGL((k_cheb_step<T, WW, 0, GG>), dim3(nb), dim3(kBlock), 0, c->stream, S.nrows,
+                           S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, d, dn, res_in, res_out, z, dinv, c1,
+                           c2, rvec, sc, cps, nsys, first, partials(c));
+    });
   });
   check_launch();
   // algorithmic bytes: values + column indices once; d gathered once; res_in,
   // z, dinv (and rvec) read; res_out, dn, z written
   if (timed)
     prof_end(c, double(S.nnz) * (sizeof(T) + 4.0) + double(S.nrows) * sizeof(T) * (W * (rvec ? 7.0 : 6.0) + 1.0));
+}
+
+// Autotune G for the velocity-row kernels of width W in precision T: time the
+// plain SELL product on the velocity block for every compiled G and keep the
+// fastest (cached per context; skipped while a graph is being captured).
+template <class T>
+void tune_lanes(stokes_ctx* c, int W) {
+  const int key = W * 2 + (std::is_same<T, float>::value ? 1 : 0);
+  if (c->force_lanes > 0 || c->lanes.count(key)) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_CHECK(hipStreamIsCapturing(c->stream, &cs));
+  if (cs != hipStreamCaptureStatusNone) return;
+  std::vector<int> cand;
+  for (int g : {1, 2, 4, 8})
+    if (W % g == 0) cand.push_back(g);
+  if (cand.size() == 1) {
+    c->lanes[key] = 1;
+    return;
+  }
+  const int64_t n = c->n_int * W;
+  DevBuf x, y;
+  x.alloc(n * sizeof(T));
+  y.alloc(n * sizeof(T));
+  HIP_CHECK(hipMemsetAsync(x.p, 0, n * sizeof(T), c->stream));
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  const Sell& S = c->sA;
+  const T* vals = pick<T>(c->A64, c->A32);
+  int best = cand[0];
+  float best_ms = 1e30f;
+  for (int g : cand) {
+    c->force_lanes = g;
+    spmv<T>(c, S, vals, W, x.as<T>(), y.as<T>(), T(1), nullptr, T(0));  // warm-up
+    HIP_CHECK(hipEventRecord(e0, c->stream));
+    for (int rep = 0; rep < 3; ++rep) spmv<T>(c, S, vals, W, x.as<T>(), y.as<T>(), T(1), nullptr, T(0));
+    HIP_CHECK(hipEventRecord(e1, c->stream));
+    HIP_CHECK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    if (const char* e = std::getenv("STOKES_LOG"); e && std::atoi(e) >= 1)
+      std::fprintf(stderr, "[stokes] lanes W=%d %s G=%d: %.1f us per SpMV\n", W,
+                   std::is_same<T, float>::value ? "fp32" : "fp64", g, 1e3 * ms / 3);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = g;
+    }
+  }
+  c->force_lanes = 0;
+  HIP_CHECK(hipEventDestroy(e0));
+  HIP_CHECK(hipEventDestroy(e1));
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+  c->lanes[key] = best;
+}
+
+void ensure_lanes(stokes_ctx* c, int W, bool f32) {
+  if (f32) tune_lanes<float>(c, W);
+  else tune_lanes<double>(c, W);
 }
 
 template <class T>

@@ -781,6 +781,8 @@ int refine_loop(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, 
 
 int solve_internal(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, const double* F, const double* g,
                    double* xu, double* xp, SolveStats& st) {
+  ops::ensure_lanes(c, c->dim * nrb, false);  // FP64 outer operator
+  if (o.precision == STOKES_MIXED) ops::ensure_lanes(c, c->dim * nrb, true);
   if (o.precision == STOKES_MIXED) return refine_loop<float>(c, o, method, nrb, F, g, xu, xp, st);
   return refine_loop<double>(c, o, method, nrb, F, g, xu, xp, st);
 }

@@ -110,6 +110,44 @@ def test_multigrid_vcycle_symmetric_and_contracting(gpu_lib, n):
         assert rates.max() <= 0.5, (op, rates)
 
 
+@pytest.mark.parametrize("dim", [3, 2])
+def test_lanes_per_row_variants_bitwise_equal(gpu_lib, dim, monkeypatch):
+    """Every lanes-per-row variant of the velocity-row kernels accumulates each
+    component over the row in the same order: results are bitwise equal."""
+    n, nrhs = (4, 8) if dim == 3 else (6, 8)
+    rng = np.random.default_rng(9)
+    outs = {}
+    for G in (1, 2, 4, 8):
+        monkeypatch.setenv("STOKES_LANES", str(G))
+        P = _problem(dim, n, seed=6)
+        x_u = rng.standard_normal((nrhs, dim, P.n_p2)) if G == 1 else outs[1][0]
+        x_p = rng.standard_normal((nrhs, P.n_p1)) if G == 1 else outs[1][1]
+        xc = torch.tensor(np.concatenate([x_u.ravel(), x_p.ravel()]), device="cuda")
+        res = [x_u, x_p]
+        for prec in (0, 1):
+            res.append(P.apply(0, torch.tensor(x_u.ravel(), device="cuda"), precision=prec, nrhs=nrhs).cpu().numpy())
+            res.append(P.apply(2, torch.tensor(x_p.ravel(), device="cuda"), precision=prec, nrhs=nrhs).cpu().numpy())
+            res.append(P.apply(5, xc, precision=prec, nrhs=nrhs).cpu().numpy())
+        outs[G] = res
+        del P
+    for G in (2, 4, 8):
+        for a, b in zip(outs[1][2:], outs[G][2:]):
+            assert np.array_equal(a, b), G
+
+
+def test_batched_eight_rhs_with_grouped_lanes_matches_oracle(gpu_lib, monkeypatch):
+    monkeypatch.setenv("STOKES_LANES", "8")
+    kw = dict(dim=3, n=4, seed=7, mu=0.05, alpha=80.0)
+    P, S = _problem(**kw), _oracle(**kw)
+    fs = np.stack([inputs.fourier_forcing(S.mesh.p2coords, inputs.forcing_seed(7, b)) for b in range(8)])
+    u, p, info = P.solve(torch.tensor(fs, device="cuda"), method="coupled", precision=1, rtol=1e-12)
+    assert info["status"] == 0
+    for b in range(8):
+        U, Pp = S.solve(*S.rhs(fs[b]))
+        assert _rel(u[b].cpu().numpy(), S.full_velocity(U)) <= 1e-8
+        assert _rel(p[b].cpu().numpy(), Pp) <= 1e-8
+
+
 def test_mass_bounds_are_element_constants(gpu_lib):
     P = _problem(3, 3)
     b = P.bounds()
