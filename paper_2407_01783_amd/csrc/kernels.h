@@ -844,46 +844,89 @@ struct Coef8 {
   double v[8];
 };
 
-// partial dots h[i][r] = V_i . w over blockIdx.y = i; block partials to part
-template <typename TV, int D, int NRB>
-__global__ __launch_bounds__(kBlock) void k_mdot(int64_t n_int, int64_t n_p1, const TV* __restrict__ V, int64_t ldv,
-                                                 const double* __restrict__ w, double* __restrict__ part) {
-  constexpr int W = D * NRB;
-  const TV* v = V + (int64_t)blockIdx.y * ldv;
-  const int64_t nv = n_int * W;
-  double acc[NRB];
+// Both kernels map NRB lanes to one row (lane `sub` = right-hand side sub),
+// so the lanes of a row read its W contiguous values together.
+
+// Sum over the lanes of a wavefront that share lane mod G (G a power of two
+// up to 64); lanes 0..G-1 then hold the G sums.
+template <int G>
+__device__ __forceinline__ double wave_sum_strided(double x) {
 #pragma unroll
-  for (int r = 0; r < NRB; ++r) acc[r] = 0;
-  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n_int + n_p1;
-       row += (int64_t)gridDim.x * blockDim.x) {
-    if (row < n_int) {
-#pragma unroll
-      for (int r = 0; r < NRB; ++r)
-#pragma unroll
-        for (int d = 0; d < D; ++d) acc[r] += (double)v[row * W + r * D + d] * w[row * W + r * D + d];
-    } else {
-      const int64_t pr = row - n_int;
-#pragma unroll
-      for (int r = 0; r < NRB; ++r) acc[r] += (double)v[nv + pr * NRB + r] * w[nv + pr * NRB + r];
-    }
-  }
-  __shared__ double tot[NRB];
-  block_sum<NRB>(acc, tot);
-  if (threadIdx.x < NRB) part[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * NRB + threadIdx.x] = tot[threadIdx.x];
+  for (int off = 32; off >= G; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
 }
 
-// h[i][r] = sum over blocks of part (one block per i, fixed order)
+constexpr int kMdotChunk = 8;  // basis vectors per pass over w
+
+// Partial dots h[j][r] = V_j . w for the basis vectors j of chunk blockIdx.y
+// (kMdotChunk at a time, so w is read once per chunk): block partials to
+// part[((chunk * gridDim.x + block) * kMdotChunk + j) * NRB + r].
+template <typename TV, int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_mdot(int64_t n_int, int64_t n_p1, const TV* __restrict__ V, int64_t ldv,
+                                                 int nb, const double* __restrict__ w, double* __restrict__ part) {
+  constexpr int W = D * NRB, CH = kMdotChunk;
+  const int sub = (int)(threadIdx.x % NRB);
+  const int j0 = blockIdx.y * CH;
+  const int nj = nb - j0 < CH ? nb - j0 : CH;
+  const int64_t nv = n_int * W;
+  double acc[CH];
+#pragma unroll
+  for (int j = 0; j < CH; ++j) acc[j] = 0;
+  for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / NRB; t < n_int + n_p1;
+       t += (int64_t)gridDim.x * blockDim.x / NRB) {
+    if (t < n_int) {
+      const int64_t o = t * W + sub * D;
+      double wv[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) wv[d] = w[o + d];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        if (j < nj) {
+          const TV* v = V + (int64_t)(j0 + j) * ldv + o;
+          double s = 0;
+#pragma unroll
+          for (int d = 0; d < D; ++d) s += (double)v[d] * wv[d];
+          acc[j] += s;
+        }
+      }
+    } else {
+      const int64_t o = nv + (t - n_int) * NRB + sub;
+      const double wv = w[o];
+#pragma unroll
+      for (int j = 0; j < CH; ++j)
+        if (j < nj) acc[j] += (double)V[(int64_t)(j0 + j) * ldv + o] * wv;
+    }
+  }
+  __shared__ double sh[kBlock / 64][CH][NRB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < CH; ++j) {
+    const double s = wave_sum_strided<NRB>(acc[j]);
+    if (lane < NRB) sh[wave][j][lane] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < CH * NRB) {
+    const int j = threadIdx.x / NRB, r = threadIdx.x % NRB;
+    double s = 0;
+    for (int q = 0; q < kBlock / 64; ++q) s += sh[q][j][r];
+    part[(((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * CH + j) * NRB + r] = s;
+  }
+}
+
+// h[i][r] = sum over blocks of the partials of basis vector i (one block per
+// i, fixed order)
 template <int NRB>
 __global__ __launch_bounds__(kBlock) void k_mdot_fin(int nblk, const double* __restrict__ part, double* __restrict__ h) {
+  const int i = blockIdx.x, ch = i / kMdotChunk, j = i % kMdotChunk;
   double acc[NRB];
 #pragma unroll
   for (int r = 0; r < NRB; ++r) acc[r] = 0;
   for (int b = threadIdx.x; b < nblk; b += blockDim.x)
 #pragma unroll
-    for (int r = 0; r < NRB; ++r) acc[r] += part[((int64_t)blockIdx.x * nblk + b) * NRB + r];
+    for (int r = 0; r < NRB; ++r) acc[r] += part[(((int64_t)ch * nblk + b) * kMdotChunk + j) * NRB + r];
   __shared__ double tot[NRB];
   block_sum<NRB>(acc, tot);
-  if (threadIdx.x < NRB) h[blockIdx.x * NRB + threadIdx.x] = tot[threadIdx.x];
+  if (threadIdx.x < NRB) h[i * NRB + threadIdx.x] = tot[threadIdx.x];
 }
 
 // w += sgn * sum_{i<nb} h[i][r] V_i ; NORM: res[r] = ||w_r||^2 after the update
@@ -895,47 +938,40 @@ __global__ __launch_bounds__(kBlock) void k_mupdate(int64_t n_int, int64_t n_p1,
   __shared__ double hs[64 * NRB];
   for (int i = threadIdx.x; i < nb * NRB; i += blockDim.x) hs[i] = sgn * h[i];
   __syncthreads();
+  const int sub = (int)(threadIdx.x % NRB);
   const int64_t nv = n_int * W;
-  double part[NRB];
+  double part = 0;
+  for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / NRB; t < n_int + n_p1;
+       t += (int64_t)gridDim.x * blockDim.x / NRB) {
+    if (t < n_int) {
+      const int64_t o = t * W + sub * D;
+      double a[D];
 #pragma unroll
-  for (int r = 0; r < NRB; ++r) part[r] = 0;
-  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n_int + n_p1;
-       row += (int64_t)gridDim.x * blockDim.x) {
-    if (row < n_int) {
-      double a[W];
-#pragma unroll
-      for (int k = 0; k < W; ++k) a[k] = w[row * W + k];
+      for (int d = 0; d < D; ++d) a[d] = w[o + d];
       for (int i = 0; i < nb; ++i) {
-        const TV* v = V + (int64_t)i * ldv + row * W;
+        const TV* v = V + (int64_t)i * ldv + o;
+        const double hi = hs[i * NRB + sub];
 #pragma unroll
-        for (int r = 0; r < NRB; ++r)
-#pragma unroll
-          for (int d = 0; d < D; ++d) a[r * D + d] += hs[i * NRB + r] * (double)v[r * D + d];
+        for (int d = 0; d < D; ++d) a[d] += hi * (double)v[d];
       }
 #pragma unroll
-      for (int k = 0; k < W; ++k) {
-        w[row * W + k] = a[k];
-        if (NORM) part[k / D] += a[k] * a[k];
+      for (int d = 0; d < D; ++d) {
+        w[o + d] = a[d];
+        if (NORM) part += a[d] * a[d];
       }
     } else {
-      const int64_t pr = row - n_int;
-      double a[NRB];
-#pragma unroll
-      for (int r = 0; r < NRB; ++r) a[r] = w[nv + pr * NRB + r];
-      for (int i = 0; i < nb; ++i) {
-        const TV* v = V + (int64_t)i * ldv + nv + pr * NRB;
-#pragma unroll
-        for (int r = 0; r < NRB; ++r) a[r] += hs[i * NRB + r] * (double)v[r];
-      }
-#pragma unroll
-      for (int r = 0; r < NRB; ++r) {
-        w[nv + pr * NRB + r] = a[r];
-        if (NORM) part[r] += a[r] * a[r];
-      }
+      const int64_t o = nv + (t - n_int) * NRB + sub;
+      double a = w[o];
+      for (int i = 0; i < nb; ++i) a += hs[i * NRB + sub] * (double)V[(int64_t)i * ldv + o];
+      w[o] = a;
+      if (NORM) part += a * a;
     }
   }
   if (NORM) {
-    grid_reduce<NRB>(part, partials);
+    double pf[NRB];
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) pf[r] = r == sub ? part : 0.0;
+    grid_reduce<NRB>(pf, partials);
   }
 }
 

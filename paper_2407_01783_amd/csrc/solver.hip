@@ -449,8 +449,9 @@ class Engine {
     double* w = static_cast<double*>(c_->workspace("gm_w", nc * sizeof(double)));
     double* zd = static_cast<double*>(c_->workspace("gm_zd", nc * sizeof(double)));
     T* vin = buf("gm_vin", nc);
-    const int nbx = ops::grid_for(c_->n_int + c_->n_p1);
-    double* part = static_cast<double*>(c_->workspace("gm_part", (int64_t)(m + 1) * nbx * 8 * sizeof(double)));
+    const int nbx = ops::grid_for((c_->n_int + c_->n_p1) * nrb_);
+    double* part = static_cast<double*>(
+        c_->workspace("gm_part", (int64_t)((m + 1 + kMdotChunk - 1) / kMdotChunk) * nbx * kMdotChunk * 8 * sizeof(double)));
     double* hdev = static_cast<double*>(c_->workspace("gm_h", 3 * 64 * 8 * sizeof(double)));
     double* h1 = hdev;
     double* h2 = hdev + 64 * 8;
@@ -462,8 +463,8 @@ class Engine {
     auto mdot = [&](const double* Vb, int nb, const double* x, double* hout) {
       dispatch_dn(D_, nrb_, [&](auto Dc, auto Nc) {
         constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
-        hipLaunchKernelGGL((k_mdot<double, D, N>), dim3(nbx, nb), dim3(kBlock), 0, c_->stream, c_->n_int, c_->n_p1,
-                           Vb, nc, x, part);
+        hipLaunchKernelGGL((k_mdot<double, D, N>), dim3(nbx, (nb + kMdotChunk - 1) / kMdotChunk), dim3(kBlock), 0,
+                           c_->stream, c_->n_int, c_->n_p1, Vb, nc, nb, x, part);
         ops::check_launch();
         hipLaunchKernelGGL((k_mdot_fin<N>), dim3(nb), dim3(kBlock), 0, c_->stream, nbx, (const double*)part, hout);
       });
