@@ -718,6 +718,30 @@ void assemble_ctx(stokes_ctx* c) {
   up_csr(P2full, c->p2full);
   up_csr(Bfull, c->bfull);
   up_csr(P1, c->p1);
+  {
+    // boundary coupling of interior rows (load vector and Dirichlet lifting)
+    std::vector<int32_t> rows, ptr(1, 0), cols, src;
+    for (int64_t k = 0; k < c->n_int; ++k) {
+      const int32_t v = c->h_int2nat[k];
+      const size_t before = cols.size();
+      for (int64_t e = P2full.rowptr[v]; e < P2full.rowptr[v + 1]; ++e) {
+        if (!m.p2_bnd[P2full.cols[e]]) continue;
+        cols.push_back(P2full.cols[e]);
+        src.push_back(static_cast<int32_t>(e));
+      }
+      if (cols.size() > before) {
+        rows.push_back(static_cast<int32_t>(k));
+        ptr.push_back(static_cast<int32_t>(cols.size()));
+      }
+    }
+    c->n_bc = static_cast<int64_t>(rows.size());
+    if (c->n_bc > 0) {
+      upload(c->bc_rows, rows);
+      upload(c->bc_ptr, ptr);
+      upload(c->bc_cols, cols);
+      upload(c->bc_src, src);
+    }
+  }
 
   // ---- element gathers (FP64, full numbering)
   const int64_t nnz2 = c->p2full.nnz, nnzb = c->bfull.nnz, nnz1 = c->p1.nnz;

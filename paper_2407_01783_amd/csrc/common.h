@@ -135,6 +135,10 @@ struct stokes_ctx {
   // full-numbering CSR matrices (assembly products)
   stokes::DevCsr p2full, bfull, p1;
   stokes::DevCsr xl;              // P1 x P1 pattern of B_I Lambda_V^-1 B_I^T
+  // interior rows with boundary neighbours: internal row ids, CSR over their
+  // boundary columns (natural ids) and the entry index in the p2full pattern
+  int64_t n_bc = 0;
+  stokes::DevBuf bc_rows, bc_ptr, bc_cols, bc_src;
   stokes::DevBuf XL_csr;          // double [nnz xl]
   stokes::DevBuf M_full, L_full;  // double [nnz p2full]
   stokes::DevBuf B_full;          // double [nnz bfull][dim]

@@ -707,45 +707,39 @@ __global__ __launch_bounds__(kBlock) void k_p_out(int64_t n_p1, const T* __restr
 
 // ------------------------------------------------- right-hand side (FP64)
 
-// F~ on interior rows: F~ = (M f)_I - ((alpha M + mu L) G)_I, G = ubc on the
-// boundary columns; CSR over all P2 nodes, output internal layout.  One
-// wavefront per row: the lanes read the row's entries contiguously and the
-// partial sums are combined with wavefront shuffles.
+// Boundary columns of the load vector and the lifting, on the interior rows
+// that touch the boundary: F[row] += sum_{c in Gamma} (M_ic f_c - A_ic G_c)
+// (the interior columns of M f come from the sliced-ELL mass product).
 template <int D, int NRB>
-__global__ __launch_bounds__(kBlock) void k_rhs_u(int64_t n_int, int64_t n_p2, const int32_t* __restrict__ int2nat,
-                                                  const int32_t* __restrict__ nat2int,
-                                                  const int32_t* __restrict__ rp, const int32_t* __restrict__ cols,
-                                                  const double* __restrict__ M, const double* __restrict__ L,
-                                                  double alpha, double mu, const double* __restrict__ f,
-                                                  const double* __restrict__ ubc, double* __restrict__ F) {
+__global__ __launch_bounds__(kBlock) void k_rhs_bnd(int64_t nbc, int64_t n_p2, const int32_t* __restrict__ rows,
+                                                    const int32_t* __restrict__ ptr, const int32_t* __restrict__ cols,
+                                                    const int32_t* __restrict__ src, const double* __restrict__ M,
+                                                    const double* __restrict__ L, double alpha, double mu,
+                                                    const double* __restrict__ f, const double* __restrict__ ubc,
+                                                    double* __restrict__ F) {
   constexpr int W = D * NRB;
-  const int lane = threadIdx.x & 63;
-  const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
-  for (int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); row < n_int; row += waves) {
-    const int64_t nat = int2nat[row];
+  GRID_STRIDE_ROWS(q, nbc) {
     double acc[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = 0;
-    for (int64_t k = rp[nat] + lane; k < rp[nat + 1]; k += 64) {
+    for (int32_t k = ptr[q]; k < ptr[q + 1]; ++k) {
       const int64_t c = cols[k];
-      const double m = M[k];
-      const bool bnd = nat2int[c] < 0;
-      const double a = alpha * m + mu * L[k];
+      const int64_t e = src[k];
+      const double m = M[e];
+      const double a = alpha * m + mu * L[e];
 #pragma unroll
       for (int r = 0; r < NRB; ++r)
 #pragma unroll
         for (int d = 0; d < D; ++d) {
           const int64_t o = ((int64_t)r * D + d) * n_p2 + c;
           double v = f ? m * f[o] : 0.0;
-          if (bnd && ubc) v -= a * ubc[o];
+          if (ubc) v -= a * ubc[o];
           acc[r * D + d] += v;
         }
     }
+    const int64_t row = rows[q];
 #pragma unroll
-    for (int w = 0; w < W; ++w) acc[w] = wave_sum(acc[w]);
-    if (lane == 0)
-#pragma unroll
-      for (int w = 0; w < W; ++w) F[row * W + w] = acc[w];
+    for (int w = 0; w < W; ++w) F[row * W + w] += acc[w];
   }
 }
 

@@ -474,12 +474,24 @@ void p_out(stokes_ctx* c, int nrb, const T* src, double* dst) {
 }
 
 void rhs(stokes_ctx* c, int nrb, const double* f, const double* ubc, double* F, double* g) {
+  // F~ = (M_V f)_I - A_{I,Gamma} G: interior columns by the sliced-ELL mass
+  // product on f_I, boundary columns on the rows that touch the boundary
+  const int W = c->dim * nrb;
+  if (f) {
+    double* fI = static_cast<double*>(c->workspace("rhs_fI", c->n_int * W * sizeof(double)));
+    vel_in<double>(c, nrb, f, fI);
+    spmv<double>(c, c->sA, c->MV64.as<double>(), W, fI, F, 1.0, nullptr, 0.0);
+  } else {
+    hipLaunchKernelGGL((k_set<double>), dim3(grid_for(c->n_int * W)), dim3(kBlock), 0, c->stream, c->n_int * W, 0.0,
+                       F);
+  }
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
     constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
-    hipLaunchKernelGGL((k_rhs_u<D, N>), dim3(grid_for(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int, c->n_p2,
-                       c->int2nat.as<int32_t>(), c->nat2int.as<int32_t>(), c->p2full.rowptr.as<int32_t>(),
-                       c->p2full.cols.as<int32_t>(), c->M_full.as<double>(), c->L_full.as<double>(), c->prob.alpha,
-                       c->prob.mu, f, ubc, F);
+    if (c->n_bc > 0 && (f || ubc))
+      hipLaunchKernelGGL((k_rhs_bnd<D, N>), dim3(grid_for(c->n_bc)), dim3(kBlock), 0, c->stream, c->n_bc, c->n_p2,
+                         c->bc_rows.as<int32_t>(), c->bc_ptr.as<int32_t>(), c->bc_cols.as<int32_t>(),
+                         c->bc_src.as<int32_t>(), c->M_full.as<double>(), c->L_full.as<double>(), c->prob.alpha,
+                         c->prob.mu, f, ubc, F);
     check_launch();
     hipLaunchKernelGGL((k_rhs_p<D, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1, c->n_p2,
                        c->nat2int.as<int32_t>(), c->bfull.rowptr.as<int32_t>(), c->bfull.cols.as<int32_t>(),
