@@ -110,3 +110,56 @@ def test_fullsize_benchmark_solve_residual_rows(cube64, precision):
     rhs_est = np.sqrt(n_u * np.mean(rf ** 2))
     print(f"[solve] sampled residual estimate {res_est / rhs_est:.2e}", flush=True)
     assert res_est <= 2.0 * opts["rtol"] * rhs_est
+
+
+# ------------------------------------------------------------------ cube32 sweep
+# 3D n = 32 (jitter seed 0, dt = 1e-2, forcing seed 1000): both methods and
+# the preconditioner variants across the paper's mu range, with and without
+# the augmented Lagrangian (the solution does not depend on gamma); every
+# solve is checked on sampled residual rows of the plain system.
+
+C2_N, C2_SEED, C2_DT, C2_FSEED = 32, 0, 1e-2, 1000
+
+
+@pytest.fixture(scope="module")
+def cube32_mesh():
+    return omesh.KuhnMesh(3, C2_N, seed=C2_SEED, jitter=0.1)
+
+
+def _sampled_rel_res(m, mu, alpha, f, uf, pp, seed):
+    rng = np.random.default_rng(seed)
+    nodes = _sample(rng, m.interior_nodes, 100)
+    vrows = [(c, i) for c in range(3) for i in nodes]
+    prow = _sample(rng, m.n_p1, 100)
+    rm, rpr, rf = ofem.residual_rows(m, mu, alpha, f, uf, pp, vrows, prow)
+    n_u, n_p = 3 * m.n_free_nodes, m.n_p1
+    return np.sqrt(n_u * np.mean(rm ** 2) + n_p * np.mean(rpr ** 2)) / np.sqrt(n_u * np.mean(rf ** 2))
+
+
+C2_CASES = [
+    # (method, precision, options)
+    ("coupled", 1, dict(coupled_pc=1, inner_mode=1, cheb_degree=6)),
+    ("coupled", 0, dict(coupled_pc=0)),
+    ("schur", 0, dict(schur_pc=1)),
+]
+
+
+@pytest.mark.parametrize("mu", [1.0, 1e-2, 1e-4])
+@pytest.mark.parametrize("gamma", [0.0, 10.0])
+@pytest.mark.parametrize("case", range(len(C2_CASES)))
+def test_cube32_mu_gamma_sweep_residual_rows(gpu_lib, cube32_mesh, mu, gamma, case):
+    from paper_2407_01783_amd.stokes import StokesProblem
+    method, precision, extra = C2_CASES[case]
+    m = cube32_mesh
+    alpha = 1.0 / C2_DT
+    print(f"[case] cube32 mu={mu} gamma={gamma} {method} precision={precision} {extra}", flush=True)
+    prob = StokesProblem(3, C2_N, mesh_seed=C2_SEED, jitter=0.1, mu=mu, alpha=alpha, gamma=gamma)
+    f = inputs.fourier_forcing(m.p2coords, C2_FSEED)
+    # the augmented velocity block at mu = 1 is the hard case of the paper
+    # (its condition number grows with gamma): allow more refinement sweeps
+    u, p, info = prob.solve(torch.tensor(f[None], device="cuda"), method=method, precision=precision, rtol=1e-8,
+                            max_outer=3000, max_refine=40, **extra)
+    print(f"[solve] {info}", flush=True)
+    assert info["status"] == 0 and info["rel_res"] <= 1e-8
+    est = _sampled_rel_res(m, mu, alpha, f, u.cpu().numpy()[0], p.cpu().numpy()[0], 31)
+    assert est <= 2e-8, est
