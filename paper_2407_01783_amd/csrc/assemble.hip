@@ -312,6 +312,17 @@ __global__ __launch_bounds__(kBlock) void k_gather_b(int64_t n_p1, const int64_t
   }
 }
 
+// column-scaled copy: out[k] = vals[k] * dinv[cols[k]] over the SELL entries
+__global__ __launch_bounds__(kBlock) void k_scale_cols(int64_t n, const int32_t* __restrict__ cols,
+                                                       const double* __restrict__ vals, const double* __restrict__ dinv,
+                                                       double* __restrict__ out, float* __restrict__ out32) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const double v = vals[k] * dinv[cols[k]];
+    out[k] = v;
+    out32[k] = (float)v;
+  }
+}
+
 // rows of X = B_I Lambda_V^-1 B_I^T (lumped-mass pressure operator of Sec. 4.3),
 // one wavefront per P1 row k: each lane owns output entries (k, l) and merges
 // the sorted B rows k and l, summing over the shared interior P2 columns j
@@ -836,6 +847,10 @@ void assemble_ctx(stokes_ctx* c) {
            out.as<double>());
   };
   dinv(c->sA, c->A64, c->dA64);
+  c->AD64.alloc(c->sA.nnz_pad * sizeof(double));
+  c->AD32.alloc(c->sA.nnz_pad * sizeof(float));
+  launch(c, c->sA.nnz_pad, k_scale_cols, c->sA.nnz_pad, c->sA.cols.as<int32_t>(), c->A64.as<double>(),
+         c->dA64.as<double>(), c->AD64.as<double>(), c->AD32.as<float>());
   dinv(c->sA, c->MV64, c->dMV64);
   dinv(c->sQ, c->MQ64, c->dMQ64);
   dinv(c->sQ, c->XQ64, c->dXQ64);
@@ -1057,6 +1072,8 @@ void reform_A(stokes_ctx* c) {
   launch(c, c->sA.nrows, k_dinv, c->sA.nrows, c->sA.slice_ptr.as<int64_t>(), c->sA.cols.as<int32_t>(),
          c->A64.as<double>(), c->dA64.as<double>());
   launch(c, c->n_int, k_cast<double, float>, c->n_int, c->dA64.as<double>(), c->dA32.as<float>());
+  launch(c, n, k_scale_cols, n, c->sA.cols.as<int32_t>(), c->A64.as<double>(), c->dA64.as<double>(),
+         c->AD64.as<double>(), c->AD32.as<float>());
   double lo, hi, g;
   lanczos_bounds(c, c->sA, c->A64.as<double>(), c->dA64.as<double>(), 40, lo, hi, g);
   c->bA.hi = std::min(g, 1.1 * hi);

@@ -157,6 +157,7 @@ struct stokes_ctx {
   stokes::Sell sQ;   // P1 x P1, scalar values
   stokes::Sell sX;   // P1 x P1, B_I Lambda_V^-1 B_I^T (two-ring stencil)
   stokes::DevBuf A64, A32, MV64, MV32;       // values of A_II and M_II (SELL)
+  stokes::DevBuf AD64, AD32;                 // A_II D^{-1}: column-scaled copy (first Chebyshev step)
   stokes::DevBuf B64, B32, Bt64, Bt32;       // [nnz_pad][dim]
   stokes::DevBuf MQ64, MQ32, LQ64, LQ32, XQ64, XQ32;  // XQ = M_Q + L_Q
   stokes::DevBuf dA64, dA32, dMV64, dMV32;   // inverse diagonals (interior)

@@ -494,7 +494,8 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, const int64
 // formed on the fly at every gathered column, so no separate pass is needed:
 //   res = r - S d0 ;  d1 = c1 d0 + c2 dinv res ;  z = d0 + d1
 // ACC: z += d0 + d1 (z holds a previous approximation) instead of z = d0 + d1
-template <typename T, int W, int ACC, int G>
+// SC: vals already hold S_ij dinv_j (no gather of dinv at the columns).
+template <typename T, int W, int ACC, int G, int SC>
 __global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, const int64_t* __restrict__ sp,
                                                        const int32_t* __restrict__ cols, const T* __restrict__ vals,
                                                        const T* __restrict__ r, const T* __restrict__ dinv, T theta_inv,
@@ -510,7 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, const int6
     const T* rs_ = r + sub * WG;
     for (int64_t k = sp[s] + (row & 63); k < end; k += 64) {
       const int32_t c = __builtin_nontemporal_load(cols + k);
-      const T v = __builtin_nontemporal_load(vals + k) * dinv[c];
+      const T v = SC ? __builtin_nontemporal_load(vals + k) : __builtin_nontemporal_load(vals + k) * dinv[c];
       const T* xp = rs_ + (int64_t)c * W;
 #pragma unroll
       for (int w = 0; w < WG; ++w) acc[w] = fma(v, xp[w], acc[w]);

@@ -330,19 +330,24 @@ template <class T>
 void cheb_first(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* r, const T* dinv, T theta_inv, T* d1,
                 T* res, T* z, T c1, T c2, int accumulate) {
   const int G = lanes_op(c, &S, W, std::is_same<T, float>::value);
+  // the velocity operator has a column-scaled copy S D^{-1}
+  const T* scaled = (&S == &c->sA && vals == avals<T>(c).template as<T>()) ? pick<T>(c->AD64, c->AD32) : nullptr;
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       const int nb = grid_for(S.nrows * GG);
-      if (accumulate)
-        hipLaunchKernelGGL((k_cheb_first<T, WW, 1, GG>), dim3(nb), dim3(kBlock), 0, c->stream, S.nrows,
-                           S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, r, dinv, theta_inv, d1, res, z, c1,
-                           c2);
-      else
-        hipLaunchKernelGGL((k_cheb_first<T, WW, 0, GG>), dim3(nb), dim3(kBlock), 0, c->stream, S.nrows,
-                           S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, r, dinv, theta_inv, d1, res, z, c1,
-                           c2);
+      auto go = [&](auto kern, const T* v) {
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, S.nrows, S.slice_ptr.as<int64_t>(),
+                           S.cols.as<int32_t>(), v, r, dinv, theta_inv, d1, res, z, c1, c2);
+      };
+      if (scaled) {
+        if (accumulate) go(k_cheb_first<T, WW, 1, GG, 1>, scaled);
+        else go(k_cheb_first<T, WW, 0, GG, 1>, scaled);
+      } else {
+        if (accumulate) go(k_cheb_first<T, WW, 1, GG, 0>, vals);
+        else go(k_cheb_first<T, WW, 0, GG, 0>, vals);
+      }
     });
   });
   check_launch();
