@@ -193,11 +193,14 @@ class Matrices:
     B      : list of d (n_p1, n_p2) CSR planes sharing one pattern
     MQ, LQ : (n_p1, n_p1) CSR
     Lam    : (n_p2,) lumped |phi| mass
+    D      : d x d list of (n_p2, n_p2) CSR grad-div blocks on the Ms pattern,
+             D[a][b][i, j] = int d_a phi_i d_b phi_j (only with grad_div=True)
     """
 
-    def __init__(self, Ms, Ls, B, MQ, LQ, Lam, vol, grad):
+    def __init__(self, Ms, Ls, B, MQ, LQ, Lam, vol, grad, D=None):
         self.Ms, self.Ls, self.B, self.MQ, self.LQ, self.Lam = Ms, Ls, B, MQ, LQ, Lam
         self.vol, self.grad = vol, grad
+        self.D = D
 
 
 def _coo_to_csr(rows, cols, vals, shape):
@@ -207,8 +210,12 @@ def _coo_to_csr(rows, cols, vals, shape):
     return A
 
 
-def assemble(mesh):
-    """Assemble every matrix of Sec. 2.2 / 3.2 / 4.1 on ``mesh`` (COO -> CSR)."""
+def assemble(mesh, grad_div=False):
+    """Assemble every matrix of Sec. 2.2 / 3.2 / 4.1 on ``mesh`` (COO -> CSR).
+
+    grad_div=True also assembles the grad-div blocks D of Sec. 3.2
+    (D_ij = int div phi_i div phi_j for vector basis functions phi_i = phi e_a),
+    as the d x d scalar blocks D[a][b][i, j] = int d_a phi_i d_b phi_j."""
     d = mesh.dim
     ref = reference_tensors(d)
     vol, grad, _ = element_geometry(mesh)
@@ -240,7 +247,14 @@ def assemble(mesh):
 
     Lam = np.zeros(mesh.n_p2)
     np.add.at(Lam, P2.ravel(), (vol[:, None] * ref["absphi"][None]).ravel())
-    return Matrices(Ms, Ls, B, MQ, LQ, Lam, vol, grad)
+    D = None
+    if grad_div:
+        D = [[None] * d for _ in range(d)]
+        for a in range(d):
+            for b in range(d):
+                De = vol[:, None, None] * np.einsum("ep,eq,ipjq->eij", grad[:, :, a], grad[:, :, b], ref["T"])
+                D[a][b] = _coo_to_csr(r2, c2, De.ravel(), shape2)
+    return Matrices(Ms, Ls, B, MQ, LQ, Lam, vol, grad, D)
 
 
 def element_matrices(mesh, e):
@@ -256,6 +270,7 @@ def element_matrices(mesh, e):
     return dict(
         M=vol * ref["M"],
         L=vol * np.einsum("ab,iajb->ij", G, ref["T"]),
+        D=vol * np.einsum("pa,qb,ipjq->abij", grad, grad, ref["T"]),
         B=vol * np.einsum("ac,kia->cki", grad, ref["W"]),
         MQ=vol * ref["MQ"],
         LQ=vol * G,
@@ -289,11 +304,12 @@ def assemble_rows(mesh, rows):
     return out
 
 
-def residual_rows(mesh, mu, alpha, f, u_full, p, vel_rows, p_rows):
+def residual_rows(mesh, mu, alpha, f, u_full, p, vel_rows, p_rows, strain=False):
     """Rows of the coupled residual computed one by one from incident elements.
 
     Discrete problem of Sec. 2.2 with the velocity block alpha M_V + mu L_V
-    (the A~_{lambda,3} form of Sec. 3.2) and F = M_V f:
+    (the A~_{lambda,3} form of Sec. 3.2; strain=True: alpha M_V + mu (L_V + D),
+    the matrix A of Sec. 3.2) and F = M_V f:
       momentum row (node i, component c):
           (M f_c)_i - ((alpha M + mu L) u_c)_i + sum_k B_c[k, i] p_k
       continuity row k:   - sum_c (B_c u_c)_k
@@ -326,6 +342,8 @@ def residual_rows(mesh, mu, alpha, f, u_full, p, vel_rows, p_rows):
                 mf = em["M"][a] @ f[c, loc]
                 rf[key] += mf
                 rm[key] += mf - A[a] @ u_full[c, loc] + em["B"][c, :, a] @ p[vs]
+                if strain:
+                    rm[key] -= mu * sum(em["D"][c, b, a] @ u_full[b, loc] for b in range(d))
         for kk, k in enumerate(vs):
             if int(k) in rp:
                 rp[int(k)] -= sum(em["B"][c, kk, :] @ u_full[c, loc] for c in range(d))

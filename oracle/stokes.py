@@ -8,7 +8,10 @@ The paper's discrete problem (Sec. 2.2, Eq. "Saddle_point_A_BT_B"):
 Readings used here (listed with the others in the design notes):
 
 * viscous block: mu L_V, the vector Laplacian (the paper's A~_{lambda,3} =
-  dt^-1 M_V + mu L_V of Sec. 3.2); alpha = 1/dt.
+  dt^-1 M_V + mu L_V of Sec. 3.2); alpha = 1/dt.  strain=True uses the
+  paper's own matrix A = dt^-1 M_V + mu (L_V + D) of Sec. 3.2 (D the grad-div
+  matrix), which equals the strain-rate form 2 mu eps:eps on H^1_0; the
+  Dirichlet lifting uses the same A.
 * Dirichlet data on the whole boundary (Sec. 3.1, V = H^1_0): the velocity
   is eliminated on boundary nodes with nodal values G and lifted,
       F~ = (M_V f)_I - A_{I,Gamma} G,    g = -B_Gamma G,
@@ -37,11 +40,14 @@ class StokesSystem:
     Unknown layout: U is (d, n_I) (component-major over interior P2 nodes in
     increasing node id), P is (n_p1,)."""
 
-    def __init__(self, mesh, mu, alpha, gamma=0.0, mats=None):
+    def __init__(self, mesh, mu, alpha, gamma=0.0, mats=None, strain=False):
         self.mesh = mesh
         self.mu, self.alpha, self.gamma = float(mu), float(alpha), float(gamma)
-        self.mats = assemble(mesh) if mats is None else mats
+        self.strain = bool(strain)
+        self.mats = assemble(mesh, grad_div=self.strain) if mats is None else mats
         m = self.mats
+        if self.strain and m.D is None:
+            raise ValueError("strain=True needs matrices assembled with grad_div=True")
         self.d = mesh.dim
         self.I = mesh.interior_nodes
         self.nI = self.I.size
@@ -57,6 +63,32 @@ class StokesSystem:
         self.B_I = [b[:, self.I].tocsr() for b in m.B]
         self.mQ = m.MQ @ np.ones(self.np1)   # M_Q 1 (pressure integral weights)
         self._MQ_lu = None
+        # velocity operator on component-major vectors (index c * n_p2 + node):
+        # I_d (x) A_s, plus mu D (strain) and the viscous part E for dJ/dmu
+        d, n2 = self.d, mesh.n_p2
+        blocks, eblocks = [], []
+        for a in range(d):
+            row, erow = [], []
+            for b in range(d):
+                if a == b:
+                    Ab, Eb = self.As_full.copy(), m.Ls.copy()
+                    if self.strain:
+                        Ab.data = Ab.data + self.mu * m.D[a][a].data
+                        Eb.data = Eb.data + m.D[a][a].data
+                elif self.strain:
+                    Ab, Eb = self.mu * m.D[a][b], m.D[a][b]
+                else:
+                    Ab = Eb = None
+                row.append(Ab)
+                erow.append(Eb)
+            blocks.append(row)
+            eblocks.append(erow)
+        self.Avel_full = sp.bmat(blocks, format="csr")
+        Evel_full = sp.bmat(eblocks, format="csr")
+        self.Iv = np.concatenate([c * n2 + self.I for c in range(d)])
+        self.Avel_II = self.Avel_full[self.Iv][:, self.Iv].tocsr()
+        self.Avel_Iall = self.Avel_full[self.Iv].tocsr()
+        self.Evel_Iall = Evel_full[self.Iv].tocsr()
 
     # ------------------------------------------------------------- helpers
     def MQ_solve(self, r):
@@ -79,8 +111,9 @@ class StokesSystem:
         f = np.asarray(f, dtype=np.float64).reshape(self.d, -1)
         G = self.lift(ubc)
         F = np.empty((self.d, self.nI))
+        AG = (self.Avel_Iall @ G.ravel()).reshape(self.d, self.nI)
         for c in range(self.d):
-            F[c] = (self.mats.Ms @ f[c])[self.I] - self.A_Iall @ G[c]
+            F[c] = (self.mats.Ms @ f[c])[self.I] - AG[c]
         g = np.zeros(self.np1)
         for c in range(self.d):
             g -= self.mats.B[c] @ G[c]
@@ -96,10 +129,10 @@ class StokesSystem:
         gamma = self.gamma if gamma is None else gamma
         U = np.asarray(U).reshape(self.d, self.nI)
         BU = sum(self.B_I[c] @ U[c] for c in range(self.d))
-        RU = np.empty_like(U)
+        RU = (self.Avel_II @ U.ravel()).reshape(self.d, self.nI)
         w = self.MQ_solve(BU) if gamma != 0.0 else None
         for c in range(self.d):
-            RU[c] = self.A_II @ U[c] - self.B_I[c].T @ P
+            RU[c] = RU[c] - self.B_I[c].T @ P
             if w is not None:
                 RU[c] += gamma * self.mu * (self.B_I[c].T @ w)
         return RU, BU
@@ -126,7 +159,7 @@ class StokesSystem:
         """Sparse K = [[I_d (x) A_II, -B_I^T], [B_I, 0]], optionally bordered with
         the zero-mean constraint [0, m^T] / column [0; m] (m = M_Q 1)."""
         d = self.d
-        Ablk = sp.block_diag([self.A_II] * d, format="csr")
+        Ablk = self.Avel_II
         BT = sp.vstack([b.T for b in self.B_I], format="csr")
         Bm = sp.hstack(self.B_I, format="csr")
         if not bordered:
@@ -158,14 +191,14 @@ class StokesSystem:
     def solve_minres(self, F, g, rtol=1e-13, maxiter=5000, inner_rtol=1e-14, callback=None):
         """Preconditioned MINRES on the symmetric form [[A, B^T], [B, 0]] (U, -P).
 
-        Block-diagonal SPD preconditioner: per-component CG on A_II (Jacobi,
+        Block-diagonal SPD preconditioner: CG on the velocity block (Jacobi,
         tight tolerance) and mu M_Q^{-1} + alpha (M_Q + L_Q)^{-1} on the
         pressure, both by CG.  Only the iteration count depends on it."""
         d, nI, np1 = self.d, self.nI, self.np1
-        Ablk = sp.block_diag([self.A_II] * d, format="csr")
+        Ablk = self.Avel_II
         Bm = sp.hstack(self.B_I, format="csr")
         Ksym = sp.bmat([[Ablk, Bm.T], [Bm, None]], format="csr")
-        Dinv_A = 1.0 / self.A_II.diagonal()
+        Dinv_A = 1.0 / Ablk.diagonal()
         MQ, XQ = self.mats.MQ, (self.mats.MQ + self.mats.LQ).tocsr()
         Dinv_MQ, Dinv_XQ = 1.0 / MQ.diagonal(), 1.0 / XQ.diagonal()
 
@@ -176,8 +209,7 @@ class StokesSystem:
 
         def prec(v):
             out = np.empty_like(v)
-            for c in range(d):
-                out[c * nI:(c + 1) * nI] = cg(self.A_II, v[c * nI:(c + 1) * nI], Dinv_A)
+            out[:d * nI] = cg(Ablk, v[:d * nI], Dinv_A)
             vp = v[d * nI:]
             out[d * nI:] = self.mu * cg(MQ, vp, Dinv_MQ) + self.alpha * cg(XQ, vp, Dinv_XQ)
             return out
@@ -208,8 +240,9 @@ class StokesSystem:
         K^T = [[A, B^T], [-B, 0]], becomes the forward system after the
         substitution q = -lam_p:  A lam_u - B^T q = j_u,  B lam_u = -j_p.
         Then dJ/df_c = M_s[:, I] lam_u,c (all P2 nodes) and
-        dJ/dmu = -sum_c lam_u,c . (L_s[I, :] u_c).  Pi is the zero-mean
-        normalisation of the pressure output."""
+        dJ/dmu = -lam_u . (E[I, :] u) with E the viscous matrix (I_d (x) L_s,
+        plus D with strain).  Pi is the zero-mean normalisation of the
+        pressure output."""
         d = self.d
         ju = np.asarray(dJdu_full).reshape(d, -1)[:, self.I]
         jp = np.zeros(self.np1) if dJdp is None else np.asarray(dJdp, dtype=np.float64)
@@ -218,14 +251,12 @@ class StokesSystem:
         lam_u, q = self.solve(ju, -jp, method=method, **kw)
         lam_p = -q
         dJdf = np.zeros((d, self.mesh.n_p2))
-        Ls_I = self.mats.Ls[self.I]
-        dJdmu = 0.0
         u_full = np.asarray(u_full).reshape(d, -1)
         for c in range(d):
             ext = np.zeros(self.mesh.n_p2)
             ext[self.I] = lam_u[c]
             dJdf[c] = self.mats.Ms @ ext
-            dJdmu -= lam_u[c] @ (Ls_I @ u_full[c])
+        dJdmu = -float(lam_u.ravel() @ (self.Evel_Iall @ u_full.ravel()))
         return dJdf, dJdmu, lam_u, lam_p
 
 

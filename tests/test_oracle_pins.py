@@ -153,6 +153,7 @@ def test_element_matrices_vs_nodal_quadrature(dim):
         mons1, C1 = _lagrange(X, 1)
         nl, nv = nodes2.shape[0], dim + 1
         M, L = np.zeros((nl, nl)), np.zeros((nl, nl))
+        Dq = np.zeros((dim, dim, nl, nl))
         B = np.zeros((dim, nv, nl))
         MQ, LQ = np.zeros((nv, nv)), np.zeros((nv, nv))
         absphi = np.zeros(nl)
@@ -164,6 +165,7 @@ def test_element_matrices_vs_nodal_quadrature(dim):
             ww = w * detJ
             M += ww * np.outer(p2, p2)
             L += ww * g2.T @ g2
+            Dq += ww * np.einsum("ai,bj->abij", g2, g2)
             for c in range(dim):
                 B[c] += ww * np.outer(p1, g2[c])
             MQ += ww * np.outer(p1, p1)
@@ -172,6 +174,7 @@ def test_element_matrices_vs_nodal_quadrature(dim):
         scale = np.abs(em["M"]).max()
         assert np.allclose(em["M"], M, rtol=0, atol=1e-13 * scale)
         assert np.allclose(em["L"], L, rtol=0, atol=1e-12 * np.abs(L).max())
+        assert np.allclose(em["D"], Dq, rtol=0, atol=1e-12 * np.abs(Dq).max())   # grad-div blocks
         assert np.allclose(em["B"], B, rtol=0, atol=1e-12 * np.abs(B).max())
         assert np.allclose(em["MQ"], MQ, rtol=0, atol=1e-13 * np.abs(MQ).max())
         assert np.allclose(em["LQ"], LQ, rtol=0, atol=1e-12 * np.abs(LQ).max())
@@ -270,6 +273,126 @@ def test_residual_rows_match_assembled_system():
         assert np.abs(rm).max() <= 1e-10 * scale
         # continuity holds up to the l2-mean removed from g (compatibility)
         assert np.abs(rp - rp.mean()).max() <= 1e-10 * scale
+
+
+def test_grad_div_identities():
+    """The grad-div blocks D[a][b]_ij = int d_a phi_i d_b phi_j against facts
+    that do not depend on how they were computed:
+    * H^1_0 identity (integration by parts twice, Sec. 3.2): for interior
+      nodes i, j, int d_b phi_i d_a phi_j = int d_a phi_i d_b phi_j, i.e.
+      D[b][a]_II = D[a][b]_II -- but not between two boundary nodes;
+    * rigid motions have zero strain: (I (x) L_s + T) u = 0 on every row, with
+      T[a][b] = D[b][a] the transposed-gradient form;
+    * a divergence-free linear field u = (y, z, x) has D u = 0 on every row;
+    * sum_a D[a][a] restricted to one component of a linear field x_a e_a
+      gives int d_a phi_i = 0 for interior i."""
+    for dim, n in ((2, 4), (3, 3)):
+        m = mesh.KuhnMesh(dim, n, seed=4, jitter=0.15)
+        mats = fem.assemble(m, grad_div=True)
+        D, I = mats.D, m.interior_nodes
+        scale = max(abs(D[a][b]).max() for a in range(dim) for b in range(dim))
+        for a in range(dim):
+            for b in range(dim):
+                assert abs(D[a][b] - D[b][a].T).max() <= 1e-14 * scale          # symmetric operator
+                dII = (D[a][b][I][:, I] - D[b][a][I][:, I])
+                assert abs(dII).max() <= 1e-12 * scale, (a, b)
+        Gm = np.nonzero(m.p2_boundary)[0]                                          # both nodes on the boundary:
+        assert abs(D[0][1][Gm][:, Gm] - D[1][0][Gm][:, Gm]).max() > 1e-3 * scale  # the identity fails
+        x = m.p2coords
+        rigid = [np.stack([-x[:, 1], x[:, 0]] + ([np.zeros(m.n_p2)] if dim == 3 else []))]
+        if dim == 3:
+            rigid += [np.stack([np.zeros(m.n_p2), -x[:, 2], x[:, 1]]), np.stack([x[:, 2], np.zeros(m.n_p2), -x[:, 0]])]
+        rigid += [np.stack([np.ones(m.n_p2) if c == k else np.zeros(m.n_p2) for c in range(dim)]) for k in range(dim)]
+        lscale = abs(mats.Ls).max()
+        for u in rigid:
+            for a in range(dim):
+                Eu = mats.Ls @ u[a] + sum(D[b][a] @ u[b] for b in range(dim))
+                assert np.abs(Eu).max() <= 1e-12 * lscale * np.abs(u).max()
+        cyc = np.stack([x[:, (c + 1) % dim] for c in range(dim)])                 # (y, x) / (y, z, x)
+        for a in range(dim):
+            assert np.abs(sum(D[a][b] @ cyc[b] for b in range(dim))).max() <= 1e-13 * scale
+        for a in range(dim):
+            assert np.abs((D[a][a] @ x[:, a])[I]).max() <= 1e-13 * scale
+
+
+def test_strain_system_solutions_agree():
+    """Strain form A = alpha M + mu (L + D): direct, dense least squares and
+    MINRES reach the same solution, with Dirichlet data; the momentum residual
+    vanishes row by row (residual_rows with the grad-div term)."""
+    for dim, n in ((2, 3), (3, 2)):
+        m = mesh.KuhnMesh(dim, n, seed=2, jitter=0.1)
+        s = stokes.StokesSystem(m, 0.3, 20.0, strain=True)
+        rng = np.random.default_rng(dim)
+        f = inputs.fourier_forcing(m.p2coords, 1000 + dim)
+        ubc = rng.standard_normal((dim, m.n_p2))
+        F, g = s.rhs(f, ubc)
+        U1, P1 = s.solve_direct(F, g)
+        U2, P2 = s.solve_dense_lstsq(F, g)
+        U3, P3, _ = s.solve_minres(F, g, rtol=1e-13)
+        for U, P in ((U2, P2), (U3, P3)):
+            assert np.abs(U - U1).max() <= 1e-9 * np.abs(U1).max()
+            assert np.abs(P - P1).max() <= 1e-8 * np.abs(P1).max()
+        assert s.residual(U1, P1, F, g) < 1e-12
+        uf = s.full_velocity(U1, ubc)
+        rows = [(c, int(i)) for c in range(dim) for i in m.interior_nodes]
+        rm, _, _ = fem.residual_rows(m, s.mu, s.alpha, f, uf, P1, rows, [], strain=True)
+        assert np.abs(rm).max() <= 1e-10 * np.abs(F).max()
+        # the strain form differs from the vector-Laplacian form
+        s0 = stokes.StokesSystem(m, 0.3, 20.0, mats=s.mats)
+        U0, _ = s0.solve_direct(*s0.rhs(f, ubc))
+        assert np.abs(U0 - U1).max() > 1e-6 * np.abs(U1).max()
+
+
+def test_strain_manufactured_rates_2d():
+    """For a divergence-free exact solution the strain form has the same
+    forcing (-mu div(2 eps(u)) = -mu Lap u when div u = 0): O(h^3) / O(h^2)."""
+    mu, alpha = 1.0, 100.0
+    pi = math.pi
+
+    def u_ex(x):
+        return np.stack([np.sin(pi * x[:, 0]) * np.sin(pi * x[:, 1]),
+                         np.cos(pi * x[:, 0]) * np.cos(pi * x[:, 1])], axis=1)
+
+    def p_ex(x):
+        return np.cos(pi * x[:, 0]) * np.cos(pi * x[:, 1])
+
+    errs = []
+    for n in (4, 8, 16):
+        m = mesh.KuhnMesh(2, n)
+        s = stokes.StokesSystem(m, mu, alpha, strain=True)
+        u, p, f = inputs.manufactured_2d(m.p2coords, mu, alpha)
+        F, g = s.rhs(f, u)
+        U, P = s.solve_direct(F, g)
+        errs.append(_l2_errors_2d(m, s, U, P, u, u_ex, p_ex))
+    ru = [math.log2(errs[i][0] / errs[i + 1][0]) for i in range(2)]
+    rp = [math.log2(errs[i][1] / errs[i + 1][1]) for i in range(2)]
+    assert min(ru) > 2.7, (errs, ru)
+    assert min(rp) > 1.7, (errs, rp)
+
+
+def test_strain_adjoint_gradient_vs_finite_differences():
+    m = mesh.KuhnMesh(3, 2, seed=6, jitter=0.1)
+    s = stokes.StokesSystem(m, 0.4, 25.0, strain=True)
+    f = inputs.fourier_forcing(m.p2coords, 1006)
+    U, _ = s.solve_direct(*s.rhs(f))
+    u = s.full_velocity(U)
+    Ut, _ = s.solve_direct(*s.rhs(inputs.fourier_forcing(m.p2coords, 9006)))
+    ut = s.full_velocity(Ut)
+    _, dJdu = stokes.quadratic_loss(s, u, ut)
+    dJdf, dJdmu, _, _ = s.adjoint_gradient(u, dJdu)
+
+    def J_of(fv, mu):
+        s2 = stokes.StokesSystem(m, mu, s.alpha, mats=s.mats, strain=True)
+        U2, _ = s2.solve_direct(*s2.rhs(fv))
+        return stokes.quadratic_loss(s2, s2.full_velocity(U2), ut)[0]
+
+    for dvec in inputs.fd_directions(f.shape, 3, seed=8):
+        h = 1e-3
+        fd = (J_of(f + h * dvec, s.mu) - J_of(f - h * dvec, s.mu)) / (2 * h)
+        assert abs(fd - np.sum(dJdf * dvec)) <= 1e-8 * abs(fd)
+    h = 1e-5 * s.mu
+    fd = (J_of(f, s.mu + h) - J_of(f, s.mu - h)) / (2 * h)
+    assert abs(fd - dJdmu) <= 1e-6 * abs(fd)
 
 
 # ------------------------------------------------------------------- solves
