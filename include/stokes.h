@@ -72,6 +72,13 @@ enum { STOKES_CC_LAPLACE = 0, STOKES_CC_LUMPED = 1, STOKES_CC_MASS = 2 };
  * "incomplete Full" of Sec. 6.2 (left factor dropped), UPPER = block upper
  * triangular [[A~, -B^T], [0, S~]]. */
 enum { STOKES_PC_FULL = 0, STOKES_PC_UPPER = 1, STOKES_PC_LOWER = 2 };
+/* stokes_problem.flags: STOKES_FLAG_STRAIN selects the paper's own velocity
+ * matrix A = alpha M_V + mu (L_V + D) of Sec. 3.2 (D the grad-div matrix;
+ * equal to the strain-rate form 2 mu eps(u):eps(v) on H^1_0) instead of the
+ * vector-Laplacian block alpha M_V + mu L_V.  The inner velocity
+ * preconditioner stays A~_{lambda,3} = alpha M_V + mu L_V (Sec. 3.2); the
+ * Dirichlet lifting and dJ/dmu use the same A. */
+enum { STOKES_FLAG_STRAIN = 1 };
 
 typedef struct {
   int32_t dim;        /* 2 or 3 */
@@ -81,7 +88,7 @@ typedef struct {
   double mu;          /* viscosity, > 0 */
   double alpha;       /* 1/dt, > 0 */
   double gamma;       /* augmented-Lagrangian weight, >= 0 */
-  int32_t flags;      /* reserved, must be 0 */
+  int32_t flags;      /* 0 or STOKES_FLAG_STRAIN */
 } stokes_problem;
 
 typedef struct {
@@ -184,7 +191,9 @@ stokes_status stokes_solve_adjoint(stokes_ctx* ctx, int32_t nrhs, const double* 
 
 /* Apply one assembled operator in FP64 (precision 0) or FP32 (1) to device
  * arrays in the caller layout.  op: 0 = y = A_gamma=0 x on interior nodes
- * (x, y velocity-shaped, boundary entries of x ignored, of y set to 0);
+ * (x, y velocity-shaped, boundary entries of x ignored, of y set to 0; A is
+ * the context's velocity matrix, alpha M + mu (L + D) with
+ * STOKES_FLAG_STRAIN);
  * 1 = y = B x (x velocity-shaped, y pressure-shaped); 2 = y = B^T x (x
  * pressure, y velocity, boundary 0); 3 = M_Q x; 4 = L_Q x; 5 = the coupled
  * operator: (y_u, y_p) = (A u - B^T p, B u) with x = (x_u, x_p) packed as
@@ -223,7 +232,9 @@ stokes_status stokes_export_mesh(const stokes_ctx* ctx, double* p2coords_host, i
  * of stokes_host_pattern.  which: 0 = M_s (all P2), 1 = L_s (all P2),
  * 2..4 = B plane x, y, z (P1 x all P2), 5 = M_Q, 6 = L_Q, 7 = A_II (interior,
  * pattern 1), 8 = Lambda_V (diagonal: rowptr/cols ignored, vals [n_p2]),
- * 9 = B_I Lambda_V^-1 B_I^T (P1 x P1, stokes_query sizes[10] entries). */
+ * 9 = B_I Lambda_V^-1 B_I^T (P1 x P1, stokes_query sizes[10] entries),
+ * 10 + dim a + b = grad-div block D[a][b] (all P2, int d_a phi_i d_b phi_j;
+ * STOKES_FLAG_STRAIN contexts only). */
 stokes_status stokes_export_csr(const stokes_ctx* ctx, int32_t which, int32_t* rowptr_host,
                                 int32_t* cols_host, double* vals_host);
 

@@ -21,6 +21,7 @@ FP64, MIXED = 0, 1
 INNER_TOL, INNER_FIXED = 0, 1
 CC_LAPLACE, CC_LUMPED, CC_MASS = 0, 1, 2
 PC_FULL, PC_UPPER, PC_LOWER = 0, 1, 2
+FLAG_STRAIN = 1
 
 
 class StokesError(RuntimeError):
@@ -129,9 +130,9 @@ def default_opts(**kw):
     return o
 
 
-def make_problem(dim, n, mesh_seed=0, jitter=0.0, mu=1.0, alpha=1.0, gamma=0.0):
+def make_problem(dim, n, mesh_seed=0, jitter=0.0, mu=1.0, alpha=1.0, gamma=0.0, flags=0):
     return Problem(dim=int(dim), n=int(n), mesh_seed=int(mesh_seed), jitter=float(jitter), mu=float(mu),
-                   alpha=float(alpha), gamma=float(gamma), flags=0)
+                   alpha=float(alpha), gamma=float(gamma), flags=int(flags))
 
 
 def ptr(x):

@@ -55,7 +55,7 @@ stokes_status check_problem(const stokes_problem* p) {
   if (!(p->alpha > 0) || !std::isfinite(p->alpha)) throw Error(STOKES_ERR_ARG, "alpha must be finite and > 0");
   if (!(p->gamma >= 0) || !std::isfinite(p->gamma)) throw Error(STOKES_ERR_ARG, "gamma must be finite and >= 0");
   if (!(p->jitter >= 0 && p->jitter <= 0.2)) throw Error(STOKES_ERR_ARG, "jitter must be in [0, 0.2]");
-  if (p->flags != 0) throw Error(STOKES_ERR_ARG, "flags must be 0");
+  if ((p->flags & ~STOKES_FLAG_STRAIN) != 0) throw Error(STOKES_ERR_ARG, "flags must be 0 or STOKES_FLAG_STRAIN");
   const int64_t n2 = ipow64(2 * int64_t(p->n) + 1, p->dim);
   if (n2 >= (int64_t(1) << 31) / 4) throw Error(STOKES_ERR_UNSUPPORTED, "mesh too large for 32-bit indices");
   return STOKES_OK;
@@ -417,6 +417,7 @@ stokes_status stokes_assemble(const stokes_problem* prob, void* hip_stream, stok
     }
     auto c = std::make_unique<stokes_ctx>();
     c->prob = *prob;
+    c->strain = (prob->flags & STOKES_FLAG_STRAIN) != 0;
     HIP_CHECK(hipGetDevice(&c->device));
     c->user_stream = static_cast<hipStream_t>(hip_stream);
     if (const char* e = std::getenv("STOKES_GRAPHS")) c->use_graphs = std::atoi(e) != 0;
@@ -574,7 +575,7 @@ stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t
         using T = std::remove_pointer_t<decltype(XU)>;
         (void)tag;
         switch (op) {
-          case 0: ops::spmv<T>(c, c->sA, ops::pick<T>(c->A64, c->A32), D * nrb, XU, YU, (T)1, nullptr, (T)0); break;
+          case 0: ops::velop<T>(c, nrb, XU, YU, (T)1, nullptr, (T)0); break;
           case 1: ops::Bmul<T>(c, nrb, XU, YP, (T)1, nullptr, (T)0); break;
           case 2: ops::Btmul<T>(c, nrb, XP, nullptr, YU, (T)1, nullptr, (T)0); break;
           case 3: ops::spmv<T>(c, c->sQ, ops::pick<T>(c->MQ64, c->MQ32), nrb, XP, YP, (T)1, nullptr, (T)0); break;
@@ -698,7 +699,8 @@ stokes_status stokes_export_csr(const stokes_ctx* cc, int32_t which, int32_t* ro
   stokes_ctx* c = const_cast<stokes_ctx*>(cc);
   return guard([&]() -> stokes_status {
     if (!c) throw Error(STOKES_ERR_ARG, "ctx is NULL");
-    if (which < 0 || which > 9) throw Error(STOKES_ERR_ARG, "which must be in [0, 9]");
+    if (which < 0 || which > 9 + c->dim * c->dim) throw Error(STOKES_ERR_ARG, "which out of range");
+    if (which >= 10 && !c->strain) throw Error(STOKES_ERR_STATE, "grad-div blocks exist only with STOKES_FLAG_STRAIN");
     if (!vals) throw Error(STOKES_ERR_ARG, "vals is NULL");
     HIP_CHECK(hipSetDevice(c->device));
     HIP_CHECK(hipStreamSynchronize(c->stream));
@@ -721,6 +723,9 @@ stokes_status stokes_export_csr(const stokes_ctx* cc, int32_t which, int32_t* ro
       case 5: copy_csr(c->p1, c->MQ_csr, 1, 0); break;
       case 6: copy_csr(c->p1, c->LQ_csr, 1, 0); break;
       case 9: copy_csr(c->xl, c->XL_csr, 1, 0); break;
+      case 10: case 11: case 12: case 13: case 14: case 15: case 16: case 17: case 18:
+        copy_csr(c->p2full, c->D_full, c->dim * c->dim, which - 10);
+        break;
       case 7: {
         // A_II in the natural interior numbering (pattern 1 of stokes_host_pattern)
         const Sell& S = c->sA;

@@ -259,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_p2(int64_t n_p2, const int64_
                                                       const int32_t* __restrict__ p2, const double* __restrict__ vol,
                                                       const double* __restrict__ jinv, const int32_t* __restrict__ rp,
                                                       const int32_t* __restrict__ cols, double* __restrict__ Mo,
-                                                      double* __restrict__ Lo) {
+                                                      double* __restrict__ Lo, double* __restrict__ Do) {
   using Tb = Tab<D>;
   GRID_STRIDE_ROWS(v, n_p2) {
     const int64_t lo = rp[v], hi = rp[v + 1];
@@ -281,6 +281,17 @@ __global__ __launch_bounds__(kBlock) void k_gather_p2(int64_t n_p2, const int64_
         const int64_t slot = find_slot(cols, lo, hi, p2[e * Tb::NL + j]);
         Mo[slot] += V * Tb::M(i, j);
         Lo[slot] += V * l;
+        if (Do) {
+          // grad-div blocks: int d_a phi_i d_b phi_j, d_a phi = sum_p Jinv[p][a] d phi / d xi_p
+          for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b) {
+              double t = 0;
+              for (int p = 0; p < D; ++p)
+                for (int r = 0; r < D; ++r)
+                  t += jinv[e * D * D + p * D + a] * jinv[e * D * D + r * D + b] * Tb::S(i, p, j, r);
+              Do[slot * D * D + a * D + b] += V * t;
+            }
+        }
       }
     }
   }
@@ -308,6 +319,26 @@ __global__ __launch_bounds__(kBlock) void k_gather_b(int64_t n_p1, const int64_t
           Bo[slot * D + c] += V * s;
         }
       }
+    }
+  }
+}
+
+// strain-form velocity blocks on the SELL entries:
+//   out[k][a][b] = delta_ab (alpha M + mu L)[s] + mu D[s][a][b],  s = src[k]
+__global__ __launch_bounds__(kBlock) void k_fill_blk(int64_t n, int dd, const int32_t* __restrict__ src, double alpha,
+                                                     double mu, const double* __restrict__ M,
+                                                     const double* __restrict__ L, const double* __restrict__ Dg,
+                                                     double* __restrict__ out, float* __restrict__ out32) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = src[k];
+    for (int q = 0; q < dd * dd; ++q) {
+      double o = 0;
+      if (s >= 0) {
+        o = mu * Dg[s * dd * dd + q];
+        if (q / dd == q % dd) o += alpha * M[s] + mu * L[s];
+      }
+      out[k * dd * dd + q] = o;
+      out32[k * dd * dd + q] = (float)o;
     }
   }
 }
@@ -764,13 +795,17 @@ void assemble_ctx(stokes_ctx* c) {
   c->lam_full.alloc(m.n_p2 * sizeof(double));
   HIP_CHECK(hipMemsetAsync(c->M_full.p, 0, nnz2 * sizeof(double), c->stream));
   HIP_CHECK(hipMemsetAsync(c->L_full.p, 0, nnz2 * sizeof(double), c->stream));
+  if (c->strain) {
+    c->D_full.alloc(nnz2 * D * D * sizeof(double));
+    HIP_CHECK(hipMemsetAsync(c->D_full.p, 0, nnz2 * D * D * sizeof(double), c->stream));
+  }
   HIP_CHECK(hipMemsetAsync(c->B_full.p, 0, nnzb * D * sizeof(double), c->stream));
   HIP_CHECK(hipMemsetAsync(c->MQ_csr.p, 0, nnz1 * sizeof(double), c->stream));
   HIP_CHECK(hipMemsetAsync(c->LQ_csr.p, 0, nnz1 * sizeof(double), c->stream));
   if (D == 3) {
     launch(c, m.n_p2, k_gather_p2<3>, m.n_p2, d_i2p.as<int64_t>(), d_i2l.as<int32_t>(), d_p2.as<int32_t>(),
            d_vol.as<double>(), d_jinv.as<double>(), c->p2full.rowptr.as<int32_t>(), c->p2full.cols.as<int32_t>(),
-           c->M_full.as<double>(), c->L_full.as<double>());
+           c->M_full.as<double>(), c->L_full.as<double>(), c->strain ? c->D_full.as<double>() : nullptr);
     launch(c, m.n_p1, k_gather_b<3>, m.n_p1, d_i1p.as<int64_t>(), d_i1l.as<int32_t>(), d_p2.as<int32_t>(),
            d_vol.as<double>(), d_jinv.as<double>(), c->bfull.rowptr.as<int32_t>(), c->bfull.cols.as<int32_t>(),
            c->B_full.as<double>());
@@ -782,7 +817,7 @@ void assemble_ctx(stokes_ctx* c) {
   } else {
     launch(c, m.n_p2, k_gather_p2<2>, m.n_p2, d_i2p.as<int64_t>(), d_i2l.as<int32_t>(), d_p2.as<int32_t>(),
            d_vol.as<double>(), d_jinv.as<double>(), c->p2full.rowptr.as<int32_t>(), c->p2full.cols.as<int32_t>(),
-           c->M_full.as<double>(), c->L_full.as<double>());
+           c->M_full.as<double>(), c->L_full.as<double>(), c->strain ? c->D_full.as<double>() : nullptr);
     launch(c, m.n_p1, k_gather_b<2>, m.n_p1, d_i1p.as<int64_t>(), d_i1l.as<int32_t>(), d_p2.as<int32_t>(),
            d_vol.as<double>(), d_jinv.as<double>(), c->bfull.rowptr.as<int32_t>(), c->bfull.cols.as<int32_t>(),
            c->B_full.as<double>());
@@ -851,6 +886,13 @@ void assemble_ctx(stokes_ctx* c) {
   c->AD32.alloc(c->sA.nnz_pad * sizeof(float));
   launch(c, c->sA.nnz_pad, k_scale_cols, c->sA.nnz_pad, c->sA.cols.as<int32_t>(), c->A64.as<double>(),
          c->dA64.as<double>(), c->AD64.as<double>(), c->AD32.as<float>());
+  if (c->strain) {
+    c->AB64.alloc(c->sA.nnz_pad * D * D * sizeof(double));
+    c->AB32.alloc(c->sA.nnz_pad * D * D * sizeof(float));
+    launch(c, c->sA.nnz_pad, k_fill_blk, c->sA.nnz_pad, D, c->sA.src.as<int32_t>(), alpha, mu,
+           c->M_full.as<double>(), c->L_full.as<double>(), c->D_full.as<double>(), c->AB64.as<double>(),
+           c->AB32.as<float>());
+  }
   dinv(c->sA, c->MV64, c->dMV64);
   dinv(c->sQ, c->MQ64, c->dMQ64);
   dinv(c->sQ, c->XQ64, c->dXQ64);
@@ -1074,6 +1116,9 @@ void reform_A(stokes_ctx* c) {
   launch(c, c->n_int, k_cast<double, float>, c->n_int, c->dA64.as<double>(), c->dA32.as<float>());
   launch(c, n, k_scale_cols, n, c->sA.cols.as<int32_t>(), c->A64.as<double>(), c->dA64.as<double>(),
          c->AD64.as<double>(), c->AD32.as<float>());
+  if (c->strain)
+    launch(c, n, k_fill_blk, n, c->dim, c->sA.src.as<int32_t>(), c->prob.alpha, c->prob.mu, c->M_full.as<double>(),
+           c->L_full.as<double>(), c->D_full.as<double>(), c->AB64.as<double>(), c->AB32.as<float>());
   double lo, hi, g;
   lanczos_bounds(c, c->sA, c->A64.as<double>(), c->dA64.as<double>(), 40, lo, hi, g);
   c->bA.hi = std::min(g, 1.1 * hi);

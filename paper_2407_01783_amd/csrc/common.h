@@ -141,6 +141,8 @@ struct stokes_ctx {
   stokes::DevBuf bc_rows, bc_ptr, bc_cols, bc_src;
   stokes::DevBuf XL_csr;          // double [nnz xl]
   stokes::DevBuf M_full, L_full;  // double [nnz p2full]
+  bool strain = false;            // velocity block alpha M + mu (L + D)
+  stokes::DevBuf D_full;          // double [nnz p2full][dim*dim] grad-div blocks (strain)
   stokes::DevBuf B_full;          // double [nnz bfull][dim]
   stokes::DevBuf MQ_csr, LQ_csr;  // double [nnz p1]
   stokes::DevBuf lam_full;        // double [n_p2]  Lambda_V
@@ -158,6 +160,7 @@ struct stokes_ctx {
   stokes::Sell sX;   // P1 x P1, B_I Lambda_V^-1 B_I^T (two-ring stencil)
   stokes::DevBuf A64, A32, MV64, MV32;       // values of A_II and M_II (SELL)
   stokes::DevBuf AD64, AD32;                 // A_II D^{-1}: column-scaled copy (first Chebyshev step)
+  stokes::DevBuf AB64, AB32;                 // strain: [nnz_pad][dim*dim] blocks alpha M + mu (L + D)
   stokes::DevBuf B64, B32, Bt64, Bt32;       // [nnz_pad][dim]
   stokes::DevBuf MQ64, MQ32, LQ64, LQ32, XQ64, XQ32;  // XQ = M_Q + L_Q
   stokes::DevBuf dA64, dA32, dMV64, dMV32;   // inverse diagonals (interior)

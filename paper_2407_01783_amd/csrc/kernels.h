@@ -601,6 +601,104 @@ __global__ __launch_bounds__(kBlock) void k_momentum(int64_t nrows, const int64_
   }
 }
 
+// ---------------------------------------------- strain-form velocity block
+// The velocity block alpha M + mu (L + D) couples the components: entry k of
+// the sliced-ELL pattern carries a dim x dim block V[k][a][b] (row-major),
+// and y[row][r][a] += sum_b V[k][a][b] x[col][r][b] for every right-hand side.
+template <typename T, int D, int NRB>
+__device__ __forceinline__ void sell_row_blk(const int64_t* __restrict__ sp, const int32_t* __restrict__ cols,
+                                             const T* __restrict__ vals, const T* __restrict__ x, int64_t row,
+                                             T (&acc)[D * NRB]) {
+  constexpr int W = D * NRB, DD = D * D;
+  const int64_t s = row >> 6;
+  const int64_t beg = sp[s] + (row & 63);
+  const int width = (int)((sp[s + 1] - sp[s]) >> 6);
+  constexpr int U = 2;
+  int j = 0;
+  for (; j + U <= width; j += U) {
+    int32_t c[U];
+    T v[U][DD], xv[U][W];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int64_t k = beg + 64 * (j + q);
+      c[q] = __builtin_nontemporal_load(cols + k);
+#pragma unroll
+      for (int e = 0; e < DD; ++e) v[q][e] = __builtin_nontemporal_load(vals + k * DD + e);
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+      for (int w = 0; w < W; ++w) xv[q][w] = x[(int64_t)c[q] * W + w];
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+      for (int r = 0; r < NRB; ++r)
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int b = 0; b < D; ++b) acc[r * D + a] = fma(v[q][a * D + b], xv[q][r * D + b], acc[r * D + a]);
+  }
+  for (; j < width; ++j) {
+    const int64_t k = beg + 64 * j;
+    const int32_t c = __builtin_nontemporal_load(cols + k);
+    T v[DD];
+#pragma unroll
+    for (int e = 0; e < DD; ++e) v[e] = __builtin_nontemporal_load(vals + k * DD + e);
+    const T* xp = x + (int64_t)c * W;
+#pragma unroll
+    for (int r = 0; r < NRB; ++r)
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) acc[r * D + a] = fma(v[a * D + b], xp[r * D + b], acc[r * D + a]);
+  }
+}
+
+// y = a * (A x) + b * yin with the block operator (yin may alias y)
+template <typename T, int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_spmv_blk(int64_t nrows, const int64_t* __restrict__ sp,
+                                                     const int32_t* __restrict__ cols, const T* __restrict__ vals,
+                                                     const T* __restrict__ x, T* y, T a, const T* yin, T b) {
+  constexpr int W = D * NRB;
+  XCD_ROWS(row, nrows) {
+    T acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = 0;
+    sell_row_blk<T, D, NRB>(sp, cols, vals, x, row, acc);
+    T yi[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) yi[w] = b != T(0) ? yin[row * W + w] : T(0);
+#pragma unroll
+    for (int w = 0; w < W; ++w) y[row * W + w] = fma(b, yi[w], a * acc[w]);
+  }
+}
+
+// Momentum rows with the block operator: y = sgn (A u - B^T p + extra) + yin
+template <typename T, int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_momentum_blk(int64_t nrows, const int64_t* __restrict__ spA,
+                                                         const int32_t* __restrict__ colsA, const T* __restrict__ A,
+                                                         const int64_t* __restrict__ spT,
+                                                         const int32_t* __restrict__ colsT, const T* __restrict__ Bt,
+                                                         const T* __restrict__ u, const T* __restrict__ p,
+                                                         const T* __restrict__ extra, T* y, T sgn, const T* yin) {
+  constexpr int W = D * NRB;
+  XCD_ROWS(row, nrows) {
+    T acc[W], bt[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = bt[w] = 0;
+    sell_row_blk<T, D, NRB>(spA, colsA, A, u, row, acc);
+    sell_row_Bt<T, D, NRB, 1>(spT, colsT, Bt, p, row, 0, bt);
+    T ex[W], yi[W];  // yin may alias y
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      ex[w] = extra ? extra[row * W + w] : T(0);
+      yi[w] = yin ? yin[row * W + w] : T(0);
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) y[row * W + w] = fma(sgn, acc[w] - bt[w] + ex[w], yi[w]);
+  }
+}
+
 // ------------------------------------------------------------ vector ops
 
 // y = a x + b y
@@ -715,9 +813,9 @@ template <int D, int NRB>
 __global__ __launch_bounds__(kBlock) void k_rhs_bnd(int64_t nbc, int64_t n_p2, const int32_t* __restrict__ rows,
                                                     const int32_t* __restrict__ ptr, const int32_t* __restrict__ cols,
                                                     const int32_t* __restrict__ src, const double* __restrict__ M,
-                                                    const double* __restrict__ L, double alpha, double mu,
-                                                    const double* __restrict__ f, const double* __restrict__ ubc,
-                                                    double* __restrict__ F) {
+                                                    const double* __restrict__ L, const double* __restrict__ Dg,
+                                                    double alpha, double mu, const double* __restrict__ f,
+                                                    const double* __restrict__ ubc, double* __restrict__ F) {
   constexpr int W = D * NRB;
   GRID_STRIDE_ROWS(q, nbc) {
     double acc[W];
@@ -734,7 +832,11 @@ __global__ __launch_bounds__(kBlock) void k_rhs_bnd(int64_t nbc, int64_t n_p2, c
         for (int d = 0; d < D; ++d) {
           const int64_t o = ((int64_t)r * D + d) * n_p2 + c;
           double v = f ? m * f[o] : 0.0;
-          if (ubc) v -= a * ubc[o];
+          if (ubc) {
+            v -= a * ubc[o];
+            if (Dg)  // strain form: mu sum_b D[d][b] G_b
+              for (int b = 0; b < D; ++b) v -= mu * Dg[e * D * D + d * D + b] * ubc[((int64_t)r * D + b) * n_p2 + c];
+          }
           acc[r * D + d] += v;
         }
     }
@@ -799,7 +901,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_dJdf(int64_t n_p2, const int32_t
 template <int D, int NRB>
 __global__ __launch_bounds__(kBlock) void k_adj_dJdmu(int64_t n_int, int64_t n_p2, const int32_t* __restrict__ int2nat,
                                                       const int32_t* __restrict__ rp, const int32_t* __restrict__ cols,
-                                                      const double* __restrict__ L, const double* __restrict__ u,
+                                                      const double* __restrict__ L, const double* __restrict__ Dg,
+                                                      const double* __restrict__ u,
                                                       const double* __restrict__ lam, double* res, double* partials) {
   constexpr int W = D * NRB;
   double part[NRB];
@@ -816,7 +919,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_dJdmu(int64_t n_int, int64_t n_p
 #pragma unroll
       for (int r = 0; r < NRB; ++r)
 #pragma unroll
-        for (int d = 0; d < D; ++d) acc[r * D + d] += l * u[((int64_t)r * D + d) * n_p2 + c];
+        for (int d = 0; d < D; ++d) {
+          double t = l * u[((int64_t)r * D + d) * n_p2 + c];
+          if (Dg)  // strain form: the viscous matrix is L + D
+            for (int b = 0; b < D; ++b) t += Dg[k * D * D + d * D + b] * u[((int64_t)r * D + b) * n_p2 + c];
+          acc[r * D + d] += t;
+        }
     }
 #pragma unroll
     for (int r = 0; r < NRB; ++r)

@@ -42,6 +42,10 @@ void Bmul(stokes_ctx* c, int nrb, const T* u, T* p, T a, const T* pin, T b);
 // u = a * scale .* (B^T p) + b * uin
 template <class T>
 void Btmul(stokes_ctx* c, int nrb, const T* p, const T* scale, T* u, T a, const T* uin, T b);
+// y = a * (A x) + b * yin with the velocity operator (vector Laplacian block
+// or, for strain contexts, the coupled alpha M + mu (L + D) blocks)
+template <class T>
+void velop(stokes_ctx* c, int nrb, const T* x, T* y, T a, const T* yin, T b);
 // y = sgn (A u - B^T p + extra) + yin
 template <class T>
 void momentum(stokes_ctx* c, int nrb, const T* u, const T* p, const T* extra, T* y, T sgn, const T* yin);

@@ -181,8 +181,35 @@ void Btmul(stokes_ctx* c, int nrb, const T* p, const T* scale, T* u, T a, const 
   check_launch();
 }
 
+template <class T> const DevBuf& abvals(stokes_ctx* c);
+template <> const DevBuf& abvals<double>(stokes_ctx* c) { return c->AB64; }
+template <> const DevBuf& abvals<float>(stokes_ctx* c) { return c->AB32; }
+
+template <class T>
+void velop(stokes_ctx* c, int nrb, const T* x, T* y, T a, const T* yin, T b) {
+  if (!c->strain) return spmv<T>(c, c->sA, avals<T>(c).template as<T>(), c->dim * nrb, x, y, a, yin, b);
+  dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
+    constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
+    hipLaunchKernelGGL((k_spmv_blk<T, D, N>), dim3(grid_for(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int,
+                       c->sA.slice_ptr.as<int64_t>(), c->sA.cols.as<int32_t>(), abvals<T>(c).template as<T>(), x, y,
+                       a, yin, b);
+  });
+  check_launch();
+}
+
 template <class T>
 void momentum(stokes_ctx* c, int nrb, const T* u, const T* p, const T* extra, T* y, T sgn, const T* yin) {
+  if (c->strain) {
+    dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
+      constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
+      hipLaunchKernelGGL((k_momentum_blk<T, D, N>), dim3(grid_for(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int,
+                         c->sA.slice_ptr.as<int64_t>(), c->sA.cols.as<int32_t>(), abvals<T>(c).template as<T>(),
+                         c->sBt.slice_ptr.as<int64_t>(), c->sBt.cols.as<int32_t>(), btvals<T>(c).template as<T>(), u,
+                         p, extra, y, sgn, yin);
+    });
+    check_launch();
+    return;
+  }
   const int G = lanes_w(c, c->dim * nrb, std::is_same<T, float>::value);
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
     constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
@@ -495,8 +522,8 @@ void rhs(stokes_ctx* c, int nrb, const double* f, const double* ubc, double* F, 
     if (c->n_bc > 0 && (f || ubc))
       hipLaunchKernelGGL((k_rhs_bnd<D, N>), dim3(grid_for(c->n_bc)), dim3(kBlock), 0, c->stream, c->n_bc, c->n_p2,
                          c->bc_rows.as<int32_t>(), c->bc_ptr.as<int32_t>(), c->bc_cols.as<int32_t>(),
-                         c->bc_src.as<int32_t>(), c->M_full.as<double>(), c->L_full.as<double>(), c->prob.alpha,
-                         c->prob.mu, f, ubc, F);
+                         c->bc_src.as<int32_t>(), c->M_full.as<double>(), c->L_full.as<double>(),
+                         c->strain ? c->D_full.as<double>() : nullptr, c->prob.alpha, c->prob.mu, f, ubc, F);
     check_launch();
     hipLaunchKernelGGL((k_rhs_p<D, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1, c->n_p2,
                        c->nat2int.as<int32_t>(), c->bfull.rowptr.as<int32_t>(), c->bfull.cols.as<int32_t>(),
@@ -531,7 +558,8 @@ void adj_dJdmu(stokes_ctx* c, int nrb, const double* u_full, const double* lam, 
     constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
     hipLaunchKernelGGL((k_adj_dJdmu<D, N>), dim3(grid_for(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int, c->n_p2,
                        c->int2nat.as<int32_t>(), c->p2full.rowptr.as<int32_t>(), c->p2full.cols.as<int32_t>(),
-                       c->L_full.as<double>(), u_full, lam, res_dev, partials(c));
+                       c->L_full.as<double>(), c->strain ? c->D_full.as<double>() : nullptr, u_full, lam, res_dev,
+                       partials(c));
     finish<N>(c, c->n_int, FIN_STORE, N, nullptr, 1, 0, 0, res_dev);
   });
   check_launch();
@@ -542,6 +570,7 @@ void adj_dJdmu(stokes_ctx* c, int nrb, const double* u_full, const double* lam, 
   template void Bmul<T>(stokes_ctx*, int, const T*, T*, T, const T*, T);                                            \
   template void Btmul<T>(stokes_ctx*, int, const T*, const T*, T*, T, const T*, T);                                 \
   template void momentum<T>(stokes_ctx*, int, const T*, const T*, const T*, T*, T, const T*);                       \
+  template void velop<T>(stokes_ctx*, int, const T*, T*, T, const T*, T);                                           \
   template void dot_dev<T>(stokes_ctx*, int64_t, int, const T*, const T*, const double*, double*);                  \
   template std::vector<double> dot_host<T>(stokes_ctx*, int64_t, int, const T*, const T*, const double*);           \
   template void remove_mean<T>(stokes_ctx*, int, T*);                                                               \

@@ -304,11 +304,25 @@ class Engine {
       return;
     }
     Op op;
-    op.S = &c_->sA;
     int cps = 1;
-    if (gamma_ > 0) {
-      op.extra = [this](const T* z, T* t) { al_term(z, t); };
+    if (c_->strain) {
+      // alpha M + mu (L + D) couples the components; A~_{lambda,3} (the
+      // vector-Laplacian block) stays the preconditioner, as in Sec. 3.2
       cps = D_;
+      op.apply = [this](const T* z, T* t) {
+        ops::velop<T>(c_, nrb_, z, t, (T)1, nullptr, (T)0);
+        if (gamma_ > 0) {
+          T* ta = buf("vs_al", nu());
+          al_term(z, ta);
+          ops::axpby<T>(c_, nu(), (T)1, ta, (T)1, t);
+        }
+      };
+    } else {
+      op.S = &c_->sA;
+      if (gamma_ > 0) {
+        op.extra = [this](const T* z, T* t) { al_term(z, t); };
+        cps = D_;
+      }
     }
     st_.inner_u += pcg("vcg", op, A(), pc, c_->n_int, W_, cps, b, x, o_.inner_rtol_u, o_.max_inner, 0, false,
                        o_.inner_its_u);

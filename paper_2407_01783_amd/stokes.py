@@ -22,11 +22,15 @@ def _stream_handle():
 class StokesProblem:
     """An assembled generalized Stokes operator on the Kuhn mesh (one GPU)."""
 
-    def __init__(self, dim, n, mesh_seed=0, jitter=0.0, mu=1.0, alpha=1.0, gamma=0.0):
+    def __init__(self, dim, n, mesh_seed=0, jitter=0.0, mu=1.0, alpha=1.0, gamma=0.0, strain=False):
+        """strain=True: velocity matrix alpha M + mu (L + D) (the strain-rate
+        form); otherwise alpha M + mu L (vector Laplacian)."""
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("StokesProblem needs a HIP device")
-        self.prob = _lib.make_problem(dim, n, mesh_seed, jitter, mu, alpha, gamma)
+        self.strain = bool(strain)
+        self.prob = _lib.make_problem(dim, n, mesh_seed, jitter, mu, alpha, gamma,
+                                      _lib.FLAG_STRAIN if strain else 0)
         self.device = torch.device("cuda", torch.cuda.current_device())
         h = ctypes.c_void_p()
         check(self.lib.stokes_assemble(ctypes.byref(self.prob), _stream_handle(), ctypes.byref(h)),
@@ -69,6 +73,13 @@ class StokesProblem:
 
     def export_csr(self, which):
         """(rowptr, cols, vals) numpy arrays of an assembled FP64 matrix."""
+        if which >= 10:
+            nrows, nnz = self.n_p2, self.nnz_full
+            rp = np.empty(nrows + 1, dtype=np.int32)
+            cols = np.empty(nnz, dtype=np.int32)
+            vals = np.empty(nnz)
+            check(self.lib.stokes_export_csr(self.ctx, int(which), ptr(rp), ptr(cols), ptr(vals)), "stokes_export_csr")
+            return rp, cols, vals
         if which == 8:
             vals = np.empty(self.n_p2)
             check(self.lib.stokes_export_csr(self.ctx, 8, None, None, ptr(vals)), "stokes_export_csr")

@@ -85,7 +85,7 @@ def test_problem_sizes(lib):
 
 
 @pytest.mark.parametrize("field,value", [("dim", 4), ("n", 0), ("mu", 0.0), ("mu", float("nan")),
-                                         ("alpha", -1.0), ("gamma", -0.5), ("jitter", 0.3), ("flags", 1)])
+                                         ("alpha", -1.0), ("gamma", -0.5), ("jitter", 0.3), ("flags", 2)])
 def test_invalid_problem_rejected(lib, field, value):
     pr = _lib.make_problem(3, 4, 0, 0.1, 1.0, 1.0)
     setattr(pr, field, value)
