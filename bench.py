@@ -67,11 +67,11 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(workload, nrhs):
+def measured_traffic(workload, nrhs, strain=False):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, or None when that summary was taken on
     other sources (any kernel changed since), another workload, or is absent."""
-    if workload != "cube64" or nrhs != 1 or not os.path.exists(TRAFFIC_FILE):
+    if workload != "cube64" or nrhs != 1 or strain or not os.path.exists(TRAFFIC_FILE):
         return None
     fields = {}
     with open(TRAFFIC_FILE) as fh:
@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cube64", choices=sorted(WORKLOADS))
     ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--strain", action="store_true",
+                    help="strain-rate velocity matrix alpha M + mu (L + D) instead of the vector Laplacian")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=16, help="mesh size of the CPU oracle sample")
@@ -139,7 +141,9 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    prob = StokesProblem(dim, n, mesh_seed=seed, jitter=0.1, mu=mu, alpha=alpha)
+    prob = StokesProblem(dim, n, mesh_seed=seed, jitter=0.1, mu=mu, alpha=alpha, strain=args.strain)
+    if args.strain:
+        desc += ", strain-rate form alpha M + mu (L + D)"
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     print(f"[bench] assembled {args.workload} in {setup_s:.2f} s", file=sys.stderr, flush=True)
@@ -212,7 +216,7 @@ def main():
         "mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": measured_traffic(args.workload, args.nrhs),
+                     "traffic": measured_traffic(args.workload, args.nrhs, args.strain),
                      "kernel": f"k_cheb_step<float,{dim * args.nrhs},0,G> (FP32 velocity-block SELL SpMV + Chebyshev "
                                f"update; G lanes per row, autotuned)",
                      "bytes_per_launch": bytes_per, "launches": launches,

@@ -323,23 +323,33 @@ __global__ __launch_bounds__(kBlock) void k_gather_b(int64_t n_p1, const int64_t
   }
 }
 
-// strain-form velocity blocks on the SELL entries:
-//   out[k][a][b] = delta_ab (alpha M + mu L)[s] + mu D[s][a][b],  s = src[k]
+// Strain-form velocity blocks on the SELL entries of the interior operator:
+//   V[a][b] = delta_ab (alpha M + mu L)[s] + mu D[s][a][b],  s = src[k].
+// Between interior nodes D[a][b] = D[b][a] (integration by parts on H^1_0),
+// so each block is symmetric and its dim (dim + 1) / 2 upper entries
+// (a <= b, row-major) are stored, D[a][b] taken as the mean of the two
+// assembled values.  Layout: plane e of entry k at (k - k mod 64) P + 64 e +
+// k mod 64 (P planes), so the lanes of a wavefront read each plane
+// contiguously.
 __global__ __launch_bounds__(kBlock) void k_fill_blk(int64_t n, int dd, const int32_t* __restrict__ src, double alpha,
                                                      double mu, const double* __restrict__ M,
                                                      const double* __restrict__ L, const double* __restrict__ Dg,
                                                      double* __restrict__ out, float* __restrict__ out32) {
+  const int P = dd * (dd + 1) / 2;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
     const int64_t s = src[k];
-    for (int q = 0; q < dd * dd; ++q) {
-      double o = 0;
-      if (s >= 0) {
-        o = mu * Dg[s * dd * dd + q];
-        if (q / dd == q % dd) o += alpha * M[s] + mu * L[s];
+    const int64_t base = (k - (k & 63)) * P + (k & 63);
+    int e = 0;
+    for (int a = 0; a < dd; ++a)
+      for (int b = a; b < dd; ++b, ++e) {
+        double o = 0;
+        if (s >= 0) {
+          o = 0.5 * mu * (Dg[s * dd * dd + a * dd + b] + Dg[s * dd * dd + b * dd + a]);
+          if (a == b) o += alpha * M[s] + mu * L[s];
+        }
+        out[base + 64 * e] = o;
+        out32[base + 64 * e] = (float)o;
       }
-      out[k * dd * dd + q] = o;
-      out32[k * dd * dd + q] = (float)o;
-    }
   }
 }
 
@@ -887,8 +897,8 @@ void assemble_ctx(stokes_ctx* c) {
   launch(c, c->sA.nnz_pad, k_scale_cols, c->sA.nnz_pad, c->sA.cols.as<int32_t>(), c->A64.as<double>(),
          c->dA64.as<double>(), c->AD64.as<double>(), c->AD32.as<float>());
   if (c->strain) {
-    c->AB64.alloc(c->sA.nnz_pad * D * D * sizeof(double));
-    c->AB32.alloc(c->sA.nnz_pad * D * D * sizeof(float));
+    c->AB64.alloc(c->sA.nnz_pad * (D * (D + 1) / 2) * sizeof(double));
+    c->AB32.alloc(c->sA.nnz_pad * (D * (D + 1) / 2) * sizeof(float));
     launch(c, c->sA.nnz_pad, k_fill_blk, c->sA.nnz_pad, D, c->sA.src.as<int32_t>(), alpha, mu,
            c->M_full.as<double>(), c->L_full.as<double>(), c->D_full.as<double>(), c->AB64.as<double>(),
            c->AB32.as<float>());

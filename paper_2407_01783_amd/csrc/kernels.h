@@ -603,16 +603,25 @@ __global__ __launch_bounds__(kBlock) void k_momentum(int64_t nrows, const int64_
 
 // ---------------------------------------------- strain-form velocity block
 // The velocity block alpha M + mu (L + D) couples the components: entry k of
-// the sliced-ELL pattern carries a dim x dim block V[k][a][b] (row-major),
-// and y[row][r][a] += sum_b V[k][a][b] x[col][r][b] for every right-hand side.
+// the sliced-ELL pattern carries a symmetric dim x dim block, stored as its
+// P = dim (dim + 1) / 2 upper entries in plane-major groups of 64 entries
+// (plane e of entry k at (k - k mod 64) P + 64 e + k mod 64), and
+// y[row][r][a] += sum_b V[k][a][b] x[col][r][b] for every right-hand side.
+template <int D>
+__device__ __forceinline__ constexpr int sym_index(int a, int b) {
+  // row-major position of (min, max) among the upper entries
+  return a <= b ? a * D - a * (a - 1) / 2 + (b - a) : b * D - b * (b - 1) / 2 + (a - b);
+}
+
 template <typename T, int D, int NRB>
 __device__ __forceinline__ void sell_row_blk(const int64_t* __restrict__ sp, const int32_t* __restrict__ cols,
                                              const T* __restrict__ vals, const T* __restrict__ x, int64_t row,
                                              T (&acc)[D * NRB]) {
-  constexpr int W = D * NRB, DD = D * D;
+  constexpr int W = D * NRB, DD = D * (D + 1) / 2;
   const int64_t s = row >> 6;
   const int64_t beg = sp[s] + (row & 63);
   const int width = (int)((sp[s + 1] - sp[s]) >> 6);
+  const T* __restrict__ vrow = vals + sp[s] * DD + (row & 63);
   constexpr int U = 2;
   int j = 0;
   for (; j + U <= width; j += U) {
@@ -623,7 +632,7 @@ __device__ __forceinline__ void sell_row_blk(const int64_t* __restrict__ sp, con
       const int64_t k = beg + 64 * (j + q);
       c[q] = __builtin_nontemporal_load(cols + k);
 #pragma unroll
-      for (int e = 0; e < DD; ++e) v[q][e] = __builtin_nontemporal_load(vals + k * DD + e);
+      for (int e = 0; e < DD; ++e) v[q][e] = __builtin_nontemporal_load(vrow + (int64_t)(j + q) * 64 * DD + 64 * e);
     }
 #pragma unroll
     for (int q = 0; q < U; ++q)
@@ -636,21 +645,22 @@ __device__ __forceinline__ void sell_row_blk(const int64_t* __restrict__ sp, con
 #pragma unroll
         for (int a = 0; a < D; ++a)
 #pragma unroll
-          for (int b = 0; b < D; ++b) acc[r * D + a] = fma(v[q][a * D + b], xv[q][r * D + b], acc[r * D + a]);
+          for (int b = 0; b < D; ++b)
+            acc[r * D + a] = fma(v[q][sym_index<D>(a, b)], xv[q][r * D + b], acc[r * D + a]);
   }
   for (; j < width; ++j) {
     const int64_t k = beg + 64 * j;
     const int32_t c = __builtin_nontemporal_load(cols + k);
     T v[DD];
 #pragma unroll
-    for (int e = 0; e < DD; ++e) v[e] = __builtin_nontemporal_load(vals + k * DD + e);
+    for (int e = 0; e < DD; ++e) v[e] = __builtin_nontemporal_load(vrow + (int64_t)j * 64 * DD + 64 * e);
     const T* xp = x + (int64_t)c * W;
 #pragma unroll
     for (int r = 0; r < NRB; ++r)
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int b = 0; b < D; ++b) acc[r * D + a] = fma(v[a * D + b], xp[r * D + b], acc[r * D + a]);
+        for (int b = 0; b < D; ++b) acc[r * D + a] = fma(v[sym_index<D>(a, b)], xp[r * D + b], acc[r * D + a]);
   }
 }
 
