@@ -79,6 +79,12 @@ enum { STOKES_PC_FULL = 0, STOKES_PC_UPPER = 1, STOKES_PC_LOWER = 2 };
  * preconditioner stays A~_{lambda,3} = alpha M_V + mu L_V (Sec. 3.2); the
  * Dirichlet lifting and dJ/dmu use the same A. */
 enum { STOKES_FLAG_STRAIN = 1 };
+/* stokes_solve_opts.vel_pc: the preconditioner of A~_{lambda,3} = alpha M_V
+ * + mu L_V inside the velocity solves -- a Chebyshev-Jacobi polynomial of
+ * degree cheb_degree, or one geometric-multigrid V-cycle on the nested Kuhn
+ * meshes (the counterpart of the paper's AMG V-cycles, Sec. 3.3), whose cost
+ * and iteration counts do not grow with 1/h when mu dt / h^2 is large. */
+enum { STOKES_VEL_CHEB = 0, STOKES_VEL_MG = 1 };
 
 typedef struct {
   int32_t dim;        /* 2 or 3 */
@@ -109,7 +115,8 @@ typedef struct {
   int32_t inner_its_u;    /* > 0: every inner velocity CG runs exactly this many
                              iterations (no convergence checks); 0: use inner_rtol_u */
   int32_t inner_its_p;    /* the same for the inner pressure CG (0: inner_rtol_p) */
-  int32_t reserved[2];    /* must be 0 */
+  int32_t vel_pc;         /* velocity-block preconditioner: STOKES_VEL_CHEB or STOKES_VEL_MG */
+  int32_t reserved[1];    /* must be 0 */
 } stokes_solve_opts;
 
 typedef struct {
@@ -203,7 +210,8 @@ stokes_status stokes_solve_adjoint(stokes_ctx* ctx, int32_t nrhs, const double* 
  * lumped-mass pressure operator of Sec. 4.3, assembled explicitly (x, y
  * pressure-shaped); 8 = one V-cycle of the Galerkin multigrid hierarchy of
  * B_I Lambda_V^-1 B_I^T + M_Q, the preconditioner of that operator (x, y
- * pressure-shaped). */
+ * pressure-shaped); 9 = one velocity-multigrid V-cycle for alpha M_V + mu L_V
+ * (x, y velocity-shaped, boundary entries ignored / set to 0). */
 stokes_status stokes_apply(stokes_ctx* ctx, int32_t op, int32_t precision, int32_t nrhs,
                            const double* x, double* y);
 

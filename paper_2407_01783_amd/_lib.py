@@ -22,6 +22,7 @@ INNER_TOL, INNER_FIXED = 0, 1
 CC_LAPLACE, CC_LUMPED, CC_MASS = 0, 1, 2
 PC_FULL, PC_UPPER, PC_LOWER = 0, 1, 2
 FLAG_STRAIN = 1
+VEL_CHEB, VEL_MG = 0, 1
 
 
 class StokesError(RuntimeError):
@@ -42,7 +43,7 @@ class SolveOpts(ctypes.Structure):
                 ("cheb_degree", ctypes.c_int32), ("inner_rtol_u", ctypes.c_double),
                 ("inner_rtol_p", ctypes.c_double), ("schur_pc", ctypes.c_int32), ("coupled_pc", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("profile", ctypes.c_int32), ("inner_its_u", ctypes.c_int32),
-                ("inner_its_p", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("inner_its_p", ctypes.c_int32), ("vel_pc", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class SolveInfo(ctypes.Structure):

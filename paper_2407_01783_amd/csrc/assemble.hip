@@ -1099,6 +1099,71 @@ void assemble_galerkin(stokes_ctx* c, MgHier& H) {
   }
 }
 
+// alpha M + mu L on the interior P2 nodes of a coarse Kuhn mesh (natural
+// interior order), for the velocity multigrid.
+void assemble_p2_level(stokes_ctx* c, const HostMesh& m, VmgLevel& L) {
+  const int D = m.dim;
+  HostCsr P2;
+  element_pattern(m.p2, m.nloc, m.n_p2, m.p2, m.nloc, m.n_p2, m.n_e, P2);
+  std::vector<int32_t> rows, nat2int(m.n_p2, -1);
+  for (int64_t v = 0; v < m.n_p2; ++v)
+    if (!m.p2_bnd[v]) {
+      nat2int[v] = static_cast<int32_t>(rows.size());
+      rows.push_back(static_cast<int32_t>(v));
+    }
+  DevBuf d_vc, d_el, d_p2, d_vol, d_jinv, d_ip, d_il, rp, cols, Mf, Lf;
+  upload(d_vc, m.vcoords);
+  upload(d_el, m.elems);
+  upload(d_p2, m.p2);
+  d_vol.alloc(m.n_e * sizeof(double));
+  d_jinv.alloc(m.n_e * D * D * sizeof(double));
+  if (D == 3) launch(c, m.n_e, k_geom<3>, m.n_e, d_vc.as<double>(), d_el.as<int32_t>(), d_vol.as<double>(), d_jinv.as<double>());
+  else launch(c, m.n_e, k_geom<2>, m.n_e, d_vc.as<double>(), d_el.as<int32_t>(), d_vol.as<double>(), d_jinv.as<double>());
+  {
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> lst;
+    incidence(m.p2, m.nloc, m.n_e, m.n_p2, ptr, lst);
+    upload(d_ip, ptr);
+    upload(d_il, lst);
+  }
+  std::vector<int32_t> rp32(P2.rowptr.begin(), P2.rowptr.end());
+  upload(rp, rp32);
+  upload(cols, P2.cols);
+  const int64_t nnz = P2.rowptr.back();
+  Mf.alloc(nnz * sizeof(double));
+  Lf.alloc(nnz * sizeof(double));
+  HIP_CHECK(hipMemsetAsync(Mf.p, 0, nnz * sizeof(double), c->stream));
+  HIP_CHECK(hipMemsetAsync(Lf.p, 0, nnz * sizeof(double), c->stream));
+  if (D == 3)
+    launch(c, m.n_p2, k_gather_p2<3>, m.n_p2, d_ip.as<int64_t>(), d_il.as<int32_t>(), d_p2.as<int32_t>(),
+           d_vol.as<double>(), d_jinv.as<double>(), rp.as<int32_t>(), cols.as<int32_t>(), Mf.as<double>(),
+           Lf.as<double>(), (double*)nullptr);
+  else
+    launch(c, m.n_p2, k_gather_p2<2>, m.n_p2, d_ip.as<int64_t>(), d_il.as<int32_t>(), d_p2.as<int32_t>(),
+           d_vol.as<double>(), d_jinv.as<double>(), rp.as<int32_t>(), cols.as<int32_t>(), Mf.as<double>(),
+           Lf.as<double>(), (double*)nullptr);
+  build_sell(P2, rows, nat2int, nullptr, 1, L.S);
+  const int64_t nr = L.S.nrows;
+  L.nrows = nr;
+  L.v64.alloc(L.S.nnz_pad * sizeof(double));
+  launch(c, L.S.nnz_pad, k_fill, L.S.nnz_pad, L.S.src.as<int32_t>(), 1, c->prob.alpha, Mf.as<double>(), c->prob.mu,
+         Lf.as<double>(), L.v64.as<double>());
+  L.d64.alloc(nr * sizeof(double));
+  launch(c, nr, k_dinv, nr, L.S.slice_ptr.as<int64_t>(), L.S.cols.as<int32_t>(), L.v64.as<double>(),
+         L.d64.as<double>());
+  L.v32.alloc(L.S.nnz_pad * sizeof(float));
+  L.d32.alloc(nr * sizeof(float));
+  launch(c, L.S.nnz_pad, k_cast<double, float>, L.S.nnz_pad, L.v64.as<double>(), L.v32.as<float>());
+  launch(c, nr, k_cast<double, float>, nr, L.d64.as<double>(), L.d32.as<float>());
+  double lo, hi, g;
+  lanczos_bounds(c, L.S, L.v64.as<double>(), L.d64.as<double>(), std::min<int>(40, (int)nr), lo, hi, g);
+  L.bf.hi = std::min(g, 1.1 * hi);
+  L.bf.lo = std::max(0.9 * lo, L.bf.hi / 1000.0);
+  L.bs.hi = L.bf.hi;
+  L.bs.lo = L.bf.hi / c->mg_smooth_ratio;
+  HIP_CHECK(hipStreamSynchronize(c->stream));  // the local buffers are freed on return
+}
+
 void estimate_bounds(stokes_ctx* c) {
   const int steps = 40;
   double lo, hi, g;

@@ -96,6 +96,20 @@ struct MgLevel {
   Bounds bs, bf;        // smoothing interval, full spectrum
 };
 
+// One coarse level of the velocity multigrid (scalar alpha M + mu L on the
+// interior P2 nodes of the Kuhn mesh with n cells per side, natural order).
+struct VmgLevel {
+  int n = 0;
+  int64_t nrows = 0;
+  Sell S;
+  DevBuf v64, v32, d64, d32;  // operator values and inverse diagonal
+  Bounds bs, bf;              // smoothing interval, full spectrum
+  // interpolation from this level to the next finer one: P (fine rows x
+  // nrows) and its transpose R, FP64 and FP32 values
+  DevCsr P, R;
+  DevBuf pv64, pv32, rv64, rv32;
+};
+
 // A multigrid hierarchy on the nested Kuhn meshes n, n/2, ...  Level views
 // point either at context-owned operators or at levels in `own`.
 struct MgHier {
@@ -180,6 +194,15 @@ struct stokes_ctx {
   int64_t mg_dense_max = 1500;          // largest level solved densely
   double mg_smooth_ratio = 10.0;
   int use_mgx = 1;                      // lumped CC: precondition with mgx (0: mgq)
+
+  // velocity multigrid (built on first use; level 0 is sA / A, the coarse
+  // levels rediscretise alpha M + mu L on the coarse Kuhn meshes)
+  std::vector<std::unique_ptr<stokes::VmgLevel>> vmg;
+  bool vmg_built = false;
+  double vmg_mu = -1.0;                 // mu the hierarchy was built for
+  int64_t vmg_dense_n = 0;              // rows of the coarsest level if solved densely
+  stokes::DevBuf vmg_cinv64, vmg_cinv32;
+  int vmg_smooth_degree = 3;
 
   // lanes per row of the velocity-row kernels, key W * 2 + (FP32 ? 1 : 0)
   std::map<int, int> lanes;

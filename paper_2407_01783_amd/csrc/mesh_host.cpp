@@ -367,4 +367,88 @@ void galerkin_p1(int dim, int nf, int nc, const HostCsr& A, const std::vector<do
   }
 }
 
+void p2_prolongation(int dim, int nf, const std::vector<int32_t>& fine_nat, HostCsr& P, std::vector<double>& pv) {
+  const int nc = nf / 2;
+  const int64_t n2f = 2 * int64_t(nf) + 1, n2c = 2 * int64_t(nc) + 1, nic = n2c - 2;
+  const int64_t nrows = static_cast<int64_t>(fine_nat.size());
+  auto coarse_index = [&](const int64_t* G) -> int64_t {  // interior index or -1 on the boundary
+    int64_t idx = 0, st = 1;
+    for (int d = 0; d < dim; ++d, st *= nic) {
+      if (G[d] <= 0 || G[d] >= n2c - 1) return -1;
+      idx += (G[d] - 1) * st;
+    }
+    return idx;
+  };
+  std::vector<std::vector<std::pair<int32_t, double>>> rows(nrows);
+  parallel_for(nrows, [&](int64_t b, int64_t e) {
+    for (int64_t r = b; r < e; ++r) {
+      int64_t F[3] = {0, 0, 0}, rem = fine_nat[r];
+      for (int d = 0; d < dim; ++d) {
+        F[d] = rem % n2f;
+        rem /= n2f;
+      }
+      // coarse cell and local coordinates (quarters of the coarse cell)
+      int64_t cell[3];
+      double xi[3];
+      for (int d = 0; d < dim; ++d) {
+        cell[d] = std::min<int64_t>(F[d] / 4, nc - 1);
+        xi[d] = double(F[d] - 4 * cell[d]) / 4.0;
+      }
+      // Kuhn simplex: axes by decreasing local coordinate (ties by axis)
+      int pi[3] = {0, 1, 2};
+      std::stable_sort(pi, pi + dim, [&](int a, int b2) { return xi[a] > xi[b2]; });
+      double lam[4];
+      lam[0] = 1.0 - xi[pi[0]];
+      for (int a = 1; a < dim; ++a) lam[a] = xi[pi[a - 1]] - xi[pi[a]];
+      lam[dim] = xi[pi[dim - 1]];
+      int64_t v[4][3];
+      for (int d = 0; d < dim; ++d) v[0][d] = cell[d];
+      for (int a = 1; a <= dim; ++a) {
+        for (int d = 0; d < dim; ++d) v[a][d] = v[a - 1][d];
+        v[a][pi[a - 1]] += 1;
+      }
+      auto& row = rows[r];
+      row.clear();
+      auto add = [&](const int64_t* G, double w) {
+        if (w == 0.0) return;
+        const int64_t ci = coarse_index(G);
+        if (ci >= 0) row.emplace_back(static_cast<int32_t>(ci), w);
+      };
+      for (int a = 0; a <= dim; ++a) {  // vertex functions lam (2 lam - 1) at node 2 v_a
+        int64_t G[3];
+        for (int d = 0; d < dim; ++d) G[d] = 2 * v[a][d];
+        add(G, lam[a] * (2.0 * lam[a] - 1.0));
+      }
+      for (int a = 0; a <= dim; ++a)  // edge functions 4 lam_a lam_b at node v_a + v_b
+        for (int b2 = a + 1; b2 <= dim; ++b2) {
+          int64_t G[3];
+          for (int d = 0; d < dim; ++d) G[d] = v[a][d] + v[b2][d];
+          add(G, 4.0 * lam[a] * lam[b2]);
+        }
+      std::sort(row.begin(), row.end());
+      size_t o = 0;
+      for (size_t k = 0; k < row.size(); ++k) {
+        if (o > 0 && row[o - 1].first == row[k].first) row[o - 1].second += row[k].second;
+        else row[o++] = row[k];
+      }
+      row.resize(o);
+    }
+  });
+  P.nrows = nrows;
+  P.ncols = 1;
+  for (int d = 0; d < dim; ++d) P.ncols *= nic;
+  P.rowptr.assign(nrows + 1, 0);
+  for (int64_t r = 0; r < nrows; ++r) P.rowptr[r + 1] = P.rowptr[r] + static_cast<int64_t>(rows[r].size());
+  P.cols.resize(P.rowptr[nrows]);
+  pv.resize(P.rowptr[nrows]);
+  for (int64_t r = 0; r < nrows; ++r) {
+    int64_t o = P.rowptr[r];
+    for (const auto& pr : rows[r]) {
+      P.cols[o] = pr.first;
+      pv[o] = pr.second;
+      ++o;
+    }
+  }
+}
+
 }  // namespace stokes

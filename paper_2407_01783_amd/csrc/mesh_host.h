@@ -66,6 +66,15 @@ void product_pattern(const HostCsr& A, const HostCsr& At, const std::vector<int3
 void galerkin_p1(int dim, int nf, int nc, const HostCsr& A, const std::vector<double>& av, HostCsr& out,
                  std::vector<double>& ov);
 
+// P2 interpolation from the Kuhn mesh with nf / 2 cells per side to the one
+// with nf cells: row r is the fine P2 node fine_nat[r] (natural id on the
+// (2 nf + 1)^dim grid), columns are the coarse interior P2 nodes (natural
+// order among interior nodes of the (nf + 1)^dim grid), values the coarse
+// P2 basis functions at the fine node of the unjittered nested meshes:
+// lambda_a (2 lambda_a - 1) at vertices, 4 lambda_a lambda_b at edges.
+// Coarse boundary nodes (Dirichlet) are dropped.
+void p2_prolongation(int dim, int nf, const std::vector<int32_t>& fine_nat, HostCsr& P, std::vector<double>& pv);
+
 // Incidence node -> (simplex << 4 | local index) for the node table
 // nodes[e][0..nl), as CSR over n_nodes.
 void incidence(const std::vector<int32_t>& nodes, int nl, int64_t n_e, int64_t n_nodes,

@@ -192,6 +192,80 @@ T* wsp(stokes_ctx* c, const std::string& name, int64_t n) {
   return static_cast<T*>(c->workspace(name + (std::is_same<T, float>::value ? "_f" : "_d"), n * sizeof(T)));
 }
 
+
+// y[row][w] (+)= sum_k vals[k] x[cols[k]][w] over CSR rows (grid transfers
+// of the velocity multigrid, W interleaved components per node)
+template <typename T, int W, int ACC>
+__global__ __launch_bounds__(kBlock) void k_csr_w(int64_t nrows, const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ cols, const T* __restrict__ vals,
+                                                  const T* __restrict__ x, T* __restrict__ y) {
+  GRID_STRIDE_ROWS(row, nrows) {
+    T acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = ACC ? y[row * W + w] : T(0);
+    for (int32_t k = rp[row]; k < rp[row + 1]; ++k) {
+      const T v = vals[k];
+      const T* xp = x + (int64_t)cols[k] * W;
+#pragma unroll
+      for (int w = 0; w < W; ++w) acc[w] = fma(v, xp[w], acc[w]);
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) y[row * W + w] = acc[w];
+  }
+}
+
+// y[i][w] = sum_j Cinv[i][j] x[j][w]: one wavefront per row
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_dense_mv_w(int64_t n, const T* __restrict__ Ci, const T* __restrict__ x,
+                                                       T* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (row >= n) return;  // whole wavefronts exit together
+  double acc[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) acc[w] = 0;
+  for (int64_t j = lane; j < n; j += 64) {
+    const double a = Ci[row * n + j];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] += a * (double)x[j * W + w];
+  }
+#pragma unroll
+  for (int w = 0; w < W; ++w) acc[w] = wave_sum(acc[w]);
+  if (lane == 0)
+#pragma unroll
+    for (int w = 0; w < W; ++w) y[row * W + w] = (T)acc[w];
+}
+
+template <class F>
+void dispatch_w_mg(int W, F&& f) {
+  switch (W) {
+    case 2: f(IC<2>{}); break;
+    case 3: f(IC<3>{}); break;
+    case 4: f(IC<4>{}); break;
+    case 6: f(IC<6>{}); break;
+    case 8: f(IC<8>{}); break;
+    case 12: f(IC<12>{}); break;
+    case 16: f(IC<16>{}); break;
+    case 24: f(IC<24>{}); break;
+    default: throw Error(STOKES_ERR_UNSUPPORTED, "velocity multigrid width");
+  }
+}
+
+// dense symmetric matrix of a scalar sliced-ELL operator (host)
+std::vector<double> sell_dense(stokes_ctx* c, const Sell& S, const DevBuf& v64) {
+  const int64_t nr = S.nrows;
+  std::vector<int64_t> sp(S.nslices + 1);
+  std::vector<int32_t> cols(S.nnz_pad);
+  std::vector<double> vals(S.nnz_pad);
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+  HIP_CHECK(hipMemcpy(sp.data(), S.slice_ptr.p, sp.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  HIP_CHECK(hipMemcpy(cols.data(), S.cols.p, cols.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIP_CHECK(hipMemcpy(vals.data(), v64.p, vals.size() * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<double> A(nr * nr, 0.0);
+  for (int64_t r = 0; r < nr; ++r)
+    for (int64_t k = sp[r / 64] + r % 64; k < sp[r / 64 + 1]; k += 64) A[r * nr + cols[k]] += vals[k];
+  return A;
+}
 }  // namespace
 
 // Dense inverse of the coarsest level when it is small enough.
@@ -335,5 +409,161 @@ void mg_vcycle(stokes_ctx* c, const MgHier& H, int nrb, const T* r, T* e, int lv
 
 template void mg_vcycle<double>(stokes_ctx*, const MgHier&, int, const double*, double*, int);
 template void mg_vcycle<float>(stokes_ctx*, const MgHier&, int, const float*, float*, int);
+
+// ======================================================= velocity multigrid
+//
+// Geometric multigrid for the scalar velocity block alpha M + mu L (the
+// A~_{lambda,3} preconditioner of Sec. 3.2) on the nested Kuhn meshes n, n/2,
+// ...: the counterpart of the paper's fixed number of AMG V-cycles (Sec. 3.3).
+//   * level 0 is the assembled interior operator (internal row order), the
+//     coarse levels rediscretise alpha M + mu L on the coarse meshes (their
+//     vertices keep the fine jittered positions);
+//   * interpolation is P2 interpolation of the coarse basis at the fine P2
+//     nodes (exact for the nested unjittered meshes), restriction its
+//     transpose, coarse Dirichlet nodes dropped;
+//   * Chebyshev-Jacobi smoothing on the upper spectrum, the same polynomial
+//     before and after the correction, so the cycle is symmetric positive
+//     definite; the coarsest level (<= mg_dense_max rows) is solved densely.
+
+void build_vmg(stokes_ctx* c) {
+  c->vmg.clear();
+  c->vmg_dense_n = 0;
+  const HostMesh& fm = c->mesh;
+  const int D = fm.dim;
+  int nf = fm.n, stride = 1;
+  std::vector<int32_t> fine_nat = c->h_int2nat;
+  auto rows_of = [&](int n) { return ipow(2 * int64_t(n) - 1, D); };
+  while (nf % 2 == 0 && nf >= 4 && rows_of(nf) > c->mg_dense_max) {
+    const int nc = nf / 2;
+    stride *= 2;
+    auto L = std::make_unique<VmgLevel>();
+    L->n = nc;
+    HostMesh m;
+    build_mesh(D, nc, 0, 0.0, m);
+    const int64_t nf1 = fm.n + 1;
+    for (int64_t g = 0; g < m.n_p1; ++g) {
+      int64_t rem = g, fid = 0, st = 1;
+      for (int d = 0; d < D; ++d, st *= nf1) {
+        fid += (rem % (nc + 1)) * stride * st;
+        rem /= (nc + 1);
+      }
+      for (int d = 0; d < D; ++d) m.vcoords[g * D + d] = fm.vcoords[fid * D + d];
+    }
+    assemble_p2_level(c, m, *L);
+    HostCsr P, R;
+    std::vector<double> pv;
+    p2_prolongation(D, nf, fine_nat, P, pv);
+    std::vector<int64_t> tsrc;
+    transpose_pattern(P, R, tsrc);
+    std::vector<double> rv(tsrc.size());
+    for (size_t k = 0; k < tsrc.size(); ++k) rv[k] = pv[tsrc[k]];
+    auto up = [&](const HostCsr& h, const std::vector<double>& v, DevCsr& d, DevBuf& v64, DevBuf& v32) {
+      std::vector<int32_t> rp(h.rowptr.begin(), h.rowptr.end());
+      d.nrows = h.nrows;
+      d.nnz = h.rowptr.back();
+      upload(d.rowptr, rp);
+      upload(d.cols, h.cols);
+      upload(v64, v);
+      std::vector<float> f(v.begin(), v.end());
+      upload(v32, f);
+    };
+    up(P, pv, L->P, L->pv64, L->pv32);
+    up(R, rv, L->R, L->rv64, L->rv32);
+    // natural ids of the coarse interior nodes, the rows of the next level
+    fine_nat.clear();
+    for (int64_t v = 0; v < m.n_p2; ++v)
+      if (!m.p2_bnd[v]) fine_nat.push_back(static_cast<int32_t>(v));
+    c->vmg.push_back(std::move(L));
+    nf = nc;
+  }
+  // coarsest level: dense inverse when small
+  if (!c->vmg.empty()) {
+    VmgLevel& L = *c->vmg.back();
+    if (L.nrows <= c->mg_dense_max) {
+      const std::vector<double> inv = spd_inverse(sell_dense(c, L.S, L.v64), L.nrows);
+      std::vector<float> inv32(inv.begin(), inv.end());
+      upload(c->vmg_cinv64, inv);
+      upload(c->vmg_cinv32, inv32);
+      c->vmg_dense_n = L.nrows;
+    }
+  } else if (c->n_int <= c->mg_dense_max) {
+    const std::vector<double> inv = spd_inverse(sell_dense(c, c->sA, c->A64), c->n_int);
+    std::vector<float> inv32(inv.begin(), inv.end());
+    upload(c->vmg_cinv64, inv);
+    upload(c->vmg_cinv32, inv32);
+    c->vmg_dense_n = c->n_int;
+  }
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+  c->vmg_mu = c->prob.mu;
+  c->vmg_built = true;
+}
+
+template <class T>
+void vel_vcycle(stokes_ctx* c, int W, const T* r, T* e, int lv) {
+  const int nlev = static_cast<int>(c->vmg.size()) + 1;
+  const bool fine = lv == 0;
+  const VmgLevel* L = fine ? nullptr : c->vmg[lv - 1].get();
+  const Sell& S = fine ? c->sA : L->S;
+  const T* vals = fine ? ops::pick<T>(c->A64, c->A32) : ops::pick<T>(L->v64, L->v32);
+  const T* dinv = fine ? ops::pick<T>(c->dA64, c->dA32) : ops::pick<T>(L->d64, L->d32);
+  const Bounds bf = fine ? c->bA : L->bf;
+  const Bounds bs = fine ? Bounds{c->bA.hi / c->mg_smooth_ratio, c->bA.hi} : L->bs;
+  const int64_t nr = S.nrows, n = nr * W;
+  const std::string tag = "vmg" + std::to_string(lv);
+  T* d0 = wsp<T>(c, tag + "_d0", n);
+  T* d1 = wsp<T>(c, tag + "_d1", n);
+  T* res = wsp<T>(c, tag + "_res", n);
+  auto cheb = [&](const Bounds& b, int degree, const T* rin, T* z, int acc) {
+    const Cheb k = coef(b, degree);
+    ops::cheb_first<T>(c, S, vals, W, rin, dinv, (T)k.theta_inv, d0, res, z, (T)k.c1[0], (T)k.c2[0], acc);
+    T* da = d0;
+    T* db = d1;
+    for (int j = 2; j < degree; ++j) {
+      ops::cheb_step<T>(c, S, vals, W, da, db, res, res, z, dinv, (T)k.c1[j - 1], (T)k.c2[j - 1], nullptr, nullptr, 1,
+                        0, 0);
+      std::swap(da, db);
+    }
+  };
+  if (lv == nlev - 1) {  // coarsest
+    if (c->vmg_dense_n == nr) {
+      const T* Ci = ops::pick<T>(c->vmg_cinv64, c->vmg_cinv32);
+      dispatch_w_mg(W, [&](auto Wc) {
+        constexpr int WW = decltype(Wc)::value;
+        hipLaunchKernelGGL((k_dense_mv_w<T, WW>), dim3((nr + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0,
+                           c->stream, nr, Ci, r, e);
+      });
+      ops::check_launch();
+    } else {
+      cheb(bf, c->mg_coarse_degree, r, e, 0);
+    }
+    return;
+  }
+  const VmgLevel& C = *c->vmg[lv];
+  const int nu = std::max(2, c->vmg_smooth_degree);
+  T* t = wsp<T>(c, tag + "_t", n);
+  const int64_t ncn = C.nrows * W;
+  T* rc = wsp<T>(c, "vmg" + std::to_string(lv + 1) + "_rc", ncn);
+  T* ec = wsp<T>(c, "vmg" + std::to_string(lv + 1) + "_ec", ncn);
+  cheb(bs, nu, r, e, 0);                                 // pre-smoothing from zero
+  ops::spmv<T>(c, S, vals, W, e, t, (T)-1, r, (T)1);     // t = r - A e
+  dispatch_w_mg(W, [&](auto Wc) {
+    constexpr int WW = decltype(Wc)::value;
+    hipLaunchKernelGGL((k_csr_w<T, WW, 0>), dim3(ops::grid_for(C.nrows)), dim3(kBlock), 0, c->stream, C.nrows,
+                       C.R.rowptr.as<int32_t>(), C.R.cols.as<int32_t>(), ops::pick<T>(C.rv64, C.rv32), (const T*)t, rc);
+  });
+  ops::check_launch();
+  vel_vcycle<T>(c, W, rc, ec, lv + 1);
+  dispatch_w_mg(W, [&](auto Wc) {
+    constexpr int WW = decltype(Wc)::value;
+    hipLaunchKernelGGL((k_csr_w<T, WW, 1>), dim3(ops::grid_for(nr)), dim3(kBlock), 0, c->stream, nr,
+                       C.P.rowptr.as<int32_t>(), C.P.cols.as<int32_t>(), ops::pick<T>(C.pv64, C.pv32), (const T*)ec, e);
+  });
+  ops::check_launch();
+  ops::spmv<T>(c, S, vals, W, e, t, (T)-1, r, (T)1);     // t = r - A e
+  cheb(bs, nu, t, e, 1);                                 // post-smoothing, e += p(.) t
+}
+
+template void vel_vcycle<double>(stokes_ctx*, int, const double*, double*, int);
+template void vel_vcycle<float>(stokes_ctx*, int, const float*, float*, int);
 
 }  // namespace stokes

@@ -17,6 +17,12 @@ void assemble_galerkin(stokes_ctx* c, MgHier& H);
 // e = one multigrid V-cycle of hierarchy H applied to r (pressure layout)
 template <class T>
 void mg_vcycle(stokes_ctx* c, const MgHier& H, int nrb, const T* r, T* e, int level = 0);
+// velocity multigrid: coarse level assembly, hierarchy build, one V-cycle of
+// alpha M + mu L applied to W = dim x nrhs interleaved components
+void assemble_p2_level(stokes_ctx* c, const HostMesh& m, VmgLevel& L);
+void build_vmg(stokes_ctx* c);
+template <class T>
+void vel_vcycle(stokes_ctx* c, int W, const T* r, T* e, int level = 0);
 void estimate_bounds(stokes_ctx* c);
 void reform_A(stokes_ctx* c);
 void lanczos_bounds(stokes_ctx* c, const Sell& S, const double* vals, const double* dinv, int steps, double& rlo,

@@ -298,9 +298,12 @@ class Engine {
 
   // x = A~^{-1} b (velocity block)
   void vel_solve(const T* b, T* x) {
-    const Prec pc{&c_->sA, A(), dA(), c_->bA, std::max(1, o_.cheb_degree), {}};
+    Prec pc{&c_->sA, A(), dA(), c_->bA, std::max(1, o_.cheb_degree), {}};
+    const bool mg = o_.vel_pc == STOKES_VEL_MG;
+    if (mg) pc.apply = [this](const T* r, T* z) { vel_vcycle<T>(c_, W_, r, z, 0); };
     if (o_.inner_mode == STOKES_INNER_FIXED) {
-      cheb_apply("vfx", c_->sA, A(), dA(), c_->bA, std::max(1, o_.cheb_degree), W_, b, x);
+      if (mg) vel_vcycle<T>(c_, W_, b, x, 0);
+      else cheb_apply("vfx", c_->sA, A(), dA(), c_->bA, std::max(1, o_.cheb_degree), W_, b, x);
       return;
     }
     Op op;
@@ -797,6 +800,7 @@ int refine_loop(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, 
 int solve_internal(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, const double* F, const double* g,
                    double* xu, double* xp, SolveStats& st) {
   ops::ensure_lanes(c, c->dim * nrb, false);  // FP64 outer operator
+  if (o.vel_pc == STOKES_VEL_MG && (!c->vmg_built || c->vmg_mu != c->prob.mu)) build_vmg(c);
   if (o.precision == STOKES_MIXED) ops::ensure_lanes(c, c->dim * nrb, true);
   if (o.precision == STOKES_MIXED) return refine_loop<float>(c, o, method, nrb, F, g, xu, xp, st);
   return refine_loop<double>(c, o, method, nrb, F, g, xu, xp, st);
