@@ -183,6 +183,22 @@ stokes_status stokes_solve_coupled(stokes_ctx* ctx, int32_t nrhs, const double* 
                                    double* u, double* p, const stokes_solve_opts* opts,
                                    stokes_solve_info* info);
 
+/* One rotational incremental pressure-correction step, the comparator of
+ * Sec. 7.5 (one velocity problem, one pressure Laplacian, one pressure mass
+ * problem), from p_old ([nrhs][n_p1], NULL = 0):
+ *     A u = F~ + B^T p_old,  d = B u - g,  L_Q phi = -alpha d,  M_Q psi = d,
+ *     p = p_old + phi - mu psi  (zero integral),
+ * with (F~, g) the lifted right-hand side of stokes_solve_schur (A without
+ * the augmented-Lagrangian term).  Each linear solve reaches a true FP64
+ * relative residual <= opts->rtol (inner CG in the opts precision with FP64
+ * refinement; velocity preconditioner opts->vel_pc, pressure Laplacian CG
+ * preconditioned by a multigrid V-cycle of M_Q + L_Q, mass CG by
+ * Chebyshev-Jacobi).  info->rel_res is the largest of the three final
+ * residuals.  Layouts as in stokes_solve_schur. */
+stokes_status stokes_projection_step(stokes_ctx* ctx, int32_t nrhs, const double* f, const double* ubc,
+                                     const double* p_old, double* u, double* p, const stokes_solve_opts* opts,
+                                     stokes_solve_info* info);
+
 /* Adjoint of the solve: given the forward velocity u ([nrhs][dim][n_p2]) and
  * the loss gradients dJdu ([nrhs][dim][n_p2], boundary entries ignored) and
  * dJdp ([nrhs][n_p1], NULL = 0), solve the transposed coupled system

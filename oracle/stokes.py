@@ -232,6 +232,29 @@ class StokesSystem:
         U, P, _ = self.solve_minres(F, g, **kw)
         return U, P
 
+    # ------------------------------------------------------------- projection
+    def projection_step(self, f, ubc=None, p_old=None):
+        """One rotational incremental pressure-correction step, the comparator
+        of Sec. 7.5 (one velocity problem, one pressure Laplacian, one
+        pressure mass problem), each solved directly:
+            A U = F~ + B_I^T p_old,   d = B_I U - g,
+            L_Q phi = -alpha d (zero mean),   M_Q psi = d,
+            P = p_old + phi - mu psi  (zero integral).
+        The coupled solution is its fixed point: with p_old = P*, U = U*
+        and d = 0."""
+        d_ = self.d
+        F, g = self.rhs(f, ubc)
+        p0 = np.zeros(self.np1) if p_old is None else np.asarray(p_old, dtype=np.float64)
+        bu = F + np.stack([self.B_I[c].T @ p0 for c in range(d_)])
+        U = spla.spsolve(self.Avel_II.tocsc(), bu.ravel()).reshape(d_, self.nI)
+        dvec = sum(self.B_I[c] @ U[c] for c in range(d_)) - g
+        one = sp.csr_matrix(np.ones((self.np1, 1)))
+        K = sp.bmat([[self.mats.LQ, one], [one.T, None]], format="csc")
+        phi = spla.spsolve(K, np.concatenate([-self.alpha * dvec, [0.0]]))[: self.np1]
+        psi = spla.spsolve(self.mats.MQ.tocsc(), dvec)
+        P = self.normalize_pressure(p0 + phi - self.mu * psi)
+        return U, P
+
     # ------------------------------------------------------------- adjoint
     def adjoint_gradient(self, u_full, dJdu_full, dJdp=None, method="auto", **kw):
         """Gradient of a loss J(u, p) w.r.t. the nodal forcing f and mu.

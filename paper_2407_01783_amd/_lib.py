@@ -61,7 +61,7 @@ EXPORTS = [
     "stokes_default_opts", "stokes_problem_sizes", "stokes_build_mesh_host", "stokes_host_pattern",
     "stokes_assemble", "stokes_solve_schur", "stokes_solve_coupled", "stokes_solve_adjoint", "stokes_apply",
     "stokes_residual", "stokes_query", "stokes_set_mu", "stokes_set_stream", "stokes_export_mesh",
-    "stokes_export_csr", "stokes_bounds", "stokes_destroy", "stokes_last_error",
+    "stokes_export_csr", "stokes_bounds", "stokes_destroy", "stokes_last_error", "stokes_projection_step",
 ]
 
 _lib = None
@@ -94,6 +94,7 @@ def load():
         "stokes_solve_schur": (st, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, po, pi]),
         "stokes_solve_coupled": (st, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, po, pi]),
         "stokes_solve_adjoint": (st, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, po, pi]),
+        "stokes_projection_step": (st, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, po, pi]),
         "stokes_apply": (st, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P]),
         "stokes_residual": (st, [_P, ctypes.c_int32, _P, _P, _P, _P, _D]),
         "stokes_query": (st, [_P, _I64]),

@@ -227,6 +227,59 @@ stokes_status solve_forward(stokes_ctx* c, int method, int32_t nrhs, const doubl
   return status;
 }
 
+stokes_status projection_forward(stokes_ctx* c, int32_t nrhs, const double* f, const double* ubc,
+                                 const double* p_old, double* u, double* p, const stokes_solve_opts* o,
+                                 stokes_solve_info* info) {
+  if (!c) throw Error(STOKES_ERR_ARG, "ctx is NULL");
+  if (nrhs < 1) throw Error(STOKES_ERR_ARG, "nrhs must be >= 1");
+  if (!f || !u || !p) throw Error(STOKES_ERR_ARG, "f, u and p must not be NULL");
+  check_opts(o);
+  info_reset(info);
+  const double t0 = wall();
+  HIP_CHECK(hipSetDevice(c->device));
+  StreamScope scope(c);
+  prof_start(c, o);
+  const int D = c->dim;
+  stokes_status status = STOKES_OK;
+  double maxres = 0;
+  for (int r0 = 0; r0 < nrhs;) {
+    const int nrb = chunk_size(nrhs - r0);
+    const int64_t nu = c->n_int * D * nrb, np = c->n_p1 * nrb;
+    double* F = static_cast<double*>(c->workspace("abi_F", nu * sizeof(double)));
+    double* g = static_cast<double*>(c->workspace("abi_g", np * sizeof(double)));
+    double* xu = static_cast<double*>(c->workspace("abi_xu", nu * sizeof(double)));
+    double* xp = static_cast<double*>(c->workspace("abi_xp", np * sizeof(double)));
+    double* po_int = nullptr;
+    const int64_t vo = int64_t(r0) * D * c->n_p2, po = int64_t(r0) * c->n_p1;
+    ops::rhs(c, nrb, f + vo, ubc ? ubc + vo : nullptr, F, g);
+    ops::remove_mean<double>(c, nrb, g);
+    if (p_old) {
+      po_int = static_cast<double*>(c->workspace("abi_pold", np * sizeof(double)));
+      ops::p_in<double>(c, nrb, p_old + po, po_int);
+    }
+    SolveStats st;
+    const int s = projection_internal(c, *o, nrb, F, g, po_int, xu, xp, st);
+    ops::vel_out<double>(c, nrb, xu, ubc ? ubc + vo : nullptr, u + vo, 1);
+    ops::p_out<double>(c, nrb, xp, p + po);
+    if (s != STOKES_OK) status = s;
+    for (double rr : st.rel_res) maxres = std::max(maxres, rr);
+    if (info) {
+      info->inner_iters_u += st.inner_u;
+      info->inner_iters_p += st.inner_p;
+      info->refinements += st.sweeps;
+    }
+    r0 += nrb;
+  }
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+  prof_finish(c, info);
+  if (info) {
+    info->converged = status == STOKES_OK ? 1 : 0;
+    info->rel_res = maxres;
+    info->seconds_total = wall() - t0;
+  }
+  return status;
+}
+
 }  // namespace
 }  // namespace stokes
 
@@ -468,6 +521,12 @@ stokes_status stokes_solve_coupled(stokes_ctx* ctx, int32_t nrhs, const double* 
                                    const double* x0_u, const double* x0_p, double* u, double* p,
                                    const stokes_solve_opts* opts, stokes_solve_info* info) {
   return guard([&]() { return solve_forward(ctx, 0, nrhs, f, ubc, x0_u, x0_p, u, p, opts, info); });
+}
+
+stokes_status stokes_projection_step(stokes_ctx* ctx, int32_t nrhs, const double* f, const double* ubc,
+                                     const double* p_old, double* u, double* p, const stokes_solve_opts* opts,
+                                     stokes_solve_info* info) {
+  return guard([&]() { return projection_forward(ctx, nrhs, f, ubc, p_old, u, p, opts, info); });
 }
 
 stokes_status stokes_solve_adjoint(stokes_ctx* c, int32_t nrhs, const double* u, const double* dJdu,

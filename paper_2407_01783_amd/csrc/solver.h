@@ -19,4 +19,10 @@ struct SolveStats {
 int solve_internal(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, const double* F, const double* g,
                    double* xu, double* xp, SolveStats& st);
 
+// One pressure-correction step from p_old (internal layout, may be null):
+// u and p in xu / xp.  rel_res = the largest final relative residual of its
+// three linear solves.
+int projection_internal(stokes_ctx* c, const stokes_solve_opts& o, int nrb, const double* F, const double* g,
+                        const double* pold, double* xu, double* xp, SolveStats& st);
+
 }  // namespace stokes

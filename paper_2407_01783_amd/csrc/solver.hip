@@ -115,6 +115,7 @@ class Engine {
   int64_t np() const { return c_->n_p1 * nrb_; }
 
   const T* A() const { return ops::pick<T>(c_->A64, c_->A32); }
+  void no_augmented_lagrangian() { gamma_ = 0; }
   const T* dA() const { return ops::pick<T>(c_->dA64, c_->dA32); }
   Scalars* scal(int i) { return c_->scal.as<Scalars>() + i; }
 
@@ -329,6 +330,16 @@ class Engine {
     }
     st_.inner_u += pcg("vcg", op, A(), pc, c_->n_int, W_, cps, b, x, o_.inner_rtol_u, o_.max_inner, 0, false,
                        o_.inner_its_u);
+  }
+
+  // x = M_Q^{-1} b by CG preconditioned with Chebyshev-Jacobi on the exact
+  // element bounds of the Jacobi-scaled P1 mass (tolerance inner_rtol_p)
+  void mq_solve(const T* b, T* x) {
+    Op op;
+    op.S = &c_->sQ;
+    const Prec pc{&c_->sQ, ops::pick<T>(c_->MQ64, c_->MQ32), ops::pick<T>(c_->dMQ64, c_->dMQ32), c_->bMQ, 4, {}};
+    st_.inner_p += pcg("pmq", op, ops::pick<T>(c_->MQ64, c_->MQ32), pc, c_->n_p1, nrb_, 1, b, x, o_.inner_rtol_p,
+                       o_.max_inner, 1, true);
   }
 
   // t = X z for the Cahouet-Chabard family
@@ -795,6 +806,119 @@ int refine_loop(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, 
   }
   ops::normalize_pressure<double>(c, nrb, xp);
   return status;
+}
+
+// ======================================================================
+// One rotational incremental pressure-correction step (the comparator of
+// Sec. 7.5: one velocity problem, one pressure Laplacian, one pressure mass
+// problem), each solved to a true FP64 relative residual <= rtol by inner CG
+// in T with FP64 refinement:
+//   A u = F + B^T p_old;   d = B u - g;   L_Q phi = -alpha d;   M_Q psi = d;
+//   p = p_old + phi - mu psi, normalised to zero mean.
+template <class T>
+int projection_loop(stokes_ctx* c, const stokes_solve_opts& o, int nrb, const double* F, const double* g,
+                    const double* pold, double* xu, double* xp, SolveStats& st) {
+  stokes_solve_opts oi = o;
+  const bool f32 = std::is_same<T, float>::value;
+  const double inner = f32 ? std::max(o.rtol, 1e-5) : 0.5 * o.rtol;
+  oi.inner_mode = STOKES_INNER_TOL;
+  oi.inner_rtol_u = inner;
+  oi.inner_rtol_p = inner;
+  oi.schur_pc = STOKES_CC_LAPLACE;
+  Engine<T> e(c, oi, nrb, st);
+  e.no_augmented_lagrangian();
+  Engine<double> e64(c, oi, nrb, st);
+  const int64_t nu = c->n_int * c->dim * nrb, np = c->n_p1 * nrb;
+  auto ws = [&](const char* name, int64_t n) { return static_cast<double*>(c->workspace(name, n * sizeof(double))); };
+  T* rT = f32 ? e.buf("pj_rT", std::max(nu, np)) : nullptr;
+  T* dT = f32 ? e.buf("pj_dT", std::max(nu, np)) : nullptr;
+  double* r = ws("pj_r", std::max(nu, np));
+  double* dd = ws("pj_dd", std::max(nu, np));
+  double worst = 0;
+  int status = STOKES_OK;
+  // x = K^{-1} b to rtol: r = b - K x in FP64, inner solve in T, x += d.
+  // negligible: per right-hand side, a right-hand side norm at the rounding
+  // level of the data it was formed from (then x = 0).
+  auto refined = [&](bool vel, bool mean_free, const double* b, double* x, auto apply64, auto innerT,
+                     const std::vector<double>& negligible) {
+    const int64_t n = vel ? nu : np;
+    HIP_CHECK(hipMemsetAsync(x, 0, n * sizeof(double), c->stream));
+    std::vector<double> bn = vel ? e64.dots(b, b, nullptr, nullptr) : e64.dots(nullptr, nullptr, b, b);
+    bool skip = true;
+    for (int k = 0; k < nrb; ++k) skip = skip && std::sqrt(bn[k]) <= negligible[k];
+    if (skip) return;
+    double rel = 0;
+    for (int sweep = 0;; ++sweep) {
+      apply64(x, r);
+      ops::axpby<double>(c, n, 1.0, b, -1.0, r);  // r = b - K x
+      std::vector<double> rn = vel ? e64.dots(r, r, nullptr, nullptr) : e64.dots(nullptr, nullptr, r, r);
+      rel = 0;
+      for (int k = 0; k < nrb; ++k) rel = std::max(rel, bn[k] > 0 ? std::sqrt(rn[k] / bn[k]) : 0.0);
+      if (rel <= o.rtol) break;
+      if (mean_free) ops::remove_mean<double>(c, nrb, r);  // the pressure Laplacian acts on 1-perp
+      if (sweep >= o.max_refine) {
+        status = STOKES_NOT_CONVERGED;
+        break;
+      }
+      st.sweeps += 1;
+      if constexpr (std::is_same<T, double>::value) {
+        innerT(r, dd);
+      } else {
+        ops::cast<double, T>(c, n, r, rT);
+        innerT(rT, dT);
+        ops::cast<T, double>(c, n, dT, dd);
+      }
+      ops::axpby<double>(c, n, 1.0, dd, 1.0, x);
+    }
+    worst = std::max(worst, rel);
+  };
+  // 1. velocity
+  double* bu = ws("pj_bu", nu);
+  if (pold) ops::Btmul<double>(c, nrb, pold, nullptr, bu, 1.0, F, 1.0);
+  else HIP_CHECK(hipMemcpyAsync(bu, F, nu * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  refined(true, false, bu, xu, [&](const double* x, double* y) { ops::velop<double>(c, nrb, x, y, 1.0, nullptr, 0.0); },
+          [&](const T* rr, T* z) { e.vel_solve(rr, z); }, std::vector<double>(nrb, 0.0));
+  // 2. divergence data d = B u - g and the pressure Laplacian; d below
+  // 1e-13 |B|_F |u| + 1e-12 |g| is cancellation noise (u already discretely
+  // divergence free: the fixed point) and gives phi = psi = 0
+  double* d = ws("pj_d", np);
+  ops::Bmul<double>(c, nrb, xu, d, 1.0, g, -1.0);
+  const double bfro = std::sqrt(ops::dot_host<double>(c, c->sB.nnz_pad * c->dim, 1, c->B64.as<double>(),
+                                                      c->B64.as<double>())[0]);
+  std::vector<double> un = e64.dots(xu, xu, nullptr, nullptr), gn = e64.dots(nullptr, nullptr, g, g);
+  std::vector<double> neg_d(nrb), neg_phi(nrb);
+  for (int k = 0; k < nrb; ++k) {
+    neg_d[k] = 1e-13 * bfro * std::sqrt(un[k]) + 1e-12 * std::sqrt(gn[k]);
+    neg_phi[k] = c->prob.alpha * neg_d[k];
+  }
+  double* bphi = ws("pj_bphi", np);
+  ops::axpby<double>(c, np, -c->prob.alpha, d, 0.0, bphi);
+  double* phi = ws("pj_phi", np);
+  refined(false, true, bphi, phi,
+          [&](const double* x, double* y) { ops::spmv<double>(c, c->sQ, c->LQ64.as<double>(), nrb, x, y, 1.0, nullptr, 0.0); },
+          [&](const T* rr, T* z) { e.x_solve(rr, z); }, neg_phi);
+  // 3. pressure mass
+  double* psi = ws("pj_psi", np);
+  refined(false, false, d, psi,
+          [&](const double* x, double* y) { ops::spmv<double>(c, c->sQ, c->MQ64.as<double>(), nrb, x, y, 1.0, nullptr, 0.0); },
+          [&](const T* rr, T* z) { e.mq_solve(rr, z); }, neg_d);
+  // 4. p = p_old + phi - mu psi
+  if (pold) HIP_CHECK(hipMemcpyAsync(xp, pold, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  else HIP_CHECK(hipMemsetAsync(xp, 0, np * sizeof(double), c->stream));
+  ops::axpby<double>(c, np, 1.0, phi, 1.0, xp);
+  ops::axpby<double>(c, np, -c->prob.mu, psi, 1.0, xp);
+  ops::normalize_pressure<double>(c, nrb, xp);
+  st.rel_res.assign(nrb, worst);
+  return status;
+}
+
+int projection_internal(stokes_ctx* c, const stokes_solve_opts& o, int nrb, const double* F, const double* g,
+                        const double* pold, double* xu, double* xp, SolveStats& st) {
+  ops::ensure_lanes(c, c->dim * nrb, false);
+  if (o.precision == STOKES_MIXED) ops::ensure_lanes(c, c->dim * nrb, true);
+  if (o.vel_pc == STOKES_VEL_MG && (!c->vmg_built || c->vmg_mu != c->prob.mu)) build_vmg(c);
+  if (o.precision == STOKES_MIXED) return projection_loop<float>(c, o, nrb, F, g, pold, xu, xp, st);
+  return projection_loop<double>(c, o, nrb, F, g, pold, xu, xp, st);
 }
 
 int solve_internal(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, const double* F, const double* g,

@@ -147,6 +147,23 @@ class StokesProblem:
         d["status"] = status
         return u, p, d
 
+    def projection_step(self, f, p_old=None, ubc=None, **opts):
+        """One pressure-correction step (stokes_projection_step); returns (u, p, info)."""
+        nrhs = self._nrhs(f)
+        f = self._vel(f, nrhs)
+        ubc = self._vel(ubc, nrhs) if ubc is not None else None
+        p_old = self._pres(p_old, nrhs) if p_old is not None else None
+        u = torch.empty_like(f)
+        p = torch.empty((nrhs, self.n_p1), dtype=torch.float64, device=self.device)
+        o = _lib.default_opts(**opts)
+        info = _lib.SolveInfo()
+        check(self.lib.stokes_set_stream(self.ctx, _stream_handle()))
+        status = check(self.lib.stokes_projection_step(self.ctx, nrhs, ptr(f), ptr(ubc), ptr(p_old), ptr(u), ptr(p),
+                                                       ctypes.byref(o), ctypes.byref(info)), "stokes_projection_step")
+        d = info.as_dict()
+        d["status"] = status
+        return u, p, d
+
     def adjoint(self, u, dJdu, dJdp=None, **opts):
         """Adjoint solve; returns (lam_u, lam_p, dJdf, dJdmu, info)."""
         nrhs = self._nrhs(u)

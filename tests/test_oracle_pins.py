@@ -395,6 +395,35 @@ def test_strain_adjoint_gradient_vs_finite_differences():
     assert abs(fd - dJdmu) <= 1e-6 * abs(fd)
 
 
+def test_projection_step_fixed_point_and_pieces():
+    """The coupled solution is the fixed point of the pressure-correction step
+    (with p_old = P*, U = U* and the divergence data vanish); away from it the
+    pressure Laplacian is solvable (1^T d = 0) and the step matches a dense
+    minimum-norm computation of the same three solves."""
+    for dim, n, strain in ((2, 4, False), (3, 2, False), (3, 2, True)):
+        m = mesh.KuhnMesh(dim, n, seed=7, jitter=0.1)
+        s = stokes.StokesSystem(m, 0.3, 40.0, strain=strain)
+        rng = np.random.default_rng(dim)
+        f = inputs.fourier_forcing(m.p2coords, 1000 + dim)
+        ubc = rng.standard_normal((dim, m.n_p2))
+        F, g = s.rhs(f, ubc)
+        Us, Ps = s.solve_direct(F, g)
+        U, P = s.projection_step(f, ubc, Ps)
+        assert np.abs(U - Us).max() <= 1e-10 * np.abs(Us).max()
+        assert np.abs(P - Ps).max() <= 1e-9 * np.abs(Ps).max()
+        # from p_old = 0: dense route
+        U1, P1 = s.projection_step(f, ubc, None)
+        Ad = s.Avel_II.toarray()
+        U2 = np.linalg.solve(Ad, F.ravel()).reshape(dim, -1)
+        d = sum(s.B_I[c] @ U2[c] for c in range(dim)) - g
+        assert abs(d.sum()) <= 1e-12 * np.abs(d).max()
+        phi = np.linalg.lstsq(s.mats.LQ.toarray(), -s.alpha * d, rcond=None)[0]
+        psi = np.linalg.solve(s.mats.MQ.toarray(), d)
+        P2 = s.normalize_pressure(phi - s.mu * psi)
+        assert np.abs(U1 - U2).max() <= 1e-10 * np.abs(U2).max()
+        assert np.abs(P1 - P2).max() <= 1e-8 * np.abs(P2).max()
+
+
 # ------------------------------------------------------------------- solves
 
 
