@@ -116,6 +116,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=16, help="mesh size of the CPU oracle sample")
     ap.add_argument("--opt", action="append", default=[], help="solver option override key=value")
+    ap.add_argument("--projection", action="store_true",
+                    help="also time one pressure-correction step (the comparator of the paper's Sec. 7.5) with the "
+                         "same tolerance, and report the solve / projection time ratio")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed solves, copy 1 GiB device-to-device 3 times (a kernel of known size "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -181,6 +184,25 @@ def main():
                 "outer_iters": infos64[-1]["outer_iters"], "rel_res": infos64[-1]["rel_res"]}
         print(f"[bench] fp64: {el64 / args.steps * 1e3:.1f} ms/solve", file=sys.stderr, flush=True)
 
+    projection = None
+    if args.projection:
+        popts = dict(precision=1, rtol=opts["rtol"], max_inner=5000, max_refine=30)
+
+        def proj():
+            return prob.projection_step(f, **popts)
+        proj()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            _, _, pinfo = proj()
+        torch.cuda.synchronize()
+        elp = (time.perf_counter() - t) / args.steps
+        projection = {"value": dofs / elp, "ms_per_step": elp * 1e3, "converged": pinfo["status"] == 0,
+                      "rel_res": pinfo["rel_res"], "inner_iters_u": pinfo["inner_iters_u"],
+                      "inner_iters_p": pinfo["inner_iters_p"],
+                      "solve_over_projection": (el_mixed / args.steps) / elp}
+        print(f"[bench] projection step: {elp * 1e3:.1f} ms", file=sys.stderr, flush=True)
+
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -214,6 +236,7 @@ def main():
                    "refinements": infos[-1]["refinements"], "setup_s": setup_s},
         "fp64": fp64,
         "mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
+        "projection": projection,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": measured_traffic(args.workload, args.nrhs, args.strain),
