@@ -46,7 +46,7 @@ WORKLOADS = {
 WORKLOAD_SOLVER = {"cube128": dict(restart=10)}
 
 SOLVER = dict(method="coupled", rtol=1e-8, cheb_degree=6, inner_mode=1, inner_rtol_u=1e-2, inner_rtol_p=1e-1,
-              coupled_pc=1, schur_pc=1, restart=30, max_outer=500, max_refine=12)
+              coupled_pc=1, schur_pc=1, restart=30, max_outer=500, max_refine=12, arnoldi_fp64=0)
 
 
 PROFILE_DIR = os.path.join(ROOT, "profiles")

@@ -116,7 +116,12 @@ typedef struct {
                              iterations (no convergence checks); 0: use inner_rtol_u */
   int32_t inner_its_p;    /* the same for the inner pressure CG (0: inner_rtol_p) */
   int32_t vel_pc;         /* velocity-block preconditioner: STOKES_VEL_CHEB or STOKES_VEL_MG */
-  int32_t reserved[1];    /* must be 0 */
+  int32_t arnoldi_fp64;   /* STOKES_MIXED coupled solves: 0 = the FGMRES basis and
+                             K_gamma products run in FP32 inside the FP64
+                             refinement (each sweep asks a 1e-5 reduction of its
+                             own FP64 residual); 1 = FP64 basis and K_gamma
+                             products, only the preconditioner in FP32.  Ignored
+                             for STOKES_FP64 and the Schur method. */
 } stokes_solve_opts;
 
 typedef struct {

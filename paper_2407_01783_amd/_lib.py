@@ -43,7 +43,7 @@ class SolveOpts(ctypes.Structure):
                 ("cheb_degree", ctypes.c_int32), ("inner_rtol_u", ctypes.c_double),
                 ("inner_rtol_p", ctypes.c_double), ("schur_pc", ctypes.c_int32), ("coupled_pc", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("profile", ctypes.c_int32), ("inner_its_u", ctypes.c_int32),
-                ("inner_its_p", ctypes.c_int32), ("vel_pc", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("inner_its_p", ctypes.c_int32), ("vel_pc", ctypes.c_int32), ("arnoldi_fp64", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -974,9 +974,9 @@ constexpr int kMdotChunk = 8;  // basis vectors per pass over w
 // Partial dots h[j][r] = V_j . w for the basis vectors j of chunk blockIdx.y
 // (kMdotChunk at a time, so w is read once per chunk): block partials to
 // part[((chunk * gridDim.x + block) * kMdotChunk + j) * NRB + r].
-template <typename TV, int D, int NRB>
+template <typename TV, typename TW, int D, int NRB>
 __global__ __launch_bounds__(kBlock) void k_mdot(int64_t n_int, int64_t n_p1, const TV* __restrict__ V, int64_t ldv,
-                                                 int nb, const double* __restrict__ w, double* __restrict__ part) {
+                                                 int nb, const TW* __restrict__ w, double* __restrict__ part) {
   constexpr int W = D * NRB, CH = kMdotChunk;
   const int sub = (int)(threadIdx.x % NRB);
   const int j0 = blockIdx.y * CH;
@@ -991,7 +991,7 @@ __global__ __launch_bounds__(kBlock) void k_mdot(int64_t n_int, int64_t n_p1, co
       const int64_t o = t * W + sub * D;
       double wv[D];
 #pragma unroll
-      for (int d = 0; d < D; ++d) wv[d] = w[o + d];
+      for (int d = 0; d < D; ++d) wv[d] = (double)w[o + d];
 #pragma unroll
       for (int j = 0; j < CH; ++j) {
         if (j < nj) {
@@ -1004,7 +1004,7 @@ __global__ __launch_bounds__(kBlock) void k_mdot(int64_t n_int, int64_t n_p1, co
       }
     } else {
       const int64_t o = nv + (t - n_int) * NRB + sub;
-      const double wv = w[o];
+      const double wv = (double)w[o];
 #pragma unroll
       for (int j = 0; j < CH; ++j)
         if (j < nj) acc[j] += (double)V[(int64_t)(j0 + j) * ldv + o] * wv;
@@ -1042,11 +1042,12 @@ __global__ __launch_bounds__(kBlock) void k_mdot_fin(int nblk, const double* __r
   if (threadIdx.x < NRB) h[i * NRB + threadIdx.x] = tot[threadIdx.x];
 }
 
-// w += sgn * sum_{i<nb} h[i][r] V_i ; NORM: res[r] = ||w_r||^2 after the update
-template <typename TV, int D, int NRB, int NORM>
+// w += sgn * sum_{i<nb} h[i][r] V_i (accumulated in FP64, stored in TW);
+// NORM: res[r] = ||w_r||^2 of the stored values
+template <typename TV, typename TW, int D, int NRB, int NORM>
 __global__ __launch_bounds__(kBlock) void k_mupdate(int64_t n_int, int64_t n_p1, const TV* __restrict__ V,
                                                     int64_t ldv, int nb, const double* __restrict__ h, double sgn,
-                                                    double* __restrict__ w, double* res, double* partials) {
+                                                    TW* __restrict__ w, double* res, double* partials) {
   constexpr int W = D * NRB;
   __shared__ double hs[64 * NRB];
   for (int i = threadIdx.x; i < nb * NRB; i += blockDim.x) hs[i] = sgn * h[i];
@@ -1060,7 +1061,7 @@ __global__ __launch_bounds__(kBlock) void k_mupdate(int64_t n_int, int64_t n_p1,
       const int64_t o = t * W + sub * D;
       double a[D];
 #pragma unroll
-      for (int d = 0; d < D; ++d) a[d] = w[o + d];
+      for (int d = 0; d < D; ++d) a[d] = (double)w[o + d];
       for (int i = 0; i < nb; ++i) {
         const TV* v = V + (int64_t)i * ldv + o;
         const double hi = hs[i * NRB + sub];
@@ -1069,15 +1070,17 @@ __global__ __launch_bounds__(kBlock) void k_mupdate(int64_t n_int, int64_t n_p1,
       }
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        w[o + d] = a[d];
-        if (NORM) part += a[d] * a[d];
+        const TW st = (TW)a[d];
+        w[o + d] = st;
+        if (NORM) part += (double)st * (double)st;
       }
     } else {
       const int64_t o = nv + (t - n_int) * NRB + sub;
-      double a = w[o];
+      double a = (double)w[o];
       for (int i = 0; i < nb; ++i) a += hs[i * NRB + sub] * (double)V[(int64_t)i * ldv + o];
-      w[o] = a;
-      if (NORM) part += a * a;
+      const TW st = (TW)a;
+      w[o] = st;
+      if (NORM) part += (double)st * (double)st;
     }
   }
   if (NORM) {
@@ -1089,15 +1092,15 @@ __global__ __launch_bounds__(kBlock) void k_mupdate(int64_t n_int, int64_t n_p1,
 }
 
 // v = s[r] * w  (coupled vectors, per right-hand-side scale)
-template <int D, int NRB>
+template <typename TS, int D, int NRB>
 __global__ __launch_bounds__(kBlock) void k_scale_coupled(int64_t n_int, int64_t n_p1, Coef8 s,
-                                                          const double* __restrict__ w, double* __restrict__ v) {
+                                                          const TS* __restrict__ w, TS* __restrict__ v) {
   constexpr int W = D * NRB;
   const int64_t nv = n_int * W;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv + n_p1 * NRB;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int r = i < nv ? (int)((i % W) / D) : (int)((i - nv) % NRB);
-    v[i] = s.v[r] * w[i];
+    v[i] = (TS)(s.v[r] * (double)w[i]);
   }
 }
 

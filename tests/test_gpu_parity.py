@@ -309,6 +309,25 @@ def test_batched_matches_single_and_mixed(gpu_lib):
         assert _rel(u1.cpu().numpy()[0], ub[b].cpu().numpy()) <= 1e-8
 
 
+@pytest.mark.parametrize("gamma", [0.0, 10.0])
+@pytest.mark.parametrize("arnoldi_fp64", [0, 1])
+def test_mixed_fgmres_arnoldi_precisions(gpu_lib, gamma, arnoldi_fp64):
+    # mixed coupled solves with the Arnoldi basis and K_gamma products in FP32
+    # (default) or FP64 reach the same FP64 solution through the refinement
+    kw = dict(dim=3, n=4, seed=9, mu=1e-2, alpha=100.0)
+    P, S = _problem(gamma=gamma, **kw), _oracle(**kw)
+    fs = np.stack([inputs.fourier_forcing(S.mesh.p2coords, inputs.forcing_seed(9, b)) for b in range(2)])
+    u, p, info = P.solve(torch.tensor(fs, device="cuda"), method="coupled", precision=1, rtol=1e-11,
+                         arnoldi_fp64=arnoldi_fp64, max_outer=2000, max_refine=30)
+    print(f"gamma={gamma} arnoldi_fp64={arnoldi_fp64} info={info}", flush=True)
+    assert info["status"] == 0, info
+    for b in range(2):
+        F, g = S.rhs(fs[b])
+        U, Pp = S.solve(F, g)
+        assert _rel(u[b].cpu().numpy(), S.full_velocity(U)) <= 1e-9
+        assert _rel(p[b].cpu().numpy(), Pp) <= 1e-8
+
+
 def test_warm_start_and_zero_rhs(gpu_lib):
     kw = dict(dim=3, n=3, seed=0, mu=1.0, alpha=100.0)
     P, S = _problem(**kw), _oracle(**kw)
