@@ -356,11 +356,13 @@ __global__ __launch_bounds__(kBlock) void k_fill_blk(int64_t n, int dd, const in
 // column-scaled copy: out[k] = vals[k] * dinv[cols[k]] over the SELL entries
 __global__ __launch_bounds__(kBlock) void k_scale_cols(int64_t n, const int32_t* __restrict__ cols,
                                                        const double* __restrict__ vals, const double* __restrict__ dinv,
-                                                       double* __restrict__ out, float* __restrict__ out32) {
+                                                       double* __restrict__ out, float* __restrict__ out32,
+                                                       _Float16* __restrict__ out16) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
     const double v = vals[k] * dinv[cols[k]];
     out[k] = v;
     out32[k] = (float)v;
+    out16[k] = (_Float16)v;
   }
 }
 
@@ -524,22 +526,59 @@ __global__ __launch_bounds__(kBlock) void k_sqrt(int64_t n, const double* __rest
 
 // ------------------------------------------------------------ SELL build
 
+// Stencil slots of a structured pattern: rows of one class (the parity type
+// of a grid node) share a stencil, and entry j of every row of the class is
+// the same grid offset.  Rows missing an offset (next to the boundary) get a
+// zero-valued pad in that slot, so the lanes of a slice gather the same
+// offset of consecutive nodes together.
+struct SellSlots {
+  int nclass = 0, nkeys = 0;
+  std::function<int(int64_t)> cls;           // class of a source row
+  std::function<int(int64_t, int32_t)> key;  // slot key of (source row, source column)
+};
+
 // rows_in_order[r] = source row of output row r; entries kept where
-// col_map[col] >= 0; entry_map (optional) renames source entries.
+// col_map[col] >= 0; entry_map (optional) renames source entries.  Without
+// `slots` the entries of a row are sorted by column; with it they sit in the
+// stencil slots of the row's class.  Pads carry src -1 (value 0) and the
+// column of the nearest lane of the slice that has an entry in that slot (0
+// if none), which keeps the gathered addresses of a slot together.
 void build_sell(const HostCsr& in, const std::vector<int32_t>& rows_in_order, const std::vector<int32_t>& col_map,
-                const std::vector<int64_t>* entry_map, int planes, Sell& out) {
+                const std::vector<int64_t>* entry_map, int planes, Sell& out, const SellSlots* slots = nullptr) {
   const int64_t nrows = static_cast<int64_t>(rows_in_order.size());
   const int64_t nsl = (nrows + 63) / 64;
   std::vector<int64_t> sp(nsl + 1, 0);
   std::vector<int32_t> len(nrows, 0);
+  // slot of each key per class (slots mode)
+  std::vector<int32_t> slot_of;
+  std::vector<int32_t> class_width;
+  if (slots) {
+    std::vector<char> present((size_t)slots->nclass * slots->nkeys, 0);
+    for (int64_t r = 0; r < nrows; ++r) {
+      const int64_t s = rows_in_order[r];
+      const int cl = slots->cls(s);
+      for (int64_t k = in.rowptr[s]; k < in.rowptr[s + 1]; ++k) {
+        if (col_map[in.cols[k]] < 0) continue;
+        const int key = slots->key(s, in.cols[k]);
+        if (cl < 0 || cl >= slots->nclass || key < 0 || key >= slots->nkeys)
+          throw Error(STOKES_ERR_UNSUPPORTED, "stencil slot out of range");
+        present[(size_t)cl * slots->nkeys + key] = 1;
+      }
+    }
+    slot_of.assign(present.size(), -1);
+    class_width.assign(slots->nclass, 0);
+    for (int cl = 0; cl < slots->nclass; ++cl)
+      for (int key = 0; key < slots->nkeys; ++key)
+        if (present[(size_t)cl * slots->nkeys + key]) slot_of[(size_t)cl * slots->nkeys + key] = class_width[cl]++;
+  }
   int64_t nnz = 0;
   for (int64_t r = 0; r < nrows; ++r) {
     const int64_t s = rows_in_order[r];
     int32_t c = 0;
     for (int64_t k = in.rowptr[s]; k < in.rowptr[s + 1]; ++k)
       if (col_map[in.cols[k]] >= 0) ++c;
-    len[r] = c;
     nnz += c;
+    len[r] = slots ? class_width[slots->cls(s)] : c;
   }
   for (int64_t s = 0; s < nsl; ++s) {
     int32_t w = 0;
@@ -552,18 +591,45 @@ void build_sell(const HostCsr& in, const std::vector<int32_t>& rows_in_order, co
   std::vector<std::pair<int32_t, int64_t>> buf;
   for (int64_t r = 0; r < nrows; ++r) {
     const int64_t s = rows_in_order[r];
+    const int64_t base = sp[r / 64] + (r % 64);
+    if (slots) {
+      const int cl = slots->cls(s);
+      for (int64_t k = in.rowptr[s]; k < in.rowptr[s + 1]; ++k) {
+        const int32_t c = col_map[in.cols[k]];
+        if (c < 0) continue;
+        const int32_t j = slot_of[(size_t)cl * slots->nkeys + slots->key(s, in.cols[k])];
+        if (src[base + 64 * j] >= 0) throw Error(STOKES_ERR_UNSUPPORTED, "two entries in one stencil slot");
+        cols[base + 64 * j] = c;
+        src[base + 64 * j] = static_cast<int32_t>(entry_map ? (*entry_map)[k] : k);
+      }
+      continue;
+    }
     buf.clear();
     for (int64_t k = in.rowptr[s]; k < in.rowptr[s + 1]; ++k) {
       const int32_t c = col_map[in.cols[k]];
       if (c >= 0) buf.emplace_back(c, entry_map ? (*entry_map)[k] : k);
     }
     std::sort(buf.begin(), buf.end());
-    const int64_t base = sp[r / 64] + (r % 64);
     for (size_t j = 0; j < buf.size(); ++j) {
       cols[base + 64 * j] = buf[j].first;
       src[base + 64 * j] = static_cast<int32_t>(buf[j].second);
     }
-    // padding points at the row itself when square, else column 0
+  }
+  // pads take the column of the nearest lane with an entry in the same slot
+  for (int64_t sl = 0; sl < nsl; ++sl) {
+    const int64_t w = (sp[sl + 1] - sp[sl]) / 64;
+    for (int64_t j = 0; j < w; ++j) {
+      const int64_t b0 = sp[sl] + 64 * j;
+      int first = -1;
+      for (int l = 0; l < 64 && first < 0; ++l)
+        if (src[b0 + l] >= 0) first = l;
+      if (first < 0) continue;
+      int last = first;
+      for (int l = 0; l < 64; ++l) {
+        if (src[b0 + l] >= 0) last = l;
+        else cols[b0 + l] = cols[b0 + (l < first ? first : last)];
+      }
+    }
   }
   out.nrows = nrows;
   out.nslices = nsl;
@@ -709,22 +775,41 @@ void assemble_ctx(stokes_ctx* c) {
     throw Error(STOKES_ERR_UNSUPPORTED, "mesh too large for 32-bit sparse indices");
   phase("host patterns");
 
-  // internal numbering: interior nodes by decreasing interior row length
-  std::vector<int32_t> interior;
-  std::vector<int32_t> ilen(m.n_p2, 0);
-  for (int64_t v = 0; v < m.n_p2; ++v) {
-    if (m.p2_bnd[v]) continue;
-    interior.push_back(static_cast<int32_t>(v));
-    int32_t cnt = 0;
-    for (int64_t k = P2full.rowptr[v]; k < P2full.rowptr[v + 1]; ++k)
-      if (!m.p2_bnd[P2full.cols[k]]) ++cnt;
-    ilen[v] = cnt;
-  }
-  // internal order: 8 slabs along the slowest axis (one per XCD, see the
-  // XCD-aware row partition of the gathering kernels), rows sorted by
-  // decreasing length inside each slab (the sliced-ELL padding then stays near
-  // zero), natural order among equal lengths
+  // internal numbering of the interior nodes: 8 slabs along the slowest axis
+  // (one per XCD, see the XCD-aware row partition of the gathering kernels);
+  // inside a slab, the nodes of one parity type (the 2^dim classes of P2
+  // nodes of the Kuhn lattice, each with its own stencil) in natural order.
+  // Consecutive rows of a sliced-ELL slice are then translates of each
+  // other, so the k-th stencil slot of the lanes gathers consecutive nodes.
   const int64_t n2 = 2 * int64_t(m.n) + 1, plane = D == 3 ? n2 * n2 : n2;
+  const int64_t n1 = int64_t(m.n) + 1;
+  auto p2_xyz = [n2, plane, D](int64_t v, int64_t (&x)[3]) {
+    x[0] = v % n2;
+    x[1] = D == 3 ? (v / n2) % n2 : v / n2;
+    x[2] = D == 3 ? v / plane : 0;
+  };
+  auto p1_xyz = [n1, D](int64_t q, int64_t (&x)[3]) {  // in P2 grid units
+    x[0] = 2 * (q % n1);
+    x[1] = 2 * (D == 3 ? (q / n1) % n1 : q / n1);
+    x[2] = D == 3 ? 2 * (q / (n1 * n1)) : 0;
+  };
+  auto p2_type = [&](int64_t v) {
+    int64_t x[3];
+    p2_xyz(v, x);
+    return static_cast<int>((x[0] & 1) + 2 * (x[1] & 1) + 4 * (x[2] & 1));
+  };
+  auto offset_key = [](const int64_t (&a)[3], const int64_t (&b)[3]) {  // b - a in [-2, 2]^3
+    int key = 0;
+    for (int ax = 2; ax >= 0; --ax) {
+      const int64_t d = b[ax] - a[ax];
+      if (d < -2 || d > 2) return -1;
+      key = key * 5 + static_cast<int>(d + 2);
+    }
+    return key;
+  };
+  std::vector<int32_t> interior;
+  for (int64_t v = 0; v < m.n_p2; ++v)
+    if (!m.p2_bnd[v]) interior.push_back(static_cast<int32_t>(v));
   auto slab = [&](int32_t v) {
     const int64_t K = v / plane;  // 1 .. 2n-1 on interior nodes
     return std::min<int64_t>(7, (K - 1) * 8 / (n2 - 2));
@@ -732,8 +817,24 @@ void assemble_ctx(stokes_ctx* c) {
   std::stable_sort(interior.begin(), interior.end(), [&](int32_t a, int32_t b) {
     const int64_t sa = slab(a), sb = slab(b);
     if (sa != sb) return sa < sb;
-    return ilen[a] > ilen[b];
+    return p2_type(a) < p2_type(b);
   });
+  SellSlots slots_p2p2, slots_p2p1;
+  slots_p2p2.nclass = slots_p2p1.nclass = 8;
+  slots_p2p2.nkeys = slots_p2p1.nkeys = 125;
+  slots_p2p2.cls = slots_p2p1.cls = p2_type;
+  slots_p2p2.key = [&](int64_t r, int32_t col) {
+    int64_t a[3], b[3];
+    p2_xyz(r, a);
+    p2_xyz(col, b);
+    return offset_key(a, b);
+  };
+  slots_p2p1.key = [&](int64_t r, int32_t col) {
+    int64_t a[3], b[3];
+    p2_xyz(r, a);
+    p1_xyz(col, b);
+    return offset_key(a, b);
+  };
   c->n_int = static_cast<int64_t>(interior.size());
   c->h_int2nat = interior;
   c->h_nat2int.assign(m.n_p2, -1);
@@ -843,13 +944,13 @@ void assemble_ctx(stokes_ctx* c) {
   std::vector<int32_t> p1_rows(m.n_p1), p1_ident(m.n_p1);
   std::iota(p1_rows.begin(), p1_rows.end(), 0);
   std::iota(p1_ident.begin(), p1_ident.end(), 0);
-  build_sell(P2full, c->h_int2nat, c->h_nat2int, nullptr, 1, c->sA);
+  build_sell(P2full, c->h_int2nat, c->h_nat2int, nullptr, 1, c->sA, &slots_p2p2);
   build_sell(Bfull, p1_rows, c->h_nat2int, nullptr, D, c->sB);
   {
     HostCsr BT, XLpat;
     std::vector<int64_t> tsrc;
     transpose_pattern(Bfull, BT, tsrc);
-    build_sell(BT, c->h_int2nat, p1_ident, &tsrc, D, c->sBt);
+    build_sell(BT, c->h_int2nat, p1_ident, &tsrc, D, c->sBt, &slots_p2p1);
     // B_I Lambda_V^-1 B_I^T: shared interior P2 columns only
     product_pattern(Bfull, BT, c->h_nat2int, XLpat);
     up_csr(XLpat, c->xl);
@@ -894,8 +995,9 @@ void assemble_ctx(stokes_ctx* c) {
   dinv(c->sA, c->A64, c->dA64);
   c->AD64.alloc(c->sA.nnz_pad * sizeof(double));
   c->AD32.alloc(c->sA.nnz_pad * sizeof(float));
+  c->AD16.alloc(c->sA.nnz_pad * sizeof(_Float16));
   launch(c, c->sA.nnz_pad, k_scale_cols, c->sA.nnz_pad, c->sA.cols.as<int32_t>(), c->A64.as<double>(),
-         c->dA64.as<double>(), c->AD64.as<double>(), c->AD32.as<float>());
+         c->dA64.as<double>(), c->AD64.as<double>(), c->AD32.as<float>(), c->AD16.as<_Float16>());
   if (c->strain) {
     c->AB64.alloc(c->sA.nnz_pad * (D * (D + 1) / 2) * sizeof(double));
     c->AB32.alloc(c->sA.nnz_pad * (D * (D + 1) / 2) * sizeof(float));
@@ -1190,7 +1292,7 @@ void reform_A(stokes_ctx* c) {
          c->A64.as<double>(), c->dA64.as<double>());
   launch(c, c->n_int, k_cast<double, float>, c->n_int, c->dA64.as<double>(), c->dA32.as<float>());
   launch(c, n, k_scale_cols, n, c->sA.cols.as<int32_t>(), c->A64.as<double>(), c->dA64.as<double>(),
-         c->AD64.as<double>(), c->AD32.as<float>());
+         c->AD64.as<double>(), c->AD32.as<float>(), c->AD16.as<_Float16>());
   if (c->strain)
     launch(c, n, k_fill_blk, n, c->dim, c->sA.src.as<int32_t>(), c->prob.alpha, c->prob.mu, c->M_full.as<double>(),
            c->L_full.as<double>(), c->D_full.as<double>(), c->AB64.as<double>(), c->AB32.as<float>());

@@ -55,7 +55,8 @@ void upload(DevBuf& b, const std::vector<T>& v) {
 
 // Sliced ELL with slice height 64 (one wavefront), one thread per row.
 // Entry j of row r (slice s = r / 64, lane l = r % 64) sits at
-// slice_ptr[s] + 64 j + l; padding entries have column 0 and value 0.
+// slice_ptr[s] + 64 j + l; padding entries have value 0 (src -1) and the
+// column of a neighbouring lane's entry in the same slot (0 if none).
 struct Sell {
   int64_t nrows = 0, nslices = 0, nnz = 0, nnz_pad = 0;
   int planes = 1;       // values per entry (B and B^T carry dim planes)
@@ -174,6 +175,8 @@ struct stokes_ctx {
   stokes::Sell sX;   // P1 x P1, B_I Lambda_V^-1 B_I^T (two-ring stencil)
   stokes::DevBuf A64, A32, MV64, MV32;       // values of A_II and M_II (SELL)
   stokes::DevBuf AD64, AD32;                 // A_II D^{-1}: column-scaled copy (first Chebyshev step)
+  stokes::DevBuf AD16;                       // the same in half precision (FP32 velocity Chebyshev)
+  int vel_half = 1;                          // FP32 velocity Chebyshev reads AD16
   stokes::DevBuf AB64, AB32;                 // strain: [nnz_pad][dim*dim] blocks alpha M + mu (L + D)
   stokes::DevBuf B64, B32, Bt64, Bt32;       // [nnz_pad][dim]
   stokes::DevBuf MQ64, MQ32, LQ64, LQ32, XQ64, XQ32;  // XQ = M_Q + L_Q

@@ -135,9 +135,12 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ pa
 //
 // Entries of a row are walked four at a time so that eight matrix loads and
 // 4 W/G gathers are in flight per lane.
-template <typename T, int W, int G = 1>
+//
+// TM is the storage type of the values (T, or _Float16 for a scaled copy);
+// every product and sum runs in T.
+template <typename T, int W, int G = 1, typename TM = T>
 __device__ __forceinline__ void sell_row(const int64_t* __restrict__ sp, const int32_t* __restrict__ cols,
-                                         const T* __restrict__ vals, const T* __restrict__ x, int64_t row, int sub,
+                                         const TM* __restrict__ vals, const T* __restrict__ x, int64_t row, int sub,
                                          T (&acc)[W / G]) {
   constexpr int WG = W / G;
   const int64_t s = row >> 6;
@@ -151,7 +154,7 @@ __device__ __forceinline__ void sell_row(const int64_t* __restrict__ sp, const i
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       c[u] = __builtin_nontemporal_load(cols + beg + 64 * (j + u));
-      v[u] = __builtin_nontemporal_load(vals + beg + 64 * (j + u));
+      v[u] = (T)__builtin_nontemporal_load(vals + beg + 64 * (j + u));
     }
     T xv[4][WG];
 #pragma unroll
@@ -165,7 +168,7 @@ __device__ __forceinline__ void sell_row(const int64_t* __restrict__ sp, const i
   }
   for (; j < width; ++j) {
     const int32_t c = __builtin_nontemporal_load(cols + beg + 64 * j);
-    const T v = __builtin_nontemporal_load(vals + beg + 64 * j);
+    const T v = (T)__builtin_nontemporal_load(vals + beg + 64 * j);
     const T* xp = xs + (int64_t)c * W;
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = fma(v, xp[w], acc[w]);
@@ -527,6 +530,75 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, const int6
       const T dnv = fma(c1, d0, c2 * di * rs);
       d1[i] = dnv;
       z[i] = ACC ? z[i] + (d0 + dnv) : d0 + dnv;
+    }
+  }
+}
+
+// Chebyshev steps on the column-scaled operator S D^{-1} held as TM (the
+// half-precision copy of the velocity block), in the variable q = D d:
+//   S d = (S D^{-1}) q,  and  dn = c1 d + c2 dinv res  becomes  qn = c1 q + c2 res,
+// with z += dinv qn.  The iterates z and res are those of k_cheb_first /
+// k_cheb_step up to rounding; only the stored direction is rescaled.
+//
+// First step (q0 = theta_inv r):
+//   res = r - (S D^{-1}) q0 ;  q1 = c1 q0 + c2 res ;  z = dinv (q0 + q1)  (ACC: z +=)
+template <typename T, typename TM, int W, int ACC, int G>
+__global__ __launch_bounds__(kBlock) void k_cheb_first_q(int64_t nrows, const int64_t* __restrict__ sp,
+                                                         const int32_t* __restrict__ cols, const TM* __restrict__ vals,
+                                                         const T* __restrict__ r, const T* __restrict__ dinv,
+                                                         T theta_inv, T* __restrict__ q1, T* __restrict__ res,
+                                                         T* __restrict__ z, T c1, T c2) {
+  constexpr int WG = W / G;
+  XCD_ROWS_G(row, sub, nrows, G) {
+    T acc[WG];
+#pragma unroll
+    for (int w = 0; w < WG; ++w) acc[w] = 0;
+    sell_row<T, W, G, TM>(sp, cols, vals, r, row, sub, acc);
+    const T di = dinv[row];
+    const int64_t o = row * W + sub * WG;
+#pragma unroll
+    for (int w = 0; w < WG; ++w) {
+      const int64_t i = o + w;
+      const T q0 = theta_inv * r[i];
+      const T rs = r[i] - theta_inv * acc[w];
+      res[i] = rs;
+      const T qn = fma(c1, q0, c2 * rs);
+      q1[i] = qn;
+      z[i] = ACC ? fma(di, q0 + qn, z[i]) : di * (q0 + qn);
+    }
+  }
+}
+
+// Later steps:  res = res_in - (S D^{-1}) q ;  qn = c1 q + c2 res ;  z += dinv qn
+template <typename T, typename TM, int W, int G>
+__global__ __launch_bounds__(kBlock) void k_cheb_step_q(int64_t nrows, const int64_t* __restrict__ sp,
+                                                        const int32_t* __restrict__ cols,
+                                                        const TM* __restrict__ vals, const T* __restrict__ q,
+                                                        T* __restrict__ qn, const T* res_in, T* res_out,
+                                                        T* __restrict__ z, const T* __restrict__ dinv, T c1, T c2) {
+  constexpr int WG = W / G;
+  XCD_ROWS_G(row, sub, nrows, G) {
+    T acc[WG];
+#pragma unroll
+    for (int w = 0; w < WG; ++w) acc[w] = 0;
+    sell_row<T, W, G, TM>(sp, cols, vals, q, row, sub, acc);
+    const T di = dinv[row];
+    const int64_t o = row * W + sub * WG;
+    // res_in may alias res_out: load the whole row before any store
+    T ri[WG], qq[WG], zz[WG];
+#pragma unroll
+    for (int w = 0; w < WG; ++w) {
+      ri[w] = res_in[o + w];
+      qq[w] = q[o + w];
+      zz[w] = z[o + w];
+    }
+#pragma unroll
+    for (int w = 0; w < WG; ++w) {
+      const T rs = ri[w] - acc[w];
+      res_out[o + w] = rs;
+      const T qnew = fma(c1, qq[w], c2 * rs);
+      qn[o + w] = qnew;
+      z[o + w] = fma(di, qnew, zz[w]);
     }
   }
 }

@@ -380,6 +380,42 @@ void cheb_first(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* r, 
   check_launch();
 }
 
+void cheb_first_h(stokes_ctx* c, int W, const float* r, const float* dinv, float theta_inv, float* q1, float* res,
+                  float* z, float c1, float c2) {
+  const Sell& S = c->sA;
+  const int G = lanes_op(c, &S, W, true);
+  dispatch_w(W, [&](auto Wc) {
+    constexpr int WW = decltype(Wc)::value;
+    with_g<WW>(G, [&](auto Gc) {
+      constexpr int GG = decltype(Gc)::value;
+      hipLaunchKernelGGL((k_cheb_first_q<float, _Float16, WW, 0, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0,
+                         c->stream, S.nrows, S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(),
+                         (const _Float16*)c->AD16.as<_Float16>(), r, dinv, theta_inv, q1, res, z, c1, c2);
+    });
+  });
+  check_launch();
+}
+
+void cheb_step_h(stokes_ctx* c, int W, const float* q, float* qn, const float* res_in, float* res_out, float* z,
+                 const float* dinv, float c1, float c2) {
+  const Sell& S = c->sA;
+  const bool timed = prof_begin(c, &S, nullptr, nullptr);
+  const int G = lanes_op(c, &S, W, true);
+  dispatch_w(W, [&](auto Wc) {
+    constexpr int WW = decltype(Wc)::value;
+    with_g<WW>(G, [&](auto Gc) {
+      constexpr int GG = decltype(Gc)::value;
+      hipLaunchKernelGGL((k_cheb_step_q<float, _Float16, WW, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0,
+                         c->stream, S.nrows, S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(),
+                         (const _Float16*)c->AD16.as<_Float16>(), q, qn, res_in, res_out, z, dinv, c1, c2);
+    });
+  });
+  check_launch();
+  // algorithmic bytes: half values + column indices once; q gathered once;
+  // res_in, q, z read; res_out, qn, z written (W floats each); dinv read
+  if (timed) prof_end(c, double(S.nnz) * (2.0 + 4.0) + double(S.nrows) * 4.0 * (W * 6.0 + 1.0));
+}
+
 template <class T>
 void cheb_step(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* d, T* dn, const T* res_in, T* res_out,
                T* z, const T* dinv, T c1, T c2, const T* rvec, Scalars* sc, int cps, int nsys, int first) {

@@ -132,6 +132,17 @@ class Engine {
       ops::cheb_init<T>(c_, S.nrows, W, r, dinv, (T)k.theta_inv, d0, z);
       return;
     }
+    if constexpr (std::is_same<T, float>::value) {
+      // FP32 velocity block: read the half-precision copy of A_II D^{-1}
+      if (&S == &c_->sA && vals == A() && c_->vel_half && c_->AD16.p) {
+        ops::cheb_first_h(c_, W, r, dinv, (float)k.theta_inv, d0, res, z, (float)k.c1[0], (float)k.c2[0]);
+        for (int j = 2; j < degree; ++j) {
+          ops::cheb_step_h(c_, W, d0, d1, res, res, z, dinv, (float)k.c1[j - 1], (float)k.c2[j - 1]);
+          std::swap(d0, d1);
+        }
+        return;
+      }
+    }
     ops::cheb_first<T>(c_, S, vals, W, r, dinv, (T)k.theta_inv, d0, res, z, (T)k.c1[0], (T)k.c2[0]);
     for (int j = 2; j < degree; ++j) {
       ops::cheb_step<T>(c_, S, vals, W, d0, d1, res, res, z, dinv, (T)k.c1[j - 1], (T)k.c2[j - 1], nullptr, nullptr,
