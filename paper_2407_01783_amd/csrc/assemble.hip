@@ -537,6 +537,30 @@ struct SellSlots {
   std::function<int(int64_t, int32_t)> key;  // slot key of (source row, source column)
 };
 
+// One-class slots of a P1 lattice with n cells per side (natural vertex
+// order, x fastest): the key is the offset in [-R, R]^dim.
+SellSlots p1_lattice_slots(int dim, int n, int R) {
+  SellSlots sl;
+  sl.nclass = 1;
+  const int w = 2 * R + 1;
+  sl.nkeys = dim == 3 ? w * w * w : w * w;
+  const int64_t n1 = int64_t(n) + 1;
+  sl.cls = [](int64_t) { return 0; };
+  sl.key = [=](int64_t r, int32_t c) {
+    int key = 0;
+    int64_t a = r, b = c;
+    for (int ax = 0, m = 1; ax < dim; ++ax, m *= w) {
+      const int64_t d = b % n1 - a % n1;
+      if (d < -R || d > R) return -1;
+      key += m * static_cast<int>(d + R);
+      a /= n1;
+      b /= n1;
+    }
+    return key;
+  };
+  return sl;
+}
+
 // rows_in_order[r] = source row of output row r; entries kept where
 // col_map[col] >= 0; entry_map (optional) renames source entries.  Without
 // `slots` the entries of a row are sorted by column; with it they sit in the
@@ -560,8 +584,9 @@ void build_sell(const HostCsr& in, const std::vector<int32_t>& rows_in_order, co
       for (int64_t k = in.rowptr[s]; k < in.rowptr[s + 1]; ++k) {
         if (col_map[in.cols[k]] < 0) continue;
         const int key = slots->key(s, in.cols[k]);
+        // not a lattice stencil of the expected reach: sorted rows instead
         if (cl < 0 || cl >= slots->nclass || key < 0 || key >= slots->nkeys)
-          throw Error(STOKES_ERR_UNSUPPORTED, "stencil slot out of range");
+          return build_sell(in, rows_in_order, col_map, entry_map, planes, out, nullptr);
         present[(size_t)cl * slots->nkeys + key] = 1;
       }
     }
@@ -631,14 +656,48 @@ void build_sell(const HostCsr& in, const std::vector<int32_t>& rows_in_order, co
       }
     }
   }
+  // packed columns: per slot a base and 8-bit lane offsets, where every slot
+  // of the slice spans at most 256 columns
+  std::vector<int32_t> cbase(npad / 64, 0);
+  std::vector<uint8_t> cdel(npad, 0);
+  std::vector<int32_t> pk(nsl, 0);
+  int64_t npk = 0;
+  for (int64_t sl = 0; sl < nsl; ++sl) {
+    const int64_t w = (sp[sl + 1] - sp[sl]) / 64;
+    const int lanes = static_cast<int>(std::min<int64_t>(64, nrows - sl * 64));
+    bool ok = true;
+    for (int64_t j = 0; j < w && ok; ++j) {
+      const int64_t b0 = sp[sl] + 64 * j;
+      int32_t lo = cols[b0], hi = cols[b0];
+      for (int l = 1; l < lanes; ++l) {
+        lo = std::min(lo, cols[b0 + l]);
+        hi = std::max(hi, cols[b0 + l]);
+      }
+      ok = int64_t(hi) - lo <= 255;
+    }
+    if (!ok) continue;
+    pk[sl] = 1;
+    ++npk;
+    for (int64_t j = 0; j < w; ++j) {
+      const int64_t b0 = sp[sl] + 64 * j;
+      int32_t lo = cols[b0];
+      for (int l = 1; l < lanes; ++l) lo = std::min(lo, cols[b0 + l]);
+      cbase[sp[sl] / 64 + j] = lo;
+      for (int l = 0; l < lanes; ++l) cdel[b0 + l] = static_cast<uint8_t>(cols[b0 + l] - lo);
+    }
+  }
   out.nrows = nrows;
   out.nslices = nsl;
   out.nnz = nnz;
   out.nnz_pad = npad;
+  out.packed_slices = npk;
   out.planes = planes;
   upload(out.slice_ptr, sp);
   upload(out.cols, cols);
   upload(out.src, src);
+  upload(out.cbase, cbase);
+  upload(out.cdel, cdel);
+  upload(out.pk, pk);
 }
 
 template <class K, class... A>
@@ -945,7 +1004,17 @@ void assemble_ctx(stokes_ctx* c) {
   std::iota(p1_rows.begin(), p1_rows.end(), 0);
   std::iota(p1_ident.begin(), p1_ident.end(), 0);
   build_sell(P2full, c->h_int2nat, c->h_nat2int, nullptr, 1, c->sA, &slots_p2p2);
-  build_sell(Bfull, p1_rows, c->h_nat2int, nullptr, D, c->sB);
+  SellSlots slots_p1p2;
+  slots_p1p2.nclass = 1;
+  slots_p1p2.nkeys = 125;
+  slots_p1p2.cls = [](int64_t) { return 0; };
+  slots_p1p2.key = [&](int64_t r, int32_t col) {
+    int64_t a[3], b[3];
+    p1_xyz(r, a);
+    p2_xyz(col, b);
+    return offset_key(a, b);
+  };
+  build_sell(Bfull, p1_rows, c->h_nat2int, nullptr, D, c->sB, &slots_p1p2);
   {
     HostCsr BT, XLpat;
     std::vector<int64_t> tsrc;
@@ -967,10 +1036,22 @@ void assemble_ctx(stokes_ctx* c) {
                          c->nat2int.as<int32_t>(), c->xl.rowptr.as<int32_t>(), c->xl.cols.as<int32_t>(),
                          c->XL_csr.as<double>());
     HIP_CHECK(hipGetLastError());
-    build_sell(XLpat, p1_rows, p1_ident, nullptr, 1, c->sX);
+    const SellSlots slx = p1_lattice_slots(D, m.n, 2);
+    build_sell(XLpat, p1_rows, p1_ident, nullptr, 1, c->sX, &slx);
   }
-  build_sell(P1, p1_rows, p1_ident, nullptr, 1, c->sQ);
+  {
+    const SellSlots slq = p1_lattice_slots(D, m.n, 1);
+    build_sell(P1, p1_rows, p1_ident, nullptr, 1, c->sQ, &slq);
+  }
   phase("sliced-ELL layouts");
+  if (log) {
+    const std::pair<const char*, const Sell*> ss[] = {{"A_II", &c->sA}, {"B", &c->sB}, {"B^T", &c->sBt},
+                                                      {"X", &c->sX}, {"M_Q", &c->sQ}};
+    for (const auto& e : ss)
+      std::fprintf(stderr, "[stokes] SELL %-5s %lld rows, %lld entries (%lld padded), %lld / %lld slices packed\n",
+                   e.first, (long long)e.second->nrows, (long long)e.second->nnz, (long long)e.second->nnz_pad,
+                   (long long)e.second->packed_slices, (long long)e.second->nslices);
+  }
 
   auto fill = [&](const Sell& S, DevBuf& out, double a, const DevBuf& v1, double b, const DevBuf* v2) {
     out.alloc(S.nnz_pad * S.planes * sizeof(double));
@@ -1090,7 +1171,8 @@ void assemble_p1(stokes_ctx* c, const HostMesh& m, MgLevel& L) {
            LQ.as<double>());
   std::vector<int32_t> rows(m.n_p1);
   std::iota(rows.begin(), rows.end(), 0);
-  build_sell(P1, rows, rows, nullptr, 1, L.S);
+  const SellSlots sl = p1_lattice_slots(D, m.n, 1);
+  build_sell(P1, rows, rows, nullptr, 1, L.S, &sl);
   L.nrows = m.n_p1;
   L.v64.alloc(L.S.nnz_pad * sizeof(double));
   launch(c, L.S.nnz_pad, k_fill, L.S.nnz_pad, L.S.src.as<int32_t>(), 1, 1.0, MQ.as<double>(), 1.0, LQ.as<double>(),
@@ -1118,7 +1200,8 @@ void upload_level(stokes_ctx* c, const HostCsr& A, const std::vector<double>& av
   const int64_t nr = A.nrows;
   std::vector<int32_t> rows(nr);
   std::iota(rows.begin(), rows.end(), 0);
-  build_sell(A, rows, rows, nullptr, 1, L.S);
+  const SellSlots sl = p1_lattice_slots(c->dim, L.n, 3);
+  build_sell(A, rows, rows, nullptr, 1, L.S, &sl);
   L.nrows = nr;
   DevBuf dv;
   upload(dv, av);

@@ -57,12 +57,27 @@ void upload(DevBuf& b, const std::vector<T>& v) {
 // Entry j of row r (slice s = r / 64, lane l = r % 64) sits at
 // slice_ptr[s] + 64 j + l; padding entries have value 0 (src -1) and the
 // column of a neighbouring lane's entry in the same slot (0 if none).
+// Device view of the column indices of a Sell (see slice_ref in kernels.h).
+struct SellIdx {
+  const int64_t* sp = nullptr;     // slice_ptr
+  const int32_t* cols = nullptr;   // 32-bit columns (slices with pk = 0)
+  const int32_t* cbase = nullptr;  // [nnz_pad / 64] base column of slot j of slice s at sp[s] / 64 + j
+  const uint8_t* cdel = nullptr;   // [nnz_pad] column - base (slices with pk = 1)
+  const int32_t* pk = nullptr;     // [nslices] 1 = packed columns (32-bit: a scalar load)
+};
+
 struct Sell {
   int64_t nrows = 0, nslices = 0, nnz = 0, nnz_pad = 0;
+  int64_t packed_slices = 0;
   int planes = 1;       // values per entry (B and B^T carry dim planes)
   DevBuf slice_ptr;     // int64 [nslices + 1]
   DevBuf cols;          // int32 [nnz_pad]
   DevBuf src;           // int32 [nnz_pad] source entry in the assembled CSR (-1 = pad)
+  DevBuf cbase, cdel, pk;
+  SellIdx idx() const {
+    return SellIdx{slice_ptr.as<const int64_t>(), cols.as<const int32_t>(), cbase.as<const int32_t>(),
+                   cdel.as<const uint8_t>(), pk.as<const int32_t>()};
+  }
 };
 
 struct DevCsr {

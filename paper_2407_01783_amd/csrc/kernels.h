@@ -133,28 +133,59 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ pa
 // of 64 scattered W-vectors into a few contiguous segments per column; the
 // summation order of every component is the same for every G.
 //
+// Column indices come in one of two forms per slice (SellIdx): packed --
+// slot j of the slice holds a base column plus an 8-bit lane offset, so a
+// lane reads one byte per entry -- or plain 32-bit columns where a slot
+// spreads over more than 256 columns.  The rows of a wavefront always lie
+// in one slice (an aligned group of 64 / G rows), so the slice index is read
+// from the first active lane and the form is a uniform branch.
+//
 // Entries of a row are walked four at a time so that eight matrix loads and
 // 4 W/G gathers are in flight per lane.
-//
-// TM is the storage type of the values (T, or _Float16 for a scaled copy);
-// every product and sum runs in T.
-template <typename T, int W, int G = 1, typename TM = T>
-__device__ __forceinline__ void sell_row(const int64_t* __restrict__ sp, const int32_t* __restrict__ cols,
-                                         const TM* __restrict__ vals, const T* __restrict__ x, int64_t row, int sub,
-                                         T (&acc)[W / G]) {
+struct SliceRef {
+  int64_t beg;  // entry 0 of the row
+  int64_t eb;   // first slot of the slice (index into cbase)
+  int width;    // slots of the slice
+  bool pk;      // packed columns
+};
+
+__device__ __forceinline__ SliceRef slice_ref(const SellIdx& ix, int64_t row) {
+  const int64_t s = __builtin_amdgcn_readfirstlane(static_cast<int>(row >> 6));
+  const int64_t s0 = ix.sp[s];
+  SliceRef r;
+  r.beg = s0 + (row & 63);
+  r.eb = s0 >> 6;
+  r.width = static_cast<int>((ix.sp[s + 1] - s0) >> 6);
+  r.pk = ix.pk[s] != 0;
+  return r;
+}
+
+template <bool PK>
+__device__ __forceinline__ int32_t sell_col(const SellIdx& ix, const SliceRef& r, int j) {
+  if constexpr (PK)
+    return ix.cbase[r.eb + j] + static_cast<int32_t>(__builtin_nontemporal_load(ix.cdel + r.beg + 64 * j));
+  else
+    return __builtin_nontemporal_load(ix.cols + r.beg + 64 * j);
+}
+
+// acc += sum_j v_j x[c_j][sub W/G ...]; DS: v_j is multiplied by ds[c_j]
+template <typename T, int W, int G, typename TM, bool PK, bool DS>
+__device__ __forceinline__ void sell_row_impl(const SellIdx& ix, const SliceRef& r, const TM* __restrict__ vals,
+                                              const T* __restrict__ xs, const T* __restrict__ ds,
+                                              T (&acc)[W / G]) {
   constexpr int WG = W / G;
-  const int64_t s = row >> 6;
-  const int64_t beg = sp[s] + (row & 63);
-  const int width = (int)((sp[s + 1] - sp[s]) >> 6);
-  const T* __restrict__ xs = x + sub * WG;
   int j = 0;
-  for (; j + 4 <= width; j += 4) {
+  for (; j + 4 <= r.width; j += 4) {
     int32_t c[4];
     T v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      c[u] = __builtin_nontemporal_load(cols + beg + 64 * (j + u));
-      v[u] = (T)__builtin_nontemporal_load(vals + beg + 64 * (j + u));
+      c[u] = sell_col<PK>(ix, r, j + u);
+      v[u] = (T)__builtin_nontemporal_load(vals + r.beg + 64 * (j + u));
+    }
+    if constexpr (DS) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] *= ds[c[u]];
     }
     T xv[4][WG];
 #pragma unroll
@@ -166,33 +197,47 @@ __device__ __forceinline__ void sell_row(const int64_t* __restrict__ sp, const i
 #pragma unroll
       for (int w = 0; w < WG; ++w) acc[w] = fma(v[u], xv[u][w], acc[w]);
   }
-  for (; j < width; ++j) {
-    const int32_t c = __builtin_nontemporal_load(cols + beg + 64 * j);
-    const T v = (T)__builtin_nontemporal_load(vals + beg + 64 * j);
+  for (; j < r.width; ++j) {
+    const int32_t c = sell_col<PK>(ix, r, j);
+    T v = (T)__builtin_nontemporal_load(vals + r.beg + 64 * j);
+    if constexpr (DS) v *= ds[c];
     const T* xp = xs + (int64_t)c * W;
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = fma(v, xp[w], acc[w]);
   }
 }
 
+// TM is the storage type of the values (T, or _Float16 for a scaled copy);
+// every product and sum runs in T.  ds (optional): column scaling of the
+// values (S D), gathered at the columns.
+template <typename T, int W, int G = 1, typename TM = T>
+__device__ __forceinline__ void sell_row(const SellIdx& ix, const TM* __restrict__ vals, const T* __restrict__ x,
+                                         int64_t row, int sub, T (&acc)[W / G], const T* __restrict__ ds = nullptr) {
+  const SliceRef r = slice_ref(ix, row);
+  const T* __restrict__ xs = x + sub * (W / G);
+  if (ds) {
+    if (r.pk) sell_row_impl<T, W, G, TM, true, true>(ix, r, vals, xs, ds, acc);
+    else sell_row_impl<T, W, G, TM, false, true>(ix, r, vals, xs, ds, acc);
+  } else {
+    if (r.pk) sell_row_impl<T, W, G, TM, true, false>(ix, r, vals, xs, ds, acc);
+    else sell_row_impl<T, W, G, TM, false, false>(ix, r, vals, xs, ds, acc);
+  }
+}
+
 // B rows (pressure vertex): acc[r] = sum_j sum_c B^c_j u[col_j][r][c]
 // (entries walked two at a time to keep more loads in flight)
-template <typename T, int D, int NRB>
-__device__ __forceinline__ void sell_row_B(const int64_t* __restrict__ sp, const int32_t* __restrict__ cols,
-                                           const T* __restrict__ vals, const T* __restrict__ u, int64_t row,
-                                           T (&acc)[NRB]) {
-  const int64_t s = row >> 6;
-  const int64_t beg = sp[s] + (row & 63);
-  const int width = (int)((sp[s + 1] - sp[s]) >> 6);
+template <typename T, int D, int NRB, bool PK>
+__device__ __forceinline__ void sell_row_B_impl(const SellIdx& ix, const SliceRef& rf, const T* __restrict__ vals,
+                                                const T* __restrict__ u, T (&acc)[NRB]) {
   constexpr int U = 2;
   int j = 0;
-  for (; j + U <= width; j += U) {
+  for (; j + U <= rf.width; j += U) {
     int32_t c[U];
     T b[U][D], x[U][D * NRB];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const int64_t k = beg + 64 * (j + q);
-      c[q] = __builtin_nontemporal_load(cols + k);
+      const int64_t k = rf.beg + 64 * (j + q);
+      c[q] = sell_col<PK>(ix, rf, j + q);
 #pragma unroll
       for (int d = 0; d < D; ++d) b[q][d] = __builtin_nontemporal_load(vals + k * D + d);
     }
@@ -207,9 +252,9 @@ __device__ __forceinline__ void sell_row_B(const int64_t* __restrict__ sp, const
 #pragma unroll
         for (int d = 0; d < D; ++d) acc[r] = fma(b[q][d], x[q][r * D + d], acc[r]);
   }
-  for (; j < width; ++j) {
-    const int64_t k = beg + 64 * j;
-    const int32_t c = __builtin_nontemporal_load(cols + k);
+  for (; j < rf.width; ++j) {
+    const int64_t k = rf.beg + 64 * j;
+    const int32_t c = sell_col<PK>(ix, rf, j);
     T b[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) b[d] = __builtin_nontemporal_load(vals + k * D + d);
@@ -219,6 +264,14 @@ __device__ __forceinline__ void sell_row_B(const int64_t* __restrict__ sp, const
 #pragma unroll
       for (int d = 0; d < D; ++d) acc[r] = fma(b[d], up[r * D + d], acc[r]);
   }
+}
+
+template <typename T, int D, int NRB>
+__device__ __forceinline__ void sell_row_B(const SellIdx& ix, const T* __restrict__ vals, const T* __restrict__ u,
+                                           int64_t row, T (&acc)[NRB]) {
+  const SliceRef rf = slice_ref(ix, row);
+  if (rf.pk) sell_row_B_impl<T, D, NRB, true>(ix, rf, vals, u, acc);
+  else sell_row_B_impl<T, D, NRB, false>(ix, rf, vals, u, acc);
 }
 
 // value plane d (runtime, d < D) of a small register array
@@ -233,14 +286,10 @@ __device__ __forceinline__ T plane(const T (&b)[D], int d) {
 // B^T rows (interior velocity node): acc[r][c] = sum_j B^c_j p[col_j][r];
 // with G lanes per row, lane `sub` owns components sub W/G .. (sub+1) W/G - 1
 // of the W = D NRB outputs (component w is rhs w / D, plane w mod D).
-template <typename T, int D, int NRB, int G = 1>
-__device__ __forceinline__ void sell_row_Bt(const int64_t* __restrict__ sp, const int32_t* __restrict__ cols,
-                                            const T* __restrict__ vals, const T* __restrict__ p, int64_t row,
-                                            int sub, T (&acc)[D * NRB / G]) {
+template <typename T, int D, int NRB, int G, bool PK>
+__device__ __forceinline__ void sell_row_Bt_impl(const SellIdx& ix, const SliceRef& rf, const T* __restrict__ vals,
+                                                 const T* __restrict__ p, int sub, T (&acc)[D * NRB / G]) {
   constexpr int WG = D * NRB / G;
-  const int64_t s = row >> 6;
-  const int64_t beg = sp[s] + (row & 63);
-  const int width = (int)((sp[s + 1] - sp[s]) >> 6);
   int rr[WG], dd[WG];
 #pragma unroll
   for (int w = 0; w < WG; ++w) {
@@ -249,13 +298,13 @@ __device__ __forceinline__ void sell_row_Bt(const int64_t* __restrict__ sp, cons
   }
   constexpr int U = 4;
   int j = 0;
-  for (; j + U <= width; j += U) {
+  for (; j + U <= rf.width; j += U) {
     int32_t c[U];
     T b[U][D], pv[U][WG];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const int64_t k = beg + 64 * (j + q);
-      c[q] = __builtin_nontemporal_load(cols + k);
+      const int64_t k = rf.beg + 64 * (j + q);
+      c[q] = sell_col<PK>(ix, rf, j + q);
 #pragma unroll
       for (int d = 0; d < D; ++d) b[q][d] = __builtin_nontemporal_load(vals + k * D + d);
     }
@@ -268,9 +317,9 @@ __device__ __forceinline__ void sell_row_Bt(const int64_t* __restrict__ sp, cons
 #pragma unroll
       for (int w = 0; w < WG; ++w) acc[w] = fma(G == 1 ? b[q][w % D] : plane<T, D>(b[q], dd[w]), pv[q][w], acc[w]);
   }
-  for (; j < width; ++j) {
-    const int64_t k = beg + 64 * j;
-    const int32_t c = __builtin_nontemporal_load(cols + k);
+  for (; j < rf.width; ++j) {
+    const int64_t k = rf.beg + 64 * j;
+    const int32_t c = sell_col<PK>(ix, rf, j);
     T b[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) b[d] = __builtin_nontemporal_load(vals + k * D + d);
@@ -278,6 +327,14 @@ __device__ __forceinline__ void sell_row_Bt(const int64_t* __restrict__ sp, cons
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = fma(G == 1 ? b[w % D] : plane<T, D>(b, dd[w]), pp[rr[w]], acc[w]);
   }
+}
+
+template <typename T, int D, int NRB, int G = 1>
+__device__ __forceinline__ void sell_row_Bt(const SellIdx& ix, const T* __restrict__ vals, const T* __restrict__ p,
+                                            int64_t row, int sub, T (&acc)[D * NRB / G]) {
+  const SliceRef rf = slice_ref(ix, row);
+  if (rf.pk) sell_row_Bt_impl<T, D, NRB, G, true>(ix, rf, vals, p, sub, acc);
+  else sell_row_Bt_impl<T, D, NRB, G, false>(ix, rf, vals, p, sub, acc);
 }
 
 #define GRID_STRIDE_ROWS(row, nrows)                                                      \
@@ -321,15 +378,14 @@ __device__ __forceinline__ void expand_parts(const double (&pg)[W / G], int sub,
 
 // y = a * (S x) + b * yin   (yin may alias y; ignored when b == 0)
 template <typename T, int W, int G>
-__global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, const int64_t* __restrict__ sp,
-                                                 const int32_t* __restrict__ cols, const T* __restrict__ vals,
+__global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, SellIdx ix, const T* __restrict__ vals,
                                                  const T* __restrict__ x, T* y, T a, const T* yin, T b) {
   constexpr int WG = W / G;
   XCD_ROWS_G(row, sub, nrows, G) {
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<T, W, G>(sp, cols, vals, x, row, sub, acc);
+    sell_row<T, W, G>(ix, vals, x, row, sub, acc);
     const int64_t o = row * W + sub * WG;
     // yin may alias y: every load of the row is issued before its stores
     T yi[WG];
@@ -343,8 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, const int64_t* _
 // CG direction step with the product folded in:
 //   q = S z (+ extra) + beta q,  p = z + beta p,  sigma = p . q  -> alpha
 template <typename T, int W, int G>
-__global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t nrows, const int64_t* __restrict__ sp,
-                                                    const int32_t* __restrict__ cols,
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t nrows, SellIdx ix,
                                                     const T* __restrict__ vals, const T* __restrict__ z,
                                                     const T* __restrict__ extra, T* __restrict__ q,
                                                     T* __restrict__ p, Scalars* sc, int cps, int nsys, double* partials) {
@@ -360,7 +415,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t nrows, const int64_t
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    if (sp) sell_row<T, W, G>(sp, cols, vals, z, row, sub, acc);
+    if (ix.sp) sell_row<T, W, G>(ix, vals, z, row, sub, acc);
 #pragma unroll
     for (int w = 0; w < WG; ++w) {
       const int64_t i = row * W + sub * WG + w;
@@ -449,8 +504,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_init(int64_t nrows, const T* __
 //   res = res_in - S d ;  dn = c1 d + c2 dinv res ;  z += dn
 // DOT: also rho = rvec . z -> beta (CG preconditioner use), first => beta = 0.
 template <typename T, int W, int DOT, int G>
-__global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, const int64_t* __restrict__ sp,
-                                                      const int32_t* __restrict__ cols,
+__global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, SellIdx ix,
                                                       const T* __restrict__ vals, const T* __restrict__ d,
                                                       T* __restrict__ dn, const T* res_in, T* res_out,
                                                       T* __restrict__ z, const T* __restrict__ dinv, T c1, T c2,
@@ -464,7 +518,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, const int64
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<T, W, G>(sp, cols, vals, d, row, sub, acc);
+    sell_row<T, W, G>(ix, vals, d, row, sub, acc);
     const T di = c2 * dinv[row];
     const int64_t o = row * W + sub * WG;
     // res_in may alias res_out: load the whole row before any store
@@ -499,8 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, const int64
 // ACC: z += d0 + d1 (z holds a previous approximation) instead of z = d0 + d1
 // SC: vals already hold S_ij dinv_j (no gather of dinv at the columns).
 template <typename T, int W, int ACC, int G, int SC>
-__global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, const int64_t* __restrict__ sp,
-                                                       const int32_t* __restrict__ cols, const T* __restrict__ vals,
+__global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, SellIdx ix, const T* __restrict__ vals,
                                                        const T* __restrict__ r, const T* __restrict__ dinv, T theta_inv,
                                                        T* __restrict__ d1, T* __restrict__ res, T* __restrict__ z,
                                                        T c1, T c2) {
@@ -509,16 +562,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, const int6
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    const int64_t s = row >> 6;
-    const int64_t end = sp[s + 1];
-    const T* rs_ = r + sub * WG;
-    for (int64_t k = sp[s] + (row & 63); k < end; k += 64) {
-      const int32_t c = __builtin_nontemporal_load(cols + k);
-      const T v = SC ? __builtin_nontemporal_load(vals + k) : __builtin_nontemporal_load(vals + k) * dinv[c];
-      const T* xp = rs_ + (int64_t)c * W;
-#pragma unroll
-      for (int w = 0; w < WG; ++w) acc[w] = fma(v, xp[w], acc[w]);
-    }
+    sell_row<T, W, G>(ix, vals, r, row, sub, acc, SC ? nullptr : dinv);
     const T di = dinv[row];
     const int64_t o = row * W + sub * WG;
 #pragma unroll
@@ -543,8 +587,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, const int6
 // First step (q0 = theta_inv r):
 //   res = r - (S D^{-1}) q0 ;  q1 = c1 q0 + c2 res ;  z = dinv (q0 + q1)  (ACC: z +=)
 template <typename T, typename TM, int W, int ACC, int G>
-__global__ __launch_bounds__(kBlock) void k_cheb_first_q(int64_t nrows, const int64_t* __restrict__ sp,
-                                                         const int32_t* __restrict__ cols, const TM* __restrict__ vals,
+__global__ __launch_bounds__(kBlock) void k_cheb_first_q(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
                                                          const T* __restrict__ r, const T* __restrict__ dinv,
                                                          T theta_inv, T* __restrict__ q1, T* __restrict__ res,
                                                          T* __restrict__ z, T c1, T c2) {
@@ -553,7 +596,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first_q(int64_t nrows, const in
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<T, W, G, TM>(sp, cols, vals, r, row, sub, acc);
+    sell_row<T, W, G, TM>(ix, vals, r, row, sub, acc);
     const T di = dinv[row];
     const int64_t o = row * W + sub * WG;
 #pragma unroll
@@ -571,8 +614,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first_q(int64_t nrows, const in
 
 // Later steps:  res = res_in - (S D^{-1}) q ;  qn = c1 q + c2 res ;  z += dinv qn
 template <typename T, typename TM, int W, int G>
-__global__ __launch_bounds__(kBlock) void k_cheb_step_q(int64_t nrows, const int64_t* __restrict__ sp,
-                                                        const int32_t* __restrict__ cols,
+__global__ __launch_bounds__(kBlock) void k_cheb_step_q(int64_t nrows, SellIdx ix,
                                                         const TM* __restrict__ vals, const T* __restrict__ q,
                                                         T* __restrict__ qn, const T* res_in, T* res_out,
                                                         T* __restrict__ z, const T* __restrict__ dinv, T c1, T c2) {
@@ -581,7 +623,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step_q(int64_t nrows, const int
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<T, W, G, TM>(sp, cols, vals, q, row, sub, acc);
+    sell_row<T, W, G, TM>(ix, vals, q, row, sub, acc);
     const T di = dinv[row];
     const int64_t o = row * W + sub * WG;
     // res_in may alias res_out: load the whole row before any store
@@ -607,14 +649,13 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step_q(int64_t nrows, const int
 
 // p = a * (B u) + b * pin
 template <typename T, int D, int NRB>
-__global__ __launch_bounds__(kBlock) void k_B(int64_t nrows, const int64_t* __restrict__ sp,
-                                              const int32_t* __restrict__ cols, const T* __restrict__ vals,
+__global__ __launch_bounds__(kBlock) void k_B(int64_t nrows, SellIdx ix, const T* __restrict__ vals,
                                               const T* __restrict__ u, T* pout, T a, const T* pin, T b) {
   XCD_ROWS(row, nrows) {
     T acc[NRB];
 #pragma unroll
     for (int r = 0; r < NRB; ++r) acc[r] = 0;
-    sell_row_B<T, D, NRB>(sp, cols, vals, u, row, acc);
+    sell_row_B<T, D, NRB>(ix, vals, u, row, acc);
     T pi[NRB];  // pin may alias pout
 #pragma unroll
     for (int r = 0; r < NRB; ++r) pi[r] = b != T(0) ? pin[row * NRB + r] : T(0);
@@ -625,8 +666,7 @@ __global__ __launch_bounds__(kBlock) void k_B(int64_t nrows, const int64_t* __re
 
 // u = a * scale .* (B^T p) + b * uin     (scale per node, may be null)
 template <typename T, int D, int NRB, int G>
-__global__ __launch_bounds__(kBlock) void k_Bt(int64_t nrows, const int64_t* __restrict__ sp,
-                                               const int32_t* __restrict__ cols, const T* __restrict__ vals,
+__global__ __launch_bounds__(kBlock) void k_Bt(int64_t nrows, SellIdx ix, const T* __restrict__ vals,
                                                const T* __restrict__ p, const T* __restrict__ scale, T* uout,
                                                T a, const T* uin, T b) {
   constexpr int W = D * NRB, WG = W / G;
@@ -634,7 +674,7 @@ __global__ __launch_bounds__(kBlock) void k_Bt(int64_t nrows, const int64_t* __r
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row_Bt<T, D, NRB, G>(sp, cols, vals, p, row, sub, acc);
+    sell_row_Bt<T, D, NRB, G>(ix, vals, p, row, sub, acc);
     const T sc = scale ? a * scale[row] : a;
     const int64_t o = row * W + sub * WG;
     T ui[WG];  // uin may alias uout
@@ -648,10 +688,8 @@ __global__ __launch_bounds__(kBlock) void k_Bt(int64_t nrows, const int64_t* __r
 // Momentum rows of the coupled operator:
 //   y = sgn * (A u - B^T p + extra) + yin   (sgn = -1 with yin = F gives the residual)
 template <typename T, int D, int NRB, int G>
-__global__ __launch_bounds__(kBlock) void k_momentum(int64_t nrows, const int64_t* __restrict__ spA,
-                                                     const int32_t* __restrict__ colsA, const T* __restrict__ A,
-                                                     const int64_t* __restrict__ spT,
-                                                     const int32_t* __restrict__ colsT, const T* __restrict__ Bt,
+__global__ __launch_bounds__(kBlock) void k_momentum(int64_t nrows, SellIdx ixA, const T* __restrict__ A,
+                                                     SellIdx ixT, const T* __restrict__ Bt,
                                                      const T* __restrict__ u, const T* __restrict__ p,
                                                      const T* __restrict__ extra, T* y, T sgn, const T* yin) {
   constexpr int W = D * NRB, WG = W / G;
@@ -659,8 +697,8 @@ __global__ __launch_bounds__(kBlock) void k_momentum(int64_t nrows, const int64_
     T acc[WG], bt[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = bt[w] = 0;
-    sell_row<T, W, G>(spA, colsA, A, u, row, sub, acc);
-    sell_row_Bt<T, D, NRB, G>(spT, colsT, Bt, p, row, sub, bt);
+    sell_row<T, W, G>(ixA, A, u, row, sub, acc);
+    sell_row_Bt<T, D, NRB, G>(ixT, Bt, p, row, sub, bt);
     const int64_t o = row * W + sub * WG;
     T ex[WG], yi[WG];  // yin may alias y
 #pragma unroll
@@ -759,8 +797,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_blk(int64_t nrows, const int64_
 template <typename T, int D, int NRB>
 __global__ __launch_bounds__(kBlock) void k_momentum_blk(int64_t nrows, const int64_t* __restrict__ spA,
                                                          const int32_t* __restrict__ colsA, const T* __restrict__ A,
-                                                         const int64_t* __restrict__ spT,
-                                                         const int32_t* __restrict__ colsT, const T* __restrict__ Bt,
+                                                         SellIdx ixT, const T* __restrict__ Bt,
                                                          const T* __restrict__ u, const T* __restrict__ p,
                                                          const T* __restrict__ extra, T* y, T sgn, const T* yin) {
   constexpr int W = D * NRB;
@@ -769,7 +806,7 @@ __global__ __launch_bounds__(kBlock) void k_momentum_blk(int64_t nrows, const in
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = bt[w] = 0;
     sell_row_blk<T, D, NRB>(spA, colsA, A, u, row, acc);
-    sell_row_Bt<T, D, NRB, 1>(spT, colsT, Bt, p, row, 0, bt);
+    sell_row_Bt<T, D, NRB, 1>(ixT, Bt, p, row, 0, bt);
     T ex[W], yi[W];  // yin may alias y
 #pragma unroll
     for (int w = 0; w < W; ++w) {

@@ -148,7 +148,7 @@ void spmv(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* x, T* y, 
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       hipLaunchKernelGGL((k_spmv<T, WW, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows,
-                         S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, x, y, a, yin, b);
+                         S.idx(), vals, x, y, a, yin, b);
     });
   });
   check_launch();
@@ -160,7 +160,7 @@ void Bmul(stokes_ctx* c, int nrb, const T* u, T* p, T a, const T* pin, T b) {
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
     constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
     hipLaunchKernelGGL((k_B<T, D, N>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
-                       S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), bvals<T>(c).template as<T>(), u, p, a, pin, b);
+                       S.idx(), bvals<T>(c).template as<T>(), u, p, a, pin, b);
   });
   check_launch();
 }
@@ -174,7 +174,7 @@ void Btmul(stokes_ctx* c, int nrb, const T* p, const T* scale, T* u, T a, const 
     with_g<D * N>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       hipLaunchKernelGGL((k_Bt<T, D, N, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows,
-                         S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), btvals<T>(c).template as<T>(), p, scale, u,
+                         S.idx(), btvals<T>(c).template as<T>(), p, scale, u,
                          a, uin, b);
     });
   });
@@ -204,7 +204,7 @@ void momentum(stokes_ctx* c, int nrb, const T* u, const T* p, const T* extra, T*
       constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
       hipLaunchKernelGGL((k_momentum_blk<T, D, N>), dim3(grid_for(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int,
                          c->sA.slice_ptr.as<int64_t>(), c->sA.cols.as<int32_t>(), abvals<T>(c).template as<T>(),
-                         c->sBt.slice_ptr.as<int64_t>(), c->sBt.cols.as<int32_t>(), btvals<T>(c).template as<T>(), u,
+                         c->sBt.idx(), btvals<T>(c).template as<T>(), u,
                          p, extra, y, sgn, yin);
     });
     check_launch();
@@ -216,8 +216,7 @@ void momentum(stokes_ctx* c, int nrb, const T* u, const T* p, const T* extra, T*
     with_g<D * N>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       hipLaunchKernelGGL((k_momentum<T, D, N, GG>), dim3(grid_for(c->n_int * GG)), dim3(kBlock), 0, c->stream,
-                         c->n_int, c->sA.slice_ptr.as<int64_t>(), c->sA.cols.as<int32_t>(),
-                         avals<T>(c).template as<T>(), c->sBt.slice_ptr.as<int64_t>(), c->sBt.cols.as<int32_t>(),
+                         c->n_int, c->sA.idx(), avals<T>(c).template as<T>(), c->sBt.idx(),
                          btvals<T>(c).template as<T>(), u, p, extra, y, sgn, yin);
     });
   });
@@ -304,7 +303,7 @@ void cg_spmv(stokes_ctx* c, int64_t nrows, const Sell* S, const T* vals, int W, 
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       hipLaunchKernelGGL((k_cg_spmv<T, WW, GG>), dim3(grid_for(nrows * GG)), dim3(kBlock), 0, c->stream, nrows,
-                         S ? S->slice_ptr.as<int64_t>() : nullptr, S ? S->cols.as<int32_t>() : nullptr, vals, z,
+                         S ? S->idx() : SellIdx{}, vals, z,
                          extra, q, p, sc, cps, nsys, partials(c));
       finish<WW>(c, nrows * GG, FIN_ALPHA, WW, sc, cps, nsys, 0, nullptr);
     });
@@ -365,8 +364,8 @@ void cheb_first(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* r, 
       constexpr int GG = decltype(Gc)::value;
       const int nb = grid_for(S.nrows * GG);
       auto go = [&](auto kern, const T* v) {
-        hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, S.nrows, S.slice_ptr.as<int64_t>(),
-                           S.cols.as<int32_t>(), v, r, dinv, theta_inv, d1, res, z, c1, c2);
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, S.nrows, S.idx(), v, r, dinv, theta_inv, d1,
+                           res, z, c1, c2);
       };
       if (scaled) {
         if (accumulate) go(k_cheb_first<T, WW, 1, GG, 1>, scaled);
@@ -389,7 +388,7 @@ void cheb_first_h(stokes_ctx* c, int W, const float* r, const float* dinv, float
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       hipLaunchKernelGGL((k_cheb_first_q<float, _Float16, WW, 0, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0,
-                         c->stream, S.nrows, S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(),
+                         c->stream, S.nrows, S.idx(),
                          (const _Float16*)c->AD16.as<_Float16>(), r, dinv, theta_inv, q1, res, z, c1, c2);
     });
   });
@@ -406,7 +405,7 @@ void cheb_step_h(stokes_ctx* c, int W, const float* q, float* qn, const float* r
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       hipLaunchKernelGGL((k_cheb_step_q<float, _Float16, WW, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0,
-                         c->stream, S.nrows, S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(),
+                         c->stream, S.nrows, S.idx(),
                          (const _Float16*)c->AD16.as<_Float16>(), q, qn, res_in, res_out, z, dinv, c1, c2);
     });
   });
@@ -429,12 +428,12 @@ void cheb_step(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* d, T
       const int nb = grid_for(S.nrows * GG);
       if (rvec) {
         hipLaunchKernelGGL((k_cheb_step<T, WW, 1, GG>), dim3(nb), dim3(kBlock), 0, c->stream, S.nrows,
-                           S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, d, dn, res_in, res_out, z, dinv, c1,
+                           S.idx(), vals, d, dn, res_in, res_out, z, dinv, c1,
                            c2, rvec, sc, cps, nsys, first, partials(c));
         finish<WW>(c, S.nrows * GG, FIN_RHO, WW, sc, cps, nsys, first, nullptr);
       } else
         hipLaunchKernelGGL((k_cheb_step<T, WW, 0, GG>), dim3(nb), dim3(kBlock), 0, c->stream, S.nrows,
-                           S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), vals, d, dn, res_in, res_out, z, dinv, c1,
+                           S.idx(), vals, d, dn, res_in, res_out, z, dinv, c1,
                            c2, rvec, sc, cps, nsys, first, partials(c));
     });
   });
