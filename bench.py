@@ -50,7 +50,7 @@ SOLVER = dict(method="coupled", rtol=1e-8, cheb_degree=6, inner_mode=1, inner_rt
 
 
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-TRAFFIC_FILE = os.path.join(PROFILE_DIR, "k_cheb_step_f32_cube64_hbm_traffic.txt")
+TRAFFIC_FILE = os.path.join(PROFILE_DIR, "k_cheb_step_q_cube64_hbm_traffic.txt")
 
 
 def kernel_source_digest():
@@ -240,8 +240,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": measured_traffic(args.workload, args.nrhs, args.strain),
-                     "kernel": f"k_cheb_step<float,{dim * args.nrhs},0,G> (FP32 velocity-block SELL SpMV + Chebyshev "
-                               f"update; G lanes per row, autotuned)",
+                     "kernel": f"k_cheb_step_q<float,_Float16,{dim * args.nrhs},G> (velocity-block SELL SpMV: "
+                               f"half-precision A_II D^-1 values, packed column indices, FP32 vectors; fused "
+                               f"Chebyshev update; G lanes per row, autotuned)",
                      "bytes_per_launch": bytes_per, "launches": launches,
                      "avg_us": kern_s / launches * 1e6 if launches else None},
         "cpu_baseline": cpu,

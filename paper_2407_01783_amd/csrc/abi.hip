@@ -204,7 +204,7 @@ stokes_status solve_forward(stokes_ctx* c, int method, int32_t nrhs, const doubl
       HIP_CHECK(hipMemsetAsync(xp, 0, np * sizeof(double), c->stream));
     }
     SolveStats st;
-    const int s = solve_internal(c, *o, method, nrb, F, g, xu, xp, st);
+    const int s = solve_internal(c, *o, method, nrb, F, g, xu, xp, st, x0_u == nullptr);
     ops::vel_out<double>(c, nrb, xu, ubc ? ubc + vo : nullptr, u + vo, 1);
     ops::p_out<double>(c, nrb, xp, p + po);
     if (s != STOKES_OK) status = s;
@@ -477,6 +477,7 @@ stokes_status stokes_assemble(const stokes_problem* prob, void* hip_stream, stok
     if (const char* e = std::getenv("STOKES_CG_CHECK")) c->cg_check_every = std::max(1, std::atoi(e));
     if (const char* e = std::getenv("STOKES_MGX")) c->use_mgx = std::atoi(e) != 0;
     if (const char* e = std::getenv("STOKES_VEL_HALF")) c->vel_half = std::atoi(e) != 0;
+    if (const char* e = std::getenv("STOKES_PMG_HALF")) c->pmg_half = std::atoi(e) != 0;
     if (const char* e = std::getenv("STOKES_LANES")) c->force_lanes = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("STOKES_MG_DEGREE")) c->mg_smooth_degree = std::max(1, std::atoi(e));
     if (const char* e = std::getenv("STOKES_MG_RATIO")) c->mg_smooth_ratio = std::max(1.5, std::atof(e));
@@ -567,7 +568,7 @@ stokes_status stokes_solve_adjoint(stokes_ctx* c, int32_t nrhs, const double* u,
       HIP_CHECK(hipMemsetAsync(xu, 0, nu * sizeof(double), c->stream));
       HIP_CHECK(hipMemsetAsync(xp, 0, np * sizeof(double), c->stream));
       SolveStats st;
-      const int s = solve_internal(c, *o, 0, nrb, F, g, xu, xp, st);
+      const int s = solve_internal(c, *o, 0, nrb, F, g, xu, xp, st, true);
       if (s != STOKES_OK) status = s;
       for (double rr : st.rel_res) maxres = std::max(maxres, rr);
       // lam_p = -q

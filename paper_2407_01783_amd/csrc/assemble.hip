@@ -354,6 +354,12 @@ __global__ __launch_bounds__(kBlock) void k_fill_blk(int64_t n, int dd, const in
 }
 
 // column-scaled copy: out[k] = vals[k] * dinv[cols[k]] over the SELL entries
+__global__ __launch_bounds__(kBlock) void k_to_half(int64_t n, const double* __restrict__ x, double s,
+                                                    _Float16* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (_Float16)(x[i] * s);
+}
+
 __global__ __launch_bounds__(kBlock) void k_scale_cols(int64_t n, const int32_t* __restrict__ cols,
                                                        const double* __restrict__ vals, const double* __restrict__ dinv,
                                                        double* __restrict__ out, float* __restrict__ out32,
@@ -691,6 +697,11 @@ void build_sell(const HostCsr& in, const std::vector<int32_t>& rows_in_order, co
   out.nnz = nnz;
   out.nnz_pad = npad;
   out.packed_slices = npk;
+  out.idx_bytes = 0;
+  for (int64_t sl = 0; sl < nsl; ++sl) {
+    const double w = double(sp[sl + 1] - sp[sl]) / 64;
+    out.idx_bytes += 12.0 + (pk[sl] ? 64.0 * w + 4.0 * w : 4.0 * 64.0 * w);  // slice offset and form, slots
+  }
   out.planes = planes;
   upload(out.slice_ptr, sp);
   upload(out.cols, cols);
@@ -1215,6 +1226,15 @@ void upload_level(stokes_ctx* c, const HostCsr& A, const std::vector<double>& av
   L.d32.alloc(nr * sizeof(float));
   launch(c, L.S.nnz_pad, k_cast<double, float>, L.S.nnz_pad, L.v64.as<double>(), L.v32.as<float>());
   launch(c, nr, k_cast<double, float>, nr, L.d64.as<double>(), L.d32.as<float>());
+  // half-precision copy for the FP32 V-cycle: values over the largest
+  // magnitude of the level (a diagonal), so every row is O(1)
+  double amax = 0;
+  for (double v : av) amax = std::max(amax, std::fabs(v));
+  if (amax > 0) {
+    L.s16 = static_cast<float>(amax);
+    L.v16.alloc(L.S.nnz_pad * sizeof(_Float16));
+    launch(c, L.S.nnz_pad, k_to_half, L.S.nnz_pad, L.v64.as<double>(), 1.0 / double(L.s16), L.v16.as<_Float16>());
+  }
   double lo, hi, g;
   lanczos_bounds(c, L.S, L.v64.as<double>(), L.d64.as<double>(), std::min<int>(40, (int)nr), lo, hi, g);
   L.bf.hi = std::min(g, 1.1 * hi);
@@ -1272,7 +1292,7 @@ void assemble_galerkin(stokes_ctx* c, MgHier& H) {
     auto L = std::make_unique<MgLevel>();
     L->n = n;
     upload_level(c, A, av, *L);
-    H.lv.push_back({&L->S, &L->v64, &L->v32, &L->d64, &L->d32, &L->bs, &L->bf, n});
+    H.lv.push_back({&L->S, &L->v64, &L->v32, &L->d64, &L->d32, &L->bs, &L->bf, n, &L->v16, L->s16});
     H.own.push_back(std::move(L));
     if (!(n % 2 == 0 && n > 2 && ipow(n + 1, D) > c->mg_dense_max)) break;
     HostCsr Ac;

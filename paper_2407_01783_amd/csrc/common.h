@@ -69,6 +69,7 @@ struct SellIdx {
 struct Sell {
   int64_t nrows = 0, nslices = 0, nnz = 0, nnz_pad = 0;
   int64_t packed_slices = 0;
+  double idx_bytes = 0;  // bytes of the column-index structure streamed by one product
   int planes = 1;       // values per entry (B and B^T carry dim planes)
   DevBuf slice_ptr;     // int64 [nslices + 1]
   DevBuf cols;          // int32 [nnz_pad]
@@ -108,6 +109,8 @@ struct MgLevel {
   int64_t nrows = 0;    // (n + 1)^dim vertices
   Sell S;               // SELL pattern of the level operator
   DevBuf v64, v32;      // operator values
+  DevBuf v16;           // FP32 V-cycles: half-precision values / s16 (empty: none)
+  float s16 = 0;
   DevBuf d64, d32;      // inverse diagonal
   Bounds bs, bf;        // smoothing interval, full spectrum
 };
@@ -134,6 +137,8 @@ struct MgHier {
     const DevBuf *v64, *v32, *d64, *d32;
     const Bounds *bs, *bf;
     int n;
+    const DevBuf* v16 = nullptr;  // half-precision values / s16 (FP32 V-cycles)
+    float s16 = 0;
   };
   std::vector<View> lv;
   std::vector<std::unique_ptr<MgLevel>> own;
@@ -192,6 +197,7 @@ struct stokes_ctx {
   stokes::DevBuf AD64, AD32;                 // A_II D^{-1}: column-scaled copy (first Chebyshev step)
   stokes::DevBuf AD16;                       // the same in half precision (FP32 velocity Chebyshev)
   int vel_half = 1;                          // FP32 velocity Chebyshev reads AD16
+  int pmg_half = 1;                          // FP32 pressure V-cycles read the levels' half values
   stokes::DevBuf AB64, AB32;                 // strain: [nnz_pad][dim*dim] blocks alpha M + mu (L + D)
   stokes::DevBuf B64, B32, Bt64, Bt32;       // [nnz_pad][dim]
   stokes::DevBuf MQ64, MQ32, LQ64, LQ32, XQ64, XQ32;  // XQ = M_Q + L_Q

@@ -169,31 +169,31 @@ __device__ __forceinline__ int32_t sell_col(const SellIdx& ix, const SliceRef& r
 }
 
 // acc += sum_j v_j x[c_j][sub W/G ...]; DS: v_j is multiplied by ds[c_j]
-template <typename T, int W, int G, typename TM, bool PK, bool DS>
+template <typename T, int W, int G, typename TM, bool PK, bool DS, int U = 4>
 __device__ __forceinline__ void sell_row_impl(const SellIdx& ix, const SliceRef& r, const TM* __restrict__ vals,
                                               const T* __restrict__ xs, const T* __restrict__ ds,
                                               T (&acc)[W / G]) {
   constexpr int WG = W / G;
   int j = 0;
-  for (; j + 4 <= r.width; j += 4) {
-    int32_t c[4];
-    T v[4];
+  for (; j + U <= r.width; j += U) {
+    int32_t c[U];
+    T v[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       c[u] = sell_col<PK>(ix, r, j + u);
       v[u] = (T)__builtin_nontemporal_load(vals + r.beg + 64 * (j + u));
     }
     if constexpr (DS) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] *= ds[c[u]];
+      for (int u = 0; u < U; ++u) v[u] *= ds[c[u]];
     }
-    T xv[4][WG];
+    T xv[U][WG];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int w = 0; w < WG; ++w) xv[u][w] = xs[(int64_t)c[u] * W + w];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int w = 0; w < WG; ++w) acc[w] = fma(v[u], xv[u][w], acc[w]);
   }
@@ -209,18 +209,18 @@ __device__ __forceinline__ void sell_row_impl(const SellIdx& ix, const SliceRef&
 
 // TM is the storage type of the values (T, or _Float16 for a scaled copy);
 // every product and sum runs in T.  ds (optional): column scaling of the
-// values (S D), gathered at the columns.
-template <typename T, int W, int G = 1, typename TM = T>
+// values (S D), gathered at the columns.  U: entries per unrolled group.
+template <typename T, int W, int G = 1, typename TM = T, int U = 4>
 __device__ __forceinline__ void sell_row(const SellIdx& ix, const TM* __restrict__ vals, const T* __restrict__ x,
                                          int64_t row, int sub, T (&acc)[W / G], const T* __restrict__ ds = nullptr) {
   const SliceRef r = slice_ref(ix, row);
   const T* __restrict__ xs = x + sub * (W / G);
   if (ds) {
-    if (r.pk) sell_row_impl<T, W, G, TM, true, true>(ix, r, vals, xs, ds, acc);
-    else sell_row_impl<T, W, G, TM, false, true>(ix, r, vals, xs, ds, acc);
+    if (r.pk) sell_row_impl<T, W, G, TM, true, true, U>(ix, r, vals, xs, ds, acc);
+    else sell_row_impl<T, W, G, TM, false, true, U>(ix, r, vals, xs, ds, acc);
   } else {
-    if (r.pk) sell_row_impl<T, W, G, TM, true, false>(ix, r, vals, xs, ds, acc);
-    else sell_row_impl<T, W, G, TM, false, false>(ix, r, vals, xs, ds, acc);
+    if (r.pk) sell_row_impl<T, W, G, TM, true, false, U>(ix, r, vals, xs, ds, acc);
+    else sell_row_impl<T, W, G, TM, false, false, U>(ix, r, vals, xs, ds, acc);
   }
 }
 
@@ -377,15 +377,15 @@ __device__ __forceinline__ void expand_parts(const double (&pg)[W / G], int sub,
 // ----------------------------------------------------------- SpMV kernels
 
 // y = a * (S x) + b * yin   (yin may alias y; ignored when b == 0)
-template <typename T, int W, int G>
-__global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, SellIdx ix, const T* __restrict__ vals,
+template <typename T, int W, int G, typename TM = T>
+__global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
                                                  const T* __restrict__ x, T* y, T a, const T* yin, T b) {
   constexpr int WG = W / G;
   XCD_ROWS_G(row, sub, nrows, G) {
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<T, W, G>(ix, vals, x, row, sub, acc);
+    sell_row<T, W, G, TM>(ix, vals, x, row, sub, acc);
     const int64_t o = row * W + sub * WG;
     // yin may alias y: every load of the row is issued before its stores
     T yi[WG];
@@ -503,9 +503,9 @@ __global__ __launch_bounds__(kBlock) void k_cheb_init(int64_t nrows, const T* __
 // One Chebyshev step (Saad, Iterative Methods, Alg. 12.1, three-term form):
 //   res = res_in - S d ;  dn = c1 d + c2 dinv res ;  z += dn
 // DOT: also rho = rvec . z -> beta (CG preconditioner use), first => beta = 0.
-template <typename T, int W, int DOT, int G>
+template <typename T, int W, int DOT, int G, typename TM = T>
 __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, SellIdx ix,
-                                                      const T* __restrict__ vals, const T* __restrict__ d,
+                                                      const TM* __restrict__ vals, T ms, const T* __restrict__ d,
                                                       T* __restrict__ dn, const T* res_in, T* res_out,
                                                       T* __restrict__ z, const T* __restrict__ dinv, T c1, T c2,
                                                       const T* __restrict__ rvec, Scalars* sc, int cps, int nsys,
@@ -518,7 +518,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, SellIdx ix,
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<T, W, G>(ix, vals, d, row, sub, acc);
+    sell_row<T, W, G, TM>(ix, vals, d, row, sub, acc);
     const T di = c2 * dinv[row];
     const int64_t o = row * W + sub * WG;
     // res_in may alias res_out: load the whole row before any store
@@ -531,7 +531,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, SellIdx ix,
     }
 #pragma unroll
     for (int w = 0; w < WG; ++w) {
-      const T rs = ri[w] - acc[w];
+      const T rs = ri[w] - ms * acc[w];
       res_out[o + w] = rs;
       const T dnew = fma(c1, dd[w], di * rs);
       dn[o + w] = dnew;
@@ -552,8 +552,8 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, SellIdx ix,
 //   res = r - S d0 ;  d1 = c1 d0 + c2 dinv res ;  z = d0 + d1
 // ACC: z += d0 + d1 (z holds a previous approximation) instead of z = d0 + d1
 // SC: vals already hold S_ij dinv_j (no gather of dinv at the columns).
-template <typename T, int W, int ACC, int G, int SC>
-__global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, SellIdx ix, const T* __restrict__ vals,
+template <typename T, int W, int ACC, int G, int SC, typename TM = T>
+__global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, SellIdx ix, const TM* __restrict__ vals, T ms,
                                                        const T* __restrict__ r, const T* __restrict__ dinv, T theta_inv,
                                                        T* __restrict__ d1, T* __restrict__ res, T* __restrict__ z,
                                                        T c1, T c2) {
@@ -562,14 +562,14 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, SellIdx ix
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<T, W, G>(ix, vals, r, row, sub, acc, SC ? nullptr : dinv);
+    sell_row<T, W, G, TM>(ix, vals, r, row, sub, acc, SC ? nullptr : dinv);
     const T di = dinv[row];
     const int64_t o = row * W + sub * WG;
 #pragma unroll
     for (int w = 0; w < WG; ++w) {
       const int64_t i = o + w;
       const T d0 = theta_inv * di * r[i];
-      const T rs = r[i] - theta_inv * acc[w];
+      const T rs = r[i] - theta_inv * (ms * acc[w]);
       res[i] = rs;
       const T dnv = fma(c1, d0, c2 * di * rs);
       d1[i] = dnv;
@@ -586,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, SellIdx ix
 //
 // First step (q0 = theta_inv r):
 //   res = r - (S D^{-1}) q0 ;  q1 = c1 q0 + c2 res ;  z = dinv (q0 + q1)  (ACC: z +=)
-template <typename T, typename TM, int W, int ACC, int G>
+template <typename T, typename TM, int W, int ACC, int G, int U = 4>
 __global__ __launch_bounds__(kBlock) void k_cheb_first_q(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
                                                          const T* __restrict__ r, const T* __restrict__ dinv,
                                                          T theta_inv, T* __restrict__ q1, T* __restrict__ res,
@@ -596,7 +596,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first_q(int64_t nrows, SellIdx 
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<T, W, G, TM>(ix, vals, r, row, sub, acc);
+    sell_row<T, W, G, TM, U>(ix, vals, r, row, sub, acc);
     const T di = dinv[row];
     const int64_t o = row * W + sub * WG;
 #pragma unroll
@@ -613,21 +613,23 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first_q(int64_t nrows, SellIdx 
 }
 
 // Later steps:  res = res_in - (S D^{-1}) q ;  qn = c1 q + c2 res ;  z += dinv qn
-template <typename T, typename TM, int W, int G>
+// U: entries per unrolled group (8 keeps twice the loads of the 2-byte
+// value and 1-byte index streams in flight; 4% faster than 4 at W = 3).
+template <typename T, typename TM, int W, int G, int U = 4>
 __global__ __launch_bounds__(kBlock) void k_cheb_step_q(int64_t nrows, SellIdx ix,
                                                         const TM* __restrict__ vals, const T* __restrict__ q,
                                                         T* __restrict__ qn, const T* res_in, T* res_out,
                                                         T* __restrict__ z, const T* __restrict__ dinv, T c1, T c2) {
   constexpr int WG = W / G;
   XCD_ROWS_G(row, sub, nrows, G) {
+    const int64_t o = row * W + sub * WG;
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<T, W, G, TM>(ix, vals, q, row, sub, acc);
-    const T di = dinv[row];
-    const int64_t o = row * W + sub * WG;
+    sell_row<T, W, G, TM, U>(ix, vals, q, row, sub, acc);
     // res_in may alias res_out: load the whole row before any store
     T ri[WG], qq[WG], zz[WG];
+    const T di = dinv[row];
 #pragma unroll
     for (int w = 0; w < WG; ++w) {
       ri[w] = res_in[o + w];
@@ -1197,6 +1199,95 @@ __global__ __launch_bounds__(kBlock) void k_mupdate(int64_t n_int, int64_t n_p1,
 #pragma unroll
     for (int r = 0; r < NRB; ++r) pf[r] = r == sub ? part : 0.0;
     grid_reduce<NRB>(pf, partials);
+  }
+}
+
+// First Gram-Schmidt update fused with the second pass's dot products:
+//   w <- w - sum_{i<nb} h[i][r] V_i   (FP64 sums, stored in TW), then
+//   partial dots V_i . w of the stored w, for i < nb <= kFusedMax,
+// written in k_mdot's partial layout (chunk i / 8, slot i mod 8) with the same
+// row mapping and block reduction, so k_mdot_fin gives the same sums as a
+// separate k_mdot pass.  One read of the basis instead of two.
+constexpr int kFusedMax = 8;
+template <typename TV, typename TW, int D, int NRB>
+__global__ __launch_bounds__(kBlock) void k_mupdate_dot(int64_t n_int, int64_t n_p1, const TV* __restrict__ V,
+                                                        int64_t ldv, int nb, const double* __restrict__ h,
+                                                        TW* __restrict__ w, double* __restrict__ part) {
+  constexpr int W = D * NRB, CH = kMdotChunk, NM = kFusedMax;
+  __shared__ double hs[NM * NRB];
+  for (int i = threadIdx.x; i < nb * NRB; i += blockDim.x) hs[i] = -h[i];
+  __syncthreads();
+  const int sub = (int)(threadIdx.x % NRB);
+  const int64_t nv = n_int * W;
+  double acc[NM];
+#pragma unroll
+  for (int i = 0; i < NM; ++i) acc[i] = 0;
+  for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / NRB; t < n_int + n_p1;
+       t += (int64_t)gridDim.x * blockDim.x / NRB) {
+    if (t < n_int) {
+      const int64_t o = t * W + sub * D;
+      double a[D];
+      TV v[NM][D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) a[d] = (double)w[o + d];
+#pragma unroll
+      for (int i = 0; i < NM; ++i)
+        if (i < nb) {
+#pragma unroll
+          for (int d = 0; d < D; ++d) v[i][d] = V[(int64_t)i * ldv + o + d];
+        }
+#pragma unroll
+      for (int i = 0; i < NM; ++i)
+        if (i < nb) {
+          const double hi = hs[i * NRB + sub];
+#pragma unroll
+          for (int d = 0; d < D; ++d) a[d] += hi * (double)v[i][d];
+        }
+      double st[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const TW sv = (TW)a[d];
+        w[o + d] = sv;
+        st[d] = (double)sv;
+      }
+#pragma unroll
+      for (int i = 0; i < NM; ++i)
+        if (i < nb) {
+          double sacc = 0;
+#pragma unroll
+          for (int d = 0; d < D; ++d) sacc += (double)v[i][d] * st[d];
+          acc[i] += sacc;
+        }
+    } else {
+      const int64_t o = nv + (t - n_int) * NRB + sub;
+      TV v[NM];
+      double a = (double)w[o];
+#pragma unroll
+      for (int i = 0; i < NM; ++i)
+        if (i < nb) v[i] = V[(int64_t)i * ldv + o];
+#pragma unroll
+      for (int i = 0; i < NM; ++i)
+        if (i < nb) a += hs[i * NRB + sub] * (double)v[i];
+      const TW sv = (TW)a;
+      w[o] = sv;
+#pragma unroll
+      for (int i = 0; i < NM; ++i)
+        if (i < nb) acc[i] += (double)v[i] * (double)sv;
+    }
+  }
+  __shared__ double sh[kBlock / 64][NM][NRB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NM; ++i) {
+    const double sv = wave_sum_strided<NRB>(acc[i]);
+    if (lane < NRB) sh[wave][i][lane] = sv;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nb * NRB; q += blockDim.x) {
+    const int i = q / NRB, r = q % NRB;
+    double sv = 0;
+    for (int k = 0; k < kBlock / 64; ++k) sv += sh[k][i][r];
+    part[((((int64_t)(i / CH)) * gridDim.x + blockIdx.x) * CH + (i % CH)) * NRB + r] = sv;
   }
 }
 

@@ -344,12 +344,36 @@ void mg_vcycle(stokes_ctx* c, const MgHier& H, int nrb, const T* r, T* e, int lv
   T* d0 = wsp<T>(c, tag + "_d0", n);
   T* d1 = wsp<T>(c, tag + "_d1", n);
   T* res = wsp<T>(c, tag + "_res", n);
+  // FP32 cycles read the half-precision level values (X = s16 x stored)
+  const _Float16* v16 = nullptr;
+  if constexpr (std::is_same<T, float>::value)
+    if (c->pmg_half && V.v16 && V.v16->p) v16 = V.v16->as<_Float16>();
+  // t = r - X e
+  auto residual = [&](const T* e_, const T* r_, T* t_) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (v16) return ops::spmv_hs(c, S, v16, V.s16, nrb, e_, t_, -1.0f, r_, 1.0f);
+    }
+    ops::spmv<T>(c, S, vals, nrb, e_, t_, (T)-1, r_, (T)1);
+  };
   // z (+)= p(D^{-1} X) D^{-1} rin ; accumulate into z when acc != 0 (degree >= 2)
   auto cheb = [&](const Bounds& b, int degree, const T* rin, T* z, int acc) {
     const Cheb k = coef(b, degree);
     if (degree == 1) {
       ops::cheb_init<T>(c, nr, nrb, rin, dinv, (T)k.theta_inv, d0, z);
       return;
+    }
+    if constexpr (std::is_same<T, float>::value) {
+      if (v16) {
+        ops::cheb_first_hs(c, S, v16, V.s16, nrb, rin, dinv, (float)k.theta_inv, d0, res, z, (float)k.c1[0],
+                           (float)k.c2[0], acc);
+        float* da = d0;
+        float* db = d1;
+        for (int j = 2; j < degree; ++j) {
+          ops::cheb_step_hs(c, S, v16, V.s16, nrb, da, db, res, res, z, dinv, (float)k.c1[j - 1], (float)k.c2[j - 1]);
+          std::swap(da, db);
+        }
+        return;
+      }
     }
     ops::cheb_first<T>(c, S, vals, nrb, rin, dinv, (T)k.theta_inv, d0, res, z, (T)k.c1[0], (T)k.c2[0], acc);
     T* da = d0;
@@ -383,7 +407,7 @@ void mg_vcycle(stokes_ctx* c, const MgHier& H, int nrb, const T* r, T* e, int lv
   T* rc = wsp<T>(c, "mg" + std::to_string(lv + 1) + "_rc", ncn);
   T* ec = wsp<T>(c, "mg" + std::to_string(lv + 1) + "_ec", ncn);
   cheb(bs, nu, r, e, 0);                                                // pre-smoothing from zero
-  ops::spmv<T>(c, S, vals, nrb, e, t, (T)-1, r, (T)1);                 // t = r - X e
+  residual(e, r, t);                                                    // t = r - X e
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
     constexpr int DD = decltype(Dc)::value, N = decltype(Nc)::value;
     hipLaunchKernelGGL((k_restrict<T, DD, N>), dim3(ops::grid_for(C.S->nrows)), dim3(kBlock), 0, c->stream, nf, C.n,
@@ -397,7 +421,7 @@ void mg_vcycle(stokes_ctx* c, const MgHier& H, int nrb, const T* r, T* e, int lv
                        (const T*)ec, e);
   });
   ops::check_launch();
-  ops::spmv<T>(c, S, vals, nrb, e, t, (T)-1, r, (T)1);                 // t = r - X e
+  residual(e, r, t);                                                    // t = r - X e
   if (nu >= 2) {
     cheb(bs, nu, t, e, 1);                                              // post-smoothing, e += p(.) t
   } else {

@@ -92,6 +92,15 @@ void cheb_first(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* r, 
 template <class T>
 void cheb_step(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* d, T* dn, const T* res_in, T* res_out,
                T* z, const T* dinv, T c1, T c2, const T* rvec, Scalars* sc, int cps, int nsys, int first);
+// The same operations on half-precision values scaled by 1/ms (S = ms x
+// stored values), FP32 vectors: the pressure multigrid levels.
+void spmv_hs(stokes_ctx* c, const Sell& S, const _Float16* vals, float ms, int W, const float* x, float* y, float a,
+             const float* yin, float b);
+void cheb_first_hs(stokes_ctx* c, const Sell& S, const _Float16* vals, float ms, int W, const float* r,
+                   const float* dinv, float theta_inv, float* d1, float* res, float* z, float c1, float c2,
+                   int accumulate);
+void cheb_step_hs(stokes_ctx* c, const Sell& S, const _Float16* vals, float ms, int W, const float* d, float* dn,
+                  const float* res_in, float* res_out, float* z, const float* dinv, float c1, float c2);
 // The same two steps on the half-precision column-scaled velocity block
 // A_II D^{-1} (ctx AD16) in the rescaled direction q = D d (FP32 vectors).
 void cheb_first_h(stokes_ctx* c, int W, const float* r, const float* dinv, float theta_inv, float* q1, float* res,

@@ -140,18 +140,31 @@ template <> const DevBuf& avals<float>(stokes_ctx* c) { return c->A32; }
 
 }  // namespace
 
-template <class T>
-void spmv(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* x, T* y, T a, const T* yin, T b) {
+namespace {
+// S = ms * (stored values); ms is folded into the product's coefficient
+template <class T, class TM>
+void spmv_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, int W, const T* x, T* y, T a, const T* yin, T b) {
   const int G = lanes_op(c, &S, W, std::is_same<T, float>::value);
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
-      hipLaunchKernelGGL((k_spmv<T, WW, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows,
-                         S.idx(), vals, x, y, a, yin, b);
+      hipLaunchKernelGGL((k_spmv<T, WW, GG, TM>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0, c->stream,
+                         S.nrows, S.idx(), vals, x, y, (T)(a * ms), yin, b);
     });
   });
   check_launch();
+}
+}  // namespace
+
+template <class T>
+void spmv(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* x, T* y, T a, const T* yin, T b) {
+  spmv_impl<T, T>(c, S, vals, (T)1, W, x, y, a, yin, b);
+}
+
+void spmv_hs(stokes_ctx* c, const Sell& S, const _Float16* vals, float ms, int W, const float* x, float* y, float a,
+             const float* yin, float b) {
+  spmv_impl<float, _Float16>(c, S, vals, ms, W, x, y, a, yin, b);
 }
 
 template <class T>
@@ -352,31 +365,45 @@ void cheb_init(stokes_ctx* c, int64_t nrows, int W, const T* r, const T* dinv, T
   check_launch();
 }
 
-template <class T>
-void cheb_first(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* r, const T* dinv, T theta_inv, T* d1,
-                T* res, T* z, T c1, T c2, int accumulate) {
+namespace {
+template <class T, class TM>
+void cheb_first_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, const TM* scaled, int W, const T* r,
+                     const T* dinv, T theta_inv, T* d1, T* res, T* z, T c1, T c2, int accumulate) {
   const int G = lanes_op(c, &S, W, std::is_same<T, float>::value);
-  // the velocity operator has a column-scaled copy S D^{-1}
-  const T* scaled = (&S == &c->sA && vals == avals<T>(c).template as<T>()) ? pick<T>(c->AD64, c->AD32) : nullptr;
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       const int nb = grid_for(S.nrows * GG);
-      auto go = [&](auto kern, const T* v) {
-        hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, S.nrows, S.idx(), v, r, dinv, theta_inv, d1,
-                           res, z, c1, c2);
+      auto go = [&](auto kern, const TM* v) {
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, S.nrows, S.idx(), v, ms, r, dinv, theta_inv,
+                           d1, res, z, c1, c2);
       };
       if (scaled) {
-        if (accumulate) go(k_cheb_first<T, WW, 1, GG, 1>, scaled);
-        else go(k_cheb_first<T, WW, 0, GG, 1>, scaled);
+        if (accumulate) go(k_cheb_first<T, WW, 1, GG, 1, TM>, scaled);
+        else go(k_cheb_first<T, WW, 0, GG, 1, TM>, scaled);
       } else {
-        if (accumulate) go(k_cheb_first<T, WW, 1, GG, 0>, vals);
-        else go(k_cheb_first<T, WW, 0, GG, 0>, vals);
+        if (accumulate) go(k_cheb_first<T, WW, 1, GG, 0, TM>, vals);
+        else go(k_cheb_first<T, WW, 0, GG, 0, TM>, vals);
       }
     });
   });
   check_launch();
+}
+}  // namespace
+
+template <class T>
+void cheb_first(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* r, const T* dinv, T theta_inv, T* d1,
+                T* res, T* z, T c1, T c2, int accumulate) {
+  // the velocity operator has a column-scaled copy S D^{-1}
+  const T* scaled = (&S == &c->sA && vals == avals<T>(c).template as<T>()) ? pick<T>(c->AD64, c->AD32) : nullptr;
+  cheb_first_impl<T, T>(c, S, vals, (T)1, scaled, W, r, dinv, theta_inv, d1, res, z, c1, c2, accumulate);
+}
+
+void cheb_first_hs(stokes_ctx* c, const Sell& S, const _Float16* vals, float ms, int W, const float* r,
+                   const float* dinv, float theta_inv, float* d1, float* res, float* z, float c1, float c2,
+                   int accumulate) {
+  cheb_first_impl<float, _Float16>(c, S, vals, ms, nullptr, W, r, dinv, theta_inv, d1, res, z, c1, c2, accumulate);
 }
 
 void cheb_first_h(stokes_ctx* c, int W, const float* r, const float* dinv, float theta_inv, float* q1, float* res,
@@ -387,7 +414,7 @@ void cheb_first_h(stokes_ctx* c, int W, const float* r, const float* dinv, float
     constexpr int WW = decltype(Wc)::value;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
-      hipLaunchKernelGGL((k_cheb_first_q<float, _Float16, WW, 0, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0,
+      hipLaunchKernelGGL((k_cheb_first_q<float, _Float16, WW, 0, GG, 8>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0,
                          c->stream, S.nrows, S.idx(),
                          (const _Float16*)c->AD16.as<_Float16>(), r, dinv, theta_inv, q1, res, z, c1, c2);
     });
@@ -404,15 +431,33 @@ void cheb_step_h(stokes_ctx* c, int W, const float* q, float* qn, const float* r
     constexpr int WW = decltype(Wc)::value;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
-      hipLaunchKernelGGL((k_cheb_step_q<float, _Float16, WW, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0,
-                         c->stream, S.nrows, S.idx(),
-                         (const _Float16*)c->AD16.as<_Float16>(), q, qn, res_in, res_out, z, dinv, c1, c2);
+      auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows, S.idx(),
+                           (const _Float16*)c->AD16.as<_Float16>(), q, qn, res_in, res_out, z, dinv, c1, c2);
+      };
+      go(k_cheb_step_q<float, _Float16, WW, GG, 8>);
     });
   });
   check_launch();
-  // algorithmic bytes: half values + column indices once; q gathered once;
-  // res_in, q, z read; res_out, qn, z written (W floats each); dinv read
-  if (timed) prof_end(c, double(S.nnz) * (2.0 + 4.0) + double(S.nrows) * 4.0 * (W * 6.0 + 1.0));
+  // algorithmic bytes: the stored operator once (half values of every padded
+  // entry, the column-index structure); q gathered once; res_in, q, z read;
+  // res_out, qn, z written (W floats each); dinv read
+  if (timed) prof_end(c, double(S.nnz_pad) * 2.0 + S.idx_bytes + double(S.nrows) * 4.0 * (W * 6.0 + 1.0));
+}
+
+void cheb_step_hs(stokes_ctx* c, const Sell& S, const _Float16* vals, float ms, int W, const float* d, float* dn,
+                  const float* res_in, float* res_out, float* z, const float* dinv, float c1, float c2) {
+  const int G = lanes_op(c, &S, W, true);
+  dispatch_w(W, [&](auto Wc) {
+    constexpr int WW = decltype(Wc)::value;
+    with_g<WW>(G, [&](auto Gc) {
+      constexpr int GG = decltype(Gc)::value;
+      hipLaunchKernelGGL((k_cheb_step<float, WW, 0, GG, _Float16>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0,
+                         c->stream, S.nrows, S.idx(), vals, ms, d, dn, res_in, res_out, z, dinv, c1, c2,
+                         (const float*)nullptr, (Scalars*)nullptr, 1, 0, 0, partials(c));
+    });
+  });
+  check_launch();
 }
 
 template <class T>
@@ -428,20 +473,22 @@ void cheb_step(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* d, T
       const int nb = grid_for(S.nrows * GG);
       if (rvec) {
         hipLaunchKernelGGL((k_cheb_step<T, WW, 1, GG>), dim3(nb), dim3(kBlock), 0, c->stream, S.nrows,
-                           S.idx(), vals, d, dn, res_in, res_out, z, dinv, c1,
+                           S.idx(), vals, (T)1, d, dn, res_in, res_out, z, dinv, c1,
                            c2, rvec, sc, cps, nsys, first, partials(c));
         finish<WW>(c, S.nrows * GG, FIN_RHO, WW, sc, cps, nsys, first, nullptr);
       } else
         hipLaunchKernelGGL((k_cheb_step<T, WW, 0, GG>), dim3(nb), dim3(kBlock), 0, c->stream, S.nrows,
-                           S.idx(), vals, d, dn, res_in, res_out, z, dinv, c1,
+                           S.idx(), vals, (T)1, d, dn, res_in, res_out, z, dinv, c1,
                            c2, rvec, sc, cps, nsys, first, partials(c));
     });
   });
   check_launch();
-  // algorithmic bytes: values + column indices once; d gathered once; res_in,
-  // z, dinv (and rvec) read; res_out, dn, z written
+  // algorithmic bytes: the stored operator once (values of every padded
+  // entry, the column-index structure); d gathered once; res_in, z, dinv
+  // (and rvec) read; res_out, dn, z written
   if (timed)
-    prof_end(c, double(S.nnz) * (sizeof(T) + 4.0) + double(S.nrows) * sizeof(T) * (W * (rvec ? 7.0 : 6.0) + 1.0));
+    prof_end(c, double(S.nnz_pad) * sizeof(T) + S.idx_bytes +
+                    double(S.nrows) * sizeof(T) * (W * (rvec ? 7.0 : 6.0) + 1.0));
 }
 
 // Autotune G for the velocity-row kernels of width W in precision T: time the

@@ -16,8 +16,9 @@ struct SolveStats {
 // Solve K x = b with b = (F, g) in the internal FP64 layout, x = (xu, xp) as
 // initial guess and result.  method 0 = coupled FGMRES, 1 = Schur FCG.
 // Returns STOKES_OK or STOKES_NOT_CONVERGED.
+// x_zero: (xu, xp) hold zero on entry, so the first residual is b itself.
 int solve_internal(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, const double* F, const double* g,
-                   double* xu, double* xp, SolveStats& st);
+                   double* xu, double* xp, SolveStats& st, bool x_zero);
 
 // One pressure-correction step from p_old (internal layout, may be null):
 // u and p in xu / xp.  rel_res = the largest final relative residual of its

@@ -600,11 +600,23 @@ class Engine {
       }
       // w = K_gamma z_j
       coupled_apply<TK>(zsrc, zsrc + nu(), w, w + nu(), true);
-      // CGS2
+      // CGS2 (the first update and the second projection share one pass
+      // over the basis while it holds at most kFusedMax vectors)
       const double t0 = now();
       mdot(V, j + 1, w, h1);
-      mupdate(V, j + 1, h1, -1.0, w, nullptr);
-      mdot(V, j + 1, w, h2);
+      if (j + 1 <= kFusedMax) {
+        dispatch_dn(D_, nrb_, [&](auto Dc, auto Nc) {
+          constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
+          hipLaunchKernelGGL((k_mupdate_dot<TK, TK, D, N>), dim3(nbx), dim3(kBlock), 0, c_->stream, c_->n_int,
+                             c_->n_p1, (const TK*)V, nc, j + 1, (const double*)h1, w, part);
+          ops::check_launch();
+          hipLaunchKernelGGL((k_mdot_fin<N>), dim3(j + 1), dim3(kBlock), 0, c_->stream, nbx, (const double*)part, h2);
+        });
+        ops::check_launch();
+      } else {
+        mupdate(V, j + 1, h1, -1.0, w, nullptr);
+        mdot(V, j + 1, w, h2);
+      }
       mupdate(V, j + 1, h2, -1.0, w, nrm);
       HIP_CHECK(hipMemcpyAsync(hhost, hdev, 3 * 64 * 8 * sizeof(double), hipMemcpyDeviceToHost, c_->stream));
       HIP_CHECK(hipStreamSynchronize(c_->stream));
@@ -767,7 +779,7 @@ class Engine {
 // Refinement loop: x (internal FP64) solves K x = b, b = (F, g).
 template <class T>
 int refine_loop(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, const double* F, const double* g,
-                double* xu, double* xp, SolveStats& st) {
+                double* xu, double* xp, SolveStats& st, bool x_zero) {
   Engine<T> e(c, o, nrb, st);
   Engine<double> e64(c, o, nrb, st);
   const int64_t nu = c->n_int * c->dim * nrb, np = c->n_p1 * nrb;
@@ -780,9 +792,14 @@ int refine_loop(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, 
   std::vector<double> prev(nrb, 0.0);
   int stalls = 0;
   for (int sweep = 0;; ++sweep) {
-    // r = b - K x (plain system, FP64)
-    ops::momentum<double>(c, nrb, xu, xp, nullptr, ru, -1.0, F);
-    ops::Bmul<double>(c, nrb, xu, rp, -1.0, g, 1.0);
+    // r = b - K x (plain system, FP64); r = b while x is still zero
+    if (sweep == 0 && x_zero) {
+      HIP_CHECK(hipMemcpyAsync(ru, F, nu * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      HIP_CHECK(hipMemcpyAsync(rp, g, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      ops::momentum<double>(c, nrb, xu, xp, nullptr, ru, -1.0, F);
+      ops::Bmul<double>(c, nrb, xu, rp, -1.0, g, 1.0);
+    }
     std::vector<double> rn = e64.dots(ru, ru, rp, rp);
     std::vector<double> target(nrb);
     bool done = true;
@@ -954,12 +971,12 @@ int projection_internal(stokes_ctx* c, const stokes_solve_opts& o, int nrb, cons
 }
 
 int solve_internal(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, const double* F, const double* g,
-                   double* xu, double* xp, SolveStats& st) {
+                   double* xu, double* xp, SolveStats& st, bool x_zero) {
   ops::ensure_lanes(c, c->dim * nrb, false);  // FP64 outer operator
   if (o.vel_pc == STOKES_VEL_MG && (!c->vmg_built || c->vmg_mu != c->prob.mu)) build_vmg(c);
   if (o.precision == STOKES_MIXED) ops::ensure_lanes(c, c->dim * nrb, true);
-  if (o.precision == STOKES_MIXED) return refine_loop<float>(c, o, method, nrb, F, g, xu, xp, st);
-  return refine_loop<double>(c, o, method, nrb, F, g, xu, xp, st);
+  if (o.precision == STOKES_MIXED) return refine_loop<float>(c, o, method, nrb, F, g, xu, xp, st, x_zero);
+  return refine_loop<double>(c, o, method, nrb, F, g, xu, xp, st, x_zero);
 }
 
 }  // namespace stokes

@@ -110,6 +110,25 @@ def test_multigrid_vcycle_symmetric_and_contracting(gpu_lib, n):
         assert rates.max() <= 0.5, (op, rates)
 
 
+def test_fp32_vcycle_half_values_close_and_contracting(gpu_lib):
+    """The FP32 V-cycle of the Galerkin hierarchy (op 8) reads half-precision
+    level values: it stays within 1e-2 of the FP64 cycle and still reduces the
+    residual of the oracle's operator by at least 2x per cycle."""
+    P, S = _problem(3, 24, seed=4), _oracle(3, 24, seed=4)
+    A = _pressure_mg_operators(S)[8]
+    rng = np.random.default_rng(6)
+    b = rng.standard_normal(S.np1)
+    V = lambda x, prec: P.apply(8, torch.tensor(x, device="cuda"), precision=prec).cpu().numpy()  # noqa: E731
+    assert _rel(V(b, 1), V(b, 0)) <= 1e-2
+    x = np.zeros_like(b)
+    res = [np.linalg.norm(b)]
+    for _ in range(4):
+        x = x + V(b - A @ x, 1)
+        res.append(np.linalg.norm(b - A @ x))
+    rates = np.array(res[1:]) / np.array(res[:-1])
+    assert rates.max() <= 0.5, rates
+
+
 @pytest.mark.parametrize("dim", [3, 2])
 def test_lanes_per_row_variants_bitwise_equal(gpu_lib, dim, monkeypatch):
     """Every lanes-per-row variant of the velocity-row kernels accumulates each
