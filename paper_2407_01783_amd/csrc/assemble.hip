@@ -20,6 +20,7 @@
 #include <cmath>
 #include <functional>
 #include <numeric>
+#include <thread>
 
 #include "common.h"
 #include "kernels.h"
@@ -538,170 +539,220 @@ __global__ __launch_bounds__(kBlock) void k_sqrt(int64_t n, const double* __rest
 // zero-valued pad in that slot, so the lanes of a slice gather the same
 // offset of consecutive nodes together.
 struct SellSlots {
-  int nclass = 0, nkeys = 0;
-  std::function<int(int64_t)> cls;           // class of a source row
-  std::function<int(int64_t, int32_t)> key;  // slot key of (source row, source column)
+  int R = 2;                      // keys: offsets in [-R, R]^3
+  int nclass = 1;
+  const int32_t* rxyz = nullptr;  // lattice coordinates of the source rows [3 per row]
+  const int32_t* cxyz = nullptr;  // ... of the source columns (same units)
+  const uint8_t* rcls = nullptr;  // class of a source row (null: 0)
+  int nkeys() const { return (2 * R + 1) * (2 * R + 1) * (2 * R + 1); }
+  int cls(int64_t r) const { return rcls ? rcls[r] : 0; }
+  int key(int64_t r, int32_t c) const {  // -1: outside the reach
+    const int w = 2 * R + 1;
+    int k = 0;
+    for (int ax = 2; ax >= 0; --ax) {
+      const int d = cxyz[3 * int64_t(c) + ax] - rxyz[3 * r + ax];
+      if (d < -R || d > R) return -1;
+      k = k * w + d + R;
+    }
+    return k;
+  }
 };
 
-// One-class slots of a P1 lattice with n cells per side (natural vertex
-// order, x fastest): the key is the offset in [-R, R]^dim.
-SellSlots p1_lattice_slots(int dim, int n, int R) {
-  SellSlots sl;
-  sl.nclass = 1;
-  const int w = 2 * R + 1;
-  sl.nkeys = dim == 3 ? w * w * w : w * w;
-  const int64_t n1 = int64_t(n) + 1;
-  sl.cls = [](int64_t) { return 0; };
-  sl.key = [=](int64_t r, int32_t c) {
-    int key = 0;
-    int64_t a = r, b = c;
-    for (int ax = 0, m = 1; ax < dim; ++ax, m *= w) {
-      const int64_t d = b % n1 - a % n1;
-      if (d < -R || d > R) return -1;
-      key += m * static_cast<int>(d + R);
-      a /= n1;
-      b /= n1;
-    }
-    return key;
-  };
-  return sl;
+// Lattice coordinates of the nodes of an m^dim grid (x fastest), times `scale`.
+std::vector<int32_t> lattice_coords(int dim, int64_t m, int scale) {
+  const int64_t n = dim == 3 ? m * m * m : m * m;
+  std::vector<int32_t> x(3 * n, 0);
+  for (int64_t v = 0; v < n; ++v) {
+    x[3 * v] = static_cast<int32_t>(scale * (v % m));
+    x[3 * v + 1] = static_cast<int32_t>(scale * ((v / m) % m));
+    x[3 * v + 2] = dim == 3 ? static_cast<int32_t>(scale * (v / (m * m))) : 0;
+  }
+  return x;
+}
+
+// f(begin, end) over [0, n) split across host threads (inline when small).
+template <class F>
+void parallel_for(int64_t n, F&& f) {
+  const int T = std::max(1, std::min(16, static_cast<int>(std::thread::hardware_concurrency())));
+  if (n < 65536 || T == 1) {
+    f(int64_t(0), n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t ch = (n + T - 1) / T;
+  for (int t = 0; t < T; ++t) {
+    const int64_t b = t * ch, e = std::min(n, b + ch);
+    if (b >= e) break;
+    th.emplace_back([&f, b, e] { f(b, e); });
+  }
+  for (auto& x : th) x.join();
 }
 
 // rows_in_order[r] = source row of output row r; entries kept where
 // col_map[col] >= 0; entry_map (optional) renames source entries.  Without
 // `slots` the entries of a row are sorted by column; with it they sit in the
-// stencil slots of the row's class.  Pads carry src -1 (value 0) and the
-// column of the nearest lane of the slice that has an entry in that slot (0
-// if none), which keeps the gathered addresses of a slot together.
+// stencil slots of the row's class (a pattern that is not a lattice stencil
+// of that reach falls back to sorted rows).  Pads carry src -1 (value 0) and
+// the column of the nearest lane of the slice that has an entry in that slot
+// (0 if none), which keeps the gathered addresses of a slot together.
 void build_sell(const HostCsr& in, const std::vector<int32_t>& rows_in_order, const std::vector<int32_t>& col_map,
                 const std::vector<int64_t>* entry_map, int planes, Sell& out, const SellSlots* slots = nullptr) {
   const int64_t nrows = static_cast<int64_t>(rows_in_order.size());
   const int64_t nsl = (nrows + 63) / 64;
   std::vector<int64_t> sp(nsl + 1, 0);
-  std::vector<int32_t> len(nrows, 0);
+  std::vector<int32_t> len(nrows, 0), cnt(nrows, 0);
   // slot of each key per class (slots mode)
-  std::vector<int32_t> slot_of;
-  std::vector<int32_t> class_width;
+  std::vector<int32_t> slot_of, class_width;
   if (slots) {
-    std::vector<char> present((size_t)slots->nclass * slots->nkeys, 0);
-    for (int64_t r = 0; r < nrows; ++r) {
-      const int64_t s = rows_in_order[r];
-      const int cl = slots->cls(s);
-      for (int64_t k = in.rowptr[s]; k < in.rowptr[s + 1]; ++k) {
-        if (col_map[in.cols[k]] < 0) continue;
-        const int key = slots->key(s, in.cols[k]);
-        // not a lattice stencil of the expected reach: sorted rows instead
-        if (cl < 0 || cl >= slots->nclass || key < 0 || key >= slots->nkeys)
-          return build_sell(in, rows_in_order, col_map, entry_map, planes, out, nullptr);
-        present[(size_t)cl * slots->nkeys + key] = 1;
-      }
+    const int nk = slots->nkeys(), ncl = slots->nclass;
+    std::vector<char> present((size_t)ncl * nk, 0);
+    std::vector<std::vector<char>> part;
+    std::vector<char> bad;
+    const int T = std::max(1, std::min(16, static_cast<int>(std::thread::hardware_concurrency())));
+    part.assign(T, std::vector<char>((size_t)ncl * nk, 0));
+    bad.assign(T, 0);
+    std::vector<std::thread> th;
+    const int64_t ch = (nrows + T - 1) / T;
+    for (int t = 0; t < T; ++t) {
+      th.emplace_back([&, t] {
+        for (int64_t r = t * ch; r < std::min(nrows, (t + 1) * ch); ++r) {
+          const int64_t sr = rows_in_order[r];
+          const int cl = slots->cls(sr);
+          if (cl < 0 || cl >= ncl) {
+            bad[t] = 1;
+            return;
+          }
+          for (int64_t k = in.rowptr[sr]; k < in.rowptr[sr + 1]; ++k) {
+            if (col_map[in.cols[k]] < 0) continue;
+            const int key = slots->key(sr, in.cols[k]);
+            if (key < 0) {
+              bad[t] = 1;
+              return;
+            }
+            part[t][(size_t)cl * nk + key] = 1;
+          }
+        }
+      });
+    }
+    for (auto& x : th) x.join();
+    for (int t = 0; t < T; ++t) {
+      if (bad[t]) return build_sell(in, rows_in_order, col_map, entry_map, planes, out, nullptr);
+      for (size_t i = 0; i < present.size(); ++i) present[i] |= part[t][i];
     }
     slot_of.assign(present.size(), -1);
-    class_width.assign(slots->nclass, 0);
-    for (int cl = 0; cl < slots->nclass; ++cl)
-      for (int key = 0; key < slots->nkeys; ++key)
-        if (present[(size_t)cl * slots->nkeys + key]) slot_of[(size_t)cl * slots->nkeys + key] = class_width[cl]++;
+    class_width.assign(ncl, 0);
+    for (int cl = 0; cl < ncl; ++cl)
+      for (int key = 0; key < nk; ++key)
+        if (present[(size_t)cl * nk + key]) slot_of[(size_t)cl * nk + key] = class_width[cl]++;
   }
+  parallel_for(nrows, [&](int64_t b, int64_t e) {
+    for (int64_t r = b; r < e; ++r) {
+      const int64_t sr = rows_in_order[r];
+      int32_t c = 0;
+      for (int64_t k = in.rowptr[sr]; k < in.rowptr[sr + 1]; ++k)
+        if (col_map[in.cols[k]] >= 0) ++c;
+      cnt[r] = c;
+      len[r] = slots ? class_width[slots->cls(sr)] : c;
+    }
+  });
   int64_t nnz = 0;
-  for (int64_t r = 0; r < nrows; ++r) {
-    const int64_t s = rows_in_order[r];
-    int32_t c = 0;
-    for (int64_t k = in.rowptr[s]; k < in.rowptr[s + 1]; ++k)
-      if (col_map[in.cols[k]] >= 0) ++c;
-    nnz += c;
-    len[r] = slots ? class_width[slots->cls(s)] : c;
-  }
-  for (int64_t s = 0; s < nsl; ++s) {
+  for (int64_t r = 0; r < nrows; ++r) nnz += cnt[r];
+  for (int64_t sl = 0; sl < nsl; ++sl) {
     int32_t w = 0;
-    for (int64_t r = s * 64; r < std::min(nrows, (s + 1) * 64); ++r) w = std::max(w, len[r]);
-    sp[s + 1] = sp[s] + 64 * int64_t(w);
+    for (int64_t r = sl * 64; r < std::min(nrows, (sl + 1) * 64); ++r) w = std::max(w, len[r]);
+    sp[sl + 1] = sp[sl] + 64 * int64_t(w);
   }
   const int64_t npad = sp[nsl];
   if (npad >= (int64_t(1) << 31)) throw Error(STOKES_ERR_UNSUPPORTED, "sparse operator exceeds 2^31 entries");
   std::vector<int32_t> cols(npad, 0), src(npad, -1);
-  std::vector<std::pair<int32_t, int64_t>> buf;
-  for (int64_t r = 0; r < nrows; ++r) {
-    const int64_t s = rows_in_order[r];
-    const int64_t base = sp[r / 64] + (r % 64);
-    if (slots) {
-      const int cl = slots->cls(s);
-      for (int64_t k = in.rowptr[s]; k < in.rowptr[s + 1]; ++k) {
+  std::vector<char> clash(nsl, 0);
+  parallel_for(nsl, [&](int64_t b, int64_t e) {
+    std::vector<std::pair<int32_t, int64_t>> buf;
+    for (int64_t r = b * 64; r < std::min(nrows, e * 64); ++r) {
+      const int64_t sr = rows_in_order[r];
+      const int64_t base = sp[r / 64] + (r % 64);
+      if (slots) {
+        const int cl = slots->cls(sr);
+        for (int64_t k = in.rowptr[sr]; k < in.rowptr[sr + 1]; ++k) {
+          const int32_t c = col_map[in.cols[k]];
+          if (c < 0) continue;
+          const int32_t j = slot_of[(size_t)cl * slots->nkeys() + slots->key(sr, in.cols[k])];
+          if (src[base + 64 * j] >= 0) clash[r / 64] = 1;
+          cols[base + 64 * j] = c;
+          src[base + 64 * j] = static_cast<int32_t>(entry_map ? (*entry_map)[k] : k);
+        }
+        continue;
+      }
+      buf.clear();
+      for (int64_t k = in.rowptr[sr]; k < in.rowptr[sr + 1]; ++k) {
         const int32_t c = col_map[in.cols[k]];
-        if (c < 0) continue;
-        const int32_t j = slot_of[(size_t)cl * slots->nkeys + slots->key(s, in.cols[k])];
-        if (src[base + 64 * j] >= 0) throw Error(STOKES_ERR_UNSUPPORTED, "two entries in one stencil slot");
-        cols[base + 64 * j] = c;
-        src[base + 64 * j] = static_cast<int32_t>(entry_map ? (*entry_map)[k] : k);
+        if (c >= 0) buf.emplace_back(c, entry_map ? (*entry_map)[k] : k);
       }
-      continue;
-    }
-    buf.clear();
-    for (int64_t k = in.rowptr[s]; k < in.rowptr[s + 1]; ++k) {
-      const int32_t c = col_map[in.cols[k]];
-      if (c >= 0) buf.emplace_back(c, entry_map ? (*entry_map)[k] : k);
-    }
-    std::sort(buf.begin(), buf.end());
-    for (size_t j = 0; j < buf.size(); ++j) {
-      cols[base + 64 * j] = buf[j].first;
-      src[base + 64 * j] = static_cast<int32_t>(buf[j].second);
-    }
-  }
-  // pads take the column of the nearest lane with an entry in the same slot
-  for (int64_t sl = 0; sl < nsl; ++sl) {
-    const int64_t w = (sp[sl + 1] - sp[sl]) / 64;
-    for (int64_t j = 0; j < w; ++j) {
-      const int64_t b0 = sp[sl] + 64 * j;
-      int first = -1;
-      for (int l = 0; l < 64 && first < 0; ++l)
-        if (src[b0 + l] >= 0) first = l;
-      if (first < 0) continue;
-      int last = first;
-      for (int l = 0; l < 64; ++l) {
-        if (src[b0 + l] >= 0) last = l;
-        else cols[b0 + l] = cols[b0 + (l < first ? first : last)];
+      std::sort(buf.begin(), buf.end());
+      for (size_t j = 0; j < buf.size(); ++j) {
+        cols[base + 64 * j] = buf[j].first;
+        src[base + 64 * j] = static_cast<int32_t>(buf[j].second);
       }
     }
-  }
+  });
+  for (char x : clash)
+    if (x) return build_sell(in, rows_in_order, col_map, entry_map, planes, out, nullptr);
+  // pads take the column of the nearest lane with an entry in the same slot;
   // packed columns: per slot a base and 8-bit lane offsets, where every slot
   // of the slice spans at most 256 columns
   std::vector<int32_t> cbase(npad / 64, 0);
   std::vector<uint8_t> cdel(npad, 0);
   std::vector<int32_t> pk(nsl, 0);
-  int64_t npk = 0;
-  for (int64_t sl = 0; sl < nsl; ++sl) {
-    const int64_t w = (sp[sl + 1] - sp[sl]) / 64;
-    const int lanes = static_cast<int>(std::min<int64_t>(64, nrows - sl * 64));
-    bool ok = true;
-    for (int64_t j = 0; j < w && ok; ++j) {
-      const int64_t b0 = sp[sl] + 64 * j;
-      int32_t lo = cols[b0], hi = cols[b0];
-      for (int l = 1; l < lanes; ++l) {
-        lo = std::min(lo, cols[b0 + l]);
-        hi = std::max(hi, cols[b0 + l]);
+  parallel_for(nsl, [&](int64_t b, int64_t e) {
+    for (int64_t sl = b; sl < e; ++sl) {
+      const int64_t w = (sp[sl + 1] - sp[sl]) / 64;
+      for (int64_t j = 0; j < w; ++j) {
+        const int64_t b0 = sp[sl] + 64 * j;
+        int first = -1;
+        for (int l = 0; l < 64 && first < 0; ++l)
+          if (src[b0 + l] >= 0) first = l;
+        if (first < 0) continue;
+        int last = first;
+        for (int l = 0; l < 64; ++l) {
+          if (src[b0 + l] >= 0) last = l;
+          else cols[b0 + l] = cols[b0 + (l < first ? first : last)];
+        }
       }
-      ok = int64_t(hi) - lo <= 255;
+      const int lanes = static_cast<int>(std::min<int64_t>(64, nrows - sl * 64));
+      bool ok = true;
+      for (int64_t j = 0; j < w && ok; ++j) {
+        const int64_t b0 = sp[sl] + 64 * j;
+        int32_t lo = cols[b0], hi = cols[b0];
+        for (int l = 1; l < lanes; ++l) {
+          lo = std::min(lo, cols[b0 + l]);
+          hi = std::max(hi, cols[b0 + l]);
+        }
+        ok = int64_t(hi) - lo <= 255;
+      }
+      if (!ok) continue;
+      pk[sl] = 1;
+      for (int64_t j = 0; j < w; ++j) {
+        const int64_t b0 = sp[sl] + 64 * j;
+        int32_t lo = cols[b0];
+        for (int l = 1; l < lanes; ++l) lo = std::min(lo, cols[b0 + l]);
+        cbase[sp[sl] / 64 + j] = lo;
+        for (int l = 0; l < lanes; ++l) cdel[b0 + l] = static_cast<uint8_t>(cols[b0 + l] - lo);
+      }
     }
-    if (!ok) continue;
-    pk[sl] = 1;
-    ++npk;
-    for (int64_t j = 0; j < w; ++j) {
-      const int64_t b0 = sp[sl] + 64 * j;
-      int32_t lo = cols[b0];
-      for (int l = 1; l < lanes; ++l) lo = std::min(lo, cols[b0 + l]);
-      cbase[sp[sl] / 64 + j] = lo;
-      for (int l = 0; l < lanes; ++l) cdel[b0 + l] = static_cast<uint8_t>(cols[b0 + l] - lo);
-    }
+  });
+  int64_t npk = 0;
+  double idx_bytes = 0;
+  for (int64_t sl = 0; sl < nsl; ++sl) {
+    npk += pk[sl];
+    const double w = double(sp[sl + 1] - sp[sl]) / 64;
+    idx_bytes += 12.0 + (pk[sl] ? 64.0 * w + 4.0 * w : 4.0 * 64.0 * w);  // slice offset and form, slots
   }
   out.nrows = nrows;
   out.nslices = nsl;
   out.nnz = nnz;
   out.nnz_pad = npad;
   out.packed_slices = npk;
-  out.idx_bytes = 0;
-  for (int64_t sl = 0; sl < nsl; ++sl) {
-    const double w = double(sp[sl + 1] - sp[sl]) / 64;
-    out.idx_bytes += 12.0 + (pk[sl] ? 64.0 * w + 4.0 * w : 4.0 * 64.0 * w);  // slice offset and form, slots
-  }
+  out.idx_bytes = idx_bytes;
   out.planes = planes;
   upload(out.slice_ptr, sp);
   upload(out.cols, cols);
@@ -853,58 +904,36 @@ void assemble_ctx(stokes_ctx* c) {
   // other, so the k-th stencil slot of the lanes gathers consecutive nodes.
   const int64_t n2 = 2 * int64_t(m.n) + 1, plane = D == 3 ? n2 * n2 : n2;
   const int64_t n1 = int64_t(m.n) + 1;
-  auto p2_xyz = [n2, plane, D](int64_t v, int64_t (&x)[3]) {
-    x[0] = v % n2;
-    x[1] = D == 3 ? (v / n2) % n2 : v / n2;
-    x[2] = D == 3 ? v / plane : 0;
-  };
-  auto p1_xyz = [n1, D](int64_t q, int64_t (&x)[3]) {  // in P2 grid units
-    x[0] = 2 * (q % n1);
-    x[1] = 2 * (D == 3 ? (q / n1) % n1 : q / n1);
-    x[2] = D == 3 ? 2 * (q / (n1 * n1)) : 0;
-  };
-  auto p2_type = [&](int64_t v) {
-    int64_t x[3];
-    p2_xyz(v, x);
-    return static_cast<int>((x[0] & 1) + 2 * (x[1] & 1) + 4 * (x[2] & 1));
-  };
-  auto offset_key = [](const int64_t (&a)[3], const int64_t (&b)[3]) {  // b - a in [-2, 2]^3
-    int key = 0;
-    for (int ax = 2; ax >= 0; --ax) {
-      const int64_t d = b[ax] - a[ax];
-      if (d < -2 || d > 2) return -1;
-      key = key * 5 + static_cast<int>(d + 2);
-    }
-    return key;
-  };
-  std::vector<int32_t> interior;
+  // lattice coordinates in P2 grid units (P1 vertices at even points) and
+  // the parity type of every P2 node
+  const std::vector<int32_t> p2xyz = lattice_coords(D, n2, 1), p1xyz = lattice_coords(D, n1, 2);
+  std::vector<uint8_t> p2type(m.n_p2);
   for (int64_t v = 0; v < m.n_p2; ++v)
-    if (!m.p2_bnd[v]) interior.push_back(static_cast<int32_t>(v));
-  auto slab = [&](int32_t v) {
-    const int64_t K = v / plane;  // 1 .. 2n-1 on interior nodes
-    return std::min<int64_t>(7, (K - 1) * 8 / (n2 - 2));
-  };
-  std::stable_sort(interior.begin(), interior.end(), [&](int32_t a, int32_t b) {
-    const int64_t sa = slab(a), sb = slab(b);
-    if (sa != sb) return sa < sb;
-    return p2_type(a) < p2_type(b);
-  });
-  SellSlots slots_p2p2, slots_p2p1;
+    p2type[v] = static_cast<uint8_t>((p2xyz[3 * v] & 1) + 2 * (p2xyz[3 * v + 1] & 1) + 4 * (p2xyz[3 * v + 2] & 1));
+  // stable bucket order by (slab, type), natural order inside a bucket
+  std::vector<int32_t> interior;
+  {
+    std::vector<int64_t> start(65, 0);
+    std::vector<uint8_t> bucket(m.n_p2, 0);
+    for (int64_t v = 0; v < m.n_p2; ++v) {
+      if (m.p2_bnd[v]) continue;
+      const int64_t K = v / plane;  // 1 .. 2n-1 on interior nodes
+      const int64_t sl = std::min<int64_t>(7, (K - 1) * 8 / (n2 - 2));
+      bucket[v] = static_cast<uint8_t>(sl * 8 + p2type[v]);
+      ++start[bucket[v] + 1];
+    }
+    for (int k = 0; k < 64; ++k) start[k + 1] += start[k];
+    interior.resize(start[64]);
+    for (int64_t v = 0; v < m.n_p2; ++v)
+      if (!m.p2_bnd[v]) interior[start[bucket[v]]++] = static_cast<int32_t>(v);
+  }
+  SellSlots slots_p2p2, slots_p2p1, slots_p1p2;
   slots_p2p2.nclass = slots_p2p1.nclass = 8;
-  slots_p2p2.nkeys = slots_p2p1.nkeys = 125;
-  slots_p2p2.cls = slots_p2p1.cls = p2_type;
-  slots_p2p2.key = [&](int64_t r, int32_t col) {
-    int64_t a[3], b[3];
-    p2_xyz(r, a);
-    p2_xyz(col, b);
-    return offset_key(a, b);
-  };
-  slots_p2p1.key = [&](int64_t r, int32_t col) {
-    int64_t a[3], b[3];
-    p2_xyz(r, a);
-    p1_xyz(col, b);
-    return offset_key(a, b);
-  };
+  slots_p2p2.rcls = slots_p2p1.rcls = p2type.data();
+  slots_p2p2.rxyz = slots_p2p2.cxyz = slots_p2p1.rxyz = p2xyz.data();
+  slots_p2p1.cxyz = p1xyz.data();
+  slots_p1p2.rxyz = p1xyz.data();
+  slots_p1p2.cxyz = p2xyz.data();
   c->n_int = static_cast<int64_t>(interior.size());
   c->h_int2nat = interior;
   c->h_nat2int.assign(m.n_p2, -1);
@@ -1015,16 +1044,6 @@ void assemble_ctx(stokes_ctx* c) {
   std::iota(p1_rows.begin(), p1_rows.end(), 0);
   std::iota(p1_ident.begin(), p1_ident.end(), 0);
   build_sell(P2full, c->h_int2nat, c->h_nat2int, nullptr, 1, c->sA, &slots_p2p2);
-  SellSlots slots_p1p2;
-  slots_p1p2.nclass = 1;
-  slots_p1p2.nkeys = 125;
-  slots_p1p2.cls = [](int64_t) { return 0; };
-  slots_p1p2.key = [&](int64_t r, int32_t col) {
-    int64_t a[3], b[3];
-    p1_xyz(r, a);
-    p2_xyz(col, b);
-    return offset_key(a, b);
-  };
   build_sell(Bfull, p1_rows, c->h_nat2int, nullptr, D, c->sB, &slots_p1p2);
   {
     HostCsr BT, XLpat;
@@ -1047,11 +1066,17 @@ void assemble_ctx(stokes_ctx* c) {
                          c->nat2int.as<int32_t>(), c->xl.rowptr.as<int32_t>(), c->xl.cols.as<int32_t>(),
                          c->XL_csr.as<double>());
     HIP_CHECK(hipGetLastError());
-    const SellSlots slx = p1_lattice_slots(D, m.n, 2);
+    const std::vector<int32_t> q1 = lattice_coords(D, n1, 1);
+    SellSlots slx;
+    slx.R = 2;
+    slx.rxyz = slx.cxyz = q1.data();
     build_sell(XLpat, p1_rows, p1_ident, nullptr, 1, c->sX, &slx);
   }
   {
-    const SellSlots slq = p1_lattice_slots(D, m.n, 1);
+    const std::vector<int32_t> q1 = lattice_coords(D, n1, 1);
+    SellSlots slq;
+    slq.R = 1;
+    slq.rxyz = slq.cxyz = q1.data();
     build_sell(P1, p1_rows, p1_ident, nullptr, 1, c->sQ, &slq);
   }
   phase("sliced-ELL layouts");
@@ -1182,7 +1207,10 @@ void assemble_p1(stokes_ctx* c, const HostMesh& m, MgLevel& L) {
            LQ.as<double>());
   std::vector<int32_t> rows(m.n_p1);
   std::iota(rows.begin(), rows.end(), 0);
-  const SellSlots sl = p1_lattice_slots(D, m.n, 1);
+  const std::vector<int32_t> q1 = lattice_coords(D, int64_t(m.n) + 1, 1);
+  SellSlots sl;
+  sl.R = 1;
+  sl.rxyz = sl.cxyz = q1.data();
   build_sell(P1, rows, rows, nullptr, 1, L.S, &sl);
   L.nrows = m.n_p1;
   L.v64.alloc(L.S.nnz_pad * sizeof(double));
@@ -1211,7 +1239,10 @@ void upload_level(stokes_ctx* c, const HostCsr& A, const std::vector<double>& av
   const int64_t nr = A.nrows;
   std::vector<int32_t> rows(nr);
   std::iota(rows.begin(), rows.end(), 0);
-  const SellSlots sl = p1_lattice_slots(c->dim, L.n, 3);
+  const std::vector<int32_t> q1 = lattice_coords(c->dim, int64_t(L.n) + 1, 1);
+  SellSlots sl;
+  sl.R = 3;
+  sl.rxyz = sl.cxyz = q1.data();
   build_sell(A, rows, rows, nullptr, 1, L.S, &sl);
   L.nrows = nr;
   DevBuf dv;
