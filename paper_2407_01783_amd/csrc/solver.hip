@@ -103,7 +103,12 @@ class Engine {
     alpha_ = c->prob.alpha;
     const bool f32 = std::is_same<T, float>::value;
     al_deg_ = f32 ? 18 : 26;  // M_Q^{-1} inside A_gamma: 2 * 0.382^k below 1e-7 / 1e-11
-    cc_mq_deg_ = 6;           // mu M_Q^{-1} term of the Cahouet-Chabard operator
+    // mu (1 + gamma) M_Q^{-1} term of the Cahouet-Chabard operator: next to
+    // alpha X^{-1} it weighs at most about mu (1 + gamma) / (alpha h^2) on the
+    // finest pressure modes, so a low-degree polynomial suffices when that
+    // ratio is small (unsteady, small-viscosity regime)
+    const double h = 1.0 / std::max(1, c->mesh.n);
+    cc_mq_deg_ = mu_ * (1.0 + gamma_) / (alpha_ * h * h) < 0.1 ? 2 : 6;
     mv_deg_ = 8;              // M_V^{-1} inside B M^{-1} B^T
   }
 
