@@ -647,6 +647,151 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step_q(int64_t nrows, SellIdx i
   }
 }
 
+// ------------------------------------------ bfloat16 Chebyshev directions
+// The velocity Chebyshev polynomial may keep its direction q in bfloat16
+// (FP32 exponent range, 8-bit mantissa): it only shapes the preconditioner,
+// and the residual and z are updated with the rounded q, so the recurrence
+// stays consistent.  Rows of W values are stored WP = (W == 3 ? 4 : W) wide
+// (one aligned 8-byte load per gathered node at W = 3; the pad is 0).
+__device__ __forceinline__ uint16_t bf16_of(float f) {  // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float f_of_bf16(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+template <int W>
+__host__ __device__ constexpr int bf_width() { return W == 3 ? 4 : W; }
+
+// out[0..WG) = row values at component offset `off` of node c (WP per node)
+template <int WP, int WG>
+__device__ __forceinline__ void load_bf(const uint16_t* __restrict__ xq, int64_t c, int off, float (&out)[WG]) {
+  if constexpr (WP == 4 && WG >= 3) {
+    const uint2 u = *reinterpret_cast<const uint2*>(xq + c * 4);
+    out[0] = __uint_as_float(u.x << 16);
+    out[1] = __uint_as_float(u.x & 0xFFFF0000u);
+    out[2] = __uint_as_float(u.y << 16);
+    if constexpr (WG == 4) out[3] = __uint_as_float(u.y & 0xFFFF0000u);
+  } else if constexpr (WG % 2 == 0 && WP % 2 == 0) {
+    // pairs of values as 32-bit words (c WP and off are even: 4-byte aligned)
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(xq + c * WP + off);
+#pragma unroll
+    for (int k = 0; k < WG / 2; ++k) {
+      const uint32_t u = p[k];
+      out[2 * k] = __uint_as_float(u << 16);
+      out[2 * k + 1] = __uint_as_float(u & 0xFFFF0000u);
+    }
+  } else {
+#pragma unroll
+    for (int w = 0; w < WG; ++w) out[w] = f_of_bf16(xq[c * WP + off + w]);
+  }
+}
+
+template <int W, int G, typename TM, bool PK, int U>
+__device__ __forceinline__ void sell_row_bq_impl(const SellIdx& ix, const SliceRef& r, const TM* __restrict__ vals,
+                                                 const uint16_t* __restrict__ xq, int off, float (&acc)[W / G]) {
+  constexpr int WG = W / G, WP = bf_width<W>();
+  int j = 0;
+  for (; j + U <= r.width; j += U) {
+    int32_t c[U];
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[u] = sell_col<PK>(ix, r, j + u);
+      v[u] = (float)__builtin_nontemporal_load(vals + r.beg + 64 * (j + u));
+    }
+    float xv[U][WG];
+#pragma unroll
+    for (int u = 0; u < U; ++u) load_bf<WP, WG>(xq, c[u], off, xv[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int w = 0; w < WG; ++w) acc[w] = fma(v[u], xv[u][w], acc[w]);
+  }
+  for (; j < r.width; ++j) {
+    const int32_t c = sell_col<PK>(ix, r, j);
+    const float v = (float)__builtin_nontemporal_load(vals + r.beg + 64 * j);
+    float xv[WG];
+    load_bf<WP, WG>(xq, c, off, xv);
+#pragma unroll
+    for (int w = 0; w < WG; ++w) acc[w] = fma(v, xv[w], acc[w]);
+  }
+}
+
+// First step with a bfloat16 direction out:  q0 = theta_inv r (not stored),
+// res = r - (S D^{-1}) q0, q1 = bf16(c1 q0 + c2 res), z (+)= dinv (q0 + q1)
+template <typename TM, int W, int ACC, int G, int U = 8>
+__global__ __launch_bounds__(kBlock) void k_cheb_first_qb(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
+                                                          const float* __restrict__ r, const float* __restrict__ dinv,
+                                                          float theta_inv, uint16_t* __restrict__ q1,
+                                                          float* __restrict__ res, float* __restrict__ z, float c1,
+                                                          float c2) {
+  constexpr int WG = W / G, WP = bf_width<W>();
+  XCD_ROWS_G(row, sub, nrows, G) {
+    float acc[WG];
+#pragma unroll
+    for (int w = 0; w < WG; ++w) acc[w] = 0;
+    sell_row<float, W, G, TM, U>(ix, vals, r, row, sub, acc);
+    const float di = dinv[row];
+    const int64_t o = row * W + sub * WG, oq = row * WP + sub * WG;
+#pragma unroll
+    for (int w = 0; w < WG; ++w) {
+      const int64_t i = o + w;
+      const float q0 = theta_inv * r[i];
+      const float rs = r[i] - theta_inv * acc[w];
+      res[i] = rs;
+      const uint16_t qb = bf16_of(fma(c1, q0, c2 * rs));
+      q1[oq + w] = qb;
+      const float qn = f_of_bf16(qb);
+      z[i] = ACC ? fma(di, q0 + qn, z[i]) : di * (q0 + qn);
+    }
+    if constexpr (WP != W) {
+      if (sub == G - 1) q1[row * WP + W] = 0;
+    }
+  }
+}
+
+// Later steps:  res = res_in - (S D^{-1}) q ;  qn = bf16(c1 q + c2 res) ;  z += dinv qn
+template <typename TM, int W, int G, int U = 8>
+__global__ __launch_bounds__(kBlock) void k_cheb_step_qb(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
+                                                         const uint16_t* __restrict__ q, uint16_t* __restrict__ qn,
+                                                         const float* res_in, float* res_out, float* __restrict__ z,
+                                                         const float* __restrict__ dinv, float c1, float c2) {
+  constexpr int WG = W / G, WP = bf_width<W>();
+  XCD_ROWS_G(row, sub, nrows, G) {
+    const int64_t o = row * W + sub * WG;
+    float acc[WG];
+#pragma unroll
+    for (int w = 0; w < WG; ++w) acc[w] = 0;
+    {
+      const SliceRef rf = slice_ref(ix, row);
+      if (rf.pk) sell_row_bq_impl<W, G, TM, true, U>(ix, rf, vals, q, sub * WG, acc);
+      else sell_row_bq_impl<W, G, TM, false, U>(ix, rf, vals, q, sub * WG, acc);
+    }
+    // res_in may alias res_out: load the whole row before any store
+    float ri[WG], qq[WG], zz[WG];
+    const float di = dinv[row];
+    load_bf<WP, WG>(q, row, sub * WG, qq);
+#pragma unroll
+    for (int w = 0; w < WG; ++w) {
+      ri[w] = res_in[o + w];
+      zz[w] = z[o + w];
+    }
+    const int64_t oq = row * WP + sub * WG;
+#pragma unroll
+    for (int w = 0; w < WG; ++w) {
+      const float rs = ri[w] - acc[w];
+      res_out[o + w] = rs;
+      const uint16_t qb = bf16_of(fma(c1, qq[w], c2 * rs));
+      qn[oq + w] = qb;
+      z[o + w] = fma(di, f_of_bf16(qb), zz[w]);
+    }
+    if constexpr (WP != W) {
+      if (sub == G - 1) qn[row * WP + W] = 0;
+    }
+  }
+}
+
 // ------------------------------------------------------------- B and B^T
 
 // p = a * (B u) + b * pin

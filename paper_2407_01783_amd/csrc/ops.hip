@@ -422,6 +422,47 @@ void cheb_first_h(stokes_ctx* c, int W, const float* r, const float* dinv, float
   check_launch();
 }
 
+void cheb_first_hb(stokes_ctx* c, int W, const float* r, const float* dinv, float theta_inv, uint16_t* q1,
+                   float* res, float* z, float c1, float c2) {
+  const Sell& S = c->sA;
+  const int G = lanes_op(c, &S, W, true);
+  dispatch_w(W, [&](auto Wc) {
+    constexpr int WW = decltype(Wc)::value;
+    with_g<WW>(G, [&](auto Gc) {
+      constexpr int GG = decltype(Gc)::value;
+      hipLaunchKernelGGL((k_cheb_first_qb<_Float16, WW, 0, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0,
+                         c->stream, S.nrows, S.idx(), (const _Float16*)c->AD16.as<_Float16>(), r, dinv, theta_inv,
+                         q1, res, z, c1, c2);
+    });
+  });
+  check_launch();
+}
+
+void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const float* res_in, float* res_out,
+                  float* z, const float* dinv, float c1, float c2) {
+  const Sell& S = c->sA;
+  const bool timed = prof_begin(c, &S, nullptr, nullptr);
+  const int G = lanes_op(c, &S, W, true);
+  int wp = W;
+  dispatch_w(W, [&](auto Wc) {
+    constexpr int WW = decltype(Wc)::value;
+    wp = bf_width<WW>();
+    with_g<WW>(G, [&](auto Gc) {
+      constexpr int GG = decltype(Gc)::value;
+      hipLaunchKernelGGL((k_cheb_step_qb<_Float16, WW, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0,
+                         c->stream, S.nrows, S.idx(), (const _Float16*)c->AD16.as<_Float16>(), q, qn, res_in,
+                         res_out, z, dinv, c1, c2);
+    });
+  });
+  check_launch();
+  // algorithmic bytes: the stored operator once (half values of every padded
+  // entry, the column-index structure); res_in, z read and res_out, z written
+  // (W floats each); q read once (gathered and own row) and qn written (WP
+  // bfloat16 each); dinv read
+  if (timed)
+    prof_end(c, double(S.nnz_pad) * 2.0 + S.idx_bytes + double(S.nrows) * (4.0 * (W * 4.0 + 1.0) + 2.0 * 2.0 * wp));
+}
+
 void cheb_step_h(stokes_ctx* c, int W, const float* q, float* qn, const float* res_in, float* res_out, float* z,
                  const float* dinv, float c1, float c2) {
   const Sell& S = c->sA;

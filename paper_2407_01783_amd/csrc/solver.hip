@@ -139,6 +139,17 @@ class Engine {
     }
     if constexpr (std::is_same<T, float>::value) {
       // FP32 velocity block: read the half-precision copy of A_II D^{-1}
+      if (&S == &c_->sA && vals == A() && c_->vel_half && c_->AD16.p && c_->vel_bf) {
+        // the direction in bfloat16 (the float buffers hold it, narrower)
+        uint16_t* q0 = reinterpret_cast<uint16_t*>(d0);
+        uint16_t* q1 = reinterpret_cast<uint16_t*>(d1);
+        ops::cheb_first_hb(c_, W, r, dinv, (float)k.theta_inv, q0, res, z, (float)k.c1[0], (float)k.c2[0]);
+        for (int j = 2; j < degree; ++j) {
+          ops::cheb_step_hb(c_, W, q0, q1, res, res, z, dinv, (float)k.c1[j - 1], (float)k.c2[j - 1]);
+          std::swap(q0, q1);
+        }
+        return;
+      }
       if (&S == &c_->sA && vals == A() && c_->vel_half && c_->AD16.p) {
         ops::cheb_first_h(c_, W, r, dinv, (float)k.theta_inv, d0, res, z, (float)k.c1[0], (float)k.c2[0]);
         for (int j = 2; j < degree; ++j) {
