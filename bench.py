@@ -50,7 +50,7 @@ SOLVER = dict(method="coupled", rtol=1e-8, cheb_degree=6, inner_mode=1, inner_rt
 
 
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-TRAFFIC_FILE = os.path.join(PROFILE_DIR, "k_cheb_step_q_cube64_hbm_traffic.txt")
+TRAFFIC_FILE = os.path.join(PROFILE_DIR, "k_cheb_step_qb_cube64_hbm_traffic.txt")
 
 
 # Sources that decide what one launch of the dominant kernel reads and writes:
@@ -245,9 +245,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": measured_traffic(args.workload, args.nrhs, args.strain),
-                     "kernel": f"k_cheb_step_q<float,_Float16,{dim * args.nrhs},G> (velocity-block SELL SpMV: "
-                               f"half-precision A_II D^-1 values, packed column indices, FP32 vectors; fused "
-                               f"Chebyshev update; G lanes per row, autotuned)",
+                     "kernel": f"k_cheb_step_qb<_Float16,{dim * args.nrhs},G> (velocity-block SELL SpMV: "
+                               f"half-precision A_II D^-1 values, packed column indices, bfloat16 direction, FP32 "
+                               f"residual and iterate; fused Chebyshev update; G lanes per row, autotuned)",
                      "bytes_per_launch": bytes_per, "launches": launches,
                      "avg_us": kern_s / launches * 1e6 if launches else None},
         "cpu_baseline": cpu,
