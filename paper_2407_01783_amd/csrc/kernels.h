@@ -815,7 +815,7 @@ __global__ __launch_bounds__(kBlock) void k_B(int64_t nrows, SellIdx ix, const T
 template <typename T, int D, int NRB, int G>
 __global__ __launch_bounds__(kBlock) void k_Bt(int64_t nrows, SellIdx ix, const T* __restrict__ vals,
                                                const T* __restrict__ p, const T* __restrict__ scale, T* uout,
-                                               T a, const T* uin, T b) {
+                                               T a, const T* uin, T b, T* __restrict__ btout) {
   constexpr int W = D * NRB, WG = W / G;
   XCD_ROWS_G(row, sub, nrows, G) {
     T acc[WG];
@@ -829,6 +829,10 @@ __global__ __launch_bounds__(kBlock) void k_Bt(int64_t nrows, SellIdx ix, const 
     for (int w = 0; w < WG; ++w) ui[w] = b != T(0) ? uin[o + w] : T(0);
 #pragma unroll
     for (int w = 0; w < WG; ++w) uout[o + w] = fma(b, ui[w], sc * acc[w]);
+    if (btout) {  // the scaled product alone, for reuse
+#pragma unroll
+      for (int w = 0; w < WG; ++w) btout[o + w] = sc * acc[w];
+    }
   }
 }
 

@@ -45,9 +45,9 @@ void spmv(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* x, T* y, 
 // p = a * B u + b * pin
 template <class T>
 void Bmul(stokes_ctx* c, int nrb, const T* u, T* p, T a, const T* pin, T b);
-// u = a * scale .* (B^T p) + b * uin
+// u = a * scale .* (B^T p) + b * uin; btout (optional) = a * scale .* (B^T p)
 template <class T>
-void Btmul(stokes_ctx* c, int nrb, const T* p, const T* scale, T* u, T a, const T* uin, T b);
+void Btmul(stokes_ctx* c, int nrb, const T* p, const T* scale, T* u, T a, const T* uin, T b, T* btout = nullptr);
 // y = a * (A x) + b * yin with the velocity operator (vector Laplacian block
 // or, for strain contexts, the coupled alpha M + mu (L + D) blocks)
 template <class T>

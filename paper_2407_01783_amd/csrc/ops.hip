@@ -179,7 +179,7 @@ void Bmul(stokes_ctx* c, int nrb, const T* u, T* p, T a, const T* pin, T b) {
 }
 
 template <class T>
-void Btmul(stokes_ctx* c, int nrb, const T* p, const T* scale, T* u, T a, const T* uin, T b) {
+void Btmul(stokes_ctx* c, int nrb, const T* p, const T* scale, T* u, T a, const T* uin, T b, T* btout) {
   const Sell& S = c->sBt;
   const int G = lanes_op(c, &S, c->dim * nrb, std::is_same<T, float>::value);
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
@@ -188,7 +188,7 @@ void Btmul(stokes_ctx* c, int nrb, const T* p, const T* scale, T* u, T a, const 
       constexpr int GG = decltype(Gc)::value;
       hipLaunchKernelGGL((k_Bt<T, D, N, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows,
                          S.idx(), btvals<T>(c).template as<T>(), p, scale, u,
-                         a, uin, b);
+                         a, uin, b, btout);
     });
   });
   check_launch();
@@ -691,7 +691,7 @@ void adj_dJdmu(stokes_ctx* c, int nrb, const double* u_full, const double* lam, 
 #define INST(T)                                                                                                      \
   template void spmv<T>(stokes_ctx*, const Sell&, const T*, int, const T*, T*, T, const T*, T);                     \
   template void Bmul<T>(stokes_ctx*, int, const T*, T*, T, const T*, T);                                            \
-  template void Btmul<T>(stokes_ctx*, int, const T*, const T*, T*, T, const T*, T);                                 \
+  template void Btmul<T>(stokes_ctx*, int, const T*, const T*, T*, T, const T*, T, T*);                             \
   template void momentum<T>(stokes_ctx*, int, const T*, const T*, const T*, T*, T, const T*);                       \
   template void velop<T>(stokes_ctx*, int, const T*, T*, T, const T*, T);                                           \
   template void dot_dev<T>(stokes_ctx*, int64_t, int, const T*, const T*, const double*, double*);                  \

@@ -424,14 +424,15 @@ class Engine {
     ops::remove_mean<T>(c_, nrb_, z);
   }
 
-  // z = P^{-1} v, block preconditioners of the coupled matrix (Sec. 2.4)
-  void block_prec(const T* vu, const T* vp, T* zu, T* zp) {
+  // z = P^{-1} v, block preconditioners of the coupled matrix (Sec. 2.4);
+  // bt (optional, upper triangular only) receives B^T z_p
+  void block_prec(const T* vu, const T* vp, T* zu, T* zp, T* bt = nullptr) {
     T* tp = buf("bp_tp", np());
     T* tu = buf("bp_tu", nu());
     T* yu = buf("bp_yu", nu());
     if (o_.coupled_pc == STOKES_PC_UPPER) {
       cc_apply(vp, zp);
-      ops::Btmul<T>(c_, nrb_, zp, nullptr, tu, (T)1, vu, (T)1);  // tu = v_u + B^T z_p
+      ops::Btmul<T>(c_, nrb_, zp, nullptr, tu, (T)1, vu, (T)1, bt);  // tu = v_u + B^T z_p
       vel_solve(tu, zu);
       return;
     }
@@ -605,7 +606,11 @@ class Engine {
         ops::cast<TK, T>(c_, nc, Vj, vin);
         vsrc = vin;
       }
-      block_prec(vsrc, vsrc + nu(), Zj, Zj + nu());
+      // with the upper triangular preconditioner in the Krylov precision the
+      // product B^T z_p of the preconditioner is reused by K_gamma z_j
+      const bool reuse_bt = std::is_same<T, TK>::value && o_.coupled_pc == STOKES_PC_UPPER && gamma_ == 0;
+      T* bt = reuse_bt ? buf("gm_bt", nu()) : nullptr;
+      block_prec(vsrc, vsrc + nu(), Zj, Zj + nu(), bt);
       const TK* zsrc;
       if constexpr (std::is_same<T, TK>::value) {
         zsrc = Zj;
@@ -615,7 +620,16 @@ class Engine {
         zsrc = zk;
       }
       // w = K_gamma z_j
-      coupled_apply<TK>(zsrc, zsrc + nu(), w, w + nu(), true);
+      if constexpr (std::is_same<T, TK>::value) {
+        if (reuse_bt) {
+          ops::velop<TK>(c_, nrb_, zsrc, w, (TK)1, bt, (TK)-1);          // A z_u - B^T z_p
+          ops::Bmul<TK>(c_, nrb_, zsrc, w + nu(), (TK)1, nullptr, (TK)0);  // B z_u
+        } else {
+          coupled_apply<TK>(zsrc, zsrc + nu(), w, w + nu(), true);
+        }
+      } else {
+        coupled_apply<TK>(zsrc, zsrc + nu(), w, w + nu(), true);
+      }
       // CGS2 (the first update and the second projection share one pass
       // over the basis while it holds at most kFusedMax vectors)
       const double t0 = now();
