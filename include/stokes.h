@@ -232,7 +232,12 @@ stokes_status stokes_solve_adjoint(stokes_ctx* ctx, int32_t nrhs, const double* 
  * pressure-shaped); 8 = one V-cycle of the Galerkin multigrid hierarchy of
  * B_I Lambda_V^-1 B_I^T + M_Q, the preconditioner of that operator (x, y
  * pressure-shaped); 9 = one velocity-multigrid V-cycle for alpha M_V + mu L_V
- * (x, y velocity-shaped, boundary entries ignored / set to 0). */
+ * (x, y velocity-shaped, boundary entries ignored / set to 0); 10 = the
+ * FIXED-mode velocity preconditioner: the degree-6 Chebyshev-Jacobi
+ * polynomial of A~_{lambda,3} = alpha M_V + mu L_V on the interval of
+ * stokes_bounds[0..1] (x, y velocity-shaped; precision 1 reads a
+ * half-precision copy of A D^-1 and keeps the Chebyshev direction in
+ * bfloat16, so it agrees with precision 0 to about 1e-3). */
 stokes_status stokes_apply(stokes_ctx* ctx, int32_t op, int32_t precision, int32_t nrhs,
                            const double* x, double* y);
 

@@ -288,3 +288,30 @@ def quadratic_loss(sysm, u_full, u_target_full):
     diff = np.asarray(u_full).reshape(sysm.d, -1) - np.asarray(u_target_full).reshape(sysm.d, -1)
     Md = np.stack([sysm.mats.Ms @ diff[c] for c in range(sysm.d)])
     return 0.5 * float(np.sum(diff * Md)), Md
+
+
+def chebyshev_jacobi(A, lo, hi, k, r):
+    """z = q_k(D^-1 A) D^-1 r, the degree-k Chebyshev-Jacobi polynomial
+    preconditioner (the FIXED inner velocity operator, standing in for the
+    paper's fixed inner cycles of Sec. 3.3; Saad, Iterative Methods for Sparse
+    Linear Systems, Sec. 12.1): k steps of the Chebyshev iteration for
+    D^-1 A z = D^-1 r from z = 0 on the interval [lo, hi] of D^-1 A (D = diag A).
+
+    Written in closed form rather than as the three-term recurrence: the
+    iteration's error after k steps is T_k((theta - M)/delta) / T_k(theta/delta)
+    times the initial error (theta = (hi + lo)/2, delta = (hi - lo)/2, T_k the
+    Chebyshev polynomial of the first kind), so
+        z = (1 - T_k((theta - lambda)/delta) / T_k(theta/delta)) / lambda
+    on every eigenpair of the symmetric S = D^-1/2 A D^-1/2, evaluated by a
+    dense eigendecomposition (small A only).  r: [..., n] (rows along the last
+    axis)."""
+    A = A.toarray() if sp.issparse(A) else np.asarray(A, dtype=float)
+    dh = 1.0 / np.sqrt(np.diag(A))
+    S = dh[:, None] * A * dh[None, :]
+    lam, Q = np.linalg.eigh(0.5 * (S + S.T))
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    Tk = np.polynomial.chebyshev.Chebyshev.basis(k)
+    q = (1.0 - Tk((theta - lam) / delta) / Tk(theta / delta)) / lam
+    r = np.asarray(r, dtype=float)
+    y = (r * dh) @ Q          # rows of r in the eigenbasis of S
+    return ((y * q) @ Q.T) * dh

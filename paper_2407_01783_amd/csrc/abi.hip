@@ -602,7 +602,7 @@ stokes_status stokes_solve_adjoint(stokes_ctx* c, int32_t nrhs, const double* u,
 stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t nrhs, const double* x, double* y) {
   return guard([&]() -> stokes_status {
     if (!c) throw Error(STOKES_ERR_ARG, "ctx is NULL");
-    if (op < 0 || op > 9) throw Error(STOKES_ERR_ARG, "op must be in [0, 9]");
+    if (op < 0 || op > 10) throw Error(STOKES_ERR_ARG, "op must be in [0, 10]");
     if (precision != 0 && precision != 1) throw Error(STOKES_ERR_ARG, "precision must be 0 or 1");
     if (nrhs < 1) throw Error(STOKES_ERR_ARG, "nrhs must be >= 1");
     if (!x || !y) throw Error(STOKES_ERR_ARG, "x and y must not be NULL");
@@ -622,9 +622,9 @@ stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t
       float* xpf = static_cast<float*>(c->workspace("ap_xpf", np * sizeof(float)));
       float* yuf = static_cast<float*>(c->workspace("ap_yuf", nu * sizeof(float)));
       float* ypf = static_cast<float*>(c->workspace("ap_ypf", np * sizeof(float)));
-      const bool in_vel = op == 0 || op == 1 || op == 5 || op == 9;
+      const bool in_vel = op == 0 || op == 1 || op == 5 || op == 9 || op == 10;
       const bool in_p = op == 2 || op == 3 || op == 4 || op == 5 || op == 6 || op == 7 || op == 8;
-      const bool out_vel = op == 0 || op == 2 || op == 5 || op == 9;
+      const bool out_vel = op == 0 || op == 2 || op == 5 || op == 9 || op == 10;
       const double* xv = x + vo;
       const double* xpp = op == 5 ? x + tot_u + po : x + po;
       if (in_vel) ops::vel_in<double>(c, nrb, xv, xu);
@@ -645,6 +645,7 @@ stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t
           case 6: mg_vcycle<T>(c, c->mgq, nrb, XP, YP, 0); break;
           case 8: mg_vcycle<T>(c, c->mgx, nrb, XP, YP, 0); break;
           case 9: vel_vcycle<T>(c, D * nrb, XU, YU, 0); break;
+          case 10: vel_cheb_apply<T>(c, nrb, 6, XU, YU); break;
           case 7: ops::spmv<T>(c, c->sX, ops::pick<T>(c->XL64, c->XL32), nrb, XP, YP, (T)1, nullptr, (T)0); break;
           default:
             ops::momentum<T>(c, nrb, XU, XP, nullptr, YU, (T)1, nullptr);

@@ -26,4 +26,11 @@ int solve_internal(stokes_ctx* c, const stokes_solve_opts& o, int method, int nr
 int projection_internal(stokes_ctx* c, const stokes_solve_opts& o, int nrb, const double* F, const double* g,
                         const double* pold, double* xu, double* xp, SolveStats& st);
 
+// z = the degree-`degree` Chebyshev-Jacobi polynomial of A_II applied to r
+// (internal velocity layout, W = dim nrb values per row): the FIXED-mode
+// velocity preconditioner of the coupled solves, in T (FP32: the
+// half-precision A_II D^{-1} copy and the bfloat16 direction).
+template <class T>
+void vel_cheb_apply(stokes_ctx* c, int nrb, int degree, const T* r, T* z);
+
 }  // namespace stokes

@@ -1000,6 +1000,18 @@ int projection_internal(stokes_ctx* c, const stokes_solve_opts& o, int nrb, cons
   return projection_loop<double>(c, o, nrb, F, g, pold, xu, xp, st);
 }
 
+template <class T>
+void vel_cheb_apply(stokes_ctx* c, int nrb, int degree, const T* r, T* z) {
+  stokes_solve_opts o;
+  stokes_default_opts(&o);
+  SolveStats st;
+  Engine<T> e(c, o, nrb, st);
+  e.cheb_apply("vfx", c->sA, ops::pick<T>(c->A64, c->A32), ops::pick<T>(c->dA64, c->dA32), c->bA, degree,
+               c->dim * nrb, r, z);
+}
+template void vel_cheb_apply<float>(stokes_ctx*, int, int, const float*, float*);
+template void vel_cheb_apply<double>(stokes_ctx*, int, int, const double*, double*);
+
 int solve_internal(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, const double* F, const double* g,
                    double* xu, double* xp, SolveStats& st, bool x_zero) {
   ops::ensure_lanes(c, c->dim * nrb, false);  // FP64 outer operator

@@ -188,7 +188,7 @@ class StokesProblem:
         """One assembled operator (see stokes_apply) on caller-layout tensors."""
         x = torch.as_tensor(x, dtype=torch.float64, device=self.device).contiguous()
         nu, npr = nrhs * self.dim * self.n_p2, nrhs * self.n_p1
-        out_len = {0: nu, 1: npr, 2: nu, 3: npr, 4: npr, 5: nu + npr, 6: npr, 7: npr, 8: npr, 9: nu}[op]
+        out_len = {0: nu, 1: npr, 2: nu, 3: npr, 4: npr, 5: nu + npr, 6: npr, 7: npr, 8: npr, 9: nu, 10: nu}[op]
         y = torch.empty(out_len, dtype=torch.float64, device=self.device)
         check(self.lib.stokes_set_stream(self.ctx, _stream_handle()))
         check(self.lib.stokes_apply(self.ctx, int(op), int(precision), int(nrhs), ptr(x), ptr(y)), "stokes_apply")

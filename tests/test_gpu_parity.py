@@ -129,6 +129,27 @@ def test_fp32_vcycle_half_values_close_and_contracting(gpu_lib):
     assert rates.max() <= 0.5, rates
 
 
+@pytest.mark.parametrize("dim,n,nrhs", [(3, 4, 1), (3, 5, 2), (2, 12, 3)])
+def test_velocity_chebyshev_preconditioner_matches_closed_form(gpu_lib, dim, n, nrhs):
+    """apply op 10 (the FIXED-mode velocity preconditioner, degree 6 on the
+    context's interval) against the oracle's closed-form Chebyshev-Jacobi
+    polynomial: FP64 to rounding; FP32 (half-precision A D^-1 values,
+    bfloat16 direction) to 2e-3 (measured 1-1.5e-4)."""
+    kw = dict(dim=dim, n=n, seed=7, mu=0.05, alpha=100.0)
+    P, S = _problem(**kw), _oracle(**kw)
+    lo, hi = P.bounds()[:2]
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((nrhs, dim, S.mesh.n_p2))
+    ref = np.zeros_like(x)
+    for b in range(nrhs):
+        ref[b][:, S.I] = ostokes.chebyshev_jacobi(S.A_II, lo, hi, 6, x[b][:, S.I])
+    for prec, tol in ((0, 1e-11), (1, 2e-3)):
+        y = P.apply(10, torch.tensor(x.ravel(), device="cuda"), precision=prec, nrhs=nrhs).cpu().numpy()
+        err = _rel(y, ref.ravel())
+        print(f"precision {prec}: rel err {err:.2e}", flush=True)
+        assert err <= tol, (prec, err)
+
+
 @pytest.mark.parametrize("dim", [3, 2])
 def test_lanes_per_row_variants_bitwise_equal(gpu_lib, dim, monkeypatch):
     """Every lanes-per-row variant of the velocity-row kernels accumulates each

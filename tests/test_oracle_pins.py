@@ -602,3 +602,51 @@ def test_adjoint_pressure_loss_gradient():
         h = 1e-3
         fd = (J_of(f + h * dvec)[0] - J_of(f - h * dvec)[0]) / (2 * h)
         assert abs(fd - np.sum(dJdf * dvec)) <= 1e-8 * max(abs(fd), 1e-12)
+
+
+# ------------------------------------------- Chebyshev-Jacobi closed form
+
+def _chebyshev_recurrence(A, lo, hi, k, r):
+    """Saad's Chebyshev acceleration (Iterative Methods, Alg. 12.1) on
+    D^-1 A x = D^-1 r from x = 0: k iterates, one product per step."""
+    A = np.asarray(A)
+    d = np.diag(A)
+    b = r / d
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    sigma = theta / delta
+    rho = 1.0 / sigma
+    dvec = b / theta
+    x = dvec.copy()
+    for _ in range(1, k):
+        res = b - (A @ x) / d
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        dvec = rho_new * rho * dvec + (2.0 * rho_new / delta) * res
+        rho = rho_new
+        x = x + dvec
+    return x
+
+
+def test_chebyshev_jacobi_matches_recurrence_and_error_bound():
+    """The closed form equals the textbook three-term iteration, meets the
+    Chebyshev error bound 2 rho^k in the A-norm when [lo, hi] holds the
+    spectrum of D^-1 A, and reaches A^-1 r for large k."""
+    rng = np.random.default_rng(11)
+    Bm = rng.standard_normal((40, 40))
+    A = Bm @ Bm.T + 40 * np.eye(40)
+    d = np.diag(A)
+    ev = np.linalg.eigvalsh(A / np.sqrt(np.outer(d, d)))
+    lo, hi = 0.9 * ev.min(), 1.05 * ev.max()
+    r = rng.standard_normal(40)
+    x_star = np.linalg.solve(A, r)
+    anorm = lambda v: np.sqrt(v @ A @ v)  # noqa: E731
+    kappa = hi / lo
+    rho = (np.sqrt(kappa) - 1) / (np.sqrt(kappa) + 1)
+    for k in (1, 2, 3, 6, 9):
+        z = stokes.chebyshev_jacobi(A, lo, hi, k, r)
+        assert np.allclose(z, _chebyshev_recurrence(A, lo, hi, k, r), rtol=1e-12, atol=1e-14), k
+        assert anorm(z - x_star) <= 2 * rho ** k * anorm(x_star) * (1 + 1e-12), k
+    assert np.allclose(stokes.chebyshev_jacobi(A, lo, hi, 60, r), x_star, rtol=1e-10)
+    # several right-hand sides along the leading axis
+    R = rng.standard_normal((3, 40))
+    Z = stokes.chebyshev_jacobi(A, lo, hi, 6, R)
+    assert np.allclose(Z[1], stokes.chebyshev_jacobi(A, lo, hi, 6, R[1]), rtol=1e-13)
