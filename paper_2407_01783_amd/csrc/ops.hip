@@ -113,9 +113,26 @@ int lanes_w(stokes_ctx* c, int W, bool f32) {
   return it != c->lanes.end() ? it->second : heuristic_lanes(W);
 }
 
+// B^T rows have their own tuned G (key offset kBtKey)
+constexpr int kBtKey = 1 << 20;
+int lanes_bt(stokes_ctx* c, int W, bool f32) {
+  if (c->force_lanes > 0) return c->force_lanes;
+  const auto it = c->lanes.find(kBtKey + W * 2 + (f32 ? 1 : 0));
+  return it != c->lanes.end() ? it->second : lanes_w(c, W, f32);
+}
+
+// the bfloat16-direction Chebyshev kernels too (key offset kQbKey)
+constexpr int kQbKey = 2 << 20;
+int lanes_qb(stokes_ctx* c, int W) {
+  if (c->force_lanes > 0) return c->force_lanes;
+  const auto it = c->lanes.find(kQbKey + W * 2 + 1);
+  return it != c->lanes.end() ? it->second : lanes_w(c, W, true);
+}
+
 // velocity-row operators use the tuned G; the pressure operators one lane per row
 int lanes_op(stokes_ctx* c, const Sell* S, int W, bool f32) {
-  return (S == &c->sA || S == &c->sBt) ? lanes_w(c, W, f32) : 1;
+  if (S == &c->sBt) return lanes_bt(c, W, f32);
+  return S == &c->sA ? lanes_w(c, W, f32) : 1;
 }
 
 int lanes_rows(stokes_ctx* c, int64_t nrows, int W, bool f32) {
@@ -425,7 +442,7 @@ void cheb_first_h(stokes_ctx* c, int W, const float* r, const float* dinv, float
 void cheb_first_hb(stokes_ctx* c, int W, const float* r, const float* dinv, float theta_inv, uint16_t* q1,
                    float* res, float* z, float c1, float c2) {
   const Sell& S = c->sA;
-  const int G = lanes_op(c, &S, W, true);
+  const int G = lanes_qb(c, W);
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
     with_g<WW>(G, [&](auto Gc) {
@@ -442,7 +459,7 @@ void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const f
                   float* z, const float* dinv, float c1, float c2) {
   const Sell& S = c->sA;
   const bool timed = prof_begin(c, &S, nullptr, nullptr);
-  const int G = lanes_op(c, &S, W, true);
+  const int G = lanes_qb(c, W);
   int wp = W;
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
@@ -578,11 +595,71 @@ void tune_lanes(stokes_ctx* c, int W) {
       best = g;
     }
   }
+  c->lanes[key] = best;
+  // the same for the B^T product (pressure gathers, d value planes)
+  if (W % c->dim == 0) {
+    const int nrb = W / c->dim;
+    DevBuf pz;
+    pz.alloc(c->n_p1 * nrb * sizeof(T));
+    HIP_CHECK(hipMemsetAsync(pz.p, 0, c->n_p1 * nrb * sizeof(T), c->stream));
+    int bbest = best;
+    float bms = 1e30f;
+    for (int g : cand) {
+      c->force_lanes = g;
+      Btmul<T>(c, nrb, pz.as<T>(), nullptr, y.as<T>(), T(1), nullptr, T(0));  // warm-up
+      HIP_CHECK(hipEventRecord(e0, c->stream));
+      for (int rep = 0; rep < 3; ++rep) Btmul<T>(c, nrb, pz.as<T>(), nullptr, y.as<T>(), T(1), nullptr, T(0));
+      HIP_CHECK(hipEventRecord(e1, c->stream));
+      HIP_CHECK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+      if (const char* e = std::getenv("STOKES_LOG"); e && std::atoi(e) >= 1)
+        std::fprintf(stderr, "[stokes] lanes W=%d %s G=%d: %.1f us per B^T product\n", W,
+                     std::is_same<T, float>::value ? "fp32" : "fp64", g, 1e3 * ms / 3);
+      if (ms < bms) {
+        bms = ms;
+        bbest = g;
+      }
+    }
+    c->lanes[kBtKey + key] = bbest;
+  }
+  // the bfloat16-direction Chebyshev step (FP32 contexts with the half copy)
+  if (std::is_same<T, float>::value && c->AD16.p) {
+    DevBuf qa, qb;
+    qa.alloc(c->n_int * W * sizeof(uint16_t) * 2);
+    qb.alloc(c->n_int * W * sizeof(uint16_t) * 2);
+    HIP_CHECK(hipMemsetAsync(qa.p, 0, qa.bytes, c->stream));
+    int qbest = best;
+    float qms = 1e30f;
+    const bool prof = c->prof_on;
+    c->prof_on = false;
+    for (int g : cand) {
+      c->force_lanes = g;
+      float* xr = reinterpret_cast<float*>(x.p);
+      float* yz = reinterpret_cast<float*>(y.p);
+      const float* di = c->dA32.as<float>();
+      cheb_step_hb(c, W, qa.as<uint16_t>(), qb.as<uint16_t>(), xr, xr, yz, di, 0.5f, 0.5f);  // warm-up
+      HIP_CHECK(hipEventRecord(e0, c->stream));
+      for (int rep = 0; rep < 3; ++rep)
+        cheb_step_hb(c, W, qa.as<uint16_t>(), qb.as<uint16_t>(), xr, xr, yz, di, 0.5f, 0.5f);
+      HIP_CHECK(hipEventRecord(e1, c->stream));
+      HIP_CHECK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+      if (const char* e = std::getenv("STOKES_LOG"); e && std::atoi(e) >= 1)
+        std::fprintf(stderr, "[stokes] lanes W=%d G=%d: %.1f us per bfloat16 Chebyshev step\n", W, g, 1e3 * ms / 3);
+      if (ms < qms) {
+        qms = ms;
+        qbest = g;
+      }
+    }
+    c->prof_on = prof;
+    c->lanes[kQbKey + key] = qbest;
+  }
   c->force_lanes = 0;
   HIP_CHECK(hipEventDestroy(e0));
   HIP_CHECK(hipEventDestroy(e1));
   HIP_CHECK(hipStreamSynchronize(c->stream));
-  c->lanes[key] = best;
 }
 
 void ensure_lanes(stokes_ctx* c, int W, bool f32) {
