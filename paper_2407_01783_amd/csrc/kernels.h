@@ -874,24 +874,19 @@ __device__ __forceinline__ constexpr int sym_index(int a, int b) {
   return a <= b ? a * D - a * (a - 1) / 2 + (b - a) : b * D - b * (b - 1) / 2 + (a - b);
 }
 
-template <typename T, int D, int NRB>
-__device__ __forceinline__ void sell_row_blk(const int64_t* __restrict__ sp, const int32_t* __restrict__ cols,
-                                             const T* __restrict__ vals, const T* __restrict__ x, int64_t row,
-                                             T (&acc)[D * NRB]) {
+template <typename T, int D, int NRB, bool PK>
+__device__ __forceinline__ void sell_row_blk_impl(const SellIdx& ix, const SliceRef& rf, const T* __restrict__ vals,
+                                                  const T* __restrict__ x, int64_t row, T (&acc)[D * NRB]) {
   constexpr int W = D * NRB, DD = D * (D + 1) / 2;
-  const int64_t s = row >> 6;
-  const int64_t beg = sp[s] + (row & 63);
-  const int width = (int)((sp[s + 1] - sp[s]) >> 6);
-  const T* __restrict__ vrow = vals + sp[s] * DD + (row & 63);
+  const T* __restrict__ vrow = vals + (rf.beg - (row & 63)) * DD + (row & 63);
   constexpr int U = 2;
   int j = 0;
-  for (; j + U <= width; j += U) {
+  for (; j + U <= rf.width; j += U) {
     int32_t c[U];
     T v[U][DD], xv[U][W];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const int64_t k = beg + 64 * (j + q);
-      c[q] = __builtin_nontemporal_load(cols + k);
+      c[q] = sell_col<PK>(ix, rf, j + q);
 #pragma unroll
       for (int e = 0; e < DD; ++e) v[q][e] = __builtin_nontemporal_load(vrow + (int64_t)(j + q) * 64 * DD + 64 * e);
     }
@@ -909,9 +904,8 @@ __device__ __forceinline__ void sell_row_blk(const int64_t* __restrict__ sp, con
           for (int b = 0; b < D; ++b)
             acc[r * D + a] = fma(v[q][sym_index<D>(a, b)], xv[q][r * D + b], acc[r * D + a]);
   }
-  for (; j < width; ++j) {
-    const int64_t k = beg + 64 * j;
-    const int32_t c = __builtin_nontemporal_load(cols + k);
+  for (; j < rf.width; ++j) {
+    const int32_t c = sell_col<PK>(ix, rf, j);
     T v[DD];
 #pragma unroll
     for (int e = 0; e < DD; ++e) v[e] = __builtin_nontemporal_load(vrow + (int64_t)j * 64 * DD + 64 * e);
@@ -925,17 +919,24 @@ __device__ __forceinline__ void sell_row_blk(const int64_t* __restrict__ sp, con
   }
 }
 
+template <typename T, int D, int NRB>
+__device__ __forceinline__ void sell_row_blk(const SellIdx& ix, const T* __restrict__ vals, const T* __restrict__ x,
+                                             int64_t row, T (&acc)[D * NRB]) {
+  const SliceRef rf = slice_ref(ix, row);
+  if (rf.pk) sell_row_blk_impl<T, D, NRB, true>(ix, rf, vals, x, row, acc);
+  else sell_row_blk_impl<T, D, NRB, false>(ix, rf, vals, x, row, acc);
+}
+
 // y = a * (A x) + b * yin with the block operator (yin may alias y)
 template <typename T, int D, int NRB>
-__global__ __launch_bounds__(kBlock) void k_spmv_blk(int64_t nrows, const int64_t* __restrict__ sp,
-                                                     const int32_t* __restrict__ cols, const T* __restrict__ vals,
+__global__ __launch_bounds__(kBlock) void k_spmv_blk(int64_t nrows, SellIdx ix, const T* __restrict__ vals,
                                                      const T* __restrict__ x, T* y, T a, const T* yin, T b) {
   constexpr int W = D * NRB;
   XCD_ROWS(row, nrows) {
     T acc[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = 0;
-    sell_row_blk<T, D, NRB>(sp, cols, vals, x, row, acc);
+    sell_row_blk<T, D, NRB>(ix, vals, x, row, acc);
     T yi[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) yi[w] = b != T(0) ? yin[row * W + w] : T(0);
@@ -946,8 +947,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_blk(int64_t nrows, const int64_
 
 // Momentum rows with the block operator: y = sgn (A u - B^T p + extra) + yin
 template <typename T, int D, int NRB>
-__global__ __launch_bounds__(kBlock) void k_momentum_blk(int64_t nrows, const int64_t* __restrict__ spA,
-                                                         const int32_t* __restrict__ colsA, const T* __restrict__ A,
+__global__ __launch_bounds__(kBlock) void k_momentum_blk(int64_t nrows, SellIdx ixA, const T* __restrict__ A,
                                                          SellIdx ixT, const T* __restrict__ Bt,
                                                          const T* __restrict__ u, const T* __restrict__ p,
                                                          const T* __restrict__ extra, T* y, T sgn, const T* yin) {
@@ -956,7 +956,7 @@ __global__ __launch_bounds__(kBlock) void k_momentum_blk(int64_t nrows, const in
     T acc[W], bt[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = bt[w] = 0;
-    sell_row_blk<T, D, NRB>(spA, colsA, A, u, row, acc);
+    sell_row_blk<T, D, NRB>(ixA, A, u, row, acc);
     sell_row_Bt<T, D, NRB, 1>(ixT, Bt, p, row, 0, bt);
     T ex[W], yi[W];  // yin may alias y
 #pragma unroll

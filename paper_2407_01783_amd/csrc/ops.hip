@@ -221,8 +221,7 @@ void velop(stokes_ctx* c, int nrb, const T* x, T* y, T a, const T* yin, T b) {
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
     constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
     hipLaunchKernelGGL((k_spmv_blk<T, D, N>), dim3(grid_for(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int,
-                       c->sA.slice_ptr.as<int64_t>(), c->sA.cols.as<int32_t>(), abvals<T>(c).template as<T>(), x, y,
-                       a, yin, b);
+                       c->sA.idx(), abvals<T>(c).template as<T>(), x, y, a, yin, b);
   });
   check_launch();
 }
@@ -233,8 +232,7 @@ void momentum(stokes_ctx* c, int nrb, const T* u, const T* p, const T* extra, T*
     dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
       constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
       hipLaunchKernelGGL((k_momentum_blk<T, D, N>), dim3(grid_for(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int,
-                         c->sA.slice_ptr.as<int64_t>(), c->sA.cols.as<int32_t>(), abvals<T>(c).template as<T>(),
-                         c->sBt.idx(), btvals<T>(c).template as<T>(), u,
+                         c->sA.idx(), abvals<T>(c).template as<T>(), c->sBt.idx(), btvals<T>(c).template as<T>(), u,
                          p, extra, y, sgn, yin);
     });
     check_launch();
