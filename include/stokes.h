@@ -85,6 +85,8 @@ enum { STOKES_FLAG_STRAIN = 1 };
  * meshes (the counterpart of the paper's AMG V-cycles, Sec. 3.3), whose cost
  * and iteration counts do not grow with 1/h when mu dt / h^2 is large. */
 enum { STOKES_VEL_CHEB = 0, STOKES_VEL_MG = 1 };
+/* stokes_solve_opts.arnoldi_fp64: precision of the mixed FGMRES cycle. */
+enum { STOKES_ARNOLDI_FP32 = 0, STOKES_ARNOLDI_FP64 = 1, STOKES_ARNOLDI_FP64_K = 2 };
 
 typedef struct {
   int32_t dim;        /* 2 or 3 */
@@ -116,12 +118,15 @@ typedef struct {
                              iterations (no convergence checks); 0: use inner_rtol_u */
   int32_t inner_its_p;    /* the same for the inner pressure CG (0: inner_rtol_p) */
   int32_t vel_pc;         /* velocity-block preconditioner: STOKES_VEL_CHEB or STOKES_VEL_MG */
-  int32_t arnoldi_fp64;   /* STOKES_MIXED coupled solves: 0 = the FGMRES basis and
-                             K_gamma products run in FP32 inside the FP64
-                             refinement (each sweep asks a 1e-5 reduction of its
-                             own FP64 residual); 1 = FP64 basis and K_gamma
-                             products, only the preconditioner in FP32.  Ignored
-                             for STOKES_FP64 and the Schur method. */
+  int32_t arnoldi_fp64;   /* STOKES_MIXED coupled solves (each refinement sweep
+                             asks a 1e-5 reduction of its own FP64 residual):
+                             STOKES_ARNOLDI_FP32 = FGMRES basis, Gram-Schmidt
+                             updates and K_gamma products in FP32 (sums in FP64);
+                             STOKES_ARNOLDI_FP64 (default) = basis and
+                             orthogonalization in FP64, K_gamma products with
+                             the FP32 matrices; STOKES_ARNOLDI_FP64_K = also
+                             K_gamma in FP64.  Ignored for STOKES_FP64 and the
+                             Schur method. */
 } stokes_solve_opts;
 
 typedef struct {

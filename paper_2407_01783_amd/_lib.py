@@ -23,6 +23,7 @@ CC_LAPLACE, CC_LUMPED, CC_MASS = 0, 1, 2
 PC_FULL, PC_UPPER, PC_LOWER = 0, 1, 2
 FLAG_STRAIN = 1
 VEL_CHEB, VEL_MG = 0, 1
+ARNOLDI_FP32, ARNOLDI_FP64, ARNOLDI_FP64_K = 0, 1, 2
 
 
 class StokesError(RuntimeError):

@@ -76,7 +76,7 @@ void check_opts(const stokes_solve_opts* o) {
   if (o->inner_its_u < 0 || o->inner_its_u > 1000 || o->inner_its_p < 0 || o->inner_its_p > 1000)
     throw Error(STOKES_ERR_ARG, "inner_its_u / inner_its_p must be in [0, 1000]");
   if (o->vel_pc != STOKES_VEL_CHEB && o->vel_pc != STOKES_VEL_MG) throw Error(STOKES_ERR_ARG, "vel_pc");
-  if (o->arnoldi_fp64 != 0 && o->arnoldi_fp64 != 1) throw Error(STOKES_ERR_ARG, "arnoldi_fp64 must be 0 or 1");
+  if (o->arnoldi_fp64 < 0 || o->arnoldi_fp64 > 2) throw Error(STOKES_ERR_ARG, "arnoldi_fp64 must be 0, 1 or 2");
 }
 
 template <class F>
@@ -377,6 +377,7 @@ void stokes_default_opts(stokes_solve_opts* o) {
   o->coupled_pc = STOKES_PC_FULL;
   o->max_refine = 8;
   o->profile = 0;
+  o->arnoldi_fp64 = STOKES_ARNOLDI_FP64;
 }
 
 const char* stokes_last_error(void) { return g_last_error.c_str(); }

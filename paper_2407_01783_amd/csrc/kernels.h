@@ -1356,12 +1356,13 @@ __global__ __launch_bounds__(kBlock) void k_mupdate(int64_t n_int, int64_t n_p1,
 //   partial dots V_i . w of the stored w, for i < nb <= kFusedMax,
 // written in k_mdot's partial layout (chunk i / 8, slot i mod 8) with the same
 // row mapping and block reduction, so k_mdot_fin gives the same sums as a
-// separate k_mdot pass.  One read of the basis instead of two.
+// separate k_mdot pass.  One read of the basis instead of two.  w is read
+// from win (TI, may be w itself) and written in TW.
 constexpr int kFusedMax = 8;
-template <typename TV, typename TW, int D, int NRB>
+template <typename TV, typename TW, int D, int NRB, typename TI = TW>
 __global__ __launch_bounds__(kBlock) void k_mupdate_dot(int64_t n_int, int64_t n_p1, const TV* __restrict__ V,
                                                         int64_t ldv, int nb, const double* __restrict__ h,
-                                                        TW* __restrict__ w, double* __restrict__ part) {
+                                                        const TI* win, TW* w, double* __restrict__ part) {
   constexpr int W = D * NRB, CH = kMdotChunk, NM = kFusedMax;
   __shared__ double hs[NM * NRB];
   for (int i = threadIdx.x; i < nb * NRB; i += blockDim.x) hs[i] = -h[i];
@@ -1378,7 +1379,7 @@ __global__ __launch_bounds__(kBlock) void k_mupdate_dot(int64_t n_int, int64_t n
       double a[D];
       TV v[NM][D];
 #pragma unroll
-      for (int d = 0; d < D; ++d) a[d] = (double)w[o + d];
+      for (int d = 0; d < D; ++d) a[d] = (double)win[o + d];
 #pragma unroll
       for (int i = 0; i < NM; ++i)
         if (i < nb) {
@@ -1410,7 +1411,7 @@ __global__ __launch_bounds__(kBlock) void k_mupdate_dot(int64_t n_int, int64_t n
     } else {
       const int64_t o = nv + (t - n_int) * NRB + sub;
       TV v[NM];
-      double a = (double)w[o];
+      double a = (double)win[o];
 #pragma unroll
       for (int i = 0; i < NM; ++i)
         if (i < nb) v[i] = V[(int64_t)i * ldv + o];
@@ -1440,16 +1441,20 @@ __global__ __launch_bounds__(kBlock) void k_mupdate_dot(int64_t n_int, int64_t n
   }
 }
 
-// v = s[r] * w  (coupled vectors, per right-hand-side scale)
-template <typename TS, int D, int NRB>
+// v = s[r] * w  (coupled vectors, per right-hand-side scale); vf (optional)
+// receives the same values rounded to TF
+template <typename TS, int D, int NRB, typename TF = TS>
 __global__ __launch_bounds__(kBlock) void k_scale_coupled(int64_t n_int, int64_t n_p1, Coef8 s,
-                                                          const TS* __restrict__ w, TS* __restrict__ v) {
+                                                          const TS* __restrict__ w, TS* __restrict__ v,
+                                                          TF* __restrict__ vf) {
   constexpr int W = D * NRB;
   const int64_t nv = n_int * W;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv + n_p1 * NRB;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int r = i < nv ? (int)((i % W) / D) : (int)((i - nv) % NRB);
-    v[i] = (TS)(s.v[r] * (double)w[i]);
+    const TS x = (TS)(s.v[r] * (double)w[i]);
+    v[i] = x;
+    if (vf) vf[i] = (TF)x;
   }
 }
 

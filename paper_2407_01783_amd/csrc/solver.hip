@@ -502,7 +502,7 @@ class Engine {
   int fgmres_cycle(const double* ru, const double* rp, double* xu, double* xp, const std::vector<double>& target,
                    int max_steps) {
     if constexpr (std::is_same<T, float>::value) {
-      if (!o_.arnoldi_fp64) return fgmres_cycle_t<float>(ru, rp, xu, xp, target, max_steps);
+      if (o_.arnoldi_fp64 == STOKES_ARNOLDI_FP32) return fgmres_cycle_t<float>(ru, rp, xu, xp, target, max_steps);
     }
     return fgmres_cycle_t<double>(ru, rp, xu, xp, target, max_steps);
   }
@@ -527,10 +527,11 @@ class Engine {
     double* yhost = static_cast<double*>(c_->workspace_host("gm_yh", 64 * 8 * sizeof(double)));
     double* ydev = static_cast<double*>(c_->workspace("gm_y", 64 * 8 * sizeof(double)));
 
-    auto mdot = [&](const TK* Vb, int nb, const TK* x, double* hout) {
+    auto mdot = [&](const TK* Vb, int nb, const auto* x, double* hout) {
+      using TX = std::remove_const_t<std::remove_pointer_t<decltype(x)>>;
       dispatch_dn(D_, nrb_, [&](auto Dc, auto Nc) {
         constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
-        hipLaunchKernelGGL((k_mdot<TK, TK, D, N>), dim3(nbx, (nb + kMdotChunk - 1) / kMdotChunk), dim3(kBlock), 0,
+        hipLaunchKernelGGL((k_mdot<TK, TX, D, N>), dim3(nbx, (nb + kMdotChunk - 1) / kMdotChunk), dim3(kBlock), 0,
                            c_->stream, c_->n_int, c_->n_p1, Vb, nc, nb, x, part);
         ops::check_launch();
         hipLaunchKernelGGL((k_mdot_fin<N>), dim3(nb), dim3(kBlock), 0, c_->stream, nbx, (const double*)part, hout);
@@ -556,13 +557,16 @@ class Engine {
       });
       ops::check_launch();
     };
+    // the preconditioner's input v_j in T: the basis itself, or a rounded
+    // copy written by the scaling that forms v_j
+    T* vin = std::is_same<T, TK>::value ? nullptr : buf("gm_vin", nc);
     auto scale_into = [&](const std::vector<double>& s, const TK* src, TK* dst) {
       Coef8 cs{};
       for (int r = 0; r < 8; ++r) cs.v[r] = r < nrb_ ? s[r] : 0;
       dispatch_dn(D_, nrb_, [&](auto Dc, auto Nc) {
         constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
-        hipLaunchKernelGGL((k_scale_coupled<TK, D, N>), dim3(ops::grid_for(nc)), dim3(kBlock), 0, c_->stream,
-                           c_->n_int, c_->n_p1, cs, src, dst);
+        hipLaunchKernelGGL((k_scale_coupled<TK, D, N, T>), dim3(ops::grid_for(nc)), dim3(kBlock), 0, c_->stream,
+                           c_->n_int, c_->n_p1, cs, src, dst, vin);
       });
       ops::check_launch();
     };
@@ -602,43 +606,54 @@ class Engine {
       if constexpr (std::is_same<T, TK>::value) {
         vsrc = Vj;
       } else {
-        T* vin = buf("gm_vin", nc);
-        ops::cast<TK, T>(c_, nc, Vj, vin);
         vsrc = vin;
       }
-      // with the upper triangular preconditioner in the Krylov precision the
-      // product B^T z_p of the preconditioner is reused by K_gamma z_j
-      const bool reuse_bt = std::is_same<T, TK>::value && o_.coupled_pc == STOKES_PC_UPPER && gamma_ == 0;
+      // K_gamma z_j in the inner precision T (the FP32 matrices) unless the
+      // FP64 operator is asked for
+      const bool k_inner = std::is_same<T, TK>::value || o_.arnoldi_fp64 != STOKES_ARNOLDI_FP64_K;
+      // with the upper triangular preconditioner the product B^T z_p of the
+      // preconditioner is reused by K_gamma z_j
+      const bool reuse_bt = k_inner && o_.coupled_pc == STOKES_PC_UPPER && gamma_ == 0;
       T* bt = reuse_bt ? buf("gm_bt", nu()) : nullptr;
       block_prec(vsrc, vsrc + nu(), Zj, Zj + nu(), bt);
-      const TK* zsrc;
+      // w = K_gamma z_j
+      auto k_apply_inner = [&](T* out) {
+        if (reuse_bt) {
+          ops::velop<T>(c_, nrb_, Zj, out, (T)1, bt, (T)-1);             // A z_u - B^T z_p
+          ops::Bmul<T>(c_, nrb_, Zj, out + nu(), (T)1, nullptr, (T)0);  // B z_u
+        } else {
+          coupled_apply<T>(Zj, Zj + nu(), out, out + nu(), true);
+        }
+      };
+      T* wk = nullptr;  // K_gamma z_j in T, read by the first Gram-Schmidt pass
       if constexpr (std::is_same<T, TK>::value) {
-        zsrc = Zj;
+        k_apply_inner(w);
+      } else if (k_inner) {
+        wk = buf("gm_wk", nc);
+        k_apply_inner(wk);
+        if (j + 1 > kFusedMax) {
+          ops::cast<T, TK>(c_, nc, wk, w);
+          wk = nullptr;
+        }
       } else {
         TK* zk = static_cast<TK*>(c_->workspace(std::string("gm_zk") + kt, nc * sizeof(TK)));
         ops::cast<T, TK>(c_, nc, Zj, zk);
-        zsrc = zk;
-      }
-      // w = K_gamma z_j
-      if constexpr (std::is_same<T, TK>::value) {
-        if (reuse_bt) {
-          ops::velop<TK>(c_, nrb_, zsrc, w, (TK)1, bt, (TK)-1);          // A z_u - B^T z_p
-          ops::Bmul<TK>(c_, nrb_, zsrc, w + nu(), (TK)1, nullptr, (TK)0);  // B z_u
-        } else {
-          coupled_apply<TK>(zsrc, zsrc + nu(), w, w + nu(), true);
-        }
-      } else {
-        coupled_apply<TK>(zsrc, zsrc + nu(), w, w + nu(), true);
+        coupled_apply<TK>(zk, zk + nu(), w, w + nu(), true);
       }
       // CGS2 (the first update and the second projection share one pass
       // over the basis while it holds at most kFusedMax vectors)
       const double t0 = now();
-      mdot(V, j + 1, w, h1);
+      if (wk) mdot(V, j + 1, (const T*)wk, h1);
+      else mdot(V, j + 1, (const TK*)w, h1);
       if (j + 1 <= kFusedMax) {
         dispatch_dn(D_, nrb_, [&](auto Dc, auto Nc) {
           constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
-          hipLaunchKernelGGL((k_mupdate_dot<TK, TK, D, N>), dim3(nbx), dim3(kBlock), 0, c_->stream, c_->n_int,
-                             c_->n_p1, (const TK*)V, nc, j + 1, (const double*)h1, w, part);
+          if (wk)
+            hipLaunchKernelGGL((k_mupdate_dot<TK, TK, D, N, T>), dim3(nbx), dim3(kBlock), 0, c_->stream, c_->n_int,
+                               c_->n_p1, (const TK*)V, nc, j + 1, (const double*)h1, (const T*)wk, w, part);
+          else
+            hipLaunchKernelGGL((k_mupdate_dot<TK, TK, D, N>), dim3(nbx), dim3(kBlock), 0, c_->stream, c_->n_int,
+                               c_->n_p1, (const TK*)V, nc, j + 1, (const double*)h1, (const TK*)w, w, part);
           ops::check_launch();
           hipLaunchKernelGGL((k_mdot_fin<N>), dim3(j + 1), dim3(kBlock), 0, c_->stream, nbx, (const double*)part, h2);
         });

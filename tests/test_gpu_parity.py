@@ -350,10 +350,11 @@ def test_batched_matches_single_and_mixed(gpu_lib):
 
 
 @pytest.mark.parametrize("gamma", [0.0, 10.0])
-@pytest.mark.parametrize("arnoldi_fp64", [0, 1])
+@pytest.mark.parametrize("arnoldi_fp64", [0, 1, 2])
 def test_mixed_fgmres_arnoldi_precisions(gpu_lib, gamma, arnoldi_fp64):
-    # mixed coupled solves with the Arnoldi basis and K_gamma products in FP32
-    # (default) or FP64 reach the same FP64 solution through the refinement
+    # mixed coupled solves in the three Arnoldi modes (FP32 basis and K_gamma;
+    # FP64 basis and orthogonalization with FP32 K_gamma, the default; FP64
+    # basis and K_gamma) reach the same FP64 solution through the refinement
     kw = dict(dim=3, n=4, seed=9, mu=1e-2, alpha=100.0)
     P, S = _problem(gamma=gamma, **kw), _oracle(**kw)
     fs = np.stack([inputs.fourier_forcing(S.mesh.p2coords, inputs.forcing_seed(9, b)) for b in range(2)])
