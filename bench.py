@@ -162,8 +162,8 @@ def main():
 
     def run(precision, steps, warmup, profile, **over):
         o = dict(opts, **over)
-        for _ in range(warmup):
-            prob.solve(f, method=method, precision=precision, **o)
+        for _ in range(warmup):  # same options as the timed solves (profiling events are created here)
+            prob.solve(f, method=method, precision=precision, profile=profile, **o)
         torch.cuda.synchronize()
         infos = []
         t = time.perf_counter()

@@ -113,7 +113,8 @@ typedef struct {
   int32_t schur_pc;       /* STOKES_CC_* */
   int32_t coupled_pc;     /* STOKES_PC_* */
   int32_t max_refine;     /* cap on iterative-refinement sweeps */
-  int32_t profile;        /* 1: time the dominant SpMV with HIP events */
+  int32_t profile;        /* 1: time the dominant SpMV with HIP events (one
+                             launch in eight, on the solver's stream) */
   int32_t inner_its_u;    /* > 0: every inner velocity CG runs exactly this many
                              iterations (no convergence checks); 0: use inner_rtol_u */
   int32_t inner_its_p;    /* the same for the inner pressure CG (0: inner_rtol_p) */
@@ -135,7 +136,7 @@ typedef struct {
   int32_t inner_iters_u;  /* inner velocity CG iterations (all solves) */
   int32_t inner_iters_p;  /* inner pressure CG iterations */
   int32_t refinements;    /* sweeps of the refinement loop */
-  int32_t spmv_launches;  /* launches of the timed SpMV (profile = 1) */
+  int32_t spmv_launches;  /* timed launches of the dominant SpMV (profile = 1) */
   double rel_res;         /* max over right-hand sides of the final true residual */
   double seconds_total;   /* wall time of the call */
   double spmv_seconds;    /* summed duration of the timed SpMV launches */

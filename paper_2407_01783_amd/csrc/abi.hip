@@ -143,6 +143,7 @@ double wall() {
 void prof_start(stokes_ctx* c, const stokes_solve_opts* o) {
   c->prof_on = o->profile ? 1 : 0;
   c->prof_idx = 0;
+  c->prof_seen = 0;
   if (c->prof_on && c->prof_ev.empty()) {
     c->prof_ev.resize(16384);
     for (auto& pr : c->prof_ev) {

@@ -241,7 +241,7 @@ struct stokes_ctx {
   stokes::DevBuf ones64, ones32;  // n_p1 * 8 ones (pressure sums)
 
   // timing of the dominant SpMV (opts.profile): event pairs, read at the end
-  int prof_on = 0, prof_idx = 0;
+  int prof_on = 0, prof_idx = 0, prof_seen = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
   double prof_bytes = 0;
 
