@@ -673,6 +673,11 @@ class Engine {
         }
         for (int i = 0; i <= j; ++i) Hat(i, j, r) = hhost[i * R + r] + hhost[64 * 8 + i * R + r];
         const double hn = std::sqrt(std::max(0.0, hhost[2 * 64 * 8 + r]));
+        if (log_level() >= 2) {
+          double hs = hn * hn;
+          for (int i = 0; i <= j; ++i) hs += Hat(i, j, r) * Hat(i, j, r);
+          std::fprintf(stderr, "[stokes] arnoldi j=%d r=%d |w_perp|/|w| = %.3e\n", j, r, hn / std::sqrt(hs));
+        }
         // apply previous rotations, then a new one
         for (int i = 0; i < j; ++i) {
           const double a = Hat(i, j, r), b = Hat(i + 1, j, r);
