@@ -114,7 +114,7 @@ typedef struct {
   int32_t coupled_pc;     /* STOKES_PC_* */
   int32_t max_refine;     /* cap on iterative-refinement sweeps */
   int32_t profile;        /* 1: time the dominant SpMV with HIP events (one
-                             launch in eight, on the solver's stream) */
+                             launch in seven, on the solver's stream) */
   int32_t inner_its_u;    /* > 0: every inner velocity CG runs exactly this many
                              iterations (no convergence checks); 0: use inner_rtol_u */
   int32_t inner_its_p;    /* the same for the inner pressure CG (0: inner_rtol_p) */

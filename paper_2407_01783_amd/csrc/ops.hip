@@ -27,9 +27,10 @@ const float* pick<float>(const DevBuf&, const DevBuf& b32) {
 
 // Timing of the dominant kernel (the velocity-block SpMV) with HIP events on
 // the context stream; events are read back at the end of the solve.  One
-// launch in kProfStride is bracketed (every launch does the same work), so
-// the event records add little to the timed solve.
-constexpr int kProfStride = 8;
+// launch in kProfStride is bracketed (every launch does the same work; the
+// stride is prime to the 4 steps of one polynomial, so the samples rotate
+// over its positions), so the event records add little to the timed solve.
+constexpr int kProfStride = 7;
 bool prof_begin(stokes_ctx* c, const Sell* S, const void* vals, const void* avals) {
   if (!c->prof_on || S != &c->sA || vals != avals) return false;
   if (c->prof_seen++ % kProfStride != 0) return false;
