@@ -1304,13 +1304,18 @@ __global__ __launch_bounds__(kBlock) void k_mdot_fin(int nblk, const double* __r
 
 // w += sgn * sum_{i<nb} h[i][r] V_i (accumulated in FP64, stored in TW);
 // NORM: res[r] = ||w_r||^2 of the stored values
-template <typename TV, typename TW, int D, int NRB, int NORM>
+// sig2 (optional): per basis vector and right-hand side, a factor on h (the
+// squared scale of a basis stored unnormalized); wf (optional): the stored w
+// again, rounded to TF.
+template <typename TV, typename TW, int D, int NRB, int NORM, typename TF = TW>
 __global__ __launch_bounds__(kBlock) void k_mupdate(int64_t n_int, int64_t n_p1, const TV* __restrict__ V,
                                                     int64_t ldv, int nb, const double* __restrict__ h, double sgn,
-                                                    TW* __restrict__ w, double* res, double* partials) {
+                                                    TW* __restrict__ w, double* res, double* partials,
+                                                    const double* __restrict__ sig2 = nullptr,
+                                                    TF* __restrict__ wf = nullptr) {
   constexpr int W = D * NRB;
   __shared__ double hs[64 * NRB];
-  for (int i = threadIdx.x; i < nb * NRB; i += blockDim.x) hs[i] = sgn * h[i];
+  for (int i = threadIdx.x; i < nb * NRB; i += blockDim.x) hs[i] = sgn * h[i] * (sig2 ? sig2[i] : 1.0);
   __syncthreads();
   const int sub = (int)(threadIdx.x % NRB);
   const int64_t nv = n_int * W;
@@ -1332,6 +1337,7 @@ __global__ __launch_bounds__(kBlock) void k_mupdate(int64_t n_int, int64_t n_p1,
       for (int d = 0; d < D; ++d) {
         const TW st = (TW)a[d];
         w[o + d] = st;
+        if (wf) wf[o + d] = (TF)st;
         if (NORM) part += (double)st * (double)st;
       }
     } else {
@@ -1340,6 +1346,7 @@ __global__ __launch_bounds__(kBlock) void k_mupdate(int64_t n_int, int64_t n_p1,
       for (int i = 0; i < nb; ++i) a += hs[i * NRB + sub] * (double)V[(int64_t)i * ldv + o];
       const TW st = (TW)a;
       w[o] = st;
+      if (wf) wf[o] = (TF)st;
       if (NORM) part += (double)st * (double)st;
     }
   }
@@ -1362,10 +1369,11 @@ constexpr int kFusedMax = 8;
 template <typename TV, typename TW, int D, int NRB, typename TI = TW>
 __global__ __launch_bounds__(kBlock) void k_mupdate_dot(int64_t n_int, int64_t n_p1, const TV* __restrict__ V,
                                                         int64_t ldv, int nb, const double* __restrict__ h,
-                                                        const TI* win, TW* w, double* __restrict__ part) {
+                                                        const TI* win, TW* w, double* __restrict__ part,
+                                                        const double* __restrict__ sig2 = nullptr) {
   constexpr int W = D * NRB, CH = kMdotChunk, NM = kFusedMax;
   __shared__ double hs[NM * NRB];
-  for (int i = threadIdx.x; i < nb * NRB; i += blockDim.x) hs[i] = -h[i];
+  for (int i = threadIdx.x; i < nb * NRB; i += blockDim.x) hs[i] = -h[i] * (sig2 ? sig2[i] : 1.0);
   __syncthreads();
   const int sub = (int)(threadIdx.x % NRB);
   const int64_t nv = n_int * W;

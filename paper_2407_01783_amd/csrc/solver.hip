@@ -538,21 +538,24 @@ class Engine {
       });
       ops::check_launch();
     };
-    auto mupdate = [&](auto* Vb, int nb, const double* h, double sgn, auto* x, double* res) {
+    auto mupdate = [&](auto* Vb, int nb, const double* h, double sgn, auto* x, double* res,
+                       const double* sig2 = nullptr, T* wf = nullptr) {
       using TV = std::remove_const_t<std::remove_pointer_t<decltype(Vb)>>;
       using TW = std::remove_pointer_t<decltype(x)>;
       dispatch_dn(D_, nrb_, [&](auto Dc, auto Nc) {
         constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
         if (res) {
-          hipLaunchKernelGGL((k_mupdate<TV, TW, D, N, 1>), dim3(nbx), dim3(kBlock), 0, c_->stream, c_->n_int,
-                             c_->n_p1, (const TV*)Vb, nc, nb, h, sgn, x, res, c_->red.partials.as<double>());
+          hipLaunchKernelGGL((k_mupdate<TV, TW, D, N, 1, T>), dim3(nbx), dim3(kBlock), 0, c_->stream, c_->n_int,
+                             c_->n_p1, (const TV*)Vb, nc, nb, h, sgn, x, res, c_->red.partials.as<double>(), sig2,
+                             wf);
           ops::check_launch();
           hipLaunchKernelGGL((k_finish<N>), dim3(1), dim3(kBlock), 0, c_->stream,
                              (const double*)c_->red.partials.as<double>(), nbx, (int)FIN_STORE, N, (Scalars*)nullptr,
                              1, 0, 0, res);
         } else {
-          hipLaunchKernelGGL((k_mupdate<TV, TW, D, N, 0>), dim3(nbx), dim3(kBlock), 0, c_->stream, c_->n_int,
-                             c_->n_p1, (const TV*)Vb, nc, nb, h, sgn, x, res, c_->red.partials.as<double>());
+          hipLaunchKernelGGL((k_mupdate<TV, TW, D, N, 0, T>), dim3(nbx), dim3(kBlock), 0, c_->stream, c_->n_int,
+                             c_->n_p1, (const TV*)Vb, nc, nb, h, sgn, x, res, c_->red.partials.as<double>(), sig2,
+                             wf);
         }
       });
       ops::check_launch();
@@ -593,6 +596,19 @@ class Engine {
       g[0 * R + r] = beta[r];
     }
     scale_into(s, w, V);
+    // The basis after v_0 is kept unnormalized: column i holds v_i / sig[i]
+    // (sig per right-hand side, on the host; its square on the device for
+    // the Gram-Schmidt coefficients).  Each new column is left where the
+    // second update writes it, which saves a scaling pass per step; the
+    // Hessenberg entries, the norms and the solution coefficients carry sig.
+    std::vector<double> sig((m + 1) * R, 0.0);
+    double* sig2host = static_cast<double*>(c_->workspace_host("gm_s2h", 64 * 8 * sizeof(double)));
+    double* sig2dev = static_cast<double*>(c_->workspace("gm_s2", 64 * 8 * sizeof(double)));
+    for (int r = 0; r < R; ++r) {
+      sig[r] = active[r] ? 1.0 : 0.0;
+      sig2host[r] = sig[r];
+    }
+    HIP_CHECK(hipMemcpyAsync(sig2dev, sig2host, R * sizeof(double), hipMemcpyHostToDevice, c_->stream));
     auto Hat = [&](int i, int j, int r) -> double& { return H[((size_t)i * m + j) * R + r]; };
     int j = 0;
     for (; j < m; ++j) {
@@ -601,6 +617,7 @@ class Engine {
       if (!any) break;
       TK* Vj = V + (int64_t)j * nc;
       T* Zj = Z + (int64_t)j * nc;
+      TK* wj = V + (int64_t)(j + 1) * nc;  // K_gamma z_j, orthogonalized in place: the next column
       // z_j = P^{-1} v_j in the inner precision
       const T* vsrc;
       if constexpr (std::is_same<T, TK>::value) {
@@ -627,52 +644,59 @@ class Engine {
       };
       T* wk = nullptr;  // K_gamma z_j in T, read by the first Gram-Schmidt pass
       if constexpr (std::is_same<T, TK>::value) {
-        k_apply_inner(w);
+        k_apply_inner(wj);
       } else if (k_inner) {
         wk = buf("gm_wk", nc);
         k_apply_inner(wk);
         if (j + 1 > kFusedMax) {
-          ops::cast<T, TK>(c_, nc, wk, w);
+          ops::cast<T, TK>(c_, nc, wk, wj);
           wk = nullptr;
         }
       } else {
         TK* zk = static_cast<TK*>(c_->workspace(std::string("gm_zk") + kt, nc * sizeof(TK)));
         ops::cast<T, TK>(c_, nc, Zj, zk);
-        coupled_apply<TK>(zk, zk + nu(), w, w + nu(), true);
+        coupled_apply<TK>(zk, zk + nu(), wj, wj + nu(), true);
       }
       // CGS2 (the first update and the second projection share one pass
       // over the basis while it holds at most kFusedMax vectors)
       const double t0 = now();
       if (wk) mdot(V, j + 1, (const T*)wk, h1);
-      else mdot(V, j + 1, (const TK*)w, h1);
+      else mdot(V, j + 1, (const TK*)wj, h1);
       if (j + 1 <= kFusedMax) {
         dispatch_dn(D_, nrb_, [&](auto Dc, auto Nc) {
           constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
           if (wk)
             hipLaunchKernelGGL((k_mupdate_dot<TK, TK, D, N, T>), dim3(nbx), dim3(kBlock), 0, c_->stream, c_->n_int,
-                               c_->n_p1, (const TK*)V, nc, j + 1, (const double*)h1, (const T*)wk, w, part);
+                               c_->n_p1, (const TK*)V, nc, j + 1, (const double*)h1, (const T*)wk, wj, part,
+                               (const double*)sig2dev);
           else
             hipLaunchKernelGGL((k_mupdate_dot<TK, TK, D, N>), dim3(nbx), dim3(kBlock), 0, c_->stream, c_->n_int,
-                               c_->n_p1, (const TK*)V, nc, j + 1, (const double*)h1, (const TK*)w, w, part);
+                               c_->n_p1, (const TK*)V, nc, j + 1, (const double*)h1, (const TK*)wj, wj, part,
+                               (const double*)sig2dev);
           ops::check_launch();
           hipLaunchKernelGGL((k_mdot_fin<N>), dim3(j + 1), dim3(kBlock), 0, c_->stream, nbx, (const double*)part, h2);
         });
         ops::check_launch();
       } else {
-        mupdate(V, j + 1, h1, -1.0, w, nullptr);
-        mdot(V, j + 1, w, h2);
+        mupdate(V, j + 1, h1, -1.0, wj, nullptr, sig2dev);
+        mdot(V, j + 1, wj, h2);
       }
-      mupdate(V, j + 1, h2, -1.0, w, nrm);
+      // the second update also leaves the next preconditioner input (in T)
+      mupdate(V, j + 1, h2, -1.0, wj, nrm, sig2dev, vin);
       HIP_CHECK(hipMemcpyAsync(hhost, hdev, 3 * 64 * 8 * sizeof(double), hipMemcpyDeviceToHost, c_->stream));
       HIP_CHECK(hipStreamSynchronize(c_->stream));
       st_.seconds_orth += now() - t0;
+      bool dropped = false;  // a right-hand side stopped while others go on
       for (int r = 0; r < R; ++r) {
         if (!active[r]) {
           s[r] = 0;
           continue;
         }
-        for (int i = 0; i <= j; ++i) Hat(i, j, r) = hhost[i * R + r] + hhost[64 * 8 + i * R + r];
-        const double hn = std::sqrt(std::max(0.0, hhost[2 * 64 * 8 + r]));
+        const double sj = sig[j * R + r];
+        for (int i = 0; i <= j; ++i)
+          Hat(i, j, r) = sj * sig[i * R + r] * (hhost[i * R + r] + hhost[64 * 8 + i * R + r]);
+        const double wn = std::sqrt(std::max(0.0, hhost[2 * 64 * 8 + r]));
+        const double hn = sj * wn;
         if (log_level() >= 2) {
           double hs = hn * hn;
           for (int i = 0; i <= j; ++i) hs += Hat(i, j, r) * Hat(i, j, r);
@@ -695,10 +719,21 @@ class Engine {
         kdone[r] = j + 1;
         const double est = std::fabs(g[(j + 1) * R + r]);
         if (est <= target[r] || hn <= 1e-300) active[r] = 0;
-        s[r] = (active[r] && hn > 0) ? 1.0 / hn : 0.0;
+        s[r] = active[r] && wn > 0 ? 1.0 : 0.0;
+        sig[(j + 1) * R + r] = active[r] && wn > 0 ? 1.0 / wn : 0.0;
+        dropped = dropped || !active[r];
       }
       st_.outer += 1;
-      if (j + 1 < m) scale_into(s, w, V + (int64_t)(j + 1) * nc);
+      if (j + 1 < m) {
+        bool any_left = false;
+        for (int r = 0; r < R; ++r) any_left = any_left || active[r];
+        // zero the finished right-hand sides' part of the new column (it
+        // would otherwise grow unnormalized through the later steps)
+        if (dropped && any_left) scale_into(s, wj, wj);
+        for (int r = 0; r < R; ++r) sig2host[(j + 1) * R + r] = sig[(j + 1) * R + r] * sig[(j + 1) * R + r];
+        HIP_CHECK(hipMemcpyAsync(sig2dev + (j + 1) * R, sig2host + (j + 1) * R, R * sizeof(double),
+                                 hipMemcpyHostToDevice, c_->stream));
+      }
     }
     // y = H^{-1} g per right-hand side; x += Z y
     const int steps = j;
@@ -712,6 +747,8 @@ class Engine {
       }
     }
     if (steps > 0) {
+      for (int i = 0; i < steps; ++i)
+        for (int r = 0; r < R; ++r) yhost[i * R + r] *= sig[i * R + r];  // z_i = sig_i P(stored column i)
       HIP_CHECK(hipMemcpyAsync(ydev, yhost, steps * R * sizeof(double), hipMemcpyHostToDevice, c_->stream));
       // x is the concatenation (xu, xp) only when contiguous; update both parts
       double* xc = static_cast<double*>(c_->workspace("gm_x", nc * sizeof(double)));
