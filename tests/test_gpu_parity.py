@@ -369,6 +369,27 @@ def test_mixed_fgmres_arnoldi_precisions(gpu_lib, gamma, arnoldi_fp64):
         assert _rel(p[b].cpu().numpy(), Pp) <= 1e-8
 
 
+@pytest.mark.parametrize("arnoldi_fp64", [0, 1])
+def test_batched_mixed_with_zero_and_scaled_rhs(gpu_lib, arnoldi_fp64):
+    # right-hand sides that finish at different FGMRES steps (a zero one from
+    # the start, a tiny one, a regular one) in one batched mixed solve: each
+    # matches the oracle, the zero one exactly, the scaled one by linearity
+    kw = dict(dim=3, n=4, seed=10, mu=1e-2, alpha=100.0)
+    P, S = _problem(**kw), _oracle(**kw)
+    f0 = inputs.fourier_forcing(S.mesh.p2coords, inputs.forcing_seed(10, 0))
+    f1 = inputs.fourier_forcing(S.mesh.p2coords, inputs.forcing_seed(10, 1))
+    fs = np.stack([f0, np.zeros_like(f0), 1e-6 * f1])
+    u, p, info = P.solve(torch.tensor(fs, device="cuda"), method="coupled", precision=1, rtol=1e-10,
+                         arnoldi_fp64=arnoldi_fp64, max_outer=2000, max_refine=30)
+    assert info["status"] == 0, info
+    assert float(u[1].abs().max()) == 0.0 and float(p[1].abs().max()) == 0.0
+    for b, fb in ((0, f0), (2, 1e-6 * f1)):
+        F, g = S.rhs(fb)
+        U, Pp = S.solve(F, g)
+        assert _rel(u[b].cpu().numpy(), S.full_velocity(U)) <= 1e-8, b
+        assert _rel(p[b].cpu().numpy(), Pp) <= 1e-8, b
+
+
 def test_warm_start_and_zero_rhs(gpu_lib):
     kw = dict(dim=3, n=3, seed=0, mu=1.0, alpha=100.0)
     P, S = _problem(**kw), _oracle(**kw)
