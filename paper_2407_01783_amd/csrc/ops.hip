@@ -14,6 +14,14 @@ int grid_for(int64_t rows) {
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nb, kMaxBlocks)));
 }
 
+// One row (group) per thread and as many workgroups as that takes (a multiple
+// of 8 for the XCD partition): the dispatcher then balances rows of
+// different lengths across the CUs instead of a fixed grid-stride share.
+int grid_full(int64_t rows) {
+  const int64_t nb = (rows + kBlock - 1) / kBlock;
+  return static_cast<int>(std::max<int64_t>(8, std::min<int64_t>((nb + 7) / 8 * 8, int64_t(1) << 24)));
+}
+
 void check_launch() { HIP_CHECK(hipGetLastError()); }
 
 template <>
@@ -171,7 +179,7 @@ void spmv_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, int W, const 
     constexpr int WW = decltype(Wc)::value;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
-      hipLaunchKernelGGL((k_spmv<T, WW, GG, TM>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0, c->stream,
+      hipLaunchKernelGGL((k_spmv<T, WW, GG, TM>), dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream,
                          S.nrows, S.idx(), vals, x, y, (T)(a * ms), yin, b);
     });
   });
@@ -194,7 +202,7 @@ void Bmul(stokes_ctx* c, int nrb, const T* u, T* p, T a, const T* pin, T b) {
   const Sell& S = c->sB;
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
     constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
-    hipLaunchKernelGGL((k_B<T, D, N>), dim3(grid_for(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
+    hipLaunchKernelGGL((k_B<T, D, N>), dim3(grid_full(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows,
                        S.idx(), bvals<T>(c).template as<T>(), u, p, a, pin, b);
   });
   check_launch();
@@ -208,7 +216,7 @@ void Btmul(stokes_ctx* c, int nrb, const T* p, const T* scale, T* u, T a, const 
     constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
     with_g<D * N>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
-      hipLaunchKernelGGL((k_Bt<T, D, N, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows,
+      hipLaunchKernelGGL((k_Bt<T, D, N, GG>), dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows,
                          S.idx(), btvals<T>(c).template as<T>(), p, scale, u,
                          a, uin, b, btout);
     });
@@ -225,7 +233,7 @@ void velop(stokes_ctx* c, int nrb, const T* x, T* y, T a, const T* yin, T b) {
   if (!c->strain) return spmv<T>(c, c->sA, avals<T>(c).template as<T>(), c->dim * nrb, x, y, a, yin, b);
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
     constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
-    hipLaunchKernelGGL((k_spmv_blk<T, D, N>), dim3(grid_for(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int,
+    hipLaunchKernelGGL((k_spmv_blk<T, D, N>), dim3(grid_full(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int,
                        c->sA.idx(), abvals<T>(c).template as<T>(), x, y, a, yin, b);
   });
   check_launch();
@@ -236,7 +244,7 @@ void momentum(stokes_ctx* c, int nrb, const T* u, const T* p, const T* extra, T*
   if (c->strain) {
     dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
       constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
-      hipLaunchKernelGGL((k_momentum_blk<T, D, N>), dim3(grid_for(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int,
+      hipLaunchKernelGGL((k_momentum_blk<T, D, N>), dim3(grid_full(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int,
                          c->sA.idx(), abvals<T>(c).template as<T>(), c->sBt.idx(), btvals<T>(c).template as<T>(), u,
                          p, extra, y, sgn, yin);
     });
@@ -248,7 +256,7 @@ void momentum(stokes_ctx* c, int nrb, const T* u, const T* p, const T* extra, T*
     constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
     with_g<D * N>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
-      hipLaunchKernelGGL((k_momentum<T, D, N, GG>), dim3(grid_for(c->n_int * GG)), dim3(kBlock), 0, c->stream,
+      hipLaunchKernelGGL((k_momentum<T, D, N, GG>), dim3(grid_full(c->n_int * GG)), dim3(kBlock), 0, c->stream,
                          c->n_int, c->sA.idx(), avals<T>(c).template as<T>(), c->sBt.idx(),
                          btvals<T>(c).template as<T>(), u, p, extra, y, sgn, yin);
     });
@@ -394,7 +402,7 @@ void cheb_first_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, const T
     constexpr int WW = decltype(Wc)::value;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
-      const int nb = grid_for(S.nrows * GG);
+      const int nb = grid_full(S.nrows * GG);
       auto go = [&](auto kern, const TM* v) {
         hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, S.nrows, S.idx(), v, ms, r, dinv, theta_inv,
                            d1, res, z, c1, c2);
@@ -434,7 +442,7 @@ void cheb_first_h(stokes_ctx* c, int W, const float* r, const float* dinv, float
     constexpr int WW = decltype(Wc)::value;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
-      hipLaunchKernelGGL((k_cheb_first_q<float, _Float16, WW, 0, GG, 8>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0,
+      hipLaunchKernelGGL((k_cheb_first_q<float, _Float16, WW, 0, GG, 8>), dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0,
                          c->stream, S.nrows, S.idx(),
                          (const _Float16*)c->AD16.as<_Float16>(), r, dinv, theta_inv, q1, res, z, c1, c2);
     });
@@ -450,7 +458,8 @@ void cheb_first_hb(stokes_ctx* c, int W, const float* r, const float* dinv, floa
     constexpr int WW = decltype(Wc)::value;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
-      hipLaunchKernelGGL((k_cheb_first_qb<_Float16, WW, 0, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0,
+      hipLaunchKernelGGL((k_cheb_first_qb<_Float16, WW, 0, GG>),
+                         dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0,
                          c->stream, S.nrows, S.idx(), (const _Float16*)c->AD16.as<_Float16>(), r, dinv, theta_inv,
                          q1, res, z, c1, c2);
     });
@@ -469,7 +478,8 @@ void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const f
     wp = bf_width<WW>();
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
-      hipLaunchKernelGGL((k_cheb_step_qb<_Float16, WW, GG>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0,
+      hipLaunchKernelGGL((k_cheb_step_qb<_Float16, WW, GG>),
+                         dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0,
                          c->stream, S.nrows, S.idx(), (const _Float16*)c->AD16.as<_Float16>(), q, qn, res_in,
                          res_out, z, dinv, c1, c2);
     });
@@ -493,7 +503,7 @@ void cheb_step_h(stokes_ctx* c, int W, const float* q, float* qn, const float* r
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows, S.idx(),
+        hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows, S.idx(),
                            (const _Float16*)c->AD16.as<_Float16>(), q, qn, res_in, res_out, z, dinv, c1, c2);
       };
       go(k_cheb_step_q<float, _Float16, WW, GG, 8>);
@@ -513,7 +523,7 @@ void cheb_step_hs(stokes_ctx* c, const Sell& S, const _Float16* vals, float ms, 
     constexpr int WW = decltype(Wc)::value;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
-      hipLaunchKernelGGL((k_cheb_step<float, WW, 0, GG, _Float16>), dim3(grid_for(S.nrows * GG)), dim3(kBlock), 0,
+      hipLaunchKernelGGL((k_cheb_step<float, WW, 0, GG, _Float16>), dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0,
                          c->stream, S.nrows, S.idx(), vals, ms, d, dn, res_in, res_out, z, dinv, c1, c2,
                          (const float*)nullptr, (Scalars*)nullptr, 1, 0, 0, partials(c));
     });
@@ -538,7 +548,7 @@ void cheb_step(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* d, T
                            c2, rvec, sc, cps, nsys, first, partials(c));
         finish<WW>(c, S.nrows * GG, FIN_RHO, WW, sc, cps, nsys, first, nullptr);
       } else
-        hipLaunchKernelGGL((k_cheb_step<T, WW, 0, GG>), dim3(nb), dim3(kBlock), 0, c->stream, S.nrows,
+        hipLaunchKernelGGL((k_cheb_step<T, WW, 0, GG>), dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows,
                            S.idx(), vals, (T)1, d, dn, res_in, res_out, z, dinv, c1,
                            c2, rvec, sc, cps, nsys, first, partials(c));
     });
