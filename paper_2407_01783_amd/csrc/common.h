@@ -71,6 +71,7 @@ struct Sell {
   int64_t packed_slices = 0;
   double idx_bytes = 0;  // bytes of the column-index structure streamed by one product
   int planes = 1;       // values per entry (B and B^T carry dim planes)
+  int es = 1;           // lanes sharing a row in the scalar products (1: one lane per row; tuned per MG level)
   DevBuf slice_ptr;     // int64 [nslices + 1]
   DevBuf cols;          // int32 [nnz_pad]
   DevBuf src;           // int32 [nnz_pad] source entry in the assembled CSR (-1 = pad)
@@ -216,6 +217,7 @@ struct stokes_ctx {
   // coarse levels P^T A P
   stokes::MgHier mgq, mgx;
   int mg_smooth_degree = 2, mg_coarse_degree = 24;
+  int mg_es = 1;                        // tune entry-split lanes per pressure-MG level (0: one lane per row)
   int64_t mg_dense_max = 1500;          // largest level solved densely
   double mg_smooth_ratio = 10.0;
   int use_mgx = 1;                      // lumped CC: precondition with mgx (0: mgq)

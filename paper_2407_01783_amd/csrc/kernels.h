@@ -140,8 +140,9 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ pa
 // in one slice (an aligned group of 64 / G rows), so the slice index is read
 // from the first active lane and the form is a uniform branch.
 //
-// Entries of a row are walked four at a time so that eight matrix loads and
-// 4 W/G gathers are in flight per lane.
+// Entries of a row are walked U at a time (U = 4, or 8 when a lane carries
+// at most two components) so that 2U matrix loads and U W/G gathers are in
+// flight per lane.
 struct SliceRef {
   int64_t beg;  // entry 0 of the row
   int64_t eb;   // first slot of the slice (index into cbase)
@@ -385,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, SellIdx ix, cons
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<T, W, G, TM>(ix, vals, x, row, sub, acc);
+    sell_row<T, W, G, TM, (W / G <= 2 ? 8 : 4)>(ix, vals, x, row, sub, acc);
     const int64_t o = row * W + sub * WG;
     // yin may alias y: every load of the row is issued before its stores
     T yi[WG];
@@ -393,6 +394,146 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, SellIdx ix, cons
     for (int w = 0; w < WG; ++w) yi[w] = b != T(0) ? yin[o + w] : T(0);
 #pragma unroll
     for (int w = 0; w < WG; ++w) y[o + w] = fma(b, yi[w], a * acc[w]);
+  }
+}
+
+// ------------------------------------------------ entry-split SELL rows
+//
+// Operators with few but long rows (the coarse levels of the pressure
+// multigrid: a two-ring stencil of some 60-130 entries on a few thousand
+// rows) leave too few wavefronts in flight when one lane walks a whole row,
+// and each lane then waits on a long chain of dependent gathers.  Here E
+// lanes share a row (E in {2, 4, 8, 16}): lane `sub` of the group takes the
+// slots sub, sub + E, sub + 2E, ... and accumulates every component of
+// them; a butterfly of lane exchanges then leaves the row sums in every lane
+// of the group (each exchange adds the same two values in both lanes, so all
+// E lanes hold the same bits).  A wavefront holds 64 / E consecutive rows
+// starting at a multiple of 64 / E, so they share one slice.
+template <typename T, int W, int E, typename TM, bool PK, bool DS, int U>
+__device__ __forceinline__ void sell_row_es_impl(const SellIdx& ix, const SliceRef& r, const TM* __restrict__ vals,
+                                                 const T* __restrict__ x, const T* __restrict__ ds, int sub,
+                                                 T (&acc)[W]) {
+  int j = sub;
+  for (; j + E * (U - 1) < r.width; j += E * U) {
+    int32_t c[U];
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[u] = sell_col<PK>(ix, r, j + E * u);
+      v[u] = (T)__builtin_nontemporal_load(vals + r.beg + 64 * (j + E * u));
+    }
+    if constexpr (DS) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] *= ds[c[u]];
+    }
+    T xv[U][W];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int w = 0; w < W; ++w) xv[u][w] = x[(int64_t)c[u] * W + w];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int w = 0; w < W; ++w) acc[w] = fma(v[u], xv[u][w], acc[w]);
+  }
+  for (; j < r.width; j += E) {
+    const int32_t c = sell_col<PK>(ix, r, j);
+    T v = (T)__builtin_nontemporal_load(vals + r.beg + 64 * j);
+    if constexpr (DS) v *= ds[c];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = fma(v, x[(int64_t)c * W + w], acc[w]);
+  }
+}
+
+// acc = sum over the row's entries of v_j x[c_j][0..W) (v_j ds[c_j] when ds
+// is given), in every lane of the row group.
+template <typename T, int W, int E, typename TM>
+__device__ __forceinline__ void sell_row_es(const SellIdx& ix, const TM* __restrict__ vals, const T* __restrict__ x,
+                                            int64_t row, int sub, T (&acc)[W], const T* __restrict__ ds = nullptr) {
+  constexpr int U = W <= 2 ? 8 : 4;
+  const SliceRef r = slice_ref(ix, row);
+  if (ds) {
+    if (r.pk) sell_row_es_impl<T, W, E, TM, true, true, U>(ix, r, vals, x, ds, sub, acc);
+    else sell_row_es_impl<T, W, E, TM, false, true, U>(ix, r, vals, x, ds, sub, acc);
+  } else {
+    if (r.pk) sell_row_es_impl<T, W, E, TM, true, false, U>(ix, r, vals, x, ds, sub, acc);
+    else sell_row_es_impl<T, W, E, TM, false, false, U>(ix, r, vals, x, ds, sub, acc);
+  }
+#pragma unroll
+  for (int o = E / 2; o >= 1; o /= 2)
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] += __shfl_xor(acc[w], o);
+}
+
+// Entry-split forms of k_spmv, k_cheb_first (column scaling gathered) and
+// k_cheb_step (no fused dot): the same arithmetic per row; lane `sub` of a
+// row group stores the components w with w mod E == sub.
+template <typename T, int W, int E, typename TM = T>
+__global__ __launch_bounds__(kBlock) void k_spmv_es(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
+                                                    const T* __restrict__ x, T* y, T a, const T* yin, T b) {
+  XCD_ROWS_G(row, sub, nrows, E) {
+    T acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = 0;
+    sell_row_es<T, W, E, TM>(ix, vals, x, row, sub, acc);
+    const int64_t o = row * W;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      if (w % E != sub) continue;
+      const T yi = b != T(0) ? yin[o + w] : T(0);
+      y[o + w] = fma(b, yi, a * acc[w]);
+    }
+  }
+}
+
+template <typename T, int W, int ACC, int E, typename TM = T>
+__global__ __launch_bounds__(kBlock) void k_cheb_first_es(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
+                                                          T ms, const T* __restrict__ r, const T* __restrict__ dinv,
+                                                          T theta_inv, T* __restrict__ d1, T* __restrict__ res,
+                                                          T* __restrict__ z, T c1, T c2) {
+  XCD_ROWS_G(row, sub, nrows, E) {
+    T acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = 0;
+    sell_row_es<T, W, E, TM>(ix, vals, r, row, sub, acc, dinv);
+    const T di = dinv[row];
+    const int64_t o = row * W;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      if (w % E != sub) continue;
+      const int64_t i = o + w;
+      const T d0 = theta_inv * di * r[i];
+      const T rs = r[i] - theta_inv * (ms * acc[w]);
+      res[i] = rs;
+      const T dnv = fma(c1, d0, c2 * di * rs);
+      d1[i] = dnv;
+      z[i] = ACC ? z[i] + (d0 + dnv) : d0 + dnv;
+    }
+  }
+}
+
+template <typename T, int W, int E, typename TM = T>
+__global__ __launch_bounds__(kBlock) void k_cheb_step_es(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
+                                                         T ms, const T* __restrict__ d, T* __restrict__ dn,
+                                                         const T* res_in, T* res_out, T* __restrict__ z,
+                                                         const T* __restrict__ dinv, T c1, T c2) {
+  XCD_ROWS_G(row, sub, nrows, E) {
+    T acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = 0;
+    sell_row_es<T, W, E, TM>(ix, vals, d, row, sub, acc);
+    const T di = c2 * dinv[row];
+    const int64_t o = row * W;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      if (w % E != sub) continue;
+      // res_in may alias res_out: this lane alone reads and then writes o + w
+      const T rs = res_in[o + w] - ms * acc[w];
+      res_out[o + w] = rs;
+      const T dnew = fma(c1, d[o + w], di * rs);
+      dn[o + w] = dnew;
+      z[o + w] += dnew;
+    }
   }
 }
 
@@ -518,7 +659,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, SellIdx ix,
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<T, W, G, TM>(ix, vals, d, row, sub, acc);
+    sell_row<T, W, G, TM, (W / G <= 2 ? 8 : 4)>(ix, vals, d, row, sub, acc);
     const T di = c2 * dinv[row];
     const int64_t o = row * W + sub * WG;
     // res_in may alias res_out: load the whole row before any store
@@ -562,7 +703,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, SellIdx ix
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<T, W, G, TM>(ix, vals, r, row, sub, acc, SC ? nullptr : dinv);
+    sell_row<T, W, G, TM, (W / G <= 2 ? 8 : 4)>(ix, vals, r, row, sub, acc, SC ? nullptr : dinv);
     const T di = dinv[row];
     const int64_t o = row * W + sub * WG;
 #pragma unroll

@@ -19,6 +19,7 @@
 //     vertices, else a Chebyshev polynomial over its whole spectrum.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <memory>
 #include <type_traits>
 
@@ -292,6 +293,56 @@ static void dense_coarsest(stokes_ctx* c, MgHier& H) {
   H.dense_n = nr;
 }
 
+// Entry-split lanes per level (Sell::es): time the level product in the form
+// the FP32 V-cycle uses (half values when present) with E = 1, 2, 4, 8, 16
+// lanes per row and keep the fastest.  The coarse levels have a few thousand
+// rows of a two-ring stencil, where one lane per row leaves the chip idle.
+namespace {
+void tune_levels(stokes_ctx* c, MgHier& H) {
+  if (!c->mg_es) return;
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  for (auto& L : H.own) {
+    Sell& S = L->S;
+    if (S.nrows == 0) continue;
+    DevBuf x, y;
+    x.alloc(S.nrows * sizeof(float));
+    y.alloc(S.nrows * sizeof(float));
+    HIP_CHECK(hipMemsetAsync(x.p, 0, S.nrows * sizeof(float), c->stream));
+    const bool half = c->pmg_half && L->v16.p;
+    auto run = [&]() {
+      if (half)
+        ops::spmv_hs(c, S, L->v16.as<_Float16>(), L->s16, 1, x.as<float>(), y.as<float>(), 1.0f, nullptr, 0.0f);
+      else
+        ops::spmv<float>(c, S, L->v32.as<float>(), 1, x.as<float>(), y.as<float>(), 1.0f, nullptr, 0.0f);
+    };
+    int best = 1;
+    float best_ms = 1e30f;
+    for (int e : {1, 2, 4, 8, 16}) {
+      S.es = e;
+      run();  // warm-up
+      HIP_CHECK(hipEventRecord(e0, c->stream));
+      for (int rep = 0; rep < 5; ++rep) run();
+      HIP_CHECK(hipEventRecord(e1, c->stream));
+      HIP_CHECK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+      if (const char* ev = std::getenv("STOKES_LOG"); ev && std::atoi(ev) >= 1)
+        std::fprintf(stderr, "[stokes] mg level n=%d rows=%lld E=%d: %.1f us per product\n", L->n,
+                     (long long)S.nrows, e, 1e3 * ms / 5);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = e;
+      }
+    }
+    S.es = best;
+  }
+  HIP_CHECK(hipEventDestroy(e0));
+  HIP_CHECK(hipEventDestroy(e1));
+}
+}  // namespace
+
 // Build both hierarchies (called once per context after assembly).
 void build_mg(stokes_ctx* c) {
   MgHier& H = c->mgq;
@@ -328,6 +379,8 @@ void build_mg(stokes_ctx* c) {
   dense_coarsest(c, H);
   assemble_galerkin(c, c->mgx);
   dense_coarsest(c, c->mgx);
+  tune_levels(c, c->mgq);
+  tune_levels(c, c->mgx);
 }
 
 template <class T>

@@ -113,6 +113,26 @@ void with_g(int G, F&& f) {
   f(IC<1>{});
 }
 
+// Entry-split lanes E of a scalar operator (Sell::es, tuned per multigrid
+// level); compiled for the pressure widths W in {1, 2, 4, 8}.  Returns false
+// (nothing launched) for other E or W.
+template <int WW, class F>
+bool with_e(int E, F&& f) {
+  if constexpr (WW == 1 || WW == 2 || WW == 4 || WW == 8) {
+    switch (E) {
+      case 2: f(IC<2>{}); return true;
+      case 4: f(IC<4>{}); return true;
+      case 8: f(IC<8>{}); return true;
+      case 16: f(IC<16>{}); return true;
+      default: return false;
+    }
+  } else {
+    (void)E;
+    (void)f;
+    return false;
+  }
+}
+
 // Before tuning: the largest G leaving each lane at least 3 components.
 int heuristic_lanes(int W) {
   for (int g : {8, 4, 2})
@@ -177,6 +197,12 @@ void spmv_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, int W, const 
   const int G = lanes_op(c, &S, W, std::is_same<T, float>::value);
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
+    if (S.es > 1 && with_e<WW>(S.es, [&](auto Ec) {
+          constexpr int EE = decltype(Ec)::value;
+          hipLaunchKernelGGL((k_spmv_es<T, WW, EE, TM>), dim3(grid_full(S.nrows * EE)), dim3(kBlock), 0, c->stream,
+                             S.nrows, S.idx(), vals, x, y, (T)(a * ms), yin, b);
+        }))
+      return;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       hipLaunchKernelGGL((k_spmv<T, WW, GG, TM>), dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream,
@@ -400,6 +426,13 @@ void cheb_first_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, const T
   const int G = lanes_op(c, &S, W, std::is_same<T, float>::value);
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
+    if (!scaled && S.es > 1 && with_e<WW>(S.es, [&](auto Ec) {
+          constexpr int EE = decltype(Ec)::value;
+          auto kern = accumulate ? k_cheb_first_es<T, WW, 1, EE, TM> : k_cheb_first_es<T, WW, 0, EE, TM>;
+          hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows * EE)), dim3(kBlock), 0, c->stream, S.nrows, S.idx(), vals,
+                             ms, r, dinv, theta_inv, d1, res, z, c1, c2);
+        }))
+      return;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       const int nb = grid_full(S.nrows * GG);
@@ -521,6 +554,12 @@ void cheb_step_hs(stokes_ctx* c, const Sell& S, const _Float16* vals, float ms, 
   const int G = lanes_op(c, &S, W, true);
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
+    if (S.es > 1 && with_e<WW>(S.es, [&](auto Ec) {
+          constexpr int EE = decltype(Ec)::value;
+          hipLaunchKernelGGL((k_cheb_step_es<float, WW, EE, _Float16>), dim3(grid_full(S.nrows * EE)), dim3(kBlock),
+                             0, c->stream, S.nrows, S.idx(), vals, ms, d, dn, res_in, res_out, z, dinv, c1, c2);
+        }))
+      return;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       hipLaunchKernelGGL((k_cheb_step<float, WW, 0, GG, _Float16>), dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0,
@@ -539,6 +578,12 @@ void cheb_step(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* d, T
   const int G = lanes_op(c, &S, W, std::is_same<T, float>::value);
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
+    if (!rvec && S.es > 1 && with_e<WW>(S.es, [&](auto Ec) {
+          constexpr int EE = decltype(Ec)::value;
+          hipLaunchKernelGGL((k_cheb_step_es<T, WW, EE>), dim3(grid_full(S.nrows * EE)), dim3(kBlock), 0, c->stream,
+                             S.nrows, S.idx(), vals, (T)1, d, dn, res_in, res_out, z, dinv, c1, c2);
+        }))
+      return;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       const int nb = grid_for(S.nrows * GG);
