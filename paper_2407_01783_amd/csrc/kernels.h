@@ -12,6 +12,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace stokes {
@@ -140,9 +142,9 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ pa
 // in one slice (an aligned group of 64 / G rows), so the slice index is read
 // from the first active lane and the form is a uniform branch.
 //
-// Entries of a row are walked U at a time (U = 4, or 8 when a lane carries
-// at most two components) so that 2U matrix loads and U W/G gathers are in
-// flight per lane.
+// Entries of a row are walked U at a time (U = 4; 8 when a lane carries two
+// components, 16 when it carries one) so that 2U matrix loads and U W/G
+// gathers are in flight per lane.
 struct SliceRef {
   int64_t beg;  // entry 0 of the row
   int64_t eb;   // first slot of the slice (index into cbase)
@@ -170,42 +172,41 @@ __device__ __forceinline__ int32_t sell_col(const SellIdx& ix, const SliceRef& r
 }
 
 // acc += sum_j v_j x[c_j][sub W/G ...]; DS: v_j is multiplied by ds[c_j]
+// Groups of U entries, then groups of 4 (U > 4) and single entries for the
+// rest of the row, so short rows keep several loads in flight too.
 template <typename T, int W, int G, typename TM, bool PK, bool DS, int U = 4>
 __device__ __forceinline__ void sell_row_impl(const SellIdx& ix, const SliceRef& r, const TM* __restrict__ vals,
                                               const T* __restrict__ xs, const T* __restrict__ ds,
                                               T (&acc)[W / G]) {
   constexpr int WG = W / G;
-  int j = 0;
-  for (; j + U <= r.width; j += U) {
-    int32_t c[U];
-    T v[U];
+  auto group = [&](auto Uc, int j) {
+    constexpr int UU = decltype(Uc)::value;
+    int32_t c[UU];
+    T v[UU];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < UU; ++u) {
       c[u] = sell_col<PK>(ix, r, j + u);
       v[u] = (T)__builtin_nontemporal_load(vals + r.beg + 64 * (j + u));
     }
     if constexpr (DS) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) v[u] *= ds[c[u]];
+      for (int u = 0; u < UU; ++u) v[u] *= ds[c[u]];
     }
-    T xv[U][WG];
+    T xv[UU][WG];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int u = 0; u < UU; ++u)
 #pragma unroll
       for (int w = 0; w < WG; ++w) xv[u][w] = xs[(int64_t)c[u] * W + w];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int u = 0; u < UU; ++u)
 #pragma unroll
       for (int w = 0; w < WG; ++w) acc[w] = fma(v[u], xv[u][w], acc[w]);
-  }
-  for (; j < r.width; ++j) {
-    const int32_t c = sell_col<PK>(ix, r, j);
-    T v = (T)__builtin_nontemporal_load(vals + r.beg + 64 * j);
-    if constexpr (DS) v *= ds[c];
-    const T* xp = xs + (int64_t)c * W;
-#pragma unroll
-    for (int w = 0; w < WG; ++w) acc[w] = fma(v, xp[w], acc[w]);
-  }
+  };
+  int j = 0;
+  for (; j + U <= r.width; j += U) group(std::integral_constant<int, U>{}, j);
+  if constexpr (U > 4)
+    for (; j + 4 <= r.width; j += 4) group(std::integral_constant<int, 4>{}, j);
+  for (; j < r.width; ++j) group(std::integral_constant<int, 1>{}, j);
 }
 
 // TM is the storage type of the values (T, or _Float16 for a scaled copy);
@@ -386,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, SellIdx ix, cons
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<T, W, G, TM, (W / G <= 2 ? 8 : 4)>(ix, vals, x, row, sub, acc);
+    sell_row<T, W, G, TM, (W / G == 1 ? 16 : W / G <= 2 ? 8 : 4)>(ix, vals, x, row, sub, acc);
     const int64_t o = row * W + sub * WG;
     // yin may alias y: every load of the row is issued before its stores
     T yi[WG];
@@ -413,36 +414,34 @@ template <typename T, int W, int E, typename TM, bool PK, bool DS, int U>
 __device__ __forceinline__ void sell_row_es_impl(const SellIdx& ix, const SliceRef& r, const TM* __restrict__ vals,
                                                  const T* __restrict__ x, const T* __restrict__ ds, int sub,
                                                  T (&acc)[W]) {
-  int j = sub;
-  for (; j + E * (U - 1) < r.width; j += E * U) {
-    int32_t c[U];
-    T v[U];
+  auto group = [&](auto Uc, int j) {
+    constexpr int UU = decltype(Uc)::value;
+    int32_t c[UU];
+    T v[UU];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < UU; ++u) {
       c[u] = sell_col<PK>(ix, r, j + E * u);
       v[u] = (T)__builtin_nontemporal_load(vals + r.beg + 64 * (j + E * u));
     }
     if constexpr (DS) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) v[u] *= ds[c[u]];
+      for (int u = 0; u < UU; ++u) v[u] *= ds[c[u]];
     }
-    T xv[U][W];
+    T xv[UU][W];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int u = 0; u < UU; ++u)
 #pragma unroll
       for (int w = 0; w < W; ++w) xv[u][w] = x[(int64_t)c[u] * W + w];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int u = 0; u < UU; ++u)
 #pragma unroll
       for (int w = 0; w < W; ++w) acc[w] = fma(v[u], xv[u][w], acc[w]);
-  }
-  for (; j < r.width; j += E) {
-    const int32_t c = sell_col<PK>(ix, r, j);
-    T v = (T)__builtin_nontemporal_load(vals + r.beg + 64 * j);
-    if constexpr (DS) v *= ds[c];
-#pragma unroll
-    for (int w = 0; w < W; ++w) acc[w] = fma(v, x[(int64_t)c * W + w], acc[w]);
-  }
+  };
+  int j = sub;
+  for (; j + E * (U - 1) < r.width; j += E * U) group(std::integral_constant<int, U>{}, j);
+  if constexpr (U > 2)
+    for (; j + E < r.width; j += 2 * E) group(std::integral_constant<int, 2>{}, j);
+  for (; j < r.width; j += E) group(std::integral_constant<int, 1>{}, j);
 }
 
 // acc = sum over the row's entries of v_j x[c_j][0..W) (v_j ds[c_j] when ds
@@ -659,7 +658,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, SellIdx ix,
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<T, W, G, TM, (W / G <= 2 ? 8 : 4)>(ix, vals, d, row, sub, acc);
+    sell_row<T, W, G, TM, (W / G == 1 ? 16 : W / G <= 2 ? 8 : 4)>(ix, vals, d, row, sub, acc);
     const T di = c2 * dinv[row];
     const int64_t o = row * W + sub * WG;
     // res_in may alias res_out: load the whole row before any store
@@ -703,7 +702,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, SellIdx ix
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<T, W, G, TM, (W / G <= 2 ? 8 : 4)>(ix, vals, r, row, sub, acc, SC ? nullptr : dinv);
+    sell_row<T, W, G, TM, (W / G == 1 ? 16 : W / G <= 2 ? 8 : 4)>(ix, vals, r, row, sub, acc, SC ? nullptr : dinv);
     const T di = dinv[row];
     const int64_t o = row * W + sub * WG;
 #pragma unroll

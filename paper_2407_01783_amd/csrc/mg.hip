@@ -295,11 +295,16 @@ static void dense_coarsest(stokes_ctx* c, MgHier& H) {
 
 // Entry-split lanes per level (Sell::es): time the level product in the form
 // the FP32 V-cycle uses (half values when present) with E = 1, 2, 4, 8, 16
-// lanes per row and keep the fastest.  The coarse levels have a few thousand
+// lanes per row and keep the fastest (mg_es = 1), or set one E on every level
+// (mg_es in {2, 4, 8, 16}; 0 keeps one lane per row).  The coarse levels have a few thousand
 // rows of a two-ring stencil, where one lane per row leaves the chip idle.
 namespace {
 void tune_levels(stokes_ctx* c, MgHier& H) {
-  if (!c->mg_es) return;
+  if (c->mg_es == 0) return;
+  if (c->mg_es > 1) {  // a fixed E on every level
+    for (auto& L : H.own) L->S.es = c->mg_es;
+    return;
+  }
   hipEvent_t e0, e1;
   HIP_CHECK(hipEventCreate(&e0));
   HIP_CHECK(hipEventCreate(&e1));

@@ -305,10 +305,10 @@ template <class T>
 std::vector<double> dot_host(stokes_ctx* c, int64_t nrows, int W, const T* x, const T* y, const double* rw) {
   double* res = c->red.result.as<double>();
   dot_dev<T>(c, nrows, W, x, y, rw, res);
-  std::vector<double> h(W);
-  HIP_CHECK(hipMemcpyAsync(h.data(), res, W * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  double* hp = static_cast<double*>(c->workspace_host("dot_h", std::max(W, kMaxSys) * sizeof(double)));
+  HIP_CHECK(hipMemcpyAsync(hp, res, W * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_CHECK(hipStreamSynchronize(c->stream));
-  return h;
+  return std::vector<double>(hp, hp + W);
 }
 
 template <class T>

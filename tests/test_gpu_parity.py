@@ -129,6 +129,29 @@ def test_fp32_vcycle_half_values_close_and_contracting(gpu_lib):
     assert rates.max() <= 0.5, rates
 
 
+def test_entry_split_levels_match_one_lane_per_row(gpu_lib, monkeypatch):
+    """The Galerkin pressure V-cycle (op 8) with every level's products split
+    over E = 2, 4, 8, 16 lanes per row equals the one-lane-per-row cycle up to
+    the summation order: FP64 to 1e-12, FP32 (half-precision level values) to
+    1e-4, for one and two right-hand sides (3D n=32: SELL levels of 35,937
+    and 4,913 rows above the dense coarsest)."""
+    rng = np.random.default_rng(21)
+    outs = {}
+    for E in (0, 2, 4, 8, 16):
+        monkeypatch.setenv("STOKES_MG_ES", str(E))
+        P = _problem(3, 32, seed=5)
+        if E == 0:
+            xs = {r: rng.standard_normal(r * P.n_p1) for r in (1, 2)}
+        outs[E] = {(r, prec): P.apply(8, torch.tensor(xs[r], device="cuda"), precision=prec, nrhs=r).cpu().numpy()
+                   for r in (1, 2) for prec in (0, 1)}
+        del P
+    for E in (2, 4, 8, 16):
+        for (r, prec), y in outs[E].items():
+            err = _rel(y, outs[0][(r, prec)])
+            print(f"E={E} nrhs={r} precision={prec}: rel diff {err:.2e}", flush=True)
+            assert err <= (1e-12 if prec == 0 else 1e-4), (E, r, prec, err)
+
+
 @pytest.mark.parametrize("dim,n,nrhs", [(3, 4, 1), (3, 5, 2), (2, 12, 3)])
 def test_velocity_chebyshev_preconditioner_matches_closed_form(gpu_lib, dim, n, nrhs):
     """apply op 10 (the FIXED-mode velocity preconditioner, degree 6 on the
