@@ -910,20 +910,35 @@ void assemble_ctx(stokes_ctx* c) {
   std::vector<uint8_t> p2type(m.n_p2);
   for (int64_t v = 0; v < m.n_p2; ++v)
     p2type[v] = static_cast<uint8_t>((p2xyz[3 * v] & 1) + 2 * (p2xyz[3 * v + 1] & 1) + 4 * (p2xyz[3 * v + 2] & 1));
-  // stable bucket order by (slab, type), natural order inside a bucket
+  // Stable bucket order by (slab, block, type), natural order inside a
+  // bucket.  A block is `zblock` consecutive lattice planes of the slab (0:
+  // the whole slab; by default 4 planes once a plane holds more than 2^16
+  // nodes, else the whole slab): a kernel walks the rows of one type block
+  // by block, so the gathered neighbours (all types, the block's planes and
+  // one halo plane on each side) stay in the caches while the other types of
+  // the same block are walked.  On the large meshes with many right-hand
+  // sides a slab's worth of them does not (cube128 x 8: the bfloat16
+  // Chebyshev step 3.83 -> 3.53 ms); on smaller ones the blocks only cost.
   std::vector<int32_t> interior;
   {
-    std::vector<int64_t> start(65, 0);
-    std::vector<uint8_t> bucket(m.n_p2, 0);
+    const int64_t nK = n2 - 2;  // interior planes (3D) or lines (2D)
+    std::vector<int64_t> slab_lo(9);
+    for (int sl = 0; sl <= 8; ++sl) slab_lo[sl] = (sl * nK + 7) / 8;  // first K - 1 with slab >= sl
+    const int64_t zbk = c->zblock >= 0 ? c->zblock : (plane > (int64_t(1) << 16) ? 4 : 0);
+    const int64_t zb = zbk > 0 ? zbk : nK;
+    const int64_t nblk = (nK + zb - 1) / zb + 8;  // blocks per slab, bounded
+    std::vector<int64_t> start(8 * nblk * 8 + 1, 0);
+    std::vector<int32_t> bucket(m.n_p2, 0);
     for (int64_t v = 0; v < m.n_p2; ++v) {
       if (m.p2_bnd[v]) continue;
       const int64_t K = v / plane;  // 1 .. 2n-1 on interior nodes
-      const int64_t sl = std::min<int64_t>(7, (K - 1) * 8 / (n2 - 2));
-      bucket[v] = static_cast<uint8_t>(sl * 8 + p2type[v]);
+      const int64_t sl = std::min<int64_t>(7, (K - 1) * 8 / nK);
+      const int64_t blk = std::min<int64_t>(nblk - 1, (K - 1 - slab_lo[sl]) / zb);
+      bucket[v] = static_cast<int32_t>((sl * nblk + blk) * 8 + p2type[v]);
       ++start[bucket[v] + 1];
     }
-    for (int k = 0; k < 64; ++k) start[k + 1] += start[k];
-    interior.resize(start[64]);
+    for (size_t k = 0; k + 1 < start.size(); ++k) start[k + 1] += start[k];
+    interior.resize(start.back());
     for (int64_t v = 0; v < m.n_p2; ++v)
       if (!m.p2_bnd[v]) interior[start[bucket[v]]++] = static_cast<int32_t>(v);
   }

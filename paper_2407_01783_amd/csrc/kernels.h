@@ -827,35 +827,71 @@ __device__ __forceinline__ void load_bf(const uint16_t* __restrict__ xq, int64_t
   }
 }
 
+// Packed form of a gathered row: 32-bit words holding two bfloat16 values
+// each, unpacked only where the products use them, so that an unrolled group
+// keeps half as many registers in flight as with the values widened to FP32.
+template <int WP, int WG>
+struct BfRaw {
+  static constexpr bool kOn = (WP == 4 && WG >= 3) || (WG % 2 == 0 && WP % 2 == 0);
+  static constexpr int kWords = WP == 4 && WG >= 3 ? 2 : WG / 2;
+};
+
+template <int WP, int WG>
+__device__ __forceinline__ void load_bf_raw(const uint16_t* __restrict__ xq, int64_t c, int off,
+                                            uint32_t (&raw)[BfRaw<WP, WG>::kWords]) {
+  if constexpr (WP == 4 && WG >= 3) {
+    const uint2 u = *reinterpret_cast<const uint2*>(xq + c * 4);
+    raw[0] = u.x;
+    raw[1] = u.y;
+  } else {
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(xq + c * WP + off);
+#pragma unroll
+    for (int k = 0; k < WG / 2; ++k) raw[k] = p[k];
+  }
+}
+
+// component w of a packed row (the low half of a word is the even component)
+__device__ __forceinline__ float bf_word(uint32_t u, int hi) {
+  return __uint_as_float(hi ? (u & 0xFFFF0000u) : (u << 16));
+}
+
 template <int W, int G, typename TM, bool PK, int U>
 __device__ __forceinline__ void sell_row_bq_impl(const SellIdx& ix, const SliceRef& r, const TM* __restrict__ vals,
                                                  const uint16_t* __restrict__ xq, int off, float (&acc)[W / G]) {
   constexpr int WG = W / G, WP = bf_width<W>();
-  int j = 0;
-  for (; j + U <= r.width; j += U) {
-    int32_t c[U];
-    float v[U];
+  using Raw = BfRaw<WP, WG>;
+  auto group = [&](auto Uc, int j) {
+    constexpr int UU = decltype(Uc)::value;
+    int32_t c[UU];
+    float v[UU];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < UU; ++u) {
       c[u] = sell_col<PK>(ix, r, j + u);
       v[u] = (float)__builtin_nontemporal_load(vals + r.beg + 64 * (j + u));
     }
-    float xv[U][WG];
+    if constexpr (Raw::kOn) {
+      uint32_t xr[UU][Raw::kWords];
 #pragma unroll
-    for (int u = 0; u < U; ++u) load_bf<WP, WG>(xq, c[u], off, xv[u]);
+      for (int u = 0; u < UU; ++u) load_bf_raw<WP, WG>(xq, c[u], off, xr[u]);
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+      for (int u = 0; u < UU; ++u)
 #pragma unroll
-      for (int w = 0; w < WG; ++w) acc[w] = fma(v[u], xv[u][w], acc[w]);
-  }
-  for (; j < r.width; ++j) {
-    const int32_t c = sell_col<PK>(ix, r, j);
-    const float v = (float)__builtin_nontemporal_load(vals + r.beg + 64 * j);
-    float xv[WG];
-    load_bf<WP, WG>(xq, c, off, xv);
+        for (int w = 0; w < WG; ++w) acc[w] = fma(v[u], bf_word(xr[u][w / 2], w & 1), acc[w]);
+    } else {
+      float xv[UU][WG];
 #pragma unroll
-    for (int w = 0; w < WG; ++w) acc[w] = fma(v, xv[w], acc[w]);
-  }
+      for (int u = 0; u < UU; ++u) load_bf<WP, WG>(xq, c[u], off, xv[u]);
+#pragma unroll
+      for (int u = 0; u < UU; ++u)
+#pragma unroll
+        for (int w = 0; w < WG; ++w) acc[w] = fma(v[u], xv[u][w], acc[w]);
+    }
+  };
+  int j = 0;
+  for (; j + U <= r.width; j += U) group(std::integral_constant<int, U>{}, j);
+  if constexpr (U > 4)
+    for (; j + 4 <= r.width; j += 4) group(std::integral_constant<int, 4>{}, j);
+  for (; j < r.width; ++j) group(std::integral_constant<int, 1>{}, j);
 }
 
 // First step with a bfloat16 direction out:  q0 = theta_inv r (not stored),
@@ -871,7 +907,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first_qb(int64_t nrows, SellIdx
     float acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<float, W, G, TM, U>(ix, vals, r, row, sub, acc);
+    sell_row<float, W, G, TM, (W / G >= 8 ? 4 : U)>(ix, vals, r, row, sub, acc);
     const float di = dinv[row];
     const int64_t o = row * W + sub * WG, oq = row * WP + sub * WG;
 #pragma unroll
@@ -905,8 +941,11 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step_qb(int64_t nrows, SellIdx 
     for (int w = 0; w < WG; ++w) acc[w] = 0;
     {
       const SliceRef rf = slice_ref(ix, row);
-      if (rf.pk) sell_row_bq_impl<W, G, TM, true, U>(ix, rf, vals, q, sub * WG, acc);
-      else sell_row_bq_impl<W, G, TM, false, U>(ix, rf, vals, q, sub * WG, acc);
+      // wide lanes (8 or more components) take four entries per group: with
+      // eight, the gathered words alone hold most of the registers
+      constexpr int UB = WG >= 8 ? 4 : U;
+      if (rf.pk) sell_row_bq_impl<W, G, TM, true, UB>(ix, rf, vals, q, sub * WG, acc);
+      else sell_row_bq_impl<W, G, TM, false, UB>(ix, rf, vals, q, sub * WG, acc);
     }
     // res_in may alias res_out: load the whole row before any store
     float ri[WG], qq[WG], zz[WG];

@@ -133,17 +133,17 @@ def test_entry_split_levels_match_one_lane_per_row(gpu_lib, monkeypatch):
     """The Galerkin pressure V-cycle (op 8) with every level's products split
     over E = 2, 4, 8, 16 lanes per row equals the one-lane-per-row cycle up to
     the summation order: FP64 to 1e-12, FP32 (half-precision level values) to
-    1e-4, for one and two right-hand sides (3D n=32: SELL levels of 35,937
-    and 4,913 rows above the dense coarsest)."""
+    1e-4, for 1, 2, 4 and 8 right-hand sides (3D n=32: SELL levels of
+    35,937 and 4,913 rows above the dense coarsest)."""
     rng = np.random.default_rng(21)
     outs = {}
     for E in (0, 2, 4, 8, 16):
         monkeypatch.setenv("STOKES_MG_ES", str(E))
         P = _problem(3, 32, seed=5)
         if E == 0:
-            xs = {r: rng.standard_normal(r * P.n_p1) for r in (1, 2)}
+            xs = {r: rng.standard_normal(r * P.n_p1) for r in (1, 2, 4, 8)}
         outs[E] = {(r, prec): P.apply(8, torch.tensor(xs[r], device="cuda"), precision=prec, nrhs=r).cpu().numpy()
-                   for r in (1, 2) for prec in (0, 1)}
+                   for r in (1, 2, 4, 8) for prec in (0, 1)}
         del P
     for E in (2, 4, 8, 16):
         for (r, prec), y in outs[E].items():
