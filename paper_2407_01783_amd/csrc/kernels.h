@@ -1203,6 +1203,28 @@ __global__ __launch_bounds__(kBlock) void k_shift(int64_t nrows, T* x, const dou
   }
 }
 
+// dst[row][r] = src[row][r] - scale * (total of slot r over the block
+// partials of a k_dot): every workgroup adds the partials itself, in the same
+// fixed order, so all of them subtract the same bits and no separate
+// finishing kernel runs.  dst may alias src.
+template <typename T, int NRB>
+__global__ __launch_bounds__(kBlock) void k_shift_p(int64_t nrows, const T* src, T* dst,
+                                                    const double* __restrict__ partials, int nparts, double scale) {
+  double a[NRB];
+#pragma unroll
+  for (int r = 0; r < NRB; ++r) a[r] = 0;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) a[r] += partials[(size_t)b * NRB + r];
+  }
+  __shared__ double tot[NRB];
+  block_sum<NRB>(a, tot);
+  GRID_STRIDE_ROWS(row, nrows) {
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) dst[row * NRB + r] = src[row * NRB + r] - (T)(tot[r] * scale);
+  }
+}
+
 // ------------------------------------------------------- layout transfers
 
 // caller [nrb][D][n_p2] (double) -> internal [n_int][nrb][D] (T), interior only

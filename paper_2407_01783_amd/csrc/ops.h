@@ -65,6 +65,8 @@ std::vector<double> dot_host(stokes_ctx* c, int64_t nrows, int W, const T* x, co
 // x[row][r] -= mean over rows (l2 mean per right-hand side)
 template <class T>
 void remove_mean(stokes_ctx* c, int nrb, T* x);
+template <class T>
+void remove_mean_into(stokes_ctx* c, int nrb, const T* x, T* y);  // y = x - mean(x) per right-hand side
 // x[row][r] -= (m . x_r) / (m . 1) with m = M_Q 1 (zero pressure integral)
 template <class T>
 void normalize_pressure(stokes_ctx* c, int nrb, T* x);

@@ -313,16 +313,20 @@ std::vector<double> dot_host(stokes_ctx* c, int64_t nrows, int W, const T* x, co
 
 template <class T>
 void remove_mean(stokes_ctx* c, int nrb, T* x) {
-  double* res = c->red.result.as<double>() + kMaxSys;
+  remove_mean_into<T>(c, nrb, x, x);
+}
+
+template <class T>
+void remove_mean_into(stokes_ctx* c, int nrb, const T* x, T* y) {
   const T* ones = std::is_same<T, double>::value ? (const T*)c->ones64.p : (const T*)c->ones32.p;
+  const int nb = grid_for(c->n_p1);
   dispatch_w(nrb, [&](auto Nc) {
     constexpr int N = decltype(Nc)::value;
-    hipLaunchKernelGGL((k_dot<T, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1,
-                       (const T*)x, ones, (const double*)nullptr, res, partials(c));
-    finish<N>(c, c->n_p1, FIN_STORE, N, nullptr, 1, 0, 0, res);
+    hipLaunchKernelGGL((k_dot<T, N>), dim3(nb), dim3(kBlock), 0, c->stream, c->n_p1, x, ones,
+                       (const double*)nullptr, (double*)nullptr, partials(c));
     check_launch();
-    hipLaunchKernelGGL((k_shift<T, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1, x,
-                       (const double*)res, 1.0 / double(c->n_p1));
+    hipLaunchKernelGGL((k_shift_p<T, N>), dim3(nb), dim3(kBlock), 0, c->stream, c->n_p1, x, y,
+                       (const double*)partials(c), nb, 1.0 / double(c->n_p1));
   });
   check_launch();
 }
@@ -832,6 +836,7 @@ void adj_dJdmu(stokes_ctx* c, int nrb, const double* u_full, const double* lam, 
   template void dot_dev<T>(stokes_ctx*, int64_t, int, const T*, const T*, const double*, double*);                  \
   template std::vector<double> dot_host<T>(stokes_ctx*, int64_t, int, const T*, const T*, const double*);           \
   template void remove_mean<T>(stokes_ctx*, int, T*);                                                               \
+  template void remove_mean_into<T>(stokes_ctx*, int, const T*, T*);                                                \
   template void normalize_pressure<T>(stokes_ctx*, int, T*);                                                        \
   template void axpby<T>(stokes_ctx*, int64_t, T, const T*, T, T*);                                                 \
   template void axpy_sys<T>(stokes_ctx*, int64_t, int, int, const double*, double, const T*, T*);                   \

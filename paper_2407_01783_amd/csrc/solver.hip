@@ -415,8 +415,7 @@ class Engine {
   void cc_apply(const T* r, T* z) {
     T* y = buf("cc_y", np());
     T* rm = buf("cc_r", np());
-    HIP_CHECK(hipMemcpyAsync(rm, r, np() * sizeof(T), hipMemcpyDeviceToDevice, c_->stream));
-    ops::remove_mean<T>(c_, nrb_, rm);
+    ops::remove_mean_into<T>(c_, nrb_, r, rm);
     x_solve(rm, z);
     cheb_apply("ccq", c_->sQ, ops::pick<T>(c_->MQ64, c_->MQ32), ops::pick<T>(c_->dMQ64, c_->dMQ32), c_->bMQ,
                cc_mq_deg_, nrb_, rm, y);
