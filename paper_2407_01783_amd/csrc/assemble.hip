@@ -1130,6 +1130,7 @@ void assemble_ctx(stokes_ctx* c) {
   c->AD16.alloc(c->sA.nnz_pad * sizeof(_Float16));
   launch(c, c->sA.nnz_pad, k_scale_cols, c->sA.nnz_pad, c->sA.cols.as<int32_t>(), c->A64.as<double>(),
          c->dA64.as<double>(), c->AD64.as<double>(), c->AD32.as<float>(), c->AD16.as<_Float16>());
+  build_interleaved(c);
   if (c->strain) {
     c->AB64.alloc(c->sA.nnz_pad * (D * (D + 1) / 2) * sizeof(double));
     c->AB32.alloc(c->sA.nnz_pad * (D * (D + 1) / 2) * sizeof(float));
@@ -1183,6 +1184,29 @@ void assemble_ctx(stokes_ctx* c) {
   build_mg(c);
   phase("multigrid hierarchies");
   HIP_CHECK(hipStreamSynchronize(c->stream));
+}
+
+// Four-slot interleaved copies of the half-precision velocity values and of
+// the velocity pattern's column indices, read by the bfloat16 Chebyshev step.
+void build_interleaved(stokes_ctx* c) {
+  const Sell& S = c->sA;
+  if (!c->vel_il || !c->AD16.p || S.nslices == 0) return;
+  if (!c->AD16i.p) {
+    c->AD16i.alloc(S.nnz_pad * sizeof(_Float16));
+    if (S.cdel.p) {  // packed slices exist
+      c->cdel_i.alloc(S.nnz_pad * sizeof(uint8_t));
+      hipLaunchKernelGGL(k_interleave4<uint8_t>, dim3(S.nslices), dim3(64), 0, c->stream, S.nslices,
+                         S.slice_ptr.as<int64_t>(), S.cdel.as<uint8_t>(), c->cdel_i.as<uint8_t>());
+      HIP_CHECK(hipGetLastError());
+    }
+    c->cols_i.alloc(S.nnz_pad * sizeof(int32_t));
+    hipLaunchKernelGGL(k_interleave4<int32_t>, dim3(S.nslices), dim3(64), 0, c->stream, S.nslices,
+                       S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), c->cols_i.as<int32_t>());
+    HIP_CHECK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_interleave4<uint16_t>, dim3(S.nslices), dim3(64), 0, c->stream, S.nslices,
+                     S.slice_ptr.as<int64_t>(), c->AD16.as<uint16_t>(), c->AD16i.as<uint16_t>());
+  HIP_CHECK(hipGetLastError());
 }
 
 // M_Q + L_Q on a P1 mesh (a coarse level of the pressure multigrid).
@@ -1442,6 +1466,7 @@ void reform_A(stokes_ctx* c) {
   launch(c, c->n_int, k_cast<double, float>, c->n_int, c->dA64.as<double>(), c->dA32.as<float>());
   launch(c, n, k_scale_cols, n, c->sA.cols.as<int32_t>(), c->A64.as<double>(), c->dA64.as<double>(),
          c->AD64.as<double>(), c->AD32.as<float>(), c->AD16.as<_Float16>());
+  build_interleaved(c);
   if (c->strain)
     launch(c, n, k_fill_blk, n, c->dim, c->sA.src.as<int32_t>(), c->prob.alpha, c->prob.mu, c->M_full.as<double>(),
            c->L_full.as<double>(), c->D_full.as<double>(), c->AB64.as<double>(), c->AB32.as<float>());

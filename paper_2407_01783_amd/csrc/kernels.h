@@ -894,6 +894,108 @@ __device__ __forceinline__ void sell_row_bq_impl(const SellIdx& ix, const SliceR
   for (; j < r.width; ++j) group(std::integral_constant<int, 1>{}, j);
 }
 
+// Four-slot interleaved copy of a slice (the velocity Chebyshev step's
+// values and column indices): slots 4g .. 4g+3 of row r of a slice that
+// starts at entry s0 sit at s0 + 256 g + 4 r + (0..3), so one lane reads the
+// four values of a group with one 8-byte load and their packed column
+// offsets with one 4-byte load.  Slots from 4 floor(width / 4) on keep their
+// slot-major places (s0 + 64 j + r): the copy is a permutation inside each
+// slice, with the same slice pointers and column bases.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float half_bits(uint32_t h) {
+  return (float)__builtin_bit_cast(_Float16, static_cast<uint16_t>(h));
+}
+
+template <int W, int G, bool PK>
+__device__ __forceinline__ void sell_row_bq4_impl(const SellIdx& ix, const SliceRef& r,
+                                                  const _Float16* __restrict__ vals,
+                                                  const uint16_t* __restrict__ xq, int off, float (&acc)[W / G]) {
+  constexpr int WG = W / G, WP = bf_width<W>();
+  using Raw = BfRaw<WP, WG>;
+  static_assert(Raw::kOn, "interleaved rows take the packed bfloat16 gathers");
+  const int64_t s0 = r.eb << 6;
+  const int lr = static_cast<int>(r.beg - s0);
+  const int g4 = r.width >> 2;
+  // one group of four slots: values and columns, then the gathers
+  auto load = [&](int g, int32_t (&c)[4], float (&v)[4]) {
+    const int64_t e = s0 + 256 * (int64_t)g + 4 * lr;
+    const u32x2_t vv = __builtin_nontemporal_load(reinterpret_cast<const u32x2_t*>(vals + e));
+    v[0] = half_bits(vv.x & 0xFFFFu);
+    v[1] = half_bits(vv.x >> 16);
+    v[2] = half_bits(vv.y & 0xFFFFu);
+    v[3] = half_bits(vv.y >> 16);
+    if constexpr (PK) {
+      const uint32_t d4 = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(ix.cdel + e));
+#pragma unroll
+      for (int k = 0; k < 4; ++k) c[k] = ix.cbase[r.eb + 4 * g + k] + static_cast<int32_t>((d4 >> (8 * k)) & 0xFFu);
+    } else {
+      const i32x4_t cc = __builtin_nontemporal_load(reinterpret_cast<const i32x4_t*>(ix.cols + e));
+      c[0] = cc.x;
+      c[1] = cc.y;
+      c[2] = cc.z;
+      c[3] = cc.w;
+    }
+  };
+  int g = 0;
+  for (; g + 2 <= g4; g += 2) {
+    int32_t c[2][4];
+    float v[2][4];
+    load(g, c[0], v[0]);
+    load(g + 1, c[1], v[1]);
+    uint32_t xr[2][4][Raw::kWords];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) load_bf_raw<WP, WG>(xq, c[h][k], off, xr[h][k]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int w = 0; w < WG; ++w) acc[w] = fma(v[h][k], bf_word(xr[h][k][w / 2], w & 1), acc[w]);
+  }
+  if (g < g4) {
+    int32_t c[4];
+    float v[4];
+    load(g, c, v);
+    uint32_t xr[4][Raw::kWords];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) load_bf_raw<WP, WG>(xq, c[k], off, xr[k]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int w = 0; w < WG; ++w) acc[w] = fma(v[k], bf_word(xr[k][w / 2], w & 1), acc[w]);
+  }
+  // the remaining width mod 4 slots, slot-major
+  for (int j = 4 * g4; j < r.width; ++j) {
+    const int32_t c = sell_col<PK>(ix, r, j);
+    const float v = (float)__builtin_nontemporal_load(vals + r.beg + 64 * j);
+    uint32_t xr[Raw::kWords];
+    load_bf_raw<WP, WG>(xq, c, off, xr);
+#pragma unroll
+    for (int w = 0; w < WG; ++w) acc[w] = fma(v, bf_word(xr[w / 2], w & 1), acc[w]);
+  }
+}
+
+// Permute one scalar array of a sliced-ELL layout into the four-slot
+// interleaved order above (one workgroup of 64 threads per slice).
+template <typename E>
+__global__ __launch_bounds__(64) void k_interleave4(int64_t nslices, const int64_t* __restrict__ sp,
+                                                    const E* __restrict__ src, E* __restrict__ dst) {
+  const int64_t s = blockIdx.x;
+  if (s >= nslices) return;
+  const int64_t s0 = sp[s];
+  const int w = static_cast<int>((sp[s + 1] - s0) >> 6);
+  const int lr = threadIdx.x, g4 = w >> 2;
+  for (int j = 0; j < w; ++j) {
+    const int64_t from = s0 + 64 * (int64_t)j + lr;
+    const int64_t to = j < 4 * g4 ? s0 + 256 * (int64_t)(j >> 2) + 4 * lr + (j & 3) : from;
+    dst[to] = src[from];
+  }
+}
+
 // First step with a bfloat16 direction out:  q0 = theta_inv r (not stored),
 // res = r - (S D^{-1}) q0, q1 = bf16(c1 q0 + c2 res), z (+)= dinv (q0 + q1)
 template <typename TM, int W, int ACC, int G, int U = 8>
@@ -928,7 +1030,8 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first_qb(int64_t nrows, SellIdx
 }
 
 // Later steps:  res = res_in - (S D^{-1}) q ;  qn = bf16(c1 q + c2 res) ;  z += dinv qn
-template <typename TM, int W, int G, int U = 8>
+// IL: ix.cdel / ix.cols and vals are the four-slot interleaved copies.
+template <typename TM, int W, int G, int U = 8, bool IL = false>
 __global__ __launch_bounds__(kBlock) void k_cheb_step_qb(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
                                                          const uint16_t* __restrict__ q, uint16_t* __restrict__ qn,
                                                          const float* res_in, float* res_out, float* __restrict__ z,
@@ -944,8 +1047,13 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step_qb(int64_t nrows, SellIdx 
       // wide lanes (8 or more components) take four entries per group: with
       // eight, the gathered words alone hold most of the registers
       constexpr int UB = WG >= 8 ? 4 : U;
-      if (rf.pk) sell_row_bq_impl<W, G, TM, true, UB>(ix, rf, vals, q, sub * WG, acc);
-      else sell_row_bq_impl<W, G, TM, false, UB>(ix, rf, vals, q, sub * WG, acc);
+      if constexpr (IL) {
+        if (rf.pk) sell_row_bq4_impl<W, G, true>(ix, rf, vals, q, sub * WG, acc);
+        else sell_row_bq4_impl<W, G, false>(ix, rf, vals, q, sub * WG, acc);
+      } else {
+        if (rf.pk) sell_row_bq_impl<W, G, TM, true, UB>(ix, rf, vals, q, sub * WG, acc);
+        else sell_row_bq_impl<W, G, TM, false, UB>(ix, rf, vals, q, sub * WG, acc);
+      }
     }
     // res_in may alias res_out: load the whole row before any store
     float ri[WG], qq[WG], zz[WG];

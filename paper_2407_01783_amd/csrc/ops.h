@@ -11,6 +11,7 @@ namespace stokes {
 void assemble_ctx(stokes_ctx* c);
 void assemble_p1(stokes_ctx* c, const HostMesh& m, MgLevel& L);
 void build_mg(stokes_ctx* c);
+void build_interleaved(stokes_ctx* c);  // four-slot copies for the bfloat16 Chebyshev step
 // Galerkin hierarchy on B_I Lambda_V^-1 B_I^T + M_Q (levels only; the dense
 // coarsest inverse is added by build_mg)
 void assemble_galerkin(stokes_ctx* c, MgHier& H);

@@ -515,10 +515,20 @@ void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const f
     wp = bf_width<WW>();
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
-      hipLaunchKernelGGL((k_cheb_step_qb<_Float16, WW, GG>),
-                         dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0,
-                         c->stream, S.nrows, S.idx(), (const _Float16*)c->AD16.as<_Float16>(), q, qn, res_in,
-                         res_out, z, dinv, c1, c2);
+      const int nb = grid_full(S.nrows * GG);
+      if constexpr (BfRaw<bf_width<WW>(), WW / GG>::kOn) {
+        if (c->vel_il && c->AD16i.p) {  // the four-slot interleaved copies
+          SellIdx ix = S.idx();
+          ix.cdel = c->cdel_i.as<const uint8_t>();
+          ix.cols = c->cols_i.as<const int32_t>();
+          hipLaunchKernelGGL((k_cheb_step_qb<_Float16, WW, GG, 8, true>), dim3(nb), dim3(kBlock), 0, c->stream,
+                             S.nrows, ix, (const _Float16*)c->AD16i.as<_Float16>(), q, qn, res_in, res_out, z,
+                             dinv, c1, c2);
+          return;
+        }
+      }
+      hipLaunchKernelGGL((k_cheb_step_qb<_Float16, WW, GG>), dim3(nb), dim3(kBlock), 0, c->stream, S.nrows,
+                         S.idx(), (const _Float16*)c->AD16.as<_Float16>(), q, qn, res_in, res_out, z, dinv, c1, c2);
     });
   });
   check_launch();

@@ -152,6 +152,24 @@ def test_entry_split_levels_match_one_lane_per_row(gpu_lib, monkeypatch):
             assert err <= (1e-12 if prec == 0 else 1e-4), (E, r, prec, err)
 
 
+@pytest.mark.parametrize("dim,n,nrhs,lanes", [(3, 6, 1, 1), (3, 5, 8, 4), (2, 16, 1, 1), (2, 12, 4, 2)])
+def test_interleaved_chebyshev_step_bitwise_equal(gpu_lib, monkeypatch, dim, n, nrhs, lanes):
+    """The bfloat16 Chebyshev step reading the four-slot interleaved copies of
+    the half-precision values and column indices (the default) sums every row
+    in the same order as the slot-major form: apply op 10 is bitwise equal."""
+    monkeypatch.setenv("STOKES_LANES", str(lanes))
+    rng = np.random.default_rng(31)
+    outs = []
+    for il in ("0", "1"):
+        monkeypatch.setenv("STOKES_VEL_IL", il)
+        P = _problem(dim, n, seed=8, mu=0.05, alpha=100.0)
+        if not outs:
+            x = rng.standard_normal(nrhs * dim * P.n_p2)
+        outs.append(P.apply(10, torch.tensor(x, device="cuda"), precision=1, nrhs=nrhs).cpu().numpy())
+        del P
+    assert np.array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("dim,n,nrhs", [(3, 4, 1), (3, 5, 2), (2, 12, 3)])
 def test_velocity_chebyshev_preconditioner_matches_closed_form(gpu_lib, dim, n, nrhs):
     """apply op 10 (the FIXED-mode velocity preconditioner, degree 6 on the
