@@ -192,8 +192,9 @@ stokes_status solve_forward(stokes_ctx* c, int method, int32_t nrhs, const doubl
     const int64_t nu = c->n_int * D * nrb, np = c->n_p1 * nrb;
     double* F = static_cast<double*>(c->workspace("abi_F", nu * sizeof(double)));
     double* g = static_cast<double*>(c->workspace("abi_g", np * sizeof(double)));
-    double* xu = static_cast<double*>(c->workspace("abi_xu", nu * sizeof(double)));
-    double* xp = static_cast<double*>(c->workspace("abi_xp", np * sizeof(double)));
+    // (xu, xp) contiguous: the Krylov updates write the coupled vector in place
+    double* xu = static_cast<double*>(c->workspace("abi_x", (nu + np) * sizeof(double)));
+    double* xp = xu + nu;
     const int64_t vo = int64_t(r0) * D * c->n_p2, po = int64_t(r0) * c->n_p1;
     ops::rhs(c, nrb, f + vo, ubc ? ubc + vo : nullptr, F, g);
     ops::remove_mean<double>(c, nrb, g);
@@ -248,8 +249,9 @@ stokes_status projection_forward(stokes_ctx* c, int32_t nrhs, const double* f, c
     const int64_t nu = c->n_int * D * nrb, np = c->n_p1 * nrb;
     double* F = static_cast<double*>(c->workspace("abi_F", nu * sizeof(double)));
     double* g = static_cast<double*>(c->workspace("abi_g", np * sizeof(double)));
-    double* xu = static_cast<double*>(c->workspace("abi_xu", nu * sizeof(double)));
-    double* xp = static_cast<double*>(c->workspace("abi_xp", np * sizeof(double)));
+    // (xu, xp) contiguous: the Krylov updates write the coupled vector in place
+    double* xu = static_cast<double*>(c->workspace("abi_x", (nu + np) * sizeof(double)));
+    double* xp = xu + nu;
     double* po_int = nullptr;
     const int64_t vo = int64_t(r0) * D * c->n_p2, po = int64_t(r0) * c->n_p1;
     ops::rhs(c, nrb, f + vo, ubc ? ubc + vo : nullptr, F, g);
@@ -561,8 +563,8 @@ stokes_status stokes_solve_adjoint(stokes_ctx* c, int32_t nrhs, const double* u,
       const int64_t nu = c->n_int * D * nrb, np = c->n_p1 * nrb;
       double* F = static_cast<double*>(c->workspace("abi_F", nu * sizeof(double)));
       double* g = static_cast<double*>(c->workspace("abi_g", np * sizeof(double)));
-      double* xu = static_cast<double*>(c->workspace("abi_xu", nu * sizeof(double)));
-      double* xp = static_cast<double*>(c->workspace("abi_xp", np * sizeof(double)));
+      double* xu = static_cast<double*>(c->workspace("abi_x", (nu + np) * sizeof(double)));
+      double* xp = xu + nu;
       const int64_t vo = int64_t(r0) * D * c->n_p2, po = int64_t(r0) * c->n_p1;
       // j_u = dJ/dU on the interior; the pressure part is Pi^T dJdp with Pi the
       // zero-integral normalisation, then negated (lam_p -> -lam_p turns the

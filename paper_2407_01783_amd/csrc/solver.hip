@@ -573,15 +573,20 @@ class Engine {
       ops::check_launch();
     };
 
-    // V_0 = r / ||r||
+    // V_0 = r / ||r|| (read in place when (ru, rp) is one coupled vector)
+    const TK* w0 = w;
     if constexpr (std::is_same<TK, double>::value) {
-      HIP_CHECK(hipMemcpyAsync(w, ru, nu() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
-      HIP_CHECK(hipMemcpyAsync(w + nu(), rp, np() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+      if (rp == ru + nu()) {
+        w0 = ru;
+      } else {
+        HIP_CHECK(hipMemcpyAsync(w, ru, nu() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+        HIP_CHECK(hipMemcpyAsync(w + nu(), rp, np() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+      }
     } else {
       ops::cast<double, float>(c_, nu(), ru, w);
       ops::cast<double, float>(c_, np(), rp, w + nu());
     }
-    mdot(w, 1, w, h1);
+    mdot(w0, 1, w0, h1);
     HIP_CHECK(hipMemcpyAsync(hhost, h1, nrb_ * sizeof(double), hipMemcpyDeviceToHost, c_->stream));
     HIP_CHECK(hipStreamSynchronize(c_->stream));
     const int R = nrb_;
@@ -594,7 +599,7 @@ class Engine {
       s[r] = active[r] ? 1.0 / beta[r] : 0.0;
       g[0 * R + r] = beta[r];
     }
-    scale_into(s, w, V);
+    scale_into(s, w0, V);
     // The basis after v_0 is kept unnormalized: column i holds v_i / sig[i]
     // (sig per right-hand side, on the host; its square on the device for
     // the Gram-Schmidt coefficients).  Each new column is left where the
@@ -749,13 +754,18 @@ class Engine {
       for (int i = 0; i < steps; ++i)
         for (int r = 0; r < R; ++r) yhost[i * R + r] *= sig[i * R + r];  // z_i = sig_i P(stored column i)
       HIP_CHECK(hipMemcpyAsync(ydev, yhost, steps * R * sizeof(double), hipMemcpyHostToDevice, c_->stream));
-      // x is the concatenation (xu, xp) only when contiguous; update both parts
-      double* xc = static_cast<double*>(c_->workspace("gm_x", nc * sizeof(double)));
-      HIP_CHECK(hipMemcpyAsync(xc, xu, nu() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
-      HIP_CHECK(hipMemcpyAsync(xc + nu(), xp, np() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
-      mupdate((const T*)Z, steps, ydev, 1.0, xc, nullptr);
-      HIP_CHECK(hipMemcpyAsync(xu, xc, nu() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
-      HIP_CHECK(hipMemcpyAsync(xp, xc + nu(), np() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+      // the update writes the coupled vector (xu, xp): in place when the two
+      // parts are contiguous, else through a staging copy
+      if (xp == xu + nu()) {
+        mupdate((const T*)Z, steps, ydev, 1.0, xu, nullptr);
+      } else {
+        double* xc = static_cast<double*>(c_->workspace("gm_x", nc * sizeof(double)));
+        HIP_CHECK(hipMemcpyAsync(xc, xu, nu() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+        HIP_CHECK(hipMemcpyAsync(xc + nu(), xp, np() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+        mupdate((const T*)Z, steps, ydev, 1.0, xc, nullptr);
+        HIP_CHECK(hipMemcpyAsync(xu, xc, nu() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+        HIP_CHECK(hipMemcpyAsync(xp, xc + nu(), np() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+      }
       HIP_CHECK(hipStreamSynchronize(c_->stream));
     }
     return steps;
@@ -869,8 +879,9 @@ int refine_loop(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, 
   Engine<T> e(c, o, nrb, st);
   Engine<double> e64(c, o, nrb, st);
   const int64_t nu = c->n_int * c->dim * nrb, np = c->n_p1 * nrb;
-  double* ru = static_cast<double*>(c->workspace("rf_ru", nu * sizeof(double)));
-  double* rp = static_cast<double*>(c->workspace("rf_rp", np * sizeof(double)));
+  // (ru, rp) contiguous: the FGMRES cycle normalizes the coupled residual in place
+  double* ru = static_cast<double*>(c->workspace("rf_r", (nu + np) * sizeof(double)));
+  double* rp = ru + nu;
   std::vector<double> bn = e64.dots(F, F, g, g);
   for (double& x : bn) x = std::sqrt(x);
   st.rel_res.assign(nrb, 0.0);
