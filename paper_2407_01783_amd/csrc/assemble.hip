@@ -1130,7 +1130,6 @@ void assemble_ctx(stokes_ctx* c) {
   c->AD16.alloc(c->sA.nnz_pad * sizeof(_Float16));
   launch(c, c->sA.nnz_pad, k_scale_cols, c->sA.nnz_pad, c->sA.cols.as<int32_t>(), c->A64.as<double>(),
          c->dA64.as<double>(), c->AD64.as<double>(), c->AD32.as<float>(), c->AD16.as<_Float16>());
-  build_interleaved(c);
   if (c->strain) {
     c->AB64.alloc(c->sA.nnz_pad * (D * (D + 1) / 2) * sizeof(double));
     c->AB32.alloc(c->sA.nnz_pad * (D * (D + 1) / 2) * sizeof(float));
@@ -1160,6 +1159,7 @@ void assemble_ctx(stokes_ctx* c) {
     launch(c, n, k_cast<double, float>, n, src.as<double>(), dst.as<float>());
   };
   to32(c->A64, c->A32, c->sA.nnz_pad);
+  build_interleaved(c);  // AD16 and A32 are final here
   to32(c->MV64, c->MV32, c->sA.nnz_pad);
   to32(c->B64, c->B32, c->sB.nnz_pad * D);
   to32(c->Bt64, c->Bt32, c->sBt.nnz_pad * D);
@@ -1207,6 +1207,12 @@ void build_interleaved(stokes_ctx* c) {
   hipLaunchKernelGGL(k_interleave4<uint16_t>, dim3(S.nslices), dim3(64), 0, c->stream, S.nslices,
                      S.slice_ptr.as<int64_t>(), c->AD16.as<uint16_t>(), c->AD16i.as<uint16_t>());
   HIP_CHECK(hipGetLastError());
+  if (c->A32.p) {
+    if (!c->A32i.p) c->A32i.alloc(S.nnz_pad * sizeof(float));
+    hipLaunchKernelGGL(k_interleave4<uint32_t>, dim3(S.nslices), dim3(64), 0, c->stream, S.nslices,
+                       S.slice_ptr.as<int64_t>(), c->A32.as<uint32_t>(), c->A32i.as<uint32_t>());
+    HIP_CHECK(hipGetLastError());
+  }
 }
 
 // M_Q + L_Q on a P1 mesh (a coarse level of the pressure multigrid).

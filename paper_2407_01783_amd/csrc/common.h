@@ -201,6 +201,7 @@ struct stokes_ctx {
   int pmg_half = 1;                          // FP32 pressure V-cycles read the levels' half values
   int vel_bf = 1;                            // FP32 velocity Chebyshev keeps its direction q in bfloat16
   stokes::DevBuf AD16i, cdel_i, cols_i;      // four-slot interleaved AD16 and sA column indices (bfloat16 step)
+  stokes::DevBuf A32i;                       // four-slot interleaved A32 (FP32 velocity product of K_gamma)
   int vel_il = 1;                            // the bfloat16 Chebyshev step reads the interleaved copies
   stokes::DevBuf AB64, AB32;                 // strain: [nnz_pad][dim*dim] blocks alpha M + mu (L + D)
   stokes::DevBuf B64, B32, Bt64, Bt32;       // [nnz_pad][dim]

@@ -226,6 +226,111 @@ __device__ __forceinline__ void sell_row(const SellIdx& ix, const TM* __restrict
   }
 }
 
+// ------------------------------------- four-slot interleaved SELL copies
+//
+// A copy of a slice's scalar arrays (values, packed column offsets, 32-bit
+// columns) in which slots 4g .. 4g+3 of row r of a slice starting at entry
+// s0 sit at s0 + 256 g + 4 r + (0..3): one lane reads the four values of a
+// group with one 8- or 16-byte load and their column offsets with one 4-byte
+// load, where the slot-major layout takes one load per entry and array.
+// Slots from 4 floor(width / 4) on keep their slot-major places
+// (s0 + 64 j + r), so the copy is a permutation inside each slice with the
+// same slice pointers and column bases (k_interleave4).  Entries are still
+// taken in slot order: products equal the slot-major ones bit for bit.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float half_bits(uint32_t h) {
+  return (float)__builtin_bit_cast(_Float16, static_cast<uint16_t>(h));
+}
+
+// the four values of a group (e = its first entry), as T
+template <typename TM, typename T>
+__device__ __forceinline__ void load4_vals(const TM* __restrict__ vals, int64_t e, T (&v)[4]) {
+  static_assert(sizeof(TM) == 2 || sizeof(TM) == 4, "half or float values");
+  if constexpr (sizeof(TM) == 2) {
+    const u32x2_t vv = __builtin_nontemporal_load(reinterpret_cast<const u32x2_t*>(vals + e));
+    v[0] = (T)half_bits(vv.x & 0xFFFFu);
+    v[1] = (T)half_bits(vv.x >> 16);
+    v[2] = (T)half_bits(vv.y & 0xFFFFu);
+    v[3] = (T)half_bits(vv.y >> 16);
+  } else {
+    const f32x4_t vv = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t*>(vals + e));
+    v[0] = (T)vv.x;
+    v[1] = (T)vv.y;
+    v[2] = (T)vv.z;
+    v[3] = (T)vv.w;
+  }
+}
+
+// the four columns of group g (e = its first entry)
+template <bool PK>
+__device__ __forceinline__ void load4_cols(const SellIdx& ix, const SliceRef& r, int g, int64_t e, int32_t (&c)[4]) {
+  if constexpr (PK) {
+    const uint32_t d4 = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(ix.cdel + e));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = ix.cbase[r.eb + 4 * g + k] + static_cast<int32_t>((d4 >> (8 * k)) & 0xFFu);
+  } else {
+    const i32x4_t cc = __builtin_nontemporal_load(reinterpret_cast<const i32x4_t*>(ix.cols + e));
+    c[0] = cc.x;
+    c[1] = cc.y;
+    c[2] = cc.z;
+    c[3] = cc.w;
+  }
+}
+
+// acc += sum_j v_j x[c_j][0..W) over the interleaved copy, one lane per row,
+// two groups of four entries in flight per lane.
+template <typename T, int W, typename TM, bool PK>
+__device__ __forceinline__ void sell_row_il_impl(const SellIdx& ix, const SliceRef& r, const TM* __restrict__ vals,
+                                                 const T* __restrict__ x, T (&acc)[W]) {
+  const int64_t s0 = r.eb << 6;
+  const int lr = static_cast<int>(r.beg - s0);
+  const int g4 = r.width >> 2;
+  auto groups = [&](auto Hc, int g) {
+    constexpr int H = decltype(Hc)::value;
+    int32_t c[H][4];
+    T v[H][4];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const int64_t e = s0 + 256 * (int64_t)(g + h) + 4 * lr;
+      load4_vals<TM, T>(vals, e, v[h]);
+      load4_cols<PK>(ix, r, g + h, e, c[h]);
+    }
+    T xv[H][4][W];
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int w = 0; w < W; ++w) xv[h][k][w] = x[(int64_t)c[h][k] * W + w];
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int w = 0; w < W; ++w) acc[w] = fma(v[h][k], xv[h][k][w], acc[w]);
+  };
+  int g = 0;
+  for (; g + 2 <= g4; g += 2) groups(std::integral_constant<int, 2>{}, g);
+  if (g < g4) groups(std::integral_constant<int, 1>{}, g);
+  for (int j = 4 * g4; j < r.width; ++j) {
+    const int32_t c = sell_col<PK>(ix, r, j);
+    const T v = (T)__builtin_nontemporal_load(vals + r.beg + 64 * j);
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = fma(v, x[(int64_t)c * W + w], acc[w]);
+  }
+}
+
+template <typename T, int W, typename TM>
+__device__ __forceinline__ void sell_row_il(const SellIdx& ix, const TM* __restrict__ vals, const T* __restrict__ x,
+                                            int64_t row, T (&acc)[W]) {
+  const SliceRef r = slice_ref(ix, row);
+  if (r.pk) sell_row_il_impl<T, W, TM, true>(ix, r, vals, x, acc);
+  else sell_row_il_impl<T, W, TM, false>(ix, r, vals, x, acc);
+}
+
 // B rows (pressure vertex): acc[r] = sum_j sum_c B^c_j u[col_j][r][c]
 // (entries walked two at a time to keep more loads in flight)
 template <typename T, int D, int NRB, bool PK>
@@ -379,7 +484,8 @@ __device__ __forceinline__ void expand_parts(const double (&pg)[W / G], int sub,
 // ----------------------------------------------------------- SpMV kernels
 
 // y = a * (S x) + b * yin   (yin may alias y; ignored when b == 0)
-template <typename T, int W, int G, typename TM = T>
+// IL (G = 1): ix and vals are the four-slot interleaved copies.
+template <typename T, int W, int G, typename TM = T, bool IL = false>
 __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
                                                  const T* __restrict__ x, T* y, T a, const T* yin, T b) {
   constexpr int WG = W / G;
@@ -387,7 +493,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, SellIdx ix, cons
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<T, W, G, TM, (W / G == 1 ? 16 : W / G <= 2 ? 8 : 4)>(ix, vals, x, row, sub, acc);
+    if constexpr (IL) sell_row_il<T, W, TM>(ix, vals, x, row, acc);
+    else sell_row<T, W, G, TM, (W / G == 1 ? 16 : W / G <= 2 ? 8 : 4)>(ix, vals, x, row, sub, acc);
     const int64_t o = row * W + sub * WG;
     // yin may alias y: every load of the row is issued before its stores
     T yi[WG];
@@ -894,20 +1001,8 @@ __device__ __forceinline__ void sell_row_bq_impl(const SellIdx& ix, const SliceR
   for (; j < r.width; ++j) group(std::integral_constant<int, 1>{}, j);
 }
 
-// Four-slot interleaved copy of a slice (the velocity Chebyshev step's
-// values and column indices): slots 4g .. 4g+3 of row r of a slice that
-// starts at entry s0 sit at s0 + 256 g + 4 r + (0..3), so one lane reads the
-// four values of a group with one 8-byte load and their packed column
-// offsets with one 4-byte load.  Slots from 4 floor(width / 4) on keep their
-// slot-major places (s0 + 64 j + r): the copy is a permutation inside each
-// slice, with the same slice pointers and column bases.
-typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
-typedef int i32x4_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ float half_bits(uint32_t h) {
-  return (float)__builtin_bit_cast(_Float16, static_cast<uint16_t>(h));
-}
-
+// The bfloat16-direction row over the four-slot interleaved copies (the
+// layout of sell_row_il_impl).
 template <int W, int G, bool PK>
 __device__ __forceinline__ void sell_row_bq4_impl(const SellIdx& ix, const SliceRef& r,
                                                   const _Float16* __restrict__ vals,
@@ -921,22 +1016,8 @@ __device__ __forceinline__ void sell_row_bq4_impl(const SellIdx& ix, const Slice
   // one group of four slots: values and columns, then the gathers
   auto load = [&](int g, int32_t (&c)[4], float (&v)[4]) {
     const int64_t e = s0 + 256 * (int64_t)g + 4 * lr;
-    const u32x2_t vv = __builtin_nontemporal_load(reinterpret_cast<const u32x2_t*>(vals + e));
-    v[0] = half_bits(vv.x & 0xFFFFu);
-    v[1] = half_bits(vv.x >> 16);
-    v[2] = half_bits(vv.y & 0xFFFFu);
-    v[3] = half_bits(vv.y >> 16);
-    if constexpr (PK) {
-      const uint32_t d4 = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(ix.cdel + e));
-#pragma unroll
-      for (int k = 0; k < 4; ++k) c[k] = ix.cbase[r.eb + 4 * g + k] + static_cast<int32_t>((d4 >> (8 * k)) & 0xFFu);
-    } else {
-      const i32x4_t cc = __builtin_nontemporal_load(reinterpret_cast<const i32x4_t*>(ix.cols + e));
-      c[0] = cc.x;
-      c[1] = cc.y;
-      c[2] = cc.z;
-      c[3] = cc.w;
-    }
+    load4_vals<_Float16, float>(vals, e, v);
+    load4_cols<PK>(ix, r, g, e, c);
   };
   int g = 0;
   for (; g + 2 <= g4; g += 2) {
@@ -998,7 +1079,8 @@ __global__ __launch_bounds__(64) void k_interleave4(int64_t nslices, const int64
 
 // First step with a bfloat16 direction out:  q0 = theta_inv r (not stored),
 // res = r - (S D^{-1}) q0, q1 = bf16(c1 q0 + c2 res), z (+)= dinv (q0 + q1)
-template <typename TM, int W, int ACC, int G, int U = 8>
+// IL (G = 1): ix and vals are the four-slot interleaved copies.
+template <typename TM, int W, int ACC, int G, int U = 8, bool IL = false>
 __global__ __launch_bounds__(kBlock) void k_cheb_first_qb(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
                                                           const float* __restrict__ r, const float* __restrict__ dinv,
                                                           float theta_inv, uint16_t* __restrict__ q1,
@@ -1009,7 +1091,8 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first_qb(int64_t nrows, SellIdx
     float acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    sell_row<float, W, G, TM, (W / G >= 8 ? 4 : U)>(ix, vals, r, row, sub, acc);
+    if constexpr (IL) sell_row_il<float, W, TM>(ix, vals, r, row, acc);
+    else sell_row<float, W, G, TM, (W / G >= 8 ? 4 : U)>(ix, vals, r, row, sub, acc);
     const float di = dinv[row];
     const int64_t o = row * W + sub * WG, oq = row * WP + sub * WG;
 #pragma unroll

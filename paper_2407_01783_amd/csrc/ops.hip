@@ -133,6 +133,14 @@ bool with_e(int E, F&& f) {
   }
 }
 
+// Index of the four-slot interleaved copy of the velocity pattern.
+SellIdx vel_il_idx(stokes_ctx* c) {
+  SellIdx ix = c->sA.idx();
+  ix.cdel = c->cdel_i.as<const uint8_t>();
+  ix.cols = c->cols_i.as<const int32_t>();
+  return ix;
+}
+
 // Before tuning: the largest G leaving each lane at least 3 components.
 int heuristic_lanes(int W) {
   for (int g : {8, 4, 2})
@@ -197,6 +205,15 @@ void spmv_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, int W, const 
   const int G = lanes_op(c, &S, W, std::is_same<T, float>::value);
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
+    // the FP32 velocity product (K_gamma in the FGMRES cycle) on the
+    // interleaved copy of A_II, one lane per row
+    if constexpr (std::is_same<T, float>::value && std::is_same<TM, float>::value) {
+      if (G == 1 && &S == &c->sA && c->vel_il && c->A32i.p && (const void*)vals == c->A32.p) {
+        hipLaunchKernelGGL((k_spmv<T, WW, 1, TM, true>), dim3(grid_full(S.nrows)), dim3(kBlock), 0, c->stream,
+                           S.nrows, vel_il_idx(c), c->A32i.as<const float>(), x, y, (T)(a * ms), yin, b);
+        return;
+      }
+    }
     if (S.es > 1 && with_e<WW>(S.es, [&](auto Ec) {
           constexpr int EE = decltype(Ec)::value;
           hipLaunchKernelGGL((k_spmv_es<T, WW, EE, TM>), dim3(grid_full(S.nrows * EE)), dim3(kBlock), 0, c->stream,
@@ -495,6 +512,14 @@ void cheb_first_hb(stokes_ctx* c, int W, const float* r, const float* dinv, floa
     constexpr int WW = decltype(Wc)::value;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
+      if constexpr (GG == 1) {
+        if (c->vel_il && c->AD16i.p) {  // the four-slot interleaved copies
+          hipLaunchKernelGGL((k_cheb_first_qb<_Float16, WW, 0, 1, 8, true>), dim3(grid_full(S.nrows)), dim3(kBlock),
+                             0, c->stream, S.nrows, vel_il_idx(c), (const _Float16*)c->AD16i.as<_Float16>(), r, dinv,
+                             theta_inv, q1, res, z, c1, c2);
+          return;
+        }
+      }
       hipLaunchKernelGGL((k_cheb_first_qb<_Float16, WW, 0, GG>),
                          dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0,
                          c->stream, S.nrows, S.idx(), (const _Float16*)c->AD16.as<_Float16>(), r, dinv, theta_inv,
@@ -518,12 +543,9 @@ void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const f
       const int nb = grid_full(S.nrows * GG);
       if constexpr (BfRaw<bf_width<WW>(), WW / GG>::kOn) {
         if (c->vel_il && c->AD16i.p) {  // the four-slot interleaved copies
-          SellIdx ix = S.idx();
-          ix.cdel = c->cdel_i.as<const uint8_t>();
-          ix.cols = c->cols_i.as<const int32_t>();
           hipLaunchKernelGGL((k_cheb_step_qb<_Float16, WW, GG, 8, true>), dim3(nb), dim3(kBlock), 0, c->stream,
-                             S.nrows, ix, (const _Float16*)c->AD16i.as<_Float16>(), q, qn, res_in, res_out, z,
-                             dinv, c1, c2);
+                             S.nrows, vel_il_idx(c), (const _Float16*)c->AD16i.as<_Float16>(), q, qn, res_in,
+                             res_out, z, dinv, c1, c2);
           return;
         }
       }
