@@ -170,6 +170,24 @@ def test_interleaved_chebyshev_step_bitwise_equal(gpu_lib, monkeypatch, dim, n, 
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_set_mu_then_mixed_solve_matches_oracle(gpu_lib):
+    """set_mu rebuilds the FP32 and half-precision copies and their four-slot
+    interleaved forms (read by the velocity Chebyshev and by K_gamma): a
+    mixed-precision coupled solve matches the oracle at the new viscosity."""
+    from paper_2407_01783_amd import inputs
+    P = _problem(3, 5, seed=3, mu=1.0, alpha=100.0)
+    mu2 = 0.02
+    P.set_mu(mu2)
+    S = _oracle(3, 5, seed=3, mu=mu2, alpha=100.0)
+    f = inputs.fourier_forcing(S.mesh.p2coords, inputs.forcing_seed(3))
+    U, Pp = S.solve(*S.rhs(f))
+    u, p, info = P.solve(torch.tensor(f[None], device="cuda"), method="coupled", precision=1, rtol=1e-10)
+    assert info["status"] == 0, info
+    eu, ep = _rel(u.cpu().numpy()[0], S.full_velocity(U)), _rel(p.cpu().numpy()[0], Pp)
+    print(f"mu {mu2}: err_u {eu:.2e} err_p {ep:.2e}", flush=True)
+    assert eu <= 1e-8 and ep <= 1e-8, (eu, ep)
+
+
 @pytest.mark.parametrize("dim,n,nrhs", [(3, 4, 1), (3, 5, 2), (2, 12, 3)])
 def test_velocity_chebyshev_preconditioner_matches_closed_form(gpu_lib, dim, n, nrhs):
     """apply op 10 (the FIXED-mode velocity preconditioner, degree 6 on the
