@@ -488,7 +488,7 @@ stokes_status stokes_assemble(const stokes_problem* prob, void* hip_stream, stok
     if (const char* e = std::getenv("STOKES_ZBLOCK")) c->zblock = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("STOKES_MG_ES")) {
       const int v = std::atoi(e);
-      c->mg_es = (v == 0 || v == 2 || v == 4 || v == 8 || v == 16) ? v : 1;
+      c->mg_es = (v == -1 || v == 0 || v == 2 || v == 4 || v == 8 || v == 16) ? v : 1;
     }
     if (const char* e = std::getenv("STOKES_MG_DEGREE")) c->mg_smooth_degree = std::max(1, std::atoi(e));
     if (const char* e = std::getenv("STOKES_MG_RATIO")) c->mg_smooth_ratio = std::max(1.5, std::atof(e));

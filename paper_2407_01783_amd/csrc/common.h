@@ -221,7 +221,7 @@ struct stokes_ctx {
   stokes::MgHier mgq, mgx;
   int mg_smooth_degree = 2, mg_coarse_degree = 24;
   int zblock = -1;                       // lattice planes per block of the interior row order (0: whole slab, -1: by size)
-  int mg_es = 1;                        // pressure-MG lanes per row: 1 tune per level, 0 one lane, 2-16 fixed
+  int mg_es = 1;                        // pressure-MG lanes per row: 1 by level size, -1 timed, 0 one lane, 2-16 fixed
   int64_t mg_dense_max = 1500;          // largest level solved densely
   double mg_smooth_ratio = 10.0;
   int use_mgx = 1;                      // lumped CC: precondition with mgx (0: mgq)

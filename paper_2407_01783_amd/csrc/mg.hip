@@ -293,14 +293,20 @@ static void dense_coarsest(stokes_ctx* c, MgHier& H) {
   H.dense_n = nr;
 }
 
-// Entry-split lanes per level (Sell::es): time the level product in the form
-// the FP32 V-cycle uses (half values when present) with E = 1, 2, 4, 8, 16
-// lanes per row and keep the fastest (mg_es = 1), or set one E on every level
-// (mg_es in {2, 4, 8, 16}; 0 keeps one lane per row).  The coarse levels have a few thousand
-// rows of a two-ring stencil, where one lane per row leaves the chip idle.
+// Entry-split lanes per level (Sell::es).  The coarse levels have a few
+// thousand rows of a two-ring stencil, where one lane per row leaves the chip
+// idle.  mg_es = 1 (default): 8 lanes per row on levels below 2^14 rows, one
+// lane above -- a fixed rule, so that every context sums the same way and
+// solves are reproducible bit for bit; -1: time the level product in the form
+// the FP32 V-cycle uses (half values when present) for E = 1, 2, 4, 8, 16
+// and keep the fastest; 0: one lane per row; 2, 4, 8, 16: that E everywhere.
 namespace {
 void tune_levels(stokes_ctx* c, MgHier& H) {
   if (c->mg_es == 0) return;
+  if (c->mg_es == 1) {
+    for (auto& L : H.own) L->S.es = L->S.nrows < (int64_t(1) << 14) ? 8 : 1;
+    return;
+  }
   if (c->mg_es > 1) {  // a fixed E on every level
     for (auto& L : H.own) L->S.es = c->mg_es;
     return;

@@ -188,6 +188,24 @@ def test_set_mu_then_mixed_solve_matches_oracle(gpu_lib):
     assert eu <= 1e-8 and ep <= 1e-8, (eu, ep)
 
 
+def test_mixed_solve_bitwise_reproducible_across_contexts(gpu_lib):
+    """Two contexts of the same problem give bitwise-equal mixed solves: the
+    tuned lanes per velocity row do not change any sum, and the lanes per row
+    of the pressure levels follow a fixed rule (3D n=16: a 4,913-row finest
+    pressure level with 8 lanes per row)."""
+    from paper_2407_01783_amd import inputs
+    outs = []
+    for _ in range(2):
+        P = _problem(3, 16, seed=6, mu=1e-2, alpha=100.0)
+        xy, _ = P.mesh()
+        f = np.stack([inputs.fourier_forcing(xy, inputs.forcing_seed(6, k)) for k in range(2)])
+        u, p, info = P.solve(torch.tensor(f, device="cuda"), method="coupled", precision=1, rtol=1e-8)
+        assert info["status"] == 0, info
+        outs.append((u.cpu().numpy(), p.cpu().numpy()))
+        del P
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 @pytest.mark.parametrize("dim,n,zb", [(3, 8, 2), (2, 16, 3)])
 def test_plane_blocked_row_order(gpu_lib, monkeypatch, dim, n, zb):
     """Interior rows blocked by zb lattice planes inside each slab (the order
