@@ -1019,36 +1019,32 @@ __device__ __forceinline__ void sell_row_bq4_impl(const SellIdx& ix, const Slice
     load4_vals<_Float16, float>(vals, e, v);
     load4_cols<PK>(ix, r, g, e, c);
   };
-  int g = 0;
-  for (; g + 2 <= g4; g += 2) {
-    int32_t c[2][4];
-    float v[2][4];
-    load(g, c[0], v[0]);
-    load(g + 1, c[1], v[1]);
-    uint32_t xr[2][4][Raw::kWords];
+  // H groups at a time: values and offsets first, then all their gathers
+  auto groups = [&](auto Hc, int g) {
+    constexpr int H = decltype(Hc)::value;
+    int32_t c[H][4];
+    float v[H][4];
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < H; ++h) load(g + h, c[h], v[h]);
+    uint32_t xr[H][4][Raw::kWords];
+#pragma unroll
+    for (int h = 0; h < H; ++h)
 #pragma unroll
       for (int k = 0; k < 4; ++k) load_bf_raw<WP, WG>(xq, c[h][k], off, xr[h][k]);
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < H; ++h)
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int w = 0; w < WG; ++w) acc[w] = fma(v[h][k], bf_word(xr[h][k][w / 2], w & 1), acc[w]);
-  }
-  if (g < g4) {
-    int32_t c[4];
-    float v[4];
-    load(g, c, v);
-    uint32_t xr[4][Raw::kWords];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) load_bf_raw<WP, WG>(xq, c[k], off, xr[k]);
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int w = 0; w < WG; ++w) acc[w] = fma(v[k], bf_word(xr[k][w / 2], w & 1), acc[w]);
-  }
+  };
+  // narrow lanes keep four groups (16 entries) in flight, wide ones two
+  constexpr int HG = WG <= 4 ? 4 : 2;
+  int g = 0;
+  for (; g + HG <= g4; g += HG) groups(std::integral_constant<int, HG>{}, g);
+  if constexpr (HG > 2)
+    for (; g + 2 <= g4; g += 2) groups(std::integral_constant<int, 2>{}, g);
+  if (g < g4) groups(std::integral_constant<int, 1>{}, g);
   // the remaining width mod 4 slots, slot-major
   for (int j = 4 * g4; j < r.width; ++j) {
     const int32_t c = sell_col<PK>(ix, r, j);
