@@ -1467,6 +1467,8 @@ __global__ __launch_bounds__(kBlock) void k_p_out(int64_t n_p1, const T* __restr
 // Boundary columns of the load vector and the lifting, on the interior rows
 // that touch the boundary: F[row] += sum_{c in Gamma} (M_ic f_c - A_ic G_c)
 // (the interior columns of M f come from the sliced-ELL mass product).
+constexpr int kRhsLanes = 4;
+
 template <int D, int NRB>
 __global__ __launch_bounds__(kBlock) void k_rhs_bnd(int64_t nbc, int64_t n_p2, const int32_t* __restrict__ rows,
                                                     const int32_t* __restrict__ ptr, const int32_t* __restrict__ cols,
@@ -1474,12 +1476,14 @@ __global__ __launch_bounds__(kBlock) void k_rhs_bnd(int64_t nbc, int64_t n_p2, c
                                                     const double* __restrict__ L, const double* __restrict__ Dg,
                                                     double alpha, double mu, const double* __restrict__ f,
                                                     const double* __restrict__ ubc, double* __restrict__ F) {
+  // kRhsLanes lanes per row take every kRhsLanes-th boundary column and add
+  // their sums by lane exchanges (the lanes of a row share a wavefront)
   constexpr int W = D * NRB;
-  GRID_STRIDE_ROWS(q, nbc) {
+  GRID_STRIDE_ROWS_G(q, sub, nbc, kRhsLanes) {
     double acc[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = 0;
-    for (int32_t k = ptr[q]; k < ptr[q + 1]; ++k) {
+    for (int32_t k = ptr[q] + sub; k < ptr[q + 1]; k += kRhsLanes) {
       const int64_t c = cols[k];
       const int64_t e = src[k];
       const double m = M[e];
@@ -1498,9 +1502,15 @@ __global__ __launch_bounds__(kBlock) void k_rhs_bnd(int64_t nbc, int64_t n_p2, c
           acc[r * D + d] += v;
         }
     }
-    const int64_t row = rows[q];
 #pragma unroll
-    for (int w = 0; w < W; ++w) F[row * W + w] += acc[w];
+    for (int o = kRhsLanes / 2; o >= 1; o /= 2)
+#pragma unroll
+      for (int w = 0; w < W; ++w) acc[w] += __shfl_xor(acc[w], o);
+    if (sub == 0) {
+      const int64_t row = rows[q];
+#pragma unroll
+      for (int w = 0; w < W; ++w) F[row * W + w] += acc[w];
+    }
   }
 }
 

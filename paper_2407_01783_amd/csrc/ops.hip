@@ -814,7 +814,8 @@ void rhs(stokes_ctx* c, int nrb, const double* f, const double* ubc, double* F, 
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
     constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
     if (c->n_bc > 0 && (f || ubc))
-      hipLaunchKernelGGL((k_rhs_bnd<D, N>), dim3(grid_for(c->n_bc)), dim3(kBlock), 0, c->stream, c->n_bc, c->n_p2,
+      hipLaunchKernelGGL((k_rhs_bnd<D, N>), dim3(grid_for(c->n_bc * kRhsLanes)), dim3(kBlock), 0, c->stream, c->n_bc,
+                         c->n_p2,
                          c->bc_rows.as<int32_t>(), c->bc_ptr.as<int32_t>(), c->bc_cols.as<int32_t>(),
                          c->bc_src.as<int32_t>(), c->M_full.as<double>(), c->L_full.as<double>(),
                          c->strain ? c->D_full.as<double>() : nullptr, c->prob.alpha, c->prob.mu, f, ubc, F);
