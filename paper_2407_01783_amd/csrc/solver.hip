@@ -35,6 +35,12 @@ namespace stokes {
 
 namespace {
 
+// FGMRES: the next step's preconditioner is queued ahead of the host's
+// rotations while the residual estimate is above this multiple of the goal
+// (a step shrinks it by about 5x on the benchmark problems, so the step in
+// flight is then almost surely not the last).
+constexpr double kQueueAhead = 30.0;
+
 template <int V>
 using IC = std::integral_constant<int, V>;
 
@@ -614,29 +620,53 @@ class Engine {
     }
     HIP_CHECK(hipMemcpyAsync(sig2dev, sig2host, R * sizeof(double), hipMemcpyHostToDevice, c_->stream));
     auto Hat = [&](int i, int j, int r) -> double& { return H[((size_t)i * m + j) * R + r]; };
+    // K_gamma z_j in the inner precision T (the FP32 matrices) unless the
+    // FP64 operator is asked for
+    const bool k_inner = std::is_same<T, TK>::value || o_.arnoldi_fp64 != STOKES_ARNOLDI_FP64_K;
+    // with the upper triangular preconditioner the product B^T z_p of the
+    // preconditioner is reused by K_gamma z_j
+    const bool reuse_bt = k_inner && o_.coupled_pc == STOKES_PC_UPPER && gamma_ == 0;
+    T* bt = reuse_bt ? buf("gm_bt", nu()) : nullptr;
+    // z_jj = P^{-1} v_jj in the inner precision: its input is the basis
+    // column itself, or the rounded copy vin that the step before wrote
+    auto precondition = [&](int jj) {
+      const T* vsrc;
+      if constexpr (std::is_same<T, TK>::value) {
+        vsrc = V + (int64_t)jj * nc;
+      } else {
+        vsrc = vin;
+      }
+      T* Zjj = Z + (int64_t)jj * nc;
+      block_prec(vsrc, vsrc + nu(), Zjj, Zjj + nu(), bt);
+    };
+    // With one right-hand side far from its goal, the preconditioner of the
+    // next step is queued before the host reads this step's Gram-Schmidt
+    // sums (it needs no host value), so the GPU does not idle while the
+    // host applies the rotations; the host waits on an event recorded
+    // before it.  Near the goal the step may be the last one, and the host
+    // waits for the stream as before.  A queued z past the last step is
+    // left unused.
+    hipEvent_t ev_h = nullptr;
+    HIP_CHECK(hipEventCreateWithFlags(&ev_h, hipEventDisableTiming));
+    struct EventGuard {
+      hipEvent_t e;
+      ~EventGuard() { (void)hipEventDestroy(e); }
+    } ev_guard{ev_h};
+    // only for a fixed preconditioner (FIXED inner mode: a linear map that
+    // accepts any input; TOL-mode inner CGs stop with an error on a
+    // vanishing right-hand side, which a step past convergence can be)
+    const bool queue_ahead = R == 1 && o_.inner_mode == STOKES_INNER_FIXED;
+    bool z_queued = false;             // z_j already queued during step j - 1
+    double est_prev = g[0];            // residual estimate after the previous step (R = 1)
     int j = 0;
     for (; j < m; ++j) {
       bool any = false;
       for (int r = 0; r < R; ++r) any = any || active[r];
       if (!any) break;
-      TK* Vj = V + (int64_t)j * nc;
       T* Zj = Z + (int64_t)j * nc;
       TK* wj = V + (int64_t)(j + 1) * nc;  // K_gamma z_j, orthogonalized in place: the next column
-      // z_j = P^{-1} v_j in the inner precision
-      const T* vsrc;
-      if constexpr (std::is_same<T, TK>::value) {
-        vsrc = Vj;
-      } else {
-        vsrc = vin;
-      }
-      // K_gamma z_j in the inner precision T (the FP32 matrices) unless the
-      // FP64 operator is asked for
-      const bool k_inner = std::is_same<T, TK>::value || o_.arnoldi_fp64 != STOKES_ARNOLDI_FP64_K;
-      // with the upper triangular preconditioner the product B^T z_p of the
-      // preconditioner is reused by K_gamma z_j
-      const bool reuse_bt = k_inner && o_.coupled_pc == STOKES_PC_UPPER && gamma_ == 0;
-      T* bt = reuse_bt ? buf("gm_bt", nu()) : nullptr;
-      block_prec(vsrc, vsrc + nu(), Zj, Zj + nu(), bt);
+      if (!z_queued) precondition(j);
+      z_queued = false;
       // w = K_gamma z_j
       auto k_apply_inner = [&](T* out) {
         if (reuse_bt) {
@@ -688,7 +718,14 @@ class Engine {
       // the second update also leaves the next preconditioner input (in T)
       mupdate(V, j + 1, h2, -1.0, wj, nrm, sig2dev, vin);
       HIP_CHECK(hipMemcpyAsync(hhost, hdev, 3 * 64 * 8 * sizeof(double), hipMemcpyDeviceToHost, c_->stream));
-      HIP_CHECK(hipStreamSynchronize(c_->stream));
+      if (queue_ahead && j + 1 < m && est_prev > kQueueAhead * target[0]) {
+        HIP_CHECK(hipEventRecord(ev_h, c_->stream));
+        precondition(j + 1);
+        z_queued = true;
+        HIP_CHECK(hipEventSynchronize(ev_h));
+      } else {
+        HIP_CHECK(hipStreamSynchronize(c_->stream));
+      }
       st_.seconds_orth += now() - t0;
       bool dropped = false;  // a right-hand side stopped while others go on
       for (int r = 0; r < R; ++r) {
@@ -722,6 +759,7 @@ class Engine {
         g[j * R + r] = cc * g[j * R + r];
         kdone[r] = j + 1;
         const double est = std::fabs(g[(j + 1) * R + r]);
+        if (r == 0) est_prev = est;
         if (est <= target[r] || hn <= 1e-300) active[r] = 0;
         s[r] = active[r] && wn > 0 ? 1.0 : 0.0;
         sig[(j + 1) * R + r] = active[r] && wn > 0 ? 1.0 / wn : 0.0;
