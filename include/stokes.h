@@ -30,6 +30,11 @@
  *   best iterate), or a negative error code; stokes_last_error() then gives a
  *   message (thread-local).  Arguments are validated before any HIP call.
  *   After an error the output arrays are unspecified.
+ * - The solve entry points return STOKES_ERR_NONFINITE (-4) when the
+ *   right-hand side they form from f and ubc (or the adjoint's dJdu, dJdp)
+ *   is not finite, when the first residual of a given initial guess is not
+ *   finite, or when an iterate or a residual of the solve becomes non-finite;
+ *   a NaN or Inf is never reported as convergence.
  * - One context per host thread at a time; calls on one context serialise on
  *   its stream.
  */
@@ -141,6 +146,23 @@ typedef struct {
   double seconds_total;   /* wall time of the call */
   double spmv_seconds;    /* summed duration of the timed SpMV launches */
   double spmv_bytes;      /* algorithmic bytes of one timed SpMV launch */
+  /* Phase times (opts->profile = 1; 0 otherwise): GPU time summed over every
+   * application of the phase, measured by HIP events on the solver's stream
+   * (so work queued ahead of the host is attributed correctly). */
+  double seconds_inner_u; /* velocity-block solves A~^{-1} (Sec. 3) */
+  double seconds_inner_p; /* pressure-block applications: the Cahouet-Chabard
+                             operator (Sec. 4.1), including its X^{-1} solves */
+  double seconds_orth;    /* Gram-Schmidt passes of the FGMRES cycles (CGS2) */
+  /* Residual history, CALLER-OWNED host buffer (may be NULL): entry k is the
+   * relative residual after outer iteration k as the outer method estimates
+   * it (FGMRES: its least-squares residual, Schur CG: the Schur residual),
+   * divided by ||b||, the largest over the right-hand sides of a batch;
+   * batches of more than 8 right-hand sides append in order.  Set res_hist
+   * and res_hist_cap before the call (they are kept); the call writes at most
+   * res_hist_cap entries and sets res_hist_len to the number written. */
+  double* res_hist;
+  int32_t res_hist_cap;
+  int32_t res_hist_len;
 } stokes_solve_info;
 
 /* Fill *opts with defaults: FP64, rtol 1e-8, FGMRES(30), Chebyshev degree 4,
@@ -195,8 +217,8 @@ stokes_status stokes_solve_coupled(stokes_ctx* ctx, int32_t nrhs, const double* 
                                    stokes_solve_info* info);
 
 /* One rotational incremental pressure-correction step, the comparator of
- * Sec. 7.5 (one velocity problem, one pressure Laplacian, one pressure mass
- * problem), from p_old ([nrhs][n_p1], NULL = 0):
+ * Sec. 7.5 and Table 8 (a momentum solve, then a pressure Poisson solve and a
+ * pressure-mass solve), from p_old ([nrhs][n_p1], NULL = 0):
  *     A u = F~ + B^T p_old,  d = B u - g,  L_Q phi = -alpha d,  M_Q psi = d,
  *     p = p_old + phi - mu psi  (zero integral),
  * with (F~, g) the lifted right-hand side of stokes_solve_schur (A without

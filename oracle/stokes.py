@@ -235,8 +235,8 @@ class StokesSystem:
     # ------------------------------------------------------------- projection
     def projection_step(self, f, ubc=None, p_old=None):
         """One rotational incremental pressure-correction step, the comparator
-        of Sec. 7.5 (one velocity problem, one pressure Laplacian, one
-        pressure mass problem), each solved directly:
+        of Sec. 7.5 and Table 8: a momentum solve, then a pressure Poisson
+        solve and a pressure-mass solve, each done directly:
             A U = F~ + B_I^T p_old,   d = B_I U - g,
             L_Q phi = -alpha d (zero mean),   M_Q psi = d,
             P = p_old + phi - mu psi  (zero integral).

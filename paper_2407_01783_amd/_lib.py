@@ -52,10 +52,22 @@ class SolveInfo(ctypes.Structure):
                 ("inner_iters_p", ctypes.c_int32), ("refinements", ctypes.c_int32),
                 ("spmv_launches", ctypes.c_int32), ("rel_res", ctypes.c_double),
                 ("seconds_total", ctypes.c_double), ("spmv_seconds", ctypes.c_double),
-                ("spmv_bytes", ctypes.c_double)]
+                ("spmv_bytes", ctypes.c_double), ("seconds_inner_u", ctypes.c_double),
+                ("seconds_inner_p", ctypes.c_double), ("seconds_orth", ctypes.c_double),
+                ("res_hist", ctypes.POINTER(ctypes.c_double)), ("res_hist_cap", ctypes.c_int32),
+                ("res_hist_len", ctypes.c_int32)]
+
+    def attach_history(self, cap):
+        """Give the call a caller-owned history buffer of ``cap`` entries."""
+        self._hist = (ctypes.c_double * max(1, int(cap)))()
+        self.res_hist = ctypes.cast(self._hist, ctypes.POINTER(ctypes.c_double))
+        self.res_hist_cap = int(cap)
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("res_hist", "res_hist_cap")}
+        if getattr(self, "_hist", None) is not None:
+            d["res_hist"] = list(self._hist[: self.res_hist_len])
+        return d
 
 
 EXPORTS = [

@@ -17,7 +17,8 @@ namespace stokes {
 
 namespace {
 thread_local std::string g_last_error;
-}
+
+}  // namespace
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 
@@ -132,8 +133,28 @@ struct StreamScope {
   }
 };
 
+// Zero the outputs of *info; the caller's residual-history buffer and its
+// capacity are kept.
 void info_reset(stokes_solve_info* info) {
-  if (info) std::memset(info, 0, sizeof(*info));
+  if (!info) return;
+  double* hist = info->res_hist;
+  const int32_t cap = info->res_hist_cap;
+  std::memset(info, 0, sizeof(*info));
+  info->res_hist = hist;
+  info->res_hist_cap = hist ? std::max<int32_t>(0, cap) : 0;
+}
+
+// Add one batch's counters and residual history to *info.
+void info_add(stokes_solve_info* info, const SolveStats& st) {
+  if (!info) return;
+  info->outer_iters += st.outer;
+  info->inner_iters_u += st.inner_u;
+  info->inner_iters_p += st.inner_p;
+  info->refinements += st.sweeps;
+  for (double v : st.hist) {
+    if (info->res_hist_len >= info->res_hist_cap) break;
+    info->res_hist[info->res_hist_len++] = v;
+  }
 }
 
 double wall() {
@@ -144,6 +165,10 @@ void prof_start(stokes_ctx* c, const stokes_solve_opts* o) {
   c->prof_on = o->profile ? 1 : 0;
   c->prof_idx = 0;
   c->prof_seen = 0;
+  for (auto& t : c->phase) {
+    t.idx = 0;
+    t.acc = 0;
+  }
   if (c->prof_on && c->prof_ev.empty()) {
     c->prof_ev.resize(16384);
     for (auto& pr : c->prof_ev) {
@@ -166,6 +191,9 @@ void prof_finish(stokes_ctx* c, stokes_solve_info* info) {
     info->spmv_seconds += s;
     info->spmv_launches += c->prof_idx;
     info->spmv_bytes = c->prof_bytes;
+    info->seconds_inner_u = ops::phase_collect(c, PHASE_VEL);
+    info->seconds_inner_p = ops::phase_collect(c, PHASE_PRES);
+    info->seconds_orth = ops::phase_collect(c, PHASE_ORTH);
   }
   c->prof_on = 0;
 }
@@ -211,12 +239,7 @@ stokes_status solve_forward(stokes_ctx* c, int method, int32_t nrhs, const doubl
     ops::p_out<double>(c, nrb, xp, p + po);
     if (s != STOKES_OK) status = s;
     for (double rr : st.rel_res) maxres = std::max(maxres, rr);
-    if (info) {
-      info->outer_iters += st.outer;
-      info->inner_iters_u += st.inner_u;
-      info->inner_iters_p += st.inner_p;
-      info->refinements += st.sweeps;
-    }
+    info_add(info, st);
     r0 += nrb;
   }
   HIP_CHECK(hipStreamSynchronize(c->stream));
@@ -266,11 +289,7 @@ stokes_status projection_forward(stokes_ctx* c, int32_t nrhs, const double* f, c
     ops::p_out<double>(c, nrb, xp, p + po);
     if (s != STOKES_OK) status = s;
     for (double rr : st.rel_res) maxres = std::max(maxres, rr);
-    if (info) {
-      info->inner_iters_u += st.inner_u;
-      info->inner_iters_p += st.inner_p;
-      info->refinements += st.sweeps;
-    }
+    info_add(info, st);
     r0 += nrb;
   }
   HIP_CHECK(hipStreamSynchronize(c->stream));
@@ -344,6 +363,11 @@ stokes_ctx::~stokes_ctx() {
     (void)hipEventDestroy(pr.first);
     (void)hipEventDestroy(pr.second);
   }
+  for (auto& t : phase)
+    for (auto& pr : t.ev) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
   for (auto& kv : ws_host)
     if (kv.second.first) (void)hipHostFree(kv.second.first);
   if (h_scal) (void)hipHostFree(h_scal);
@@ -590,12 +614,7 @@ stokes_status stokes_solve_adjoint(stokes_ctx* c, int32_t nrhs, const double* u,
       ops::adj_dJdmu(c, nrb, u + vo, xu, c->red.result.as<double>() + 4 * kMaxSys);
       HIP_CHECK(hipMemcpyAsync(dJdmu + r0, c->red.result.as<double>() + 4 * kMaxSys, nrb * sizeof(double),
                                hipMemcpyDeviceToDevice, c->stream));
-      if (info) {
-        info->outer_iters += st.outer;
-        info->inner_iters_u += st.inner_u;
-        info->inner_iters_p += st.inner_p;
-        info->refinements += st.sweeps;
-      }
+      info_add(info, st);
       r0 += nrb;
     }
     HIP_CHECK(hipStreamSynchronize(c->stream));

@@ -147,6 +147,15 @@ struct MgHier {
   DevBuf cinv64, cinv32;      // [n][n] inverse of the coarsest operator
 };
 
+// GPU time of one solver phase, from pairs of HIP events recorded on the
+// solver stream around each application (opts.profile = 1 only).
+struct PhaseTimer {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  int idx = 0;       // pairs recorded since the last collection
+  double acc = 0;    // seconds collected so far in this call
+};
+enum { PHASE_VEL = 0, PHASE_PRES = 1, PHASE_ORTH = 2, NUM_PHASES = 3 };
+
 // Per-solver device scalars (one set per Krylov instance).
 struct Scalars {
   double rho[kMaxSys], rho_old[kMaxSys], alpha[kMaxSys], beta[kMaxSys];
@@ -250,6 +259,7 @@ struct stokes_ctx {
   int prof_on = 0, prof_idx = 0, prof_seen = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
   double prof_bytes = 0;
+  stokes::PhaseTimer phase[stokes::NUM_PHASES];  // phase times of stokes_solve_info (profile = 1)
 
   // pinned host mirror of the solver scalars
   stokes::Scalars* h_scal = nullptr;

@@ -36,6 +36,21 @@ int grid_for(int64_t rows);
 void ensure_lanes(stokes_ctx* c, int W, bool f32);
 bool prof_begin(stokes_ctx* c, const Sell* S, const void* vals, const void* avals);
 void prof_end(stokes_ctx* c, double bytes);
+// Phase timing (PHASE_*): begin returns false when profiling is off or the
+// stream is being captured; collect synchronises and returns the summed
+// seconds of the recorded pairs, which it releases for reuse.
+bool phase_begin(stokes_ctx* c, int k);
+void phase_end(stokes_ctx* c, int k) noexcept;
+double phase_collect(stokes_ctx* c, int k);
+struct PhaseScope {
+  stokes_ctx* c;
+  int k;
+  bool on;
+  PhaseScope(stokes_ctx* cc, int kk) : c(cc), k(kk), on(phase_begin(cc, kk)) {}
+  ~PhaseScope() {
+    if (on) phase_end(c, k);
+  }
+};
 void check_launch();
 
 template <class T> const T* pick(const DevBuf& b64, const DevBuf& b32);
@@ -127,7 +142,9 @@ template <class T>
 void p_out(stokes_ctx* c, int nrb, const T* src, double* dst);
 
 // FP64 right-hand side and adjoint gradient pieces
-void rhs(stokes_ctx* c, int nrb, const double* f, const double* ubc, double* F, double* g);
+// fI: staging buffer of n_int * dim * nrb doubles for the interior forcing
+// (nullptr: a context workspace)
+void rhs(stokes_ctx* c, int nrb, const double* f, const double* ubc, double* F, double* g, double* fI = nullptr);
 void adj_jp(stokes_ctx* c, int nrb, double* g);
 void adj_dJdf(stokes_ctx* c, int nrb, const double* lam, double* out);
 void adj_dJdmu(stokes_ctx* c, int nrb, const double* u_full, const double* lam, double* res_dev);

@@ -56,6 +56,42 @@ void prof_end(stokes_ctx* c, double bytes) {
   c->prof_bytes = bytes;
 }
 
+double phase_collect(stokes_ctx* c, int k) {
+  PhaseTimer& t = c->phase[k];
+  if (t.idx == 0) return t.acc;
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < t.idx; ++i) {
+    float ms = 0;
+    HIP_CHECK(hipEventElapsedTime(&ms, t.ev[i].first, t.ev[i].second));
+    t.acc += ms * 1e-3;
+  }
+  t.idx = 0;
+  return t.acc;
+}
+
+bool phase_begin(stokes_ctx* c, int k) {
+  if (!c->prof_on) return false;
+  PhaseTimer& t = c->phase[k];
+  if (t.ev.empty()) {
+    t.ev.resize(1024);
+    for (auto& pr : t.ev) {
+      HIP_CHECK(hipEventCreate(&pr.first));
+      HIP_CHECK(hipEventCreate(&pr.second));
+    }
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_CHECK(hipStreamIsCapturing(c->stream, &cs));
+  if (cs != hipStreamCaptureStatusNone) return false;
+  if (t.idx >= static_cast<int>(t.ev.size())) phase_collect(c, k);  // pool full: fold into acc
+  HIP_CHECK(hipEventRecord(t.ev[t.idx].first, c->stream));
+  return true;
+}
+
+void phase_end(stokes_ctx* c, int k) noexcept {
+  PhaseTimer& t = c->phase[k];
+  if (hipEventRecord(t.ev[t.idx].second, c->stream) == hipSuccess) t.idx++;
+}
+
 namespace {
 
 template <int V>
@@ -799,12 +835,12 @@ void p_out(stokes_ctx* c, int nrb, const T* src, double* dst) {
   check_launch();
 }
 
-void rhs(stokes_ctx* c, int nrb, const double* f, const double* ubc, double* F, double* g) {
+void rhs(stokes_ctx* c, int nrb, const double* f, const double* ubc, double* F, double* g, double* fI) {
   // F~ = (M_V f)_I - A_{I,Gamma} G: interior columns by the sliced-ELL mass
   // product on f_I, boundary columns on the rows that touch the boundary
   const int W = c->dim * nrb;
   if (f) {
-    double* fI = static_cast<double*>(c->workspace("rhs_fI", c->n_int * W * sizeof(double)));
+    if (!fI) fI = static_cast<double*>(c->workspace("rhs_fI", c->n_int * W * sizeof(double)));
     vel_in<double>(c, nrb, f, fI);
     spmv<double>(c, c->sA, c->MV64.as<double>(), W, fI, F, 1.0, nullptr, 0.0);
   } else {

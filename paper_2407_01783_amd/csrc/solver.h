@@ -11,6 +11,8 @@ struct SolveStats {
   int inner_u = 0, inner_p = 0, outer = 0, sweeps = 0;
   double seconds_orth = 0;
   std::vector<double> rel_res;  // per right-hand side, final true residual
+  std::vector<double> inv_bn;   // per right-hand side, 1 / ||b|| (0 for b = 0)
+  std::vector<double> hist;     // per outer iteration: estimated relative residual (max over right-hand sides)
 };
 
 // Solve K x = b with b = (F, g) in the internal FP64 layout, x = (xu, xp) as

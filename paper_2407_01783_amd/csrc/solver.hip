@@ -332,6 +332,7 @@ class Engine {
 
   // x = A~^{-1} b (velocity block)
   void vel_solve(const T* b, T* x) {
+    ops::PhaseScope phase(c_, PHASE_VEL);
     Prec pc{&c_->sA, A(), dA(), c_->bA, std::max(1, o_.cheb_degree), {}};
     const bool mg = o_.vel_pc == STOKES_VEL_MG;
     if (mg) pc.apply = [this](const T* r, T* z) { vel_vcycle<T>(c_, W_, r, z, 0); };
@@ -419,6 +420,7 @@ class Engine {
   // z = C r = alpha X^{-1} r + mu (1 + gamma) M_Q^{-1} r on the mean-free
   // pressures (X is singular on constants: its inverse acts on 1-perp)
   void cc_apply(const T* r, T* z) {
+    ops::PhaseScope phase(c_, PHASE_PRES);
     T* y = buf("cc_y", np());
     T* rm = buf("cc_r", np());
     ops::remove_mean_into<T>(c_, nrb_, r, rm);
@@ -451,6 +453,13 @@ class Engine {
   }
 
   // ------------------------------------------------------- helpers
+  // residual history: the largest per-right-hand-side estimate over ||b||
+  void record_hist(const std::vector<double>& est) {
+    double v = 0;
+    for (size_t r = 0; r < est.size(); ++r) v = std::max(v, est[r] * (r < st_.inv_bn.size() ? st_.inv_bn[r] : 0.0));
+    st_.hist.push_back(v);
+  }
+
   template <class TX, class TY>
   void axpy_rhs(int64_t nrows, bool vel, const double* a, const double* b, const TX* x, TY* y) {
     Coef8 ca{}, cb{};
@@ -600,6 +609,7 @@ class Engine {
     std::vector<int> active(R), kdone(R, 0);
     std::vector<double> s(R);
     for (int r = 0; r < R; ++r) {
+      if (!std::isfinite(hhost[r])) throw Error(STOKES_ERR_NONFINITE, "FGMRES: non-finite residual norm");
       beta[r] = std::sqrt(std::max(0.0, hhost[r]));
       active[r] = beta[r] > target[r];
       s[r] = active[r] ? 1.0 / beta[r] : 0.0;
@@ -658,6 +668,7 @@ class Engine {
     const bool queue_ahead = R == 1 && o_.inner_mode == STOKES_INNER_FIXED;
     bool z_queued = false;             // z_j already queued during step j - 1
     double est_prev = g[0];            // residual estimate after the previous step (R = 1)
+    std::vector<double> last_est(beta);  // per right-hand side, for the residual history
     int j = 0;
     for (; j < m; ++j) {
       bool any = false;
@@ -694,6 +705,7 @@ class Engine {
       // CGS2 (the first update and the second projection share one pass
       // over the basis while it holds at most kFusedMax vectors)
       const double t0 = now();
+      const bool orth_timed = ops::phase_begin(c_, PHASE_ORTH);
       if (wk) mdot(V, j + 1, (const T*)wk, h1);
       else mdot(V, j + 1, (const TK*)wj, h1);
       if (j + 1 <= kFusedMax) {
@@ -717,6 +729,7 @@ class Engine {
       }
       // the second update also leaves the next preconditioner input (in T)
       mupdate(V, j + 1, h2, -1.0, wj, nrm, sig2dev, vin);
+      if (orth_timed) ops::phase_end(c_, PHASE_ORTH);
       HIP_CHECK(hipMemcpyAsync(hhost, hdev, 3 * 64 * 8 * sizeof(double), hipMemcpyDeviceToHost, c_->stream));
       if (queue_ahead && j + 1 < m && est_prev > kQueueAhead * target[0]) {
         HIP_CHECK(hipEventRecord(ev_h, c_->stream));
@@ -736,6 +749,8 @@ class Engine {
         const double sj = sig[j * R + r];
         for (int i = 0; i <= j; ++i)
           Hat(i, j, r) = sj * sig[i * R + r] * (hhost[i * R + r] + hhost[64 * 8 + i * R + r]);
+        if (!std::isfinite(hhost[2 * 64 * 8 + r]) || !std::isfinite(hhost[r]) || !std::isfinite(hhost[64 * 8 + r]))
+          throw Error(STOKES_ERR_NONFINITE, "FGMRES: non-finite Gram-Schmidt sums at step " + std::to_string(j));
         const double wn = std::sqrt(std::max(0.0, hhost[2 * 64 * 8 + r]));
         const double hn = sj * wn;
         if (log_level() >= 2) {
@@ -760,12 +775,14 @@ class Engine {
         kdone[r] = j + 1;
         const double est = std::fabs(g[(j + 1) * R + r]);
         if (r == 0) est_prev = est;
+        last_est[r] = est;
         if (est <= target[r] || hn <= 1e-300) active[r] = 0;
         s[r] = active[r] && wn > 0 ? 1.0 : 0.0;
         sig[(j + 1) * R + r] = active[r] && wn > 0 ? 1.0 / wn : 0.0;
         dropped = dropped || !active[r];
       }
       st_.outer += 1;
+      record_hist(last_est);
       if (j + 1 < m) {
         bool any_left = false;
         for (int r = 0; r < R; ++r) any_left = any_left || active[r];
@@ -880,6 +897,11 @@ class Engine {
       axpy_rhs<T, double>(c_->n_int, true, al.data(), one.data(), vu, xu);
       axpy_rhs<double, double>(c_->n_p1, false, mal.data(), one.data(), q, s);
       ss = dots(nullptr, nullptr, s, s);
+      {
+        std::vector<double> sn(R);
+        for (int r = 0; r < R; ++r) sn[r] = std::sqrt(std::max(0.0, ss[r]));
+        record_hist(sn);
+      }
       any = false;
       for (int r = 0; r < R; ++r) {
         if (active[r] && !(std::sqrt(ss[r]) > target[r])) active[r] = 0;
@@ -922,6 +944,12 @@ int refine_loop(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, 
   double* rp = ru + nu;
   std::vector<double> bn = e64.dots(F, F, g, g);
   for (double& x : bn) x = std::sqrt(x);
+  for (int r = 0; r < nrb; ++r)
+    if (!std::isfinite(bn[r]))
+      throw Error(STOKES_ERR_NONFINITE, "right-hand side " + std::to_string(r) +
+                                            " is not finite (forcing, boundary data or loss gradient)");
+  st.inv_bn.assign(nrb, 0.0);
+  for (int r = 0; r < nrb; ++r) st.inv_bn[r] = bn[r] > 0 ? 1.0 / bn[r] : 0.0;
   st.rel_res.assign(nrb, 0.0);
   int status = STOKES_NOT_CONVERGED;
   std::vector<double> prev(nrb, 0.0);
@@ -940,6 +968,11 @@ int refine_loop(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, 
     bool done = true;
     for (int r = 0; r < nrb; ++r) {
       rn[r] = std::sqrt(rn[r]);
+      if (!std::isfinite(rn[r]))
+        throw Error(STOKES_ERR_NONFINITE, sweep == 0 && !x_zero
+                                              ? "the residual of the initial guess is not finite"
+                                              : "the solve produced a non-finite residual at refinement sweep " +
+                                                    std::to_string(sweep));
       st.rel_res[r] = bn[r] > 0 ? rn[r] / bn[r] : 0.0;
       if (bn[r] > 0 && st.rel_res[r] > o.rtol) done = false;
       // goal of this sweep: the final tolerance, or the reduction the inner
@@ -993,9 +1026,9 @@ int refine_loop(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, 
 }
 
 // ======================================================================
-// One rotational incremental pressure-correction step (the comparator of
-// Sec. 7.5: one velocity problem, one pressure Laplacian, one pressure mass
-// problem), each solved to a true FP64 relative residual <= rtol by inner CG
+// One rotational incremental pressure-correction step, the comparator of
+// Sec. 7.5 and Table 8: a momentum solve, then a pressure Poisson solve and a
+// pressure-mass solve, each solved to a true FP64 relative residual <= rtol by inner CG
 // in T with FP64 refinement:
 //   A u = F + B^T p_old;   d = B u - g;   L_Q phi = -alpha d;   M_Q psi = d;
 //   p = p_old + phi - mu psi, normalised to zero mean.
@@ -1028,6 +1061,10 @@ int projection_loop(stokes_ctx* c, const stokes_solve_opts& o, int nrb, const do
     const int64_t n = vel ? nu : np;
     HIP_CHECK(hipMemsetAsync(x, 0, n * sizeof(double), c->stream));
     std::vector<double> bn = vel ? e64.dots(b, b, nullptr, nullptr) : e64.dots(nullptr, nullptr, b, b);
+    for (int k = 0; k < nrb; ++k)
+      if (!std::isfinite(bn[k]))
+        throw Error(STOKES_ERR_NONFINITE, std::string("pressure-correction step: non-finite ") +
+                                              (vel ? "velocity" : "pressure") + " right-hand side");
     bool skip = true;
     for (int k = 0; k < nrb; ++k) skip = skip && std::sqrt(bn[k]) <= negligible[k];
     if (skip) return;
@@ -1037,7 +1074,11 @@ int projection_loop(stokes_ctx* c, const stokes_solve_opts& o, int nrb, const do
       ops::axpby<double>(c, n, 1.0, b, -1.0, r);  // r = b - K x
       std::vector<double> rn = vel ? e64.dots(r, r, nullptr, nullptr) : e64.dots(nullptr, nullptr, r, r);
       rel = 0;
-      for (int k = 0; k < nrb; ++k) rel = std::max(rel, bn[k] > 0 ? std::sqrt(rn[k] / bn[k]) : 0.0);
+      for (int k = 0; k < nrb; ++k) {
+        if (!std::isfinite(rn[k]))
+          throw Error(STOKES_ERR_NONFINITE, "pressure-correction step: non-finite residual");
+        rel = std::max(rel, bn[k] > 0 ? std::sqrt(rn[k] / bn[k]) : 0.0);
+      }
       if (rel <= o.rtol) break;
       if (mean_free) ops::remove_mean<double>(c, nrb, r);  // the pressure Laplacian acts on 1-perp
       if (sweep >= o.max_refine) {
@@ -1080,12 +1121,20 @@ int projection_loop(stokes_ctx* c, const stokes_solve_opts& o, int nrb, const do
   double* phi = ws("pj_phi", np);
   refined(false, true, bphi, phi,
           [&](const double* x, double* y) { ops::spmv<double>(c, c->sQ, c->LQ64.as<double>(), nrb, x, y, 1.0, nullptr, 0.0); },
-          [&](const T* rr, T* z) { e.x_solve(rr, z); }, neg_phi);
+          [&](const T* rr, T* z) {
+            ops::PhaseScope phase(c, PHASE_PRES);
+            e.x_solve(rr, z);
+          },
+          neg_phi);
   // 3. pressure mass
   double* psi = ws("pj_psi", np);
   refined(false, false, d, psi,
           [&](const double* x, double* y) { ops::spmv<double>(c, c->sQ, c->MQ64.as<double>(), nrb, x, y, 1.0, nullptr, 0.0); },
-          [&](const T* rr, T* z) { e.mq_solve(rr, z); }, neg_d);
+          [&](const T* rr, T* z) {
+            ops::PhaseScope phase(c, PHASE_PRES);
+            e.mq_solve(rr, z);
+          },
+          neg_d);
   // 4. p = p_old + phi - mu psi
   if (pold) HIP_CHECK(hipMemcpyAsync(xp, pold, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   else HIP_CHECK(hipMemsetAsync(xp, 0, np * sizeof(double), c->stream));

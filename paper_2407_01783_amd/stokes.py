@@ -125,8 +125,10 @@ class StokesProblem:
         return int(f.shape[0])
 
     # ----------------------------------------------------------- solves
-    def solve(self, f, ubc=None, method="coupled", x0=None, **opts):
-        """Solve for (u, p); returns (u, p, info dict).  f: [nrhs,] dim, n_p2."""
+    def solve(self, f, ubc=None, method="coupled", x0=None, hist_cap=0, **opts):
+        """Solve for (u, p); returns (u, p, info dict).  f: [nrhs,] dim, n_p2.
+        hist_cap > 0 returns up to that many residual-history entries as
+        info["res_hist"]."""
         nrhs = self._nrhs(f)
         f = self._vel(f, nrhs)
         ubc = self._vel(ubc, nrhs) if ubc is not None else None
@@ -137,6 +139,8 @@ class StokesProblem:
             x0u, x0p = self._vel(x0[0], nrhs), self._pres(x0[1], nrhs)
         o = _lib.default_opts(**opts)
         info = _lib.SolveInfo()
+        if hist_cap > 0:
+            info.attach_history(hist_cap)
         fn = self.lib.stokes_solve_coupled if method == "coupled" else self.lib.stokes_solve_schur
         if method not in ("coupled", "schur"):
             raise ValueError("method must be 'coupled' or 'schur'")
@@ -223,6 +227,7 @@ class StokesSolve(torch.autograd.Function):
         if info["status"] != 0:
             raise _lib.StokesError(info["status"], "forward solve did not converge")
         ctx.problem, ctx.opts = problem, opts
+        ctx.mu_val = mu_val  # the operator of this solve, restored for the adjoint
         ctx.shape = f.shape
         ctx.mu_like = mu if torch.is_tensor(mu) else None
         ctx.save_for_backward(u)
@@ -235,7 +240,16 @@ class StokesSolve(torch.autograd.Function):
         nrhs = u.shape[0]
         gu = torch.zeros_like(u) if grad_u is None else grad_u.reshape(u.shape)
         gp = None if grad_p is None else grad_p.reshape(nrhs, prob.n_p1)
-        _, _, dJdf, dJdmu, info = prob.adjoint(u, gu, gp, **ctx.opts)
+        # the adjoint needs the forward solve's operator: another solve on the
+        # same problem (or a set_mu call) may have changed mu since
+        mu_now = prob.mu
+        if mu_now != ctx.mu_val:
+            prob.set_mu(ctx.mu_val)
+        try:
+            _, _, dJdf, dJdmu, info = prob.adjoint(u, gu, gp, **ctx.opts)
+        finally:
+            if mu_now != ctx.mu_val:
+                prob.set_mu(mu_now)
         if info["status"] != 0:
             raise _lib.StokesError(info["status"], "adjoint solve did not converge")
         gmu = None

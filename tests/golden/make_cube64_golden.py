@@ -1,0 +1,90 @@
+"""Write tests/golden/cube64_oracle.txt: the FP64 oracle solution of the 64^3
+benchmark workload, sampled on a seeded set of elements.
+
+Workload: unit cube, 64 cells per side, Kuhn split, interior-vertex jitter
+0.1 h with mesh seed 1, mu = 1e-3, dt = 5e-3 (alpha = 200), Taylor-Hood
+P2/P1, Fourier forcing of seed 1001, homogeneous Dirichlet velocity.
+
+The discrete problem is the saddle-point system of Sec. 2.2 with the velocity
+block alpha M_V + mu L_V (the A~_{lambda,3} form of Sec. 3.2).  The oracle
+solves it by preconditioned MINRES at rtol 1e-14, then applies one
+residual-correction sweep (a second MINRES solve on the true residual), so
+that the stored solution's error sits far below the 1e-8 error bar of the
+solver under test.
+
+Stored: the ids of 400 sampled elements (seeded draw), the velocity at every
+P2 node of those elements, the pressure at their vertices, the global norms
+||u||_M (M = I_d (x) M_s over all P2 nodes) and ||p||_{M_Q}, and the true
+relative residual of the stored solution.  The error in the M-norm of the
+paper's error definition is then estimated on the sampled elements:
+    sum_K e_K^T M_K e_K / sum_K u_K^T M_K u_K
+over the sampled K, an unbiased ratio of the element sums that make up
+||e||_M^2 / ||u||_M^2.
+
+Runs on the CPU only, calling nothing but oracle/ and the seeded input
+generators (about 40 minutes and 12 GB on one core).  Usage:
+    python tests/golden/make_cube64_golden.py [out_path]
+"""
+
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import mesh as omesh  # noqa: E402
+from oracle import stokes as ostokes  # noqa: E402
+from paper_2407_01783_amd import inputs  # noqa: E402
+
+N, SEED, JITTER, MU, ALPHA = 64, 1, 0.1, 1e-3, 200.0
+N_SAMPLE_ELEMS = 400
+
+
+def main(out):
+    t0 = time.time()
+    mesh = omesh.KuhnMesh(3, N, seed=SEED, jitter=JITTER)
+    S = ostokes.StokesSystem(mesh, MU, ALPHA)
+    f = inputs.fourier_forcing(mesh.p2coords, inputs.forcing_seed(SEED))
+    F, g = S.rhs(f)
+    print(f"assembled in {time.time() - t0:.0f} s", flush=True)
+    U, P, info = S.solve_minres(F, g, rtol=1e-14, maxiter=400)
+    r0 = S.residual(U, P, F, g)
+    print(f"minres info {info}, true rel res {r0:.3e} ({time.time() - t0:.0f} s)", flush=True)
+    # one correction sweep on the true residual
+    RU, RP = S.apply_coupled(U, P, gamma=0.0)
+    dU, dP, info2 = S.solve_minres(F - RU, g - RP, rtol=1e-10, maxiter=400)
+    U, P = U + dU, S.normalize_pressure(P + dP)
+    res = S.residual(U, P, F, g)
+    print(f"corrected: info {info2}, true rel res {res:.3e} ({time.time() - t0:.0f} s)", flush=True)
+
+    u = S.full_velocity(U)  # (3, n_p2), zero on the boundary
+    unorm = np.sqrt(sum(float(u[c] @ (S.mats.Ms @ u[c])) for c in range(3)))
+    pnorm = np.sqrt(float(P @ (S.mats.MQ @ P)))
+    rng = np.random.default_rng(20250701)
+    elems = np.sort(rng.choice(mesh.n_e, size=N_SAMPLE_ELEMS, replace=False))
+    vnodes = np.unique(mesh.p2[elems].ravel())
+    pverts = np.unique(mesh.elems[elems].ravel())
+    with open(out, "w") as fh:
+        fh.write("# FP64 oracle solution of the 64^3 benchmark workload (see make_cube64_golden.py)\n")
+        fh.write(f"# n {N} mesh_seed {SEED} jitter {JITTER} mu {MU!r} alpha {ALPHA!r} forcing_seed "
+                 f"{inputs.forcing_seed(SEED)}\n")
+        fh.write(f"rel_res {res!r}\n")
+        fh.write(f"unorm_M {unorm!r}\n")
+        fh.write(f"pnorm_MQ {pnorm!r}\n")
+        fh.write(f"elems {len(elems)}\n")
+        fh.write(" ".join(str(int(e)) for e in elems) + "\n")
+        fh.write(f"vel {len(vnodes)}\n")
+        for v in vnodes:
+            fh.write(f"{int(v)} {u[0, v]!r} {u[1, v]!r} {u[2, v]!r}\n")
+        fh.write(f"p {len(pverts)}\n")
+        for k in pverts:
+            fh.write(f"{int(k)} {P[k]!r}\n")
+    print(f"wrote {out} ({time.time() - t0:.0f} s)", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                            "cube64_oracle.txt"))

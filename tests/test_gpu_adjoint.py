@@ -85,3 +85,34 @@ def test_autograd_function_matches_oracle_gradient(small):
     assert _rel(ft.grad.cpu().numpy(), dJdf) <= 1e-8
     assert abs(float(mu.grad) - dJdmu) <= 1e-8 * abs(dJdmu)
     assert p.shape == (S.np1,)
+
+
+def test_autograd_two_solves_at_different_mu(small):
+    """Two StokesSolve calls on one problem at different mu, backpropagated
+    together: each backward must run the adjoint with its own forward
+    operator (mu saved by the forward pass), and the problem's mu is left as
+    the caller set it."""
+    from paper_2407_01783_amd.stokes import StokesSolve
+    P, S = small
+    mesh_ = S.mesh
+    f = inputs.fourier_forcing(mesh_.p2coords, inputs.forcing_seed(SEED, 2))
+    ut = S.full_velocity(S.solve(*S.rhs(inputs.fourier_forcing(mesh_.p2coords, inputs.target_seed(SEED))))[0])
+    target = torch.tensor(ut, device="cuda")
+    ft = torch.tensor(f, device="cuda", requires_grad=True)
+    mus = (MU, 3.0 * MU)
+    mut = [torch.tensor(m, dtype=torch.float64, requires_grad=True) for m in mus]
+    opts = dict(method="coupled", precision=0, rtol=1e-12)
+    us = [StokesSolve.apply(ft, m, P, opts)[0] for m in mut]
+    assert P.mu == mus[1]
+    loss = sum(0.5 * ((u - target) ** 2).sum() for u in us)
+    loss.backward()
+    assert P.mu == mus[1]
+    gf = np.zeros_like(f)
+    for m, u, mt in zip(mus, us, mut):
+        Sm = ostokes.StokesSystem(mesh_, m, ALPHA)
+        un = u.detach().cpu().numpy()
+        dJdf, dJdmu, _, _ = Sm.adjoint_gradient(un, un - ut)
+        gf += dJdf
+        assert abs(float(mt.grad) - dJdmu) <= 1e-8 * abs(dJdmu), (m, float(mt.grad), dJdmu)
+    assert _rel(ft.grad.cpu().numpy(), gf) <= 1e-8
+    P.set_mu(MU)

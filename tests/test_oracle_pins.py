@@ -424,6 +424,97 @@ def test_projection_step_fixed_point_and_pieces():
         assert np.abs(P1 - P2).max() <= 1e-8 * np.abs(P2).max()
 
 
+def _inf_sup_range(s, limit):
+    """Spectrum on 1-perp of L_Q^-1 B M_V^-1 B^T (limit "mass") or of
+    M_Q^-1 B L_V^-1 B^T (limit "visc"), by dense generalized eigenvalues.
+
+    Integration by parts over V_h in H^1_0 bounds both above by 1
+    (p^T B M^-1 B^T p = sup_v (grad p, v)^2 / |v|^2 <= |grad p|^2, and
+    p^T B L^-1 B^T p <= |p|^2 |div v|^2 / |grad v|^2 <= |p|^2); the discrete
+    inf-sup condition of the Taylor-Hood pair bounds them below by beta^2 > 0."""
+    import scipy.linalg as sla
+    Bm = sp.hstack(s.B_I).toarray()
+    blk = (s.mats.Ms if limit == "mass" else s.mats.Ls)[s.I][:, s.I].toarray()
+    X = Bm @ np.linalg.solve(sla.block_diag(*([blk] * s.d)), Bm.T)
+    Y = (s.mats.LQ if limit == "mass" else s.mats.MQ).toarray()
+    n = X.shape[0]
+    Q = np.linalg.qr(np.hstack([np.ones((n, 1)), np.eye(n)[:, : n - 1]]))[0][:, 1:]
+    ev = sla.eigh(Q.T @ X @ Q, Q.T @ Y @ Q, eigvals_only=True)
+    return ev.min(), ev.max()
+
+
+class _MutatedProjection(stokes.StokesSystem):
+    """The pressure-correction step with one deliberate mistake (for the pin
+    below): the sign of phi, the sign of the mu psi term, or alpha dropped
+    from phi's right-hand side."""
+
+    def __init__(self, *a, mutation, **kw):
+        super().__init__(*a, **kw)
+        self.mutation = mutation
+
+    def projection_step(self, f, ubc=None, p_old=None):
+        import scipy.sparse.linalg as spla
+        F, g = self.rhs(f, ubc)
+        p0 = np.zeros(self.np1) if p_old is None else p_old
+        bu = F + np.stack([self.B_I[c].T @ p0 for c in range(self.d)])
+        U = spla.spsolve(self.Avel_II.tocsc(), bu.ravel()).reshape(self.d, self.nI)
+        dv = sum(self.B_I[c] @ U[c] for c in range(self.d)) - g
+        scale = 1.0 if self.mutation == "drop_alpha" else self.alpha
+        phi = np.linalg.lstsq(self.mats.LQ.toarray(), -scale * dv, rcond=None)[0]
+        psi = np.linalg.solve(self.mats.MQ.toarray(), dv)
+        sphi = -1.0 if self.mutation == "flip_phi" else 1.0
+        spsi = 1.0 if self.mutation == "flip_psi" else -1.0
+        return U, self.normalize_pressure(p0 + sphi * phi + spsi * self.mu * psi)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 4), (3, 2)])
+def test_projection_step_contracts_at_the_inf_sup_rate(dim, n):
+    """Iterating the pressure-correction step from p = 0 is a Richardson
+    iteration on the Schur complement S = B A^-1 B^T: with exact solves the
+    pressure error obeys e+ = (I - C S) e, C = alpha L_Q^-1 + mu M_Q^-1 (the
+    Cahouet-Chabard operator of Sec. 4.1).  In the mass limit (mu -> 0,
+    A = alpha M) C S = L_Q^-1 B M^-1 B^T and in the viscous limit (alpha -> 0,
+    A = mu L) C S = M_Q^-1 B L^-1 B^T; both have spectrum [beta^2, <= 1]
+    (see _inf_sup_range), so C S is self-adjoint in the S inner product and
+    every step shrinks ||e||_S by at least the factor 1 - beta^2.
+
+    A flipped sign of phi or of mu psi, or alpha dropped from phi's
+    right-hand side, breaks this bound in one of the two limits (the error
+    grows, or shrinks by a factor near 1); each mutant is run to show it."""
+    m = mesh.KuhnMesh(dim, n, seed=1, jitter=0.1)
+    f = inputs.fourier_forcing(m.p2coords, inputs.forcing_seed(1))
+
+    def ratios(s, steps=6):
+        F, g = s.rhs(f)
+        _, Ps = s.solve_direct(F, g)
+        Bm = sp.hstack(s.B_I).toarray()
+        Ad = s.Avel_II.toarray()
+
+        def snorm(e):
+            return math.sqrt(float(e @ (Bm @ np.linalg.solve(Ad, Bm.T @ e))))
+
+        p = np.zeros(s.np1)
+        e0 = snorm(p - Ps)
+        out = []
+        for _ in range(steps):
+            _, p = s.projection_step(f, None, p)
+            e1 = snorm(p - Ps)
+            out.append(e1 / e0)
+            e0 = e1
+        return np.array(out)
+
+    for limit, mu, alpha, mutations in (("mass", 1e-9, 1e3, ("flip_phi", "drop_alpha")),
+                                        ("visc", 50.0, 1e-9, ("flip_psi",))):
+        s = stokes.StokesSystem(m, mu, alpha)
+        lo, hi = _inf_sup_range(s, limit)
+        assert 0 < lo and hi <= 1 + 1e-10, (limit, lo, hi)
+        r = ratios(s)
+        assert np.all(r <= 1 - lo + 1e-8), (limit, lo, r)
+        for mut in mutations:
+            rm = ratios(_MutatedProjection(m, mu, alpha, mutation=mut), steps=3)
+            assert np.any(rm > 1 - lo + 1e-3), (limit, mut, lo, rm)
+
+
 # ------------------------------------------------------------------- solves
 
 
