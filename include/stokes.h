@@ -275,6 +275,21 @@ stokes_status stokes_apply(stokes_ctx* ctx, int32_t op, int32_t precision, int32
 stokes_status stokes_residual(stokes_ctx* ctx, int32_t nrhs, const double* f, const double* ubc,
                               const double* u, const double* p, double* rel_res_host);
 
+/* Allocation-free variant of stokes_residual, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): same arguments, same result, but it calls
+ * no hipMalloc/hipFree and no allocating library routine.  Its temporaries
+ * live in a fixed device array of 128 MiB that the library holds on every GPU
+ * it has run on until the process ends (its address is looked up when a
+ * context is assembled).  Right-hand sides are processed one at a time, each
+ * needing 16 (n_int dim + n_p1) bytes (n_int = stokes_query sizes[2]); a mesh
+ * beyond 128 MiB returns STOKES_ERR_UNSUPPORTED (the 64^3 cube needs 103 MB).
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (from several host threads or contexts) race and must be serialised by the
+ * caller. */
+stokes_status stokes_residual_noalloc(stokes_ctx* ctx, int32_t nrhs, const double* f, const double* ubc,
+                                      const double* u, const double* p, double* rel_res_host);
+
 /* sizes[0..9] as in stokes_problem_sizes, for an assembled context;
  * sizes[10] = entries of B_I Lambda_V^-1 B_I^T (export_csr which 9),
  * sizes[11] = 0 (reserved). */

@@ -75,6 +75,7 @@ EXPORTS = [
     "stokes_assemble", "stokes_solve_schur", "stokes_solve_coupled", "stokes_solve_adjoint", "stokes_apply",
     "stokes_residual", "stokes_query", "stokes_set_mu", "stokes_set_stream", "stokes_export_mesh",
     "stokes_export_csr", "stokes_bounds", "stokes_destroy", "stokes_last_error", "stokes_projection_step",
+    "stokes_residual_noalloc",
 ]
 
 _lib = None
@@ -110,6 +111,7 @@ def load():
         "stokes_projection_step": (st, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, po, pi]),
         "stokes_apply": (st, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P]),
         "stokes_residual": (st, [_P, ctypes.c_int32, _P, _P, _P, _P, _D]),
+        "stokes_residual_noalloc": (st, [_P, ctypes.c_int32, _P, _P, _P, _P, _D]),
         "stokes_query": (st, [_P, _I64]),
         "stokes_set_mu": (st, [_P, ctypes.c_double]),
         "stokes_set_stream": (st, [_P, _P]),

@@ -8,16 +8,44 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 
 #include "kernels.h"
 #include "ops.h"
 #include "solver.h"
+
+// Device scratch of stokes_residual_noalloc: one copy per GPU, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, never the
+// device memory: kernels and copies take the per-device address that
+// hipGetSymbolAddress returns (g_scratch_dev below).
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace stokes {
 
 namespace {
 thread_local std::string g_last_error;
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev`, looked up once per device with
+// that device current (the caller makes it current).
+void* scratch_on(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) throw Error(STOKES_ERR_UNSUPPORTED, "device index out of range for scratch");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Error(STOKES_ERR_HIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    }
+    g_scratch_dev[dev] = p;
+  }
+  return g_scratch_dev[dev];
+}
 }  // namespace
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
@@ -500,6 +528,7 @@ stokes_status stokes_assemble(const stokes_problem* prob, void* hip_stream, stok
     c->prob = *prob;
     c->strain = (prob->flags & STOKES_FLAG_STRAIN) != 0;
     HIP_CHECK(hipGetDevice(&c->device));
+    (void)scratch_on(c->device);  // set-up of the allocation-free residual, once per device
     c->user_stream = static_cast<hipStream_t>(hip_stream);
     if (const char* e = std::getenv("STOKES_GRAPHS")) c->use_graphs = std::atoi(e) != 0;
     if (const char* e = std::getenv("STOKES_CG_CHECK")) c->cg_check_every = std::max(1, std::atoi(e));
@@ -736,6 +765,56 @@ stokes_status stokes_residual(stokes_ctx* c, int32_t nrhs, const double* f, cons
         rel[r0 + r] = den > 0 ? std::sqrt(num / den) : std::sqrt(num);
       }
       r0 += nrb;
+    }
+    return STOKES_OK;
+  });
+}
+
+stokes_status stokes_residual_noalloc(stokes_ctx* c, int32_t nrhs, const double* f, const double* ubc,
+                                      const double* u, const double* p, double* rel) {
+  return guard([&]() -> stokes_status {
+    if (!c) throw Error(STOKES_ERR_ARG, "ctx is NULL");
+    if (nrhs < 1) throw Error(STOKES_ERR_ARG, "nrhs must be >= 1");
+    if (!f || !u || !p || !rel) throw Error(STOKES_ERR_ARG, "NULL array argument");
+    const int D = c->dim;
+    const int64_t nu = c->n_int * D, np = c->n_p1;  // one right-hand side at a time
+    const size_t need = size_t(2 * nu + 2 * np) * sizeof(double);
+    if (need > kScratchBytes)
+      throw Error(STOKES_ERR_UNSUPPORTED, "stokes_residual_noalloc needs " + std::to_string(need) +
+                                              " bytes of scratch for this mesh; the limit is " +
+                                              std::to_string(kScratchBytes) + " (use stokes_residual)");
+    HIP_CHECK(hipSetDevice(c->device));
+    double* base = static_cast<double*>(scratch_on(c->device));
+    StreamScope scope(c);
+    // [F | xu | g | xp]: the residual overwrites (F, g) in place; xu first
+    // stages the interior forcing.  Every slot is fully written before it is
+    // read, so nothing left by an earlier call is used.
+    double* F = base;
+    double* xu = F + nu;
+    double* g = xu + nu;
+    double* xp = g + np;
+    double* res = c->red.result.as<double>();
+    double h[2 * 3 + 2];
+    for (int r = 0; r < nrhs; ++r) {
+      const int64_t vo = int64_t(r) * D * c->n_p2, po = int64_t(r) * c->n_p1;
+      ops::rhs(c, 1, f + vo, ubc ? ubc + vo : nullptr, F, g, xu);
+      ops::remove_mean<double>(c, 1, g);
+      ops::vel_in<double>(c, 1, u + vo, xu);
+      ops::p_in<double>(c, 1, p + po, xp);
+      ops::dot_dev<double>(c, c->n_int, D, F, F, nullptr, res);
+      ops::dot_dev<double>(c, c->n_p1, 1, g, g, nullptr, res + D);
+      ops::momentum<double>(c, 1, xu, xp, nullptr, F, -1.0, F);  // r_u = F - (A u - B^T p)
+      ops::Bmul<double>(c, 1, xu, g, -1.0, g, 1.0);              // r_p = g - B u
+      ops::dot_dev<double>(c, c->n_int, D, F, F, nullptr, res + D + 1);
+      ops::dot_dev<double>(c, c->n_p1, 1, g, g, nullptr, res + 2 * D + 1);
+      HIP_CHECK(hipMemcpyAsync(h, res, (2 * D + 2) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIP_CHECK(hipStreamSynchronize(c->stream));
+      double den = h[D], num = h[2 * D + 1];
+      for (int d = 0; d < D; ++d) {
+        den += h[d];
+        num += h[D + 1 + d];
+      }
+      rel[r] = den > 0 ? std::sqrt(num / den) : std::sqrt(num);
     }
     return STOKES_OK;
   });
