@@ -13,8 +13,13 @@ relative residual is <= 1e-8.  The
 operator is assembled once, before the timed region; the forcing is resident
 in HBM.
 
-Printed: one JSON line with the mixed-precision DOFs/s as `value`, the FP64
-path's DOFs/s beside it, the roofline of the dominant kernel (the FP32
+Printed: one JSON line with the mixed-precision DOFs/s as `value`, and beside
+it the same solve in other arithmetic: the FP64 path, the mixed path with
+every preconditioner value stored in FP32 (no half-precision or bfloat16
+copies), the mixed path with FP32 inner CG solves to a tolerance (Chebyshev-
+Jacobi degree 4 preconditioner), and the mixed path with the FGMRES basis in
+FP32; one pressure-correction step (the comparator of Sec. 7.5, Table 8) with
+the same tolerance; the roofline of the dominant kernel (the FP32
 Chebyshev-Jacobi SpMV step on the velocity block, timed with HIP events on the
 solver's stream during the timed solves) and the CPU oracle baseline.
 """
@@ -89,9 +94,42 @@ def measured_traffic(workload, nrhs, strain=False):
     return float(fields["hbm_bytes_per_launch"])
 
 
+ORACLE_ITERS_FILE = os.path.join(ROOT, "tests", "golden", "cube64_oracle_iters.txt")
+
+
+def cpu_baseline_sampled(dim, n, mesh_seed, mu, alpha, fseed, iters=2):
+    """The FP64 oracle (preconditioned MINRES) on the benchmark workload
+    itself, timed on a bounded sample: `iters` MINRES iterations (assembly
+    excluded, as on the GPU side), scaled to a full solve by the oracle's own
+    iteration count to a true relative residual <= 1e-8 on this workload
+    (tests/golden/cube64_oracle_iters.txt, written by an oracle-only script)."""
+    from oracle import mesh as omesh
+    from oracle import stokes as ostokes
+    from paper_2407_01783_amd import inputs
+    with open(ORACLE_ITERS_FILE) as fh:
+        k_full = next(int(ln.split()[1]) for ln in fh if ln.startswith("minres_iters_1e-8"))
+    t0 = time.perf_counter()
+    m = omesh.KuhnMesh(dim, n, seed=mesh_seed, jitter=0.1)
+    S = ostokes.StokesSystem(m, mu, alpha)
+    F, g = S.rhs(inputs.fourier_forcing(m.p2coords, fseed))
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    S.solve_minres(F, g, rtol=1e-30, maxiter=iters)
+    dt = time.perf_counter() - t0
+    per_it = dt / iters
+    dofs = dim * m.n_p2 + m.n_p1
+    return {"value": dofs / (per_it * k_full), "unit": "DOFs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} iterations of the oracle's preconditioned MINRES on this workload "
+                      f"({dofs} DOFs; {dt:.1f} s, {per_it:.1f} s per iteration; oracle assembly {setup:.0f} s "
+                      f"excluded), scaled to the {k_full} iterations the oracle needs for a true rel-res <= 1e-8 "
+                      f"here; scipy sparse kernels run on one thread"}
+
+
 def cpu_baseline(dim, mesh_seed, mu, alpha, fseed, n_sample):
     """The FP64 oracle (MINRES, block preconditioner) on a smaller mesh of the
-    same workload family, solved to a true relative residual <= 1e-8."""
+    same workload family, solved to a true relative residual <= 1e-8 (used
+    for the workloads whose own oracle system is too large to assemble in a
+    benchmark run)."""
     from oracle import mesh as omesh
     from oracle import stokes as ostokes
     from paper_2407_01783_amd import inputs
@@ -121,9 +159,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=16, help="mesh size of the CPU oracle sample")
     ap.add_argument("--opt", action="append", default=[], help="solver option override key=value")
-    ap.add_argument("--projection", action="store_true",
-                    help="also time one pressure-correction step (the comparator of the paper's Sec. 7.5) with the "
-                         "same tolerance, and report the solve / projection time ratio")
+    ap.add_argument("--no-projection", action="store_true",
+                    help="skip timing one pressure-correction step (the comparator of the paper's Sec. 7.5) with "
+                         "the same tolerance")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FP32-storage and tolerance-inner mixed legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed solves, copy 1 GiB device-to-device 3 times (a kernel of known size "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -182,6 +222,19 @@ def main():
     bytes_per = infos[-1]["spmv_bytes"]
     achieved = bytes_per / (kern_s / launches) / 1e9 if launches else None
 
+    def leg(el, infos_):
+        okl = all(i["status"] == 0 and i["rel_res"] <= opts["rtol"] for i in infos_)
+        return {"value": dofs * args.steps / el, "ms_per_step": el / args.steps * 1e3, "converged": okl,
+                "outer_iters": infos_[-1]["outer_iters"], "inner_iters_u": infos_[-1]["inner_iters_u"],
+                "inner_iters_p": infos_[-1]["inner_iters_p"], "rel_res": max(i["rel_res"] for i in infos_)}
+
+    # phase times (GPU time by HIP events) of one more mixed solve, outside
+    # the timed region (its events would perturb the timed solves)
+    _, pinfos = run(1, 1, 0, 2)
+    pi = pinfos[-1]
+    phases = {"inner_u_ms": pi["seconds_inner_u"] * 1e3, "inner_p_ms": pi["seconds_inner_p"] * 1e3,
+              "orth_ms": pi["seconds_orth"] * 1e3, "total_ms": pi["seconds_total"] * 1e3}
+
     fp64 = None
     if not args.no_fp64:
         el64, infos64 = run(0, args.steps, args.warmup, 0)
@@ -201,8 +254,43 @@ def main():
         print(f"[bench] mixed, FP32 Arnoldi basis: {el32 / args.steps * 1e3:.1f} ms/solve", file=sys.stderr,
               flush=True)
 
+    # BJ-style FP32 inner solves: inner CG to a tolerance, Chebyshev-Jacobi
+    # degree 4 preconditioner (the default leg keeps the fixed inner operators)
+    tol_inner = None
+    fp32_storage = None
+    if not args.no_variants and method == "coupled":
+        el_t, infos_t = run(1, args.steps, args.warmup, 0, inner_mode=0, cheb_degree=4)
+        tol_inner = leg(el_t, infos_t)
+        tol_inner["options"] = "inner_mode=TOL, cheb_degree=4, inner_rtol_u=%g, inner_rtol_p=%g" % (
+            opts["inner_rtol_u"], opts["inner_rtol_p"])
+        print(f"[bench] mixed, FP32 inner CG to tolerance: {el_t / args.steps * 1e3:.1f} ms/solve", file=sys.stderr,
+              flush=True)
+        # every preconditioner value in FP32: a second context built without
+        # the half-precision A D^-1 / bfloat16 direction / half pressure levels
+        saved = {k: os.environ.get(k) for k in ("STOKES_VEL_HALF", "STOKES_VEL_BF", "STOKES_PMG_HALF")}
+        for k in saved:
+            os.environ[k] = "0"
+        try:
+            prob32 = StokesProblem(dim, n, mesh_seed=seed, jitter=0.1, mu=mu, alpha=alpha, strain=args.strain)
+        finally:
+            for k, v in saved.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+        main_prob, prob = prob, prob32
+        try:
+            el_s, infos_s = run(1, args.steps, args.warmup, 0)
+        finally:
+            prob = main_prob
+            del prob32
+            torch.cuda.empty_cache()
+        fp32_storage = leg(el_s, infos_s)
+        print(f"[bench] mixed, FP32 preconditioner storage: {el_s / args.steps * 1e3:.1f} ms/solve",
+              file=sys.stderr, flush=True)
+
     projection = None
-    if args.projection:
+    if not args.no_projection:
         popts = dict(precision=1, rtol=opts["rtol"], max_inner=5000, max_refine=30)
 
         def proj():
@@ -230,7 +318,10 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(dim, seed, mu, alpha, fseed, args.cpu_n)
+        if args.workload == "cube64" and os.path.exists(ORACLE_ITERS_FILE):
+            cpu = cpu_baseline_sampled(dim, n, seed, mu, alpha, fseed)
+        else:
+            cpu = cpu_baseline(dim, seed, mu, alpha, fseed, args.cpu_n)
 
     value = dofs * args.steps / el_mixed
     line = {
@@ -244,7 +335,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f64 outer + f32 inner (fp16/bf16-stored preconditioner values)",
         "data": "synthetic",
         "config": {"workload": desc, "nrhs": args.nrhs, "method": method,
                    "solver": {k: v for k, v in opts.items()}, "converged": ok,
@@ -254,6 +345,9 @@ def main():
         "fp64": fp64,
         "mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
         "mixed_fgmres_fp32_basis": fgmres_fp32,
+        "mixed_fp32_storage": fp32_storage,
+        "mixed_tol_inner": tol_inner,
+        "phases": phases,
         "projection": projection,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,

@@ -119,7 +119,8 @@ typedef struct {
   int32_t coupled_pc;     /* STOKES_PC_* */
   int32_t max_refine;     /* cap on iterative-refinement sweeps */
   int32_t profile;        /* 1: time the dominant SpMV with HIP events (one
-                             launch in seven, on the solver's stream) */
+                             launch in seven, on the solver's stream); 2: also
+                             the phase times of stokes_solve_info */
   int32_t inner_its_u;    /* > 0: every inner velocity CG runs exactly this many
                              iterations (no convergence checks); 0: use inner_rtol_u */
   int32_t inner_its_p;    /* the same for the inner pressure CG (0: inner_rtol_p) */
@@ -146,7 +147,7 @@ typedef struct {
   double seconds_total;   /* wall time of the call */
   double spmv_seconds;    /* summed duration of the timed SpMV launches */
   double spmv_bytes;      /* algorithmic bytes of one timed SpMV launch */
-  /* Phase times (opts->profile = 1; 0 otherwise): GPU time summed over every
+  /* Phase times (opts->profile = 2; 0 otherwise): GPU time summed over every
    * application of the phase, measured by HIP events on the solver's stream
    * (so work queued ahead of the host is attributed correctly). */
   double seconds_inner_u; /* velocity-block solves A~^{-1} (Sec. 3) */

@@ -17,6 +17,10 @@ problem ...", arXiv 2407.01783):
 * ``fem``    -- element matrices by exact barycentric integration and global
   assembly of M_V, L_V, B, M_Q, L_Q and the lumped Lambda_V (Sec. 2.2,
   Sec. 3.2, Sec. 4.1).
+* ``p3``     -- the Taylor-Hood P3/P2 pair on the same Kuhn mesh (the paper's
+  second element pair, Sec. 3.3, Table 4): P3 numbering on the (3n+1)^d
+  lattice, exact P3/P2 reference integrals, closed-form int |phi_i|, and the
+  assembly; ``stokes`` solves with these matrices unchanged.
 * ``stokes`` -- Dirichlet elimination and lifting, the saddle-point system
   A U - B^T P = F, B U = g (Sec. 2.2, Eq. "Saddle_point_A_BT_B"), its direct or
   MINRES solution with the pressure normalised to zero mean, the true coupled
@@ -27,4 +31,4 @@ where the paper is silent or garbled are listed in the repository's design
 notes; the ones that matter here are repeated in the docstrings.
 """
 
-from . import mesh, fem, stokes  # noqa: F401
+from . import mesh, fem, stokes, p3  # noqa: F401

@@ -106,6 +106,7 @@ void check_opts(const stokes_solve_opts* o) {
     throw Error(STOKES_ERR_ARG, "inner_its_u / inner_its_p must be in [0, 1000]");
   if (o->vel_pc != STOKES_VEL_CHEB && o->vel_pc != STOKES_VEL_MG) throw Error(STOKES_ERR_ARG, "vel_pc");
   if (o->arnoldi_fp64 < 0 || o->arnoldi_fp64 > 2) throw Error(STOKES_ERR_ARG, "arnoldi_fp64 must be 0, 1 or 2");
+  if (o->profile < 0 || o->profile > 2) throw Error(STOKES_ERR_ARG, "profile must be 0, 1 or 2");
 }
 
 template <class F>
@@ -190,7 +191,7 @@ double wall() {
 }
 
 void prof_start(stokes_ctx* c, const stokes_solve_opts* o) {
-  c->prof_on = o->profile ? 1 : 0;
+  c->prof_on = o->profile;
   c->prof_idx = 0;
   c->prof_seen = 0;
   for (auto& t : c->phase) {

@@ -148,7 +148,7 @@ struct MgHier {
 };
 
 // GPU time of one solver phase, from pairs of HIP events recorded on the
-// solver stream around each application (opts.profile = 1 only).
+// solver stream around each application (opts.profile = 2 only).
 struct PhaseTimer {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   int idx = 0;       // pairs recorded since the last collection

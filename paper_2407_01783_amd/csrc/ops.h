@@ -36,7 +36,7 @@ int grid_for(int64_t rows);
 void ensure_lanes(stokes_ctx* c, int W, bool f32);
 bool prof_begin(stokes_ctx* c, const Sell* S, const void* vals, const void* avals);
 void prof_end(stokes_ctx* c, double bytes);
-// Phase timing (PHASE_*): begin returns false when profiling is off or the
+// Phase timing (PHASE_*, opts.profile = 2): begin returns false when it is off or the
 // stream is being captured; collect synchronises and returns the summed
 // seconds of the recorded pairs, which it releases for reuse.
 bool phase_begin(stokes_ctx* c, int k);

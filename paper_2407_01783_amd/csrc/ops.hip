@@ -70,7 +70,7 @@ double phase_collect(stokes_ctx* c, int k) {
 }
 
 bool phase_begin(stokes_ctx* c, int k) {
-  if (!c->prof_on) return false;
+  if (c->prof_on < 2) return false;
   PhaseTimer& t = c->phase[k];
   if (t.ev.empty()) {
     t.ev.resize(1024);

@@ -5,7 +5,7 @@
   gradient returns STOKES_ERR_NONFINITE (-4) from every solve entry point,
   and the context keeps working afterwards.
 * The residual history of stokes_solve_info has one entry per outer
-  iteration and ends near the final residual; the phase times (profile = 1)
+  iteration and ends near the final residual; the phase times (profile = 2)
   are positive and fit inside the call's wall time.
 """
 
@@ -81,7 +81,7 @@ def test_nonfinite_projection_and_adjoint(prob):
 @pytest.mark.parametrize("method,precision,inner_mode", [("coupled", 1, 1), ("coupled", 0, 0), ("schur", 0, 0)])
 def test_residual_history_and_phase_times(prob, method, precision, inner_mode):
     P, f = prob
-    u, p, info = P.solve(f, method=method, precision=precision, inner_mode=inner_mode, rtol=1e-10, profile=1,
+    u, p, info = P.solve(f, method=method, precision=precision, inner_mode=inner_mode, rtol=1e-10, profile=2,
                          coupled_pc=1, hist_cap=500)
     print(f"[case] history {method} p{precision}: {info}", flush=True)
     assert info["status"] == 0
