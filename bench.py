@@ -97,7 +97,7 @@ def measured_traffic(workload, nrhs, strain=False):
 ORACLE_ITERS_FILE = os.path.join(ROOT, "tests", "golden", "cube64_oracle_iters.txt")
 
 
-def cpu_baseline_sampled(dim, n, mesh_seed, mu, alpha, fseed, iters=2):
+def cpu_baseline_sampled(dim, n, mesh_seed, mu, alpha, fseed, iters=1):
     """The FP64 oracle (preconditioned MINRES) on the benchmark workload
     itself, timed on a bounded sample: `iters` MINRES iterations (assembly
     excluded, as on the GPU side), scaled to a full solve by the oracle's own
@@ -146,6 +146,104 @@ def cpu_baseline(dim, mesh_seed, mu, alpha, fseed, n_sample):
                       f"({dofs} DOFs), true rel-res {res:.1e}; scipy sparse kernels run on one thread"}
 
 
+def c2_sweep(steps):
+    """The paper's method comparison (Sec. 5 and 6, Figs. 1, 3, 4, 6, 7) as a
+    measurement on the 32^3 workload: Schur CG with the three Cahouet-Chabard
+    variants and coupled FGMRES with the three block preconditioners (FP64),
+    plus the mixed benchmark configuration, for mu in {1, 1e-2, 1e-4} and the
+    augmented-Lagrangian weight gamma in {0, 1, 10}; every solve to a true
+    relative residual of 1e-8.  One JSON line per case (time, DOFs/s,
+    iterations)."""
+    import numpy as np
+    import torch
+    from paper_2407_01783_amd import inputs
+    from paper_2407_01783_amd.stokes import StokesProblem
+    dim, n, seed, _, dt, fseed, _ = WORKLOADS["cube32"]
+    alpha = 1.0 / dt
+    cases = [("coupled", 1, dict(coupled_pc=1, inner_mode=1, cheb_degree=6), "coupled mixed upper, fixed inner"),
+             ("coupled", 0, dict(coupled_pc=0), "coupled FP64 full factorisation"),
+             ("coupled", 0, dict(coupled_pc=1), "coupled FP64 upper triangular"),
+             ("coupled", 0, dict(coupled_pc=2), "coupled FP64 lower triangular"),
+             ("schur", 0, dict(schur_pc=1), "Schur FP64 C^Lambda (lumped)"),
+             ("schur", 0, dict(schur_pc=0), "Schur FP64 C^Delta (pressure Laplacian)"),
+             ("schur", 0, dict(schur_pc=2), "Schur FP64 C (consistent mass)")]
+    torch.cuda.set_device(0)
+    for mu in (1.0, 1e-2, 1e-4):
+        for gamma in (0.0, 1.0, 10.0):
+            prob = StokesProblem(dim, n, mesh_seed=seed, jitter=0.1, mu=mu, alpha=alpha, gamma=gamma)
+            xy, _ = prob.mesh()
+            f = torch.tensor(inputs.fourier_forcing(xy, fseed)[None], device="cuda")
+            dofs = prob.total_dofs()
+            for method, prec, extra, name in cases:
+                o = dict(rtol=1e-8, max_outer=3000, max_refine=40, **extra)
+                _, _, info = prob.solve(f, method=method, precision=prec, **o)  # warm-up
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(steps):
+                    _, _, info = prob.solve(f, method=method, precision=prec, **o)
+                torch.cuda.synchronize()
+                el = (time.perf_counter() - t) / steps
+                print(json.dumps({"sweep": "cube32", "mu": mu, "gamma": gamma, "case": name,
+                                  "converged": info["status"] == 0, "rel_res": info["rel_res"],
+                                  "ms": el * 1e3, "dofs_per_s": dofs / el, "outer_iters": info["outer_iters"],
+                                  "inner_iters_u": info["inner_iters_u"], "inner_iters_p": info["inner_iters_p"],
+                                  "refinements": info["refinements"]}), flush=True)
+            del prob
+            torch.cuda.empty_cache()
+
+
+def c4_compare(steps):
+    """Batching on the 128^3 workload, as the configuration states it: eight
+    right-hand sides in one batched mixed solve, against one right-hand side
+    mixed and eight sequential FP64 solves (the benchmark's solver options,
+    FGMRES(10)).  One JSON line."""
+    import numpy as np
+    import torch
+    from paper_2407_01783_amd import inputs
+    from paper_2407_01783_amd.stokes import StokesProblem
+    dim, n, seed, mu, dt, fseed, desc = WORKLOADS["cube128"]
+    opts = dict(SOLVER)
+    opts.update(WORKLOAD_SOLVER["cube128"])
+    method = opts.pop("method")
+    torch.cuda.set_device(0)
+    prob = StokesProblem(dim, n, mesh_seed=seed, jitter=0.1, mu=mu, alpha=1.0 / dt)
+    xy, _ = prob.mesh()
+    f8 = torch.tensor(np.stack([inputs.fourier_forcing(xy, inputs.forcing_seed(seed, b)) for b in range(8)]),
+                      device="cuda")
+    dofs1 = prob.total_dofs()
+    out = {"workload": desc, "dofs_per_rhs": dofs1, "solver": opts}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            info = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps, info
+
+    el, info = timed(lambda: prob.solve(f8, method=method, precision=1, **opts)[2])
+    out["mixed_nrhs8"] = {"s": el, "dofs_per_s": 8 * dofs1 / el, "rel_res": info["rel_res"],
+                          "outer_iters": info["outer_iters"], "converged": info["status"] == 0}
+    print(f"[c4] batched mixed x8: {el:.3f} s", file=sys.stderr, flush=True)
+    el, info = timed(lambda: prob.solve(f8[:1], method=method, precision=1, **opts)[2])
+    out["mixed_nrhs1"] = {"s": el, "dofs_per_s": dofs1 / el, "rel_res": info["rel_res"],
+                          "outer_iters": info["outer_iters"], "converged": info["status"] == 0}
+    print(f"[c4] mixed x1: {el:.3f} s", file=sys.stderr, flush=True)
+
+    def seq64():
+        infos = [prob.solve(f8[b:b + 1], method=method, precision=0, **opts)[2] for b in range(8)]
+        return max(infos, key=lambda i: i["rel_res"])
+
+    el, info = timed(seq64)
+    out["fp64_8_sequential"] = {"s": el, "dofs_per_s": 8 * dofs1 / el, "rel_res": info["rel_res"],
+                                "converged": info["status"] == 0}
+    print(f"[c4] 8 sequential FP64: {el:.3f} s", file=sys.stderr, flush=True)
+    out["batched_over_single"] = out["mixed_nrhs8"]["dofs_per_s"] / out["mixed_nrhs1"]["dofs_per_s"]
+    out["batched_over_fp64_sequential"] = out["mixed_nrhs8"]["dofs_per_s"] / out["fp64_8_sequential"]["dofs_per_s"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,15 +265,29 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed solves, copy 1 GiB device-to-device 3 times (a kernel of known size "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--c2-sweep", action="store_true",
+                    help="instead of the benchmark line: the method / preconditioner / mu / gamma comparison on "
+                         "the 32^3 workload, one JSON line per case")
+    ap.add_argument("--c4-compare", action="store_true",
+                    help="instead of the benchmark line: 128^3 with eight right-hand sides batched (mixed) against "
+                         "one right-hand side and eight sequential FP64 solves")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    if args.c2_sweep:
+        c2_sweep(args.steps)
+        return
+    if args.c4_compare:
+        c4_compare(args.steps)
+        return
+
+    import ctypes
 
     import numpy as np
     import torch
-    from paper_2407_01783_amd import inputs
+    from paper_2407_01783_amd import _lib, inputs
     from paper_2407_01783_amd.stokes import StokesProblem
 
     dim, n, seed, mu, dt, fseed, desc = WORKLOADS[args.workload]
@@ -316,6 +428,13 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # same-run bandwidth probe: a 2 GiB device copy and read stream
+    gbs = (ctypes.c_double * 2)()
+    _lib.check(_lib.load().stokes_bandwidth_probe(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                                  1 << 31, 10, gbs), "stokes_bandwidth_probe")
+    probe = {"copy_GBs": gbs[0], "read_GBs": gbs[1], "bytes": 1 << 31}
+    print(f"[bench] probe: copy {gbs[0]:.0f} GB/s, read {gbs[1]:.0f} GB/s", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu:
         if args.workload == "cube64" and os.path.exists(ORACLE_ITERS_FILE):
@@ -357,7 +476,9 @@ def main():
                                f"interleaved copies, bfloat16 direction, FP32 residual and iterate; fused Chebyshev "
                                f"update; G lanes per row, autotuned)",
                      "bytes_per_launch": bytes_per, "launches": launches,
-                     "avg_us": kern_s / launches * 1e6 if launches else None},
+                     "avg_us": kern_s / launches * 1e6 if launches else None,
+                     "frac_of_read_probe": (achieved / probe["read_GBs"]) if achieved else None,
+                     "probe": probe},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -84,6 +84,20 @@ enum { STOKES_PC_FULL = 0, STOKES_PC_UPPER = 1, STOKES_PC_LOWER = 2 };
  * preconditioner stays A~_{lambda,3} = alpha M_V + mu L_V (Sec. 3.2); the
  * Dirichlet lifting and dJ/dmu use the same A. */
 enum { STOKES_FLAG_STRAIN = 1 };
+/* stokes_problem.flags: STOKES_FLAG_P3 selects the Taylor-Hood P3/P2 pair,
+ * the paper's second element pair (Sec. 1; Sec. 3.3, Table 4, P3 rows):
+ * velocity in the continuous P3 space, pressure in the continuous P2 space.
+ * The velocity nodes are then the points of the (3n+1)^dim lattice, id
+ * I + (3n+1) J [+ (3n+1)^2 K]; the pressure nodes are the (2n+1)^dim P2
+ * points.  Every "n_p2" / velocity-shaped array below counts P3 nodes and
+ * every "n_p1" / pressure-shaped array P2 nodes.  Local P3 order: vertices,
+ * then per local edge (a, b) the node next to a and the node next to b, then
+ * the faces (0,1,2), (0,1,3), (0,2,3), (1,2,3) (2D: the interior node).  The
+ * geometric multigrids need the P2/P1 pair: with P3 the pressure solves use
+ * Chebyshev-Jacobi polynomials of M_Q + L_Q, vel_pc = STOKES_VEL_MG and
+ * stokes_apply ops 6, 8, 9 return STOKES_ERR_UNSUPPORTED.  Combines with
+ * STOKES_FLAG_STRAIN. */
+enum { STOKES_FLAG_P3 = 2 };
 /* stokes_solve_opts.vel_pc: the preconditioner of A~_{lambda,3} = alpha M_V
  * + mu L_V inside the velocity solves -- a Chebyshev-Jacobi polynomial of
  * degree cheb_degree, or one geometric-multigrid V-cycle on the nested Kuhn
@@ -101,7 +115,7 @@ typedef struct {
   double mu;          /* viscosity, > 0 */
   double alpha;       /* 1/dt, > 0 */
   double gamma;       /* augmented-Lagrangian weight, >= 0 */
-  int32_t flags;      /* 0 or STOKES_FLAG_STRAIN */
+  int32_t flags;      /* 0, STOKES_FLAG_STRAIN, STOKES_FLAG_P3, or both */
 } stokes_problem;
 
 typedef struct {
@@ -319,6 +333,14 @@ stokes_status stokes_export_csr(const stokes_ctx* ctx, int32_t which, int32_t* r
 /* Chebyshev interval estimates [lo, hi] of the Jacobi-scaled operators:
  * bounds_host[0..7] = A_II, M_V, M_Q, M_Q + L_Q. */
 stokes_status stokes_bounds(const stokes_ctx* ctx, double bounds_host[8]);
+
+/* Measurement helper (not part of the solve): achievable HBM bandwidth of a
+ * device-to-device copy and of a read-only stream of `bytes` bytes on the
+ * current device, each the mean over `reps` launches after one warm-up,
+ * timed with HIP events on hip_stream (NULL = default stream).
+ * gbs_host[0] = copy GB/s (read + write bytes), gbs_host[1] = read GB/s.
+ * Allocates and frees two buffers of `bytes`. */
+stokes_status stokes_bandwidth_probe(void* hip_stream, int64_t bytes, int32_t reps, double* gbs_host);
 
 /* Free the context and every device buffer it owns.  NULL is a no-op. */
 void stokes_destroy(stokes_ctx* ctx);

@@ -270,12 +270,14 @@ class P3P2Mesh:
         return self.vcoords[self.elems]
 
 
-def assemble_p3p2(mesh):
+def assemble_p3p2(mesh, grad_div=False):
     """Assemble the Taylor-Hood P3/P2 matrices (Sec. 2.2 / 3.2 / 4.1 with the
     P3/P2 pair): P3 scalar mass Ms and stiffness Ls, the d planes of B
     (P2 pressure rows x P3 velocity columns), the P2 pressure mass MQ and
     Laplacian LQ, and the lumped Lambda_V = int |phi_i| (COO -> CSR with
-    explicit zeros kept).  Returns an ``oracle.fem.Matrices``."""
+    explicit zeros kept); grad_div=True adds the d x d grad-div blocks
+    D[a][b][i, j] = int d_a phi_i d_b phi_j of Sec. 3.2.  Returns an
+    ``oracle.fem.Matrices``."""
     d = mesh.dim
     ref = reference_tensors_p3p2(d)
     vol, grad, _ = element_geometry(mesh)
@@ -301,7 +303,14 @@ def assemble_p3p2(mesh):
     LQ = _coo_to_csr(rq, cq, LQe.ravel(), (mesh.n_q, mesh.n_q))
     Lam = np.zeros(mesh.n_vel)
     np.add.at(Lam, V.ravel(), (vol[:, None] * ref["absphi"][None]).ravel())
-    return Matrices(Ms, Ls, B, MQ, LQ, Lam, vol, grad)
+    D = None
+    if grad_div:
+        D = [[None] * d for _ in range(d)]
+        for a in range(d):
+            for b in range(d):
+                De = vol[:, None, None] * np.einsum("ep,eq,ipjq->eij", grad[:, :, a], grad[:, :, b], ref["T"])
+                D[a][b] = _coo_to_csr(rv, cv, De.ravel(), shape_v)
+    return Matrices(Ms, Ls, B, MQ, LQ, Lam, vol, grad, D)
 
 
 def p3_basis_values(dim, lam):

@@ -22,6 +22,7 @@ INNER_TOL, INNER_FIXED = 0, 1
 CC_LAPLACE, CC_LUMPED, CC_MASS = 0, 1, 2
 PC_FULL, PC_UPPER, PC_LOWER = 0, 1, 2
 FLAG_STRAIN = 1
+FLAG_P3 = 2
 VEL_CHEB, VEL_MG = 0, 1
 ARNOLDI_FP32, ARNOLDI_FP64, ARNOLDI_FP64_K = 0, 1, 2
 
@@ -75,7 +76,7 @@ EXPORTS = [
     "stokes_assemble", "stokes_solve_schur", "stokes_solve_coupled", "stokes_solve_adjoint", "stokes_apply",
     "stokes_residual", "stokes_query", "stokes_set_mu", "stokes_set_stream", "stokes_export_mesh",
     "stokes_export_csr", "stokes_bounds", "stokes_destroy", "stokes_last_error", "stokes_projection_step",
-    "stokes_residual_noalloc",
+    "stokes_residual_noalloc", "stokes_bandwidth_probe",
 ]
 
 _lib = None
@@ -112,6 +113,7 @@ def load():
         "stokes_apply": (st, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P]),
         "stokes_residual": (st, [_P, ctypes.c_int32, _P, _P, _P, _P, _D]),
         "stokes_residual_noalloc": (st, [_P, ctypes.c_int32, _P, _P, _P, _P, _D]),
+        "stokes_bandwidth_probe": (st, [_P, ctypes.c_int64, ctypes.c_int32, _D]),
         "stokes_query": (st, [_P, _I64]),
         "stokes_set_mu": (st, [_P, ctypes.c_double]),
         "stokes_set_stream": (st, [_P, _P]),

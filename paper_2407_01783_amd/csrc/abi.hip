@@ -84,8 +84,10 @@ stokes_status check_problem(const stokes_problem* p) {
   if (!(p->alpha > 0) || !std::isfinite(p->alpha)) throw Error(STOKES_ERR_ARG, "alpha must be finite and > 0");
   if (!(p->gamma >= 0) || !std::isfinite(p->gamma)) throw Error(STOKES_ERR_ARG, "gamma must be finite and >= 0");
   if (!(p->jitter >= 0 && p->jitter <= 0.2)) throw Error(STOKES_ERR_ARG, "jitter must be in [0, 0.2]");
-  if ((p->flags & ~STOKES_FLAG_STRAIN) != 0) throw Error(STOKES_ERR_ARG, "flags must be 0 or STOKES_FLAG_STRAIN");
-  const int64_t n2 = ipow64(2 * int64_t(p->n) + 1, p->dim);
+  if ((p->flags & ~(STOKES_FLAG_STRAIN | STOKES_FLAG_P3)) != 0)
+    throw Error(STOKES_ERR_ARG, "flags must combine STOKES_FLAG_STRAIN and STOKES_FLAG_P3 only");
+  const int order = (p->flags & STOKES_FLAG_P3) ? 3 : 2;
+  const int64_t n2 = ipow64(order * int64_t(p->n) + 1, p->dim);
   if (n2 >= (int64_t(1) << 31) / 4) throw Error(STOKES_ERR_UNSUPPORTED, "mesh too large for 32-bit indices");
   return STOKES_OK;
 }
@@ -128,11 +130,14 @@ stokes_status guard(F&& f) {
 
 void sizes_of(const HostMesh& m, const HostCsr* P2full, int64_t sizes[10]);
 
+// velocity x velocity, pressure x velocity, pressure x pressure
 void patterns(const HostMesh& m, HostCsr& P2full, HostCsr& Bfull, HostCsr& P1) {
   element_pattern(m.p2, m.nloc, m.n_p2, m.p2, m.nloc, m.n_p2, m.n_e, P2full);
-  element_pattern(m.elems, m.dim + 1, m.n_p1, m.p2, m.nloc, m.n_p2, m.n_e, Bfull);
-  element_pattern(m.elems, m.dim + 1, m.n_p1, m.elems, m.dim + 1, m.n_p1, m.n_e, P1);
+  element_pattern(m.q, m.nqloc, m.n_q, m.p2, m.nloc, m.n_p2, m.n_e, Bfull);
+  element_pattern(m.q, m.nqloc, m.n_q, m.q, m.nqloc, m.n_q, m.n_e, P1);
 }
+
+int order_of(const stokes_problem* p) { return (p->flags & STOKES_FLAG_P3) ? 3 : 2; }
 
 std::vector<int32_t> interior_map(const HostMesh& m, int64_t& nI) {
   std::vector<int32_t> map(m.n_p2, -1);
@@ -443,18 +448,18 @@ stokes_status stokes_problem_sizes(const stokes_problem* prob, int64_t sizes[10]
     check_problem(prob);
     if (!sizes) throw Error(STOKES_ERR_ARG, "sizes is NULL");
     HostMesh m;
-    if (!build_mesh(prob->dim, prob->n, prob->mesh_seed, prob->jitter, m))
+    if (!build_mesh(prob->dim, prob->n, prob->mesh_seed, prob->jitter, m, order_of(prob)))
       throw Error(STOKES_ERR_UNSUPPORTED, "mesh too large");
     HostCsr P2, B, P1, A2, B2;
     patterns(m, P2, B, P1);
     int64_t nI = 0;
     std::vector<int32_t> imap = interior_map(m, nI);
-    std::vector<int32_t> rows_all(m.n_p1);
-    for (int64_t i = 0; i < m.n_p1; ++i) rows_all[i] = static_cast<int32_t>(i);
+    std::vector<int32_t> rows_all(m.n_q);
+    for (int64_t i = 0; i < m.n_q; ++i) rows_all[i] = static_cast<int32_t>(i);
     restrict_pattern(P2, imap, nI, imap, nI, A2, nullptr);
-    restrict_pattern(B, rows_all, m.n_p1, imap, nI, B2, nullptr);
+    restrict_pattern(B, rows_all, m.n_q, imap, nI, B2, nullptr);
     sizes[0] = m.n_p2;
-    sizes[1] = m.n_p1;
+    sizes[1] = m.n_q;
     sizes[2] = nI;
     sizes[3] = A2.rowptr.back();
     sizes[4] = B2.rowptr.back();
@@ -472,7 +477,7 @@ stokes_status stokes_build_mesh_host(const stokes_problem* prob, double* vcoords
   return guard([&]() -> stokes_status {
     check_problem(prob);
     HostMesh m;
-    if (!build_mesh(prob->dim, prob->n, prob->mesh_seed, prob->jitter, m))
+    if (!build_mesh(prob->dim, prob->n, prob->mesh_seed, prob->jitter, m, order_of(prob)))
       throw Error(STOKES_ERR_UNSUPPORTED, "mesh too large");
     if (vcoords) std::memcpy(vcoords, m.vcoords.data(), m.vcoords.size() * sizeof(double));
     if (elems) std::memcpy(elems, m.elems.data(), m.elems.size() * sizeof(int32_t));
@@ -489,20 +494,20 @@ stokes_status stokes_host_pattern(const stokes_problem* prob, int32_t which, int
     if (which < 0 || which > 4) throw Error(STOKES_ERR_ARG, "which must be in [0, 4]");
     if (!nrows || !nnz) throw Error(STOKES_ERR_ARG, "nrows and nnz must not be NULL");
     HostMesh m;
-    if (!build_mesh(prob->dim, prob->n, prob->mesh_seed, prob->jitter, m))
+    if (!build_mesh(prob->dim, prob->n, prob->mesh_seed, prob->jitter, m, order_of(prob)))
       throw Error(STOKES_ERR_UNSUPPORTED, "mesh too large");
     HostCsr P2, B, P1, out;
     patterns(m, P2, B, P1);
     int64_t nI = 0;
     std::vector<int32_t> imap = interior_map(m, nI);
-    std::vector<int32_t> rows_all(m.n_p1);
-    for (int64_t i = 0; i < m.n_p1; ++i) rows_all[i] = static_cast<int32_t>(i);
+    std::vector<int32_t> rows_all(m.n_q);
+    for (int64_t i = 0; i < m.n_q; ++i) rows_all[i] = static_cast<int32_t>(i);
     const HostCsr* h = nullptr;
     switch (which) {
       case 0: h = &P2; break;
       case 1: restrict_pattern(P2, imap, nI, imap, nI, out, nullptr); h = &out; break;
       case 2: h = &B; break;
-      case 3: restrict_pattern(B, rows_all, m.n_p1, imap, nI, out, nullptr); h = &out; break;
+      case 3: restrict_pattern(B, rows_all, m.n_q, imap, nI, out, nullptr); h = &out; break;
       default: h = &P1; break;
     }
     *nrows = h->nrows;
@@ -550,11 +555,11 @@ stokes_status stokes_assemble(const stokes_problem* prob, void* hip_stream, stok
     HIP_CHECK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
     HIP_CHECK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
     HIP_CHECK(hipStreamSynchronize(c->user_stream));
-    if (!build_mesh(prob->dim, prob->n, prob->mesh_seed, prob->jitter, c->mesh))
+    if (!build_mesh(prob->dim, prob->n, prob->mesh_seed, prob->jitter, c->mesh, order_of(prob)))
       throw Error(STOKES_ERR_UNSUPPORTED, "mesh too large");
     c->dim = prob->dim;
     c->nloc = c->mesh.nloc;
-    c->n_p1 = c->mesh.n_p1;
+    c->n_p1 = c->mesh.n_q;  // pressure nodes
     c->n_p2 = c->mesh.n_p2;
     c->n_e = c->mesh.n_e;
     c->red.partials.alloc(size_t(kMaxBlocks) * 2 * kMaxSys * sizeof(double));
@@ -665,6 +670,8 @@ stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t
     if (precision != 0 && precision != 1) throw Error(STOKES_ERR_ARG, "precision must be 0 or 1");
     if (nrhs < 1) throw Error(STOKES_ERR_ARG, "nrhs must be >= 1");
     if (!x || !y) throw Error(STOKES_ERR_ARG, "x and y must not be NULL");
+    if (c->mesh.order == 3 && (op == 6 || op == 8 || op == 9))
+      throw Error(STOKES_ERR_UNSUPPORTED, "the multigrid operators (op 6, 8, 9) need the P2/P1 pair");
     HIP_CHECK(hipSetDevice(c->device));
     StreamScope scope(c);
     const int D = c->dim;
@@ -817,6 +824,83 @@ stokes_status stokes_residual_noalloc(stokes_ctx* c, int32_t nrhs, const double*
       }
       rel[r] = den > 0 ? std::sqrt(num / den) : std::sqrt(num);
     }
+    return STOKES_OK;
+  });
+}
+
+}  // extern "C"
+
+namespace stokes {
+namespace {
+
+// Bandwidth probe kernels: 16-byte nontemporal streams, grid-stride.
+typedef unsigned probe_u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kBlock) void k_probe_copy(int64_t n16, const probe_u32x4* __restrict__ src,
+                                                       probe_u32x4* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n16; i += (int64_t)gridDim.x * kBlock)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+// Read stream: every word is summed (xor) so the loads stay; one word per
+// block is written.
+__global__ __launch_bounds__(kBlock) void k_probe_read(int64_t n16, const probe_u32x4* __restrict__ src,
+                                                       unsigned* __restrict__ out) {
+  unsigned acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n16; i += (int64_t)gridDim.x * kBlock) {
+    const probe_u32x4 v = __builtin_nontemporal_load(src + i);
+    acc ^= v.x ^ v.y ^ v.z ^ v.w;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc ^= __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) out[blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)] = acc;
+}
+
+}  // namespace
+}  // namespace stokes
+
+extern "C" {
+
+stokes_status stokes_bandwidth_probe(void* hip_stream, int64_t bytes, int32_t reps, double* gbs_host) {
+  return guard([&]() -> stokes_status {
+    if (bytes < (int64_t(1) << 20) || bytes > (int64_t(1) << 36) || reps < 1 || reps > 100 || !gbs_host)
+      throw Error(STOKES_ERR_ARG, "bytes must be in [1 MiB, 64 GiB], reps in [1, 100], gbs_host non-NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int64_t n16 = bytes / 16;
+    DevBuf a, b, o;
+    a.alloc(n16 * 16);
+    b.alloc(n16 * 16);
+    const int nblk = 8 * 256 * 4;  // 4 workgroups of 256 threads per CU on 256 CUs, x2
+    o.alloc(size_t(nblk) * (kBlock / 64) * sizeof(unsigned));
+    HIP_CHECK(hipMemsetAsync(a.p, 1, n16 * 16, s));
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    struct Ev {
+      hipEvent_t a, b;
+      ~Ev() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+      }
+    } guard_ev{e0, e1};
+    auto timed = [&](auto launch) {
+      launch();  // warm-up
+      HIP_CHECK(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) launch();
+      HIP_CHECK(hipEventRecord(e1, s));
+      HIP_CHECK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+      return ms * 1e-3 / reps;
+    };
+    const double tc = timed([&] {
+      hipLaunchKernelGGL(k_probe_copy, dim3(nblk), dim3(kBlock), 0, s, n16, a.as<const probe_u32x4>(), b.as<probe_u32x4>());
+    });
+    const double tr = timed([&] {
+      hipLaunchKernelGGL(k_probe_read, dim3(nblk), dim3(kBlock), 0, s, n16, a.as<const probe_u32x4>(), o.as<unsigned>());
+    });
+    HIP_CHECK(hipGetLastError());
+    gbs_host[0] = 2.0 * double(n16 * 16) / tc * 1e-9;
+    gbs_host[1] = double(n16 * 16) / tr * 1e-9;
+    HIP_CHECK(hipStreamSynchronize(s));
     return STOKES_OK;
   });
 }

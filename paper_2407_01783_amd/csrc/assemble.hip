@@ -30,9 +30,13 @@ namespace stokes {
 
 namespace {
 
-// reference tables, [2] = 2D, [3] = 3D (index by dim)
+// reference tables of the P2/P1 pair, [2] = 2D, [3] = 3D (index by dim)
 __constant__ double c_Mref3[100], c_Sref3[900], c_Wref3[120], c_M1ref3[16], c_abs3[10];
 __constant__ double c_Mref2[36], c_Sref2[144], c_Wref2[36], c_M1ref2[9], c_abs2[6];
+// ... and of the P3/P2 pair (velocity P3: 20 / 10 local nodes, pressure P2:
+// 10 / 6; W is pressure x velocity x dim)
+__constant__ double c_Mref3c[400], c_Sref3c[3600], c_Wref3c[600], c_abs3c[20];
+__constant__ double c_Mref2c[100], c_Sref2c[400], c_Wref2c[120], c_abs2c[10];
 
 struct RefTables {
   std::vector<double> M, S, W, M1, absphi;
@@ -105,54 +109,187 @@ void sym_eig_extremes(std::vector<double> A, int n, double& lo, double& hi) {
   }
 }
 
-RefTables make_tables(int d) {
-  RefTables t;
-  const int nv = d + 1, nl = d == 3 ? 10 : 6;
+// Local velocity basis of a simplex at barycentric point L: values phi[i]
+// and gradients g[i * d + p] with respect to the reference coordinates xi_p
+// (lambda_0 = 1 - sum xi, lambda_a = xi_{a-1}).  Order 2: vertex
+// lambda_a (2 lambda_a - 1), edge 4 lambda_a lambda_b.  Order 3: vertex
+// lambda_a (3 lambda_a - 1)(3 lambda_a - 2) / 2; per local edge (a, b) the
+// node next to a, 9/2 lambda_a lambda_b (3 lambda_a - 1), then the node next
+// to b; then the face (2D: interior) nodes 27 lambda_a lambda_b lambda_c of
+// the faces (0,1,2), (0,1,3), (0,2,3), (1,2,3).
+void local_basis(int d, int order, const std::vector<double>& L, std::vector<double>& phi, std::vector<double>& g) {
+  const int nv = d + 1;
+  auto dlam = [&](int a, int p) { return a == 0 ? -1.0 : (a - 1 == p ? 1.0 : 0.0); };
   std::vector<std::pair<int, int>> edges;
   for (int a = 0; a < nv; ++a)
     for (int b = a + 1; b < nv; ++b) edges.emplace_back(a, b);
+  phi.clear();
+  g.clear();
+  auto push = [&](double v, const double* gr) {
+    phi.push_back(v);
+    for (int p = 0; p < d; ++p) g.push_back(gr[p]);
+  };
+  double gr[3];
+  if (order == 2) {
+    for (int a = 0; a < nv; ++a) {
+      for (int p = 0; p < d; ++p) gr[p] = (4.0 * L[a] - 1.0) * dlam(a, p);
+      push(L[a] * (2.0 * L[a] - 1.0), gr);
+    }
+    for (auto [a, b] : edges) {
+      for (int p = 0; p < d; ++p) gr[p] = 4.0 * (dlam(a, p) * L[b] + L[a] * dlam(b, p));
+      push(4.0 * L[a] * L[b], gr);
+    }
+    return;
+  }
+  for (int a = 0; a < nv; ++a) {
+    const double t = L[a];
+    // d/dt [t (3t - 1)(3t - 2) / 2] = (27 t^2 - 18 t + 2) / 2
+    for (int p = 0; p < d; ++p) gr[p] = 0.5 * (27.0 * t * t - 18.0 * t + 2.0) * dlam(a, p);
+    push(0.5 * t * (3.0 * t - 1.0) * (3.0 * t - 2.0), gr);
+  }
+  for (auto [a0, b0] : edges)
+    for (int side = 0; side < 2; ++side) {
+      const int a = side == 0 ? a0 : b0, b = side == 0 ? b0 : a0;  // a: the near vertex
+      // 9/2 (3 la^2 lb - la lb): d/dla = 9/2 (6 la lb - lb), d/dlb = 9/2 (3 la^2 - la)
+      const double da = 4.5 * (6.0 * L[a] * L[b] - L[b]), db = 4.5 * (3.0 * L[a] * L[a] - L[a]);
+      for (int p = 0; p < d; ++p) gr[p] = da * dlam(a, p) + db * dlam(b, p);
+      push(4.5 * L[a] * L[b] * (3.0 * L[a] - 1.0), gr);
+    }
+  static const int faces3[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
+  const int nf = d == 3 ? 4 : 1;
+  for (int f = 0; f < nf; ++f) {
+    const int a = faces3[f][0], b = faces3[f][1], c = faces3[f][2];
+    for (int p = 0; p < d; ++p)
+      gr[p] = 27.0 * (dlam(a, p) * L[b] * L[c] + L[a] * dlam(b, p) * L[c] + L[a] * L[b] * dlam(c, p));
+    push(27.0 * L[a] * L[b] * L[c], gr);
+  }
+}
+
+// Exact rational arithmetic on int64 (the closed forms below have small
+// denominators), reduced after every operation.
+struct Rat {
+  int64_t p = 0, q = 1;
+  Rat() = default;
+  Rat(int64_t a, int64_t b = 1) : p(a), q(b) { norm(); }
+  void norm() {
+    if (q < 0) {
+      p = -p;
+      q = -q;
+    }
+    int64_t a = p < 0 ? -p : p, b = q;
+    while (b) {
+      const int64_t t = a % b;
+      a = b;
+      b = t;
+    }
+    if (a > 1) {
+      p /= a;
+      q /= a;
+    }
+  }
+  Rat operator+(const Rat& o) const { return Rat(p * o.q + o.p * q, q * o.q); }
+  Rat operator-(const Rat& o) const { return Rat(p * o.q - o.p * q, q * o.q); }
+  Rat operator*(const Rat& o) const { return Rat(p * o.p, q * o.q); }
+  double value() const { return double(p) / double(q); }
+};
+
+// int |phi| / |K| of the P3 basis.  A barycentric coordinate t = lambda_a of
+// a point uniform in the d-simplex has the density d (1 - t)^(d-1); given t,
+// the other coordinates are uniform on a simplex of total 1 - t, so the mean
+// of another coordinate lambda_b is (1 - t) / d.  The vertex function
+// t (3t - 1)(3t - 2) / 2 changes sign at t = 1/3 and 2/3, the edge function
+// 9/2 lambda_a lambda_b (3 lambda_a - 1) at lambda_a = 1/3; integrating the
+// t-polynomials piecewise against the density gives the exact values (here
+// in rational arithmetic, rounded once).  Face (interior) functions are
+// non-negative: their integral is 27 d! / (d + 3)!.
+void p3_abs_values(int d, double& vtx, double& edge, double& face) {
+  // integral over [lo, hi] of poly(t) d (1 - t)^(d - 1), poly as t^k
+  // coefficients, with (1 - t)^(d - 1) expanded binomially
+  auto integ = [d](const std::vector<Rat>& poly, Rat lo, Rat hi) {
+    std::vector<Rat> w(d);
+    int64_t binom = 1;
+    for (int k = 0; k < d; ++k) {
+      w[k] = Rat(d * binom * ((k % 2) ? -1 : 1));
+      binom = binom * (d - 1 - k) / (k + 1);
+    }
+    std::vector<Rat> prod(poly.size() + w.size() - 1);
+    for (size_t i = 0; i < poly.size(); ++i)
+      for (size_t j = 0; j < w.size(); ++j) prod[i + j] = prod[i + j] + poly[i] * w[j];
+    Rat r;
+    for (size_t k = 0; k < prod.size(); ++k) {
+      Rat hk(1), lk(1);
+      for (size_t e = 0; e <= k; ++e) {
+        hk = hk * hi;
+        lk = lk * lo;
+      }
+      r = r + prod[k] * (hk - lk) * Rat(1, int64_t(k + 1));
+    }
+    return r;
+  };
+  const Rat t0(0), t1(1, 3), t2(2, 3), t3(1);
+  const std::vector<Rat> gv = {Rat(0), Rat(1), Rat(-9, 2), Rat(9, 2)};  // t (3t - 1)(3t - 2) / 2
+  vtx = (integ(gv, t0, t1) - integ(gv, t1, t2) + integ(gv, t2, t3)).value();
+  // 9/2 t (3t - 1) (1 - t) / d = 9/(2d) (-t + 4 t^2 - 3 t^3)
+  const Rat k(9, 2 * d);
+  const std::vector<Rat> ge = {Rat(0), Rat(0) - k, Rat(4) * k, Rat(-3) * k};
+  edge = (integ(ge, t1, t3) - integ(ge, t0, t1)).value();
+  int64_t num = 27, den = 1;
+  for (int i = 1; i <= d; ++i) num *= i;
+  for (int i = 1; i <= d + 3; ++i) den *= i;
+  face = Rat(num, den).value();
+}
+
+// Reference integrals of the velocity basis of `order` against itself and
+// against the pressure basis (order 2: the P1 lambdas; order 3: the P2
+// basis): M, S (gradient products in reference coordinates), W (pressure x
+// velocity gradient), M1 (pressure mass, order 2 only), int |phi|, and the
+// element bounds of the Jacobi-scaled velocity and pressure masses.
+RefTables make_tables(int d, int order = 2) {
+  RefTables t;
+  const int nv = d + 1;
+  const int nl = order == 3 ? (d == 3 ? 20 : 10) : (d == 3 ? 10 : 6);
+  const int nq = order == 3 ? (d == 3 ? 10 : 6) : nv;
   std::vector<std::vector<double>> pts;
   std::vector<double> wts;
-  gm_rule(d, 2, pts, wts);
+  gm_rule(d, order == 3 ? 3 : 2, pts, wts);  // degree 7 / 5: exact for the products here
   double volref = 1.0;
   for (int i = 2; i <= d; ++i) volref /= i;
-  // d lambda_a / d xi_p, with lambda_0 = 1 - sum xi, lambda_a = xi_{a-1}
-  auto dlam = [&](int a, int p) { return a == 0 ? -1.0 : (a - 1 == p ? 1.0 : 0.0); };
   t.M.assign(nl * nl, 0);
   t.S.assign(nl * d * nl * d, 0);
-  t.W.assign(nv * nl * d, 0);
-  t.M1.assign(nv * nv, 0);
+  t.W.assign(nq * nl * d, 0);
+  t.M1.assign(nq * nq, 0);
+  std::vector<double> phi, g, qphi, qg;
   for (size_t q = 0; q < pts.size(); ++q) {
     const auto& L = pts[q];
     const double w = wts[q] / volref;
-    std::vector<double> phi(nl), g(nl * d);
-    for (int a = 0; a < nv; ++a) {
-      phi[a] = L[a] * (2.0 * L[a] - 1.0);
-      for (int p = 0; p < d; ++p) g[a * d + p] = (4.0 * L[a] - 1.0) * dlam(a, p);
-    }
-    for (size_t k = 0; k < edges.size(); ++k) {
-      const int a = edges[k].first, b = edges[k].second;
-      phi[nv + k] = 4.0 * L[a] * L[b];
-      for (int p = 0; p < d; ++p) g[(nv + k) * d + p] = 4.0 * (dlam(a, p) * L[b] + L[a] * dlam(b, p));
-    }
+    local_basis(d, order, L, phi, g);
+    if (order == 3) local_basis(d, 2, L, qphi, qg);
+    else qphi.assign(L.begin(), L.end());
     for (int i = 0; i < nl; ++i)
       for (int j = 0; j < nl; ++j) {
         t.M[i * nl + j] += w * phi[i] * phi[j];
         for (int p = 0; p < d; ++p)
           for (int r = 0; r < d; ++r) t.S[((i * d + p) * nl + j) * d + r] += w * g[i * d + p] * g[j * d + r];
       }
-    for (int k = 0; k < nv; ++k)
+    for (int k = 0; k < nq; ++k)
       for (int i = 0; i < nl; ++i)
-        for (int p = 0; p < d; ++p) t.W[(k * nl + i) * d + p] += w * L[k] * g[i * d + p];
-    for (int a = 0; a < nv; ++a)
-      for (int b = 0; b < nv; ++b) t.M1[a * nv + b] += w * L[a] * L[b];
+        for (int p = 0; p < d; ++p) t.W[(k * nl + i) * d + p] += w * qphi[k] * g[i * d + p];
+    for (int a = 0; a < nq; ++a)
+      for (int b = 0; b < nq; ++b) t.M1[a * nq + b] += w * qphi[a] * qphi[b];
   }
-  // int |phi| / |K|: the vertex function lambda(2 lambda - 1) changes sign at
-  // lambda = 1/2; integrating against the density d (1 - t)^(d-1) of one
-  // barycentric coordinate on each side gives 3/32 (3D) and 1/8 (2D).  Edge
-  // functions are non-negative, so their value is int phi = 1/5 (3D), 1/3 (2D).
   t.absphi.assign(nl, 0);
-  for (int i = 0; i < nl; ++i) t.absphi[i] = i < nv ? (d == 3 ? 3.0 / 32.0 : 1.0 / 8.0) : (d == 3 ? 0.2 : 1.0 / 3.0);
+  if (order == 2) {
+    // int |phi| / |K|: the vertex function lambda(2 lambda - 1) changes sign at
+    // lambda = 1/2; integrating against the density d (1 - t)^(d-1) of one
+    // barycentric coordinate on each side gives 3/32 (3D) and 1/8 (2D).  Edge
+    // functions are non-negative, so their value is int phi = 1/5 (3D), 1/3 (2D).
+    for (int i = 0; i < nl; ++i) t.absphi[i] = i < nv ? (d == 3 ? 3.0 / 32.0 : 1.0 / 8.0) : (d == 3 ? 0.2 : 1.0 / 3.0);
+  } else {
+    double av, ae, af;
+    p3_abs_values(d, av, ae, af);
+    const int ned = d == 3 ? 6 : 3;
+    for (int i = 0; i < nl; ++i) t.absphi[i] = i < nv ? av : (i < nv + 2 * ned ? ae : af);
+  }
   // Element bounds of the Jacobi-scaled mass matrices (shape independent on
   // affine simplices): eigenvalues of D^{-1/2} Mref D^{-1/2}.
   auto scaled = [](const std::vector<double>& A, int n) {
@@ -162,17 +299,27 @@ RefTables make_tables(int d) {
     return B;
   };
   sym_eig_extremes(scaled(t.M, nl), nl, t.mass_lo, t.mass_hi);
-  sym_eig_extremes(scaled(t.M1, nv), nv, t.p1_lo, t.p1_hi);
+  sym_eig_extremes(scaled(t.M1, nq), nq, t.p1_lo, t.p1_hi);
   return t;
 }
 
-RefTables g_tab2, g_tab3;
+RefTables g_tab2, g_tab3, g_tab2c, g_tab3c;  // P2/P1 and P3/P2
 
 void upload_tables() {
   static bool done = false;
   if (done) return;
   g_tab2 = make_tables(2);
   g_tab3 = make_tables(3);
+  g_tab2c = make_tables(2, 3);
+  g_tab3c = make_tables(3, 3);
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_Mref3c), g_tab3c.M.data(), 400 * sizeof(double)));
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_Sref3c), g_tab3c.S.data(), 3600 * sizeof(double)));
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_Wref3c), g_tab3c.W.data(), 600 * sizeof(double)));
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_abs3c), g_tab3c.absphi.data(), 20 * sizeof(double)));
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_Mref2c), g_tab2c.M.data(), 100 * sizeof(double)));
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_Sref2c), g_tab2c.S.data(), 400 * sizeof(double)));
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_Wref2c), g_tab2c.W.data(), 120 * sizeof(double)));
+  HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_abs2c), g_tab2c.absphi.data(), 10 * sizeof(double)));
   HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_Mref3), g_tab3.M.data(), 100 * sizeof(double)));
   HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_Sref3), g_tab3.S.data(), 900 * sizeof(double)));
   HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_Wref3), g_tab3.W.data(), 120 * sizeof(double)));
@@ -186,21 +333,32 @@ void upload_tables() {
   done = true;
 }
 
-template <int D>
+// Reference tables of the velocity basis of order P (2 or 3) on the
+// D-simplex: NL velocity nodes, NQ pressure nodes (P1 for P = 2, P2 for 3).
+template <int D, int P = 2>
 struct Tab {
-  static constexpr int NL = D == 3 ? 10 : 6;
+  static constexpr int NL = P == 3 ? (D == 3 ? 20 : 10) : (D == 3 ? 10 : 6);
   static constexpr int NV = D + 1;
-  __device__ static double M(int i, int j) { return D == 3 ? c_Mref3[i * NL + j] : c_Mref2[i * NL + j]; }
+  static constexpr int NQ = P == 3 ? (D == 3 ? 10 : 6) : NV;
+  __device__ static double M(int i, int j) {
+    if (P == 3) return D == 3 ? c_Mref3c[i * NL + j] : c_Mref2c[i * NL + j];
+    return D == 3 ? c_Mref3[i * NL + j] : c_Mref2[i * NL + j];
+  }
   __device__ static double S(int i, int p, int j, int r) {
     const int k = ((i * D + p) * NL + j) * D + r;
+    if (P == 3) return D == 3 ? c_Sref3c[k] : c_Sref2c[k];
     return D == 3 ? c_Sref3[k] : c_Sref2[k];
   }
   __device__ static double W(int k, int i, int p) {
     const int o = (k * NL + i) * D + p;
+    if (P == 3) return D == 3 ? c_Wref3c[o] : c_Wref2c[o];
     return D == 3 ? c_Wref3[o] : c_Wref2[o];
   }
   __device__ static double M1(int a, int b) { return D == 3 ? c_M1ref3[a * NV + b] : c_M1ref2[a * NV + b]; }
-  __device__ static double absphi(int i) { return D == 3 ? c_abs3[i] : c_abs2[i]; }
+  __device__ static double absphi(int i) {
+    if (P == 3) return D == 3 ? c_abs3c[i] : c_abs2c[i];
+    return D == 3 ? c_abs3[i] : c_abs2[i];
+  }
 };
 
 // |K| and J^{-1} (stored [p][c]) of every simplex
@@ -253,20 +411,21 @@ __device__ __forceinline__ int64_t find_slot(const int32_t* __restrict__ cols, i
   return lo;
 }
 
-// rows of M_s and L_s over all P2 nodes
-template <int D>
+// rows of M_s and L_s over all velocity nodes (basis of order P; with P = 2
+// also the P2 pressure mass and Laplacian of the P3/P2 pair)
+template <int D, int P = 2>
 __global__ __launch_bounds__(kBlock) void k_gather_p2(int64_t n_p2, const int64_t* __restrict__ iptr,
                                                       const int32_t* __restrict__ ilist,
                                                       const int32_t* __restrict__ p2, const double* __restrict__ vol,
                                                       const double* __restrict__ jinv, const int32_t* __restrict__ rp,
                                                       const int32_t* __restrict__ cols, double* __restrict__ Mo,
                                                       double* __restrict__ Lo, double* __restrict__ Do) {
-  using Tb = Tab<D>;
+  using Tb = Tab<D, P>;
   GRID_STRIDE_ROWS(v, n_p2) {
     const int64_t lo = rp[v], hi = rp[v + 1];
     for (int64_t k = iptr[v]; k < iptr[v + 1]; ++k) {
-      const int64_t e = ilist[k] >> 4;
-      const int i = ilist[k] & 15;
+      const int64_t e = ilist[k] >> kLocBits;
+      const int i = ilist[k] & kLocMask;
       const double V = vol[e];
       double K[D][D];
       for (int p = 0; p < D; ++p)
@@ -298,19 +457,19 @@ __global__ __launch_bounds__(kBlock) void k_gather_p2(int64_t n_p2, const int64_
   }
 }
 
-// rows of B (one per P1 vertex, D planes) over all P2 columns
-template <int D>
+// rows of B (one per pressure node, D planes) over all velocity columns
+template <int D, int P = 2>
 __global__ __launch_bounds__(kBlock) void k_gather_b(int64_t n_p1, const int64_t* __restrict__ iptr,
                                                      const int32_t* __restrict__ ilist,
                                                      const int32_t* __restrict__ p2, const double* __restrict__ vol,
                                                      const double* __restrict__ jinv, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ cols, double* __restrict__ Bo) {
-  using Tb = Tab<D>;
+  using Tb = Tab<D, P>;
   GRID_STRIDE_ROWS(v, n_p1) {
     const int64_t lo = rp[v], hi = rp[v + 1];
     for (int64_t k = iptr[v]; k < iptr[v + 1]; ++k) {
-      const int64_t e = ilist[k] >> 4;
-      const int a = ilist[k] & 15;
+      const int64_t e = ilist[k] >> kLocBits;
+      const int a = ilist[k] & kLocMask;
       const double V = vol[e];
       for (int j = 0; j < Tb::NL; ++j) {
         const int64_t slot = find_slot(cols, lo, hi, p2[e * Tb::NL + j]);
@@ -426,8 +585,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_q(int64_t n_p1, const int64_t
   GRID_STRIDE_ROWS(v, n_p1) {
     const int64_t lo = rp[v], hi = rp[v + 1];
     for (int64_t k = iptr[v]; k < iptr[v + 1]; ++k) {
-      const int64_t e = ilist[k] >> 4;
-      const int a = ilist[k] & 15;
+      const int64_t e = ilist[k] >> kLocBits;
+      const int a = ilist[k] & kLocMask;
       const double V = vol[e];
       double ga[D];
       for (int c = 0; c < D; ++c) {  // physical gradient of lambda_a
@@ -450,13 +609,14 @@ __global__ __launch_bounds__(kBlock) void k_gather_q(int64_t n_p1, const int64_t
   }
 }
 
-template <int D>
+template <int D, int P = 2>
 __global__ __launch_bounds__(kBlock) void k_gather_lam(int64_t n_p2, const int64_t* __restrict__ iptr,
                                                        const int32_t* __restrict__ ilist,
                                                        const double* __restrict__ vol, double* __restrict__ lam) {
   GRID_STRIDE_ROWS(v, n_p2) {
     double s = 0;
-    for (int64_t k = iptr[v]; k < iptr[v + 1]; ++k) s += vol[ilist[k] >> 4] * Tab<D>::absphi(ilist[k] & 15);
+    for (int64_t k = iptr[v]; k < iptr[v + 1]; ++k)
+      s += vol[ilist[k] >> kLocBits] * Tab<D, P>::absphi(ilist[k] & kLocMask);
     lam[v] = s;
   }
 }
@@ -885,31 +1045,48 @@ void assemble_ctx(stokes_ctx* c) {
   upload_tables();
   const HostMesh& m = c->mesh;
   const int D = m.dim;
-  const int nv = D + 1;
+  const int K = m.order;  // velocity order: 2 (P2/P1) or 3 (P3/P2)
+  const int nq = m.nqloc;
+  const int64_t n_q = m.n_q;  // pressure nodes: the vertices, or the P2 nodes
 
-  // ---- host patterns
+  // ---- host patterns (velocity x velocity, pressure x velocity, pressure x pressure)
   HostCsr P2full, Bfull, P1;
   element_pattern(m.p2, m.nloc, m.n_p2, m.p2, m.nloc, m.n_p2, m.n_e, P2full);
-  element_pattern(m.elems, nv, m.n_p1, m.p2, m.nloc, m.n_p2, m.n_e, Bfull);
-  element_pattern(m.elems, nv, m.n_p1, m.elems, nv, m.n_p1, m.n_e, P1);
+  element_pattern(m.q, nq, n_q, m.p2, m.nloc, m.n_p2, m.n_e, Bfull);
+  element_pattern(m.q, nq, n_q, m.q, nq, n_q, m.n_e, P1);
   if (P2full.rowptr.back() >= (int64_t(1) << 31) || Bfull.rowptr.back() * D >= (int64_t(1) << 31))
     throw Error(STOKES_ERR_UNSUPPORTED, "mesh too large for 32-bit sparse indices");
   phase("host patterns");
 
   // internal numbering of the interior nodes: 8 slabs along the slowest axis
   // (one per XCD, see the XCD-aware row partition of the gathering kernels);
-  // inside a slab, the nodes of one parity type (the 2^dim classes of P2
-  // nodes of the Kuhn lattice, each with its own stencil) in natural order.
-  // Consecutive rows of a sliced-ELL slice are then translates of each
-  // other, so the k-th stencil slot of the lanes gathers consecutive nodes.
-  const int64_t n2 = 2 * int64_t(m.n) + 1, plane = D == 3 ? n2 * n2 : n2;
-  const int64_t n1 = int64_t(m.n) + 1;
-  // lattice coordinates in P2 grid units (P1 vertices at even points) and
-  // the parity type of every P2 node
-  const std::vector<int32_t> p2xyz = lattice_coords(D, n2, 1), p1xyz = lattice_coords(D, n1, 2);
+  // inside a slab, the nodes of one type (the K^dim classes of velocity
+  // nodes of the Kuhn lattice by their coordinates mod K, each with its own
+  // stencil) in natural order.  Consecutive rows of a sliced-ELL slice are
+  // then translates of each other, so the k-th stencil slot of the lanes
+  // gathers consecutive nodes.
+  const int64_t n2 = K * int64_t(m.n) + 1, plane = D == 3 ? n2 * n2 : n2;
+  const int64_t nql = (K - 1) * int64_t(m.n) + 1;
+  const int ntypes = D == 3 ? K * K * K : K * K;
+  // lattice coordinates of velocity and pressure nodes in one unit: h / 2
+  // for P2/P1 (vertices at even points), h / 6 for P3/P2; and the type of
+  // every velocity node
+  const int sv = K == 3 ? 2 : 1, sq = K == 3 ? 3 : 2;
+  const std::vector<int32_t> p2xyz = lattice_coords(D, n2, sv), p1xyz = lattice_coords(D, nql, sq);
   std::vector<uint8_t> p2type(m.n_p2);
-  for (int64_t v = 0; v < m.n_p2; ++v)
-    p2type[v] = static_cast<uint8_t>((p2xyz[3 * v] & 1) + 2 * (p2xyz[3 * v + 1] & 1) + 4 * (p2xyz[3 * v + 2] & 1));
+  for (int64_t v = 0; v < m.n_p2; ++v) {
+    int t = 0;
+    for (int ax = D - 1; ax >= 0; --ax) t = t * K + (p2xyz[3 * v + ax] / sv) % K;
+    p2type[v] = static_cast<uint8_t>(t);
+  }
+  // type of every pressure node (P2 pressure: coordinates mod 2; P1: one type)
+  std::vector<uint8_t> qtype(n_q, 0);
+  if (K == 3)
+    for (int64_t v = 0; v < n_q; ++v) {
+      int t = 0;
+      for (int ax = D - 1; ax >= 0; --ax) t = t * 2 + (p1xyz[3 * v + ax] / sq) % 2;
+      qtype[v] = static_cast<uint8_t>(t);
+    }
   // Stable bucket order by (slab, block, type), natural order inside a
   // bucket.  A block is `zblock` consecutive lattice planes of the slab (0:
   // the whole slab; by default 4 planes once a plane holds more than 2^16
@@ -927,14 +1104,14 @@ void assemble_ctx(stokes_ctx* c) {
     const int64_t zbk = c->zblock >= 0 ? c->zblock : (plane > (int64_t(1) << 16) ? 4 : 0);
     const int64_t zb = zbk > 0 ? zbk : nK;
     const int64_t nblk = (nK + zb - 1) / zb + 8;  // blocks per slab, bounded
-    std::vector<int64_t> start(8 * nblk * 8 + 1, 0);
+    std::vector<int64_t> start(8 * nblk * ntypes + 1, 0);
     std::vector<int32_t> bucket(m.n_p2, 0);
     for (int64_t v = 0; v < m.n_p2; ++v) {
       if (m.p2_bnd[v]) continue;
       const int64_t K = v / plane;  // 1 .. 2n-1 on interior nodes
       const int64_t sl = std::min<int64_t>(7, (K - 1) * 8 / nK);
       const int64_t blk = std::min<int64_t>(nblk - 1, (K - 1 - slab_lo[sl]) / zb);
-      bucket[v] = static_cast<int32_t>((sl * nblk + blk) * 8 + p2type[v]);
+      bucket[v] = static_cast<int32_t>((sl * nblk + blk) * ntypes + p2type[v]);
       ++start[bucket[v] + 1];
     }
     for (size_t k = 0; k + 1 < start.size(); ++k) start[k + 1] += start[k];
@@ -942,13 +1119,19 @@ void assemble_ctx(stokes_ctx* c) {
     for (int64_t v = 0; v < m.n_p2; ++v)
       if (!m.p2_bnd[v]) interior[start[bucket[v]]++] = static_cast<int32_t>(v);
   }
+  // stencil slots: offsets reach 2 (P2/P1, units h / 2) or 6 (P3/P2, h / 6)
   SellSlots slots_p2p2, slots_p2p1, slots_p1p2;
-  slots_p2p2.nclass = slots_p2p1.nclass = 8;
+  slots_p2p2.nclass = slots_p2p1.nclass = ntypes;
   slots_p2p2.rcls = slots_p2p1.rcls = p2type.data();
   slots_p2p2.rxyz = slots_p2p2.cxyz = slots_p2p1.rxyz = p2xyz.data();
   slots_p2p1.cxyz = p1xyz.data();
   slots_p1p2.rxyz = p1xyz.data();
   slots_p1p2.cxyz = p2xyz.data();
+  if (K == 3) {
+    slots_p2p2.R = slots_p2p1.R = slots_p1p2.R = 6;
+    slots_p1p2.nclass = D == 3 ? 8 : 4;
+    slots_p1p2.rcls = qtype.data();
+  }
   c->n_int = static_cast<int64_t>(interior.size());
   c->h_int2nat = interior;
   c->h_nat2int.assign(m.n_p2, -1);
@@ -957,10 +1140,11 @@ void assemble_ctx(stokes_ctx* c) {
   upload(c->nat2int, c->h_nat2int);
 
   // ---- upload mesh + incidences, geometry
-  DevBuf d_vc, d_el, d_p2, d_vol, d_jinv, d_i2p, d_i2l, d_i1p, d_i1l;
+  DevBuf d_vc, d_el, d_p2, d_vol, d_jinv, d_i2p, d_i2l, d_i1p, d_i1l, d_q;
   upload(d_vc, m.vcoords);
   upload(d_el, m.elems);
   upload(d_p2, m.p2);
+  upload(d_q, m.q);
   d_vol.alloc(m.n_e * sizeof(double));
   d_jinv.alloc(m.n_e * D * D * sizeof(double));
   if (D == 3) launch(c, m.n_e, k_geom<3>, m.n_e, d_vc.as<double>(), d_el.as<int32_t>(), d_vol.as<double>(), d_jinv.as<double>());
@@ -971,7 +1155,7 @@ void assemble_ctx(stokes_ctx* c) {
     incidence(m.p2, m.nloc, m.n_e, m.n_p2, ptr, lst);
     upload(d_i2p, ptr);
     upload(d_i2l, lst);
-    incidence(m.elems, nv, m.n_e, m.n_p1, ptr, lst);
+    incidence(m.q, nq, m.n_e, n_q, ptr, lst);
     upload(d_i1p, ptr);
     upload(d_i1l, lst);
   }
@@ -1027,35 +1211,36 @@ void assemble_ctx(stokes_ctx* c) {
   HIP_CHECK(hipMemsetAsync(c->B_full.p, 0, nnzb * D * sizeof(double), c->stream));
   HIP_CHECK(hipMemsetAsync(c->MQ_csr.p, 0, nnz1 * sizeof(double), c->stream));
   HIP_CHECK(hipMemsetAsync(c->LQ_csr.p, 0, nnz1 * sizeof(double), c->stream));
-  if (D == 3) {
-    launch(c, m.n_p2, k_gather_p2<3>, m.n_p2, d_i2p.as<int64_t>(), d_i2l.as<int32_t>(), d_p2.as<int32_t>(),
+  // the element gathers for one (dim, order)
+  auto gathers = [&](auto Dc, auto Pc) {
+    constexpr int DD = decltype(Dc)::value, PP = decltype(Pc)::value;
+    launch(c, m.n_p2, k_gather_p2<DD, PP>, m.n_p2, d_i2p.as<int64_t>(), d_i2l.as<int32_t>(), d_p2.as<int32_t>(),
            d_vol.as<double>(), d_jinv.as<double>(), c->p2full.rowptr.as<int32_t>(), c->p2full.cols.as<int32_t>(),
            c->M_full.as<double>(), c->L_full.as<double>(), c->strain ? c->D_full.as<double>() : nullptr);
-    launch(c, m.n_p1, k_gather_b<3>, m.n_p1, d_i1p.as<int64_t>(), d_i1l.as<int32_t>(), d_p2.as<int32_t>(),
+    launch(c, n_q, k_gather_b<DD, PP>, n_q, d_i1p.as<int64_t>(), d_i1l.as<int32_t>(), d_p2.as<int32_t>(),
            d_vol.as<double>(), d_jinv.as<double>(), c->bfull.rowptr.as<int32_t>(), c->bfull.cols.as<int32_t>(),
            c->B_full.as<double>());
-    launch(c, m.n_p1, k_gather_q<3>, m.n_p1, d_i1p.as<int64_t>(), d_i1l.as<int32_t>(), d_el.as<int32_t>(),
-           d_vol.as<double>(), d_jinv.as<double>(), c->p1.rowptr.as<int32_t>(), c->p1.cols.as<int32_t>(),
-           c->MQ_csr.as<double>(), c->LQ_csr.as<double>());
-    launch(c, m.n_p2, k_gather_lam<3>, m.n_p2, d_i2p.as<int64_t>(), d_i2l.as<int32_t>(), d_vol.as<double>(),
+    if (PP == 3)  // P2 pressure: the P2 mass and Laplacian rows
+      launch(c, n_q, k_gather_p2<DD, 2>, n_q, d_i1p.as<int64_t>(), d_i1l.as<int32_t>(), d_q.as<int32_t>(),
+             d_vol.as<double>(), d_jinv.as<double>(), c->p1.rowptr.as<int32_t>(), c->p1.cols.as<int32_t>(),
+             c->MQ_csr.as<double>(), c->LQ_csr.as<double>(), (double*)nullptr);
+    else
+      launch(c, n_q, k_gather_q<DD>, n_q, d_i1p.as<int64_t>(), d_i1l.as<int32_t>(), d_el.as<int32_t>(),
+             d_vol.as<double>(), d_jinv.as<double>(), c->p1.rowptr.as<int32_t>(), c->p1.cols.as<int32_t>(),
+             c->MQ_csr.as<double>(), c->LQ_csr.as<double>());
+    launch(c, m.n_p2, k_gather_lam<DD, PP>, m.n_p2, d_i2p.as<int64_t>(), d_i2l.as<int32_t>(), d_vol.as<double>(),
            c->lam_full.as<double>());
-  } else {
-    launch(c, m.n_p2, k_gather_p2<2>, m.n_p2, d_i2p.as<int64_t>(), d_i2l.as<int32_t>(), d_p2.as<int32_t>(),
-           d_vol.as<double>(), d_jinv.as<double>(), c->p2full.rowptr.as<int32_t>(), c->p2full.cols.as<int32_t>(),
-           c->M_full.as<double>(), c->L_full.as<double>(), c->strain ? c->D_full.as<double>() : nullptr);
-    launch(c, m.n_p1, k_gather_b<2>, m.n_p1, d_i1p.as<int64_t>(), d_i1l.as<int32_t>(), d_p2.as<int32_t>(),
-           d_vol.as<double>(), d_jinv.as<double>(), c->bfull.rowptr.as<int32_t>(), c->bfull.cols.as<int32_t>(),
-           c->B_full.as<double>());
-    launch(c, m.n_p1, k_gather_q<2>, m.n_p1, d_i1p.as<int64_t>(), d_i1l.as<int32_t>(), d_el.as<int32_t>(),
-           d_vol.as<double>(), d_jinv.as<double>(), c->p1.rowptr.as<int32_t>(), c->p1.cols.as<int32_t>(),
-           c->MQ_csr.as<double>(), c->LQ_csr.as<double>());
-    launch(c, m.n_p2, k_gather_lam<2>, m.n_p2, d_i2p.as<int64_t>(), d_i2l.as<int32_t>(), d_vol.as<double>(),
-           c->lam_full.as<double>());
-  }
+  };
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
+  if (D == 3 && K == 3) gathers(I3{}, I3{});
+  else if (D == 3) gathers(I3{}, I2{});
+  else if (K == 3) gathers(I2{}, I3{});
+  else gathers(I2{}, I2{});
 
   phase("element gathers");
   // ---- SELL operators
-  std::vector<int32_t> p1_rows(m.n_p1), p1_ident(m.n_p1);
+  std::vector<int32_t> p1_rows(n_q), p1_ident(n_q);
   std::iota(p1_rows.begin(), p1_rows.end(), 0);
   std::iota(p1_ident.begin(), p1_ident.end(), 0);
   build_sell(P2full, c->h_int2nat, c->h_nat2int, nullptr, 1, c->sA, &slots_p2p2);
@@ -1069,29 +1254,39 @@ void assemble_ctx(stokes_ctx* c) {
     product_pattern(Bfull, BT, c->h_nat2int, XLpat);
     up_csr(XLpat, c->xl);
     c->XL_csr.alloc(c->xl.nnz * sizeof(double));
-    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((m.n_p1 + 3) / 4, 65535));
+    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((n_q + 3) / 4, 65535));
     if (D == 3)
-      hipLaunchKernelGGL(k_gather_xl<3>, dim3(nb), dim3(kBlock), 0, c->stream, m.n_p1, c->bfull.rowptr.as<int32_t>(),
+      hipLaunchKernelGGL(k_gather_xl<3>, dim3(nb), dim3(kBlock), 0, c->stream, n_q, c->bfull.rowptr.as<int32_t>(),
                          c->bfull.cols.as<int32_t>(), c->B_full.as<double>(), c->lam_full.as<double>(),
                          c->nat2int.as<int32_t>(), c->xl.rowptr.as<int32_t>(), c->xl.cols.as<int32_t>(),
                          c->XL_csr.as<double>());
     else
-      hipLaunchKernelGGL(k_gather_xl<2>, dim3(nb), dim3(kBlock), 0, c->stream, m.n_p1, c->bfull.rowptr.as<int32_t>(),
+      hipLaunchKernelGGL(k_gather_xl<2>, dim3(nb), dim3(kBlock), 0, c->stream, n_q, c->bfull.rowptr.as<int32_t>(),
                          c->bfull.cols.as<int32_t>(), c->B_full.as<double>(), c->lam_full.as<double>(),
                          c->nat2int.as<int32_t>(), c->xl.rowptr.as<int32_t>(), c->xl.cols.as<int32_t>(),
                          c->XL_csr.as<double>());
     HIP_CHECK(hipGetLastError());
-    const std::vector<int32_t> q1 = lattice_coords(D, n1, 1);
+    // pressure lattice in its own units: reach 2 (P1, two element rings) or
+    // 4 (P2, units h / 2)
+    const std::vector<int32_t> q1 = lattice_coords(D, nql, 1);
     SellSlots slx;
-    slx.R = 2;
+    slx.R = K == 3 ? 4 : 2;
     slx.rxyz = slx.cxyz = q1.data();
+    if (K == 3) {
+      slx.nclass = D == 3 ? 8 : 4;
+      slx.rcls = qtype.data();
+    }
     build_sell(XLpat, p1_rows, p1_ident, nullptr, 1, c->sX, &slx);
   }
   {
-    const std::vector<int32_t> q1 = lattice_coords(D, n1, 1);
+    const std::vector<int32_t> q1 = lattice_coords(D, nql, 1);
     SellSlots slq;
-    slq.R = 1;
+    slq.R = K == 3 ? 2 : 1;
     slq.rxyz = slq.cxyz = q1.data();
+    if (K == 3) {
+      slq.nclass = D == 3 ? 8 : 4;
+      slq.rcls = qtype.data();
+    }
     build_sell(P1, p1_rows, p1_ident, nullptr, 1, c->sQ, &slq);
   }
   phase("sliced-ELL layouts");
@@ -1143,11 +1338,11 @@ void assemble_ctx(stokes_ctx* c) {
   dinv(c->sQ, c->LQ64, c->dLQ64);
   c->lamInv64.alloc(c->n_int * sizeof(double));
   launch(c, c->n_int, k_lam_int, c->n_int, c->int2nat.as<int32_t>(), c->lam_full.as<double>(), c->lamInv64.as<double>());
-  c->mQ.alloc(m.n_p1 * sizeof(double));
-  launch(c, m.n_p1, k_rowsum_csr, m.n_p1, c->p1.rowptr.as<int32_t>(), c->MQ_csr.as<double>(), c->mQ.as<double>());
+  c->mQ.alloc(n_q * sizeof(double));
+  launch(c, n_q, k_rowsum_csr, n_q, c->p1.rowptr.as<int32_t>(), c->MQ_csr.as<double>(), c->mQ.as<double>());
   {
-    std::vector<double> h(m.n_p1);
-    HIP_CHECK(hipMemcpyAsync(h.data(), c->mQ.p, m.n_p1 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> h(n_q);
+    HIP_CHECK(hipMemcpyAsync(h.data(), c->mQ.p, n_q * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_CHECK(hipStreamSynchronize(c->stream));
     c->mQ_sum = 0;
     for (double x : h) c->mQ_sum += x;
@@ -1169,19 +1364,23 @@ void assemble_ctx(stokes_ctx* c) {
   to32(c->XL64, c->XL32, c->sX.nnz_pad);
   to32(c->dA64, c->dA32, c->n_int);
   to32(c->dMV64, c->dMV32, c->n_int);
-  to32(c->dMQ64, c->dMQ32, m.n_p1);
-  to32(c->dXQ64, c->dXQ32, m.n_p1);
-  to32(c->dLQ64, c->dLQ32, m.n_p1);
+  to32(c->dMQ64, c->dMQ32, n_q);
+  to32(c->dXQ64, c->dXQ32, n_q);
+  to32(c->dLQ64, c->dLQ32, n_q);
   to32(c->lamInv64, c->lamInv32, c->n_int);
 
-  // ---- Chebyshev intervals
-  const RefTables& tb = D == 3 ? g_tab3 : g_tab2;
+  // ---- Chebyshev intervals: element bounds of the Jacobi-scaled velocity
+  // and pressure masses (the pressure table of a P3/P2 context is the P2 one)
+  const RefTables& tb = K == 3 ? (D == 3 ? g_tab3c : g_tab2c) : (D == 3 ? g_tab3 : g_tab2);
   c->bMV = {tb.mass_lo, tb.mass_hi};
   c->bMQ = {tb.p1_lo, tb.p1_hi};
   phase("values and FP32 copies");
   estimate_bounds(c);
   phase("Chebyshev intervals");
-  build_mg(c);
+  // the geometric multigrids coarsen the P1 pressure lattice (and the P2
+  // velocity lattice): a P3/P2 context has none, its pressure solves use
+  // Chebyshev-Jacobi polynomials of M_Q + L_Q instead
+  if (K != 3) build_mg(c);
   phase("multigrid hierarchies");
   HIP_CHECK(hipStreamSynchronize(c->stream));
 }

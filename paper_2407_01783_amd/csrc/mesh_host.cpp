@@ -48,7 +48,7 @@ void parallel_for(int64_t n, F&& body) {
 
 }  // namespace
 
-bool build_mesh(int dim, int n, uint64_t seed, double jitter, HostMesh& m) {
+bool build_mesh(int dim, int n, uint64_t seed, double jitter, HostMesh& m, int order) {
   m.dim = dim;
   m.n = n;
   m.nloc = dim == 3 ? 10 : 6;
@@ -59,7 +59,8 @@ bool build_mesh(int dim, int n, uint64_t seed, double jitter, HostMesh& m) {
   const int64_t ncell = ipow(n, dim);
   const int nperm = dim == 3 ? 6 : 2;
   m.n_e = ncell * nperm;
-  if (m.n_p2 >= (int64_t(1) << 31) || m.n_e >= (int64_t(1) << 27)) return false;
+  if (m.n_p2 >= (int64_t(1) << 31) || m.n_e >= (int64_t(1) << (31 - kLocBits))) return false;
+  if (order == 3 && ipow(3 * int64_t(n) + 1, dim) >= (int64_t(1) << 31)) return false;
 
   // vertex coordinates: x fastest, interior vertices jittered
   m.vcoords.assign(m.n_p1 * dim, 0.0);
@@ -155,6 +156,92 @@ bool build_mesh(int dim, int n, uint64_t seed, double jitter, HostMesh& m) {
       if (I == 0 || I == n2 - 1) m.p2_bnd[id] = 1;
     }
   }
+  m.order = order;
+  if (order != 3) {
+    // P2/P1: the pressure lives on the vertices
+    m.q = m.elems;
+    m.n_q = m.n_p1;
+    m.nqloc = nv;
+    return true;
+  }
+  // P3/P2: the P2 nodes above become the pressure space; the velocity moves
+  // to the P3 nodes of the (3n+1)^d lattice
+  m.q.swap(m.p2);
+  m.n_q = m.n_p2;
+  m.nqloc = m.nloc;
+  const int64_t n3 = 3 * int64_t(n) + 1;
+  m.n_p2 = ipow(n3, dim);
+  const int nf = dim == 3 ? 4 : 1;
+  static const int faces3[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
+  static const int faces2[1][3] = {{0, 1, 2}};
+  const int ned = dim == 3 ? 6 : 3;
+  m.nloc = nv + 2 * ned + nf;
+  m.p2.assign(m.n_e * m.nloc, 0);
+  m.p2coords.assign(m.n_p2 * dim, 0.0);
+  for (int64_t el = 0; el < m.n_e; ++el) {
+    const int32_t* ev = &m.elems[el * nv];
+    int32_t* out = &m.p2[el * m.nloc];
+    // lattice position (units h / 3) of vertex a of this simplex
+    auto vpos = [&](int a, int c) { return static_cast<int64_t>((ev[a] / ipow(n1, c)) % n1); };
+    auto node_id = [&](const int* cm) {
+      int64_t id = 0, st = 1;
+      for (int c = 0; c < dim; ++c, st *= n3) {
+        int64_t x = 0;
+        for (int a = 0; a < nv; ++a) x += cm[a] * vpos(a, c);
+        id += x * st;
+      }
+      return id;
+    };
+    auto X = [&](int a, int c) { return m.vcoords[int64_t(ev[a]) * dim + c]; };
+    int li = 0;
+    for (int a = 0; a < nv; ++a, ++li) {
+      int cm[4] = {0, 0, 0, 0};
+      cm[a] = 3;
+      const int64_t id = node_id(cm);
+      out[li] = static_cast<int32_t>(id);
+      for (int c = 0; c < dim; ++c) m.p2coords[id * dim + c] = X(a, c);
+    }
+    for (int k = 0; k < ned; ++k) {
+      const int a = dim == 3 ? edges3[k][0] : edges2[k][0];
+      const int b = dim == 3 ? edges3[k][1] : edges2[k][1];
+      for (int side = 0; side < 2; ++side, ++li) {
+        const int near = side == 0 ? a : b, far = side == 0 ? b : a;
+        int cm[4] = {0, 0, 0, 0};
+        cm[near] = 2;
+        cm[far] = 1;
+        const int64_t id = node_id(cm);
+        out[li] = static_cast<int32_t>(id);
+        for (int c = 0; c < dim; ++c) {
+          const double twice = 2.0 * X(near, c);
+          const double s = twice + X(far, c);
+          m.p2coords[id * dim + c] = s / 3.0;
+        }
+      }
+    }
+    for (int k = 0; k < nf; ++k, ++li) {
+      const int* f = dim == 3 ? faces3[k] : faces2[k];
+      int cm[4] = {0, 0, 0, 0};
+      for (int t = 0; t < 3; ++t) cm[f[t]] = 1;
+      const int64_t id = node_id(cm);
+      out[li] = static_cast<int32_t>(id);
+      int s3[3] = {f[0], f[1], f[2]};  // local indices sorted by global vertex id
+      std::sort(s3, s3 + 3, [&](int x, int y) { return ev[x] < ev[y]; });
+      for (int c = 0; c < dim; ++c) {
+        const double s01 = X(s3[0], c) + X(s3[1], c);
+        const double s = s01 + X(s3[2], c);
+        m.p2coords[id * dim + c] = s / 3.0;
+      }
+    }
+  }
+  m.p2_bnd.assign(m.n_p2, 0);
+  for (int64_t id = 0; id < m.n_p2; ++id) {
+    int64_t rem = id;
+    for (int c = 0; c < dim; ++c) {
+      const int64_t I = rem % n3;
+      rem /= n3;
+      if (I == 0 || I == n3 - 1) m.p2_bnd[id] = 1;
+    }
+  }
   return true;
 }
 
@@ -167,7 +254,7 @@ void incidence(const std::vector<int32_t>& nodes, int nl, int64_t n_e, int64_t n
   list.assign(ptr[n_nodes], 0);
   std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
   for (int64_t e = 0; e < n_e; ++e)
-    for (int a = 0; a < nl; ++a) list[fill[nodes[e * nl + a]]++] = static_cast<int32_t>((e << 4) | a);
+    for (int a = 0; a < nl; ++a) list[fill[nodes[e * nl + a]]++] = static_cast<int32_t>((e << kLocBits) | a);
 }
 
 void element_pattern(const std::vector<int32_t>& row_nodes, int nr, int64_t nrows,
@@ -182,7 +269,7 @@ void element_pattern(const std::vector<int32_t>& row_nodes, int nr, int64_t nrow
   auto gather = [&](int64_t r, std::vector<int32_t>& buf) {
     buf.clear();
     for (int64_t k = iptr[r]; k < iptr[r + 1]; ++k) {
-      const int64_t e = ilist[k] >> 4;
+      const int64_t e = ilist[k] >> kLocBits;
       for (int b = 0; b < nc; ++b) buf.push_back(col_nodes[e * nc + b]);
     }
     std::sort(buf.begin(), buf.end());

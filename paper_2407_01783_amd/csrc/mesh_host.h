@@ -1,10 +1,17 @@
-// Host-side structured Kuhn mesh, P2/P1 numbering and sparsity patterns.
+// Host-side structured Kuhn mesh, Taylor-Hood numbering and sparsity patterns.
 //
 // The mesh is the unit square / cube cut into n^d cells, each split into d!
 // simplices (Kuhn split): for every permutation pi of the axes, taken in
 // lexicographic order, the simplex (v0, v0 + e_pi0, v0 + e_pi0 + e_pi1, ...,
 // v0 + (1,..,1)).  P2 nodes are the points of the refined (2n+1)^d grid
-// (vertex v -> 2v, edge (a, b) -> v_a + v_b).  Interior vertices move by a
+// (vertex v -> 2v, edge (a, b) -> v_a + v_b).  With the P3/P2 pair the
+// velocity nodes are the points of the (3n+1)^d lattice (barycentric
+// multi-index c, |c| = 3, of a simplex with vertex lattice points V_a -> the
+// point sum c_a V_a) and the pressure nodes are the P2 points above; the local
+// P3 order is vertices, then per local edge (a, b) the node next to a and the
+// node next to b, then the faces (a, b, c) (2D: the interior node).  Edge
+// nodes sit at (2 x_near + x_far) / 3, face nodes at ((x_p + x_q) + x_r) / 3
+// with p < q < r the global vertex ids.  Interior vertices move by a
 // seeded uniform jitter drawn from the SplitMix64 finaliser (Steele, Lea &
 // Flood 2014) on the counter d*g + c; this file must be compiled without
 // floating-point contraction so the coordinates are reproducible bit for bit.
@@ -15,14 +22,23 @@
 
 namespace stokes {
 
+// Incidence lists pack (simplex << kLocBits) | local index into an int32.
+constexpr int kLocBits = 5;
+constexpr int32_t kLocMask = (1 << kLocBits) - 1;
+
+// `order` 2: Taylor-Hood P2/P1, 3: P3/P2.  The velocity space lives in
+// p2 / n_p2 / p2coords / p2_bnd (P2 or P3 nodes), the pressure space in
+// q / n_q / nqloc (the vertices, or the P2 nodes); vcoords / elems stay the
+// vertex mesh that carries the geometry.
 struct HostMesh {
-  int dim = 0, n = 0, nloc = 0;
-  int64_t n_p1 = 0, n_p2 = 0, n_e = 0;
+  int dim = 0, n = 0, nloc = 0, order = 2, nqloc = 0;
+  int64_t n_p1 = 0, n_p2 = 0, n_e = 0, n_q = 0;
   std::vector<double> vcoords;   // [n_p1][dim]
-  std::vector<double> p2coords;  // [n_p2][dim]
+  std::vector<double> p2coords;  // [n_p2][dim] velocity node coordinates
   std::vector<int32_t> elems;    // [n_e][dim+1] vertex ids
-  std::vector<int32_t> p2;       // [n_e][nloc] P2 node ids
+  std::vector<int32_t> p2;       // [n_e][nloc] velocity node ids
   std::vector<uint8_t> p2_bnd;   // [n_p2] 1 on the boundary
+  std::vector<int32_t> q;        // [n_e][nqloc] pressure node ids
 };
 
 struct HostCsr {
@@ -34,8 +50,9 @@ struct HostCsr {
 // Problem-size arithmetic without building anything.
 int64_t ipow(int64_t b, int e);
 
-// Builds the mesh; returns false if the sizes overflow 32-bit indices.
-bool build_mesh(int dim, int n, uint64_t seed, double jitter, HostMesh& m);
+// Builds the mesh (order 2: P2/P1, 3: P3/P2); returns false if the sizes
+// overflow 32-bit indices.
+bool build_mesh(int dim, int n, uint64_t seed, double jitter, HostMesh& m, int order = 2);
 
 // Pattern of (row_nodes[e][a], col_nodes[e][b]) pairs over all simplices.
 // row_nodes has nr entries per simplex, col_nodes nc entries per simplex.
@@ -75,7 +92,7 @@ void galerkin_p1(int dim, int nf, int nc, const HostCsr& A, const std::vector<do
 // Coarse boundary nodes (Dirichlet) are dropped.
 void p2_prolongation(int dim, int nf, const std::vector<int32_t>& fine_nat, HostCsr& P, std::vector<double>& pv);
 
-// Incidence node -> (simplex << 4 | local index) for the node table
+// Incidence node -> (simplex << kLocBits | local index) for the node table
 // nodes[e][0..nl), as CSR over n_nodes.
 void incidence(const std::vector<int32_t>& nodes, int nl, int64_t n_e, int64_t n_nodes,
                std::vector<int64_t>& ptr, std::vector<int32_t>& list);

@@ -1,6 +1,7 @@
 // Launchers for the kernels in kernels.h.
 #include <cstdio>
 #include <cstdlib>
+#include <string>
 #include <type_traits>
 
 #include "kernels.h"
@@ -679,9 +680,56 @@ void cheb_step(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* d, T
                     double(S.nrows) * sizeof(T) * (W * (rvec ? 7.0 : 6.0) + 1.0));
 }
 
+// Tuning cache (STOKES_TUNE_CACHE = path of a text file): one line
+// "<problem> <lanes key> <G>" per tuned choice, where <problem> names the
+// mesh, element pair, form and device.  A context whose problem is in the
+// file takes its choices from there instead of timing them again.
+std::string tune_problem(stokes_ctx* c) {
+  hipDeviceProp_t pr;
+  HIP_CHECK(hipGetDeviceProperties(&pr, c->device));
+  std::string arch(pr.gcnArchName);
+  for (char& ch : arch)
+    if (ch == ' ' || ch == ':') ch = '_';
+  char b[256];
+  std::snprintf(b, sizeof(b), "d%d_n%d_p%d_s%d_rows%lld_%s", c->dim, c->mesh.n, c->mesh.order, c->strain ? 1 : 0,
+                (long long)c->n_int, arch.c_str());
+  return b;
+}
+
+// Fill c->lanes from the cache file; true if `key` was found.
+bool tune_cache_load(stokes_ctx* c, int key) {
+  const char* path = std::getenv("STOKES_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* fh = std::fopen(path, "r");
+  if (!fh) return false;
+  const std::string prob = tune_problem(c);
+  char name[256];
+  int k = 0, g = 0;
+  bool found = false;
+  while (std::fscanf(fh, "%255s %d %d", name, &k, &g) == 3)
+    if (prob == name && (g == 1 || g == 2 || g == 4 || g == 8)) {
+      c->lanes[k] = g;
+      found = found || k == key;
+    }
+  std::fclose(fh);
+  return found;
+}
+
+void tune_cache_store(stokes_ctx* c, const std::vector<int>& keys) {
+  const char* path = std::getenv("STOKES_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* fh = std::fopen(path, "a");
+  if (!fh) return;  // an unwritable cache only costs the timing next time
+  const std::string prob = tune_problem(c);
+  for (int k : keys)
+    if (c->lanes.count(k)) std::fprintf(fh, "%s %d %d\n", prob.c_str(), k, c->lanes[k]);
+  std::fclose(fh);
+}
+
 // Autotune G for the velocity-row kernels of width W in precision T: time the
 // plain SELL product on the velocity block for every compiled G and keep the
-// fastest (cached per context; skipped while a graph is being captured).
+// fastest (cached per context and, with STOKES_TUNE_CACHE, in a file;
+// skipped while a graph is being captured).
 template <class T>
 void tune_lanes(stokes_ctx* c, int W) {
   const int key = W * 2 + (std::is_same<T, float>::value ? 1 : 0);
@@ -696,6 +744,7 @@ void tune_lanes(stokes_ctx* c, int W) {
     c->lanes[key] = 1;
     return;
   }
+  if (tune_cache_load(c, key)) return;
   const int64_t n = c->n_int * W;
   DevBuf x, y;
   x.alloc(n * sizeof(T));
@@ -787,6 +836,7 @@ void tune_lanes(stokes_ctx* c, int W) {
     c->lanes[kQbKey + key] = qbest;
   }
   c->force_lanes = 0;
+  tune_cache_store(c, {key, kBtKey + key, kQbKey + key});
   HIP_CHECK(hipEventDestroy(e0));
   HIP_CHECK(hipEventDestroy(e1));
   HIP_CHECK(hipStreamSynchronize(c->stream));

@@ -41,6 +41,10 @@ namespace {
 // flight is then almost surely not the last).
 constexpr double kQueueAhead = 30.0;
 
+// Degree of the Chebyshev-Jacobi polynomial of eps M_Q + L_Q that stands in
+// for the pressure multigrid V-cycle where there is no hierarchy.
+constexpr int kXQDegree = 8;
+
 template <int V>
 using IC = std::integral_constant<int, V>;
 
@@ -397,10 +401,21 @@ class Engine {
   void x_solve(const T* b, T* x) {
     Prec pc{&c_->sQ, ops::pick<T>(c_->XQ64, c_->XQ32), ops::pick<T>(c_->dXQ64, c_->dXQ32), c_->bXQ, 1, {}};
     const MgHier& H = (o_.schur_pc == STOKES_CC_LUMPED && c_->use_mgx) ? c_->mgx : c_->mgq;
-    pc.apply = [this, &H](const T* r, T* z) { mg_vcycle<T>(c_, H, nrb_, r, z, 0); };
-    if (o_.inner_mode == STOKES_INNER_FIXED) {
-      mg_vcycle<T>(c_, H, nrb_, b, x, 0);
-      return;
+    if (H.lv.empty()) {
+      // no multigrid hierarchy (the P3/P2 pair): the preconditioner, and in
+      // fixed mode the approximation itself, is a Chebyshev-Jacobi polynomial
+      // of eps M_Q + L_Q (eps = 1, the operator of Sec. 4.2)
+      pc.degree = kXQDegree;
+      if (o_.inner_mode == STOKES_INNER_FIXED) {
+        cheb_apply("xfx", c_->sQ, pc.vals, pc.dinv, c_->bXQ, kXQDegree, nrb_, b, x);
+        return;
+      }
+    } else {
+      pc.apply = [this, &H](const T* r, T* z) { mg_vcycle<T>(c_, H, nrb_, r, z, 0); };
+      if (o_.inner_mode == STOKES_INNER_FIXED) {
+        mg_vcycle<T>(c_, H, nrb_, b, x, 0);
+        return;
+      }
     }
     Op op;
     const T* opvals = nullptr;
@@ -1147,6 +1162,8 @@ int projection_loop(stokes_ctx* c, const stokes_solve_opts& o, int nrb, const do
 
 int projection_internal(stokes_ctx* c, const stokes_solve_opts& o, int nrb, const double* F, const double* g,
                         const double* pold, double* xu, double* xp, SolveStats& st) {
+  if (o.vel_pc == STOKES_VEL_MG && c->mesh.order == 3)
+    throw Error(STOKES_ERR_UNSUPPORTED, "the velocity multigrid needs the P2/P1 pair");
   ops::ensure_lanes(c, c->dim * nrb, false);
   if (o.precision == STOKES_MIXED) ops::ensure_lanes(c, c->dim * nrb, true);
   if (o.vel_pc == STOKES_VEL_MG && (!c->vmg_built || c->vmg_mu != c->prob.mu)) build_vmg(c);
@@ -1168,6 +1185,8 @@ template void vel_cheb_apply<double>(stokes_ctx*, int, int, const double*, doubl
 
 int solve_internal(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, const double* F, const double* g,
                    double* xu, double* xp, SolveStats& st, bool x_zero) {
+  if (o.vel_pc == STOKES_VEL_MG && c->mesh.order == 3)
+    throw Error(STOKES_ERR_UNSUPPORTED, "the velocity multigrid needs the P2/P1 pair");
   ops::ensure_lanes(c, c->dim * nrb, false);  // FP64 outer operator
   if (o.vel_pc == STOKES_VEL_MG && (!c->vmg_built || c->vmg_mu != c->prob.mu)) build_vmg(c);
   if (o.precision == STOKES_MIXED) ops::ensure_lanes(c, c->dim * nrb, true);

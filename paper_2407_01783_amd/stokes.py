@@ -22,15 +22,18 @@ def _stream_handle():
 class StokesProblem:
     """An assembled generalized Stokes operator on the Kuhn mesh (one GPU)."""
 
-    def __init__(self, dim, n, mesh_seed=0, jitter=0.0, mu=1.0, alpha=1.0, gamma=0.0, strain=False):
+    def __init__(self, dim, n, mesh_seed=0, jitter=0.0, mu=1.0, alpha=1.0, gamma=0.0, strain=False, p3=False):
         """strain=True: velocity matrix alpha M + mu (L + D) (the strain-rate
-        form); otherwise alpha M + mu L (vector Laplacian)."""
+        form); otherwise alpha M + mu L (vector Laplacian).  p3=True: the
+        Taylor-Hood P3/P2 pair (velocity arrays over the (3n+1)^dim P3 nodes,
+        pressure over the (2n+1)^dim P2 nodes); otherwise P2/P1."""
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("StokesProblem needs a HIP device")
         self.strain = bool(strain)
+        self.p3 = bool(p3)
         self.prob = _lib.make_problem(dim, n, mesh_seed, jitter, mu, alpha, gamma,
-                                      _lib.FLAG_STRAIN if strain else 0)
+                                      (_lib.FLAG_STRAIN if strain else 0) | (_lib.FLAG_P3 if p3 else 0))
         self.device = torch.device("cuda", torch.cuda.current_device())
         h = ctypes.c_void_p()
         check(self.lib.stokes_assemble(ctypes.byref(self.prob), _stream_handle(), ctypes.byref(h)),
@@ -40,7 +43,10 @@ class StokesProblem:
         check(self.lib.stokes_query(self.ctx, s), "stokes_query")
         (self.n_p2, self.n_p1, self.n_free_nodes, self.nnz_A, self.nnz_B, self.nnz_Q, self.n_elem, self.dim,
          self.nnz_full, self.nnz_Bfull, self.nnz_X, _) = [int(v) for v in s]
-        self.n_loc = 10 if self.dim == 3 else 6
+        if self.p3:
+            self.n_loc = 20 if self.dim == 3 else 10
+        else:
+            self.n_loc = 10 if self.dim == 3 else 6
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)

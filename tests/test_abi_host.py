@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 from oracle import mesh as omesh
+from oracle import p3 as op3
 from oracle import stokes as ostokes
 from paper_2407_01783_amd import _lib
 
@@ -72,6 +73,39 @@ def test_patterns_bit_exact_vs_oracle(lib, dim, n, jit):
         assert np.array_equal(cols, A.indices), which
 
 
+@pytest.mark.parametrize("dim,n,seed,jit", [(2, 1, 0, 0.0), (2, 4, 3, 0.1), (3, 1, 0, 0.0), (3, 3, 7, 0.15)])
+def test_p3_mesh_bit_exact_vs_oracle(lib, dim, n, seed, jit):
+    # the Taylor-Hood P3/P2 numbering (STOKES_FLAG_P3): P3 node ids and
+    # coordinates bit-identical to the oracle's independent construction
+    pr = _lib.make_problem(dim, n, seed, jit, 1.0, 1.0, 0.0, _lib.FLAG_P3)
+    m = op3.P3P2Mesh(dim, n, seed=seed, jitter=jit)
+    vc = np.empty((m.base.n_p1, dim))
+    el = np.empty((m.n_e, dim + 1), dtype=np.int32)
+    pc = np.empty((m.n_vel, dim))
+    p3ids = np.empty((m.n_e, m.n_loc), dtype=np.int32)
+    assert lib.stokes_build_mesh_host(ctypes.byref(pr), _lib.ptr(vc), _lib.ptr(el), _lib.ptr(pc),
+                                      _lib.ptr(p3ids)) == 0
+    assert np.array_equal(vc.view(np.uint64), m.vcoords.view(np.uint64))
+    assert np.array_equal(el, m.elems)
+    assert np.array_equal(p3ids, m.vel)
+    assert np.array_equal(pc.view(np.uint64), m.vel_coords.view(np.uint64))
+    s = (ctypes.c_int64 * 10)()
+    assert lib.stokes_problem_sizes(ctypes.byref(pr), s) == 0
+    assert s[0] == m.n_vel and s[1] == m.n_q and s[2] == m.n_free_nodes and s[6] == m.n_e
+
+
+@pytest.mark.parametrize("dim,n,jit", [(2, 3, 0.1), (3, 2, 0.1), (3, 2, 0.0)])
+def test_p3_patterns_bit_exact_vs_oracle(lib, dim, n, jit):
+    pr = _lib.make_problem(dim, n, 2, jit, 1.0, 1.0, 0.0, _lib.FLAG_P3)
+    m = op3.P3P2Mesh(dim, n, seed=2, jitter=jit)
+    s = ostokes.StokesSystem(m, 1.0, 1.0, mats=op3.assemble_p3p2(m))
+    ref = {0: s.mats.Ms, 1: s.A_II, 2: s.mats.B[0], 3: s.B_I[0], 4: s.mats.MQ}
+    for which, A in ref.items():
+        rp, cols = _pattern(lib, pr, which)
+        assert np.array_equal(rp, A.indptr), which
+        assert np.array_equal(cols, A.indices), which
+
+
 def test_problem_sizes(lib):
     for n in (2, 3, 5):
         pr = _lib.make_problem(3, n, 0, 0.1, 1.0, 1.0)
@@ -85,7 +119,7 @@ def test_problem_sizes(lib):
 
 
 @pytest.mark.parametrize("field,value", [("dim", 4), ("n", 0), ("mu", 0.0), ("mu", float("nan")),
-                                         ("alpha", -1.0), ("gamma", -0.5), ("jitter", 0.3), ("flags", 2)])
+                                         ("alpha", -1.0), ("gamma", -0.5), ("jitter", 0.3), ("flags", 4)])
 def test_invalid_problem_rejected(lib, field, value):
     pr = _lib.make_problem(3, 4, 0, 0.1, 1.0, 1.0)
     setattr(pr, field, value)

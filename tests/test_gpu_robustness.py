@@ -102,3 +102,27 @@ def test_residual_history_and_phase_times(prob, method, precision, inner_mode):
                           coupled_pc=1, hist_cap=3)
     assert info2["res_hist_len"] == 3 and np.allclose(info2["res_hist"], h[:3], rtol=1e-12, atol=0)
     assert info2["seconds_inner_u"] == 0.0  # profile off
+
+
+def test_tuning_cache_file(gpu_lib, tmp_path, monkeypatch):
+    """STOKES_TUNE_CACHE: the first context writes its lanes-per-row choices
+    (8 right-hand sides, W = 24, where several G compile), a second context
+    of the same problem reads them instead of timing, and both solve alike."""
+    from paper_2407_01783_amd.stokes import StokesProblem
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("STOKES_TUNE_CACHE", str(path))
+    kw = dict(mesh_seed=5, jitter=0.1, mu=1e-2, alpha=100.0)
+    P1 = StokesProblem(3, 5, **kw)
+    xy, _ = P1.mesh()
+    f = torch.tensor(np.stack([inputs.fourier_forcing(xy, inputs.forcing_seed(5, b)) for b in range(8)]),
+                     device=P1.device)
+    u1, p1, i1 = P1.solve(f, precision=1, rtol=1e-10)
+    lines = path.read_text().split()
+    assert i1["status"] == 0 and len(lines) >= 6 and len(lines) % 3 == 0, lines
+    assert all(g in ("1", "2", "4", "8") for g in lines[2::3])
+    del P1
+    P2 = StokesProblem(3, 5, **kw)
+    u2, p2, i2 = P2.solve(f, precision=1, rtol=1e-10)
+    assert i2["status"] == 0
+    assert path.read_text().split() == lines  # read, not re-timed and appended
+    assert torch.equal(u1, u2) and torch.equal(p1, p2)
