@@ -307,7 +307,9 @@ stokes_status stokes_residual_noalloc(stokes_ctx* ctx, int32_t nrhs, const doubl
 
 /* sizes[0..9] as in stokes_problem_sizes, for an assembled context;
  * sizes[10] = entries of B_I Lambda_V^-1 B_I^T (export_csr which 9),
- * sizes[11] = 0 (reserved). */
+ * sizes[11] = slices of 64 A_II rows whose columns the velocity kernels
+ * compute (one base per slot and at most one jump across the slice) instead
+ * of loading (0 with STOKES_VEL_AF=0 in the environment at assembly). */
 stokes_status stokes_query(const stokes_ctx* ctx, int64_t sizes[12]);
 
 /* Change mu and re-form A = alpha M + mu L on the device. */

@@ -543,6 +543,7 @@ stokes_status stokes_assemble(const stokes_problem* prob, void* hip_stream, stok
     if (const char* e = std::getenv("STOKES_PMG_HALF")) c->pmg_half = std::atoi(e) != 0;
     if (const char* e = std::getenv("STOKES_VEL_BF")) c->vel_bf = std::atoi(e) != 0;
     if (const char* e = std::getenv("STOKES_VEL_IL")) c->vel_il = std::atoi(e) != 0;
+    if (const char* e = std::getenv("STOKES_VEL_AF")) c->vel_af = std::atoi(e) != 0;
     if (const char* e = std::getenv("STOKES_LANES")) c->force_lanes = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("STOKES_ZBLOCK")) c->zblock = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("STOKES_MG_ES")) {
@@ -919,7 +920,7 @@ stokes_status stokes_query(const stokes_ctx* c, int64_t sizes[12]) {
     sizes[8] = c->p2full.nnz;
     sizes[9] = c->bfull.nnz;
     sizes[10] = c->xl.nnz;
-    sizes[11] = 0;
+    sizes[11] = c->vel_af ? c->sA.affine_slices : 0;
     return STOKES_OK;
   });
 }

@@ -900,19 +900,83 @@ void build_sell(const HostCsr& in, const std::vector<int32_t>& rows_in_order, co
       }
     }
   });
-  int64_t npk = 0;
-  double idx_bytes = 0;
+  // Affine slots: in the typed row order the 64 rows of a slice are mostly
+  // consecutive nodes of one lattice line, so slot j of lane l often holds
+  // the column base_j + l, with at most one jump where the slice crosses to
+  // the next lattice line.  A packed slice whose every slot has that form
+  // (entries only; a pad lane's formula column must merely be a valid
+  // column, its value is 0) is marked pk = 2 and gets (base, brk | jump << 8)
+  // per slot: the kernels that know the form compute the columns instead of
+  // loading them.  Its packed offsets stay valid for every other kernel.
+  int64_t ncols = 0;
+  for (int32_t v : col_map) ncols = std::max<int64_t>(ncols, int64_t(v) + 1);
+  std::vector<int32_t> cmeta(2 * (npad / 64), 0);
+  parallel_for(nsl, [&](int64_t b, int64_t e) {
+    std::vector<int32_t> base, meta;
+    for (int64_t sl = b; sl < e; ++sl) {
+      if (pk[sl] != 1) continue;
+      const int64_t w = (sp[sl + 1] - sp[sl]) / 64;
+      const int lanes = static_cast<int>(std::min<int64_t>(64, nrows - sl * 64));
+      base.assign(w, 0);
+      meta.assign(w, 0);
+      bool ok = true;
+      for (int64_t j = 0; j < w && ok; ++j) {
+        const int64_t b0 = sp[sl] + 64 * j;
+        int64_t d0 = cols[b0], jump = 0;
+        int brk = 64;
+        bool have = false;
+        for (int l = 0; l < lanes && ok; ++l) {
+          if (src[b0 + l] < 0) continue;
+          const int64_t d = int64_t(cols[b0 + l]) - l;
+          if (!have) {
+            d0 = d;
+            have = true;
+          } else if (brk == 64) {
+            if (d != d0) {
+              brk = l;
+              jump = d - d0;
+            }
+          } else if (d != d0 + jump) {
+            ok = false;
+          }
+        }
+        if (!ok || jump < -(int64_t(1) << 22) || jump >= (int64_t(1) << 22)) {
+          ok = false;
+          break;
+        }
+        for (int l = 0; l < 64 && ok; ++l) {  // every lane's formula column is a valid column
+          const int64_t c = d0 + l + (l >= brk ? jump : 0);
+          ok = c >= 0 && c < ncols;
+        }
+        base[j] = static_cast<int32_t>(d0);
+        meta[j] = static_cast<int32_t>(brk | (jump * 256));
+      }
+      if (!ok) continue;
+      pk[sl] = 2;
+      for (int64_t j = 0; j < w; ++j) {
+        cmeta[2 * (sp[sl] / 64 + j)] = base[j];
+        cmeta[2 * (sp[sl] / 64 + j) + 1] = meta[j];
+      }
+    }
+  });
+  int64_t npk = 0, naf = 0;
+  double idx_bytes = 0, idx_bytes_af = 0;
   for (int64_t sl = 0; sl < nsl; ++sl) {
-    npk += pk[sl];
+    npk += pk[sl] != 0;
+    naf += pk[sl] == 2;
     const double w = double(sp[sl + 1] - sp[sl]) / 64;
-    idx_bytes += 12.0 + (pk[sl] ? 64.0 * w + 4.0 * w : 4.0 * 64.0 * w);  // slice offset and form, slots
+    const double packed_or_wide = 12.0 + (pk[sl] ? 64.0 * w + 4.0 * w : 4.0 * 64.0 * w);  // slice offset and form, slots
+    idx_bytes += packed_or_wide;
+    idx_bytes_af += pk[sl] == 2 ? 12.0 + 8.0 * w : packed_or_wide;
   }
   out.nrows = nrows;
   out.nslices = nsl;
   out.nnz = nnz;
   out.nnz_pad = npad;
   out.packed_slices = npk;
+  out.affine_slices = naf;
   out.idx_bytes = idx_bytes;
+  out.idx_bytes_af = idx_bytes_af;
   out.planes = planes;
   upload(out.slice_ptr, sp);
   upload(out.cols, cols);
@@ -920,6 +984,7 @@ void build_sell(const HostCsr& in, const std::vector<int32_t>& rows_in_order, co
   upload(out.cbase, cbase);
   upload(out.cdel, cdel);
   upload(out.pk, pk);
+  upload(out.cmeta, cmeta);
 }
 
 template <class K, class... A>
@@ -1294,9 +1359,11 @@ void assemble_ctx(stokes_ctx* c) {
     const std::pair<const char*, const Sell*> ss[] = {{"A_II", &c->sA}, {"B", &c->sB}, {"B^T", &c->sBt},
                                                       {"X", &c->sX}, {"M_Q", &c->sQ}};
     for (const auto& e : ss)
-      std::fprintf(stderr, "[stokes] SELL %-5s %lld rows, %lld entries (%lld padded), %lld / %lld slices packed\n",
+      std::fprintf(stderr,
+                   "[stokes] SELL %-5s %lld rows, %lld entries (%lld padded), %lld / %lld slices packed, %lld affine\n",
                    e.first, (long long)e.second->nrows, (long long)e.second->nnz, (long long)e.second->nnz_pad,
-                   (long long)e.second->packed_slices, (long long)e.second->nslices);
+                   (long long)e.second->packed_slices, (long long)e.second->nslices,
+                   (long long)e.second->affine_slices);
   }
 
   auto fill = [&](const Sell& S, DevBuf& out, double a, const DevBuf& v1, double b, const DevBuf* v2) {

@@ -63,22 +63,26 @@ struct SellIdx {
   const int32_t* cols = nullptr;   // 32-bit columns (slices with pk = 0)
   const int32_t* cbase = nullptr;  // [nnz_pad / 64] base column of slot j of slice s at sp[s] / 64 + j
   const uint8_t* cdel = nullptr;   // [nnz_pad] column - base (slices with pk = 1)
-  const int32_t* pk = nullptr;     // [nslices] 1 = packed columns (32-bit: a scalar load)
+  const int32_t* pk = nullptr;     // [nslices] 1 = packed columns, 2 = packed and affine (32-bit: a scalar load)
+  // [2 per slot] affine slots: column of lane l = base + l + (l >= brk ? jump : 0),
+  // stored as (base, brk | jump << 8); null: kernels read the packed offsets
+  const int32_t* cmeta = nullptr;
 };
 
 struct Sell {
   int64_t nrows = 0, nslices = 0, nnz = 0, nnz_pad = 0;
-  int64_t packed_slices = 0;
-  double idx_bytes = 0;  // bytes of the column-index structure streamed by one product
+  int64_t packed_slices = 0, affine_slices = 0;
+  double idx_bytes = 0;     // bytes of the column-index structure streamed by one product
+  double idx_bytes_af = 0;  // ... by a product that computes the affine slots' columns
   int planes = 1;       // values per entry (B and B^T carry dim planes)
   int es = 1;           // lanes sharing a row in the scalar products (1: one lane per row; tuned per MG level)
   DevBuf slice_ptr;     // int64 [nslices + 1]
   DevBuf cols;          // int32 [nnz_pad]
   DevBuf src;           // int32 [nnz_pad] source entry in the assembled CSR (-1 = pad)
-  DevBuf cbase, cdel, pk;
+  DevBuf cbase, cdel, pk, cmeta;
   SellIdx idx() const {
     return SellIdx{slice_ptr.as<const int64_t>(), cols.as<const int32_t>(), cbase.as<const int32_t>(),
-                   cdel.as<const uint8_t>(), pk.as<const int32_t>()};
+                   cdel.as<const uint8_t>(), pk.as<const int32_t>(), cmeta.as<const int32_t>()};
   }
 };
 
@@ -212,6 +216,7 @@ struct stokes_ctx {
   stokes::DevBuf AD16i, cdel_i, cols_i;      // four-slot interleaved AD16 and sA column indices (bfloat16 step)
   stokes::DevBuf A32i;                       // four-slot interleaved A32 (FP32 velocity product of K_gamma)
   int vel_il = 1;                            // the bfloat16 Chebyshev step reads the interleaved copies
+  int vel_af = 1;                            // ... and computes the columns of affine slots
   stokes::DevBuf AB64, AB32;                 // strain: [nnz_pad][dim*dim] blocks alpha M + mu (L + D)
   stokes::DevBuf B64, B32, Bt64, Bt32;       // [nnz_pad][dim]
   stokes::DevBuf MQ64, MQ32, LQ64, LQ32, XQ64, XQ32;  // XQ = M_Q + L_Q

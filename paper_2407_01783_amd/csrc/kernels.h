@@ -150,6 +150,7 @@ struct SliceRef {
   int64_t eb;   // first slot of the slice (index into cbase)
   int width;    // slots of the slice
   bool pk;      // packed columns
+  bool af;      // affine slots (columns computed from cmeta; packed offsets also valid)
 };
 
 __device__ __forceinline__ SliceRef slice_ref(const SellIdx& ix, int64_t row) {
@@ -159,8 +160,30 @@ __device__ __forceinline__ SliceRef slice_ref(const SellIdx& ix, int64_t row) {
   r.beg = s0 + (row & 63);
   r.eb = s0 >> 6;
   r.width = static_cast<int>((ix.sp[s + 1] - s0) >> 6);
-  r.pk = ix.pk[s] != 0;
+  const int form = ix.pk[s];
+  r.pk = form != 0;
+  r.af = form == 2 && ix.cmeta != nullptr;
   return r;
+}
+
+// Column of slot j of an affine slice: base + lane, plus the slot's jump from
+// its break lane on (the two words of the slot are the same for every lane:
+// scalar loads).
+__device__ __forceinline__ int32_t affine_col(const SellIdx& ix, const SliceRef& r, int64_t slot) {
+  const int lane = static_cast<int>(r.beg - (r.eb << 6));
+  const int32_t base = ix.cmeta[2 * slot], meta = ix.cmeta[2 * slot + 1];
+  return base + lane + (lane >= (meta & 0xFF) ? (meta >> 8) : 0);
+}
+
+// Column of slot j in form F: 0 = 32-bit columns, 1 = packed offsets,
+// 2 = affine (computed).
+template <int F>
+__device__ __forceinline__ int32_t sell_col_f(const SellIdx& ix, const SliceRef& r, int j) {
+  if constexpr (F == 2) return affine_col(ix, r, r.eb + j);
+  else if constexpr (F == 1)
+    return ix.cbase[r.eb + j] + static_cast<int32_t>(__builtin_nontemporal_load(ix.cdel + r.beg + 64 * j));
+  else
+    return __builtin_nontemporal_load(ix.cols + r.beg + 64 * j);
 }
 
 template <bool PK>
@@ -264,10 +287,13 @@ __device__ __forceinline__ void load4_vals(const TM* __restrict__ vals, int64_t 
   }
 }
 
-// the four columns of group g (e = its first entry)
-template <bool PK>
+// the four columns of group g (e = its first entry), in form F (sell_col_f)
+template <int F>
 __device__ __forceinline__ void load4_cols(const SellIdx& ix, const SliceRef& r, int g, int64_t e, int32_t (&c)[4]) {
-  if constexpr (PK) {
+  if constexpr (F == 2) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = affine_col(ix, r, r.eb + 4 * g + k);
+  } else if constexpr (F == 1) {
     const uint32_t d4 = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(ix.cdel + e));
 #pragma unroll
     for (int k = 0; k < 4; ++k) c[k] = ix.cbase[r.eb + 4 * g + k] + static_cast<int32_t>((d4 >> (8 * k)) & 0xFFu);
@@ -282,7 +308,7 @@ __device__ __forceinline__ void load4_cols(const SellIdx& ix, const SliceRef& r,
 
 // acc += sum_j v_j x[c_j][0..W) over the interleaved copy, one lane per row,
 // two groups of four entries in flight per lane.
-template <typename T, int W, typename TM, bool PK>
+template <typename T, int W, typename TM, int F>
 __device__ __forceinline__ void sell_row_il_impl(const SellIdx& ix, const SliceRef& r, const TM* __restrict__ vals,
                                                  const T* __restrict__ x, T (&acc)[W]) {
   const int64_t s0 = r.eb << 6;
@@ -296,7 +322,7 @@ __device__ __forceinline__ void sell_row_il_impl(const SellIdx& ix, const SliceR
     for (int h = 0; h < H; ++h) {
       const int64_t e = s0 + 256 * (int64_t)(g + h) + 4 * lr;
       load4_vals<TM, T>(vals, e, v[h]);
-      load4_cols<PK>(ix, r, g + h, e, c[h]);
+      load4_cols<F>(ix, r, g + h, e, c[h]);
     }
     T xv[H][4][W];
 #pragma unroll
@@ -316,7 +342,7 @@ __device__ __forceinline__ void sell_row_il_impl(const SellIdx& ix, const SliceR
   for (; g + 2 <= g4; g += 2) groups(std::integral_constant<int, 2>{}, g);
   if (g < g4) groups(std::integral_constant<int, 1>{}, g);
   for (int j = 4 * g4; j < r.width; ++j) {
-    const int32_t c = sell_col<PK>(ix, r, j);
+    const int32_t c = sell_col_f<F>(ix, r, j);
     const T v = (T)__builtin_nontemporal_load(vals + r.beg + 64 * j);
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = fma(v, x[(int64_t)c * W + w], acc[w]);
@@ -327,8 +353,9 @@ template <typename T, int W, typename TM>
 __device__ __forceinline__ void sell_row_il(const SellIdx& ix, const TM* __restrict__ vals, const T* __restrict__ x,
                                             int64_t row, T (&acc)[W]) {
   const SliceRef r = slice_ref(ix, row);
-  if (r.pk) sell_row_il_impl<T, W, TM, true>(ix, r, vals, x, acc);
-  else sell_row_il_impl<T, W, TM, false>(ix, r, vals, x, acc);
+  if (r.af) sell_row_il_impl<T, W, TM, 2>(ix, r, vals, x, acc);
+  else if (r.pk) sell_row_il_impl<T, W, TM, 1>(ix, r, vals, x, acc);
+  else sell_row_il_impl<T, W, TM, 0>(ix, r, vals, x, acc);
 }
 
 // B rows (pressure vertex): acc[r] = sum_j sum_c B^c_j u[col_j][r][c]
@@ -1003,7 +1030,7 @@ __device__ __forceinline__ void sell_row_bq_impl(const SellIdx& ix, const SliceR
 
 // The bfloat16-direction row over the four-slot interleaved copies (the
 // layout of sell_row_il_impl).
-template <int W, int G, bool PK>
+template <int W, int G, int F>
 __device__ __forceinline__ void sell_row_bq4_impl(const SellIdx& ix, const SliceRef& r,
                                                   const _Float16* __restrict__ vals,
                                                   const uint16_t* __restrict__ xq, int off, float (&acc)[W / G]) {
@@ -1017,7 +1044,7 @@ __device__ __forceinline__ void sell_row_bq4_impl(const SellIdx& ix, const Slice
   auto load = [&](int g, int32_t (&c)[4], float (&v)[4]) {
     const int64_t e = s0 + 256 * (int64_t)g + 4 * lr;
     load4_vals<_Float16, float>(vals, e, v);
-    load4_cols<PK>(ix, r, g, e, c);
+    load4_cols<F>(ix, r, g, e, c);
   };
   // H groups at a time: values and offsets first, then all their gathers
   auto groups = [&](auto Hc, int g) {
@@ -1047,7 +1074,7 @@ __device__ __forceinline__ void sell_row_bq4_impl(const SellIdx& ix, const Slice
   if (g < g4) groups(std::integral_constant<int, 1>{}, g);
   // the remaining width mod 4 slots, slot-major
   for (int j = 4 * g4; j < r.width; ++j) {
-    const int32_t c = sell_col<PK>(ix, r, j);
+    const int32_t c = sell_col_f<F>(ix, r, j);
     const float v = (float)__builtin_nontemporal_load(vals + r.beg + 64 * j);
     uint32_t xr[Raw::kWords];
     load_bf_raw<WP, WG>(xq, c, off, xr);
@@ -1127,8 +1154,9 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step_qb(int64_t nrows, SellIdx 
       // eight, the gathered words alone hold most of the registers
       constexpr int UB = WG >= 8 ? 4 : U;
       if constexpr (IL) {
-        if (rf.pk) sell_row_bq4_impl<W, G, true>(ix, rf, vals, q, sub * WG, acc);
-        else sell_row_bq4_impl<W, G, false>(ix, rf, vals, q, sub * WG, acc);
+        if (rf.af) sell_row_bq4_impl<W, G, 2>(ix, rf, vals, q, sub * WG, acc);
+        else if (rf.pk) sell_row_bq4_impl<W, G, 1>(ix, rf, vals, q, sub * WG, acc);
+        else sell_row_bq4_impl<W, G, 0>(ix, rf, vals, q, sub * WG, acc);
       } else {
         if (rf.pk) sell_row_bq_impl<W, G, TM, true, UB>(ix, rf, vals, q, sub * WG, acc);
         else sell_row_bq_impl<W, G, TM, false, UB>(ix, rf, vals, q, sub * WG, acc);

@@ -175,6 +175,7 @@ SellIdx vel_il_idx(stokes_ctx* c) {
   SellIdx ix = c->sA.idx();
   ix.cdel = c->cdel_i.as<const uint8_t>();
   ix.cols = c->cols_i.as<const int32_t>();
+  if (!c->vel_af) ix.cmeta = nullptr;  // read the packed offsets of affine slots too
   return ix;
 }
 
@@ -572,6 +573,7 @@ void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const f
   const bool timed = prof_begin(c, &S, nullptr, nullptr);
   const int G = lanes_qb(c, W);
   int wp = W;
+  bool il = false;
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
     wp = bf_width<WW>();
@@ -583,6 +585,7 @@ void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const f
           hipLaunchKernelGGL((k_cheb_step_qb<_Float16, WW, GG, 8, true>), dim3(nb), dim3(kBlock), 0, c->stream,
                              S.nrows, vel_il_idx(c), (const _Float16*)c->AD16i.as<_Float16>(), q, qn, res_in,
                              res_out, z, dinv, c1, c2);
+          il = true;
           return;
         }
       }
@@ -592,11 +595,13 @@ void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const f
   });
   check_launch();
   // algorithmic bytes: the stored operator once (half values of every padded
-  // entry, the column-index structure); res_in, z read and res_out, z written
-  // (W floats each); q read once (gathered and own row) and qn written (WP
-  // bfloat16 each); dinv read
+  // entry, the column-index structure it reads: slot words alone for the
+  // affine slices of the interleaved copy); res_in, z read and res_out, z
+  // written (W floats each); q read once (gathered and own row) and qn
+  // written (WP bfloat16 each); dinv read
   if (timed)
-    prof_end(c, double(S.nnz_pad) * 2.0 + S.idx_bytes + double(S.nrows) * (4.0 * (W * 4.0 + 1.0) + 2.0 * 2.0 * wp));
+    prof_end(c, double(S.nnz_pad) * 2.0 + (il && c->vel_af ? S.idx_bytes_af : S.idx_bytes) +
+                    double(S.nrows) * (4.0 * (W * 4.0 + 1.0) + 2.0 * 2.0 * wp));
 }
 
 void cheb_step_h(stokes_ctx* c, int W, const float* q, float* qn, const float* res_in, float* res_out, float* z,

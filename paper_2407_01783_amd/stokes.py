@@ -42,7 +42,7 @@ class StokesProblem:
         s = (ctypes.c_int64 * 12)()
         check(self.lib.stokes_query(self.ctx, s), "stokes_query")
         (self.n_p2, self.n_p1, self.n_free_nodes, self.nnz_A, self.nnz_B, self.nnz_Q, self.n_elem, self.dim,
-         self.nnz_full, self.nnz_Bfull, self.nnz_X, _) = [int(v) for v in s]
+         self.nnz_full, self.nnz_Bfull, self.nnz_X, self.affine_slices) = [int(v) for v in s]
         if self.p3:
             self.n_loc = 20 if self.dim == 3 else 10
         else:

@@ -170,6 +170,39 @@ def test_interleaved_chebyshev_step_bitwise_equal(gpu_lib, monkeypatch, dim, n, 
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("dim,n,nrhs", [(3, 64, 2), (2, 130, 1), (2, 132, 4)])
+def test_affine_columns_bitwise_equal(gpu_lib, monkeypatch, dim, n, nrhs):
+    """Slices of A_II whose columns the velocity kernels compute from one base
+    per slot and one jump (the default) read the same columns as the stored
+    index form: the bfloat16 Chebyshev step (apply op 10), the FP32 K_gamma
+    product inside FGMRES and a whole mixed coupled solve are bitwise equal
+    with the form switched off.  The form needs lattice lines of about 64
+    interior nodes of one parity type (n >= 64 in 3D, about 130 in 2D):
+    smaller meshes have no such slices."""
+    from paper_2407_01783_amd import inputs
+    rng = np.random.default_rng(47)
+    outs = []
+    for af in ("0", "1"):
+        monkeypatch.setenv("STOKES_VEL_AF", af)
+        P = _problem(dim, n, seed=12, mu=0.03, alpha=150.0)
+        if af == "1":
+            print(f"affine slices {P.affine_slices} of {(P.n_free_nodes + 63) // 64}", flush=True)
+            assert P.affine_slices > 0
+        else:
+            assert P.affine_slices == 0
+        if not outs:
+            x = rng.standard_normal(nrhs * dim * P.n_p2)
+            xy, _ = P.mesh()
+            f = np.stack([inputs.fourier_forcing(xy, inputs.forcing_seed(12, k)) for k in range(nrhs)])
+        y = P.apply(10, torch.tensor(x, device="cuda"), precision=1, nrhs=nrhs).cpu().numpy()
+        u, p, info = P.solve(torch.tensor(f, device="cuda"), method="coupled", precision=1, rtol=1e-8)
+        assert info["status"] == 0, info
+        outs.append((y, u.cpu().numpy(), p.cpu().numpy()))
+        del P
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
 def test_set_mu_then_mixed_solve_matches_oracle(gpu_lib):
     """set_mu rebuilds the FP32 and half-precision copies and their four-slot
     interleaved forms (read by the velocity Chebyshev and by K_gamma): a
