@@ -178,6 +178,13 @@ typedef struct {
   double* res_hist;
   int32_t res_hist_cap;
   int32_t res_hist_len;
+  /* Algorithmic HBM bytes of the kernels the call launched, counted by the
+   * library from its layouts (always, at no device cost): each stored
+   * operator once per product (every padded entry's values and the column
+   * index structure it reads), each streamed vector once per pass, each
+   * gathered vector once.  bytes_alg / seconds_total over the device's HBM
+   * bandwidth is the solve-level roofline fraction. */
+  double bytes_alg;
 } stokes_solve_info;
 
 /* Fill *opts with defaults: FP64, rtol 1e-8, FGMRES(30), Chebyshev degree 4,

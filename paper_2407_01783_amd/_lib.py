@@ -56,7 +56,7 @@ class SolveInfo(ctypes.Structure):
                 ("spmv_bytes", ctypes.c_double), ("seconds_inner_u", ctypes.c_double),
                 ("seconds_inner_p", ctypes.c_double), ("seconds_orth", ctypes.c_double),
                 ("res_hist", ctypes.POINTER(ctypes.c_double)), ("res_hist_cap", ctypes.c_int32),
-                ("res_hist_len", ctypes.c_int32)]
+                ("res_hist_len", ctypes.c_int32), ("bytes_alg", ctypes.c_double)]
 
     def attach_history(self, cap):
         """Give the call a caller-owned history buffer of ``cap`` entries."""

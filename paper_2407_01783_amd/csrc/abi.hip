@@ -196,6 +196,7 @@ double wall() {
 }
 
 void prof_start(stokes_ctx* c, const stokes_solve_opts* o) {
+  c->abytes = 0;
   c->prof_on = o->profile;
   c->prof_idx = 0;
   c->prof_seen = 0;
@@ -213,6 +214,7 @@ void prof_start(stokes_ctx* c, const stokes_solve_opts* o) {
 }
 
 void prof_finish(stokes_ctx* c, stokes_solve_info* info) {
+  if (info) info->bytes_alg = c->abytes;
   if (!c->prof_on) return;
   HIP_CHECK(hipStreamSynchronize(c->stream));
   double s = 0;
@@ -264,8 +266,8 @@ stokes_status solve_forward(stokes_ctx* c, int method, int32_t nrhs, const doubl
       ops::vel_in<double>(c, nrb, x0_u + vo, xu);
       ops::p_in<double>(c, nrb, x0_p + po, xp);
     } else {
-      HIP_CHECK(hipMemsetAsync(xu, 0, nu * sizeof(double), c->stream));
-      HIP_CHECK(hipMemsetAsync(xp, 0, np * sizeof(double), c->stream));
+      ops::zero_dev(c, xu, nu * sizeof(double));
+      ops::zero_dev(c, xp, np * sizeof(double));
     }
     SolveStats st;
     const int s = solve_internal(c, *o, method, nrb, F, g, xu, xp, st, x0_u == nullptr);
@@ -355,6 +357,7 @@ void stokes_ctx::run_graph(const std::string& key, const std::function<void()>& 
   Graph& g = graphs[key];
   if (g.exec && g.gen == ws_gen) {
     HIP_CHECK(hipGraphLaunch(g.exec, stream));
+    abytes += g.bytes;  // the launchers counted the sequence once, at capture
     return;
   }
   if (g.exec) {
@@ -371,6 +374,7 @@ void stokes_ctx::run_graph(const std::string& key, const std::function<void()>& 
   }
   const uint64_t gen0 = ws_gen;
   hipGraph_t graph = nullptr;
+  const double b0 = abytes;
   HIP_CHECK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
   try {
     enqueue();
@@ -380,6 +384,7 @@ void stokes_ctx::run_graph(const std::string& key, const std::function<void()>& 
     throw;
   }
   HIP_CHECK(hipStreamEndCapture(stream, &graph));
+  g.bytes = abytes - b0;  // counted at capture, moved by the launch below
   if (ws_gen != gen0) throw Error(STOKES_ERR_STATE, "workspace reallocated during graph capture");
   hipGraphExec_t exec = nullptr;
   HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
@@ -634,10 +639,10 @@ stokes_status stokes_solve_adjoint(stokes_ctx* c, int32_t nrhs, const double* u,
         ops::p_in<double>(c, nrb, dJdp + po, g);
         ops::adj_jp(c, nrb, g);
       } else {
-        HIP_CHECK(hipMemsetAsync(g, 0, np * sizeof(double), c->stream));
+        ops::zero_dev(c, g, np * sizeof(double));
       }
-      HIP_CHECK(hipMemsetAsync(xu, 0, nu * sizeof(double), c->stream));
-      HIP_CHECK(hipMemsetAsync(xp, 0, np * sizeof(double), c->stream));
+      ops::zero_dev(c, xu, nu * sizeof(double));
+      ops::zero_dev(c, xp, np * sizeof(double));
       SolveStats st;
       const int s = solve_internal(c, *o, 0, nrb, F, g, xu, xp, st, true);
       if (s != STOKES_OK) status = s;

@@ -977,6 +977,7 @@ void build_sell(const HostCsr& in, const std::vector<int32_t>& rows_in_order, co
   out.affine_slices = naf;
   out.idx_bytes = idx_bytes;
   out.idx_bytes_af = idx_bytes_af;
+  out.ncols = ncols;
   out.planes = planes;
   upload(out.slice_ptr, sp);
   upload(out.cols, cols);

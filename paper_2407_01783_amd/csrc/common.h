@@ -74,6 +74,7 @@ struct Sell {
   int64_t packed_slices = 0, affine_slices = 0;
   double idx_bytes = 0;     // bytes of the column-index structure streamed by one product
   double idx_bytes_af = 0;  // ... by a product that computes the affine slots' columns
+  int64_t ncols = 0;        // columns (rows of a gathered vector)
   int planes = 1;       // values per entry (B and B^T carry dim planes)
   int es = 1;           // lanes sharing a row in the scalar products (1: one lane per row; tuned per MG level)
   DevBuf slice_ptr;     // int64 [nslices + 1]
@@ -264,6 +265,7 @@ struct stokes_ctx {
   int prof_on = 0, prof_idx = 0, prof_seen = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
   double prof_bytes = 0;
+  double abytes = 0;  // algorithmic bytes of the kernels launched since the call began (bytes_alg)
   stokes::PhaseTimer phase[stokes::NUM_PHASES];  // phase times of stokes_solve_info (profile = 1)
 
   // pinned host mirror of the solver scalars
@@ -277,6 +279,7 @@ struct stokes_ctx {
     hipGraphExec_t exec = nullptr;
     uint64_t gen = 0;
     int eager_runs = 0;
+    double bytes = 0;  // algorithmic bytes of one replay
   };
   std::map<std::string, Graph> graphs;
   int use_graphs = 1;

@@ -458,6 +458,7 @@ void mg_vcycle(stokes_ctx* c, const MgHier& H, int nrb, const T* r, T* e, int lv
                            c->stream, nr, Ci, r, e);
       });
       ops::check_launch();
+      ops::count_bytes(c, double(nr) * nr * sizeof(T) + 2.0 * nr * nrb * sizeof(T));  // dense inverse, r, e
     } else {
       cheb(bf, c->mg_coarse_degree, r, e, 0);
     }
@@ -478,6 +479,7 @@ void mg_vcycle(stokes_ctx* c, const MgHier& H, int nrb, const T* r, T* e, int lv
                        (const T*)t, rc);
   });
   ops::check_launch();
+  ops::count_bytes(c, double(n + ncn) * sizeof(T));  // fine residual read, coarse one written
   mg_vcycle<T>(c, H, nrb, rc, ec, lv + 1);
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
     constexpr int DD = decltype(Dc)::value, N = decltype(Nc)::value;
@@ -485,6 +487,7 @@ void mg_vcycle(stokes_ctx* c, const MgHier& H, int nrb, const T* r, T* e, int lv
                        (const T*)ec, e);
   });
   ops::check_launch();
+  ops::count_bytes(c, double(ncn + 2 * n) * sizeof(T));  // coarse correction read, e read and written
   residual(e, r, t);                                                    // t = r - X e
   if (nu >= 2) {
     cheb(bs, nu, t, e, 1);                                              // post-smoothing, e += p(.) t
@@ -621,6 +624,7 @@ void vel_vcycle(stokes_ctx* c, int W, const T* r, T* e, int lv) {
                            c->stream, nr, Ci, r, e);
       });
       ops::check_launch();
+      ops::count_bytes(c, double(nr) * nr * sizeof(T) + 2.0 * nr * W * sizeof(T));
     } else {
       cheb(bf, c->mg_coarse_degree, r, e, 0);
     }
@@ -640,6 +644,8 @@ void vel_vcycle(stokes_ctx* c, int W, const T* r, T* e, int lv) {
                        C.R.rowptr.as<int32_t>(), C.R.cols.as<int32_t>(), ops::pick<T>(C.rv64, C.rv32), (const T*)t, rc);
   });
   ops::check_launch();
+  // CSR restriction: row pointers, columns and values, fine residual gathered, coarse written
+  ops::count_bytes(c, double(C.nrows + 1) * 4.0 + double(C.R.nnz) * (4.0 + sizeof(T)) + double(n + ncn) * sizeof(T));
   vel_vcycle<T>(c, W, rc, ec, lv + 1);
   dispatch_w_mg(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
@@ -647,6 +653,7 @@ void vel_vcycle(stokes_ctx* c, int W, const T* r, T* e, int lv) {
                        C.P.rowptr.as<int32_t>(), C.P.cols.as<int32_t>(), ops::pick<T>(C.pv64, C.pv32), (const T*)ec, e);
   });
   ops::check_launch();
+  ops::count_bytes(c, double(nr + 1) * 4.0 + double(C.P.nnz) * (4.0 + sizeof(T)) + double(ncn + 2 * n) * sizeof(T));
   ops::spmv<T>(c, S, vals, W, e, t, (T)-1, r, (T)1);     // t = r - A e
   cheb(bs, nu, t, e, 1);                                 // post-smoothing, e += p(.) t
 }

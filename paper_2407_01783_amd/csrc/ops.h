@@ -53,6 +53,24 @@ struct PhaseScope {
 };
 void check_launch();
 
+// Algorithmic bytes (stokes_solve_info::bytes_alg): every launcher adds what
+// its kernel must move at least: the stored operator once (values of every
+// padded entry, `planes` of them, and the index structure it reads), each
+// streamed vector once per pass and each gathered vector once.
+inline void count_bytes(stokes_ctx* c, double b) { c->abytes += b; }
+inline double op_bytes(const Sell& S, double value_size, bool affine = false) {
+  return double(S.nnz_pad) * S.planes * value_size + (affine ? S.idx_bytes_af : S.idx_bytes);
+}
+// stream-ordered device copy and zero fill, counted
+inline void copy_dev(stokes_ctx* c, void* dst, const void* src, size_t bytes) {
+  HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
+  count_bytes(c, 2.0 * double(bytes));
+}
+inline void zero_dev(stokes_ctx* c, void* dst, size_t bytes) {
+  HIP_CHECK(hipMemsetAsync(dst, 0, bytes, c->stream));
+  count_bytes(c, double(bytes));
+}
+
 template <class T> const T* pick(const DevBuf& b64, const DevBuf& b32);
 
 // y = a * (S x) + b * yin, S scalar SELL shared by W values per row

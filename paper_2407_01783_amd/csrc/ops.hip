@@ -241,6 +241,7 @@ namespace {
 template <class T, class TM>
 void spmv_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, int W, const T* x, T* y, T a, const T* yin, T b) {
   const int G = lanes_op(c, &S, W, std::is_same<T, float>::value);
+  bool il = false;
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
     // the FP32 velocity product (K_gamma in the FGMRES cycle) on the
@@ -249,6 +250,7 @@ void spmv_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, int W, const 
       if (G == 1 && &S == &c->sA && c->vel_il && c->A32i.p && (const void*)vals == c->A32.p) {
         hipLaunchKernelGGL((k_spmv<T, WW, 1, TM, true>), dim3(grid_full(S.nrows)), dim3(kBlock), 0, c->stream,
                            S.nrows, vel_il_idx(c), c->A32i.as<const float>(), x, y, (T)(a * ms), yin, b);
+        il = true;
         return;
       }
     }
@@ -265,6 +267,9 @@ void spmv_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, int W, const 
     });
   });
   check_launch();
+  // operator, x gathered, y written (and yin read)
+  count_bytes(c, op_bytes(S, sizeof(TM), il && c->vel_af) + double(S.ncols) * W * sizeof(T) +
+                     double(S.nrows) * W * sizeof(T) * (yin ? 2 : 1));
 }
 }  // namespace
 
@@ -287,6 +292,9 @@ void Bmul(stokes_ctx* c, int nrb, const T* u, T* p, T a, const T* pin, T b) {
                        S.idx(), bvals<T>(c).template as<T>(), u, p, a, pin, b);
   });
   check_launch();
+  // B (dim planes), u gathered, p written (and pin read)
+  count_bytes(c, op_bytes(S, sizeof(T)) + double(S.ncols) * c->dim * nrb * sizeof(T) +
+                     double(S.nrows) * nrb * sizeof(T) * (pin ? 2 : 1));
 }
 
 template <class T>
@@ -303,6 +311,9 @@ void Btmul(stokes_ctx* c, int nrb, const T* p, const T* scale, T* u, T a, const 
     });
   });
   check_launch();
+  // B^T (dim planes), p gathered, row scale read, u written (and uin read, btout written)
+  count_bytes(c, op_bytes(S, sizeof(T)) + double(S.ncols) * nrb * sizeof(T) + (scale ? double(S.nrows) * sizeof(T) : 0) +
+                     double(S.nrows) * c->dim * nrb * sizeof(T) * (1 + (uin ? 1 : 0) + (btout ? 1 : 0)));
 }
 
 template <class T> const DevBuf& abvals(stokes_ctx* c);
@@ -318,6 +329,10 @@ void velop(stokes_ctx* c, int nrb, const T* x, T* y, T a, const T* yin, T b) {
                        c->sA.idx(), abvals<T>(c).template as<T>(), x, y, a, yin, b);
   });
   check_launch();
+  // dim x dim blocks per entry, x gathered, y written (and yin read)
+  const double W = double(c->dim) * nrb;
+  count_bytes(c, double(c->sA.nnz_pad) * c->dim * c->dim * sizeof(T) + c->sA.idx_bytes +
+                     double(c->n_int) * W * sizeof(T) * (yin ? 3 : 2));
 }
 
 template <class T>
@@ -330,6 +345,9 @@ void momentum(stokes_ctx* c, int nrb, const T* u, const T* p, const T* extra, T*
                          p, extra, y, sgn, yin);
     });
     check_launch();
+    count_bytes(c, double(c->sA.nnz_pad) * c->dim * c->dim * sizeof(T) + c->sA.idx_bytes +
+                       op_bytes(c->sBt, sizeof(T)) + double(c->n_p1) * nrb * sizeof(T) +
+                       double(c->n_int) * c->dim * nrb * sizeof(T) * (2 + (extra ? 1 : 0) + (yin ? 1 : 0)));
     return;
   }
   const int G = lanes_w(c, c->dim * nrb, std::is_same<T, float>::value);
@@ -343,6 +361,9 @@ void momentum(stokes_ctx* c, int nrb, const T* u, const T* p, const T* extra, T*
     });
   });
   check_launch();
+  // A and B^T, u and p gathered, y written (extra and yin read)
+  count_bytes(c, op_bytes(c->sA, sizeof(T)) + op_bytes(c->sBt, sizeof(T)) + double(c->n_p1) * nrb * sizeof(T) +
+                     double(c->n_int) * c->dim * nrb * sizeof(T) * (2 + (extra ? 1 : 0) + (yin ? 1 : 0)));
 }
 
 template <class T>
@@ -354,6 +375,7 @@ void dot_dev(stokes_ctx* c, int64_t nrows, int W, const T* x, const T* y, const 
     finish<WW>(c, nrows, FIN_STORE, WW, nullptr, 1, 0, 0, res);
   });
   check_launch();
+  count_bytes(c, double(nrows) * (W * sizeof(T) * (y == nullptr || x == y ? 1 : 2) + (rw ? sizeof(double) : 0)));
 }
 
 template <class T>
@@ -384,6 +406,7 @@ void remove_mean_into(stokes_ctx* c, int nrb, const T* x, T* y) {
                        (const double*)partials(c), nb, 1.0 / double(c->n_p1));
   });
   check_launch();
+  count_bytes(c, double(c->n_p1) * nrb * sizeof(T) * 3);  // sum pass, then read x and write y
 }
 
 template <class T>
@@ -400,24 +423,28 @@ void normalize_pressure(stokes_ctx* c, int nrb, T* x) {
                        (const double*)res, 1.0 / c->mQ_sum);
   });
   check_launch();
+  count_bytes(c, double(c->n_p1) * (nrb * sizeof(T) * 3 + sizeof(double)));  // weighted sum, then shift in place
 }
 
 template <class Tin, class Tout>
 void cast(stokes_ctx* c, int64_t n, const Tin* x, Tout* y) {
   hipLaunchKernelGGL((k_cast<Tin, Tout>), dim3(grid_for(n)), dim3(kBlock), 0, c->stream, n, x, y);
   check_launch();
+  count_bytes(c, double(n) * (sizeof(Tin) + sizeof(Tout)));
 }
 
 template <class T>
 void axpby(stokes_ctx* c, int64_t n, T a, const T* x, T b, T* y) {
   hipLaunchKernelGGL((k_axpby<T>), dim3(grid_for(n)), dim3(kBlock), 0, c->stream, n, a, x, b, y);
   check_launch();
+  count_bytes(c, double(n) * sizeof(T) * 3);
 }
 
 template <class T>
 void axpy_sys(stokes_ctx* c, int64_t n, int W, int cps, const double* coef, double scale, const T* v, T* y) {
   hipLaunchKernelGGL((k_axpy_sys<T>), dim3(grid_for(n)), dim3(kBlock), 0, c->stream, n, W, cps, coef, scale, v, y);
   check_launch();
+  count_bytes(c, double(n) * sizeof(T) * 3);
 }
 
 template <class T>
@@ -435,6 +462,9 @@ void cg_spmv(stokes_ctx* c, int64_t nrows, const Sell* S, const T* vals, int W, 
     });
   });
   check_launch();
+  // operator and z gathered (z streamed without one), q and p read and written (extra read)
+  count_bytes(c, (S ? op_bytes(*S, sizeof(T)) + double(S->ncols) * W * sizeof(T) : 0) +
+                     double(nrows) * W * sizeof(T) * (4 + (extra ? 1 : 0) + (S ? 0 : 1)));
 }
 
 template <class T>
@@ -462,6 +492,9 @@ void cg_update(stokes_ctx* c, int64_t nrows, int W, int prec, T* x, T* r, const 
     });
   });
   check_launch();
+  // x, r read and written, p, q read; dinv; d0 and z (or z) written
+  count_bytes(c, double(nrows) * (W * sizeof(T) * (6 + (prec == 0 ? 2 : prec == 1 ? 1 : 0)) +
+                                  (prec == 2 ? 0 : sizeof(T))));
 }
 
 template <class T>
@@ -476,6 +509,7 @@ void cheb_init(stokes_ctx* c, int64_t nrows, int W, const T* r, const T* dinv, T
     });
   });
   check_launch();
+  count_bytes(c, double(nrows) * (W * sizeof(T) * 3 + sizeof(T)));
 }
 
 namespace {
@@ -509,6 +543,9 @@ void cheb_first_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, const T
     });
   });
   check_launch();
+  // operator, r gathered (and dinv with the unscaled one), dinv read; res, d1, z written (z read)
+  count_bytes(c, op_bytes(S, sizeof(TM)) + double(S.ncols) * (W * sizeof(T) + (scaled ? 0 : sizeof(T))) +
+                     double(S.nrows) * (sizeof(T) + W * sizeof(T) * (3 + (accumulate ? 1 : 0))));
 }
 }  // namespace
 
@@ -540,14 +577,19 @@ void cheb_first_h(stokes_ctx* c, int W, const float* r, const float* dinv, float
     });
   });
   check_launch();
+  // half values, r gathered, dinv read; q1, res, z written
+  count_bytes(c, op_bytes(S, 2) + double(S.nrows) * 4.0 * (4.0 * W + 1.0));
 }
 
 void cheb_first_hb(stokes_ctx* c, int W, const float* r, const float* dinv, float theta_inv, uint16_t* q1,
                    float* res, float* z, float c1, float c2) {
   const Sell& S = c->sA;
   const int G = lanes_qb(c, W);
+  int wp = W;
+  bool il = false;
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
+    wp = bf_width<WW>();
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       if constexpr (GG == 1) {
@@ -555,6 +597,7 @@ void cheb_first_hb(stokes_ctx* c, int W, const float* r, const float* dinv, floa
           hipLaunchKernelGGL((k_cheb_first_qb<_Float16, WW, 0, 1, 8, true>), dim3(grid_full(S.nrows)), dim3(kBlock),
                              0, c->stream, S.nrows, vel_il_idx(c), (const _Float16*)c->AD16i.as<_Float16>(), r, dinv,
                              theta_inv, q1, res, z, c1, c2);
+          il = true;
           return;
         }
       }
@@ -565,6 +608,8 @@ void cheb_first_hb(stokes_ctx* c, int W, const float* r, const float* dinv, floa
     });
   });
   check_launch();
+  // half values, r gathered, dinv read; res, z (floats) and q1 (bfloat16) written
+  count_bytes(c, op_bytes(S, 2, il && c->vel_af) + double(S.nrows) * (4.0 * (3.0 * W + 1.0) + 2.0 * wp));
 }
 
 void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const float* res_in, float* res_out,
@@ -599,9 +644,9 @@ void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const f
   // affine slices of the interleaved copy); res_in, z read and res_out, z
   // written (W floats each); q read once (gathered and own row) and qn
   // written (WP bfloat16 each); dinv read
-  if (timed)
-    prof_end(c, double(S.nnz_pad) * 2.0 + (il && c->vel_af ? S.idx_bytes_af : S.idx_bytes) +
-                    double(S.nrows) * (4.0 * (W * 4.0 + 1.0) + 2.0 * 2.0 * wp));
+  const double bytes = op_bytes(S, 2, il && c->vel_af) + double(S.nrows) * (4.0 * (W * 4.0 + 1.0) + 2.0 * 2.0 * wp);
+  count_bytes(c, bytes);
+  if (timed) prof_end(c, bytes);
 }
 
 void cheb_step_h(stokes_ctx* c, int W, const float* q, float* qn, const float* res_in, float* res_out, float* z,
@@ -624,7 +669,9 @@ void cheb_step_h(stokes_ctx* c, int W, const float* q, float* qn, const float* r
   // algorithmic bytes: the stored operator once (half values of every padded
   // entry, the column-index structure); q gathered once; res_in, q, z read;
   // res_out, qn, z written (W floats each); dinv read
-  if (timed) prof_end(c, double(S.nnz_pad) * 2.0 + S.idx_bytes + double(S.nrows) * 4.0 * (W * 6.0 + 1.0));
+  const double bytes = op_bytes(S, 2) + double(S.nrows) * 4.0 * (W * 6.0 + 1.0);
+  count_bytes(c, bytes);
+  if (timed) prof_end(c, bytes);
 }
 
 void cheb_step_hs(stokes_ctx* c, const Sell& S, const _Float16* vals, float ms, int W, const float* d, float* dn,
@@ -646,6 +693,8 @@ void cheb_step_hs(stokes_ctx* c, const Sell& S, const _Float16* vals, float ms, 
     });
   });
   check_launch();
+  // half values, d gathered; res_in, z, dinv read; res_out, dn, z written
+  count_bytes(c, op_bytes(S, 2) + double(S.ncols) * W * 4.0 + double(S.nrows) * 4.0 * (W * 5.0 + 1.0));
 }
 
 template <class T>
@@ -680,9 +729,10 @@ void cheb_step(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* d, T
   // algorithmic bytes: the stored operator once (values of every padded
   // entry, the column-index structure); d gathered once; res_in, z, dinv
   // (and rvec) read; res_out, dn, z written
-  if (timed)
-    prof_end(c, double(S.nnz_pad) * sizeof(T) + S.idx_bytes +
-                    double(S.nrows) * sizeof(T) * (W * (rvec ? 7.0 : 6.0) + 1.0));
+  const double bytes = op_bytes(S, sizeof(T)) + double(S.ncols) * W * sizeof(T) +
+                       double(S.nrows) * sizeof(T) * (W * (rvec ? 6.0 : 5.0) + 1.0);
+  count_bytes(c, bytes);
+  if (timed) prof_end(c, bytes);
 }
 
 // Tuning cache (STOKES_TUNE_CACHE = path of a text file): one line
@@ -860,6 +910,7 @@ void vel_in(stokes_ctx* c, int nrb, const double* src, T* dst) {
                        c->int2nat.as<int32_t>(), src, dst);
   });
   check_launch();
+  count_bytes(c, double(c->n_int) * (4.0 + c->dim * nrb * (8.0 + sizeof(T))));
 }
 
 template <class T>
@@ -870,6 +921,8 @@ void vel_out(stokes_ctx* c, int nrb, const T* src, const double* ubc, double* ds
                        c->nat2int.as<int32_t>(), src, ubc, dst, bnd_fill);
   });
   check_launch();
+  count_bytes(c, double(c->n_p2) * 4.0 + double(c->dim) * nrb * (c->n_int * sizeof(T) + c->n_p2 * 8.0) +
+                     (ubc ? double(c->n_p2 - c->n_int) * c->dim * nrb * 8.0 : 0));
 }
 
 template <class T>
@@ -879,6 +932,7 @@ void p_in(stokes_ctx* c, int nrb, const double* src, T* dst) {
     hipLaunchKernelGGL((k_p_in<T, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1, src, dst);
   });
   check_launch();
+  count_bytes(c, double(c->n_p1) * nrb * (8.0 + sizeof(T)));
 }
 
 template <class T>
@@ -888,6 +942,7 @@ void p_out(stokes_ctx* c, int nrb, const T* src, double* dst) {
     hipLaunchKernelGGL((k_p_out<T, N>), dim3(grid_for(c->n_p1)), dim3(kBlock), 0, c->stream, c->n_p1, src, dst);
   });
   check_launch();
+  count_bytes(c, double(c->n_p1) * nrb * (8.0 + sizeof(T)));
 }
 
 void rhs(stokes_ctx* c, int nrb, const double* f, const double* ubc, double* F, double* g, double* fI) {
@@ -901,6 +956,7 @@ void rhs(stokes_ctx* c, int nrb, const double* f, const double* ubc, double* F, 
   } else {
     hipLaunchKernelGGL((k_set<double>), dim3(grid_for(c->n_int * W)), dim3(kBlock), 0, c->stream, c->n_int * W, 0.0,
                        F);
+    count_bytes(c, double(c->n_int) * W * 8.0);
   }
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
     constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
@@ -916,6 +972,14 @@ void rhs(stokes_ctx* c, int nrb, const double* f, const double* ubc, double* F, 
                        c->B_full.as<double>(), ubc, g);
   });
   check_launch();
+  // boundary rows: their column lists and M, L (D) entries, f and ubc gathered, F rows read and written;
+  // pressure rows: the full B pattern and values, ubc gathered, g written
+  const double nbe = double(c->bc_cols.bytes) / 4.0, nb = double(c->bfull.nnz);
+  if (c->n_bc > 0 && (f || ubc))
+    count_bytes(c, nbe * (4.0 + 4.0 + 16.0 + (c->strain ? 8.0 * c->dim * c->dim : 0)) + double(c->n_bc) * (8.0 + 16.0 * W) +
+                       ((f ? 1 : 0) + (ubc ? 1 : 0)) * double(c->n_p2) * W * 8.0);
+  count_bytes(c, double(c->n_p1) * 4.0 + nb * (4.0 + 8.0 * c->dim) + (ubc ? double(c->n_p2) * W * 8.0 : 0) +
+                     double(c->n_p1) * nrb * 8.0);
 }
 
 void adj_jp(stokes_ctx* c, int nrb, double* g) {
@@ -927,6 +991,7 @@ void adj_jp(stokes_ctx* c, int nrb, double* g) {
                        c->mQ.as<double>(), (const double*)sum, 1.0 / c->mQ_sum, g);
   });
   check_launch();
+  count_bytes(c, double(c->n_p1) * (8.0 + 16.0 * nrb));
 }
 
 void adj_dJdf(stokes_ctx* c, int nrb, const double* lam, double* out) {
@@ -937,6 +1002,8 @@ void adj_dJdf(stokes_ctx* c, int nrb, const double* lam, double* out) {
                        c->M_full.as<double>(), lam, out);
   });
   check_launch();
+  const double W = double(c->dim) * nrb;
+  count_bytes(c, double(c->n_p2) * (8.0 + W * 8.0) + double(c->p2full.nnz) * 12.0 + double(c->n_int) * W * 8.0);
 }
 
 void adj_dJdmu(stokes_ctx* c, int nrb, const double* u_full, const double* lam, double* res_dev) {
@@ -949,6 +1016,9 @@ void adj_dJdmu(stokes_ctx* c, int nrb, const double* u_full, const double* lam, 
     finish<N>(c, c->n_int, FIN_STORE, N, nullptr, 1, 0, 0, res_dev);
   });
   check_launch();
+  const double W = double(c->dim) * nrb;
+  count_bytes(c, double(c->n_int) * (12.0 + W * 8.0) + double(c->p2full.nnz) * (12.0 + (c->strain ? 8.0 * c->dim * c->dim : 0)) +
+                     double(c->n_p2) * W * 8.0);
 }
 
 #define INST(T)                                                                                                      \

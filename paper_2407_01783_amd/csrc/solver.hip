@@ -209,10 +209,10 @@ class Engine {
     T* d1 = buf(tag + "_d1", n);
     T* res = buf(tag + "_res", n);
     T* t = (op.apply || op.extra) ? buf(tag + "_t", n) : nullptr;
-    HIP_CHECK(hipMemsetAsync(x, 0, n * sizeof(T), c_->stream));
-    HIP_CHECK(hipMemsetAsync(p, 0, n * sizeof(T), c_->stream));
-    HIP_CHECK(hipMemsetAsync(q, 0, n * sizeof(T), c_->stream));
-    HIP_CHECK(hipMemcpyAsync(r, b, n * sizeof(T), hipMemcpyDeviceToDevice, c_->stream));
+    ops::zero_dev(c_, x, n * sizeof(T));
+    ops::zero_dev(c_, p, n * sizeof(T));
+    ops::zero_dev(c_, q, n * sizeof(T));
+    ops::copy_dev(c_, r, b, n * sizeof(T));
     double* slots = c_->red.result.as<double>() + 2 * kMaxSys;
     ops::dot_dev<T>(c_, nrows, W, b, nullptr, nullptr, slots);
     hipLaunchKernelGGL(k_scal_init, dim3(1), dim3(64), 0, c_->stream, sc, (const double*)slots, cps, nsys,
@@ -492,6 +492,7 @@ class Engine {
                            nrows, ca, cb, x, y);
     });
     ops::check_launch();
+    ops::count_bytes(c_, double(nrows) * (vel ? D_ * nrb_ : nrb_) * (sizeof(TX) + 2 * sizeof(TY)));
   }
 
   // per right-hand-side dots over (velocity, pressure) FP64 pieces
@@ -566,6 +567,7 @@ class Engine {
         hipLaunchKernelGGL((k_mdot_fin<N>), dim3(nb), dim3(kBlock), 0, c_->stream, nbx, (const double*)part, hout);
       });
       ops::check_launch();
+      ops::count_bytes(c_, double(nc) * (nb * sizeof(TK) + sizeof(TX)));  // nb basis vectors and x
     };
     auto mupdate = [&](auto* Vb, int nb, const double* h, double sgn, auto* x, double* res,
                        const double* sig2 = nullptr, T* wf = nullptr) {
@@ -588,6 +590,8 @@ class Engine {
         }
       });
       ops::check_launch();
+      // nb basis vectors read, x read and written (and its copy in T written)
+      ops::count_bytes(c_, double(nc) * (nb * sizeof(TV) + 2 * sizeof(TW) + (wf ? sizeof(T) : 0)));
     };
     // the preconditioner's input v_j in T: the basis itself, or a rounded
     // copy written by the scaling that forms v_j
@@ -601,6 +605,7 @@ class Engine {
                            c_->n_int, c_->n_p1, cs, src, dst, vin);
       });
       ops::check_launch();
+      ops::count_bytes(c_, double(nc) * (2 * sizeof(TK) + (vin ? sizeof(T) : 0)));
     };
 
     // V_0 = r / ||r|| (read in place when (ru, rp) is one coupled vector)
@@ -609,8 +614,8 @@ class Engine {
       if (rp == ru + nu()) {
         w0 = ru;
       } else {
-        HIP_CHECK(hipMemcpyAsync(w, ru, nu() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
-        HIP_CHECK(hipMemcpyAsync(w + nu(), rp, np() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+        ops::copy_dev(c_, w, ru, nu() * sizeof(double));
+        ops::copy_dev(c_, w + nu(), rp, np() * sizeof(double));
       }
     } else {
       ops::cast<double, float>(c_, nu(), ru, w);
@@ -738,6 +743,8 @@ class Engine {
           hipLaunchKernelGGL((k_mdot_fin<N>), dim3(j + 1), dim3(kBlock), 0, c_->stream, nbx, (const double*)part, h2);
         });
         ops::check_launch();
+        // j + 1 basis vectors read once for the update and the dots; w_j (or its T copy) read, w_j written
+        ops::count_bytes(c_, double(nc) * ((j + 1) * sizeof(TK) + (wk ? sizeof(T) : sizeof(TK)) + sizeof(TK)));
       } else {
         mupdate(V, j + 1, h1, -1.0, wj, nullptr, sig2dev);
         mdot(V, j + 1, wj, h2);
@@ -830,11 +837,11 @@ class Engine {
         mupdate((const T*)Z, steps, ydev, 1.0, xu, nullptr);
       } else {
         double* xc = static_cast<double*>(c_->workspace("gm_x", nc * sizeof(double)));
-        HIP_CHECK(hipMemcpyAsync(xc, xu, nu() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
-        HIP_CHECK(hipMemcpyAsync(xc + nu(), xp, np() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+        ops::copy_dev(c_, xc, xu, nu() * sizeof(double));
+        ops::copy_dev(c_, xc + nu(), xp, np() * sizeof(double));
         mupdate((const T*)Z, steps, ydev, 1.0, xc, nullptr);
-        HIP_CHECK(hipMemcpyAsync(xu, xc, nu() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
-        HIP_CHECK(hipMemcpyAsync(xp, xc + nu(), np() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+        ops::copy_dev(c_, xu, xc, nu() * sizeof(double));
+        ops::copy_dev(c_, xp, xc + nu(), np() * sizeof(double));
       }
       HIP_CHECK(hipStreamSynchronize(c_->stream));
     }
@@ -857,11 +864,11 @@ class Engine {
     double* pp = static_cast<double*>(c_->workspace("sc_p", np() * sizeof(double)));
     double* q = static_cast<double*>(c_->workspace("sc_q", np() * sizeof(double)));
     auto to_T = [&](const double* x, T* y, int64_t n) {
-      if (std::is_same<T, double>::value) HIP_CHECK(hipMemcpyAsync(y, x, n * sizeof(T), hipMemcpyDeviceToDevice, c_->stream));
+      if (std::is_same<T, double>::value) ops::copy_dev(c_, y, x, n * sizeof(T));
       else ops::cast<double, float>(c_, n, x, reinterpret_cast<float*>(y));
     };
     auto to_64 = [&](const T* x, double* y, int64_t n) {
-      if (std::is_same<T, double>::value) HIP_CHECK(hipMemcpyAsync(y, x, n * sizeof(T), hipMemcpyDeviceToDevice, c_->stream));
+      if (std::is_same<T, double>::value) ops::copy_dev(c_, y, x, n * sizeof(T));
       else ops::cast<float, double>(c_, n, reinterpret_cast<const float*>(x), y);
     };
     std::vector<double> one(R, 1.0), zero(R, 0.0), mone(R, -1.0);
@@ -871,7 +878,7 @@ class Engine {
     axpy_rhs<T, double>(c_->n_int, true, one.data(), one.data(), vu, xu);
     ops::Bmul<T>(c_, nrb_, vu, tp, (T)1, nullptr, (T)0);
     to_64(tp, q, np());
-    HIP_CHECK(hipMemcpyAsync(s, rp, np() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+    ops::copy_dev(c_, s, rp, np() * sizeof(double));
     ops::axpby<double>(c_, np(), -1.0, q, 1.0, s);
     ops::remove_mean<double>(c_, nrb_, s);
     auto cc64 = [&](const double* in, double* out) {
@@ -889,7 +896,7 @@ class Engine {
     if (!any) return 0;
     cc64(s, z);
     std::vector<double> rho = dots(nullptr, nullptr, s, z);
-    HIP_CHECK(hipMemcpyAsync(pp, z, np() * sizeof(double), hipMemcpyDeviceToDevice, c_->stream));
+    ops::copy_dev(c_, pp, z, np() * sizeof(double));
     int it = 0;
     while (it < max_steps) {
       ++it;
@@ -972,8 +979,8 @@ int refine_loop(stokes_ctx* c, const stokes_solve_opts& o, int method, int nrb, 
   for (int sweep = 0;; ++sweep) {
     // r = b - K x (plain system, FP64); r = b while x is still zero
     if (sweep == 0 && x_zero) {
-      HIP_CHECK(hipMemcpyAsync(ru, F, nu * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-      HIP_CHECK(hipMemcpyAsync(rp, g, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      ops::copy_dev(c, ru, F, nu * sizeof(double));
+      ops::copy_dev(c, rp, g, np * sizeof(double));
     } else {
       ops::momentum<double>(c, nrb, xu, xp, nullptr, ru, -1.0, F);
       ops::Bmul<double>(c, nrb, xu, rp, -1.0, g, 1.0);
@@ -1074,7 +1081,7 @@ int projection_loop(stokes_ctx* c, const stokes_solve_opts& o, int nrb, const do
   auto refined = [&](bool vel, bool mean_free, const double* b, double* x, auto apply64, auto innerT,
                      const std::vector<double>& negligible) {
     const int64_t n = vel ? nu : np;
-    HIP_CHECK(hipMemsetAsync(x, 0, n * sizeof(double), c->stream));
+    ops::zero_dev(c, x, n * sizeof(double));
     std::vector<double> bn = vel ? e64.dots(b, b, nullptr, nullptr) : e64.dots(nullptr, nullptr, b, b);
     for (int k = 0; k < nrb; ++k)
       if (!std::isfinite(bn[k]))
@@ -1115,7 +1122,7 @@ int projection_loop(stokes_ctx* c, const stokes_solve_opts& o, int nrb, const do
   // 1. velocity
   double* bu = ws("pj_bu", nu);
   if (pold) ops::Btmul<double>(c, nrb, pold, nullptr, bu, 1.0, F, 1.0);
-  else HIP_CHECK(hipMemcpyAsync(bu, F, nu * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  else ops::copy_dev(c, bu, F, nu * sizeof(double));
   refined(true, false, bu, xu, [&](const double* x, double* y) { ops::velop<double>(c, nrb, x, y, 1.0, nullptr, 0.0); },
           [&](const T* rr, T* z) { e.vel_solve(rr, z); }, std::vector<double>(nrb, 0.0));
   // 2. divergence data d = B u - g and the pressure Laplacian; d below
@@ -1151,8 +1158,8 @@ int projection_loop(stokes_ctx* c, const stokes_solve_opts& o, int nrb, const do
           },
           neg_d);
   // 4. p = p_old + phi - mu psi
-  if (pold) HIP_CHECK(hipMemcpyAsync(xp, pold, np * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  else HIP_CHECK(hipMemsetAsync(xp, 0, np * sizeof(double), c->stream));
+  if (pold) ops::copy_dev(c, xp, pold, np * sizeof(double));
+  else ops::zero_dev(c, xp, np * sizeof(double));
   ops::axpby<double>(c, np, 1.0, phi, 1.0, xp);
   ops::axpby<double>(c, np, -c->prob.mu, psi, 1.0, xp);
   ops::normalize_pressure<double>(c, nrb, xp);

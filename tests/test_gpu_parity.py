@@ -576,6 +576,8 @@ def test_graph_replay_matches_eager_bitwise(gpu_lib, monkeypatch):
             got = Pg.solve(fb, method=method, precision=1)
             assert torch.equal(ref[0], got[0]) and torch.equal(ref[1], got[1]), method
             assert got[2]["status"] == 0
+            # a replayed graph adds the bytes its launchers counted at capture
+            assert got[2]["bytes_alg"] == ref[2]["bytes_alg"] > 0, method
 
 
 def test_degenerate_single_interior_node(gpu_lib):

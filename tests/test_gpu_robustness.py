@@ -126,3 +126,24 @@ def test_tuning_cache_file(gpu_lib, tmp_path, monkeypatch):
     assert i2["status"] == 0
     assert path.read_text().split() == lines  # read, not re-timed and appended
     assert torch.equal(u1, u2) and torch.equal(p1, p2)
+
+
+@pytest.mark.parametrize("method,precision,inner_mode", [("coupled", 1, 1), ("coupled", 0, 0), ("schur", 1, 0)])
+def test_algorithmic_bytes_of_a_solve(prob, method, precision, inner_mode):
+    """bytes_alg counts every kernel of the call: the same solve counts the
+    same bytes; it covers at least one pass of the stored velocity operator
+    per outer iteration; a batch of two right-hand sides reads the operators
+    once for both, so it counts less than two single solves."""
+    P, f = prob
+    kw = dict(method=method, precision=precision, inner_mode=inner_mode, rtol=1e-10)
+    _, _, a = P.solve(f, **kw)
+    _, _, b = P.solve(f, **kw)
+    print(f"[case] bytes {method} p{precision} m{inner_mode}: {a['bytes_alg']:.4g} B in {a['seconds_total']:.4g} s, "
+          f"{a['outer_iters']} outer", flush=True)
+    assert a["status"] == 0 and a["bytes_alg"] == b["bytes_alg"] > 0
+    val = 2 if precision else 8
+    assert a["bytes_alg"] >= a["outer_iters"] * P.nnz_A * val
+    f2 = torch.cat([f, 0.5 * f])
+    _, _, c = P.solve(f2, **kw)
+    assert c["status"] == 0 and c["bytes_alg"] < 2 * a["bytes_alg"] * max(1.0, c["outer_iters"] / a["outer_iters"])
+
