@@ -76,17 +76,17 @@ def main(out):
         fh.write("# FP64 oracle solution of the 64^3 benchmark workload (see make_cube64_golden.py)\n")
         fh.write(f"# n {N} mesh_seed {SEED} jitter {JITTER} mu {MU!r} alpha {ALPHA!r} forcing_seed "
                  f"{inputs.forcing_seed(SEED)}\n")
-        fh.write(f"rel_res {res!r}\n")
-        fh.write(f"unorm_M {unorm!r}\n")
-        fh.write(f"pnorm_MQ {pnorm!r}\n")
+        fh.write(f"rel_res {float(res)!r}\n")
+        fh.write(f"unorm_M {float(unorm)!r}\n")
+        fh.write(f"pnorm_MQ {float(pnorm)!r}\n")
         fh.write(f"elems {len(elems)}\n")
         fh.write(" ".join(str(int(e)) for e in elems) + "\n")
         fh.write(f"vel {len(vnodes)}\n")
         for v in vnodes:
-            fh.write(f"{int(v)} {u[0, v]!r} {u[1, v]!r} {u[2, v]!r}\n")
+            fh.write(f"{int(v)} {float(u[0, v])!r} {float(u[1, v])!r} {float(u[2, v])!r}\n")
         fh.write(f"p {len(pverts)}\n")
         for k in pverts:
-            fh.write(f"{int(k)} {P[k]!r}\n")
+            fh.write(f"{int(k)} {float(P[k])!r}\n")
     print(f"wrote {out} ({time.time() - t0:.0f} s)", flush=True)
 
 
