@@ -95,6 +95,36 @@ def measured_traffic(workload, nrhs, strain=False):
 
 
 ORACLE_ITERS_FILE = os.path.join(ROOT, "tests", "golden", "cube64_oracle_iters.txt")
+ORACLE_SOLUTION_FILE = os.path.join(ROOT, "tests", "golden", "cube64_oracle.txt")
+
+
+def error_vs_stored_oracle(u, p):
+    """Nodal relative l2 error of the timed solve against the stored FP64
+    oracle solution of the 64^3 workload (the velocity at every P2 node and
+    the pressure at every vertex of 400 seeded elements; values written by
+    tests/golden/make_cube64_golden.py).  The M-norm error is checked by the
+    full-size tests."""
+    import numpy as np
+    vel, pres = {}, {}
+    with open(ORACLE_SOLUTION_FILE) as fh:
+        lines = [ln.split() for ln in fh if not ln.startswith("#")]
+    i = 0
+    while i < len(lines):
+        key = lines[i][0]
+        if key in ("vel", "p"):
+            n = int(lines[i][1])
+            for r in lines[i + 1:i + 1 + n]:
+                (vel if key == "vel" else pres)[int(r[0])] = [float(v) for v in r[1:]]
+            i += n
+        i += 1
+    uv = u.cpu().numpy()[0]
+    pv = p.cpu().numpy()[0]
+    ug = np.array([vel[k] for k in sorted(vel)]).T
+    pg = np.array([pres[k][0] for k in sorted(pres)])
+    eu = np.linalg.norm(uv[:, sorted(vel)] - ug) / np.linalg.norm(ug)
+    ep = np.linalg.norm(pv[sorted(pres)] - pg) / np.linalg.norm(pg)
+    return {"nodal_rel_l2_u": float(eu), "nodal_rel_l2_p": float(ep), "nodes": len(vel), "vertices": len(pres),
+            "reference": "FP64 oracle solution (rel-res 8.4e-16) on 400 seeded elements"}
 
 
 def cpu_baseline_sampled(dim, n, mesh_seed, mu, alpha, fseed, iters=1):
@@ -326,13 +356,19 @@ def main():
         infos = []
         t = time.perf_counter()
         for _ in range(steps):
-            _, _, info = prob.solve(f, method=method, precision=precision, profile=profile, **o)
+            u, p, info = prob.solve(f, method=method, precision=precision, profile=profile, **o)
             infos.append(info)
         torch.cuda.synchronize()
         el = time.perf_counter() - t
+        last_out[:] = [u, p]
         return el, infos
 
+    last_out = []
+
     el_mixed, infos = run(1, args.steps, args.warmup, 1)
+    err = None
+    if args.workload == "cube64" and args.nrhs == 1 and not args.strain and os.path.exists(ORACLE_SOLUTION_FILE):
+        err = error_vs_stored_oracle(*last_out)
     print(f"[bench] mixed: {el_mixed / args.steps * 1e3:.1f} ms/solve", file=sys.stderr, flush=True)
     ok = all(i["status"] == 0 and i["rel_res"] <= opts["rtol"] for i in infos)
     launches = sum(i["spmv_launches"] for i in infos)
@@ -481,6 +517,7 @@ def main():
         "mixed_fp32_storage": fp32_storage,
         "mixed_tol_inner": tol_inner,
         "phases": phases,
+        "error_vs_oracle": err,
         "projection": projection,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,

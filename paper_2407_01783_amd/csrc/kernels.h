@@ -340,13 +340,45 @@ __device__ __forceinline__ void sell_row_il_impl(const SellIdx& ix, const SliceR
   };
   int g = 0;
   for (; g + 2 <= g4; g += 2) groups(std::integral_constant<int, 2>{}, g);
-  if (g < g4) groups(std::integral_constant<int, 1>{}, g);
-  for (int j = 4 * g4; j < r.width; ++j) {
-    const int32_t c = sell_col_f<F>(ix, r, j);
-    const T v = (T)__builtin_nontemporal_load(vals + r.beg + 64 * j);
-#pragma unroll
-    for (int w = 0; w < W; ++w) acc[w] = fma(v, x[(int64_t)c * W + w], acc[w]);
+  // the last group (if any) and the width mod 4 tail slots (slot-major) in
+  // one round trip: every load first, then the sums in slot order
+  const bool last = g < g4;
+  const int t = r.width - 4 * g4;
+  if (!last && t == 0) return;
+  int32_t c[4], ct[3];
+  T v[4], vt[3];
+  if (last) {
+    const int64_t e = s0 + 256 * (int64_t)g + 4 * lr;
+    load4_vals<TM, T>(vals, e, v);
+    load4_cols<F>(ix, r, g, e, c);
   }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (k < t) {
+      ct[k] = sell_col_f<F>(ix, r, 4 * g4 + k);
+      vt[k] = (T)__builtin_nontemporal_load(vals + r.beg + 64 * (4 * g4 + k));
+    }
+  T xv[4][W], xt[3][W];
+  if (last)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int w = 0; w < W; ++w) xv[k][w] = x[(int64_t)c[k] * W + w];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (k < t)
+#pragma unroll
+      for (int w = 0; w < W; ++w) xt[k][w] = x[(int64_t)ct[k] * W + w];
+  if (last)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int w = 0; w < W; ++w) acc[w] = fma(v[k], xv[k][w], acc[w]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (k < t)
+#pragma unroll
+      for (int w = 0; w < W; ++w) acc[w] = fma(vt[k], xt[k][w], acc[w]);
 }
 
 template <typename T, int W, typename TM>

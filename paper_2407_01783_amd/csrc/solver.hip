@@ -433,17 +433,29 @@ class Engine {
   }
 
   // z = C r = alpha X^{-1} r + mu (1 + gamma) M_Q^{-1} r on the mean-free
-  // pressures (X is singular on constants: its inverse acts on 1-perp)
-  void cc_apply(const T* r, T* z) {
+  // pressures (X is singular on constants: its inverse acts on 1-perp).
+  // Inside the coupled preconditioner with fixed inner operators both
+  // projections are skipped (mean_free = false): X^{-1} is then one V-cycle
+  // (or polynomial) of the nonsingular eps M_Q + L_Q, the input already sums
+  // to zero up to rounding (B u does for interior u, and the right-hand
+  // side's pressure part is made mean-free), and a constant added to z_p
+  // changes neither B^T z_p nor K z, only the pressure level that the final
+  // normalization fixes.  Inner CGs on the singular X keep them.
+  void cc_apply(const T* r, T* z, bool mean_free = true) {
     ops::PhaseScope phase(c_, PHASE_PRES);
+    mean_free = mean_free || o_.inner_mode != STOKES_INNER_FIXED;
     T* y = buf("cc_y", np());
-    T* rm = buf("cc_r", np());
-    ops::remove_mean_into<T>(c_, nrb_, r, rm);
-    x_solve(rm, z);
+    const T* rin = r;
+    if (mean_free) {
+      T* rm = buf("cc_r", np());
+      ops::remove_mean_into<T>(c_, nrb_, r, rm);
+      rin = rm;
+    }
+    x_solve(rin, z);
     cheb_apply("ccq", c_->sQ, ops::pick<T>(c_->MQ64, c_->MQ32), ops::pick<T>(c_->dMQ64, c_->dMQ32), c_->bMQ,
-               cc_mq_deg_, nrb_, rm, y);
+               cc_mq_deg_, nrb_, rin, y);
     ops::axpby<T>(c_, np(), (T)(mu_ * (1.0 + gamma_)), y, (T)alpha_, z);
-    ops::remove_mean<T>(c_, nrb_, z);
+    if (mean_free) ops::remove_mean<T>(c_, nrb_, z);
   }
 
   // z = P^{-1} v, block preconditioners of the coupled matrix (Sec. 2.4);
@@ -453,14 +465,14 @@ class Engine {
     T* tu = buf("bp_tu", nu());
     T* yu = buf("bp_yu", nu());
     if (o_.coupled_pc == STOKES_PC_UPPER) {
-      cc_apply(vp, zp);
+      cc_apply(vp, zp, false);
       ops::Btmul<T>(c_, nrb_, zp, nullptr, tu, (T)1, vu, (T)1, bt);  // tu = v_u + B^T z_p
       vel_solve(tu, zu);
       return;
     }
     vel_solve(vu, zu);                                            // y_u = A~^{-1} v_u
     ops::Bmul<T>(c_, nrb_, zu, tp, (T)-1, vp, (T)1);             // t_p = v_p - B y_u
-    cc_apply(tp, zp);                                             // z_p = S~^{-1} t_p
+    cc_apply(tp, zp, false);                                      // z_p = S~^{-1} t_p
     if (o_.coupled_pc == STOKES_PC_LOWER) return;
     ops::Btmul<T>(c_, nrb_, zp, nullptr, tu, (T)1, nullptr, (T)0);  // B^T z_p
     vel_solve(tu, yu);                                               // A~^{-1} B^T z_p
