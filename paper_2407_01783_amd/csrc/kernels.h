@@ -1132,8 +1132,20 @@ __global__ __launch_bounds__(64) void k_interleave4(int64_t nslices, const int64
   }
 }
 
+// The closing step of a deferred Chebyshev sum (the iterate is not carried
+// through the steps): z = dinv (theta_inv r + q_1 + ... + q_n + q_last),
+// with the directions q_k = D d_k kept in bfloat16.
+constexpr int kQSumMax = 14;
+struct QSum {
+  const float* r;
+  float theta_inv;
+  int n;
+  const uint16_t* q[kQSumMax];
+};
+
 // First step with a bfloat16 direction out:  q0 = theta_inv r (not stored),
-// res = r - (S D^{-1}) q0, q1 = bf16(c1 q0 + c2 res), z (+)= dinv (q0 + q1)
+// res = r - (S D^{-1}) q0, q1 = bf16(c1 q0 + c2 res), z (+)= dinv (q0 + q1);
+// ACC = 2 leaves z to the closing step (no z, no dinv).
 // IL (G = 1): ix and vals are the four-slot interleaved copies.
 template <typename TM, int W, int ACC, int G, int U = 8, bool IL = false>
 __global__ __launch_bounds__(kBlock) void k_cheb_first_qb(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
@@ -1148,7 +1160,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first_qb(int64_t nrows, SellIdx
     for (int w = 0; w < WG; ++w) acc[w] = 0;
     if constexpr (IL) sell_row_il<float, W, TM>(ix, vals, r, row, acc);
     else sell_row<float, W, G, TM, (W / G >= 8 ? 4 : U)>(ix, vals, r, row, sub, acc);
-    const float di = dinv[row];
+    const float di = ACC == 2 ? 0.f : dinv[row];
     const int64_t o = row * W + sub * WG, oq = row * WP + sub * WG;
 #pragma unroll
     for (int w = 0; w < WG; ++w) {
@@ -1159,7 +1171,8 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first_qb(int64_t nrows, SellIdx
       const uint16_t qb = bf16_of(fma(c1, q0, c2 * rs));
       q1[oq + w] = qb;
       const float qn = f_of_bf16(qb);
-      z[i] = ACC ? fma(di, q0 + qn, z[i]) : di * (q0 + qn);
+      if constexpr (ACC == 1) z[i] = fma(di, q0 + qn, z[i]);
+      else if constexpr (ACC == 0) z[i] = di * (q0 + qn);
     }
     if constexpr (WP != W) {
       if (sub == G - 1) q1[row * WP + W] = 0;
@@ -1168,12 +1181,16 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first_qb(int64_t nrows, SellIdx
 }
 
 // Later steps:  res = res_in - (S D^{-1}) q ;  qn = bf16(c1 q + c2 res) ;  z += dinv qn
+// ZM = 1: the deferred form -- no z (nor dinv); ZM = 2: the closing step --
+// neither res nor qn is stored, z = dinv (fin.theta_inv fin.r + fin.q[0] +
+// ... + fin.q[n-1] + qn).
 // IL: ix.cdel / ix.cols and vals are the four-slot interleaved copies.
-template <typename TM, int W, int G, int U = 8, bool IL = false>
+template <typename TM, int W, int G, int U = 8, bool IL = false, int ZM = 0>
 __global__ __launch_bounds__(kBlock) void k_cheb_step_qb(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
                                                          const uint16_t* __restrict__ q, uint16_t* __restrict__ qn,
                                                          const float* res_in, float* res_out, float* __restrict__ z,
-                                                         const float* __restrict__ dinv, float c1, float c2) {
+                                                         const float* __restrict__ dinv, float c1, float c2,
+                                                         QSum fin) {
   constexpr int WG = W / G, WP = bf_width<W>();
   XCD_ROWS_G(row, sub, nrows, G) {
     const int64_t o = row * W + sub * WG;
@@ -1196,23 +1213,35 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step_qb(int64_t nrows, SellIdx 
     }
     // res_in may alias res_out: load the whole row before any store
     float ri[WG], qq[WG], zz[WG];
-    const float di = dinv[row];
+    const float di = ZM == 1 ? 0.f : dinv[row];
     load_bf<WP, WG>(q, row, sub * WG, qq);
 #pragma unroll
     for (int w = 0; w < WG; ++w) {
       ri[w] = res_in[o + w];
-      zz[w] = z[o + w];
+      if constexpr (ZM == 0) zz[w] = z[o + w];
+    }
+    if constexpr (ZM == 2) {
+      // the earlier directions, summed in step order after theta_inv r
+#pragma unroll
+      for (int w = 0; w < WG; ++w) zz[w] = fin.theta_inv * fin.r[o + w];
+      for (int k = 0; k < fin.n; ++k) {
+        float t[WG];
+        load_bf<WP, WG>(fin.q[k], row, sub * WG, t);
+#pragma unroll
+        for (int w = 0; w < WG; ++w) zz[w] += t[w];
+      }
     }
     const int64_t oq = row * WP + sub * WG;
 #pragma unroll
     for (int w = 0; w < WG; ++w) {
       const float rs = ri[w] - acc[w];
-      res_out[o + w] = rs;
+      if constexpr (ZM != 2) res_out[o + w] = rs;
       const uint16_t qb = bf16_of(fma(c1, qq[w], c2 * rs));
-      qn[oq + w] = qb;
-      z[o + w] = fma(di, f_of_bf16(qb), zz[w]);
+      if constexpr (ZM != 2) qn[oq + w] = qb;
+      if constexpr (ZM == 0) z[o + w] = fma(di, f_of_bf16(qb), zz[w]);
+      else if constexpr (ZM == 2) z[o + w] = di * (zz[w] + f_of_bf16(qb));
     }
-    if constexpr (WP != W) {
+    if constexpr (WP != W && ZM != 2) {
       if (sub == G - 1) qn[row * WP + W] = 0;
     }
   }

@@ -8,6 +8,8 @@
 
 namespace stokes {
 
+struct QSum;  // closing step of a deferred Chebyshev sum (kernels.h)
+
 void assemble_ctx(stokes_ctx* c);
 void assemble_p1(stokes_ctx* c, const HostMesh& m, MgLevel& L);
 void build_mg(stokes_ctx* c);
@@ -138,10 +140,12 @@ void cheb_first_hs(stokes_ctx* c, const Sell& S, const _Float16* vals, float ms,
 void cheb_step_hs(stokes_ctx* c, const Sell& S, const _Float16* vals, float ms, int W, const float* d, float* dn,
                   const float* res_in, float* res_out, float* z, const float* dinv, float c1, float c2);
 // The same with the direction q kept in bfloat16 (W = 3 rows padded to 4).
+// zw = false: the deferred form, which leaves z to a closing step; fin: that
+// closing step (res and qn are not stored, z = dinv (theta_inv r + q_1 + ...)).
 void cheb_first_hb(stokes_ctx* c, int W, const float* r, const float* dinv, float theta_inv, uint16_t* q1,
-                   float* res, float* z, float c1, float c2);
+                   float* res, float* z, float c1, float c2, bool zw = true);
 void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const float* res_in, float* res_out,
-                  float* z, const float* dinv, float c1, float c2);
+                  float* z, const float* dinv, float c1, float c2, const QSum* fin = nullptr, bool zw = true);
 // The same two steps on the half-precision column-scaled velocity block
 // A_II D^{-1} (ctx AD16) in the rescaled direction q = D d (FP32 vectors).
 void cheb_first_h(stokes_ctx* c, int W, const float* r, const float* dinv, float theta_inv, float* q1, float* res,

@@ -582,7 +582,7 @@ void cheb_first_h(stokes_ctx* c, int W, const float* r, const float* dinv, float
 }
 
 void cheb_first_hb(stokes_ctx* c, int W, const float* r, const float* dinv, float theta_inv, uint16_t* q1,
-                   float* res, float* z, float c1, float c2) {
+                   float* res, float* z, float c1, float c2, bool zw) {
   const Sell& S = c->sA;
   const int G = lanes_qb(c, W);
   int wp = W;
@@ -594,28 +594,36 @@ void cheb_first_hb(stokes_ctx* c, int W, const float* r, const float* dinv, floa
       constexpr int GG = decltype(Gc)::value;
       if constexpr (GG == 1) {
         if (c->vel_il && c->AD16i.p) {  // the four-slot interleaved copies
-          hipLaunchKernelGGL((k_cheb_first_qb<_Float16, WW, 0, 1, 8, true>), dim3(grid_full(S.nrows)), dim3(kBlock),
-                             0, c->stream, S.nrows, vel_il_idx(c), (const _Float16*)c->AD16i.as<_Float16>(), r, dinv,
-                             theta_inv, q1, res, z, c1, c2);
+          auto kern = zw ? k_cheb_first_qb<_Float16, WW, 0, 1, 8, true> : k_cheb_first_qb<_Float16, WW, 2, 1, 8, true>;
+          hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows, vel_il_idx(c),
+                             (const _Float16*)c->AD16i.as<_Float16>(), r, dinv, theta_inv, q1, res, z, c1, c2);
           il = true;
           return;
         }
       }
-      hipLaunchKernelGGL((k_cheb_first_qb<_Float16, WW, 0, GG>),
-                         dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0,
-                         c->stream, S.nrows, S.idx(), (const _Float16*)c->AD16.as<_Float16>(), r, dinv, theta_inv,
-                         q1, res, z, c1, c2);
+      auto kern = zw ? k_cheb_first_qb<_Float16, WW, 0, GG> : k_cheb_first_qb<_Float16, WW, 2, GG>;
+      hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows, S.idx(),
+                         (const _Float16*)c->AD16.as<_Float16>(), r, dinv, theta_inv, q1, res, z, c1, c2);
     });
   });
   check_launch();
-  // half values, r gathered, dinv read; res, z (floats) and q1 (bfloat16) written
-  count_bytes(c, op_bytes(S, 2, il && c->vel_af) + double(S.nrows) * (4.0 * (3.0 * W + 1.0) + 2.0 * wp));
+  // half values, r gathered; res (floats) and q1 (bfloat16) written; dinv
+  // read and z written unless deferred
+  count_bytes(c, op_bytes(S, 2, il && c->vel_af) +
+                     double(S.nrows) * (4.0 * (2.0 * W) + 2.0 * wp + (zw ? 4.0 * (W + 1.0) : 0.0)));
 }
 
 void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const float* res_in, float* res_out,
-                  float* z, const float* dinv, float c1, float c2) {
+                  float* z, const float* dinv, float c1, float c2, const QSum* fin, bool zw) {
   const Sell& S = c->sA;
-  const bool timed = prof_begin(c, &S, nullptr, nullptr);
+  // the timed launches: the steps that carry the iterate (deferred or not), not the closing one
+  const bool timed = fin == nullptr && prof_begin(c, &S, nullptr, nullptr);
+  const int zm = fin ? 2 : zw ? 0 : 1;
+  QSum fa{};
+  if (fin) {
+    if (fin->n < 0 || fin->n > kQSumMax) throw Error(STOKES_ERR_ARG, "deferred Chebyshev sum too long");
+    fa = *fin;
+  }
   const int G = lanes_qb(c, W);
   int wp = W;
   bool il = false;
@@ -627,24 +635,34 @@ void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const f
       const int nb = grid_full(S.nrows * GG);
       if constexpr (BfRaw<bf_width<WW>(), WW / GG>::kOn) {
         if (c->vel_il && c->AD16i.p) {  // the four-slot interleaved copies
-          hipLaunchKernelGGL((k_cheb_step_qb<_Float16, WW, GG, 8, true>), dim3(nb), dim3(kBlock), 0, c->stream,
-                             S.nrows, vel_il_idx(c), (const _Float16*)c->AD16i.as<_Float16>(), q, qn, res_in,
-                             res_out, z, dinv, c1, c2);
+          auto kern = zm == 0   ? k_cheb_step_qb<_Float16, WW, GG, 8, true, 0>
+                      : zm == 1 ? k_cheb_step_qb<_Float16, WW, GG, 8, true, 1>
+                                : k_cheb_step_qb<_Float16, WW, GG, 8, true, 2>;
+          hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, S.nrows, vel_il_idx(c),
+                             (const _Float16*)c->AD16i.as<_Float16>(), q, qn, res_in, res_out, z, dinv, c1, c2, fa);
           il = true;
           return;
         }
       }
-      hipLaunchKernelGGL((k_cheb_step_qb<_Float16, WW, GG>), dim3(nb), dim3(kBlock), 0, c->stream, S.nrows,
-                         S.idx(), (const _Float16*)c->AD16.as<_Float16>(), q, qn, res_in, res_out, z, dinv, c1, c2);
+      auto kern = zm == 0   ? k_cheb_step_qb<_Float16, WW, GG, 8, false, 0>
+                  : zm == 1 ? k_cheb_step_qb<_Float16, WW, GG, 8, false, 1>
+                            : k_cheb_step_qb<_Float16, WW, GG, 8, false, 2>;
+      hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, S.nrows, S.idx(),
+                         (const _Float16*)c->AD16.as<_Float16>(), q, qn, res_in, res_out, z, dinv, c1, c2, fa);
     });
   });
   check_launch();
   // algorithmic bytes: the stored operator once (half values of every padded
   // entry, the column-index structure it reads: slot words alone for the
-  // affine slices of the interleaved copy); res_in, z read and res_out, z
-  // written (W floats each); q read once (gathered and own row) and qn
-  // written (WP bfloat16 each); dinv read
-  const double bytes = op_bytes(S, 2, il && c->vel_af) + double(S.nrows) * (4.0 * (W * 4.0 + 1.0) + 2.0 * 2.0 * wp);
+  // affine slices of the interleaved copy); q read once (gathered and own
+  // row, WP bfloat16); res_in read (W floats); then
+  //   carrying z:  res_out and z written, z and dinv read, qn written;
+  //   deferred:    res_out and qn written;
+  //   closing:     r and the n earlier directions read, dinv read, z written
+  const double vec = zm == 0   ? 4.0 * (W * 4.0 + 1.0) + 2.0 * 2.0 * wp
+                     : zm == 1 ? 4.0 * (W * 2.0) + 2.0 * 2.0 * wp
+                               : 4.0 * (W * 3.0 + 1.0) + 2.0 * wp * (1.0 + fa.n);
+  const double bytes = op_bytes(S, 2, il && c->vel_af) + double(S.nrows) * vec;
   count_bytes(c, bytes);
   if (timed) prof_end(c, bytes);
 }
@@ -872,10 +890,10 @@ void tune_lanes(stokes_ctx* c, int W) {
       float* xr = reinterpret_cast<float*>(x.p);
       float* yz = reinterpret_cast<float*>(y.p);
       const float* di = c->dA32.as<float>();
-      cheb_step_hb(c, W, qa.as<uint16_t>(), qb.as<uint16_t>(), xr, xr, yz, di, 0.5f, 0.5f);  // warm-up
+      cheb_step_hb(c, W, qa.as<uint16_t>(), qb.as<uint16_t>(), xr, xr, yz, di, 0.5f, 0.5f, nullptr, false);  // warm-up
       HIP_CHECK(hipEventRecord(e0, c->stream));
       for (int rep = 0; rep < 3; ++rep)
-        cheb_step_hb(c, W, qa.as<uint16_t>(), qb.as<uint16_t>(), xr, xr, yz, di, 0.5f, 0.5f);
+        cheb_step_hb(c, W, qa.as<uint16_t>(), qb.as<uint16_t>(), xr, xr, yz, di, 0.5f, 0.5f, nullptr, false);
       HIP_CHECK(hipEventRecord(e1, c->stream));
       HIP_CHECK(hipEventSynchronize(e1));
       float ms = 0;

@@ -153,6 +153,27 @@ class Engine {
         // the direction in bfloat16 (the float buffers hold it, narrower)
         uint16_t* q0 = reinterpret_cast<uint16_t*>(d0);
         uint16_t* q1 = reinterpret_cast<uint16_t*>(d1);
+        if (c_->cheb_defer && degree >= 3 && degree - 2 <= kQSumMax) {
+          // z = D^{-1} (theta_inv r + q_1 + ... + q_{degree-1}) formed by the
+          // last step: the steps before it neither read nor write z, and
+          // each keeps its direction q_j (buffers q_1 .. q_{degree-2})
+          std::vector<uint16_t*> q(degree - 1, nullptr);
+          for (int j = 1; j <= degree - 2; ++j)
+            q[j] = reinterpret_cast<uint16_t*>(buf(tag + "_q" + std::to_string(j), n));
+          ops::cheb_first_hb(c_, W, r, dinv, (float)k.theta_inv, q[1], res, z, (float)k.c1[0], (float)k.c2[0],
+                             false);
+          for (int j = 2; j < degree - 1; ++j)
+            ops::cheb_step_hb(c_, W, q[j - 1], q[j], res, res, z, dinv, (float)k.c1[j - 1], (float)k.c2[j - 1],
+                              nullptr, false);
+          QSum fin{};
+          fin.r = reinterpret_cast<const float*>(r);
+          fin.theta_inv = (float)k.theta_inv;
+          fin.n = degree - 2;
+          for (int j = 1; j <= degree - 2; ++j) fin.q[j - 1] = q[j];
+          ops::cheb_step_hb(c_, W, q[degree - 2], nullptr, res, nullptr, z, dinv, (float)k.c1[degree - 2],
+                            (float)k.c2[degree - 2], &fin);
+          return;
+        }
         ops::cheb_first_hb(c_, W, r, dinv, (float)k.theta_inv, q0, res, z, (float)k.c1[0], (float)k.c2[0]);
         for (int j = 2; j < degree; ++j) {
           ops::cheb_step_hb(c_, W, q0, q1, res, res, z, dinv, (float)k.c1[j - 1], (float)k.c2[j - 1]);
