@@ -522,10 +522,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": measured_traffic(args.workload, args.nrhs, args.strain),
-                     "kernel": f"k_cheb_step_qb<_Float16,{dim * args.nrhs},G,8,true> (velocity-block SELL SpMV: "
+                     "kernel": f"k_cheb_step_qb<_Float16,{dim * args.nrhs},G,8,true,1> (velocity-block SELL SpMV: "
                                f"half-precision A_II D^-1 values and computed or packed column offsets read from four-slot "
-                               f"interleaved copies, bfloat16 direction, FP32 residual and iterate; fused Chebyshev "
-                               f"update; G lanes per row, autotuned)",
+                               f"interleaved copies, bfloat16 direction, FP32 residual; a Chebyshev step of the "
+                               f"deferred sum (the iterate is formed by the closing step); G lanes per row, autotuned)",
                      "bytes_per_launch": bytes_per, "launches": launches,
                      "avg_us": kern_s / launches * 1e6 if launches else None,
                      "frac_of_read_probe": (achieved / probe["read_GBs"]) if achieved else None,

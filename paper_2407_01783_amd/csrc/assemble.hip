@@ -1155,19 +1155,21 @@ void assemble_ctx(stokes_ctx* c) {
     }
   // Stable bucket order by (slab, block, type), natural order inside a
   // bucket.  A block is `zblock` consecutive lattice planes of the slab (0:
-  // the whole slab; by default 4 planes once a plane holds more than 2^16
+  // the whole slab; by default 2 planes once a plane holds more than 2^15
   // nodes, else the whole slab): a kernel walks the rows of one type block
   // by block, so the gathered neighbours (all types, the block's planes and
   // one halo plane on each side) stay in the caches while the other types of
   // the same block are walked.  On the large meshes with many right-hand
-  // sides a slab's worth of them does not (cube128 x 8: the bfloat16
-  // Chebyshev step 3.83 -> 3.53 ms); on smaller ones the blocks only cost.
+  // sides a slab's worth of them does not (cube128 x 8: 931 -> 868 ms per
+  // batched solve with 2-plane blocks, 888 with 4, 926 with 8; one
+  // right-hand side: no change); on smaller ones the blocks only cost
+  // (cube64: 11.64 -> 11.94 ms with 4-plane blocks).
   std::vector<int32_t> interior;
   {
     const int64_t nK = n2 - 2;  // interior planes (3D) or lines (2D)
     std::vector<int64_t> slab_lo(9);
     for (int sl = 0; sl <= 8; ++sl) slab_lo[sl] = (sl * nK + 7) / 8;  // first K - 1 with slab >= sl
-    const int64_t zbk = c->zblock >= 0 ? c->zblock : (plane > (int64_t(1) << 16) ? 4 : 0);
+    const int64_t zbk = c->zblock >= 0 ? c->zblock : (plane > (int64_t(1) << 15) ? 2 : 0);
     const int64_t zb = zbk > 0 ? zbk : nK;
     const int64_t nblk = (nK + zb - 1) / zb + 8;  // blocks per slab, bounded
     std::vector<int64_t> start(8 * nblk * ntypes + 1, 0);

@@ -242,7 +242,7 @@ def test_mixed_solve_bitwise_reproducible_across_contexts(gpu_lib):
 @pytest.mark.parametrize("dim,n,zb", [(3, 8, 2), (2, 16, 3)])
 def test_plane_blocked_row_order(gpu_lib, monkeypatch, dim, n, zb):
     """Interior rows blocked by zb lattice planes inside each slab (the order
-    taken on meshes whose planes exceed 2^16 nodes) give the same FP64
+    taken on meshes whose planes exceed 2^15 nodes) give the same FP64
     operator products as the slab order, to rounding, and a mixed coupled
     solve that matches the oracle."""
     from paper_2407_01783_amd import inputs
