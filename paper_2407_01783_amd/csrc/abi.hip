@@ -550,6 +550,7 @@ stokes_status stokes_assemble(const stokes_problem* prob, void* hip_stream, stok
     if (const char* e = std::getenv("STOKES_VEL_IL")) c->vel_il = std::atoi(e) != 0;
     if (const char* e = std::getenv("STOKES_VEL_AF")) c->vel_af = std::atoi(e) != 0;
     if (const char* e = std::getenv("STOKES_CHEB_DEFER")) c->cheb_defer = std::atoi(e) != 0;
+    if (const char* e = std::getenv("STOKES_GRAM")) c->gram_cgs2 = std::atoi(e) != 0;
     if (const char* e = std::getenv("STOKES_LANES")) c->force_lanes = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("STOKES_ZBLOCK")) c->zblock = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("STOKES_MG_ES")) {

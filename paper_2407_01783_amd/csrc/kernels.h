@@ -1852,21 +1852,25 @@ __global__ __launch_bounds__(kBlock) void k_mupdate(int64_t n_int, int64_t n_p1,
 // row mapping and block reduction, so k_mdot_fin gives the same sums as a
 // separate k_mdot pass.  One read of the basis instead of two.  w is read
 // from win (TI, may be w itself) and written in TW.
+// GRAM = 1 (the update with the whole CGS2 coefficients, the new basis
+// column): also ||w||^2 of the stored w as entry nb (chunk nb / 8, slot
+// nb mod 8), and wf (optional) receives w rounded to TF.
 constexpr int kFusedMax = 8;
-template <typename TV, typename TW, int D, int NRB, typename TI = TW>
+template <typename TV, typename TW, int D, int NRB, typename TI = TW, int GRAM = 0, typename TF = TW>
 __global__ __launch_bounds__(kBlock) void k_mupdate_dot(int64_t n_int, int64_t n_p1, const TV* __restrict__ V,
                                                         int64_t ldv, int nb, const double* __restrict__ h,
                                                         const TI* win, TW* w, double* __restrict__ part,
-                                                        const double* __restrict__ sig2 = nullptr) {
-  constexpr int W = D * NRB, CH = kMdotChunk, NM = kFusedMax;
+                                                        const double* __restrict__ sig2 = nullptr,
+                                                        TF* __restrict__ wf = nullptr) {
+  constexpr int W = D * NRB, CH = kMdotChunk, NM = kFusedMax, NA = NM + GRAM;
   __shared__ double hs[NM * NRB];
   for (int i = threadIdx.x; i < nb * NRB; i += blockDim.x) hs[i] = -h[i] * (sig2 ? sig2[i] : 1.0);
   __syncthreads();
   const int sub = (int)(threadIdx.x % NRB);
   const int64_t nv = n_int * W;
-  double acc[NM];
+  double acc[NA];
 #pragma unroll
-  for (int i = 0; i < NM; ++i) acc[i] = 0;
+  for (int i = 0; i < NA; ++i) acc[i] = 0;
   for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / NRB; t < n_int + n_p1;
        t += (int64_t)gridDim.x * blockDim.x / NRB) {
     if (t < n_int) {
@@ -1893,6 +1897,7 @@ __global__ __launch_bounds__(kBlock) void k_mupdate_dot(int64_t n_int, int64_t n
       for (int d = 0; d < D; ++d) {
         const TW sv = (TW)a[d];
         w[o + d] = sv;
+        if (GRAM && wf) wf[o + d] = (TF)sv;
         st[d] = (double)sv;
       }
 #pragma unroll
@@ -1903,6 +1908,12 @@ __global__ __launch_bounds__(kBlock) void k_mupdate_dot(int64_t n_int, int64_t n
           for (int d = 0; d < D; ++d) sacc += (double)v[i][d] * st[d];
           acc[i] += sacc;
         }
+      if constexpr (GRAM) {
+        double nacc = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) nacc += st[d] * st[d];
+        acc[NM] += nacc;
+      }
     } else {
       const int64_t o = nv + (t - n_int) * NRB + sub;
       TV v[NM];
@@ -1915,24 +1926,75 @@ __global__ __launch_bounds__(kBlock) void k_mupdate_dot(int64_t n_int, int64_t n
         if (i < nb) a += hs[i * NRB + sub] * (double)v[i];
       const TW sv = (TW)a;
       w[o] = sv;
+      if (GRAM && wf) wf[o] = (TF)sv;
 #pragma unroll
       for (int i = 0; i < NM; ++i)
         if (i < nb) acc[i] += (double)v[i] * (double)sv;
+      if constexpr (GRAM) acc[NM] += (double)sv * (double)sv;
     }
   }
-  __shared__ double sh[kBlock / 64][NM][NRB];
+  __shared__ double sh[kBlock / 64][NA][NRB];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < NM; ++i) {
+  for (int i = 0; i < NA; ++i) {
     const double sv = wave_sum_strided<NRB>(acc[i]);
     if (lane < NRB) sh[wave][i][lane] = sv;
   }
   __syncthreads();
+  // entries 0 .. nb-1: the dots; entry nb (GRAM): the squared norm (slot NM of sh)
+  for (int q = threadIdx.x; q < (nb + GRAM) * NRB; q += blockDim.x) {
+    const int i = q / NRB, r = q % NRB;
+    const int si = i < nb ? i : NM;
+    double sv = 0;
+    for (int k = 0; k < kBlock / 64; ++k) sv += sh[k][si][r];
+    part[((((int64_t)(i / CH)) * gridDim.x + blockIdx.x) * CH + (i % CH)) * NRB + r] = sv;
+  }
+}
+
+// CGS2 with the second projection from the Gram matrix of the (unnormalized)
+// basis columns C_i, R_ik = C_i . C_k, kept per right-hand side: with the
+// first projection's dots a_i = C_i . w and the squared scales s_i^2 of the
+// columns, the second projection's dots are
+//   b_i = C_i . (w - sum_k s_k^2 a_k C_k) = a_i - sum_k R_ik s_k^2 a_k,
+// so one update w <- w - sum_i s_i^2 (a_i + b_i) C_i gives the CGS2 vector
+// without a second pass over the basis.  One block; writes b (h2) and a + b
+// (hsum).  R: [i][k][r] with strides 64 * 8 and 8.
+constexpr int kGramLd = 64;
+template <int NRB>
+__global__ __launch_bounds__(kBlock) void k_gram_h2(int nb, const double* __restrict__ R,
+                                                    const double* __restrict__ sig2, const double* __restrict__ h1,
+                                                    double* __restrict__ h2, double* __restrict__ hsum) {
   for (int q = threadIdx.x; q < nb * NRB; q += blockDim.x) {
     const int i = q / NRB, r = q % NRB;
-    double sv = 0;
-    for (int k = 0; k < kBlock / 64; ++k) sv += sh[k][i][r];
-    part[((((int64_t)(i / CH)) * gridDim.x + blockIdx.x) * CH + (i % CH)) * NRB + r] = sv;
+    double s = 0;
+    for (int k = 0; k < nb; ++k) s += R[((int64_t)i * kGramLd + k) * 8 + r] * sig2[k * NRB + r] * h1[k * NRB + r];
+    const double b = h1[i * NRB + r] - s;
+    h2[i * NRB + r] = b;
+    hsum[i * NRB + r] = h1[i * NRB + r] + b;
+  }
+}
+
+// The new column's Gram row from k_mupdate_dot<GRAM = 1>'s partials: entry
+// i < nb is C_i . C_nb, entry nb is ||C_nb||^2 (also written to nrm[r]).
+// One block per entry.
+template <int NRB>
+__global__ __launch_bounds__(kBlock) void k_gram_fin(int nblk, const double* __restrict__ part, int nb,
+                                                     double* __restrict__ R, double* __restrict__ nrm) {
+  const int i = blockIdx.x, ch = i / kMdotChunk, j = i % kMdotChunk;
+  double acc[NRB];
+#pragma unroll
+  for (int r = 0; r < NRB; ++r) acc[r] = 0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) acc[r] += part[(((int64_t)ch * nblk + b) * kMdotChunk + j) * NRB + r];
+  __shared__ double tot[NRB];
+  block_sum<NRB>(acc, tot);
+  if (threadIdx.x < NRB) {
+    const int r = threadIdx.x;
+    const double v = tot[r];
+    R[((int64_t)i * kGramLd + nb) * 8 + r] = v;
+    R[((int64_t)nb * kGramLd + i) * 8 + r] = v;
+    if (i == nb) nrm[r] = v;
   }
 }
 

@@ -682,6 +682,18 @@ class Engine {
       sig2host[r] = sig[r];
     }
     HIP_CHECK(hipMemcpyAsync(sig2dev, sig2host, R * sizeof(double), hipMemcpyHostToDevice, c_->stream));
+    // Gram matrix of the stored columns for the one-update CGS2 (steps with
+    // at most kFusedMax columns): column 0 is stored normalized
+    const bool gram = c_->gram_cgs2 != 0;
+    double* Rg = nullptr;
+    double* hsum = nullptr;
+    if (gram) {
+      Rg = static_cast<double*>(c_->workspace("gm_R", (size_t)kGramLd * kGramLd * 8 * sizeof(double)));
+      hsum = static_cast<double*>(c_->workspace("gm_hs", 64 * 8 * sizeof(double)));
+      double* onesh = static_cast<double*>(c_->workspace_host("gm_R00", 8 * sizeof(double)));
+      for (int r = 0; r < 8; ++r) onesh[r] = 1.0;
+      HIP_CHECK(hipMemcpyAsync(Rg, onesh, 8 * sizeof(double), hipMemcpyHostToDevice, c_->stream));
+    }
     auto Hat = [&](int i, int j, int r) -> double& { return H[((size_t)i * m + j) * R + r]; };
     // K_gamma z_j in the inner precision T (the FP32 matrices) unless the
     // FP64 operator is asked for
@@ -761,7 +773,32 @@ class Engine {
       const bool orth_timed = ops::phase_begin(c_, PHASE_ORTH);
       if (wk) mdot(V, j + 1, (const T*)wk, h1);
       else mdot(V, j + 1, (const TK*)wj, h1);
-      if (j + 1 <= kFusedMax) {
+      if (gram && j + 1 <= kFusedMax) {
+        // CGS2 in one update: the second projection's dots from the Gram
+        // matrix, then w <- w - V s^2 (h1 + h2), which also writes the next
+        // preconditioner input and the new column's Gram row and norm
+        dispatch_dn(D_, nrb_, [&](auto Dc, auto Nc) {
+          constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
+          hipLaunchKernelGGL((k_gram_h2<N>), dim3(1), dim3(kBlock), 0, c_->stream, j + 1, (const double*)Rg,
+                             (const double*)sig2dev, (const double*)h1, h2, hsum);
+          ops::check_launch();
+          if (wk)
+            hipLaunchKernelGGL((k_mupdate_dot<TK, TK, D, N, T, 1, T>), dim3(nbx), dim3(kBlock), 0, c_->stream,
+                               c_->n_int, c_->n_p1, (const TK*)V, nc, j + 1, (const double*)hsum, (const T*)wk, wj, part,
+                               (const double*)sig2dev, vin);
+          else
+            hipLaunchKernelGGL((k_mupdate_dot<TK, TK, D, N, TK, 1, T>), dim3(nbx), dim3(kBlock), 0, c_->stream,
+                               c_->n_int, c_->n_p1, (const TK*)V, nc, j + 1, (const double*)hsum, (const TK*)wj, wj,
+                               part, (const double*)sig2dev, vin);
+          ops::check_launch();
+          hipLaunchKernelGGL((k_gram_fin<N>), dim3(j + 2), dim3(kBlock), 0, c_->stream, nbx, (const double*)part, j + 1,
+                             Rg, nrm);
+        });
+        ops::check_launch();
+        // j + 1 basis vectors read once; w_j (or its T copy) read; the next column (and its T copy) written
+        ops::count_bytes(c_, double(nc) * ((j + 1) * sizeof(TK) + (wk ? sizeof(T) : sizeof(TK)) + sizeof(TK) +
+                                           (vin ? sizeof(T) : 0)));
+      } else if (j + 1 <= kFusedMax) {
         dispatch_dn(D_, nrb_, [&](auto Dc, auto Nc) {
           constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
           if (wk)
@@ -783,7 +820,7 @@ class Engine {
         mdot(V, j + 1, wj, h2);
       }
       // the second update also leaves the next preconditioner input (in T)
-      mupdate(V, j + 1, h2, -1.0, wj, nrm, sig2dev, vin);
+      if (!(gram && j + 1 <= kFusedMax)) mupdate(V, j + 1, h2, -1.0, wj, nrm, sig2dev, vin);
       if (orth_timed) ops::phase_end(c_, PHASE_ORTH);
       HIP_CHECK(hipMemcpyAsync(hhost, hdev, 3 * 64 * 8 * sizeof(double), hipMemcpyDeviceToHost, c_->stream));
       if (queue_ahead && j + 1 < m && est_prev > kQueueAhead * target[0]) {

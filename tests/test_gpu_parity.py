@@ -203,6 +203,38 @@ def test_affine_columns_bitwise_equal(gpu_lib, monkeypatch, dim, n, nrhs):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("precision,opts", [
+    (1, dict()),                                                          # the benchmark's fixed inner operators
+    (0, dict(inner_mode=0)),                                              # FP64 with inner CGs
+    (0, dict(restart=14, cheb_degree=2, coupled_pc=2, inner_mode=1)),     # FP64 cycles past 8 columns
+])
+def test_gram_cgs2_matches_three_pass_cgs2(gpu_lib, monkeypatch, precision, opts):
+    """CGS2 with the second projection's dots taken from the basis Gram
+    matrix (one pass over the basis fewer) equals the three-pass CGS2 in
+    exact arithmetic: the same outer iteration count, both solutions match
+    the oracle, and they agree with each other to the solve tolerance."""
+    from paper_2407_01783_amd import inputs
+    kw = dict(dim=3, n=6, seed=4, mu=1e-2, alpha=100.0)
+    S = _oracle(**kw)
+    f = inputs.fourier_forcing(S.mesh.p2coords, inputs.forcing_seed(4))
+    U, Pp = S.solve(*S.rhs(f))
+    outs = {}
+    for g in ("0", "1"):
+        monkeypatch.setenv("STOKES_GRAM", g)
+        P = _problem(**kw)
+        u, p, info = P.solve(torch.tensor(f[None], device="cuda"), method="coupled", precision=precision,
+                             rtol=1e-11, max_outer=2000, max_refine=30, **opts)
+        print(f"gram={g}: {info}", flush=True)
+        assert info["status"] == 0, info
+        outs[g] = (u.cpu().numpy()[0], p.cpu().numpy()[0], info["outer_iters"])
+        assert _rel(outs[g][0], S.full_velocity(U)) <= 1e-9 and _rel(outs[g][1], Pp) <= 1e-9
+        del P
+    if "restart" in opts:
+        assert outs["1"][2] > 9  # FP64 cycles run to the restart length: steps past the eighth column
+    assert abs(outs["0"][2] - outs["1"][2]) <= 1
+    assert _rel(outs["1"][0], outs["0"][0]) <= 1e-9 and _rel(outs["1"][1], outs["0"][1]) <= 1e-9
+
+
 def test_set_mu_then_mixed_solve_matches_oracle(gpu_lib):
     """set_mu rebuilds the FP32 and half-precision copies and their four-slot
     interleaved forms (read by the velocity Chebyshev and by K_gamma): a
