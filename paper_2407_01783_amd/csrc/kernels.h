@@ -1854,15 +1854,17 @@ __global__ __launch_bounds__(kBlock) void k_mupdate(int64_t n_int, int64_t n_p1,
 // from win (TI, may be w itself) and written in TW.
 // GRAM = 1 (the update with the whole CGS2 coefficients, the new basis
 // column): also ||w||^2 of the stored w as entry nb (chunk nb / 8, slot
-// nb mod 8), and wf (optional) receives w rounded to TF.
-constexpr int kFusedMax = 8;
-template <typename TV, typename TW, int D, int NRB, typename TI = TW, int GRAM = 0, typename TF = TW>
+// nb mod 8), and wf (optional) receives w rounded to TF.  NM: the largest nb
+// (the basis values of a row are held in registers for the dots); launched
+// with 8 up to 8 columns and 16 beyond, up to kFusedMax.
+constexpr int kFusedMax = 16;
+template <typename TV, typename TW, int D, int NRB, typename TI = TW, int GRAM = 0, typename TF = TW, int NM = 8>
 __global__ __launch_bounds__(kBlock) void k_mupdate_dot(int64_t n_int, int64_t n_p1, const TV* __restrict__ V,
                                                         int64_t ldv, int nb, const double* __restrict__ h,
                                                         const TI* win, TW* w, double* __restrict__ part,
                                                         const double* __restrict__ sig2 = nullptr,
                                                         TF* __restrict__ wf = nullptr) {
-  constexpr int W = D * NRB, CH = kMdotChunk, NM = kFusedMax, NA = NM + GRAM;
+  constexpr int W = D * NRB, CH = kMdotChunk, NA = NM + GRAM;
   __shared__ double hs[NM * NRB];
   for (int i = threadIdx.x; i < nb * NRB; i += blockDim.x) hs[i] = -h[i] * (sig2 ? sig2[i] : 1.0);
   __syncthreads();

@@ -782,14 +782,19 @@ class Engine {
           hipLaunchKernelGGL((k_gram_h2<N>), dim3(1), dim3(kBlock), 0, c_->stream, j + 1, (const double*)Rg,
                              (const double*)sig2dev, (const double*)h1, h2, hsum);
           ops::check_launch();
-          if (wk)
-            hipLaunchKernelGGL((k_mupdate_dot<TK, TK, D, N, T, 1, T>), dim3(nbx), dim3(kBlock), 0, c_->stream,
-                               c_->n_int, c_->n_p1, (const TK*)V, nc, j + 1, (const double*)hsum, (const T*)wk, wj, part,
-                               (const double*)sig2dev, vin);
-          else
-            hipLaunchKernelGGL((k_mupdate_dot<TK, TK, D, N, TK, 1, T>), dim3(nbx), dim3(kBlock), 0, c_->stream,
-                               c_->n_int, c_->n_p1, (const TK*)V, nc, j + 1, (const double*)hsum, (const TK*)wj, wj,
-                               part, (const double*)sig2dev, vin);
+          auto go = [&](auto NMc) {
+            constexpr int NM = decltype(NMc)::value;
+            if (wk)
+              hipLaunchKernelGGL((k_mupdate_dot<TK, TK, D, N, T, 1, T, NM>), dim3(nbx), dim3(kBlock), 0, c_->stream,
+                                 c_->n_int, c_->n_p1, (const TK*)V, nc, j + 1, (const double*)hsum, (const T*)wk, wj,
+                                 part, (const double*)sig2dev, vin);
+            else
+              hipLaunchKernelGGL((k_mupdate_dot<TK, TK, D, N, TK, 1, T, NM>), dim3(nbx), dim3(kBlock), 0, c_->stream,
+                                 c_->n_int, c_->n_p1, (const TK*)V, nc, j + 1, (const double*)hsum, (const TK*)wj, wj,
+                                 part, (const double*)sig2dev, vin);
+          };
+          if (j + 1 <= 8) go(std::integral_constant<int, 8>{});
+          else go(std::integral_constant<int, kFusedMax>{});
           ops::check_launch();
           hipLaunchKernelGGL((k_gram_fin<N>), dim3(j + 2), dim3(kBlock), 0, c_->stream, nbx, (const double*)part, j + 1,
                              Rg, nrm);
@@ -801,14 +806,19 @@ class Engine {
       } else if (j + 1 <= kFusedMax) {
         dispatch_dn(D_, nrb_, [&](auto Dc, auto Nc) {
           constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
-          if (wk)
-            hipLaunchKernelGGL((k_mupdate_dot<TK, TK, D, N, T>), dim3(nbx), dim3(kBlock), 0, c_->stream, c_->n_int,
-                               c_->n_p1, (const TK*)V, nc, j + 1, (const double*)h1, (const T*)wk, wj, part,
-                               (const double*)sig2dev);
-          else
-            hipLaunchKernelGGL((k_mupdate_dot<TK, TK, D, N>), dim3(nbx), dim3(kBlock), 0, c_->stream, c_->n_int,
-                               c_->n_p1, (const TK*)V, nc, j + 1, (const double*)h1, (const TK*)wj, wj, part,
-                               (const double*)sig2dev);
+          auto go = [&](auto NMc) {
+            constexpr int NM = decltype(NMc)::value;
+            if (wk)
+              hipLaunchKernelGGL((k_mupdate_dot<TK, TK, D, N, T, 0, TK, NM>), dim3(nbx), dim3(kBlock), 0, c_->stream,
+                                 c_->n_int, c_->n_p1, (const TK*)V, nc, j + 1, (const double*)h1, (const T*)wk, wj,
+                                 part, (const double*)sig2dev, (TK*)nullptr);
+            else
+              hipLaunchKernelGGL((k_mupdate_dot<TK, TK, D, N, TK, 0, TK, NM>), dim3(nbx), dim3(kBlock), 0, c_->stream,
+                                 c_->n_int, c_->n_p1, (const TK*)V, nc, j + 1, (const double*)h1, (const TK*)wj, wj,
+                                 part, (const double*)sig2dev, (TK*)nullptr);
+          };
+          if (j + 1 <= 8) go(std::integral_constant<int, 8>{});
+          else go(std::integral_constant<int, kFusedMax>{});
           ops::check_launch();
           hipLaunchKernelGGL((k_mdot_fin<N>), dim3(j + 1), dim3(kBlock), 0, c_->stream, nbx, (const double*)part, h2);
         });
