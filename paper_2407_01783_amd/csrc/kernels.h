@@ -306,11 +306,14 @@ __device__ __forceinline__ void load4_cols(const SellIdx& ix, const SliceRef& r,
   }
 }
 
-// acc += sum_j v_j x[c_j][0..W) over the interleaved copy, one lane per row,
-// two groups of four entries in flight per lane.
-template <typename T, int W, typename TM, int F>
+// acc += sum_j v_j x[c_j][off .. off + W/G) over the interleaved copy: G
+// lanes per row, each taking W/G of the row's components (the lanes of a
+// row read the same values and columns); two groups of four entries in
+// flight per lane.
+template <typename T, int W, int G, typename TM, int F>
 __device__ __forceinline__ void sell_row_il_impl(const SellIdx& ix, const SliceRef& r, const TM* __restrict__ vals,
-                                                 const T* __restrict__ x, T (&acc)[W]) {
+                                                 const T* __restrict__ x, int off, T (&acc)[W / G]) {
+  constexpr int WG = W / G;
   const int64_t s0 = r.eb << 6;
   const int lr = static_cast<int>(r.beg - s0);
   const int g4 = r.width >> 2;
@@ -324,19 +327,19 @@ __device__ __forceinline__ void sell_row_il_impl(const SellIdx& ix, const SliceR
       load4_vals<TM, T>(vals, e, v[h]);
       load4_cols<F>(ix, r, g + h, e, c[h]);
     }
-    T xv[H][4][W];
+    T xv[H][4][WG];
 #pragma unroll
     for (int h = 0; h < H; ++h)
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int w = 0; w < W; ++w) xv[h][k][w] = x[(int64_t)c[h][k] * W + w];
+        for (int w = 0; w < WG; ++w) xv[h][k][w] = x[(int64_t)c[h][k] * W + off + w];
 #pragma unroll
     for (int h = 0; h < H; ++h)
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int w = 0; w < W; ++w) acc[w] = fma(v[h][k], xv[h][k][w], acc[w]);
+        for (int w = 0; w < WG; ++w) acc[w] = fma(v[h][k], xv[h][k][w], acc[w]);
   };
   int g = 0;
   for (; g + 2 <= g4; g += 2) groups(std::integral_constant<int, 2>{}, g);
@@ -358,36 +361,37 @@ __device__ __forceinline__ void sell_row_il_impl(const SellIdx& ix, const SliceR
       ct[k] = sell_col_f<F>(ix, r, 4 * g4 + k);
       vt[k] = (T)__builtin_nontemporal_load(vals + r.beg + 64 * (4 * g4 + k));
     }
-  T xv[4][W], xt[3][W];
+  T xv[4][WG], xt[3][WG];
   if (last)
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
-      for (int w = 0; w < W; ++w) xv[k][w] = x[(int64_t)c[k] * W + w];
+      for (int w = 0; w < WG; ++w) xv[k][w] = x[(int64_t)c[k] * W + off + w];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
     if (k < t)
 #pragma unroll
-      for (int w = 0; w < W; ++w) xt[k][w] = x[(int64_t)ct[k] * W + w];
+      for (int w = 0; w < WG; ++w) xt[k][w] = x[(int64_t)ct[k] * W + off + w];
   if (last)
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
-      for (int w = 0; w < W; ++w) acc[w] = fma(v[k], xv[k][w], acc[w]);
+      for (int w = 0; w < WG; ++w) acc[w] = fma(v[k], xv[k][w], acc[w]);
 #pragma unroll
   for (int k = 0; k < 3; ++k)
     if (k < t)
 #pragma unroll
-      for (int w = 0; w < W; ++w) acc[w] = fma(vt[k], xt[k][w], acc[w]);
+      for (int w = 0; w < WG; ++w) acc[w] = fma(vt[k], xt[k][w], acc[w]);
 }
 
-template <typename T, int W, typename TM>
+template <typename T, int W, int G, typename TM>
 __device__ __forceinline__ void sell_row_il(const SellIdx& ix, const TM* __restrict__ vals, const T* __restrict__ x,
-                                            int64_t row, T (&acc)[W]) {
+                                            int64_t row, int sub, T (&acc)[W / G]) {
   const SliceRef r = slice_ref(ix, row);
-  if (r.af) sell_row_il_impl<T, W, TM, 2>(ix, r, vals, x, acc);
-  else if (r.pk) sell_row_il_impl<T, W, TM, 1>(ix, r, vals, x, acc);
-  else sell_row_il_impl<T, W, TM, 0>(ix, r, vals, x, acc);
+  const int off = sub * (W / G);
+  if (r.af) sell_row_il_impl<T, W, G, TM, 2>(ix, r, vals, x, off, acc);
+  else if (r.pk) sell_row_il_impl<T, W, G, TM, 1>(ix, r, vals, x, off, acc);
+  else sell_row_il_impl<T, W, G, TM, 0>(ix, r, vals, x, off, acc);
 }
 
 // B rows (pressure vertex): acc[r] = sum_j sum_c B^c_j u[col_j][r][c]
@@ -543,7 +547,7 @@ __device__ __forceinline__ void expand_parts(const double (&pg)[W / G], int sub,
 // ----------------------------------------------------------- SpMV kernels
 
 // y = a * (S x) + b * yin   (yin may alias y; ignored when b == 0)
-// IL (G = 1): ix and vals are the four-slot interleaved copies.
+// IL: ix and vals are the four-slot interleaved copies.
 template <typename T, int W, int G, typename TM = T, bool IL = false>
 __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
                                                  const T* __restrict__ x, T* y, T a, const T* yin, T b) {
@@ -552,7 +556,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, SellIdx ix, cons
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    if constexpr (IL) sell_row_il<T, W, TM>(ix, vals, x, row, acc);
+    if constexpr (IL) sell_row_il<T, W, G, TM>(ix, vals, x, row, sub, acc);
     else sell_row<T, W, G, TM, (W / G == 1 ? 16 : W / G <= 2 ? 8 : 4)>(ix, vals, x, row, sub, acc);
     const int64_t o = row * W + sub * WG;
     // yin may alias y: every load of the row is issued before its stores
@@ -1146,7 +1150,7 @@ struct QSum {
 // First step with a bfloat16 direction out:  q0 = theta_inv r (not stored),
 // res = r - (S D^{-1}) q0, q1 = bf16(c1 q0 + c2 res), z (+)= dinv (q0 + q1);
 // ACC = 2 leaves z to the closing step (no z, no dinv).
-// IL (G = 1): ix and vals are the four-slot interleaved copies.
+// IL: ix and vals are the four-slot interleaved copies.
 template <typename TM, int W, int ACC, int G, int U = 8, bool IL = false>
 __global__ __launch_bounds__(kBlock) void k_cheb_first_qb(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
                                                           const float* __restrict__ r, const float* __restrict__ dinv,
@@ -1158,7 +1162,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first_qb(int64_t nrows, SellIdx
     float acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
-    if constexpr (IL) sell_row_il<float, W, TM>(ix, vals, r, row, acc);
+    if constexpr (IL) sell_row_il<float, W, G, TM>(ix, vals, r, row, sub, acc);
     else sell_row<float, W, G, TM, (W / G >= 8 ? 4 : U)>(ix, vals, r, row, sub, acc);
     const float di = ACC == 2 ? 0.f : dinv[row];
     const int64_t o = row * W + sub * WG, oq = row * WP + sub * WG;

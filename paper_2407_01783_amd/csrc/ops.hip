@@ -245,11 +245,14 @@ void spmv_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, int W, const 
   dispatch_w(W, [&](auto Wc) {
     constexpr int WW = decltype(Wc)::value;
     // the FP32 velocity product (K_gamma in the FGMRES cycle) on the
-    // interleaved copy of A_II, one lane per row
+    // interleaved copy of A_II, G lanes per row
     if constexpr (std::is_same<T, float>::value && std::is_same<TM, float>::value) {
-      if (G == 1 && &S == &c->sA && c->vel_il && c->A32i.p && (const void*)vals == c->A32.p) {
-        hipLaunchKernelGGL((k_spmv<T, WW, 1, TM, true>), dim3(grid_full(S.nrows)), dim3(kBlock), 0, c->stream,
-                           S.nrows, vel_il_idx(c), c->A32i.as<const float>(), x, y, (T)(a * ms), yin, b);
+      if (&S == &c->sA && c->vel_il && c->A32i.p && (const void*)vals == c->A32.p) {
+        with_g<WW>(G, [&](auto Gc) {
+          constexpr int GG = decltype(Gc)::value;
+          hipLaunchKernelGGL((k_spmv<T, WW, GG, TM, true>), dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0,
+                             c->stream, S.nrows, vel_il_idx(c), c->A32i.as<const float>(), x, y, (T)(a * ms), yin, b);
+        });
         il = true;
         return;
       }
@@ -592,14 +595,12 @@ void cheb_first_hb(stokes_ctx* c, int W, const float* r, const float* dinv, floa
     wp = bf_width<WW>();
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
-      if constexpr (GG == 1) {
-        if (c->vel_il && c->AD16i.p) {  // the four-slot interleaved copies
-          auto kern = zw ? k_cheb_first_qb<_Float16, WW, 0, 1, 8, true> : k_cheb_first_qb<_Float16, WW, 2, 1, 8, true>;
-          hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows)), dim3(kBlock), 0, c->stream, S.nrows, vel_il_idx(c),
-                             (const _Float16*)c->AD16i.as<_Float16>(), r, dinv, theta_inv, q1, res, z, c1, c2);
-          il = true;
-          return;
-        }
+      if (c->vel_il && c->AD16i.p) {  // the four-slot interleaved copies
+        auto kern = zw ? k_cheb_first_qb<_Float16, WW, 0, GG, 8, true> : k_cheb_first_qb<_Float16, WW, 2, GG, 8, true>;
+        hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows, vel_il_idx(c),
+                           (const _Float16*)c->AD16i.as<_Float16>(), r, dinv, theta_inv, q1, res, z, c1, c2);
+        il = true;
+        return;
       }
       auto kern = zw ? k_cheb_first_qb<_Float16, WW, 0, GG> : k_cheb_first_qb<_Float16, WW, 2, GG>;
       hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows, S.idx(),
