@@ -235,6 +235,41 @@ def test_gram_cgs2_matches_three_pass_cgs2(gpu_lib, monkeypatch, precision, opts
     assert _rel(outs["1"][0], outs["0"][0]) <= 1e-9 and _rel(outs["1"][1], outs["0"][1]) <= 1e-9
 
 
+@pytest.mark.parametrize("degree,nrhs", [(3, 1), (4, 2), (9, 1), (16, 1)])
+def test_deferred_chebyshev_sum_matches_carried_iterate(gpu_lib, monkeypatch, degree, nrhs):
+    """The velocity Chebyshev polynomial with the iterate formed by its last
+    step (the default) and with the iterate carried through every step
+    (STOKES_CHEB_DEFER=0) is the same polynomial summed in another order:
+    op 10 agrees to bfloat16 rounding, and mixed coupled solves with fixed
+    inner operators of this degree take the same number of outer
+    iterations and match the oracle."""
+    from paper_2407_01783_amd import inputs
+    kw = dict(dim=3, n=6, seed=5, mu=1e-2, alpha=150.0)
+    S = _oracle(**kw)
+    fs = np.stack([inputs.fourier_forcing(S.mesh.p2coords, inputs.forcing_seed(5, k)) for k in range(nrhs)])
+    rng = np.random.default_rng(9)
+    outs = {}
+    for dflag in ("0", "1"):
+        monkeypatch.setenv("STOKES_CHEB_DEFER", dflag)
+        P = _problem(**kw)
+        if not outs:
+            x = rng.standard_normal(nrhs * 3 * P.n_p2)
+        y = P.apply(10, torch.tensor(x, device="cuda"), precision=1, nrhs=nrhs).cpu().numpy()
+        u, p, info = P.solve(torch.tensor(fs, device="cuda"), method="coupled", precision=1, rtol=1e-10,
+                             inner_mode=1, cheb_degree=degree, max_outer=3000, max_refine=40)
+        print(f"defer={dflag} degree={degree}: {info}", flush=True)
+        assert info["status"] == 0, info
+        outs[dflag] = (y, u.cpu().numpy(), p.cpu().numpy(), info["outer_iters"])
+        del P
+    # op 10 (degree 6): the same bfloat16 directions, the iterate summed in another order
+    assert _rel(outs["1"][0], outs["0"][0]) <= 1e-5
+    assert abs(outs["1"][3] - outs["0"][3]) <= max(1, outs["0"][3] // 10)
+    for b in range(nrhs):
+        U, Pp = S.solve(*S.rhs(fs[b]))
+        for k in ("0", "1"):
+            assert _rel(outs[k][1][b], S.full_velocity(U)) <= 1e-8 and _rel(outs[k][2][b], Pp) <= 1e-8
+
+
 def test_set_mu_then_mixed_solve_matches_oracle(gpu_lib):
     """set_mu rebuilds the FP32 and half-precision copies and their four-slot
     interleaved forms (read by the velocity Chebyshev and by K_gamma): a
