@@ -135,12 +135,16 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ pa
 // of 64 scattered W-vectors into a few contiguous segments per column; the
 // summation order of every component is the same for every G.
 //
-// Column indices come in one of two forms per slice (SellIdx): packed --
-// slot j of the slice holds a base column plus an 8-bit lane offset, so a
-// lane reads one byte per entry -- or plain 32-bit columns where a slot
-// spreads over more than 256 columns.  The rows of a wavefront always lie
-// in one slice (an aligned group of 64 / G rows), so the slice index is read
-// from the first active lane and the form is a uniform branch.
+// Column indices come in one of three forms per slice (SellIdx): computed
+// (affine) -- slot j of lane l is base_j + l, plus a jump from a break lane
+// on, from two words per slot that every lane reads alike (scalar loads) --;
+// packed -- slot j of the slice holds a base column plus an 8-bit lane
+// offset, so a lane reads one byte per entry -- or plain 32-bit columns
+// where a slot spreads over more than 256 columns.  Every walker takes the
+// computed form where the slice has it (the packed offsets stay valid for
+// it too).  The rows of a wavefront always lie in one slice (an aligned
+// group of 64 / G rows), so the slice index is read from the first active
+// lane and the form is a uniform branch.
 //
 // Entries of a row are walked U at a time (U = 4; 8 when a lane carries two
 // components, 16 when it carries one) so that 2U matrix loads and U W/G
@@ -186,18 +190,10 @@ __device__ __forceinline__ int32_t sell_col_f(const SellIdx& ix, const SliceRef&
     return __builtin_nontemporal_load(ix.cols + r.beg + 64 * j);
 }
 
-template <bool PK>
-__device__ __forceinline__ int32_t sell_col(const SellIdx& ix, const SliceRef& r, int j) {
-  if constexpr (PK)
-    return ix.cbase[r.eb + j] + static_cast<int32_t>(__builtin_nontemporal_load(ix.cdel + r.beg + 64 * j));
-  else
-    return __builtin_nontemporal_load(ix.cols + r.beg + 64 * j);
-}
-
 // acc += sum_j v_j x[c_j][sub W/G ...]; DS: v_j is multiplied by ds[c_j]
 // Groups of U entries, then groups of 4 (U > 4) and single entries for the
 // rest of the row, so short rows keep several loads in flight too.
-template <typename T, int W, int G, typename TM, bool PK, bool DS, int U = 4>
+template <typename T, int W, int G, typename TM, int F, bool DS, int U = 4>
 __device__ __forceinline__ void sell_row_impl(const SellIdx& ix, const SliceRef& r, const TM* __restrict__ vals,
                                               const T* __restrict__ xs, const T* __restrict__ ds,
                                               T (&acc)[W / G]) {
@@ -208,7 +204,7 @@ __device__ __forceinline__ void sell_row_impl(const SellIdx& ix, const SliceRef&
     T v[UU];
 #pragma unroll
     for (int u = 0; u < UU; ++u) {
-      c[u] = sell_col<PK>(ix, r, j + u);
+      c[u] = sell_col_f<F>(ix, r, j + u);
       v[u] = (T)__builtin_nontemporal_load(vals + r.beg + 64 * (j + u));
     }
     if constexpr (DS) {
@@ -241,11 +237,13 @@ __device__ __forceinline__ void sell_row(const SellIdx& ix, const TM* __restrict
   const SliceRef r = slice_ref(ix, row);
   const T* __restrict__ xs = x + sub * (W / G);
   if (ds) {
-    if (r.pk) sell_row_impl<T, W, G, TM, true, true, U>(ix, r, vals, xs, ds, acc);
-    else sell_row_impl<T, W, G, TM, false, true, U>(ix, r, vals, xs, ds, acc);
+    if (r.af) sell_row_impl<T, W, G, TM, 2, true, U>(ix, r, vals, xs, ds, acc);
+    else if (r.pk) sell_row_impl<T, W, G, TM, 1, true, U>(ix, r, vals, xs, ds, acc);
+    else sell_row_impl<T, W, G, TM, 0, true, U>(ix, r, vals, xs, ds, acc);
   } else {
-    if (r.pk) sell_row_impl<T, W, G, TM, true, false, U>(ix, r, vals, xs, ds, acc);
-    else sell_row_impl<T, W, G, TM, false, false, U>(ix, r, vals, xs, ds, acc);
+    if (r.af) sell_row_impl<T, W, G, TM, 2, false, U>(ix, r, vals, xs, ds, acc);
+    else if (r.pk) sell_row_impl<T, W, G, TM, 1, false, U>(ix, r, vals, xs, ds, acc);
+    else sell_row_impl<T, W, G, TM, 0, false, U>(ix, r, vals, xs, ds, acc);
   }
 }
 
@@ -396,7 +394,7 @@ __device__ __forceinline__ void sell_row_il(const SellIdx& ix, const TM* __restr
 
 // B rows (pressure vertex): acc[r] = sum_j sum_c B^c_j u[col_j][r][c]
 // (entries walked two at a time to keep more loads in flight)
-template <typename T, int D, int NRB, bool PK>
+template <typename T, int D, int NRB, int F>
 __device__ __forceinline__ void sell_row_B_impl(const SellIdx& ix, const SliceRef& rf, const T* __restrict__ vals,
                                                 const T* __restrict__ u, T (&acc)[NRB]) {
   constexpr int U = 2;
@@ -407,7 +405,7 @@ __device__ __forceinline__ void sell_row_B_impl(const SellIdx& ix, const SliceRe
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int64_t k = rf.beg + 64 * (j + q);
-      c[q] = sell_col<PK>(ix, rf, j + q);
+      c[q] = sell_col_f<F>(ix, rf, j + q);
 #pragma unroll
       for (int d = 0; d < D; ++d) b[q][d] = __builtin_nontemporal_load(vals + k * D + d);
     }
@@ -424,7 +422,7 @@ __device__ __forceinline__ void sell_row_B_impl(const SellIdx& ix, const SliceRe
   }
   for (; j < rf.width; ++j) {
     const int64_t k = rf.beg + 64 * j;
-    const int32_t c = sell_col<PK>(ix, rf, j);
+    const int32_t c = sell_col_f<F>(ix, rf, j);
     T b[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) b[d] = __builtin_nontemporal_load(vals + k * D + d);
@@ -440,8 +438,9 @@ template <typename T, int D, int NRB>
 __device__ __forceinline__ void sell_row_B(const SellIdx& ix, const T* __restrict__ vals, const T* __restrict__ u,
                                            int64_t row, T (&acc)[NRB]) {
   const SliceRef rf = slice_ref(ix, row);
-  if (rf.pk) sell_row_B_impl<T, D, NRB, true>(ix, rf, vals, u, acc);
-  else sell_row_B_impl<T, D, NRB, false>(ix, rf, vals, u, acc);
+  if (rf.af) sell_row_B_impl<T, D, NRB, 2>(ix, rf, vals, u, acc);
+  else if (rf.pk) sell_row_B_impl<T, D, NRB, 1>(ix, rf, vals, u, acc);
+  else sell_row_B_impl<T, D, NRB, 0>(ix, rf, vals, u, acc);
 }
 
 // value plane d (runtime, d < D) of a small register array
@@ -456,7 +455,7 @@ __device__ __forceinline__ T plane(const T (&b)[D], int d) {
 // B^T rows (interior velocity node): acc[r][c] = sum_j B^c_j p[col_j][r];
 // with G lanes per row, lane `sub` owns components sub W/G .. (sub+1) W/G - 1
 // of the W = D NRB outputs (component w is rhs w / D, plane w mod D).
-template <typename T, int D, int NRB, int G, bool PK>
+template <typename T, int D, int NRB, int G, int F>
 __device__ __forceinline__ void sell_row_Bt_impl(const SellIdx& ix, const SliceRef& rf, const T* __restrict__ vals,
                                                  const T* __restrict__ p, int sub, T (&acc)[D * NRB / G]) {
   constexpr int WG = D * NRB / G;
@@ -474,7 +473,7 @@ __device__ __forceinline__ void sell_row_Bt_impl(const SellIdx& ix, const SliceR
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int64_t k = rf.beg + 64 * (j + q);
-      c[q] = sell_col<PK>(ix, rf, j + q);
+      c[q] = sell_col_f<F>(ix, rf, j + q);
 #pragma unroll
       for (int d = 0; d < D; ++d) b[q][d] = __builtin_nontemporal_load(vals + k * D + d);
     }
@@ -489,7 +488,7 @@ __device__ __forceinline__ void sell_row_Bt_impl(const SellIdx& ix, const SliceR
   }
   for (; j < rf.width; ++j) {
     const int64_t k = rf.beg + 64 * j;
-    const int32_t c = sell_col<PK>(ix, rf, j);
+    const int32_t c = sell_col_f<F>(ix, rf, j);
     T b[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) b[d] = __builtin_nontemporal_load(vals + k * D + d);
@@ -503,8 +502,9 @@ template <typename T, int D, int NRB, int G = 1>
 __device__ __forceinline__ void sell_row_Bt(const SellIdx& ix, const T* __restrict__ vals, const T* __restrict__ p,
                                             int64_t row, int sub, T (&acc)[D * NRB / G]) {
   const SliceRef rf = slice_ref(ix, row);
-  if (rf.pk) sell_row_Bt_impl<T, D, NRB, G, true>(ix, rf, vals, p, sub, acc);
-  else sell_row_Bt_impl<T, D, NRB, G, false>(ix, rf, vals, p, sub, acc);
+  if (rf.af) sell_row_Bt_impl<T, D, NRB, G, 2>(ix, rf, vals, p, sub, acc);
+  else if (rf.pk) sell_row_Bt_impl<T, D, NRB, G, 1>(ix, rf, vals, p, sub, acc);
+  else sell_row_Bt_impl<T, D, NRB, G, 0>(ix, rf, vals, p, sub, acc);
 }
 
 #define GRID_STRIDE_ROWS(row, nrows)                                                      \
@@ -580,7 +580,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, SellIdx ix, cons
 // of the group (each exchange adds the same two values in both lanes, so all
 // E lanes hold the same bits).  A wavefront holds 64 / E consecutive rows
 // starting at a multiple of 64 / E, so they share one slice.
-template <typename T, int W, int E, typename TM, bool PK, bool DS, int U>
+template <typename T, int W, int E, typename TM, int F, bool DS, int U>
 __device__ __forceinline__ void sell_row_es_impl(const SellIdx& ix, const SliceRef& r, const TM* __restrict__ vals,
                                                  const T* __restrict__ x, const T* __restrict__ ds, int sub,
                                                  T (&acc)[W]) {
@@ -590,7 +590,7 @@ __device__ __forceinline__ void sell_row_es_impl(const SellIdx& ix, const SliceR
     T v[UU];
 #pragma unroll
     for (int u = 0; u < UU; ++u) {
-      c[u] = sell_col<PK>(ix, r, j + E * u);
+      c[u] = sell_col_f<F>(ix, r, j + E * u);
       v[u] = (T)__builtin_nontemporal_load(vals + r.beg + 64 * (j + E * u));
     }
     if constexpr (DS) {
@@ -622,11 +622,13 @@ __device__ __forceinline__ void sell_row_es(const SellIdx& ix, const TM* __restr
   constexpr int U = W <= 2 ? 8 : 4;
   const SliceRef r = slice_ref(ix, row);
   if (ds) {
-    if (r.pk) sell_row_es_impl<T, W, E, TM, true, true, U>(ix, r, vals, x, ds, sub, acc);
-    else sell_row_es_impl<T, W, E, TM, false, true, U>(ix, r, vals, x, ds, sub, acc);
+    if (r.af) sell_row_es_impl<T, W, E, TM, 2, true, U>(ix, r, vals, x, ds, sub, acc);
+    else if (r.pk) sell_row_es_impl<T, W, E, TM, 1, true, U>(ix, r, vals, x, ds, sub, acc);
+    else sell_row_es_impl<T, W, E, TM, 0, true, U>(ix, r, vals, x, ds, sub, acc);
   } else {
-    if (r.pk) sell_row_es_impl<T, W, E, TM, true, false, U>(ix, r, vals, x, ds, sub, acc);
-    else sell_row_es_impl<T, W, E, TM, false, false, U>(ix, r, vals, x, ds, sub, acc);
+    if (r.af) sell_row_es_impl<T, W, E, TM, 2, false, U>(ix, r, vals, x, ds, sub, acc);
+    else if (r.pk) sell_row_es_impl<T, W, E, TM, 1, false, U>(ix, r, vals, x, ds, sub, acc);
+    else sell_row_es_impl<T, W, E, TM, 0, false, U>(ix, r, vals, x, ds, sub, acc);
   }
 #pragma unroll
   for (int o = E / 2; o >= 1; o /= 2)
@@ -1025,7 +1027,7 @@ __device__ __forceinline__ float bf_word(uint32_t u, int hi) {
   return __uint_as_float(hi ? (u & 0xFFFF0000u) : (u << 16));
 }
 
-template <int W, int G, typename TM, bool PK, int U>
+template <int W, int G, typename TM, int F, int U>
 __device__ __forceinline__ void sell_row_bq_impl(const SellIdx& ix, const SliceRef& r, const TM* __restrict__ vals,
                                                  const uint16_t* __restrict__ xq, int off, float (&acc)[W / G]) {
   constexpr int WG = W / G, WP = bf_width<W>();
@@ -1036,7 +1038,7 @@ __device__ __forceinline__ void sell_row_bq_impl(const SellIdx& ix, const SliceR
     float v[UU];
 #pragma unroll
     for (int u = 0; u < UU; ++u) {
-      c[u] = sell_col<PK>(ix, r, j + u);
+      c[u] = sell_col_f<F>(ix, r, j + u);
       v[u] = (float)__builtin_nontemporal_load(vals + r.beg + 64 * (j + u));
     }
     if constexpr (Raw::kOn) {
@@ -1211,8 +1213,9 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step_qb(int64_t nrows, SellIdx 
         else if (rf.pk) sell_row_bq4_impl<W, G, 1>(ix, rf, vals, q, sub * WG, acc);
         else sell_row_bq4_impl<W, G, 0>(ix, rf, vals, q, sub * WG, acc);
       } else {
-        if (rf.pk) sell_row_bq_impl<W, G, TM, true, UB>(ix, rf, vals, q, sub * WG, acc);
-        else sell_row_bq_impl<W, G, TM, false, UB>(ix, rf, vals, q, sub * WG, acc);
+        if (rf.af) sell_row_bq_impl<W, G, TM, 2, UB>(ix, rf, vals, q, sub * WG, acc);
+        else if (rf.pk) sell_row_bq_impl<W, G, TM, 1, UB>(ix, rf, vals, q, sub * WG, acc);
+        else sell_row_bq_impl<W, G, TM, 0, UB>(ix, rf, vals, q, sub * WG, acc);
       }
     }
     // res_in may alias res_out: load the whole row before any store
@@ -1333,7 +1336,7 @@ __device__ __forceinline__ constexpr int sym_index(int a, int b) {
   return a <= b ? a * D - a * (a - 1) / 2 + (b - a) : b * D - b * (b - 1) / 2 + (a - b);
 }
 
-template <typename T, int D, int NRB, bool PK>
+template <typename T, int D, int NRB, int F>
 __device__ __forceinline__ void sell_row_blk_impl(const SellIdx& ix, const SliceRef& rf, const T* __restrict__ vals,
                                                   const T* __restrict__ x, int64_t row, T (&acc)[D * NRB]) {
   constexpr int W = D * NRB, DD = D * (D + 1) / 2;
@@ -1345,7 +1348,7 @@ __device__ __forceinline__ void sell_row_blk_impl(const SellIdx& ix, const Slice
     T v[U][DD], xv[U][W];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      c[q] = sell_col<PK>(ix, rf, j + q);
+      c[q] = sell_col_f<F>(ix, rf, j + q);
 #pragma unroll
       for (int e = 0; e < DD; ++e) v[q][e] = __builtin_nontemporal_load(vrow + (int64_t)(j + q) * 64 * DD + 64 * e);
     }
@@ -1364,7 +1367,7 @@ __device__ __forceinline__ void sell_row_blk_impl(const SellIdx& ix, const Slice
             acc[r * D + a] = fma(v[q][sym_index<D>(a, b)], xv[q][r * D + b], acc[r * D + a]);
   }
   for (; j < rf.width; ++j) {
-    const int32_t c = sell_col<PK>(ix, rf, j);
+    const int32_t c = sell_col_f<F>(ix, rf, j);
     T v[DD];
 #pragma unroll
     for (int e = 0; e < DD; ++e) v[e] = __builtin_nontemporal_load(vrow + (int64_t)j * 64 * DD + 64 * e);
@@ -1382,8 +1385,9 @@ template <typename T, int D, int NRB>
 __device__ __forceinline__ void sell_row_blk(const SellIdx& ix, const T* __restrict__ vals, const T* __restrict__ x,
                                              int64_t row, T (&acc)[D * NRB]) {
   const SliceRef rf = slice_ref(ix, row);
-  if (rf.pk) sell_row_blk_impl<T, D, NRB, true>(ix, rf, vals, x, row, acc);
-  else sell_row_blk_impl<T, D, NRB, false>(ix, rf, vals, x, row, acc);
+  if (rf.af) sell_row_blk_impl<T, D, NRB, 2>(ix, rf, vals, x, row, acc);
+  else if (rf.pk) sell_row_blk_impl<T, D, NRB, 1>(ix, rf, vals, x, row, acc);
+  else sell_row_blk_impl<T, D, NRB, 0>(ix, rf, vals, x, row, acc);
 }
 
 // y = a * (A x) + b * yin with the block operator (yin may alias y)

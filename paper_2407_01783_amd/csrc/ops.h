@@ -60,7 +60,7 @@ void check_launch();
 // padded entry, `planes` of them, and the index structure it reads), each
 // streamed vector once per pass and each gathered vector once.
 inline void count_bytes(stokes_ctx* c, double b) { c->abytes += b; }
-inline double op_bytes(const Sell& S, double value_size, bool affine = false) {
+inline double op_bytes(const Sell& S, double value_size, bool affine = true) {
   return double(S.nnz_pad) * S.planes * value_size + (affine ? S.idx_bytes_af : S.idx_bytes);
 }
 // stream-ordered device copy and zero fill, counted

@@ -271,7 +271,7 @@ void spmv_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, int W, const 
   });
   check_launch();
   // operator, x gathered, y written (and yin read)
-  count_bytes(c, op_bytes(S, sizeof(TM), il && c->vel_af) + double(S.ncols) * W * sizeof(T) +
+  count_bytes(c, op_bytes(S, sizeof(TM), !il || c->vel_af) + double(S.ncols) * W * sizeof(T) +
                      double(S.nrows) * W * sizeof(T) * (yin ? 2 : 1));
 }
 }  // namespace
@@ -334,7 +334,7 @@ void velop(stokes_ctx* c, int nrb, const T* x, T* y, T a, const T* yin, T b) {
   check_launch();
   // dim x dim blocks per entry, x gathered, y written (and yin read)
   const double W = double(c->dim) * nrb;
-  count_bytes(c, double(c->sA.nnz_pad) * c->dim * c->dim * sizeof(T) + c->sA.idx_bytes +
+  count_bytes(c, double(c->sA.nnz_pad) * c->dim * c->dim * sizeof(T) + c->sA.idx_bytes_af +
                      double(c->n_int) * W * sizeof(T) * (yin ? 3 : 2));
 }
 
@@ -348,7 +348,7 @@ void momentum(stokes_ctx* c, int nrb, const T* u, const T* p, const T* extra, T*
                          p, extra, y, sgn, yin);
     });
     check_launch();
-    count_bytes(c, double(c->sA.nnz_pad) * c->dim * c->dim * sizeof(T) + c->sA.idx_bytes +
+    count_bytes(c, double(c->sA.nnz_pad) * c->dim * c->dim * sizeof(T) + c->sA.idx_bytes_af +
                        op_bytes(c->sBt, sizeof(T)) + double(c->n_p1) * nrb * sizeof(T) +
                        double(c->n_int) * c->dim * nrb * sizeof(T) * (2 + (extra ? 1 : 0) + (yin ? 1 : 0)));
     return;
@@ -610,7 +610,7 @@ void cheb_first_hb(stokes_ctx* c, int W, const float* r, const float* dinv, floa
   check_launch();
   // half values, r gathered; res (floats) and q1 (bfloat16) written; dinv
   // read and z written unless deferred
-  count_bytes(c, op_bytes(S, 2, il && c->vel_af) +
+  count_bytes(c, op_bytes(S, 2, !il || c->vel_af) +
                      double(S.nrows) * (4.0 * (2.0 * W) + 2.0 * wp + (zw ? 4.0 * (W + 1.0) : 0.0)));
 }
 
@@ -663,7 +663,7 @@ void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const f
   const double vec = zm == 0   ? 4.0 * (W * 4.0 + 1.0) + 2.0 * 2.0 * wp
                      : zm == 1 ? 4.0 * (W * 2.0) + 2.0 * 2.0 * wp
                                : 4.0 * (W * 3.0 + 1.0) + 2.0 * wp * (1.0 + fa.n);
-  const double bytes = op_bytes(S, 2, il && c->vel_af) + double(S.nrows) * vec;
+  const double bytes = op_bytes(S, 2, !il || c->vel_af) + double(S.nrows) * vec;
   count_bytes(c, bytes);
   if (timed) prof_end(c, bytes);
 }
