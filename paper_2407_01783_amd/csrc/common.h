@@ -217,9 +217,9 @@ struct stokes_ctx {
   stokes::DevBuf AD16i, cdel_i, cols_i;      // four-slot interleaved AD16 and sA column indices (bfloat16 step)
   stokes::DevBuf A32i;                       // four-slot interleaved A32 (FP32 velocity product of K_gamma)
   int vel_il = 1;                            // the bfloat16 Chebyshev step reads the interleaved copies
-  int vel_af = 1;
-  int cheb_defer = 1;
-  int gram_cgs2 = 1;   // FGMRES: the CGS2 second projection from the basis Gram matrix (one pass fewer)  // bfloat16 velocity Chebyshev: sum the directions in a closing step (z not carried)                            // ... and computes the columns of affine slots
+  int vel_af = 1;                            // ... and computes the columns of affine slots
+  int cheb_defer = 1;                        // bfloat16 velocity Chebyshev: sum the directions in a closing step (z not carried)
+  int gram_cgs2 = 1;                         // FGMRES: the CGS2 second projection from the basis Gram matrix (one pass fewer)
   stokes::DevBuf AB64, AB32;                 // strain: [nnz_pad][dim*dim] blocks alpha M + mu (L + D)
   stokes::DevBuf B64, B32, Bt64, Bt32;       // [nnz_pad][dim]
   stokes::DevBuf MQ64, MQ32, LQ64, LQ32, XQ64, XQ32;  // XQ = M_Q + L_Q
