@@ -1165,6 +1165,7 @@ void assemble_ctx(stokes_ctx* c) {
   // right-hand side: no change); on smaller ones the blocks only cost
   // (cube64: 11.64 -> 11.94 ms with 4-plane blocks).
   std::vector<int32_t> interior;
+  std::vector<int32_t> h_rperm;  // slice schedule of the gathering kernels (empty: slice order)
   {
     const int64_t nK = n2 - 2;  // interior planes (3D) or lines (2D)
     std::vector<int64_t> slab_lo(9);
@@ -1183,9 +1184,57 @@ void assemble_ctx(stokes_ctx* c) {
       ++start[bucket[v] + 1];
     }
     for (size_t k = 0; k + 1 < start.size(); ++k) start[k + 1] += start[k];
+    const std::vector<int64_t> bbeg = start;  // bucket b holds rows [bbeg[b], bbeg[b + 1])
     interior.resize(start.back());
     for (int64_t v = 0; v < m.n_p2; ++v)
       if (!m.p2_bnd[v]) interior[start[bucket[v]]++] = static_cast<int32_t>(v);
+    // Slice schedule.  A kernel walking the rows in order finishes one type
+    // of a block before the next, and every type gathers the neighbours of
+    // all types: the gathered vectors of the whole block (plus halo) must
+    // stay in the XCD's L2 until the last type.  Launching the slices of an
+    // eighth sorted by (block, relative position inside the slice's type
+    // bucket, type) walks the types side by side, so a node's value is
+    // gathered by all its neighbour rows within a few lattice lines.  Only
+    // the launch order changes: each row is still computed once, by the
+    // same arithmetic.  Types alternate in runs of `chunk` slices (64 by
+    // default, on meshes whose plane exceeds 2^15 nodes, where a block's
+    // gathered vectors outgrow the L2); only products with at least
+    // kSchedMinW values per row use it (Sell::idx).
+    const int64_t chunk = c->slice_sched >= 0 ? c->slice_sched : (plane > (int64_t(1) << 15) ? 64 : 0);
+    const bool sched = chunk > 0;
+    const int64_t nint = static_cast<int64_t>(interior.size()), nsl = (nint + 63) / 64;
+    if (sched && nsl > 0) {
+      h_rperm.resize(nsl);
+      const int64_t xn = ((nint + 7) / 8 + 63) / 64 * 64;  // rows per eighth (XCD_ROWS_G)
+      std::vector<std::pair<std::pair<int64_t, double>, std::pair<int, int32_t>>> keys;
+      for (int64_t e = 0; e < 8; ++e) {
+        const int64_t s0 = std::min(nsl, e * xn / 64);
+        int64_t s1 = std::min(nsl, (e + 1) * xn / 64);
+        if (s1 == nsl && nint % 64 != 0) {  // the partial last slice keeps its place
+          h_rperm[nsl - 1] = static_cast<int32_t>(nsl - 1);
+          --s1;
+        }
+        keys.clear();
+        for (int64_t s = s0; s < s1; ++s) {
+          const int64_t b = bucket[interior[64 * s]];
+          // runs of `chunk` slices of one type: the position of the run's first slice
+          const int64_t sb = std::max<int64_t>(s0, bbeg[b] / 64);
+          const int64_t r0 = 64 * (sb + (s - sb) / chunk * chunk);
+          const double frac = double(r0 + 32 - bbeg[b]) / double(std::max<int64_t>(1, bbeg[b + 1] - bbeg[b]));
+          keys.push_back({{b / ntypes, frac}, {static_cast<int>(b % ntypes), static_cast<int32_t>(s)}});
+        }
+        std::stable_sort(keys.begin(), keys.end());
+        for (int64_t t = s0; t < s1; ++t) h_rperm[t] = keys[t - s0].second.second;
+      }
+      // a permutation inside every eighth (checked: the kernels trust it)
+      std::vector<char> seen(nsl, 0);
+      for (int64_t t = 0; t < nsl; ++t) {
+        const int64_t s = h_rperm[t];
+        if (s < 0 || s >= nsl || seen[s] || s * 64 / xn != t * 64 / xn)
+          throw Error(STOKES_ERR_STATE, "slice schedule is not a permutation inside the eighths");
+        seen[s] = 1;
+      }
+    }
   }
   // stencil slots: offsets reach 2 (P2/P1, units h / 2) or 6 (P3/P2, h / 6)
   SellSlots slots_p2p2, slots_p2p1, slots_p1p2;
@@ -1312,12 +1361,22 @@ void assemble_ctx(stokes_ctx* c) {
   std::iota(p1_rows.begin(), p1_rows.end(), 0);
   std::iota(p1_ident.begin(), p1_ident.end(), 0);
   build_sell(P2full, c->h_int2nat, c->h_nat2int, nullptr, 1, c->sA, &slots_p2p2);
+  c->rperm.release();
+  if (!h_rperm.empty()) {
+    if (c->sA.nslices != static_cast<int64_t>(h_rperm.size()))
+      throw Error(STOKES_ERR_STATE, "slice schedule does not match the velocity pattern");
+    upload(c->rperm, h_rperm);
+  }
+  c->sA.rperm = c->rperm.as<const int32_t>();
   build_sell(Bfull, p1_rows, c->h_nat2int, nullptr, D, c->sB, &slots_p1p2);
   {
     HostCsr BT, XLpat;
     std::vector<int64_t> tsrc;
     transpose_pattern(Bfull, BT, tsrc);
     build_sell(BT, c->h_int2nat, p1_ident, &tsrc, D, c->sBt, &slots_p2p1);
+    if (c->rperm.p && c->sBt.nslices != c->sA.nslices)
+      throw Error(STOKES_ERR_STATE, "slice schedule does not match the B^T pattern");
+    c->sBt.rperm = c->rperm.as<const int32_t>();
     // B_I Lambda_V^-1 B_I^T: shared interior P2 columns only
     product_pattern(Bfull, BT, c->h_nat2int, XLpat);
     up_csr(XLpat, c->xl);

@@ -67,7 +67,13 @@ struct SellIdx {
   // [2 per slot] affine slots: column of lane l = base + l + (l >= brk ? jump : 0),
   // stored as (base, brk | jump << 8); null: kernels read the packed offsets
   const int32_t* cmeta = nullptr;
+  // [nslices] slice schedule of the gathering kernels (XCD_ROWS_G): the t-th
+  // slice of an eighth of the rows in launch order is rperm[t], a slice of
+  // the same eighth; null: slice order
+  const int32_t* rperm = nullptr;
 };
+
+constexpr int kSchedMinW = 12;  // narrowest product (values per row) launched in the slice schedule
 
 struct Sell {
   int64_t nrows = 0, nslices = 0, nnz = 0, nnz_pad = 0;
@@ -81,9 +87,14 @@ struct Sell {
   DevBuf cols;          // int32 [nnz_pad]
   DevBuf src;           // int32 [nnz_pad] source entry in the assembled CSR (-1 = pad)
   DevBuf cbase, cdel, pk, cmeta;
-  SellIdx idx() const {
+  const int32_t* rperm = nullptr;  // slice schedule (not owned; the velocity-row patterns share one)
+  // the index as a kernel with W values per row reads it: the slice schedule
+  // only for W >= kSchedMinW (narrower products lose more to the lookup
+  // before each wavefront's first load than they gain in L2 reuse)
+  SellIdx idx(int W = 0) const {
     return SellIdx{slice_ptr.as<const int64_t>(), cols.as<const int32_t>(), cbase.as<const int32_t>(),
-                   cdel.as<const uint8_t>(), pk.as<const int32_t>(), cmeta.as<const int32_t>()};
+                   cdel.as<const uint8_t>(), pk.as<const int32_t>(), cmeta.as<const int32_t>(),
+                   W >= kSchedMinW ? rperm : nullptr};
   }
 };
 
@@ -237,6 +248,8 @@ struct stokes_ctx {
   // coarse levels P^T A P
   stokes::MgHier mgq, mgx;
   int mg_smooth_degree = 2, mg_coarse_degree = 24;
+  int slice_sched = -1;                 // > 0: interleave the row types in runs of this many slices (wide gathering kernels); -1: by size
+  stokes::DevBuf rperm;                 // that schedule over the interior (velocity) rows
   int zblock = -1;                       // lattice planes per block of the interior row order (0: whole slab, -1: by size)
   int mg_es = 1;                        // pressure-MG lanes per row: 1 by level size, -1 timed, 0 one lane, 2-16 fixed
   int64_t mg_dense_max = 1500;          // largest level solved densely

@@ -517,7 +517,11 @@ __device__ __forceinline__ void sell_row_Bt(const SellIdx& ix, const T* __restri
 // x-gathers then stay in one L2.  Rows of an eighth are strided over its
 // workgroups.  G lanes per row: thread t of the eighth serves row t / G as
 // lane `sub` = t mod G of its group (G divides the block size).
-#define XCD_ROWS_G(row, sub, nrows, G)                                                     \
+// PERM (the index's slice schedule, may be null): the t-th 64-row slice of an
+// eighth in launch order is slice PERM[t], a permutation inside the eighth
+// (SellIdx::rperm); a wavefront's rows lie in one slice, so the lookup is a
+// uniform load.
+#define XCD_ROWS_G(row, sub, nrows, G, PERM)                                                \
   const int64_t xg_ = (gridDim.x % 8 == 0) ? gridDim.x / 8 : gridDim.x;                   \
   const int64_t xx_ = (gridDim.x % 8 == 0) ? blockIdx.x % 8 : 0;                          \
   const int64_t xi_ = (gridDim.x % 8 == 0) ? blockIdx.x / 8 : blockIdx.x;                 \
@@ -525,9 +529,11 @@ __device__ __forceinline__ void sell_row_Bt(const SellIdx& ix, const T* __restri
   const int64_t xb_ = xx_ * xn_;                                                          \
   const int64_t xe_ = xb_ + xn_ < (nrows) ? xb_ + xn_ : (nrows);                          \
   const int sub = (int)(threadIdx.x % (G));                                               \
-  for (int64_t row = xb_ + (xi_ * blockDim.x + threadIdx.x) / (G); row < xe_; row += xg_ * blockDim.x / (G))
+  const int32_t* const xp_ = (PERM);                                                      \
+  for (int64_t xr_ = xb_ + (xi_ * blockDim.x + threadIdx.x) / (G); xr_ < xe_; xr_ += xg_ * blockDim.x / (G)) \
+    if (const int64_t row = xp_ ? ((int64_t)xp_[__builtin_amdgcn_readfirstlane((int)(xr_ >> 6))] << 6) + (xr_ & 63) : xr_; true)
 
-#define XCD_ROWS(row, nrows) XCD_ROWS_G(row, sub_unused_ [[maybe_unused]], nrows, 1)
+#define XCD_ROWS(row, nrows, PERM) XCD_ROWS_G(row, sub_unused_ [[maybe_unused]], nrows, 1, PERM)
 
 // Row-group mapping without the XCD partition (streaming kernels).
 #define GRID_STRIDE_ROWS_G(row, sub, nrows, G)                                             \
@@ -552,7 +558,7 @@ template <typename T, int W, int G, typename TM = T, bool IL = false>
 __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
                                                  const T* __restrict__ x, T* y, T a, const T* yin, T b) {
   constexpr int WG = W / G;
-  XCD_ROWS_G(row, sub, nrows, G) {
+  XCD_ROWS_G(row, sub, nrows, G, ix.rperm) {
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
@@ -642,7 +648,7 @@ __device__ __forceinline__ void sell_row_es(const SellIdx& ix, const TM* __restr
 template <typename T, int W, int E, typename TM = T>
 __global__ __launch_bounds__(kBlock) void k_spmv_es(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
                                                     const T* __restrict__ x, T* y, T a, const T* yin, T b) {
-  XCD_ROWS_G(row, sub, nrows, E) {
+  XCD_ROWS_G(row, sub, nrows, E, ix.rperm) {
     T acc[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = 0;
@@ -662,7 +668,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first_es(int64_t nrows, SellIdx
                                                           T ms, const T* __restrict__ r, const T* __restrict__ dinv,
                                                           T theta_inv, T* __restrict__ d1, T* __restrict__ res,
                                                           T* __restrict__ z, T c1, T c2) {
-  XCD_ROWS_G(row, sub, nrows, E) {
+  XCD_ROWS_G(row, sub, nrows, E, ix.rperm) {
     T acc[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = 0;
@@ -688,7 +694,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step_es(int64_t nrows, SellIdx 
                                                          T ms, const T* __restrict__ d, T* __restrict__ dn,
                                                          const T* res_in, T* res_out, T* __restrict__ z,
                                                          const T* __restrict__ dinv, T c1, T c2) {
-  XCD_ROWS_G(row, sub, nrows, E) {
+  XCD_ROWS_G(row, sub, nrows, E, ix.rperm) {
     T acc[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = 0;
@@ -723,7 +729,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t nrows, SellIdx ix,
   double part[WG];
 #pragma unroll
   for (int w = 0; w < WG; ++w) part[w] = 0;
-  XCD_ROWS_G(row, sub, nrows, G) {
+  XCD_ROWS_G(row, sub, nrows, G, ix.rperm) {
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
@@ -826,7 +832,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(int64_t nrows, SellIdx ix,
   double part[WG];
 #pragma unroll
   for (int w = 0; w < WG; ++w) part[w] = 0;
-  XCD_ROWS_G(row, sub, nrows, G) {
+  XCD_ROWS_G(row, sub, nrows, G, ix.rperm) {
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
@@ -870,7 +876,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t nrows, SellIdx ix
                                                        T* __restrict__ d1, T* __restrict__ res, T* __restrict__ z,
                                                        T c1, T c2) {
   constexpr int WG = W / G;
-  XCD_ROWS_G(row, sub, nrows, G) {
+  XCD_ROWS_G(row, sub, nrows, G, ix.rperm) {
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
@@ -904,7 +910,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first_q(int64_t nrows, SellIdx 
                                                          T theta_inv, T* __restrict__ q1, T* __restrict__ res,
                                                          T* __restrict__ z, T c1, T c2) {
   constexpr int WG = W / G;
-  XCD_ROWS_G(row, sub, nrows, G) {
+  XCD_ROWS_G(row, sub, nrows, G, ix.rperm) {
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
@@ -933,7 +939,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step_q(int64_t nrows, SellIdx i
                                                         T* __restrict__ qn, const T* res_in, T* res_out,
                                                         T* __restrict__ z, const T* __restrict__ dinv, T c1, T c2) {
   constexpr int WG = W / G;
-  XCD_ROWS_G(row, sub, nrows, G) {
+  XCD_ROWS_G(row, sub, nrows, G, ix.rperm) {
     const int64_t o = row * W + sub * WG;
     T acc[WG];
 #pragma unroll
@@ -1160,7 +1166,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first_qb(int64_t nrows, SellIdx
                                                           float* __restrict__ res, float* __restrict__ z, float c1,
                                                           float c2) {
   constexpr int WG = W / G, WP = bf_width<W>();
-  XCD_ROWS_G(row, sub, nrows, G) {
+  XCD_ROWS_G(row, sub, nrows, G, ix.rperm) {
     float acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
@@ -1198,7 +1204,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step_qb(int64_t nrows, SellIdx 
                                                          const float* __restrict__ dinv, float c1, float c2,
                                                          QSum fin) {
   constexpr int WG = W / G, WP = bf_width<W>();
-  XCD_ROWS_G(row, sub, nrows, G) {
+  XCD_ROWS_G(row, sub, nrows, G, ix.rperm) {
     const int64_t o = row * W + sub * WG;
     float acc[WG];
 #pragma unroll
@@ -1260,7 +1266,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step_qb(int64_t nrows, SellIdx 
 template <typename T, int D, int NRB>
 __global__ __launch_bounds__(kBlock) void k_B(int64_t nrows, SellIdx ix, const T* __restrict__ vals,
                                               const T* __restrict__ u, T* pout, T a, const T* pin, T b) {
-  XCD_ROWS(row, nrows) {
+  XCD_ROWS(row, nrows, ix.rperm) {
     T acc[NRB];
 #pragma unroll
     for (int r = 0; r < NRB; ++r) acc[r] = 0;
@@ -1279,7 +1285,7 @@ __global__ __launch_bounds__(kBlock) void k_Bt(int64_t nrows, SellIdx ix, const 
                                                const T* __restrict__ p, const T* __restrict__ scale, T* uout,
                                                T a, const T* uin, T b, T* __restrict__ btout) {
   constexpr int W = D * NRB, WG = W / G;
-  XCD_ROWS_G(row, sub, nrows, G) {
+  XCD_ROWS_G(row, sub, nrows, G, ix.rperm) {
     T acc[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = 0;
@@ -1306,7 +1312,7 @@ __global__ __launch_bounds__(kBlock) void k_momentum(int64_t nrows, SellIdx ixA,
                                                      const T* __restrict__ u, const T* __restrict__ p,
                                                      const T* __restrict__ extra, T* y, T sgn, const T* yin) {
   constexpr int W = D * NRB, WG = W / G;
-  XCD_ROWS_G(row, sub, nrows, G) {
+  XCD_ROWS_G(row, sub, nrows, G, ixA.rperm) {
     T acc[WG], bt[WG];
 #pragma unroll
     for (int w = 0; w < WG; ++w) acc[w] = bt[w] = 0;
@@ -1395,7 +1401,7 @@ template <typename T, int D, int NRB>
 __global__ __launch_bounds__(kBlock) void k_spmv_blk(int64_t nrows, SellIdx ix, const T* __restrict__ vals,
                                                      const T* __restrict__ x, T* y, T a, const T* yin, T b) {
   constexpr int W = D * NRB;
-  XCD_ROWS(row, nrows) {
+  XCD_ROWS(row, nrows, ix.rperm) {
     T acc[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = 0;
@@ -1415,7 +1421,7 @@ __global__ __launch_bounds__(kBlock) void k_momentum_blk(int64_t nrows, SellIdx 
                                                          const T* __restrict__ u, const T* __restrict__ p,
                                                          const T* __restrict__ extra, T* y, T sgn, const T* yin) {
   constexpr int W = D * NRB;
-  XCD_ROWS(row, nrows) {
+  XCD_ROWS(row, nrows, ixA.rperm) {
     T acc[W], bt[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) acc[w] = bt[w] = 0;

@@ -171,8 +171,8 @@ bool with_e(int E, F&& f) {
 }
 
 // Index of the four-slot interleaved copy of the velocity pattern.
-SellIdx vel_il_idx(stokes_ctx* c) {
-  SellIdx ix = c->sA.idx();
+SellIdx vel_il_idx(stokes_ctx* c, int W) {
+  SellIdx ix = c->sA.idx(W);
   ix.cdel = c->cdel_i.as<const uint8_t>();
   ix.cols = c->cols_i.as<const int32_t>();
   if (!c->vel_af) ix.cmeta = nullptr;  // read the packed offsets of affine slots too
@@ -251,7 +251,7 @@ void spmv_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, int W, const 
         with_g<WW>(G, [&](auto Gc) {
           constexpr int GG = decltype(Gc)::value;
           hipLaunchKernelGGL((k_spmv<T, WW, GG, TM, true>), dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0,
-                             c->stream, S.nrows, vel_il_idx(c), c->A32i.as<const float>(), x, y, (T)(a * ms), yin, b);
+                             c->stream, S.nrows, vel_il_idx(c, WW), c->A32i.as<const float>(), x, y, (T)(a * ms), yin, b);
         });
         il = true;
         return;
@@ -260,13 +260,13 @@ void spmv_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, int W, const 
     if (S.es > 1 && with_e<WW>(S.es, [&](auto Ec) {
           constexpr int EE = decltype(Ec)::value;
           hipLaunchKernelGGL((k_spmv_es<T, WW, EE, TM>), dim3(grid_full(S.nrows * EE)), dim3(kBlock), 0, c->stream,
-                             S.nrows, S.idx(), vals, x, y, (T)(a * ms), yin, b);
+                             S.nrows, S.idx(WW), vals, x, y, (T)(a * ms), yin, b);
         }))
       return;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       hipLaunchKernelGGL((k_spmv<T, WW, GG, TM>), dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream,
-                         S.nrows, S.idx(), vals, x, y, (T)(a * ms), yin, b);
+                         S.nrows, S.idx(WW), vals, x, y, (T)(a * ms), yin, b);
     });
   });
   check_launch();
@@ -309,7 +309,7 @@ void Btmul(stokes_ctx* c, int nrb, const T* p, const T* scale, T* u, T a, const 
     with_g<D * N>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       hipLaunchKernelGGL((k_Bt<T, D, N, GG>), dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows,
-                         S.idx(), btvals<T>(c).template as<T>(), p, scale, u,
+                         S.idx(D * N), btvals<T>(c).template as<T>(), p, scale, u,
                          a, uin, b, btout);
     });
   });
@@ -329,7 +329,7 @@ void velop(stokes_ctx* c, int nrb, const T* x, T* y, T a, const T* yin, T b) {
   dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
     constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
     hipLaunchKernelGGL((k_spmv_blk<T, D, N>), dim3(grid_full(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int,
-                       c->sA.idx(), abvals<T>(c).template as<T>(), x, y, a, yin, b);
+                       c->sA.idx(D * N), abvals<T>(c).template as<T>(), x, y, a, yin, b);
   });
   check_launch();
   // dim x dim blocks per entry, x gathered, y written (and yin read)
@@ -344,7 +344,7 @@ void momentum(stokes_ctx* c, int nrb, const T* u, const T* p, const T* extra, T*
     dispatch_dn(c->dim, nrb, [&](auto Dc, auto Nc) {
       constexpr int D = decltype(Dc)::value, N = decltype(Nc)::value;
       hipLaunchKernelGGL((k_momentum_blk<T, D, N>), dim3(grid_full(c->n_int)), dim3(kBlock), 0, c->stream, c->n_int,
-                         c->sA.idx(), abvals<T>(c).template as<T>(), c->sBt.idx(), btvals<T>(c).template as<T>(), u,
+                         c->sA.idx(D * N), abvals<T>(c).template as<T>(), c->sBt.idx(D * N), btvals<T>(c).template as<T>(), u,
                          p, extra, y, sgn, yin);
     });
     check_launch();
@@ -359,7 +359,7 @@ void momentum(stokes_ctx* c, int nrb, const T* u, const T* p, const T* extra, T*
     with_g<D * N>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       hipLaunchKernelGGL((k_momentum<T, D, N, GG>), dim3(grid_full(c->n_int * GG)), dim3(kBlock), 0, c->stream,
-                         c->n_int, c->sA.idx(), avals<T>(c).template as<T>(), c->sBt.idx(),
+                         c->n_int, c->sA.idx(D * N), avals<T>(c).template as<T>(), c->sBt.idx(D * N),
                          btvals<T>(c).template as<T>(), u, p, extra, y, sgn, yin);
     });
   });
@@ -459,7 +459,7 @@ void cg_spmv(stokes_ctx* c, int64_t nrows, const Sell* S, const T* vals, int W, 
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       hipLaunchKernelGGL((k_cg_spmv<T, WW, GG>), dim3(grid_for(nrows * GG)), dim3(kBlock), 0, c->stream, nrows,
-                         S ? S->idx() : SellIdx{}, vals, z,
+                         S ? S->idx(WW) : SellIdx{}, vals, z,
                          extra, q, p, sc, cps, nsys, partials(c));
       finish<WW>(c, nrows * GG, FIN_ALPHA, WW, sc, cps, nsys, 0, nullptr);
     });
@@ -525,7 +525,7 @@ void cheb_first_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, const T
     if (!scaled && S.es > 1 && with_e<WW>(S.es, [&](auto Ec) {
           constexpr int EE = decltype(Ec)::value;
           auto kern = accumulate ? k_cheb_first_es<T, WW, 1, EE, TM> : k_cheb_first_es<T, WW, 0, EE, TM>;
-          hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows * EE)), dim3(kBlock), 0, c->stream, S.nrows, S.idx(), vals,
+          hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows * EE)), dim3(kBlock), 0, c->stream, S.nrows, S.idx(WW), vals,
                              ms, r, dinv, theta_inv, d1, res, z, c1, c2);
         }))
       return;
@@ -533,7 +533,7 @@ void cheb_first_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, const T
       constexpr int GG = decltype(Gc)::value;
       const int nb = grid_full(S.nrows * GG);
       auto go = [&](auto kern, const TM* v) {
-        hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, S.nrows, S.idx(), v, ms, r, dinv, theta_inv,
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, S.nrows, S.idx(WW), v, ms, r, dinv, theta_inv,
                            d1, res, z, c1, c2);
       };
       if (scaled) {
@@ -575,7 +575,7 @@ void cheb_first_h(stokes_ctx* c, int W, const float* r, const float* dinv, float
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       hipLaunchKernelGGL((k_cheb_first_q<float, _Float16, WW, 0, GG, 8>), dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0,
-                         c->stream, S.nrows, S.idx(),
+                         c->stream, S.nrows, S.idx(WW),
                          (const _Float16*)c->AD16.as<_Float16>(), r, dinv, theta_inv, q1, res, z, c1, c2);
     });
   });
@@ -597,13 +597,13 @@ void cheb_first_hb(stokes_ctx* c, int W, const float* r, const float* dinv, floa
       constexpr int GG = decltype(Gc)::value;
       if (c->vel_il && c->AD16i.p) {  // the four-slot interleaved copies
         auto kern = zw ? k_cheb_first_qb<_Float16, WW, 0, GG, 8, true> : k_cheb_first_qb<_Float16, WW, 2, GG, 8, true>;
-        hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows, vel_il_idx(c),
+        hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows, vel_il_idx(c, WW),
                            (const _Float16*)c->AD16i.as<_Float16>(), r, dinv, theta_inv, q1, res, z, c1, c2);
         il = true;
         return;
       }
       auto kern = zw ? k_cheb_first_qb<_Float16, WW, 0, GG> : k_cheb_first_qb<_Float16, WW, 2, GG>;
-      hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows, S.idx(),
+      hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows, S.idx(WW),
                          (const _Float16*)c->AD16.as<_Float16>(), r, dinv, theta_inv, q1, res, z, c1, c2);
     });
   });
@@ -639,7 +639,7 @@ void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const f
           auto kern = zm == 0   ? k_cheb_step_qb<_Float16, WW, GG, 8, true, 0>
                       : zm == 1 ? k_cheb_step_qb<_Float16, WW, GG, 8, true, 1>
                                 : k_cheb_step_qb<_Float16, WW, GG, 8, true, 2>;
-          hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, S.nrows, vel_il_idx(c),
+          hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, S.nrows, vel_il_idx(c, WW),
                              (const _Float16*)c->AD16i.as<_Float16>(), q, qn, res_in, res_out, z, dinv, c1, c2, fa);
           il = true;
           return;
@@ -648,7 +648,7 @@ void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const f
       auto kern = zm == 0   ? k_cheb_step_qb<_Float16, WW, GG, 8, false, 0>
                   : zm == 1 ? k_cheb_step_qb<_Float16, WW, GG, 8, false, 1>
                             : k_cheb_step_qb<_Float16, WW, GG, 8, false, 2>;
-      hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, S.nrows, S.idx(),
+      hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, S.nrows, S.idx(WW),
                          (const _Float16*)c->AD16.as<_Float16>(), q, qn, res_in, res_out, z, dinv, c1, c2, fa);
     });
   });
@@ -678,7 +678,7 @@ void cheb_step_h(stokes_ctx* c, int W, const float* q, float* qn, const float* r
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows, S.idx(),
+        hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows, S.idx(WW),
                            (const _Float16*)c->AD16.as<_Float16>(), q, qn, res_in, res_out, z, dinv, c1, c2);
       };
       go(k_cheb_step_q<float, _Float16, WW, GG, 8>);
@@ -701,13 +701,13 @@ void cheb_step_hs(stokes_ctx* c, const Sell& S, const _Float16* vals, float ms, 
     if (S.es > 1 && with_e<WW>(S.es, [&](auto Ec) {
           constexpr int EE = decltype(Ec)::value;
           hipLaunchKernelGGL((k_cheb_step_es<float, WW, EE, _Float16>), dim3(grid_full(S.nrows * EE)), dim3(kBlock),
-                             0, c->stream, S.nrows, S.idx(), vals, ms, d, dn, res_in, res_out, z, dinv, c1, c2);
+                             0, c->stream, S.nrows, S.idx(WW), vals, ms, d, dn, res_in, res_out, z, dinv, c1, c2);
         }))
       return;
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
       hipLaunchKernelGGL((k_cheb_step<float, WW, 0, GG, _Float16>), dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0,
-                         c->stream, S.nrows, S.idx(), vals, ms, d, dn, res_in, res_out, z, dinv, c1, c2,
+                         c->stream, S.nrows, S.idx(WW), vals, ms, d, dn, res_in, res_out, z, dinv, c1, c2,
                          (const float*)nullptr, (Scalars*)nullptr, 1, 0, 0, partials(c));
     });
   });
@@ -727,7 +727,7 @@ void cheb_step(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* d, T
     if (!rvec && S.es > 1 && with_e<WW>(S.es, [&](auto Ec) {
           constexpr int EE = decltype(Ec)::value;
           hipLaunchKernelGGL((k_cheb_step_es<T, WW, EE>), dim3(grid_full(S.nrows * EE)), dim3(kBlock), 0, c->stream,
-                             S.nrows, S.idx(), vals, (T)1, d, dn, res_in, res_out, z, dinv, c1, c2);
+                             S.nrows, S.idx(WW), vals, (T)1, d, dn, res_in, res_out, z, dinv, c1, c2);
         }))
       return;
     with_g<WW>(G, [&](auto Gc) {
@@ -735,12 +735,12 @@ void cheb_step(stokes_ctx* c, const Sell& S, const T* vals, int W, const T* d, T
       const int nb = grid_for(S.nrows * GG);
       if (rvec) {
         hipLaunchKernelGGL((k_cheb_step<T, WW, 1, GG>), dim3(nb), dim3(kBlock), 0, c->stream, S.nrows,
-                           S.idx(), vals, (T)1, d, dn, res_in, res_out, z, dinv, c1,
+                           S.idx(WW), vals, (T)1, d, dn, res_in, res_out, z, dinv, c1,
                            c2, rvec, sc, cps, nsys, first, partials(c));
         finish<WW>(c, S.nrows * GG, FIN_RHO, WW, sc, cps, nsys, first, nullptr);
       } else
         hipLaunchKernelGGL((k_cheb_step<T, WW, 0, GG>), dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows,
-                           S.idx(), vals, (T)1, d, dn, res_in, res_out, z, dinv, c1,
+                           S.idx(WW), vals, (T)1, d, dn, res_in, res_out, z, dinv, c1,
                            c2, rvec, sc, cps, nsys, first, partials(c));
     });
   });

@@ -152,6 +152,48 @@ def test_entry_split_levels_match_one_lane_per_row(gpu_lib, monkeypatch):
             assert err <= (1e-12 if prec == 0 else 1e-4), (E, r, prec, err)
 
 
+@pytest.mark.parametrize("dim,n,nrhs,lanes", [(3, 10, 4, 0), (3, 8, 8, 4), (2, 40, 6, 0), (3, 9, 1, 0)])
+def test_slice_schedule_bitwise_equal(gpu_lib, monkeypatch, dim, n, nrhs, lanes):
+    """The gathering kernels launched over the velocity-row slices in a
+    type-interleaved schedule (STOKES_SLICE_SCHED=k: runs of k slices of one
+    type; products with 12 or more values per row use it, so the 3D
+    single right-hand-side case checks that it is off) compute every row
+    once by the same arithmetic: the velocity
+    operators (ops 0, 2, 5, 10) in FP64 and FP32 and a mixed coupled solve
+    are bitwise equal to the slice-order launch, and an FP64 solve with
+    tolerance-driven inner CGs (dot products summed in another order) agrees
+    to the solve tolerance."""
+    from paper_2407_01783_amd import inputs
+    if lanes:
+        monkeypatch.setenv("STOKES_LANES", str(lanes))
+    rng = np.random.default_rng(41)
+    outs = {}
+    for sched in ("0", "1", "5"):
+        monkeypatch.setenv("STOKES_SLICE_SCHED", sched)
+        P = _problem(dim, n, seed=9, mu=0.02, alpha=120.0)
+        if not outs:
+            nu, npr = nrhs * dim * P.n_p2, nrhs * P.n_p1
+            xs = {0: rng.standard_normal(nu), 2: rng.standard_normal(npr), 5: rng.standard_normal(nu + npr),
+                  10: rng.standard_normal(nu)}
+            xy, _ = P.mesh()
+            f = np.stack([inputs.fourier_forcing(xy, inputs.forcing_seed(9, k)) for k in range(nrhs)])
+        ys = [P.apply(op, torch.tensor(x, device="cuda"), precision=prec, nrhs=nrhs).cpu().numpy()
+              for op, x in xs.items() for prec in (0, 1)]
+        u, p, info = P.solve(torch.tensor(f, device="cuda"), method="coupled", precision=1, rtol=1e-8)
+        assert info["status"] == 0, info
+        u64, p64, info64 = P.solve(torch.tensor(f, device="cuda"), method="coupled", precision=0, rtol=1e-10,
+                                   inner_mode=0)
+        assert info64["status"] == 0, info64
+        print(f"sched={sched}: mixed {info['outer_iters']} outer, FP64 TOL {info64['outer_iters']} outer", flush=True)
+        outs[sched] = (ys + [u.cpu().numpy(), p.cpu().numpy()], (u64.cpu().numpy(), p64.cpu().numpy()))
+        del P
+    for k in ("1", "5"):
+        for a, b in zip(outs["0"][0], outs[k][0]):
+            assert np.array_equal(a, b)
+        for a, b in zip(outs["0"][1], outs[k][1]):
+            assert _rel(b, a) <= 1e-8
+
+
 @pytest.mark.parametrize("dim,n,nrhs,lanes", [(3, 6, 1, 1), (3, 5, 8, 4), (2, 16, 1, 1), (2, 12, 4, 2)])
 def test_interleaved_chebyshev_step_bitwise_equal(gpu_lib, monkeypatch, dim, n, nrhs, lanes):
     """The bfloat16 Chebyshev step reading the four-slot interleaved copies of
