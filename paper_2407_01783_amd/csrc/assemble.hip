@@ -704,6 +704,12 @@ struct SellSlots {
   const int32_t* rxyz = nullptr;  // lattice coordinates of the source rows [3 per row]
   const int32_t* cxyz = nullptr;  // ... of the source columns (same units)
   const uint8_t* rcls = nullptr;  // class of a source row (null: 0)
+  // > 0: lattice distance between consecutive nodes of one class along x.
+  // The slots of a class then start with pairs of offsets on one lattice
+  // line `step` apart (adjacent nodes of the column class, hence adjacent
+  // columns), the other offsets after them.
+  int step = 0;
+  bool pair_flags = false;  // count the leading pair groups of affine slices (pk = 2 + 4 groups)
   int nkeys() const { return (2 * R + 1) * (2 * R + 1) * (2 * R + 1); }
   int cls(int64_t r) const { return rcls ? rcls[r] : 0; }
   int key(int64_t r, int32_t c) const {  // -1: outside the reach
@@ -801,9 +807,40 @@ void build_sell(const HostCsr& in, const std::vector<int32_t>& rows_in_order, co
     }
     slot_of.assign(present.size(), -1);
     class_width.assign(ncl, 0);
-    for (int cl = 0; cl < ncl; ++cl)
-      for (int key = 0; key < nk; ++key)
-        if (present[(size_t)cl * nk + key]) slot_of[(size_t)cl * nk + key] = class_width[cl]++;
+    const int wk = 2 * slots->R + 1;
+    for (int cl = 0; cl < ncl; ++cl) {
+      if (slots->step <= 0) {
+        for (int key = 0; key < nk; ++key)
+          if (present[(size_t)cl * nk + key]) slot_of[(size_t)cl * nk + key] = class_width[cl]++;
+        continue;
+      }
+      // Runs: keys of one (dz, dy) line with one dx residue mod step, dx
+      // ascending in steps of `step` (consecutive keys of a run are
+      // adjacent columns).  Every run gives its keys two by two to the
+      // pairs, which take the first slots; the lone keys follow.
+      std::vector<int> paired, lone;
+      for (int zy = 0; zy < wk * wk; ++zy)
+        for (int res = 0; res < slots->step; ++res) {
+          std::vector<int> run;
+          int prev = -1000;
+          auto flush = [&]() {
+            size_t i = 0;
+            for (; i + 1 < run.size(); i += 2) paired.insert(paired.end(), {run[i], run[i + 1]});
+            if (i < run.size()) lone.push_back(run[i]);
+            run.clear();
+          };
+          for (int dxi = 0; dxi < wk; ++dxi) {
+            const int key = zy * wk + dxi, dx = dxi - slots->R;
+            if (!present[(size_t)cl * nk + key] || ((dx % slots->step) + slots->step) % slots->step != res) continue;
+            if (dx - prev != slots->step) flush();
+            run.push_back(key);
+            prev = dx;
+          }
+          flush();
+        }
+      for (int key : paired) slot_of[(size_t)cl * nk + key] = class_width[cl]++;
+      for (int key : lone) slot_of[(size_t)cl * nk + key] = class_width[cl]++;
+    }
   }
   parallel_for(nrows, [&](int64_t b, int64_t e) {
     for (int64_t r = b; r < e; ++r) {
@@ -952,7 +989,16 @@ void build_sell(const HostCsr& in, const std::vector<int32_t>& rows_in_order, co
         meta[j] = static_cast<int32_t>(brk | (jump * 256));
       }
       if (!ok) continue;
-      pk[sl] = 2;
+      int pg = 0;  // leading four-slot groups of two adjacent-node pairs (same break and jump)
+      if (slots && slots->pair_flags)
+        while (4 * (pg + 1) <= w && pg < (1 << 20)) {
+          const int64_t j = 4 * pg;
+          if (base[j + 1] != base[j] + 1 || meta[j + 1] != meta[j] || base[j + 3] != base[j + 2] + 1 ||
+              meta[j + 3] != meta[j + 2])
+            break;
+          ++pg;
+        }
+      pk[sl] = 2 + 4 * pg;
       for (int64_t j = 0; j < w; ++j) {
         cmeta[2 * (sp[sl] / 64 + j)] = base[j];
         cmeta[2 * (sp[sl] / 64 + j) + 1] = meta[j];
@@ -963,11 +1009,11 @@ void build_sell(const HostCsr& in, const std::vector<int32_t>& rows_in_order, co
   double idx_bytes = 0, idx_bytes_af = 0;
   for (int64_t sl = 0; sl < nsl; ++sl) {
     npk += pk[sl] != 0;
-    naf += pk[sl] == 2;
+    naf += (pk[sl] & 3) == 2;
     const double w = double(sp[sl + 1] - sp[sl]) / 64;
     const double packed_or_wide = 12.0 + (pk[sl] ? 64.0 * w + 4.0 * w : 4.0 * 64.0 * w);  // slice offset and form, slots
     idx_bytes += packed_or_wide;
-    idx_bytes_af += pk[sl] == 2 ? 12.0 + 8.0 * w : packed_or_wide;
+    idx_bytes_af += (pk[sl] & 3) == 2 ? 12.0 + 8.0 * w : packed_or_wide;
   }
   out.nrows = nrows;
   out.nslices = nsl;
@@ -1244,6 +1290,10 @@ void assemble_ctx(stokes_ctx* c) {
   slots_p2p1.cxyz = p1xyz.data();
   slots_p1p2.rxyz = p1xyz.data();
   slots_p1p2.cxyz = p2xyz.data();
+  // velocity slots in line order, adjacent-node pairs flagged for the
+  // bfloat16 Chebyshev step (one 16-byte gather per pair)
+  slots_p2p2.step = c->vel_pair ? K * sv : 0;
+  slots_p2p2.pair_flags = c->vel_pair == 1;
   if (K == 3) {
     slots_p2p2.R = slots_p2p1.R = slots_p1p2.R = 6;
     slots_p1p2.nclass = D == 3 ? 8 : 4;

@@ -231,6 +231,7 @@ struct stokes_ctx {
   int vel_af = 1;                            // ... and computes the columns of affine slots
   int cheb_defer = 1;                        // bfloat16 velocity Chebyshev: sum the directions in a closing step (z not carried)
   int gram_cgs2 = 1;                         // FGMRES: the CGS2 second projection from the basis Gram matrix (one pass fewer)
+  int vel_pair = 1;                          // velocity slots in pair order; 1: the bfloat16 step gathers flagged pairs at once (2: order only)
   stokes::DevBuf AB64, AB32;                 // strain: [nnz_pad][dim*dim] blocks alpha M + mu (L + D)
   stokes::DevBuf B64, B32, Bt64, Bt32;       // [nnz_pad][dim]
   stokes::DevBuf MQ64, MQ32, LQ64, LQ32, XQ64, XQ32;  // XQ = M_Q + L_Q

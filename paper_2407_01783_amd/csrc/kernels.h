@@ -155,6 +155,7 @@ struct SliceRef {
   int width;    // slots of the slice
   bool pk;      // packed columns
   bool af;      // affine slots (columns computed from cmeta; packed offsets also valid)
+  int pg;       // leading four-slot groups made of two adjacent-node slot pairs (affine slices)
 };
 
 __device__ __forceinline__ SliceRef slice_ref(const SellIdx& ix, int64_t row) {
@@ -166,13 +167,14 @@ __device__ __forceinline__ SliceRef slice_ref(const SellIdx& ix, int64_t row) {
   r.width = static_cast<int>((ix.sp[s + 1] - s0) >> 6);
   const int form = ix.pk[s];
   r.pk = form != 0;
-  r.af = form == 2 && ix.cmeta != nullptr;
+  r.af = (form & 3) == 2 && ix.cmeta != nullptr;
+  r.pg = r.af ? form >> 2 : 0;
   return r;
 }
 
 // Column of slot j of an affine slice: base + lane, plus the slot's jump from
 // its break lane on (the two words of the slot are the same for every lane:
-// scalar loads).
+// scalar loads).  Meta word: break lane in bits 0-7 (0..64), jump from bit 8.
 __device__ __forceinline__ int32_t affine_col(const SellIdx& ix, const SliceRef& r, int64_t slot) {
   const int lane = static_cast<int>(r.beg - (r.eb << 6));
   const int32_t base = ix.cmeta[2 * slot], meta = ix.cmeta[2 * slot + 1];
@@ -261,6 +263,7 @@ __device__ __forceinline__ void sell_row(const SellIdx& ix, const TM* __restrict
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
 typedef int i32x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4a8_t __attribute__((ext_vector_type(4), aligned(8)));  // 16 bytes at 8-byte alignment
 
 __device__ __forceinline__ float half_bits(uint32_t h) {
   return (float)__builtin_bit_cast(_Float16, static_cast<uint16_t>(h));
@@ -1112,6 +1115,39 @@ __device__ __forceinline__ void sell_row_bq4_impl(const SellIdx& ix, const Slice
   // narrow lanes keep four groups (16 entries) in flight, wide ones two
   constexpr int HG = WG <= 4 ? 4 : 2;
   int g = 0;
+  if constexpr (F == 2 && WP == 4 && WG >= 3) {
+    // 8-byte rows: the leading pair groups (slots 4g, 4g+1 and 4g+2, 4g+3
+    // gather adjacent nodes in every lane) take one 16-byte gather per pair
+    auto pairs = [&](auto Hc, int g0) {
+      constexpr int H = decltype(Hc)::value;
+      int32_t c[H][2];
+      float v[H][4];
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        const int64_t e = s0 + 256 * (int64_t)(g0 + h) + 4 * lr;
+        load4_vals<_Float16, float>(vals, e, v[h]);
+        c[h][0] = affine_col(ix, r, r.eb + 4 * (g0 + h));
+        c[h][1] = affine_col(ix, r, r.eb + 4 * (g0 + h) + 2);
+      }
+      u32x4a8_t u[H][2];
+#pragma unroll
+      for (int h = 0; h < H; ++h)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) u[h][k] = *reinterpret_cast<const u32x4a8_t*>(xq + (int64_t)c[h][k] * 4);
+#pragma unroll
+      for (int h = 0; h < H; ++h)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const uint32_t w0[2] = {u[h][k].x, u[h][k].y}, w1[2] = {u[h][k].z, u[h][k].w};
+#pragma unroll
+          for (int w = 0; w < WG; ++w) acc[w] = fma(v[h][2 * k], bf_word(w0[w / 2], w & 1), acc[w]);
+#pragma unroll
+          for (int w = 0; w < WG; ++w) acc[w] = fma(v[h][2 * k + 1], bf_word(w1[w / 2], w & 1), acc[w]);
+        }
+    };
+    for (; g + 4 <= r.pg; g += 4) pairs(std::integral_constant<int, 4>{}, g);
+    for (; g < r.pg; ++g) pairs(std::integral_constant<int, 1>{}, g);
+  }
   for (; g + HG <= g4; g += HG) groups(std::integral_constant<int, HG>{}, g);
   if constexpr (HG > 2)
     for (; g + 2 <= g4; g += 2) groups(std::integral_constant<int, 2>{}, g);

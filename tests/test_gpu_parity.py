@@ -245,6 +245,35 @@ def test_affine_columns_bitwise_equal(gpu_lib, monkeypatch, dim, n, nrhs):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("n,seed", [(64, 12), (65, 3)])
+def test_paired_gathers_bitwise_equal(gpu_lib, monkeypatch, n, seed):
+    """The velocity slots start with pairs of offsets that gather adjacent
+    nodes; the bfloat16 Chebyshev step with one right-hand side takes each
+    such pair of the leading four-slot groups of an affine slice with one
+    16-byte load (the default).  With the same slot order and the pair
+    groups off (STOKES_VEL_PAIR=2) every slot is gathered on its own.  The
+    same values enter the same sums: apply op 10 and a mixed coupled solve
+    are bitwise equal."""
+    from paper_2407_01783_amd import inputs
+    rng = np.random.default_rng(53)
+    outs = []
+    for pair in ("2", "1"):
+        monkeypatch.setenv("STOKES_VEL_PAIR", pair)
+        P = _problem(3, n, seed=seed, mu=0.02, alpha=150.0)
+        assert P.affine_slices > 0
+        if not outs:
+            x = rng.standard_normal(3 * P.n_p2)
+            xy, _ = P.mesh()
+            f = inputs.fourier_forcing(xy, inputs.forcing_seed(seed))[None]
+        y = P.apply(10, torch.tensor(x, device="cuda"), precision=1).cpu().numpy()
+        u, p, info = P.solve(torch.tensor(f, device="cuda"), method="coupled", precision=1, rtol=1e-8)
+        assert info["status"] == 0, info
+        outs.append((y, u.cpu().numpy(), p.cpu().numpy()))
+        del P
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("precision,opts", [
     (1, dict()),                                                          # the benchmark's fixed inner operators
     (0, dict(inner_mode=0)),                                              # FP64 with inner CGs
