@@ -554,6 +554,7 @@ stokes_status stokes_assemble(const stokes_problem* prob, void* hip_stream, stok
     if (const char* e = std::getenv("STOKES_LANES")) c->force_lanes = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("STOKES_ZBLOCK")) c->zblock = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("STOKES_VEL_PAIR")) c->vel_pair = std::max(0, std::min(2, std::atoi(e)));
+    if (const char* e = std::getenv("STOKES_SLICE_YQ")) c->slice_yq = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("STOKES_SLICE_SCHED")) c->slice_sched = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("STOKES_MG_ES")) {
       const int v = std::atoi(e);

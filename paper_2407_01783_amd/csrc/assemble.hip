@@ -21,6 +21,7 @@
 #include <functional>
 #include <numeric>
 #include <thread>
+#include <tuple>
 
 #include "common.h"
 #include "kernels.h"
@@ -1245,14 +1246,22 @@ void assemble_ctx(stokes_ctx* c) {
     // same arithmetic.  Types alternate in runs of `chunk` slices (64 by
     // default, on meshes whose plane exceeds 2^15 nodes, where a block's
     // gathered vectors outgrow the L2); only products with at least
-    // kSchedMinW values per row use it (Sell::idx).
+    // kSchedMinW values per row use it (Sell::idx).  By default the runs
+    // are whole y chunks (8 per plane) and a slab's blocks are walked
+    // chunk by chunk, so the z neighbours of a node (two planes up or
+    // down) are gathered one block apart instead of a whole block of
+    // planes apart.
     const int64_t chunk = c->slice_sched >= 0 ? c->slice_sched : (plane > (int64_t(1) << 15) ? 64 : 0);
     const bool sched = chunk > 0;
     const int64_t nint = static_cast<int64_t>(interior.size()), nsl = (nint + 63) / 64;
     if (sched && nsl > 0) {
       h_rperm.resize(nsl);
       const int64_t xn = ((nint + 7) / 8 + 63) / 64 * 64;  // rows per eighth (XCD_ROWS_G)
-      std::vector<std::pair<std::pair<int64_t, double>, std::pair<int, int32_t>>> keys;
+      // key: (slab, y chunk, block, type, position, slice) with y chunks
+      // (slice_yq > 0: the blocks of a slab walked per y chunk, so a node's
+      // z neighbours come one block apart), else (block, position, type)
+      std::vector<std::tuple<int64_t, int64_t, int64_t, int, double, int32_t>> keys;
+      const int64_t nyq = c->slice_yq >= 0 ? c->slice_yq : 8;
       for (int64_t e = 0; e < 8; ++e) {
         const int64_t s0 = std::min(nsl, e * xn / 64);
         int64_t s1 = std::min(nsl, (e + 1) * xn / 64);
@@ -1267,10 +1276,27 @@ void assemble_ctx(stokes_ctx* c) {
           const int64_t sb = std::max<int64_t>(s0, bbeg[b] / 64);
           const int64_t r0 = 64 * (sb + (s - sb) / chunk * chunk);
           const double frac = double(r0 + 32 - bbeg[b]) / double(std::max<int64_t>(1, bbeg[b + 1] - bbeg[b]));
-          keys.push_back({{b / ntypes, frac}, {static_cast<int>(b % ntypes), static_cast<int32_t>(s)}});
+          const int64_t grp = b / ntypes;
+          const int ty = static_cast<int>(b % ntypes);
+          if (nyq > 0) {
+            const double fs = double(64 * s + 32 - bbeg[b]) / double(std::max<int64_t>(1, bbeg[b + 1] - bbeg[b]));
+            const int64_t yq = std::min<int64_t>(nyq - 1, std::max<int64_t>(0, static_cast<int64_t>(fs * nyq)));
+            keys.emplace_back(grp / nblk, yq, grp % nblk, ty, fs, static_cast<int32_t>(s));
+          } else {
+            keys.emplace_back(grp, 0, 0, ty, frac, static_cast<int32_t>(s));  // sorted by (block, position, type)
+          }
         }
-        std::stable_sort(keys.begin(), keys.end());
-        for (int64_t t = s0; t < s1; ++t) h_rperm[t] = keys[t - s0].second.second;
+        if (nyq > 0) {
+          std::stable_sort(keys.begin(), keys.end());
+        } else {
+          std::stable_sort(keys.begin(), keys.end(), [](const auto& a, const auto& b) {
+            if (std::get<0>(a) != std::get<0>(b)) return std::get<0>(a) < std::get<0>(b);
+            if (std::get<4>(a) != std::get<4>(b)) return std::get<4>(a) < std::get<4>(b);
+            if (std::get<3>(a) != std::get<3>(b)) return std::get<3>(a) < std::get<3>(b);
+            return std::get<5>(a) < std::get<5>(b);
+          });
+        }
+        for (int64_t t = s0; t < s1; ++t) h_rperm[t] = std::get<5>(keys[t - s0]);
       }
       // a permutation inside every eighth (checked: the kernels trust it)
       std::vector<char> seen(nsl, 0);

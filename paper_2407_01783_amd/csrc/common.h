@@ -249,6 +249,7 @@ struct stokes_ctx {
   // coarse levels P^T A P
   stokes::MgHier mgq, mgx;
   int mg_smooth_degree = 2, mg_coarse_degree = 24;
+  int slice_yq = -1;                    // > 0: the slice schedule walks a slab's blocks per y chunk (this many per plane); -1: 8
   int slice_sched = -1;                 // > 0: interleave the row types in runs of this many slices (wide gathering kernels); -1: by size
   stokes::DevBuf rperm;                 // that schedule over the interior (velocity) rows
   int zblock = -1;                       // lattice planes per block of the interior row order (0: whole slab, -1: by size)

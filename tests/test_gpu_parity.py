@@ -157,8 +157,9 @@ def test_slice_schedule_bitwise_equal(gpu_lib, monkeypatch, dim, n, nrhs, lanes)
     """The gathering kernels launched over the velocity-row slices in a
     type-interleaved schedule (STOKES_SLICE_SCHED=k: runs of k slices of one
     type; products with 12 or more values per row use it, so the 3D
-    single right-hand-side case checks that it is off) compute every row
-    once by the same arithmetic: the velocity
+    single right-hand-side case checks that it is off; STOKES_SLICE_YQ=q
+    walks the blocks of a slab per y chunk) compute every row once by the
+    same arithmetic: the velocity
     operators (ops 0, 2, 5, 10) in FP64 and FP32 and a mixed coupled solve
     are bitwise equal to the slice-order launch, and an FP64 solve with
     tolerance-driven inner CGs (dot products summed in another order) agrees
@@ -168,8 +169,9 @@ def test_slice_schedule_bitwise_equal(gpu_lib, monkeypatch, dim, n, nrhs, lanes)
         monkeypatch.setenv("STOKES_LANES", str(lanes))
     rng = np.random.default_rng(41)
     outs = {}
-    for sched in ("0", "1", "5"):
-        monkeypatch.setenv("STOKES_SLICE_SCHED", sched)
+    for sched in ("0", "1", "5", "5/3"):
+        monkeypatch.setenv("STOKES_SLICE_SCHED", sched.split("/")[0])
+        monkeypatch.setenv("STOKES_SLICE_YQ", sched.split("/")[1] if "/" in sched else "0")
         P = _problem(dim, n, seed=9, mu=0.02, alpha=120.0)
         if not outs:
             nu, npr = nrhs * dim * P.n_p2, nrhs * P.n_p1
@@ -187,7 +189,7 @@ def test_slice_schedule_bitwise_equal(gpu_lib, monkeypatch, dim, n, nrhs, lanes)
         print(f"sched={sched}: mixed {info['outer_iters']} outer, FP64 TOL {info64['outer_iters']} outer", flush=True)
         outs[sched] = (ys + [u.cpu().numpy(), p.cpu().numpy()], (u64.cpu().numpy(), p64.cpu().numpy()))
         del P
-    for k in ("1", "5"):
+    for k in ("1", "5", "5/3"):
         for a, b in zip(outs["0"][0], outs[k][0]):
             assert np.array_equal(a, b)
         for a, b in zip(outs["0"][1], outs[k][1]):
