@@ -524,7 +524,8 @@ def main():
                      "traffic": measured_traffic(args.workload, args.nrhs, args.strain),
                      "kernel": f"k_cheb_step_qb<_Float16,{dim * args.nrhs},G,8,true,1> (velocity-block SELL SpMV: "
                                f"half-precision A_II D^-1 values and computed or packed column offsets read from four-slot "
-                               f"interleaved copies, bfloat16 direction, FP32 residual; a Chebyshev step of the "
+                               f"interleaved copies, bfloat16 direction (adjacent-node slot pairs gathered with one "
+                               f"16-byte load at W = 3), FP32 residual; a Chebyshev step of the "
                                f"deferred sum (the iterate is formed by the closing step); G lanes per row, autotuned)",
                      "bytes_per_launch": bytes_per, "launches": launches,
                      "avg_us": kern_s / launches * 1e6 if launches else None,
