@@ -990,9 +990,11 @@ void build_sell(const HostCsr& in, const std::vector<int32_t>& rows_in_order, co
         meta[j] = static_cast<int32_t>(brk | (jump * 256));
       }
       if (!ok) continue;
-      int pg = 0;  // leading four-slot groups of two adjacent-node pairs (same break and jump)
+      // leading four-slot sub-groups of two adjacent-node pairs (same break
+      // and jump), inside the eight-slot groups of the interleaved half copy
+      int pg = 0;
       if (slots && slots->pair_flags)
-        while (4 * (pg + 1) <= w && pg < (1 << 20)) {
+        while (pg < 2 * (w / 8)) {
           const int64_t j = 4 * pg;
           if (base[j + 1] != base[j] + 1 || meta[j + 1] != meta[j] || base[j + 3] != base[j + 2] + 1 ||
               meta[j + 3] != meta[j + 2])
@@ -1590,32 +1592,35 @@ void assemble_ctx(stokes_ctx* c) {
   HIP_CHECK(hipStreamSynchronize(c->stream));
 }
 
-// Four-slot interleaved copies of the half-precision velocity values and of
-// the velocity pattern's column indices, read by the bfloat16 Chebyshev step.
+// Interleaved copies of the velocity values and of the velocity pattern's
+// column indices: eight-slot groups for the half-precision values read by the
+// bfloat16 Chebyshev steps, four-slot groups for the FP32 values of the
+// velocity product of K_gamma (16 bytes of values per lane and group).
 void build_interleaved(stokes_ctx* c) {
   const Sell& S = c->sA;
   if (!c->vel_il || !c->AD16.p || S.nslices == 0) return;
+  const int64_t* sp = S.slice_ptr.as<int64_t>();
+  auto perm = [&](auto kern, const auto* src, auto* dst) {
+    hipLaunchKernelGGL(kern, dim3(S.nslices), dim3(64), 0, c->stream, S.nslices, sp, src, dst);
+    HIP_CHECK(hipGetLastError());
+  };
   if (!c->AD16i.p) {
     c->AD16i.alloc(S.nnz_pad * sizeof(_Float16));
     if (S.cdel.p) {  // packed slices exist
+      c->cdel_i8.alloc(S.nnz_pad * sizeof(uint8_t));
       c->cdel_i.alloc(S.nnz_pad * sizeof(uint8_t));
-      hipLaunchKernelGGL(k_interleave4<uint8_t>, dim3(S.nslices), dim3(64), 0, c->stream, S.nslices,
-                         S.slice_ptr.as<int64_t>(), S.cdel.as<uint8_t>(), c->cdel_i.as<uint8_t>());
-      HIP_CHECK(hipGetLastError());
+      perm(k_interleave<uint8_t, 8>, S.cdel.as<const uint8_t>(), c->cdel_i8.as<uint8_t>());
+      perm(k_interleave<uint8_t, 4>, S.cdel.as<const uint8_t>(), c->cdel_i.as<uint8_t>());
     }
+    c->cols_i8.alloc(S.nnz_pad * sizeof(int32_t));
     c->cols_i.alloc(S.nnz_pad * sizeof(int32_t));
-    hipLaunchKernelGGL(k_interleave4<int32_t>, dim3(S.nslices), dim3(64), 0, c->stream, S.nslices,
-                       S.slice_ptr.as<int64_t>(), S.cols.as<int32_t>(), c->cols_i.as<int32_t>());
-    HIP_CHECK(hipGetLastError());
+    perm(k_interleave<int32_t, 8>, S.cols.as<const int32_t>(), c->cols_i8.as<int32_t>());
+    perm(k_interleave<int32_t, 4>, S.cols.as<const int32_t>(), c->cols_i.as<int32_t>());
   }
-  hipLaunchKernelGGL(k_interleave4<uint16_t>, dim3(S.nslices), dim3(64), 0, c->stream, S.nslices,
-                     S.slice_ptr.as<int64_t>(), c->AD16.as<uint16_t>(), c->AD16i.as<uint16_t>());
-  HIP_CHECK(hipGetLastError());
+  perm(k_interleave<uint16_t, il_width<_Float16>()>, c->AD16.as<const uint16_t>(), c->AD16i.as<uint16_t>());
   if (c->A32.p) {
     if (!c->A32i.p) c->A32i.alloc(S.nnz_pad * sizeof(float));
-    hipLaunchKernelGGL(k_interleave4<uint32_t>, dim3(S.nslices), dim3(64), 0, c->stream, S.nslices,
-                       S.slice_ptr.as<int64_t>(), c->A32.as<uint32_t>(), c->A32i.as<uint32_t>());
-    HIP_CHECK(hipGetLastError());
+    perm(k_interleave<uint32_t, il_width<float>()>, c->A32.as<const uint32_t>(), c->A32i.as<uint32_t>());
   }
 }
 

@@ -225,7 +225,8 @@ struct stokes_ctx {
   int vel_half = 1;                          // FP32 velocity Chebyshev reads AD16
   int pmg_half = 1;                          // FP32 pressure V-cycles read the levels' half values
   int vel_bf = 1;                            // FP32 velocity Chebyshev keeps its direction q in bfloat16
-  stokes::DevBuf AD16i, cdel_i, cols_i;      // four-slot interleaved AD16 and sA column indices (bfloat16 step)
+  stokes::DevBuf AD16i, cdel_i8, cols_i8;    // eight-slot interleaved AD16 and sA column indices (bfloat16 steps)
+  stokes::DevBuf cdel_i, cols_i;             // four-slot interleaved sA column indices (with A32i)
   stokes::DevBuf A32i;                       // four-slot interleaved A32 (FP32 velocity product of K_gamma)
   int vel_il = 1;                            // the bfloat16 Chebyshev step reads the interleaved copies
   int vel_af = 1;                            // ... and computes the columns of affine slots

@@ -155,7 +155,7 @@ struct SliceRef {
   int width;    // slots of the slice
   bool pk;      // packed columns
   bool af;      // affine slots (columns computed from cmeta; packed offsets also valid)
-  int pg;       // leading four-slot groups made of two adjacent-node slot pairs (affine slices)
+  int pg;       // leading four-slot sub-groups made of two adjacent-node slot pairs (affine slices)
 };
 
 __device__ __forceinline__ SliceRef slice_ref(const SellIdx& ix, int64_t row) {
@@ -249,37 +249,55 @@ __device__ __forceinline__ void sell_row(const SellIdx& ix, const TM* __restrict
   }
 }
 
-// ------------------------------------- four-slot interleaved SELL copies
+// ------------------------------------- interleaved SELL copies
 //
 // A copy of a slice's scalar arrays (values, packed column offsets, 32-bit
-// columns) in which slots 4g .. 4g+3 of row r of a slice starting at entry
-// s0 sit at s0 + 256 g + 4 r + (0..3): one lane reads the four values of a
-// group with one 8- or 16-byte load and their column offsets with one 4-byte
-// load, where the slot-major layout takes one load per entry and array.
-// Slots from 4 floor(width / 4) on keep their slot-major places
-// (s0 + 64 j + r), so the copy is a permutation inside each slice with the
-// same slice pointers and column bases (k_interleave4).  Entries are still
-// taken in slot order: products equal the slot-major ones bit for bit.
+// columns) in which slots IW g .. IW g + IW - 1 of row r of a slice starting
+// at entry s0 sit at s0 + 64 IW g + IW r + (0 .. IW - 1): one lane reads the
+// IW values of a group with one load (16 bytes: IW = 4 for float values,
+// 8 for half values) and their column offsets with one 4- or 8-byte load,
+// where the slot-major layout takes one load per entry and array.  Slots
+// from IW floor(width / IW) on keep their slot-major places (s0 + 64 j + r),
+// so the copy is a permutation inside each slice with the same slice
+// pointers and column bases (k_interleave).  Entries are still taken in slot
+// order: products equal the slot-major ones bit for bit.
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 typedef int i32x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4a8_t __attribute__((ext_vector_type(4), aligned(8)));  // 16 bytes at 8-byte alignment
+
+// slots per interleaved group for values of type TM
+template <typename TM>
+constexpr int il_width() {
+  return sizeof(TM) == 2 ? 8 : 4;
+}
 
 __device__ __forceinline__ float half_bits(uint32_t h) {
   return (float)__builtin_bit_cast(_Float16, static_cast<uint16_t>(h));
 }
 
-// the four values of a group (e = its first entry), as T
-template <typename TM, typename T>
-__device__ __forceinline__ void load4_vals(const TM* __restrict__ vals, int64_t e, T (&v)[4]) {
+// the IW values of a group (e = its first entry), as T
+template <int IW, typename TM, typename T>
+__device__ __forceinline__ void load_vals(const TM* __restrict__ vals, int64_t e, T (&v)[IW]) {
   static_assert(sizeof(TM) == 2 || sizeof(TM) == 4, "half or float values");
-  if constexpr (sizeof(TM) == 2) {
+  if constexpr (sizeof(TM) == 2 && IW == 8) {
+    const u32x4_t vv = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(vals + e));
+    const uint32_t w[4] = {vv.x, vv.y, vv.z, vv.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[2 * k] = (T)half_bits(w[k] & 0xFFFFu);
+      v[2 * k + 1] = (T)half_bits(w[k] >> 16);
+    }
+  } else if constexpr (sizeof(TM) == 2) {
+    static_assert(IW == 4, "half groups of 4 or 8");
     const u32x2_t vv = __builtin_nontemporal_load(reinterpret_cast<const u32x2_t*>(vals + e));
     v[0] = (T)half_bits(vv.x & 0xFFFFu);
     v[1] = (T)half_bits(vv.x >> 16);
     v[2] = (T)half_bits(vv.y & 0xFFFFu);
     v[3] = (T)half_bits(vv.y >> 16);
   } else {
+    static_assert(IW == 4, "float groups of 4");
     const f32x4_t vv = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t*>(vals + e));
     v[0] = (T)vv.x;
     v[1] = (T)vv.y;
@@ -288,98 +306,110 @@ __device__ __forceinline__ void load4_vals(const TM* __restrict__ vals, int64_t 
   }
 }
 
-// the four columns of group g (e = its first entry), in form F (sell_col_f)
-template <int F>
-__device__ __forceinline__ void load4_cols(const SellIdx& ix, const SliceRef& r, int g, int64_t e, int32_t (&c)[4]) {
+// the IW columns of group g (e = its first entry), in form F (sell_col_f)
+template <int IW, int F>
+__device__ __forceinline__ void load_cols(const SellIdx& ix, const SliceRef& r, int g, int64_t e, int32_t (&c)[IW]) {
+  static_assert(IW == 4 || IW == 8, "groups of 4 or 8");
   if constexpr (F == 2) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) c[k] = affine_col(ix, r, r.eb + 4 * g + k);
+    for (int k = 0; k < IW; ++k) c[k] = affine_col(ix, r, r.eb + IW * g + k);
   } else if constexpr (F == 1) {
-    const uint32_t d4 = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(ix.cdel + e));
+    uint32_t d[IW / 4];
+    if constexpr (IW == 4) {
+      d[0] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(ix.cdel + e));
+    } else {
+      const u32x2_t dd = __builtin_nontemporal_load(reinterpret_cast<const u32x2_t*>(ix.cdel + e));
+      d[0] = dd.x;
+      d[1] = dd.y;
+    }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) c[k] = ix.cbase[r.eb + 4 * g + k] + static_cast<int32_t>((d4 >> (8 * k)) & 0xFFu);
+    for (int k = 0; k < IW; ++k)
+      c[k] = ix.cbase[r.eb + IW * g + k] + static_cast<int32_t>((d[k / 4] >> (8 * (k % 4))) & 0xFFu);
   } else {
-    const i32x4_t cc = __builtin_nontemporal_load(reinterpret_cast<const i32x4_t*>(ix.cols + e));
-    c[0] = cc.x;
-    c[1] = cc.y;
-    c[2] = cc.z;
-    c[3] = cc.w;
+#pragma unroll
+    for (int q = 0; q < IW / 4; ++q) {
+      const i32x4_t cc = __builtin_nontemporal_load(reinterpret_cast<const i32x4_t*>(ix.cols + e + 4 * q));
+      c[4 * q] = cc.x;
+      c[4 * q + 1] = cc.y;
+      c[4 * q + 2] = cc.z;
+      c[4 * q + 3] = cc.w;
+    }
   }
 }
 
-// acc += sum_j v_j x[c_j][off .. off + W/G) over the interleaved copy: G
-// lanes per row, each taking W/G of the row's components (the lanes of a
-// row read the same values and columns); two groups of four entries in
-// flight per lane.
+// acc += sum_j v_j x[c_j][off .. off + W/G) over the interleaved copy (IW
+// slots per group, il_width<TM>): G lanes per row, each taking W/G of the
+// row's components (the lanes of a row read the same values and columns);
+// eight entries in flight per lane.
 template <typename T, int W, int G, typename TM, int F>
 __device__ __forceinline__ void sell_row_il_impl(const SellIdx& ix, const SliceRef& r, const TM* __restrict__ vals,
                                                  const T* __restrict__ x, int off, T (&acc)[W / G]) {
-  constexpr int WG = W / G;
+  constexpr int WG = W / G, IW = il_width<TM>(), HG = 8 / IW;
   const int64_t s0 = r.eb << 6;
   const int lr = static_cast<int>(r.beg - s0);
-  const int g4 = r.width >> 2;
+  const int gi = r.width / IW;
   auto groups = [&](auto Hc, int g) {
     constexpr int H = decltype(Hc)::value;
-    int32_t c[H][4];
-    T v[H][4];
+    int32_t c[H][IW];
+    T v[H][IW];
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-      const int64_t e = s0 + 256 * (int64_t)(g + h) + 4 * lr;
-      load4_vals<TM, T>(vals, e, v[h]);
-      load4_cols<F>(ix, r, g + h, e, c[h]);
+      const int64_t e = s0 + 64 * IW * (int64_t)(g + h) + IW * lr;
+      load_vals<IW, TM, T>(vals, e, v[h]);
+      load_cols<IW, F>(ix, r, g + h, e, c[h]);
     }
-    T xv[H][4][WG];
+    T xv[H][IW][WG];
 #pragma unroll
     for (int h = 0; h < H; ++h)
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
+      for (int k = 0; k < IW; ++k)
 #pragma unroll
         for (int w = 0; w < WG; ++w) xv[h][k][w] = x[(int64_t)c[h][k] * W + off + w];
 #pragma unroll
     for (int h = 0; h < H; ++h)
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
+      for (int k = 0; k < IW; ++k)
 #pragma unroll
         for (int w = 0; w < WG; ++w) acc[w] = fma(v[h][k], xv[h][k][w], acc[w]);
   };
   int g = 0;
-  for (; g + 2 <= g4; g += 2) groups(std::integral_constant<int, 2>{}, g);
-  // the last group (if any) and the width mod 4 tail slots (slot-major) in
+  for (; g + HG <= gi; g += HG) groups(std::integral_constant<int, HG>{}, g);
+  // the last group (if any) and the width mod IW tail slots (slot-major) in
   // one round trip: every load first, then the sums in slot order
-  const bool last = g < g4;
-  const int t = r.width - 4 * g4;
+  const bool last = g < gi;
+  const int t = r.width - IW * gi;
   if (!last && t == 0) return;
-  int32_t c[4], ct[3];
-  T v[4], vt[3];
+  int32_t c[IW], ct[IW - 1];
+  T v[IW], vt[IW - 1];
   if (last) {
-    const int64_t e = s0 + 256 * (int64_t)g + 4 * lr;
-    load4_vals<TM, T>(vals, e, v);
-    load4_cols<F>(ix, r, g, e, c);
+    const int64_t e = s0 + 64 * IW * (int64_t)g + IW * lr;
+    load_vals<IW, TM, T>(vals, e, v);
+    load_cols<IW, F>(ix, r, g, e, c);
   }
 #pragma unroll
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < IW - 1; ++k)
     if (k < t) {
-      ct[k] = sell_col_f<F>(ix, r, 4 * g4 + k);
-      vt[k] = (T)__builtin_nontemporal_load(vals + r.beg + 64 * (4 * g4 + k));
+      ct[k] = sell_col_f<F>(ix, r, IW * gi + k);
+      vt[k] = (T)__builtin_nontemporal_load(vals + r.beg + 64 * (IW * gi + k));
     }
-  T xv[4][WG], xt[3][WG];
+  T xv[IW][WG], xt[IW - 1][WG];
   if (last)
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < IW; ++k)
 #pragma unroll
       for (int w = 0; w < WG; ++w) xv[k][w] = x[(int64_t)c[k] * W + off + w];
 #pragma unroll
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < IW - 1; ++k)
     if (k < t)
 #pragma unroll
       for (int w = 0; w < WG; ++w) xt[k][w] = x[(int64_t)ct[k] * W + off + w];
   if (last)
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < IW; ++k)
 #pragma unroll
       for (int w = 0; w < WG; ++w) acc[w] = fma(v[k], xv[k][w], acc[w]);
 #pragma unroll
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < IW - 1; ++k)
     if (k < t)
 #pragma unroll
       for (int w = 0; w < WG; ++w) acc[w] = fma(vt[k], xt[k][w], acc[w]);
@@ -556,7 +586,7 @@ __device__ __forceinline__ void expand_parts(const double (&pg)[W / G], int sub,
 // ----------------------------------------------------------- SpMV kernels
 
 // y = a * (S x) + b * yin   (yin may alias y; ignored when b == 0)
-// IL: ix and vals are the four-slot interleaved copies.
+// IL: ix and vals are the interleaved copies.
 template <typename T, int W, int G, typename TM = T, bool IL = false>
 __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
                                                  const T* __restrict__ x, T* y, T a, const T* yin, T b) {
@@ -1075,85 +1105,93 @@ __device__ __forceinline__ void sell_row_bq_impl(const SellIdx& ix, const SliceR
   for (; j < r.width; ++j) group(std::integral_constant<int, 1>{}, j);
 }
 
-// The bfloat16-direction row over the four-slot interleaved copies (the
-// layout of sell_row_il_impl).
+// The bfloat16-direction row over the interleaved half-precision copies
+// (the layout of sell_row_il_impl, eight slots per group).
 template <int W, int G, int F>
 __device__ __forceinline__ void sell_row_bq4_impl(const SellIdx& ix, const SliceRef& r,
                                                   const _Float16* __restrict__ vals,
                                                   const uint16_t* __restrict__ xq, int off, float (&acc)[W / G]) {
-  constexpr int WG = W / G, WP = bf_width<W>();
+  constexpr int WG = W / G, WP = bf_width<W>(), IW = il_width<_Float16>();
   using Raw = BfRaw<WP, WG>;
   static_assert(Raw::kOn, "interleaved rows take the packed bfloat16 gathers");
   const int64_t s0 = r.eb << 6;
   const int lr = static_cast<int>(r.beg - s0);
-  const int g4 = r.width >> 2;
-  // one group of four slots: values and columns, then the gathers
-  auto load = [&](int g, int32_t (&c)[4], float (&v)[4]) {
-    const int64_t e = s0 + 256 * (int64_t)g + 4 * lr;
-    load4_vals<_Float16, float>(vals, e, v);
-    load4_cols<F>(ix, r, g, e, c);
-  };
+  const int gi = r.width / IW;
+  auto entry = [&](int g) { return s0 + 64 * IW * (int64_t)g + IW * lr; };
   // H groups at a time: values and offsets first, then all their gathers
   auto groups = [&](auto Hc, int g) {
     constexpr int H = decltype(Hc)::value;
-    int32_t c[H][4];
-    float v[H][4];
+    int32_t c[H][IW];
+    float v[H][IW];
 #pragma unroll
-    for (int h = 0; h < H; ++h) load(g + h, c[h], v[h]);
-    uint32_t xr[H][4][Raw::kWords];
+    for (int h = 0; h < H; ++h) {
+      load_vals<IW, _Float16, float>(vals, entry(g + h), v[h]);
+      load_cols<IW, F>(ix, r, g + h, entry(g + h), c[h]);
+    }
+    uint32_t xr[H][IW][Raw::kWords];
 #pragma unroll
     for (int h = 0; h < H; ++h)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) load_bf_raw<WP, WG>(xq, c[h][k], off, xr[h][k]);
+      for (int k = 0; k < IW; ++k) load_bf_raw<WP, WG>(xq, c[h][k], off, xr[h][k]);
 #pragma unroll
     for (int h = 0; h < H; ++h)
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
+      for (int k = 0; k < IW; ++k)
 #pragma unroll
         for (int w = 0; w < WG; ++w) acc[w] = fma(v[h][k], bf_word(xr[h][k][w / 2], w & 1), acc[w]);
   };
-  // narrow lanes keep four groups (16 entries) in flight, wide ones two
-  constexpr int HG = WG <= 4 ? 4 : 2;
+  // narrow lanes keep two groups (16 entries) in flight, wide ones one
+  constexpr int HG = WG <= 4 ? 2 : 1;
   int g = 0;
   if constexpr (F == 2 && WP == 4 && WG >= 3) {
-    // 8-byte rows: the leading pair groups (slots 4g, 4g+1 and 4g+2, 4g+3
-    // gather adjacent nodes in every lane) take one 16-byte gather per pair
-    auto pairs = [&](auto Hc, int g0) {
-      constexpr int H = decltype(Hc)::value;
-      int32_t c[H][2];
-      float v[H][4];
+    // 8-byte rows: the leading pair sub-groups (four slots 4p .. 4p+3 of
+    // which slots 4p, 4p+1 and 4p+2, 4p+3 gather adjacent nodes in every
+    // lane; r.pg of them) take one 16-byte gather per pair.  NP: pairs of
+    // the group taken that way (4, or 2 for a group half made of pairs).
+    auto pairs = [&](auto Hc, auto NPc, int g0) {
+      constexpr int H = decltype(Hc)::value, NP = decltype(NPc)::value;
+      int32_t c[H][IW];
+      float v[H][IW];
 #pragma unroll
       for (int h = 0; h < H; ++h) {
-        const int64_t e = s0 + 256 * (int64_t)(g0 + h) + 4 * lr;
-        load4_vals<_Float16, float>(vals, e, v[h]);
-        c[h][0] = affine_col(ix, r, r.eb + 4 * (g0 + h));
-        c[h][1] = affine_col(ix, r, r.eb + 4 * (g0 + h) + 2);
+        load_vals<IW, _Float16, float>(vals, entry(g0 + h), v[h]);
+#pragma unroll
+        for (int k = 0; k < IW; ++k)
+          if (k < 2 * NP ? k % 2 == 0 : true) c[h][k] = affine_col(ix, r, r.eb + IW * (g0 + h) + k);
       }
-      u32x4a8_t u[H][2];
+      u32x4a8_t u[H][NP];
+      uint32_t xr[H][IW][Raw::kWords];
 #pragma unroll
-      for (int h = 0; h < H; ++h)
+      for (int h = 0; h < H; ++h) {
 #pragma unroll
-        for (int k = 0; k < 2; ++k) u[h][k] = *reinterpret_cast<const u32x4a8_t*>(xq + (int64_t)c[h][k] * 4);
+        for (int p = 0; p < NP; ++p) u[h][p] = *reinterpret_cast<const u32x4a8_t*>(xq + (int64_t)c[h][2 * p] * 4);
 #pragma unroll
-      for (int h = 0; h < H; ++h)
+        for (int k = 2 * NP; k < IW; ++k) load_bf_raw<WP, WG>(xq, c[h][k], off, xr[h][k]);
+      }
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          const uint32_t w0[2] = {u[h][k].x, u[h][k].y}, w1[2] = {u[h][k].z, u[h][k].w};
+      for (int h = 0; h < H; ++h) {
 #pragma unroll
-          for (int w = 0; w < WG; ++w) acc[w] = fma(v[h][2 * k], bf_word(w0[w / 2], w & 1), acc[w]);
-#pragma unroll
-          for (int w = 0; w < WG; ++w) acc[w] = fma(v[h][2 * k + 1], bf_word(w1[w / 2], w & 1), acc[w]);
+        for (int p = 0; p < NP; ++p) {
+          xr[h][2 * p][0] = u[h][p].x;
+          xr[h][2 * p][1] = u[h][p].y;
+          xr[h][2 * p + 1][0] = u[h][p].z;
+          xr[h][2 * p + 1][1] = u[h][p].w;
         }
+#pragma unroll
+        for (int k = 0; k < IW; ++k)
+#pragma unroll
+          for (int w = 0; w < WG; ++w) acc[w] = fma(v[h][k], bf_word(xr[h][k][w / 2], w & 1), acc[w]);
+      }
     };
-    for (; g + 4 <= r.pg; g += 4) pairs(std::integral_constant<int, 4>{}, g);
-    for (; g < r.pg; ++g) pairs(std::integral_constant<int, 1>{}, g);
+    const int gp = r.pg / 2;  // groups made of four pairs
+    for (; g + 2 <= gp; g += 2) pairs(std::integral_constant<int, 2>{}, std::integral_constant<int, 4>{}, g);
+    for (; g < gp; ++g) pairs(std::integral_constant<int, 1>{}, std::integral_constant<int, 4>{}, g);
+    if ((r.pg & 1) && g < gi) pairs(std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{}, g++);
   }
-  for (; g + HG <= g4; g += HG) groups(std::integral_constant<int, HG>{}, g);
-  if constexpr (HG > 2)
-    for (; g + 2 <= g4; g += 2) groups(std::integral_constant<int, 2>{}, g);
-  if (g < g4) groups(std::integral_constant<int, 1>{}, g);
-  // the remaining width mod 4 slots, slot-major
-  for (int j = 4 * g4; j < r.width; ++j) {
+  for (; g + HG <= gi; g += HG) groups(std::integral_constant<int, HG>{}, g);
+  if (g < gi) groups(std::integral_constant<int, 1>{}, g);
+  // the remaining width mod IW slots, slot-major
+  for (int j = IW * gi; j < r.width; ++j) {
     const int32_t c = sell_col_f<F>(ix, r, j);
     const float v = (float)__builtin_nontemporal_load(vals + r.beg + 64 * j);
     uint32_t xr[Raw::kWords];
@@ -1163,19 +1201,19 @@ __device__ __forceinline__ void sell_row_bq4_impl(const SellIdx& ix, const Slice
   }
 }
 
-// Permute one scalar array of a sliced-ELL layout into the four-slot
-// interleaved order above (one workgroup of 64 threads per slice).
-template <typename E>
-__global__ __launch_bounds__(64) void k_interleave4(int64_t nslices, const int64_t* __restrict__ sp,
-                                                    const E* __restrict__ src, E* __restrict__ dst) {
+// Permute one scalar array of a sliced-ELL layout into the interleaved order
+// above with IW slots per group (one workgroup of 64 threads per slice).
+template <typename E, int IW>
+__global__ __launch_bounds__(64) void k_interleave(int64_t nslices, const int64_t* __restrict__ sp,
+                                                   const E* __restrict__ src, E* __restrict__ dst) {
   const int64_t s = blockIdx.x;
   if (s >= nslices) return;
   const int64_t s0 = sp[s];
   const int w = static_cast<int>((sp[s + 1] - s0) >> 6);
-  const int lr = threadIdx.x, g4 = w >> 2;
+  const int lr = threadIdx.x, gi = w / IW;
   for (int j = 0; j < w; ++j) {
     const int64_t from = s0 + 64 * (int64_t)j + lr;
-    const int64_t to = j < 4 * g4 ? s0 + 256 * (int64_t)(j >> 2) + 4 * lr + (j & 3) : from;
+    const int64_t to = j < IW * gi ? s0 + 64 * IW * (int64_t)(j / IW) + IW * lr + (j % IW) : from;
     dst[to] = src[from];
   }
 }
@@ -1194,7 +1232,7 @@ struct QSum {
 // First step with a bfloat16 direction out:  q0 = theta_inv r (not stored),
 // res = r - (S D^{-1}) q0, q1 = bf16(c1 q0 + c2 res), z (+)= dinv (q0 + q1);
 // ACC = 2 leaves z to the closing step (no z, no dinv).
-// IL: ix and vals are the four-slot interleaved copies.
+// IL: ix and vals are the interleaved copies.
 template <typename TM, int W, int ACC, int G, int U = 8, bool IL = false>
 __global__ __launch_bounds__(kBlock) void k_cheb_first_qb(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
                                                           const float* __restrict__ r, const float* __restrict__ dinv,
@@ -1232,7 +1270,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_first_qb(int64_t nrows, SellIdx
 // ZM = 1: the deferred form -- no z (nor dinv); ZM = 2: the closing step --
 // neither res nor qn is stored, z = dinv (fin.theta_inv fin.r + fin.q[0] +
 // ... + fin.q[n-1] + qn).
-// IL: ix.cdel / ix.cols and vals are the four-slot interleaved copies.
+// IL: ix.cdel / ix.cols and vals are the interleaved copies.
 template <typename TM, int W, int G, int U = 8, bool IL = false, int ZM = 0>
 __global__ __launch_bounds__(kBlock) void k_cheb_step_qb(int64_t nrows, SellIdx ix, const TM* __restrict__ vals,
                                                          const uint16_t* __restrict__ q, uint16_t* __restrict__ qn,

@@ -13,7 +13,7 @@ struct QSum;  // closing step of a deferred Chebyshev sum (kernels.h)
 void assemble_ctx(stokes_ctx* c);
 void assemble_p1(stokes_ctx* c, const HostMesh& m, MgLevel& L);
 void build_mg(stokes_ctx* c);
-void build_interleaved(stokes_ctx* c);  // four-slot copies for the bfloat16 Chebyshev step
+void build_interleaved(stokes_ctx* c);  // interleaved copies for the bfloat16 Chebyshev steps and K_gamma
 // Galerkin hierarchy on B_I Lambda_V^-1 B_I^T + M_Q (levels only; the dense
 // coarsest inverse is added by build_mg)
 void assemble_galerkin(stokes_ctx* c, MgHier& H);

@@ -170,11 +170,11 @@ bool with_e(int E, F&& f) {
   }
 }
 
-// Index of the four-slot interleaved copy of the velocity pattern.
-SellIdx vel_il_idx(stokes_ctx* c, int W) {
+// Index of the interleaved copies of the velocity pattern (iw slots per group).
+SellIdx vel_il_idx(stokes_ctx* c, int W, int iw) {
   SellIdx ix = c->sA.idx(W);
-  ix.cdel = c->cdel_i.as<const uint8_t>();
-  ix.cols = c->cols_i.as<const int32_t>();
+  ix.cdel = (iw == 8 ? c->cdel_i8 : c->cdel_i).as<const uint8_t>();
+  ix.cols = (iw == 8 ? c->cols_i8 : c->cols_i).as<const int32_t>();
   if (!c->vel_af) ix.cmeta = nullptr;  // read the packed offsets of affine slots too
   return ix;
 }
@@ -251,7 +251,8 @@ void spmv_impl(stokes_ctx* c, const Sell& S, const TM* vals, T ms, int W, const 
         with_g<WW>(G, [&](auto Gc) {
           constexpr int GG = decltype(Gc)::value;
           hipLaunchKernelGGL((k_spmv<T, WW, GG, TM, true>), dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0,
-                             c->stream, S.nrows, vel_il_idx(c, WW), c->A32i.as<const float>(), x, y, (T)(a * ms), yin, b);
+                             c->stream, S.nrows, vel_il_idx(c, WW, il_width<float>()), c->A32i.as<const float>(), x, y,
+                             (T)(a * ms), yin, b);
         });
         il = true;
         return;
@@ -595,9 +596,10 @@ void cheb_first_hb(stokes_ctx* c, int W, const float* r, const float* dinv, floa
     wp = bf_width<WW>();
     with_g<WW>(G, [&](auto Gc) {
       constexpr int GG = decltype(Gc)::value;
-      if (c->vel_il && c->AD16i.p) {  // the four-slot interleaved copies
+      if (c->vel_il && c->AD16i.p) {  // the eight-slot interleaved copies
         auto kern = zw ? k_cheb_first_qb<_Float16, WW, 0, GG, 8, true> : k_cheb_first_qb<_Float16, WW, 2, GG, 8, true>;
-        hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows, vel_il_idx(c, WW),
+        hipLaunchKernelGGL(kern, dim3(grid_full(S.nrows * GG)), dim3(kBlock), 0, c->stream, S.nrows,
+                           vel_il_idx(c, WW, il_width<_Float16>()),
                            (const _Float16*)c->AD16i.as<_Float16>(), r, dinv, theta_inv, q1, res, z, c1, c2);
         il = true;
         return;
@@ -635,11 +637,11 @@ void cheb_step_hb(stokes_ctx* c, int W, const uint16_t* q, uint16_t* qn, const f
       constexpr int GG = decltype(Gc)::value;
       const int nb = grid_full(S.nrows * GG);
       if constexpr (BfRaw<bf_width<WW>(), WW / GG>::kOn) {
-        if (c->vel_il && c->AD16i.p) {  // the four-slot interleaved copies
+        if (c->vel_il && c->AD16i.p) {  // the eight-slot interleaved copies
           auto kern = zm == 0   ? k_cheb_step_qb<_Float16, WW, GG, 8, true, 0>
                       : zm == 1 ? k_cheb_step_qb<_Float16, WW, GG, 8, true, 1>
                                 : k_cheb_step_qb<_Float16, WW, GG, 8, true, 2>;
-          hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, S.nrows, vel_il_idx(c, WW),
+          hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, c->stream, S.nrows, vel_il_idx(c, WW, il_width<_Float16>()),
                              (const _Float16*)c->AD16i.as<_Float16>(), q, qn, res_in, res_out, z, dinv, c1, c2, fa);
           il = true;
           return;

@@ -196,11 +196,18 @@ def test_slice_schedule_bitwise_equal(gpu_lib, monkeypatch, dim, n, nrhs, lanes)
             assert _rel(b, a) <= 1e-8
 
 
-@pytest.mark.parametrize("dim,n,nrhs,lanes", [(3, 6, 1, 1), (3, 5, 8, 4), (2, 16, 1, 1), (2, 12, 4, 2)])
+@pytest.mark.parametrize("dim,n,nrhs,lanes", [(3, 6, 1, 1), (3, 5, 8, 4), (2, 16, 1, 1), (2, 12, 4, 2),
+                                               (3, 13, 1, 1), (3, 11, 2, 2), (3, 64, 1, 1)])
 def test_interleaved_chebyshev_step_bitwise_equal(gpu_lib, monkeypatch, dim, n, nrhs, lanes):
-    """The bfloat16 Chebyshev step reading the four-slot interleaved copies of
-    the half-precision values and column indices (the default) sums every row
-    in the same order as the slot-major form: apply op 10 is bitwise equal."""
+    """The bfloat16 Chebyshev steps reading the eight-slot interleaved copies
+    of the half-precision values and column indices, and the FP32 K_gamma
+    product reading the four-slot interleaved FP32 copy (the default), sum
+    every row in the same order as the slot-major forms: apply op 10 and a
+    mixed coupled solve are bitwise equal with the copies off.  The meshes
+    give slice widths 19, 27 and 65 in 3D (tails of 3 and 1 slots after the
+    eight-slot groups) and 9 to 25 in 2D; 3D n=64 has affine slices with
+    pair groups, the smaller meshes packed and 32-bit columns."""
+    from paper_2407_01783_amd import inputs
     monkeypatch.setenv("STOKES_LANES", str(lanes))
     rng = np.random.default_rng(31)
     outs = []
@@ -209,9 +216,15 @@ def test_interleaved_chebyshev_step_bitwise_equal(gpu_lib, monkeypatch, dim, n, 
         P = _problem(dim, n, seed=8, mu=0.05, alpha=100.0)
         if not outs:
             x = rng.standard_normal(nrhs * dim * P.n_p2)
-        outs.append(P.apply(10, torch.tensor(x, device="cuda"), precision=1, nrhs=nrhs).cpu().numpy())
+            xy, _ = P.mesh()
+            f = np.stack([inputs.fourier_forcing(xy, inputs.forcing_seed(8, k)) for k in range(nrhs)])
+        y = P.apply(10, torch.tensor(x, device="cuda"), precision=1, nrhs=nrhs).cpu().numpy()
+        u, p, info = P.solve(torch.tensor(f, device="cuda"), method="coupled", precision=1, rtol=1e-8)
+        assert info["status"] == 0, info
+        outs.append((y, u.cpu().numpy(), p.cpu().numpy()))
         del P
-    assert np.array_equal(outs[0], outs[1])
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("dim,n,nrhs", [(3, 64, 2), (2, 130, 1), (2, 132, 4)])
