@@ -523,7 +523,7 @@ def main():
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": measured_traffic(args.workload, args.nrhs, args.strain),
                      "kernel": f"k_cheb_step_qb<_Float16,{dim * args.nrhs},G,8,true,1> (velocity-block SELL SpMV: "
-                               f"half-precision A_II D^-1 values and computed or packed column offsets read from four-slot "
+                               f"half-precision A_II D^-1 values and computed or packed column offsets read from eight-slot "
                                f"interleaved copies, bfloat16 direction (adjacent-node slot pairs gathered with one "
                                f"16-byte load at W = 3), FP32 residual; a Chebyshev step of the "
                                f"deferred sum (the iterate is formed by the closing step); G lanes per row, autotuned)",
