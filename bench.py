@@ -289,6 +289,8 @@ def main():
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--strain", action="store_true",
                     help="strain-rate velocity matrix alpha M + mu (L + D) instead of the vector Laplacian")
+    ap.add_argument("--p3", action="store_true",
+                    help="Taylor-Hood P3/P2 on the workload's mesh instead of P2/P1")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=16, help="mesh size of the CPU oracle sample")
@@ -337,9 +339,11 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    prob = StokesProblem(dim, n, mesh_seed=seed, jitter=0.1, mu=mu, alpha=alpha, strain=args.strain)
+    prob = StokesProblem(dim, n, mesh_seed=seed, jitter=0.1, mu=mu, alpha=alpha, strain=args.strain, p3=args.p3)
     if args.strain:
         desc += ", strain-rate form alpha M + mu (L + D)"
+    if args.p3:
+        desc = desc.replace("P2/P1", "P3/P2 (this mesh)") + f", P3/P2: {prob.total_dofs():,} DOFs"
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     print(f"[bench] assembled {args.workload} in {setup_s:.2f} s", file=sys.stderr, flush=True)
@@ -367,7 +371,8 @@ def main():
 
     el_mixed, infos = run(1, args.steps, args.warmup, 1)
     err = None
-    if args.workload == "cube64" and args.nrhs == 1 and not args.strain and os.path.exists(ORACLE_SOLUTION_FILE):
+    if (args.workload == "cube64" and args.nrhs == 1 and not args.strain and not args.p3
+            and os.path.exists(ORACLE_SOLUTION_FILE)):
         err = error_vs_stored_oracle(*last_out)
     print(f"[bench] mixed: {el_mixed / args.steps * 1e3:.1f} ms/solve", file=sys.stderr, flush=True)
     ok = all(i["status"] == 0 and i["rel_res"] <= opts["rtol"] for i in infos)
@@ -433,7 +438,8 @@ def main():
         for k in saved:
             os.environ[k] = "0"
         try:
-            prob32 = StokesProblem(dim, n, mesh_seed=seed, jitter=0.1, mu=mu, alpha=alpha, strain=args.strain)
+            prob32 = StokesProblem(dim, n, mesh_seed=seed, jitter=0.1, mu=mu, alpha=alpha, strain=args.strain,
+                                   p3=args.p3)
         finally:
             for k, v in saved.items():
                 if v is None:
@@ -521,7 +527,7 @@ def main():
         "projection": projection,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": measured_traffic(args.workload, args.nrhs, args.strain),
+                     "traffic": measured_traffic(args.workload, args.nrhs, args.strain or args.p3),
                      "kernel": f"k_cheb_step_qb<_Float16,{dim * args.nrhs},G,8,true,1> (velocity-block SELL SpMV: "
                                f"half-precision A_II D^-1 values and computed or packed column offsets read from eight-slot "
                                f"interleaved copies, bfloat16 direction (adjacent-node slot pairs gathered with one "
