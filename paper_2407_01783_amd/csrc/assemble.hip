@@ -710,7 +710,7 @@ struct SellSlots {
   // line `step` apart (adjacent nodes of the column class, hence adjacent
   // columns), the other offsets after them.
   int step = 0;
-  bool pair_flags = false;  // count the leading pair groups of affine slices (pk = 2 + 4 groups)
+  bool pair_flags = false;  // count the leading pair sub-groups of affine slices (pk = 2 + 4 sub-groups)
   int nkeys() const { return (2 * R + 1) * (2 * R + 1) * (2 * R + 1); }
   int cls(int64_t r) const { return rcls ? rcls[r] : 0; }
   int key(int64_t r, int32_t c) const {  // -1: outside the reach

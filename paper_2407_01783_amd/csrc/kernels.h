@@ -1108,7 +1108,7 @@ __device__ __forceinline__ void sell_row_bq_impl(const SellIdx& ix, const SliceR
 // The bfloat16-direction row over the interleaved half-precision copies
 // (the layout of sell_row_il_impl, eight slots per group).
 template <int W, int G, int F>
-__device__ __forceinline__ void sell_row_bq4_impl(const SellIdx& ix, const SliceRef& r,
+__device__ __forceinline__ void sell_row_bq_il_impl(const SellIdx& ix, const SliceRef& r,
                                                   const _Float16* __restrict__ vals,
                                                   const uint16_t* __restrict__ xq, int off, float (&acc)[W / G]) {
   constexpr int WG = W / G, WP = bf_width<W>(), IW = il_width<_Float16>();
@@ -1289,9 +1289,9 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step_qb(int64_t nrows, SellIdx 
       // eight, the gathered words alone hold most of the registers
       constexpr int UB = WG >= 8 ? 4 : U;
       if constexpr (IL) {
-        if (rf.af) sell_row_bq4_impl<W, G, 2>(ix, rf, vals, q, sub * WG, acc);
-        else if (rf.pk) sell_row_bq4_impl<W, G, 1>(ix, rf, vals, q, sub * WG, acc);
-        else sell_row_bq4_impl<W, G, 0>(ix, rf, vals, q, sub * WG, acc);
+        if (rf.af) sell_row_bq_il_impl<W, G, 2>(ix, rf, vals, q, sub * WG, acc);
+        else if (rf.pk) sell_row_bq_il_impl<W, G, 1>(ix, rf, vals, q, sub * WG, acc);
+        else sell_row_bq_il_impl<W, G, 0>(ix, rf, vals, q, sub * WG, acc);
       } else {
         if (rf.af) sell_row_bq_impl<W, G, TM, 2, UB>(ix, rf, vals, q, sub * WG, acc);
         else if (rf.pk) sell_row_bq_impl<W, G, TM, 1, UB>(ix, rf, vals, q, sub * WG, acc);
