@@ -681,8 +681,9 @@ stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t
     if (precision != 0 && precision != 1) throw Error(STOKES_ERR_ARG, "precision must be 0 or 1");
     if (nrhs < 1) throw Error(STOKES_ERR_ARG, "nrhs must be >= 1");
     if (!x || !y) throw Error(STOKES_ERR_ARG, "x and y must not be NULL");
-    if (c->mesh.order == 3 && (op == 6 || op == 8 || op == 9))
-      throw Error(STOKES_ERR_UNSUPPORTED, "the multigrid operators (op 6, 8, 9) need the P2/P1 pair");
+    if (c->mesh.order == 3 && (op == 8 || op == 9))
+      throw Error(STOKES_ERR_UNSUPPORTED, "the Galerkin pressure multigrid (op 8) and the velocity multigrid (op 9) "
+                                          "need the P2/P1 pair");
     HIP_CHECK(hipSetDevice(c->device));
     StreamScope scope(c);
     const int D = c->dim;

@@ -1584,10 +1584,10 @@ void assemble_ctx(stokes_ctx* c) {
   phase("values and FP32 copies");
   estimate_bounds(c);
   phase("Chebyshev intervals");
-  // the geometric multigrids coarsen the P1 pressure lattice (and the P2
-  // velocity lattice): a P3/P2 context has none, its pressure solves use
-  // Chebyshev-Jacobi polynomials of M_Q + L_Q instead
-  if (K != 3) build_mg(c);
+  // the pressure multigrids (the P2 pressure of a P3/P2 context coarsens to
+  // the P1 space of its mesh first); the velocity multigrid is built on
+  // first use, for P2/P1 only
+  build_mg(c);
   phase("multigrid hierarchies");
   HIP_CHECK(hipStreamSynchronize(c->stream));
 }

@@ -354,20 +354,26 @@ void tune_levels(stokes_ctx* c, MgHier& H) {
 }
 }  // namespace
 
-// Build both hierarchies (called once per context after assembly).
+// Build both hierarchies (called once per context after assembly).  Level
+// 0 is the pressure space: the (n+1)^dim vertices of the mesh for P2/P1, the
+// (2n+1)^dim P2 nodes for P3/P2.  The P2 nodes of the mesh with n cells sit
+// where the vertices of the mesh with 2n cells would, and a P1 function of
+// the mesh is a P2 function with the nodal values that the Kuhn P1
+// interpolation from n to 2n gives (vertex values kept, edge midpoints the
+// mean of the two ends): so the P2 level is level "2n" of the same
+// hierarchy, and its first coarse level is the P1 space of the mesh itself.
 void build_mg(stokes_ctx* c) {
   MgHier& H = c->mgq;
   H.lv.clear();
   H.own.clear();
   const HostMesh& fm = c->mesh;
   const int D = fm.dim;
-  int n = fm.n;
-  int stride = 1;
+  int n = fm.order == 3 ? 2 * fm.n : fm.n;  // lattice intervals per side of the pressure nodes
   H.lv.push_back({&c->sQ, &c->XQ64, &c->XQ32, &c->dXQ64, &c->dXQ32, &c->bXQ_smooth, &c->bXQ, n});
   // coarsen while the current level is too large for the dense coarse solve
   while (n % 2 == 0 && n > 2 && ipow(n + 1, D) > c->mg_dense_max) {
     n /= 2;
-    stride *= 2;
+    const int stride = fm.n / n;  // mesh vertices per coarse cell side
     auto L = std::make_unique<MgLevel>();
     L->n = n;
     HostMesh m;
@@ -388,8 +394,20 @@ void build_mg(stokes_ctx* c) {
     H.own.push_back(std::move(L));
   }
   dense_coarsest(c, H);
-  assemble_galerkin(c, c->mgx);
-  dense_coarsest(c, c->mgx);
+  // The Galerkin hierarchy of B_I Lambda_V^-1 B_I^T + M_Q is P2/P1 only.  On
+  // the P2 pressure of a P3/P2 pair that operator is close to the P2 mass
+  // matrix, whose low-energy modes include non-smooth ones (vertex and edge
+  // values of one sign, coupled through negative entries) that the P1 coarse
+  // space does not hold: a V-cycle with the P1 space of the mesh as first
+  // coarse level contracts ever more slowly (3D), so a P3/P2 context keeps
+  // the Chebyshev-Jacobi polynomial of that operator instead.
+  c->mgx.lv.clear();
+  c->mgx.own.clear();
+  c->mgx.dense_n = 0;
+  if (fm.order != 3) {
+    assemble_galerkin(c, c->mgx);
+    dense_coarsest(c, c->mgx);
+  }
   tune_levels(c, c->mgq);
   tune_levels(c, c->mgx);
 }

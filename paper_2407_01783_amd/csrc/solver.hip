@@ -421,11 +421,14 @@ class Engine {
   // mode: the approximation itself) is one multigrid V-cycle of eps M_Q + L_Q
   void x_solve(const T* b, T* x) {
     Prec pc{&c_->sQ, ops::pick<T>(c_->XQ64, c_->XQ32), ops::pick<T>(c_->dXQ64, c_->dXQ32), c_->bXQ, 1, {}};
-    const MgHier& H = (o_.schur_pc == STOKES_CC_LUMPED && c_->use_mgx) ? c_->mgx : c_->mgq;
+    // the Galerkin hierarchy (P2/P1 only) for the lumped variant, else the
+    // V-cycle of eps M_Q + L_Q
+    const MgHier& H =
+        (o_.schur_pc == STOKES_CC_LUMPED && c_->use_mgx && !c_->mgx.lv.empty()) ? c_->mgx : c_->mgq;
     if (H.lv.empty()) {
-      // no multigrid hierarchy (the P3/P2 pair): the preconditioner, and in
-      // fixed mode the approximation itself, is a Chebyshev-Jacobi polynomial
-      // of eps M_Q + L_Q (eps = 1, the operator of Sec. 4.2)
+      // no multigrid hierarchy: the preconditioner, and in fixed mode the
+      // approximation itself, is a Chebyshev-Jacobi polynomial of
+      // eps M_Q + L_Q (eps = 1, the operator of Sec. 4.2)
       pc.degree = kXQDegree;
       if (o_.inner_mode == STOKES_INNER_FIXED) {
         cheb_apply("xfx", c_->sQ, pc.vals, pc.dinv, c_->bXQ, kXQDegree, nrb_, b, x);
