@@ -93,10 +93,12 @@ enum { STOKES_FLAG_STRAIN = 1 };
  * every "n_p1" / pressure-shaped array P2 nodes.  Local P3 order: vertices,
  * then per local edge (a, b) the node next to a and the node next to b, then
  * the faces (0,1,2), (0,1,3), (0,2,3), (1,2,3) (2D: the interior node).  The
- * geometric multigrids need the P2/P1 pair: with P3 the pressure solves use
- * Chebyshev-Jacobi polynomials of M_Q + L_Q, vel_pc = STOKES_VEL_MG and
- * stokes_apply ops 6, 8, 9 return STOKES_ERR_UNSUPPORTED.  Combines with
- * STOKES_FLAG_STRAIN. */
+ * P2 pressure nodes of the mesh with n cells are the vertices of the mesh
+ * with 2n cells, so the multigrid of eps M_Q + L_Q (op 6) runs on P3/P2 with
+ * the P1 space of the mesh as its first coarse level, and the pressure solves
+ * use it; the Galerkin hierarchy (op 8) and the velocity multigrid
+ * (vel_pc = STOKES_VEL_MG, op 9) need the P2/P1 pair and return
+ * STOKES_ERR_UNSUPPORTED.  Combines with STOKES_FLAG_STRAIN. */
 enum { STOKES_FLAG_P3 = 2 };
 /* stokes_solve_opts.vel_pc: the preconditioner of A~_{lambda,3} = alpha M_V
  * + mu L_V inside the velocity solves -- a Chebyshev-Jacobi polynomial of

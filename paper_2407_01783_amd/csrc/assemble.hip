@@ -1584,9 +1584,9 @@ void assemble_ctx(stokes_ctx* c) {
   phase("values and FP32 copies");
   estimate_bounds(c);
   phase("Chebyshev intervals");
-  // the pressure multigrids (the P2 pressure of a P3/P2 context coarsens to
-  // the P1 space of its mesh first); the velocity multigrid is built on
-  // first use, for P2/P1 only
+  // the pressure multigrids (on a P3/P2 context only the one of
+  // eps M_Q + L_Q, whose P2 pressure coarsens to the P1 space of its mesh
+  // first); the velocity multigrid is built on first use, for P2/P1 only
   build_mg(c);
   phase("multigrid hierarchies");
   HIP_CHECK(hipStreamSynchronize(c->stream));
