@@ -415,6 +415,7 @@ void build_mg(stokes_ctx* c) {
 template <class T>
 void mg_vcycle(stokes_ctx* c, const MgHier& H, int nrb, const T* r, T* e, int lv) {
   const int nlev = static_cast<int>(H.lv.size());
+  if (lv >= nlev) throw Error(STOKES_ERR_STATE, "pressure multigrid hierarchy not built");
   const MgHier::View& V = H.lv[lv];
   const Sell& S = *V.S;
   const T* vals = ops::pick<T>(*V.v64, *V.v32);

@@ -41,10 +41,6 @@ namespace {
 // flight is then almost surely not the last).
 constexpr double kQueueAhead = 30.0;
 
-// Degree of the Chebyshev-Jacobi polynomial of eps M_Q + L_Q that stands in
-// for the pressure multigrid V-cycle where there is no hierarchy.
-constexpr int kXQDegree = 8;
-
 template <int V>
 using IC = std::integral_constant<int, V>;
 
@@ -425,21 +421,10 @@ class Engine {
     // V-cycle of eps M_Q + L_Q
     const MgHier& H =
         (o_.schur_pc == STOKES_CC_LUMPED && c_->use_mgx && !c_->mgx.lv.empty()) ? c_->mgx : c_->mgq;
-    if (H.lv.empty()) {
-      // no multigrid hierarchy: the preconditioner, and in fixed mode the
-      // approximation itself, is a Chebyshev-Jacobi polynomial of
-      // eps M_Q + L_Q (eps = 1, the operator of Sec. 4.2)
-      pc.degree = kXQDegree;
-      if (o_.inner_mode == STOKES_INNER_FIXED) {
-        cheb_apply("xfx", c_->sQ, pc.vals, pc.dinv, c_->bXQ, kXQDegree, nrb_, b, x);
-        return;
-      }
-    } else {
-      pc.apply = [this, &H](const T* r, T* z) { mg_vcycle<T>(c_, H, nrb_, r, z, 0); };
-      if (o_.inner_mode == STOKES_INNER_FIXED) {
-        mg_vcycle<T>(c_, H, nrb_, b, x, 0);
-        return;
-      }
+    pc.apply = [this, &H](const T* r, T* z) { mg_vcycle<T>(c_, H, nrb_, r, z, 0); };
+    if (o_.inner_mode == STOKES_INNER_FIXED) {
+      mg_vcycle<T>(c_, H, nrb_, b, x, 0);
+      return;
     }
     Op op;
     const T* opvals = nullptr;
