@@ -13,6 +13,11 @@ What fixes each part independently of the oracle's own arithmetic:
 * global invariants: symmetry, 1^T M 1 = 1 for both masses, zero stiffness
   row sums, B (constant) = 0, B (x_c e_c) = M_Q 1, B_I^T 1 = 0 and
   rank B_I = n_q - 1 (the discrete inf-sup of the pair);
+* the P2 pressure as the vertex lattice of the mesh with 2n cells (what the
+  pressure multigrid of a P3/P2 context builds on): same coordinates, and a
+  P1 function of the mesh evaluated there by locating the containing
+  simplex by brute force equals its P2 nodal values (vertex values, edge
+  means);
 * the solve: direct = dense least squares, the exact block factorisation,
   and the convergence rates the paper reports for P3 velocities (Sec. 3.3,
   Table 4): O(h^4) for the velocity and O(h^3) for the pressure in L2 on a
@@ -27,7 +32,7 @@ import pytest
 import scipy.sparse as sp
 
 from oracle import p3, stokes
-from oracle.mesh import local_edges
+from oracle.mesh import KuhnMesh, local_edges
 from test_oracle_pins import _duffy_rule, _eval, _lagrange
 
 
@@ -282,3 +287,35 @@ def test_p3p2_manufactured_rates_2d():
     # error is O(h^4) too, so the rates are not spoilt
     assert ru[-1] > 3.7, (eu, ru)
     assert rp[-1] > 2.7, (ep, rp)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 3), (3, 2)])
+def test_p2_nodes_are_the_refined_vertex_lattice(dim, n):
+    """The P2 nodes of the Kuhn mesh with n cells per side sit at the vertices
+    of the mesh with 2n cells, id for id, and the P1 functions of the coarse
+    mesh are the P2 functions whose edge nodes carry the mean of the edge's
+    two end values: evaluating a random P1 function at every refined vertex
+    through a brute-force search for a simplex that contains it gives the P2
+    nodal values built from the element table."""
+    m1, m2 = KuhnMesh(dim, n, jitter=0.0), KuhnMesh(dim, 2 * n, jitter=0.0)
+    assert m1.n_p2 == m2.n_p1
+    np.testing.assert_allclose(m1.p2coords, m2.vcoords, rtol=0, atol=1e-15)
+    v = np.random.default_rng(5).standard_normal(m1.n_p1)
+    u2 = np.full(m1.n_p2, np.nan)
+    for e in range(m1.n_e):
+        for a in range(dim + 1):
+            u2[m1.p2[e, a]] = v[m1.elems[e, a]]
+        for q, (a, b) in enumerate(local_edges(dim)):
+            u2[m1.p2[e, dim + 1 + q]] = 0.5 * (v[m1.elems[e, a]] + v[m1.elems[e, b]])
+    X = m1.vcoords
+    for i, x in enumerate(m2.vcoords):
+        val = None
+        for e in range(m1.n_e):
+            P = X[m1.elems[e]]
+            lam = np.linalg.solve((P[1:] - P[0]).T, x - P[0])
+            bary = np.concatenate([[1.0 - lam.sum()], lam])
+            if bary.min() >= -1e-12:
+                val = bary @ v[m1.elems[e]]
+                break
+        assert val is not None, i
+        assert abs(val - u2[i]) <= 1e-12, (i, val, u2[i])
