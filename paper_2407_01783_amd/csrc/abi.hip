@@ -544,6 +544,9 @@ stokes_status stokes_assemble(const stokes_problem* prob, void* hip_stream, stok
     if (const char* e = std::getenv("STOKES_GRAPHS")) c->use_graphs = std::atoi(e) != 0;
     if (const char* e = std::getenv("STOKES_CG_CHECK")) c->cg_check_every = std::max(1, std::atoi(e));
     if (const char* e = std::getenv("STOKES_MGX")) c->use_mgx = std::atoi(e) != 0;
+    if (const char* e = std::getenv("STOKES_MGX_P3")) c->mgx_p3 = std::atoi(e) != 0;
+    if (const char* e = std::getenv("STOKES_MGX_P2_RATIO")) c->mgx_p2_ratio = std::max(1.5, std::atof(e));
+    if (const char* e = std::getenv("STOKES_MGX_P2_DEGREE")) c->mgx_p2_degree = std::max(1, std::atoi(e));
     if (const char* e = std::getenv("STOKES_VEL_HALF")) c->vel_half = std::atoi(e) != 0;
     if (const char* e = std::getenv("STOKES_PMG_HALF")) c->pmg_half = std::atoi(e) != 0;
     if (const char* e = std::getenv("STOKES_VEL_BF")) c->vel_bf = std::atoi(e) != 0;
@@ -681,9 +684,10 @@ stokes_status stokes_apply(stokes_ctx* c, int32_t op, int32_t precision, int32_t
     if (precision != 0 && precision != 1) throw Error(STOKES_ERR_ARG, "precision must be 0 or 1");
     if (nrhs < 1) throw Error(STOKES_ERR_ARG, "nrhs must be >= 1");
     if (!x || !y) throw Error(STOKES_ERR_ARG, "x and y must not be NULL");
-    if (c->mesh.order == 3 && (op == 8 || op == 9))
-      throw Error(STOKES_ERR_UNSUPPORTED, "the Galerkin pressure multigrid (op 8) and the velocity multigrid (op 9) "
-                                          "need the P2/P1 pair");
+    if (c->mesh.order == 3 && op == 9)
+      throw Error(STOKES_ERR_UNSUPPORTED, "the velocity multigrid (op 9) needs the P2/P1 pair");
+    if (op == 8 && c->mgx.lv.empty())
+      throw Error(STOKES_ERR_UNSUPPORTED, "no Galerkin pressure multigrid on this context (STOKES_MGX_P3=0)");
     HIP_CHECK(hipSetDevice(c->device));
     StreamScope scope(c);
     const int D = c->dim;

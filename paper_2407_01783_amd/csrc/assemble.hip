@@ -1584,9 +1584,9 @@ void assemble_ctx(stokes_ctx* c) {
   phase("values and FP32 copies");
   estimate_bounds(c);
   phase("Chebyshev intervals");
-  // the pressure multigrids (on a P3/P2 context only the one of
-  // eps M_Q + L_Q, whose P2 pressure coarsens to the P1 space of its mesh
-  // first); the velocity multigrid is built on first use, for P2/P1 only
+  // the pressure multigrids (the P2 pressure of a P3/P2 context coarsens to
+  // the P1 space of its mesh first); the velocity multigrid is built on
+  // first use, for P2/P1 only
   build_mg(c);
   phase("multigrid hierarchies");
   HIP_CHECK(hipStreamSynchronize(c->stream));
@@ -1772,12 +1772,15 @@ void assemble_galerkin(stokes_ctx* c, MgHier& H) {
     }
     A.rowptr[r + 1] = static_cast<int64_t>(A.cols.size());
   }
-  int n = c->mesh.n;
+  int n = c->mesh.order == 3 ? 2 * c->mesh.n : c->mesh.n;  // lattice intervals of the pressure nodes
   for (;;) {
     auto L = std::make_unique<MgLevel>();
     L->n = n;
     upload_level(c, A, av, *L);
-    H.lv.push_back({&L->S, &L->v64, &L->v32, &L->d64, &L->d32, &L->bs, &L->bf, n, &L->v16, L->s16});
+    const bool p2 = c->mesh.order == 3 && H.lv.empty();  // the P2 pressure level of a P3/P2 pair
+    if (p2) L->bs.lo = L->bs.hi / c->mgx_p2_ratio;
+    H.lv.push_back({&L->S, &L->v64, &L->v32, &L->d64, &L->d32, &L->bs, &L->bf, n, &L->v16, L->s16,
+                    p2 ? c->mgx_p2_degree : 0});
     H.own.push_back(std::move(L));
     if (!(n % 2 == 0 && n > 2 && ipow(n + 1, D) > c->mg_dense_max)) break;
     HostCsr Ac;

@@ -156,6 +156,7 @@ struct MgHier {
     int n;
     const DevBuf* v16 = nullptr;  // half-precision values / s16 (FP32 V-cycles)
     float s16 = 0;
+    int nu = 0;  // smoothing degree of this level (0: the context's)
   };
   std::vector<View> lv;
   std::vector<std::unique_ptr<MgLevel>> own;
@@ -258,6 +259,12 @@ struct stokes_ctx {
   int64_t mg_dense_max = 1500;          // largest level solved densely
   double mg_smooth_ratio = 10.0;
   int use_mgx = 1;                      // lumped CC: precondition with mgx (0: mgq)
+  // P3/P2: build the Galerkin hierarchy too (0: only the eps M_Q + L_Q one),
+  // its P2 pressure level smoothed on [lambda_max / mgx_p2_ratio,
+  // lambda_max] at degree mgx_p2_degree
+  int mgx_p3 = 1;
+  double mgx_p2_ratio = 10.0;
+  int mgx_p2_degree = 2;
 
   // velocity multigrid (built on first use; level 0 is sA / A, the coarse
   // levels rediscretise alpha M + mu L on the coarse Kuhn meshes)

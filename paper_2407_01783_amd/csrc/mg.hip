@@ -394,17 +394,17 @@ void build_mg(stokes_ctx* c) {
     H.own.push_back(std::move(L));
   }
   dense_coarsest(c, H);
-  // The Galerkin hierarchy of B_I Lambda_V^-1 B_I^T + M_Q is P2/P1 only.  On
-  // the P2 pressure of a P3/P2 pair that operator is close to the P2 mass
-  // matrix, whose low-energy modes include non-smooth ones (vertex and edge
-  // values of one sign, coupled through negative entries) that the P1 coarse
-  // space does not hold: a V-cycle with the P1 space of the mesh as first
-  // coarse level contracts ever more slowly (3D), so a P3/P2 context keeps
-  // the Chebyshev-Jacobi polynomial of that operator instead.
+  // The Galerkin hierarchy of B_I Lambda_V^-1 B_I^T + M_Q.  On the P2
+  // pressure of a P3/P2 pair that operator is close to the P2 mass matrix,
+  // whose low-energy modes include non-smooth ones (vertex and edge values
+  // coupled through negative entries) that the P1 coarse space does not
+  // hold and that the smoothing interval leaves out, so its V-cycle
+  // contracts more slowly there (about 0.72 per cycle on a 3D mesh), yet it
+  // stays symmetric positive definite and is the better preconditioner.
   c->mgx.lv.clear();
   c->mgx.own.clear();
   c->mgx.dense_n = 0;
-  if (fm.order != 3) {
+  if (fm.order != 3 || c->mgx_p3) {
     assemble_galerkin(c, c->mgx);
     dense_coarsest(c, c->mgx);
   }
@@ -483,7 +483,7 @@ void mg_vcycle(stokes_ctx* c, const MgHier& H, int nrb, const T* r, T* e, int lv
     }
     return;
   }
-  const int nu = c->mg_smooth_degree;
+  const int nu = V.nu > 0 ? V.nu : c->mg_smooth_degree;
   T* t = wsp<T>(c, tag + "_t", n);
   const MgHier::View& C = H.lv[lv + 1];
   const int nf = V.n;

@@ -417,7 +417,7 @@ class Engine {
   // mode: the approximation itself) is one multigrid V-cycle of eps M_Q + L_Q
   void x_solve(const T* b, T* x) {
     Prec pc{&c_->sQ, ops::pick<T>(c_->XQ64, c_->XQ32), ops::pick<T>(c_->dXQ64, c_->dXQ32), c_->bXQ, 1, {}};
-    // the Galerkin hierarchy (P2/P1 only) for the lumped variant, else the
+    // the Galerkin hierarchy for the lumped variant (when built), else the
     // V-cycle of eps M_Q + L_Q
     const MgHier& H =
         (o_.schur_pc == STOKES_CC_LUMPED && c_->use_mgx && !c_->mgx.lv.empty()) ? c_->mgx : c_->mgq;

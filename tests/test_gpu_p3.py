@@ -6,10 +6,9 @@ operator, solve, augmented-Lagrangian, adjoint and pressure-correction checks
 as for P2/P1, with the same bars (matrices 1e-13 of the max-norm, patterns
 bit-exact; operators 1e-13 FP64 / 2e-6 FP32; solution error 1e-10 on the
 FP64 path at rel-res 1e-12, 1e-8 on the mixed path at rel-res 1e-10 or
-tighter; gradients 1e-8).  The multigrid of eps M_Q + L_Q (op 6) coarsens
-the P2 pressure to the P1 space of the same mesh first; the Galerkin
-pressure multigrid (op 8) and the velocity multigrid (op 9) are P2/P1 only
-and are refused.
+tighter; gradients 1e-8).  The pressure multigrids (ops 6 and 8) coarsen
+the P2 pressure to the P1 space of the same mesh first; the velocity
+multigrid (op 9) needs the P2/P1 lattices and is refused.
 """
 
 import numpy as np
@@ -101,41 +100,51 @@ def test_p3_operator_actions_match_oracle(gpu_lib, dim, n, nrhs):
         for prec, tol in ((0, 1e-13), (1, 2e-6)):
             y = P.apply(op, torch.tensor(x.ravel(), device="cuda"), precision=prec, nrhs=nrhs).cpu().numpy()
             assert _rel(y, ref[op]) <= tol, (op, prec, _rel(y, ref[op]))
-    # the Galerkin pressure multigrid and the velocity multigrid are P2/P1 only
-    for op, x in ((8, x_p), (9, x_u)):
-        with pytest.raises(_lib.StokesError) as e:
-            P.apply(op, torch.tensor(x.ravel(), device="cuda"), precision=0, nrhs=nrhs)
-        assert e.value.status == -7, op
+    # the velocity multigrid is P2/P1 only
+    with pytest.raises(_lib.StokesError) as e:
+        P.apply(9, torch.tensor(x_u.ravel(), device="cuda"), precision=0, nrhs=nrhs)
+    assert e.value.status == -7
+
+
+def _p3_pressure_mg_operators(S, dim):
+    Bm = sp.hstack(S.B_I).tocsr()
+    XL = Bm @ sp.diags(np.tile(1.0 / S.mats.Lam[S.I], dim)) @ Bm.T
+    return {6: (S.mats.MQ + S.mats.LQ).tocsr(), 8: (XL + S.mats.MQ).tocsr()}
 
 
 @pytest.mark.parametrize("dim,n", [(2, 4), (2, 20), (3, 6)])
 def test_p3_pressure_multigrid_vcycle(gpu_lib, dim, n):
-    """The pressure V-cycle of a P3/P2 context (op 6, eps M_Q + L_Q with
-    eps = 1 on the P2 pressure) with the P1 space of the same mesh as first
-    coarse level.  One level ((2n+1)^dim <= 1500 pressure nodes: 2D n=4) is
-    the exact inverse; with several (2D n=20: 1,681 -> 441, 3D n=6:
-    2,197 -> 343 nodes) the cycle is symmetric positive definite and, as a
-    stationary iteration on the oracle's operator, reduces the residual by at
-    least 2x per cycle."""
+    """The pressure V-cycles of a P3/P2 context (op 6: eps M_Q + L_Q with
+    eps = 1, op 8: B_I Lambda_V^-1 B_I^T + M_Q, both on the P2 pressure) with
+    the P1 space of the same mesh as first coarse level.  One level
+    ((2n+1)^dim <= 1500 pressure nodes: 2D n=4) is the exact inverse; with
+    several (2D n=20: 1,681 -> 441, 3D n=6: 2,197 -> 343 nodes) each cycle is
+    symmetric positive definite and, as a stationary iteration on the
+    oracle's operator, reduces the residual at every one of eight cycles: by
+    at least 2x for op 6; for op 8 by at least 1.25x, since its operator is
+    close to the P2 mass matrix, whose low-energy non-smooth modes neither
+    the P1 coarse space nor the smoothing interval covers (0.72 per cycle
+    measured in 3D, 0.25 in 2D)."""
     P, S = _problem(dim, n, seed=3), _oracle(dim, n, seed=3)
     rng = np.random.default_rng(11)
     u, v, b = rng.standard_normal((3, S.mats.MQ.shape[0]))
-    A = (S.mats.MQ + S.mats.LQ).tocsr()
-    V = lambda x: P.apply(6, torch.tensor(x, device="cuda"), precision=0).cpu().numpy()  # noqa: E731
-    if (2 * n + 1) ** dim <= 1500:
-        assert _rel(V(b), np.linalg.solve(A.toarray(), b)) <= 1e-10
-        return
-    Vu, Vv = V(u), V(v)
-    assert abs(u @ Vv - v @ Vu) <= 1e-12 * abs(u @ Vv)
-    assert u @ Vu > 0 and v @ Vv > 0
-    x = np.zeros_like(b)
-    res = [np.linalg.norm(b)]
-    for _ in range(6):
-        x = x + V(b - A @ x)
-        res.append(np.linalg.norm(b - A @ x))
-    rates = np.array(res[1:]) / np.array(res[:-1])
-    print(f"P3/P2 dim={dim} n={n} op 6: rates {rates}", flush=True)
-    assert rates.max() <= 0.5, rates
+    single = (2 * n + 1) ** dim <= 1500
+    for op, A in _p3_pressure_mg_operators(S, dim).items():
+        V = lambda x: P.apply(op, torch.tensor(x, device="cuda"), precision=0).cpu().numpy()  # noqa: E731
+        if single:
+            assert _rel(V(b), np.linalg.solve(A.toarray(), b)) <= 1e-10, op
+            continue
+        Vu, Vv = V(u), V(v)
+        assert abs(u @ Vv - v @ Vu) <= 1e-12 * abs(u @ Vv), op
+        assert u @ Vu > 0 and v @ Vv > 0
+        x = np.zeros_like(b)
+        res = [np.linalg.norm(b)]
+        for _ in range(8):
+            x = x + V(b - A @ x)
+            res.append(np.linalg.norm(b - A @ x))
+        rates = np.array(res[1:]) / np.array(res[:-1])
+        print(f"P3/P2 dim={dim} n={n} op {op}: rates {rates}", flush=True)
+        assert rates.max() <= (0.5 if op == 6 else 0.8), (op, rates)
 
 
 def _solve_and_compare(P, S, f, ubc, method, tol_err, **opts):
