@@ -94,10 +94,9 @@ enum { STOKES_FLAG_STRAIN = 1 };
  * then per local edge (a, b) the node next to a and the node next to b, then
  * the faces (0,1,2), (0,1,3), (0,2,3), (1,2,3) (2D: the interior node).  The
  * P2 pressure nodes of the mesh with n cells are the vertices of the mesh
- * with 2n cells, so the multigrid of eps M_Q + L_Q (op 6) runs on P3/P2 with
- * the P1 space of the mesh as its first coarse level, and the pressure solves
- * use it; the Galerkin hierarchy (op 8) and the velocity multigrid
- * (vel_pc = STOKES_VEL_MG, op 9) need the P2/P1 pair and return
+ * with 2n cells, so both pressure multigrids (ops 6 and 8) run on P3/P2 with
+ * the P1 space of the mesh as their first coarse level; the velocity
+ * multigrid (vel_pc = STOKES_VEL_MG, op 9) needs the P2/P1 pair and returns
  * STOKES_ERR_UNSUPPORTED.  Combines with STOKES_FLAG_STRAIN. */
 enum { STOKES_FLAG_P3 = 2 };
 /* stokes_solve_opts.vel_pc: the preconditioner of A~_{lambda,3} = alpha M_V
