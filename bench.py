@@ -27,6 +27,7 @@ solver's stream during the timed solves) and the CPU oracle baseline.
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -343,7 +344,7 @@ def main():
     if args.strain:
         desc += ", strain-rate form alpha M + mu (L + D)"
     if args.p3:
-        desc = desc.replace("P2/P1", "P3/P2 (this mesh)") + f", P3/P2: {prob.total_dofs():,} DOFs"
+        desc = re.sub(r"P2/P1 [0-9,]+ DOFs", f"P3/P2 {prob.total_dofs():,} DOFs", desc)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     print(f"[bench] assembled {args.workload} in {setup_s:.2f} s", file=sys.stderr, flush=True)
