@@ -264,3 +264,22 @@ def test_p3_velocity_multigrid_refused(gpu_lib):
     with pytest.raises(_lib.StokesError) as e:
         P.solve(f, vel_pc=1)
     assert e.value.status == -7
+
+
+def test_p3_galerkin_multigrid_switch(gpu_lib, monkeypatch):
+    """STOKES_MGX_P3=0 leaves the Galerkin hierarchy unbuilt: op 8 is refused,
+    the eps M_Q + L_Q cycle (op 6) is bit for bit the one of a default
+    context, and a mixed coupled solve (lumped Cahouet-Chabard term, now on
+    the op-6 cycle) still converges to the requested residual."""
+    b = np.random.default_rng(2).standard_normal((2 * 10 + 1) ** 2)
+    ref = _problem(2, 10).apply(6, torch.tensor(b, device="cuda"), precision=0).cpu().numpy()
+    monkeypatch.setenv("STOKES_MGX_P3", "0")
+    P = _problem(2, 10)
+    with pytest.raises(_lib.StokesError) as e:
+        P.apply(8, torch.tensor(b, device="cuda"), precision=0)
+    assert e.value.status == -7
+    y = P.apply(6, torch.tensor(b, device="cuda"), precision=0).cpu().numpy()
+    assert np.array_equal(y, ref)
+    f = torch.tensor(np.random.default_rng(3).standard_normal((1, 2, P.n_p2)), device="cuda")
+    info = P.solve(f, precision=1, rtol=1e-8)[2]
+    assert info["status"] == 0 and info["rel_res"] <= 1e-8, info
