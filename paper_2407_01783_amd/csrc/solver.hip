@@ -414,7 +414,7 @@ class Engine {
   }
 
   // x = X^{-1} b on the mean-free pressures; the preconditioner (fixed
-  // mode: the approximation itself) is one multigrid V-cycle of eps M_Q + L_Q
+  // mode: the approximation itself) is one pressure multigrid V-cycle
   void x_solve(const T* b, T* x) {
     Prec pc{&c_->sQ, ops::pick<T>(c_->XQ64, c_->XQ32), ops::pick<T>(c_->dXQ64, c_->dXQ32), c_->bXQ, 1, {}};
     // the Galerkin hierarchy for the lumped variant (when built), else the
